@@ -1,0 +1,224 @@
+"""GMRES and overlapping Schwarz preconditioners (oracle).
+
+TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
+
+* ``gmres`` -- restarted GMRES(m) with right preconditioning, x0 = 0,
+  modified Gram-Schmidt Arnoldi and Givens rotations; convergence when the
+  residual norm drops below max(rtol ||b||, atol), divergence when it exceeds
+  dtol ||b||, outer cap max_it (Section 3.3 stopping rules).
+* ``RAS`` -- restricted additive Schwarz, M^{-1} = sum_i R_i^T D_i A_i^{-1}
+  R_i with A_i = R_i A R_i^T and Boolean D_i (Eq. RAS); subdomains are the
+  owner sets of a node partition grown by ``overlap`` layers of node-graph
+  neighbours; local problems solved exactly (sparse LU).
+* ``TwoLevel`` -- multiplicative two-grid preconditioner built from the
+  three-step recurrence (Eqs. presmoother, coarsecorrection, postsmoother):
+  pre-smooth with RAS, coarse correction Q = Z A_c^{-1} Z^T with the Galerkin
+  coarse matrix A_c = Z^T A Z (Section 3.1), post-smooth with RAS.  Z is the
+  P1 interpolation from a nested coarse grid, applied to each compartment.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+NC = 5
+
+
+def gmres(matvec, b, prec=None, restart=30, rtol=1e-5, atol=1e-50, dtol=1e5,
+          max_it=200):
+    """Returns (x, info) with info = dict(its, reason, resid)."""
+    prec = (lambda v: v) if prec is None else prec
+    n = len(b)
+    x = np.zeros(n)
+    bnorm = np.linalg.norm(b)
+    target = max(rtol * bnorm, atol)
+    r = b.copy()
+    beta = np.linalg.norm(r)
+    its = 0
+    if beta <= target:
+        return x, dict(its=0, reason="converged", resid=beta)
+    while True:
+        m = restart
+        V = np.zeros((m + 1, n))
+        Zs = np.zeros((m, n))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        gvec = np.zeros(m + 1)
+        gvec[0] = beta
+        V[0] = r / beta
+        reason = None
+        k = 0
+        for j in range(m):
+            Zs[j] = prec(V[j])
+            w = matvec(Zs[j])
+            for i in range(j + 1):
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            if den == 0.0:
+                reason = "breakdown"
+                break
+            cs[j] = H[j, j] / den
+            sn[j] = H[j + 1, j] / den
+            hnext = H[j + 1, j]
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            gvec[j + 1] = -sn[j] * gvec[j]
+            gvec[j] = cs[j] * gvec[j]
+            its += 1
+            k = j + 1
+            res = abs(gvec[j + 1])
+            if res < target:
+                reason = "converged"
+                break
+            if res > dtol * bnorm:
+                reason = "diverged"
+                break
+            if its >= max_it:
+                reason = "max_it"
+                break
+            if hnext == 0.0:
+                reason = "converged"   # happy breakdown: exact solution
+                break
+            V[j + 1] = w / hnext
+        if k > 0:
+            y = np.linalg.solve(np.triu(H[:k, :k]), gvec[:k])
+            x = x + Zs[:k].T @ y
+        if reason is not None:
+            r = b - matvec(x)
+            return x, dict(its=its, reason=reason, resid=np.linalg.norm(r),
+                           est=abs(gvec[k]))
+        r = b - matvec(x)
+        beta = np.linalg.norm(r)
+        if beta <= target:
+            return x, dict(its=its, reason="converged", resid=beta)
+
+
+def grow_overlap(G: sp.csr_matrix, nodes: np.ndarray, layers: int) -> np.ndarray:
+    """Node set grown by ``layers`` layers of graph neighbours."""
+    mask = np.zeros(G.shape[0], dtype=bool)
+    mask[nodes] = True
+    for _ in range(layers):
+        mask = (G @ mask.astype(np.float64)) > 0
+    return np.nonzero(mask)[0]
+
+
+def unknowns_of(nodes: np.ndarray) -> np.ndarray:
+    return (NC * nodes[:, None] + np.arange(NC)[None, :]).ravel()
+
+
+class RAS:
+    """One-level restricted additive Schwarz with exact local solves."""
+
+    def __init__(self, A: sp.csr_matrix, G: sp.csr_matrix, part: np.ndarray,
+                 n_sub: int, overlap: int):
+        self.A = A.tocsr()
+        self.subs = []
+        for i in range(n_sub):
+            owned = np.nonzero(part == i)[0]
+            if len(owned) == 0:
+                continue
+            nodes = grow_overlap(G, owned, overlap)
+            idx = unknowns_of(nodes)
+            own = np.repeat(part[nodes] == i, NC)
+            Ai = self.A[idx][:, idx].tocsc()
+            lu = spla.splu(Ai)
+            self.subs.append((idx, own, lu))
+
+    def apply(self, r):
+        z = np.zeros_like(r)
+        for idx, own, lu in self.subs:
+            zi = lu.solve(r[idx])
+            z[idx[own]] = zi[own]
+        return z
+
+    def apply_T(self, r):
+        """Transpose: sum_i R_i^T A_i^{-T} D_i R_i."""
+        z = np.zeros_like(r)
+        for idx, own, lu in self.subs:
+            ri = np.where(own, r[idx], 0.0)
+            z[idx] += lu.solve(ri, trans="T")
+        return z
+
+
+def nested_interpolation(parents_list, n_coarse: int) -> sp.csr_matrix:
+    """Node-level P1 interpolation Z (n_fine x n_coarse) of a nested grid from
+    its refinement records: a midpoint node takes the mean of its edge's two
+    end values, an old node its own value.  Z is the product of the
+    per-level interpolations."""
+    Z = sp.identity(n_coarse, format="csr")
+    for par in parents_list:
+        n_l = len(par)
+        n_prev = Z.shape[0]
+        rows = np.repeat(np.arange(n_l), 2)
+        cols = par.reshape(-1).astype(np.int64)
+        vals = np.full(2 * n_l, 0.5)
+        P = sp.coo_matrix((vals, (rows, cols)), shape=(n_l, n_prev)).tocsr()
+        P.sum_duplicates()
+        Z = P @ Z
+    return Z.tocsr()
+
+
+class TwoLevel:
+    """Multiplicative two-grid RAS (pre-smooth, coarse correction,
+    post-smooth)."""
+
+    def __init__(self, A, ras: RAS, Znodes: sp.csr_matrix):
+        self.A = A.tocsr()
+        self.ras = ras
+        self.Z = sp.kron(Znodes, sp.identity(NC), format="csr")
+        self.Ac = (self.Z.T @ self.A @ self.Z).tocsc()
+        self.lu = spla.splu(self.Ac)
+
+    def coarse(self, r):
+        return self.Z @ self.lu.solve(self.Z.T @ r)
+
+    def coarse_T(self, r):
+        return self.Z @ self.lu.solve(self.Z.T @ r, trans="T")
+
+    def apply(self, r):
+        z1 = self.ras.apply(r)
+        r1 = r - self.A @ z1
+        z2 = z1 + self.coarse(r1)
+        r2 = r - self.A @ z2
+        return z2 + self.ras.apply(r2)
+
+    def apply_T(self, r):
+        """Transpose of the operator above: the same three stages in the
+        same order with A^T, M_RAS^T and Q^T (the error propagator
+        (I - M A)(I - Q A)(I - M A) transposes to itself with the factors
+        transposed)."""
+        AT = self.A.T.tocsr()
+        z1 = self.ras.apply_T(r)
+        r1 = r - AT @ z1
+        z2 = z1 + self.coarse_T(r1)
+        r2 = r - AT @ z2
+        return z2 + self.ras.apply_T(r2)
+
+
+def make_linsolve(geo, part, n_sub, overlap, coarse=None, restart=30,
+                  rtol=1e-5, atol=1e-50, dtol=1e5, max_it=200, G=None):
+    """Newton linear solver J delta = -F by GMRES + (two-level) RAS, built
+    afresh for every Jacobian.  ``coarse`` = (parents_list, n_coarse) or
+    None.  Returns a callable (J, b) -> (x, info)."""
+    from . import fem
+    G = fem.node_graph(geo) if G is None else G
+    Zn = None
+    if coarse is not None:
+        Zn = nested_interpolation(coarse[0], coarse[1])
+
+    def solve(J, b):
+        ras = RAS(J, G, part, n_sub, overlap)
+        pc = ras if Zn is None else TwoLevel(J, ras, Zn)
+        x, info = gmres(lambda v: J @ v, b, pc.apply, restart=restart,
+                        rtol=rtol, atol=atol, dtol=dtol, max_it=max_it)
+        return x, info
+
+    return solve
