@@ -1,0 +1,232 @@
+/*
+ * seird.h -- C ABI of libseird: the backward-Euler implicit step of the
+ * five-compartment SEIRD reaction-diffusion model on P1 triangles, solved by
+ * Newton's method with GMRES preconditioned by restricted additive Schwarz
+ * (one-level, or multiplicative two-grid with a nested coarse grid), on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The model is the PDE system of Section 2.1 (Eqs. seird1-seird5, N):
+ *   d_t u - div(nu(u) grad u) = B(u) u,   u = (s, e, i, r, d),
+ *   nu(u) = N diag(nu_S, nu_E, nu_I, nu_R, nu_D)      (Eq. vec_component1)
+ *   B(u) the reaction matrix of Eq. vec_component2,
+ * discretised by backward Euler (Eq. timediscrete) and the weak form with
+ * homogeneous Neumann data (Eq. weakform) on P1 triangles, lumped nodal mass
+ * for the mass and reaction terms, exact P1 diffusion with the
+ * element-mean density.  The discrete residual of one step is
+ *
+ *   F_{c,i}(u) = m_i (u_{c,i} - u^n_{c,i})
+ *              + dt nu_c sum_{T ni i} Nbar_T sum_{j in T} K^T_{ij} u_{c,j}
+ *              - dt m_i R_c(u_i) - dt m_i src_{c,i}
+ *
+ * with m_i the lumped mass, K^T_{ij} = |T| grad(phi_i).grad(phi_j),
+ * Nbar_T the mean of N over the vertices of T and R_c the nodal reaction
+ * (B(u)u)_c.  An optional per-node transmission field g multiplies beta_I
+ * and beta_E (the product form of Eq. beta_ie).
+ *
+ * Conventions for every call:
+ *  - State and vectors are device pointers to contiguous float64 arrays in
+ *    node-major layout [n_nodes][5] (unknown 5*node + c, c = S,E,I,R,D),
+ *    owned by the caller and only borrowed for the duration of the call.
+ *  - Mesh and partition arrays are host pointers; they are copied.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  Calls that only launch work are asynchronous on that stream;
+ *    calls documented as synchronising wait for it before returning.
+ *  - Every call returns a seird_status; on failure seird_last_error()
+ *    returns a message (thread-local).  No exception crosses the ABI.
+ *  - Handles are not thread-safe; calls on one handle must not overlap.
+ *  - The library allocates its own device memory at create time (freed by
+ *    the matching destroy).
+ */
+#ifndef SEIRD_H
+#define SEIRD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int seird_status;
+#define SEIRD_OK 0
+#define SEIRD_ERR_ARG (-1)           /* invalid argument or size */
+#define SEIRD_ERR_MESH (-2)          /* degenerate or invalid mesh */
+#define SEIRD_ERR_HIP (-3)           /* HIP runtime error (sticky) */
+#define SEIRD_ERR_NONFINITE (-4)     /* NaN/Inf in a state or residual */
+#define SEIRD_ERR_BREAKDOWN (-5)     /* zero or tiny pivot in a local LU */
+#define SEIRD_ERR_DIVERGED (-6)      /* GMRES residual > dtol * ||b|| */
+#define SEIRD_ERR_NOT_CONVERGED (-7) /* iteration cap reached */
+#define SEIRD_ERR_STATE (-9)         /* total density N <= 0 at a node */
+
+typedef struct seird_problem_s *seird_problem;
+typedef struct seird_precond_s *seird_precond;
+
+/* Model parameters (Section 2.1, Table 1).  Rates per unit time, A in
+ * density units, beta_I/beta_E per density unit per time, nu[c] in
+ * length^2 per density unit per time.  alpha, mu: vital dynamics. */
+typedef struct {
+  double sigma, gamma_E, gamma_R, gamma_D, A, alpha, mu, beta_I, beta_E;
+  double nu[5];
+} seird_params;
+
+/* Schwarz preconditioner options (Section 3).
+ *  n_sub, part: node partition into owner subdomains (part[node] in
+ *    [0, n_sub)); subdomain i is its owner set grown by `overlap` layers of
+ *    mesh-graph neighbours; D_i is the Boolean owner indicator (Eq. RAS).
+ *  tile: tile edge of the banded local factors (16 or 32).
+ *  factor_prec: storage precision of the local factors used by the
+ *    preconditioner apply: 0 = float64, 1 = float32, 2 = bfloat16.  The
+ *    factorisation itself runs in float64; vectors and accumulations of
+ *    the apply stay float64.
+ *  Two-grid (multiplicative, Eqs. presmoother/coarsecorrection/
+ *  postsmoother): n_ref > 0 enables it.  The coarse grid is nested: level 0
+ *  has level_n[0] nodes and refinement record r (1..n_ref) maps each of
+ *  the level_n[r] nodes of level r to the two level-(r-1) nodes whose edge
+ *  it bisects ((p, p) for a node carried over), parents[] holding the
+ *  records back to back as int32 pairs; level_n[n_ref] must equal n_nodes
+ *  and follow the problem's node numbering.  Z is the P1 interpolation
+ *  from level 0; the coarse matrix is the Galerkin product Z^T A Z,
+ *  factored exactly in float64. */
+typedef struct {
+  int32_t n_sub;
+  int32_t overlap;
+  int32_t tile;
+  int32_t factor_prec;
+  int32_t n_ref;
+  const int64_t *level_n;  /* host, n_ref + 1 entries, or NULL */
+  const int32_t *parents;  /* host, sum_{r>=1} 2*level_n[r] entries */
+} seird_schwarz_opts;
+
+/* GMRES options (Section 3.3): right preconditioning, x0 = 0, restart
+ * length, total iteration cap, convergence ||r|| < max(rtol ||b||, atol),
+ * divergence ||r|| > dtol ||b||.  Classical Gram-Schmidt with one
+ * conditional reorthogonalisation pass. */
+typedef struct {
+  int32_t restart;
+  int32_t max_it;
+  double rtol, atol, dtol;
+} seird_krylov_opts;
+
+typedef struct {
+  int32_t its;
+  int32_t reason; /* 1 rtol/atol, 2 happy breakdown, -6 diverged, -7 max_it */
+  double resid;   /* final residual estimate */
+  double bnorm;
+} seird_krylov_stats;
+
+/* Newton options: stop when ||F(u^k)||_2 <= tol * ||M_L u^n||_2, at most
+ * max_it linear solves. */
+typedef struct {
+  double tol;
+  int32_t max_it;
+} seird_newton_opts;
+
+#define SEIRD_MAX_NEWTON 32
+typedef struct {
+  int32_t newton_its;
+  int32_t gmres_its_total;
+  int32_t gmres_its[SEIRD_MAX_NEWTON];
+  double res_hist[SEIRD_MAX_NEWTON + 1]; /* scaled residuals */
+  double eps;      /* ||u^{k+1}-u^k|| / ||u^n|| of the last update (Eq. picardtol) */
+  int32_t reason;  /* SEIRD_OK or the failing status */
+  double t_residual_ms, t_jacobian_ms, t_setup_ms, t_gmres_ms;
+  /* HIP-event time of the subdomain solve launches (the RAS apply kernel)
+   * during this step, their count, and the bytes one launch reads/writes
+   * by the algorithm (factor storage + local vectors). */
+  double t_ras_kernel_ms;
+  int32_t n_ras_launches;
+  double ras_bytes_per_launch;
+} seird_step_stats;
+
+const char *seird_last_error(void);
+/* Version string of the library (build identifier). */
+const char *seird_version(void);
+
+/* Create a problem on the current HIP device from a triangle mesh.
+ *  xy: host float64 [n_nodes][2]; tri: host int32 [n_tri][3] (either
+ *  orientation).  Returns SEIRD_ERR_MESH for out-of-range indices, repeated
+ *  vertices or zero-area triangles.  Builds the node graph, the element
+ *  incidence records and the lumped mass (Section 2.2). */
+seird_status seird_problem_create(int64_t n_nodes, const double *xy,
+                                  int64_t n_tri, const int32_t *tri,
+                                  const seird_params *params,
+                                  seird_problem *out);
+void seird_problem_destroy(seird_problem p);
+seird_status seird_set_params(seird_problem p, const seird_params *params);
+/* Per-node transmission multiplier g [n_nodes] (device float64, copied);
+ * NULL restores g = 1. */
+seird_status seird_set_beta_field(seird_problem p, const double *g_dev,
+                                  void *stream);
+seird_status seird_problem_info(seird_problem p, int64_t *n_nodes,
+                                int64_t *n_slots);
+/* Node graph of the Jacobian (host copies): rowptr [n_nodes+1] and
+ * col [n_slots] list, for every node, its mesh neighbours (itself
+ * excluded) in increasing order.  Either pointer may be NULL. */
+seird_status seird_pattern(seird_problem p, int64_t *rowptr, int32_t *col);
+/* Lumped mass m_i (device float64 [n_nodes], written). */
+seird_status seird_lumped_mass(seird_problem p, double *m_dev, void *stream);
+
+/* F = residual of one backward-Euler step (formula above) at u, given
+ * u_prev = u^n.  src: optional nodal forcing [n][5] (NULL = 0).  Async. */
+seird_status seird_residual(seird_problem p, const double *u,
+                            const double *u_prev, double dt, const double *src,
+                            double *F, void *stream);
+
+/* Exact Jacobian dF/du at u (Newton linearisation of the weak form).
+ * Storage (device float64, caller-owned, seird_jacobian_size values):
+ *   diag [n_nodes][5][5]   : node block (row = equation c, col = unknown c')
+ *   off  [n_slots][10]     : for slot (i, j) of the node graph, a[5] then
+ *                            b[5]; block (i,j)[c][c'] = a[c] delta_cc' + b[c]
+ * (the off-diagonal blocks are diagonal-plus-rank-one because N sums all
+ * five compartments).  Async. */
+seird_status seird_jacobian_size(seird_problem p, int64_t *n_vals);
+seird_status seird_jacobian(seird_problem p, const double *u, double dt,
+                            double *vals, void *stream);
+/* y = J x (transpose = 0) or y = J^T x (transpose = 1).  Async. */
+seird_status seird_spmv(seird_problem p, const double *vals, const double *x,
+                        double *y, int transpose, void *stream);
+
+/* Schwarz preconditioner for this problem. */
+seird_status seird_precond_create(seird_problem p,
+                                  const seird_schwarz_opts *opts,
+                                  const int32_t *part, seird_precond *out);
+void seird_precond_destroy(seird_precond pc);
+/* Local sizes: for subdomain s, the number of local nodes, the node
+ * bandwidth of its local ordering, and the factor storage (entries). */
+seird_status seird_precond_info(seird_precond pc, int64_t *factor_entries,
+                                int64_t *coarse_n, int32_t *max_local_nodes,
+                                int32_t *max_bandwidth);
+/* Enable (1) or disable (0) HIP-event timing of the subdomain solve
+ * launches; the totals are reported in seird_step_stats (t_ras_kernel_ms,
+ * n_ras_launches) and reset at the end of every seird_step. */
+seird_status seird_precond_timing(seird_precond pc, int enable);
+/* Extract R_i A R_i^T from the Jacobian `vals`, factor every local matrix
+ * (and the Galerkin coarse matrix) by LU without pivoting.  Synchronising;
+ * returns SEIRD_ERR_BREAKDOWN on a zero/nonfinite pivot. */
+seird_status seird_precond_setup(seird_precond pc, const double *vals,
+                                 void *stream);
+/* z = M^{-1} r (transpose = 0) or M^{-T} r (transpose = 1), with M the
+ * one-level RAS (Eq. RAS) or the multiplicative two-grid operator.  Async. */
+seird_status seird_precond_apply(seird_precond pc, const double *r, double *z,
+                                 int transpose, void *stream);
+
+/* Solve J x = b (or J^T x = b) by right-preconditioned restarted GMRES.
+ * `pc` may be NULL (no preconditioner).  Synchronising (stats). */
+seird_status seird_gmres(seird_problem p, seird_precond pc, const double *vals,
+                         const double *b, double *x,
+                         const seird_krylov_opts *opts,
+                         seird_krylov_stats *stats, int transpose,
+                         void *stream);
+
+/* One implicit step: u (in: u^n, out: u^{n+1}).  Newton iterations: F,
+ * J, preconditioner setup, GMRES, update.  Synchronising.  On failure u is
+ * unspecified and stats->reason holds the status. */
+seird_status seird_step(seird_problem p, seird_precond pc, double *u,
+                        double dt, const double *src,
+                        const seird_newton_opts *nopts,
+                        const seird_krylov_opts *kopts,
+                        seird_step_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEIRD_H */

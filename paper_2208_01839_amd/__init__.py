@@ -1,0 +1,325 @@
+"""Python binding of libseird (the SEIRD implicit-step library for MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libseird.so`` behind the C ABI declared in ``include/seird.h``.
+PyTorch supplies device memory (float64 CUDA tensors) and the current HIP
+stream.  If the shared library is missing, every entry point raises; there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Problem", "Precond", "SeirdError", "gmres", "step", "lib",
+           "library_path"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libseird.so")
+_lib = None
+
+
+class SeirdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libseird error {code}: {msg}")
+        self.code = code
+
+
+STATUS = {0: "OK", -1: "ARG", -2: "MESH", -3: "HIP", -4: "NONFINITE",
+          -5: "BREAKDOWN", -6: "DIVERGED", -7: "NOT_CONVERGED", -9: "STATE"}
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("sigma", "gamma_E", "gamma_R", "gamma_D", "A", "alpha", "mu",
+                 "beta_I", "beta_E")] + [("nu", ctypes.c_double * 5)]
+
+
+class _Schwarz(ctypes.Structure):
+    _fields_ = [("n_sub", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("factor_prec", ctypes.c_int32),
+                ("n_ref", ctypes.c_int32),
+                ("level_n", ctypes.POINTER(ctypes.c_int64)),
+                ("parents", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _Krylov(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_it", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("dtol", ctypes.c_double)]
+
+
+class _KStats(ctypes.Structure):
+    _fields_ = [("its", ctypes.c_int32), ("reason", ctypes.c_int32),
+                ("resid", ctypes.c_double), ("bnorm", ctypes.c_double)]
+
+
+class _Newton(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int32)]
+
+
+MAX_NEWTON = 32
+
+
+class _SStats(ctypes.Structure):
+    _fields_ = [("newton_its", ctypes.c_int32), ("gmres_its_total", ctypes.c_int32),
+                ("gmres_its", ctypes.c_int32 * MAX_NEWTON),
+                ("res_hist", ctypes.c_double * (MAX_NEWTON + 1)),
+                ("eps", ctypes.c_double), ("reason", ctypes.c_int32),
+                ("t_residual_ms", ctypes.c_double), ("t_jacobian_ms", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
+                ("t_ras_kernel_ms", ctypes.c_double), ("n_ras_launches", ctypes.c_int32),
+                ("ras_bytes_per_launch", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_SIGS = {
+    "seird_last_error": ([], ctypes.c_char_p),
+    "seird_version": ([], ctypes.c_char_p),
+    "seird_problem_create": ([ctypes.c_int64, _P, ctypes.c_int64, _P,
+                              ctypes.POINTER(_Params), ctypes.POINTER(_P)], ctypes.c_int),
+    "seird_problem_destroy": ([_P], None),
+    "seird_set_params": ([_P, ctypes.POINTER(_Params)], ctypes.c_int),
+    "seird_set_beta_field": ([_P, _P, _P], ctypes.c_int),
+    "seird_problem_info": ([_P, _I64P, _I64P], ctypes.c_int),
+    "seird_pattern": ([_P, _P, _P], ctypes.c_int),
+    "seird_lumped_mass": ([_P, _P, _P], ctypes.c_int),
+    "seird_residual": ([_P, _P, _P, ctypes.c_double, _P, _P, _P], ctypes.c_int),
+    "seird_jacobian_size": ([_P, _I64P], ctypes.c_int),
+    "seird_jacobian": ([_P, _P, ctypes.c_double, _P, _P], ctypes.c_int),
+    "seird_spmv": ([_P, _P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
+    "seird_precond_create": ([_P, ctypes.POINTER(_Schwarz), _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "seird_precond_destroy": ([_P], None),
+    "seird_precond_info": ([_P, _I64P, _I64P, _I32P, _I32P], ctypes.c_int),
+    "seird_precond_setup": ([_P, _P, _P], ctypes.c_int),
+    "seird_precond_timing": ([_P, ctypes.c_int], ctypes.c_int),
+    "seird_precond_apply": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
+    "seird_gmres": ([_P, _P, _P, _P, _P, ctypes.POINTER(_Krylov),
+                     ctypes.POINTER(_KStats), ctypes.c_int, _P], ctypes.c_int),
+    "seird_step": ([_P, _P, _P, ctypes.c_double, _P, ctypes.POINTER(_Newton),
+                    ctypes.POINTER(_Krylov), ctypes.POINTER(_SStats), _P], ctypes.c_int),
+}
+
+
+def lib():
+    """Load libseird.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError(f"libseird.so not built ({library_path}); run "
+                               "paper_2208_01839_amd/build.py")
+        L = ctypes.CDLL(library_path)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        msg = lib().seird_last_error().decode()
+        raise SeirdError(code, f"{STATUS.get(code, code)}: {msg}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t, n=None, name="tensor"):
+    """Device pointer of a contiguous float64 CUDA tensor."""
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _params(p) -> _Params:
+    c = _Params()
+    for k in ("sigma", "gamma_E", "gamma_R", "gamma_D", "A", "alpha", "mu",
+              "beta_I", "beta_E"):
+        setattr(c, k, float(getattr(p, k)))
+    for k in range(5):
+        c.nu[k] = float(p.nu[k])
+    return c
+
+
+def _krylov(restart=30, max_it=200, rtol=1e-5, atol=1e-50, dtol=1e5):
+    return _Krylov(int(restart), int(max_it), float(rtol), float(atol), float(dtol))
+
+
+class Problem:
+    """A SEIRD problem on a triangle mesh (host arrays are copied)."""
+
+    def __init__(self, xy, tri, params):
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self.n = len(xy)
+        self.N = 5 * self.n
+        h = ctypes.c_void_p()
+        self._params = _params(params)
+        _check(lib().seird_problem_create(self.n, xy.ctypes.data, len(tri),
+                                          tri.ctypes.data, ctypes.byref(self._params),
+                                          ctypes.byref(h)))
+        self.h = h
+        nv = ctypes.c_int64()
+        _check(lib().seird_jacobian_size(self.h, ctypes.byref(nv)))
+        self.nvals = nv.value
+        ns = ctypes.c_int64()
+        _check(lib().seird_problem_info(self.h, None, ctypes.byref(ns)))
+        self.nslots = ns.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.seird_problem_destroy(self.h)
+            self.h = None
+
+    def set_params(self, params):
+        self._params = _params(params)
+        _check(lib().seird_set_params(self.h, ctypes.byref(self._params)))
+
+    def set_beta_field(self, g):
+        _check(lib().seird_set_beta_field(self.h, _dptr(g, self.n, "g"), _stream()))
+
+    def pattern(self):
+        rp = np.zeros(self.n + 1, dtype=np.int64)
+        col = np.zeros(self.nslots, dtype=np.int32)
+        _check(lib().seird_pattern(self.h, rp.ctypes.data, col.ctypes.data))
+        return rp, col
+
+    def lumped_mass(self, out=None):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda") if out is None else out
+        _check(lib().seird_lumped_mass(self.h, _dptr(out, self.n, "out"), _stream()))
+        return out
+
+    def residual(self, u, u_prev, dt, src=None, out=None):
+        torch = _torch()
+        out = torch.empty_like(u) if out is None else out
+        _check(lib().seird_residual(self.h, _dptr(u, self.N, "u"), _dptr(u_prev, self.N, "u_prev"),
+                                    float(dt), _dptr(src, self.N, "src"), _dptr(out, self.N, "F"),
+                                    _stream()))
+        return out
+
+    def jacobian(self, u, dt, out=None):
+        torch = _torch()
+        out = torch.empty(self.nvals, dtype=torch.float64, device=u.device) if out is None else out
+        _check(lib().seird_jacobian(self.h, _dptr(u, self.N, "u"), float(dt),
+                                    _dptr(out, self.nvals, "vals"), _stream()))
+        return out
+
+    def spmv(self, vals, x, transpose=False, out=None):
+        torch = _torch()
+        out = torch.empty_like(x) if out is None else out
+        _check(lib().seird_spmv(self.h, _dptr(vals, self.nvals, "vals"), _dptr(x, self.N, "x"),
+                                _dptr(out, self.N, "y"), int(bool(transpose)), _stream()))
+        return out
+
+
+class Precond:
+    """Restricted additive Schwarz (one-level, or multiplicative two-grid
+    when ``coarse = (parents_list, n_coarse)`` is given)."""
+
+    def __init__(self, problem: Problem, part, n_sub, overlap, tile=32,
+                 factor_prec=0, coarse=None):
+        self.problem = problem
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        if len(part) != problem.n:
+            raise ValueError("partition length must equal the node count")
+        o = _Schwarz()
+        o.n_sub, o.overlap, o.tile, o.factor_prec = int(n_sub), int(overlap), int(tile), int(factor_prec)
+        keep = []
+        if coarse is not None:
+            parents, n_coarse = coarse
+            level_n = np.array([n_coarse] + [len(p) for p in parents], dtype=np.int64)
+            par = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.int32).reshape(-1)
+                                                       for p in parents]), dtype=np.int32)
+            keep = [level_n, par]
+            o.n_ref = len(parents)
+            o.level_n = level_n.ctypes.data_as(_I64P)
+            o.parents = par.ctypes.data_as(_I32P)
+        else:
+            o.n_ref = 0
+        h = ctypes.c_void_p()
+        _check(lib().seird_precond_create(problem.h, ctypes.byref(o), part.ctypes.data,
+                                          ctypes.byref(h)))
+        del keep
+        self.h = h
+        self._vals = None
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.seird_precond_destroy(self.h)
+            self.h = None
+
+    def info(self):
+        fe, cn = ctypes.c_int64(), ctypes.c_int64()
+        mn, mb = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().seird_precond_info(self.h, ctypes.byref(fe), ctypes.byref(cn),
+                                        ctypes.byref(mn), ctypes.byref(mb)))
+        return dict(factor_entries=fe.value, coarse_n=cn.value,
+                    max_local_nodes=mn.value, max_bandwidth=mb.value)
+
+    def enable_timing(self, on=True):
+        _check(lib().seird_precond_timing(self.h, int(bool(on))))
+
+    def setup(self, vals):
+        _check(lib().seird_precond_setup(self.h, _dptr(vals, self.problem.nvals, "vals"), _stream()))
+        self._vals = vals  # the two-grid apply reads it
+
+    def apply(self, r, transpose=False, out=None):
+        out = _torch().empty_like(r) if out is None else out
+        N = self.problem.N
+        _check(lib().seird_precond_apply(self.h, _dptr(r, N, "r"), _dptr(out, N, "z"),
+                                         int(bool(transpose)), _stream()))
+        return out
+
+
+def gmres(problem: Problem, pc, vals, b, transpose=False, x=None, **kw):
+    """Solve J x = b (or J^T x = b).  Returns (x, stats dict)."""
+    x = _torch().empty_like(b) if x is None else x
+    o = _krylov(**kw)
+    s = _KStats()
+    code = lib().seird_gmres(problem.h, pc.h if pc is not None else None,
+                             _dptr(vals, problem.nvals, "vals"), _dptr(b, problem.N, "b"),
+                             _dptr(x, problem.N, "x"), ctypes.byref(o), ctypes.byref(s),
+                             int(bool(transpose)), _stream())
+    stats = dict(its=s.its, reason=s.reason, resid=s.resid, bnorm=s.bnorm, status=code)
+    if code not in (0, -7):
+        _check(code)
+    return x, stats
+
+
+def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, **kw):
+    """One implicit step in place on u (float64 CUDA [n,5]).  Returns stats."""
+    n = _Newton(float(tol), int(max_it))
+    o = _krylov(**kw)
+    s = _SStats()
+    code = lib().seird_step(problem.h, pc.h if pc is not None else None,
+                            _dptr(u, problem.N, "u"), float(dt), _dptr(src, problem.N, "src"),
+                            ctypes.byref(n), ctypes.byref(o), ctypes.byref(s), _stream())
+    k = s.newton_its
+    stats = dict(newton_its=k, gmres_its=list(s.gmres_its[:k]), gmres_its_total=s.gmres_its_total,
+                 res_hist=list(s.res_hist[:k + 1]), eps=s.eps, reason=s.reason,
+                 t_residual_ms=s.t_residual_ms, t_jacobian_ms=s.t_jacobian_ms,
+                 t_setup_ms=s.t_setup_ms, t_gmres_ms=s.t_gmres_ms,
+                 t_ras_kernel_ms=s.t_ras_kernel_ms, n_ras_launches=s.n_ras_launches,
+                 ras_bytes_per_launch=s.ras_bytes_per_launch)
+    _check(code)
+    return stats

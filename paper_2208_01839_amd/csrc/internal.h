@@ -1,0 +1,137 @@
+// Internal structures of libseird (host and device views).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "seird.h"
+
+namespace seird {
+
+constexpr int NC = 5;
+
+// Error plumbing: functions throw seird::Error, the C ABI converts it.
+struct Error {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define HIPCHECK(x) ::seird::hip_check((x), #x)
+
+template <class T>
+T *dev_alloc(size_t n) {
+  T *p = nullptr;
+  if (n == 0) n = 1;
+  HIPCHECK(hipMalloc(&p, n * sizeof(T)));
+  return p;
+}
+template <class T>
+T *dev_upload(const std::vector<T> &v) {
+  T *p = dev_alloc<T>(v.size());
+  if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+void dev_free(void *p);
+
+// ---------------------------------------------------------------------
+// Mesh-level data built once per problem (Section 2.2).
+//
+// Node graph: for node i, its neighbours (sharing a triangle, itself
+// excluded) sorted; a "slot" is a position in this CSR, i.e. one
+// off-diagonal node block of the Jacobian.
+//
+// Incidence records (node-gather assembly): for every (triangle T, local
+// vertex k), with i = T[k], j = T[k+1], l = T[k+2]:
+//   Kii, Kij, Kil  (row i of the element stiffness K^T)
+//   j, l and the slots of (i,j), (i,l) in row i.
+// Grouped by i so that one thread assembles one node row without atomics.
+// ---------------------------------------------------------------------
+struct MeshHost {
+  int64_t n = 0, nt = 0;
+  std::vector<int64_t> rowptr;  // [n+1]
+  std::vector<int32_t> col;     // [nslots]
+  std::vector<int32_t> tslot;   // slot (i,j) -> slot (j,i)
+  std::vector<double> mass;     // lumped mass [n]
+  std::vector<int64_t> inc_ptr; // [n+1]
+  std::vector<int32_t> inc_j, inc_l, inc_sj, inc_sl;
+  std::vector<double> inc_K;    // [ninc][3]: Kii, Kij, Kil
+};
+
+struct MeshDev {
+  int64_t n = 0, nslots = 0;
+  int64_t *rowptr = nullptr;
+  int32_t *col = nullptr;
+  int32_t *tslot = nullptr;
+  double *mass = nullptr;
+  int64_t *inc_ptr = nullptr;
+  int32_t *inc_j = nullptr, *inc_l = nullptr, *inc_sj = nullptr, *inc_sl = nullptr;
+  double *inc_K = nullptr;
+};
+
+struct ParamsDev {
+  double sigma, gE, gR, gD, A, alpha, mu, bI, bE;
+  double nu[5];
+};
+
+// ---------------------------------------------------------------------
+// Subdomain tile-band geometry.  Local unknowns l = 5*p + c for local node
+// p (local ordering by reverse Cuthill-McKee).  Scalar lower/upper
+// bandwidth kl = ku = 5*bw + 4 for node bandwidth bw.  Tiles t x t; block
+// row K holds BL + 1 + BU tiles: slots 0..BL-1 = L_{K,K-BL..K-1}, slot BL =
+// the diagonal tile (after factorisation: strictly-lower part of L_KK^{-1}
+// and upper part of U_KK^{-1}), slots BL+1.. = U_{K,K+1..K+BU}.  Tiles are
+// row-major t*t.  Padded rows (n_loc..NT*t-1) carry an identity diagonal.
+// ---------------------------------------------------------------------
+struct SubInfo {
+  int64_t base;     // offset (entries) of the factor storage
+  int32_t n_loc;    // local unknowns (5 * local nodes)
+  int32_t nt;       // number of tile rows
+  int32_t bl, bu;   // block bandwidths
+  int32_t l2g_off;  // offset into the local->global unknown map
+  int32_t pad;
+};
+
+struct ExtractEntry {  // one node block of R_i A R_i^T
+  int32_t sub;
+  int32_t p, q;        // local node positions (row block, column block)
+  int32_t ref;         // >= 0: off-diagonal slot; < 0: diagonal of node -ref-1
+};
+
+struct PrecondHost {
+  int n_sub = 0, overlap = 0, tile = 32, prec = 0;
+  std::vector<SubInfo> subs;          // subdomains (then, if two-level, coarse)
+  std::vector<int32_t> l2g;           // local unknown -> global unknown
+  std::vector<uint8_t> owned;         // per local unknown: owned by the sub
+  std::vector<ExtractEntry> extract;  // block entries
+  std::vector<int32_t> order;         // subdomain processing order (LPT)
+  int64_t factor_entries = 0;
+  int32_t max_nodes = 0, max_bw = 0;
+  int32_t max_nloc = 0;
+  // two-level
+  bool two_level = false;
+  int64_t nc = 0;                      // coarse nodes
+  std::vector<int64_t> z_ptr;          // Z rows (fine nodes) [n+1]
+  std::vector<int32_t> z_col;
+  std::vector<double> z_val;
+  std::vector<int64_t> zt_ptr;         // Z^T rows (coarse nodes) [nc+1]
+  std::vector<int32_t> zt_col;
+  std::vector<double> zt_val;
+  SubInfo coarse;                      // coarse tile-band geometry
+  std::vector<int32_t> c_perm;         // coarse node -> coarse local position
+  // Galerkin map: coarse block k (position pair) gets sum w * fine block
+  std::vector<int32_t> gal_p, gal_q;   // coarse local positions of block k
+  std::vector<int64_t> gal_ptr;        // [nblocks+1]
+  std::vector<int32_t> gal_ref;        // fine block ref (as ExtractEntry.ref)
+  std::vector<double> gal_w;
+};
+
+void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,
+                MeshHost &m);
+void build_precond(const MeshHost &m, const seird_schwarz_opts &o,
+                   const int32_t *part, PrecondHost &ph);
+
+}  // namespace seird

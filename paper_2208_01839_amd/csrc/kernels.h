@@ -1,0 +1,79 @@
+// Launch interface between the host orchestration and the HIP kernels.
+#pragma once
+
+#include "internal.h"
+
+namespace seird {
+
+constexpr int KRYLOV_MAX = 32;  // max basis vectors handled by one Arnoldi kernel
+
+struct FactorLaunch {
+  int tile = 32;
+  double *F = nullptr;  // float64 tile-band storage (all subdomains + coarse)
+  int64_t entries = 0;
+  const SubInfo *subs = nullptr;  // device
+  int nsub = 0;
+  const int32_t *order = nullptr;
+  const ExtractEntry *ent = nullptr;
+  int64_t nent = 0;
+  int max_bu = 0;
+  int *status = nullptr;
+  // coarse
+  bool coarse = false;
+  SubInfo cs{};
+  const SubInfo *coarse_dev = nullptr;
+  const int32_t *gp = nullptr, *gq = nullptr;
+  const int64_t *gptr = nullptr;
+  const int32_t *gref = nullptr;
+  const double *gw = nullptr;
+  int64_t gal_nblk = 0;
+};
+
+struct SolveLaunch {
+  int tile = 32;
+  int prec = 0;
+  const void *F = nullptr;
+  const SubInfo *subs = nullptr;
+  const int32_t *order = nullptr;
+  int nblocks = 0;
+  int max_nt = 0;
+  bool use_lds = true;
+  const int32_t *l2g = nullptr;
+  const uint8_t *owned = nullptr;
+  const double *r = nullptr;
+  double *z = nullptr;
+  int add = 0;
+  int transpose = 0;
+  double *yloc = nullptr;
+  double *scratch = nullptr;
+  int64_t scratch_stride = 0;
+};
+
+void launch_residual(const MeshDev &m, const ParamsDev &P, const double *g, const double *u, const double *up,
+                     double dt, const double *src, double *F, hipStream_t st);
+void launch_jacobian(const MeshDev &m, const ParamsDev &P, const double *g, const double *u, double dt, double *diag,
+                     double *off, hipStream_t st);
+void launch_spmv(const MeshDev &m, const double *diag, const double *off, const double *x, const double *b, double *y,
+                 int transpose, hipStream_t st);
+void launch_mdot(const double *V, int64_t ldv, int nv, const double *w, int64_t N, int with_self, double *partials,
+                 int nb, hipStream_t st);
+void launch_reduce(const double *partials, int nb, int nv, double *out, hipStream_t st);
+void launch_maxpy_norm(double *w, const double *V, int64_t ldv, const double *h, int nv, int64_t N, double *partials,
+                       int nb, hipStream_t st);
+void launch_gemv_update(double *x, const double *Z, int64_t ldz, const double *y, int nv, int64_t N, int nb,
+                        hipStream_t st);
+void launch_axpby(double *y, const double *x, double a, const double *aptr, int ainv, double b, int64_t N, int nb,
+                  hipStream_t st);
+void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st);
+void launch_check_state(const double *u, int64_t n, int *flags, hipStream_t st);
+void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st);
+void launch_convert(void *dst, int prec, const double *src, int64_t N, hipStream_t st);
+void launch_band_solve(const SolveLaunch &sl, hipStream_t st);
+void launch_gather_copies(const int64_t *gptr, const int32_t *gidx, const double *yloc, double *z, int add, int64_t N,
+                          hipStream_t st);
+void launch_coarse_restrict(const int64_t *zt_ptr, const int32_t *zt_col, const double *zt_val, const int32_t *cperm,
+                            const double *r, double *rc, int64_t nc, hipStream_t st);
+void launch_coarse_prolong(const int64_t *z_ptr, const int32_t *z_col, const double *z_val, const int32_t *cperm,
+                           const double *xc, double *z, int64_t n, hipStream_t st);
+
+}  // namespace seird

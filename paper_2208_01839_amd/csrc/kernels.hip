@@ -1,0 +1,1015 @@
+// HIP kernels of libseird for gfx950 (wave64).
+//
+// Assembly is node-gather: one thread owns one node row and walks that
+// node's element incidence records, so every output is written by exactly
+// one thread (no atomics, no colour passes, deterministic).  The Jacobian
+// is stored as a node-block matrix whose off-diagonal blocks are
+// diagonal-plus-rank-one (10 values), which the SpMV exploits.
+// Reductions use a fixed grid and a fixed combination order, so results
+// are bitwise reproducible run to run.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace seird {
+
+// ----------------------------------------------------------------------
+// nodal reaction (Eqs. seird1-5 / vec_component2) and its Jacobian
+// ----------------------------------------------------------------------
+__device__ inline void reaction_at(const double u[5], const ParamsDev &P, double g, double R[5]) {
+  const double s = u[0], e = u[1], i = u[2], r = u[3], d = u[4];
+  const double N = s + e + i + r + d;
+  const double a = 1.0 - P.A / N;
+  const double inf = a * g * (P.bI * i + P.bE * e) * s;
+  R[0] = P.alpha * N - inf - P.mu * s;
+  R[1] = inf - (P.sigma + P.gE + P.mu) * e;
+  R[2] = P.sigma * e - (P.gR + P.gD + P.mu) * i;
+  R[3] = P.gE * e + P.gR * i - P.mu * r;
+  R[4] = P.gD * i;
+}
+
+// JR[c][c'] = d R_c / d u_c'
+__device__ inline void reaction_jac_at(const double u[5], const ParamsDev &P, double g, double JR[5][5]) {
+  const double s = u[0], e = u[1], i = u[2];
+  const double N = u[0] + u[1] + u[2] + u[3] + u[4];
+  const double a = 1.0 - P.A / N;
+  const double dadN = P.A / (N * N);
+  const double lam = g * (P.bI * i + P.bE * e);
+  // d(a lam s)/du_c' = dadN lam s + a s dlam/du_c' + a lam [c'==S]
+  double q[5];
+  const double base = dadN * lam * s;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) q[c] = base;
+  q[0] += a * lam;
+  q[1] += a * s * g * P.bE;
+  q[2] += a * s * g * P.bI;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    JR[0][c] = P.alpha - q[c];
+    JR[1][c] = q[c];
+    JR[2][c] = 0.0;
+    JR[3][c] = 0.0;
+    JR[4][c] = 0.0;
+  }
+  JR[0][0] -= P.mu;
+  JR[1][1] -= P.sigma + P.gE + P.mu;
+  JR[2][1] = P.sigma;
+  JR[2][2] = -(P.gR + P.gD + P.mu);
+  JR[3][1] = P.gE;
+  JR[3][2] = P.gR;
+  JR[3][3] = -P.mu;
+  JR[4][2] = P.gD;
+}
+
+__device__ inline void load5(const double *p, double v[5]) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) v[c] = p[c];
+}
+
+// ----------------------------------------------------------------------
+// residual: one thread per node
+// ----------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_residual(MeshDev m, ParamsDev P, const double *__restrict__ gfield,
+                                                  const double *__restrict__ u, const double *__restrict__ up,
+                                                  double dt, const double *__restrict__ src, double *__restrict__ F) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.n) return;
+  double ui[5];
+  load5(u + 5 * i, ui);
+  const double Ni = ui[0] + ui[1] + ui[2] + ui[3] + ui[4];
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t k = m.inc_ptr[i]; k < m.inc_ptr[i + 1]; ++k) {
+    const int32_t j = m.inc_j[k], l = m.inc_l[k];
+    const double Kii = m.inc_K[3 * k], Kij = m.inc_K[3 * k + 1], Kil = m.inc_K[3 * k + 2];
+    double uj[5], ul[5];
+    load5(u + 5 * (int64_t)j, uj);
+    load5(u + 5 * (int64_t)l, ul);
+    const double Nbar = (Ni + (uj[0] + uj[1] + uj[2] + uj[3] + uj[4]) + (ul[0] + ul[1] + ul[2] + ul[3] + ul[4])) *
+                        (1.0 / 3.0);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) acc[c] += Nbar * (Kii * ui[c] + Kij * uj[c] + Kil * ul[c]);
+  }
+  const double g = gfield ? gfield[i] : 1.0;
+  double R[5];
+  reaction_at(ui, P, g, R);
+  const double mi = m.mass[i];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    double f = mi * (ui[c] - up[5 * i + c]) + dt * P.nu[c] * acc[c] - dt * mi * R[c];
+    if (src) f -= dt * mi * src[5 * i + c];
+    F[5 * i + c] = f;
+  }
+}
+
+// ----------------------------------------------------------------------
+// Jacobian: one thread per node row.
+//   diag[i][c][c'] = m_i (delta - dt dR_c/du_c') + dt nu_c (sum_T Nbar K_ii) delta
+//                    + dt nu_c (1/3) sum_T sum_k K_ik u_c,k
+//   off[s] = (a[5], b[5]): a_c = dt nu_c sum_T Nbar K_ij ; b_c = dt nu_c (1/3) sum_T sum_k K_ik u_c,k
+// ----------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P, const double *__restrict__ gfield,
+                                                  const double *__restrict__ u, double dt, double *__restrict__ diag,
+                                                  double *__restrict__ off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.n) return;
+  for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) off[10 * s + q] = 0.0;
+  double ui[5];
+  load5(u + 5 * i, ui);
+  const double Ni = ui[0] + ui[1] + ui[2] + ui[3] + ui[4];
+  double da[5] = {0, 0, 0, 0, 0}, db[5] = {0, 0, 0, 0, 0};
+  double coef[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) coef[c] = dt * P.nu[c];
+  for (int64_t k = m.inc_ptr[i]; k < m.inc_ptr[i + 1]; ++k) {
+    const int32_t j = m.inc_j[k], l = m.inc_l[k];
+    const int64_t sj = m.inc_sj[k], sl = m.inc_sl[k];
+    const double Kii = m.inc_K[3 * k], Kij = m.inc_K[3 * k + 1], Kil = m.inc_K[3 * k + 2];
+    double uj[5], ul[5];
+    load5(u + 5 * (int64_t)j, uj);
+    load5(u + 5 * (int64_t)l, ul);
+    const double Nbar = (Ni + (uj[0] + uj[1] + uj[2] + uj[3] + uj[4]) + (ul[0] + ul[1] + ul[2] + ul[3] + ul[4])) *
+                        (1.0 / 3.0);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const double G3 = coef[c] * (Kii * ui[c] + Kij * uj[c] + Kil * ul[c]) * (1.0 / 3.0);
+      da[c] += coef[c] * Nbar * Kii;
+      db[c] += G3;
+      off[10 * sj + c] += coef[c] * Nbar * Kij;
+      off[10 * sj + 5 + c] += G3;
+      off[10 * sl + c] += coef[c] * Nbar * Kil;
+      off[10 * sl + 5 + c] += G3;
+    }
+  }
+  const double g = gfield ? gfield[i] : 1.0;
+  double JR[5][5];
+  reaction_jac_at(ui, P, g, JR);
+  const double mi = m.mass[i];
+  double *D = diag + 25 * i;
+#pragma unroll
+  for (int c = 0; c < 5; ++c)
+#pragma unroll
+    for (int cp = 0; cp < 5; ++cp) D[5 * c + cp] = -dt * mi * JR[c][cp] + db[c] + (c == cp ? mi + da[c] : 0.0);
+}
+
+// ----------------------------------------------------------------------
+// SpMV with the node-block Jacobian: y = J x, or y = b - J x when b != 0.
+// ----------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restrict__ diag,
+                                              const double *__restrict__ off, const double *__restrict__ x,
+                                              const double *__restrict__ b, double *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.n) return;
+  double xi[5], acc[5];
+  load5(x + 5 * i, xi);
+  const double *D = diag + 25 * i;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    double a = 0.0;
+#pragma unroll
+    for (int cp = 0; cp < 5; ++cp) a += D[5 * c + cp] * xi[cp];
+    acc[c] = a;
+  }
+  for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
+    const int64_t j = m.col[s];
+    double xj[5];
+    load5(x + 5 * j, xj);
+    const double S = xj[0] + xj[1] + xj[2] + xj[3] + xj[4];
+    const double *o = off + 10 * s;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) acc[c] += o[c] * xj[c] + o[5 + c] * S;
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) y[5 * i + c] = b ? b[5 * i + c] - acc[c] : acc[c];
+}
+
+// y = J^T x (or b - J^T x): column j of J gathered through the transposed slots
+__global__ __launch_bounds__(256) void k_spmv_t(MeshDev m, const double *__restrict__ diag,
+                                                const double *__restrict__ off, const double *__restrict__ x,
+                                                const double *__restrict__ b, double *__restrict__ y) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.n) return;
+  double xj[5], acc[5];
+  load5(x + 5 * j, xj);
+  const double *D = diag + 25 * j;
+#pragma unroll
+  for (int cp = 0; cp < 5; ++cp) {
+    double a = 0.0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) a += D[5 * c + cp] * xj[c];
+    acc[cp] = a;
+  }
+  for (int64_t s = m.rowptr[j]; s < m.rowptr[j + 1]; ++s) {
+    const int64_t i = m.col[s];
+    const int64_t ts = m.tslot[s];  // block (i, j) lives at slot ts of row i
+    double xi[5];
+    load5(x + 5 * i, xi);
+    const double *o = off + 10 * ts;
+    const double bsum = o[5] * xi[0] + o[6] * xi[1] + o[7] * xi[2] + o[8] * xi[3] + o[9] * xi[4];
+#pragma unroll
+    for (int cp = 0; cp < 5; ++cp) acc[cp] += o[cp] * xi[cp] + bsum;
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) y[5 * j + c] = b ? b[5 * j + c] - acc[c] : acc[c];
+}
+
+// ----------------------------------------------------------------------
+// deterministic reductions
+// ----------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block of 256 threads -> one value (valid in thread 0)
+__device__ inline double block_sum(double v, double *lds4) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) lds4[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+  return r;
+}
+
+// partials[k * nb + block] = sum over the block's indices of V_k . w
+// (V_k = V + k*ldv, k < nv); if with_self, partials[nv*nb + b] = w . w.
+template <int NVMAX>
+__global__ __launch_bounds__(256) void k_mdot(const double *__restrict__ V, int64_t ldv, int nv,
+                                              const double *__restrict__ w, int64_t N, int with_self,
+                                              double *__restrict__ partials) {
+  __shared__ double lds4[4];
+  double acc[NVMAX + 1];
+#pragma unroll
+  for (int k = 0; k <= NVMAX; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) {
+    const double wv = w[idx];
+#pragma unroll
+    for (int k = 0; k < NVMAX; ++k)
+      if (k < nv) acc[k] += V[k * ldv + idx] * wv;
+    acc[NVMAX] += wv * wv;
+  }
+  const int nb = gridDim.x;
+  for (int k = 0; k < NVMAX; ++k) {
+    if (k >= nv) break;
+    double r = block_sum(acc[k], lds4);
+    if (threadIdx.x == 0) partials[(int64_t)k * nb + blockIdx.x] = r;
+  }
+  if (with_self) {
+    double r = block_sum(acc[NVMAX], lds4);
+    if (threadIdx.x == 0) partials[(int64_t)nv * nb + blockIdx.x] = r;
+  }
+}
+
+// out[k] = sum_b partials[k*nb + b] (fixed order), one block per k
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ partials, int nb,
+                                                         double *__restrict__ out) {
+  __shared__ double lds4[4];
+  const int k = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) v += partials[(int64_t)k * nb + b];
+  double r = block_sum(v, lds4);
+  if (threadIdx.x == 0) out[k] = r;
+}
+
+// w -= sum_k h[k] V_k ; partial ||w||^2
+template <int NVMAX>
+__global__ __launch_bounds__(256) void k_maxpy_norm(double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
+                                                    const double *__restrict__ h, int nv, int64_t N,
+                                                    double *__restrict__ partials) {
+  __shared__ double lds4[4];
+  __shared__ double hs[NVMAX];
+  if (threadIdx.x < NVMAX) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) {
+    double v = w[idx];
+#pragma unroll
+    for (int k = 0; k < NVMAX; ++k)
+      if (k < nv) v -= hs[k] * V[k * ldv + idx];
+    w[idx] = v;
+    acc += v * v;
+  }
+  double r = block_sum(acc, lds4);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// x += sum_k y[k] Z_k
+template <int NVMAX>
+__global__ __launch_bounds__(256) void k_gemv_update(double *__restrict__ x, const double *__restrict__ Z, int64_t ldz,
+                                                     const double *__restrict__ y, int nv, int64_t N) {
+  __shared__ double ys[NVMAX];
+  if (threadIdx.x < NVMAX) ys[threadIdx.x] = threadIdx.x < nv ? y[threadIdx.x] : 0.0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) {
+    double v = x[idx];
+#pragma unroll
+    for (int k = 0; k < NVMAX; ++k)
+      if (k < nv) v += ys[k] * Z[k * ldz + idx];
+    x[idx] = v;
+  }
+}
+
+// y = a*x (+ b*y if accumulate) ; alpha read from device memory when aptr
+__global__ void k_axpby(double *__restrict__ y, const double *__restrict__ x, double a, const double *__restrict__ aptr,
+                        int ainv, double b, int64_t N) {
+  double aa = aptr ? (ainv ? 1.0 / aptr[0] : aptr[0]) : a;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride)
+    y[idx] = aa * x[idx] + (b != 0.0 ? b * y[idx] : 0.0);
+}
+
+// ||F||^2 partials plus a nonfinite flag
+__global__ __launch_bounds__(256) void k_norm2_partials(const double *__restrict__ x, const double *__restrict__ scale,
+                                                        int64_t N, double *__restrict__ partials) {
+  __shared__ double lds4[4];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) {
+    double v = x[idx];
+    if (scale) v *= scale[idx / 5];
+    acc += v * v;
+  }
+  double r = block_sum(acc, lds4);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// state check: count of nodes with N <= 0 or any nonfinite entry
+__global__ __launch_bounds__(256) void k_check_state(const double *__restrict__ u, int64_t n, int *__restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v[5];
+  load5(u + 5 * i, v);
+  const double N = v[0] + v[1] + v[2] + v[3] + v[4];
+  bool bad_nf = false;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) bad_nf |= !isfinite(v[c]);
+  if (bad_nf) atomicOr(flags, 1);
+  else if (!(N > 0.0)) atomicOr(flags, 2);
+}
+
+// ----------------------------------------------------------------------
+// Tile-band storage: init, extraction of R_i A R_i^T, conversion
+// ----------------------------------------------------------------------
+template <int T>
+__device__ inline int64_t tile_entry(const SubInfo &s, int32_t l, int32_t lp) {
+  const int32_t K = l / T, J = lp / T;
+  const int32_t W = s.bl + s.bu + 1;
+  return s.base + ((int64_t)K * W + (J - K + s.bl)) * (T * T) + (l % T) * T + (lp % T);
+}
+
+// same, returning -1 when (l, lp) falls outside the stored tile band
+template <int T>
+__device__ inline int64_t tile_entry_checked(const SubInfo &s, int32_t l, int32_t lp) {
+  const int32_t K = l / T, J = lp / T;
+  const int32_t slot = J - K + s.bl;
+  if (l < 0 || lp < 0 || K >= s.nt || J >= s.nt || slot < 0 || slot > s.bl + s.bu) return -1;
+  return tile_entry<T>(s, l, lp);
+}
+
+// identity on the padded diagonal of the last block row (storage zeroed before)
+template <int T>
+__global__ void k_pad_identity(double *__restrict__ F, const SubInfo *__restrict__ subs, int nsubs) {
+  const int s = blockIdx.x;
+  if (s >= nsubs) return;
+  const SubInfo si = subs[s];
+  for (int32_t l = si.n_loc + threadIdx.x; l < si.nt * T; l += blockDim.x) F[tile_entry<T>(si, l, l)] = 1.0;
+}
+
+// one thread per (entry, c): writes row 5p+c, columns 5q..5q+4
+template <int T>
+__global__ __launch_bounds__(256) void k_extract(double *__restrict__ F, const SubInfo *__restrict__ subs,
+                                                 const ExtractEntry *__restrict__ ent, int64_t nent,
+                                                 const double *__restrict__ diag, const double *__restrict__ off,
+                                                 int *status) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nent * 5) return;
+  const ExtractEntry e = ent[t / 5];
+  const int c = (int)(t % 5);
+  const SubInfo si = subs[e.sub];
+  const int32_t row = 5 * e.p + c;
+  for (int cp = 0; cp < 5; ++cp) {
+    const int64_t at = tile_entry_checked<T>(si, row, 5 * e.q + cp);
+    if (at < 0) {
+      atomicOr(status, 2);
+      continue;
+    }
+    double v;
+    if (e.ref < 0)
+      v = diag[25 * (int64_t)(-e.ref - 1) + 5 * c + cp];
+    else {
+      const double *o = off + 10 * (int64_t)e.ref;
+      v = o[5 + c] + (cp == c ? o[c] : 0.0);
+    }
+    F[at] = v;
+  }
+}
+
+// Galerkin coarse matrix: coarse block k (local positions p, q) =
+// sum_j w_j * fine block(ref_j), written into the coarse tile-band storage
+template <int T>
+__global__ __launch_bounds__(256) void k_galerkin(double *__restrict__ F, SubInfo cs, const int32_t *__restrict__ gp,
+                                                  const int32_t *__restrict__ gq, const int64_t *__restrict__ gptr,
+                                                  const int32_t *__restrict__ gref, const double *__restrict__ gw,
+                                                  int64_t nblk, const double *__restrict__ diag,
+                                                  const double *__restrict__ off, int *status) {
+  // 25 threads per coarse block entry (c, c')
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nblk * 25) return;
+  const int64_t k = t / 25;
+  const int c = (int)(t % 25) / 5, cp = (int)(t % 5);
+  double acc = 0.0;
+  for (int64_t j = gptr[k]; j < gptr[k + 1]; ++j) {
+    const int32_t ref = gref[j];
+    double v;
+    if (ref < 0)
+      v = diag[25 * (int64_t)(-ref - 1) + 5 * c + cp];
+    else {
+      const double *o = off + 10 * (int64_t)ref;
+      v = o[5 + c] + (c == cp ? o[c] : 0.0);
+    }
+    acc += gw[j] * v;
+  }
+  const int64_t at = tile_entry_checked<T>(cs, 5 * gp[k] + c, 5 * gq[k] + cp);
+  if (at < 0)
+    atomicOr(status, 2);
+  else
+    F[at] = acc;
+}
+
+template <class FT>
+__device__ inline FT to_ft(double v);
+template <>
+__device__ inline double to_ft<double>(double v) { return v; }
+template <>
+__device__ inline float to_ft<float>(double v) { return (float)v; }
+template <>
+__device__ inline __hip_bfloat16 to_ft<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
+template <class FT>
+__device__ inline double from_ft(FT v);
+template <>
+__device__ inline double from_ft<double>(double v) { return v; }
+template <>
+__device__ inline double from_ft<float>(float v) { return (double)v; }
+template <>
+__device__ inline double from_ft<__hip_bfloat16>(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
+
+template <class FT>
+__global__ void k_convert(FT *__restrict__ dst, const double *__restrict__ src, int64_t N) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride)
+    dst[idx] = to_ft<FT>(src[idx]);
+}
+
+// ----------------------------------------------------------------------
+// Tile-band LU without pivoting (right-looking, block version).
+// Device routines work on one tile operation with the whole workgroup
+// (256 threads).  LDS tiles are padded to T+1 columns.
+// ----------------------------------------------------------------------
+template <int T>
+struct LuLds {
+  double D[T][T + 1];   // diagonal tile being factored
+  double Li[T][T + 1];  // L_KK^{-1} (unit lower)
+  double Ui[T][T + 1];  // U_KK^{-1} (upper)
+  double S[T][T + 1];   // staging
+};
+
+// Factor the diagonal tile at dk in place and replace it by (strict lower of
+// L^{-1}) + (upper of U^{-1}); keeps Li/Ui in LDS.  Raises *status on a bad pivot.
+template <int T>
+__device__ void lu_diag_tile(double *__restrict__ dk, LuLds<T> &L, int *status) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < T * T; e += 256) L.D[e / T][e % T] = dk[e];
+  __syncthreads();
+  for (int k = 0; k < T; ++k) {
+    const double piv = L.D[k][k];
+    if (tid == 0 && (!isfinite(piv) || fabs(piv) < 1e-300)) atomicOr(status, 1);
+    const double rp = 1.0 / piv;
+    for (int i = k + 1 + tid; i < T; i += 256) L.D[i][k] *= rp;
+    __syncthreads();
+    const int w = T - k - 1;
+    for (int e = tid; e < w * w; e += 256) {
+      const int i = k + 1 + e / w, j = k + 1 + e % w;
+      L.D[i][j] -= L.D[i][k] * L.D[k][j];
+    }
+    __syncthreads();
+  }
+  // inverses: Li (forward over k), Ui (backward over k)
+  for (int e = tid; e < T * T; e += 256) {
+    const int i = e / T, j = e % T;
+    L.Li[i][j] = (i == j) ? 1.0 : 0.0;
+    L.Ui[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < T; ++k) {
+    // Li: rows i > k, columns j <= k: Li[i][j] -= L[i][k] Li[k][j]
+    // Ui: row kk = T-1-k is final after scaling by 1/U[kk][kk]
+    const int kk = T - 1 - k;
+    const double ud = 1.0 / L.D[kk][kk];
+    for (int j = kk + tid; j < T; j += 256) L.Ui[kk][j] *= ud;
+    __syncthreads();
+    const int nl = (T - 1 - k) * (k + 1);
+    for (int e = tid; e < nl; e += 256) {
+      const int i = k + 1 + e / (k + 1), j = e % (k + 1);
+      L.Li[i][j] -= L.D[i][k] * L.Li[k][j];
+    }
+    // Ui: rows i < kk, columns j >= kk
+    const int nu = kk * (T - kk);
+    for (int e = tid; e < nu; e += 256) {
+      const int i = e / (T - kk), j = kk + e % (T - kk);
+      L.Ui[i][j] -= L.D[i][kk] * L.Ui[kk][j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < T * T; e += 256) {
+    const int i = e / T, j = e % T;
+    dk[e] = (i > j) ? L.Li[i][j] : L.Ui[i][j];
+  }
+  __syncthreads();
+}
+
+// load Li/Ui from a stored (inverted) diagonal tile
+template <int T>
+__device__ void load_diag_inverses(const double *__restrict__ dk, LuLds<T> &L) {
+  for (int e = threadIdx.x; e < T * T; e += 256) {
+    const int i = e / T, j = e % T;
+    const double v = dk[e];
+    L.Li[i][j] = (i > j) ? v : (i == j ? 1.0 : 0.0);
+    L.Ui[i][j] = (i <= j) ? v : 0.0;
+  }
+  __syncthreads();
+}
+
+// X = A Ui (lower panel) or X = Li A (upper panel), in place at tile a
+template <int T>
+__device__ void panel_tile(double *__restrict__ a, LuLds<T> &L, bool lower) {
+  for (int e = threadIdx.x; e < T * T; e += 256) L.S[e / T][e % T] = a[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < T * T; e += 256) {
+    const int i = e / T, j = e % T;
+    double acc = 0.0;
+    if (lower) {
+      for (int k = 0; k <= j; ++k) acc += L.S[i][k] * L.Ui[k][j];
+    } else {
+      for (int k = 0; k <= i; ++k) acc += L.Li[i][k] * L.S[k][j];
+    }
+    a[e] = acc;
+  }
+  __syncthreads();
+}
+
+// C -= A B  with A staged in Sa (LDS) and B in Sb (LDS), C in global
+template <int T>
+__device__ void schur_tile(double *__restrict__ C, const double (*Sa)[T + 1], const double (*Sb)[T + 1]) {
+  constexpr int PER = (T * T) / 256;  // outputs per thread: 4 (T=32) or 1 (T=16)
+  if constexpr (PER == 4) {
+    // 2x2 register block per thread
+    const int bi = (threadIdx.x / 16) * 2, bj = (threadIdx.x % 16) * 2;
+    double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+#pragma unroll 8
+    for (int k = 0; k < T; ++k) {
+      const double a0 = Sa[bi][k], a1 = Sa[bi + 1][k];
+      const double b0 = Sb[k][bj], b1 = Sb[k][bj + 1];
+      c00 += a0 * b0; c01 += a0 * b1; c10 += a1 * b0; c11 += a1 * b1;
+    }
+    C[bi * T + bj] -= c00;
+    C[bi * T + bj + 1] -= c01;
+    C[(bi + 1) * T + bj] -= c10;
+    C[(bi + 1) * T + bj + 1] -= c11;
+  } else {
+    const int i = threadIdx.x / T, j = threadIdx.x % T;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) acc += Sa[i][k] * Sb[k][j];
+    C[i * T + j] -= acc;
+  }
+}
+
+template <int T>
+__device__ inline double *tile_at(double *F, const SubInfo &s, int K, int slot) {
+  return F + s.base + ((int64_t)K * (s.bl + s.bu + 1) + slot) * (T * T);
+}
+
+// One workgroup factors one subdomain (batched over subdomains, LPT order).
+// Dynamic LDS holds the U panel (bu tiles).
+template <int T>
+__global__ __launch_bounds__(256) void k_band_lu(double *__restrict__ F, const SubInfo *__restrict__ subs,
+                                                 const int32_t *__restrict__ order, int *status) {
+  __shared__ LuLds<T> L;
+  extern __shared__ double upanel_raw[];
+  double(*Up)[T][T + 1] = reinterpret_cast<double(*)[T][T + 1]>(upanel_raw);
+  const SubInfo s = subs[order[blockIdx.x]];
+  for (int K = 0; K < s.nt; ++K) {
+    lu_diag_tile<T>(tile_at<T>(F, s, K, s.bl), L, status);
+    const int ie = min(K + s.bl, s.nt - 1), je = min(K + s.bu, s.nt - 1);
+    for (int I = K + 1; I <= ie; ++I) panel_tile<T>(tile_at<T>(F, s, I, K - I + s.bl), L, true);
+    for (int J = K + 1; J <= je; ++J) {
+      double *a = tile_at<T>(F, s, K, J - K + s.bl);
+      panel_tile<T>(a, L, false);
+      for (int e = threadIdx.x; e < T * T; e += 256) Up[J - K - 1][e / T][e % T] = a[e];
+    }
+    __syncthreads();
+    for (int I = K + 1; I <= ie; ++I) {
+      const double *lik = tile_at<T>(F, s, I, K - I + s.bl);
+      for (int e = threadIdx.x; e < T * T; e += 256) L.S[e / T][e % T] = lik[e];
+      __syncthreads();
+      for (int J = K + 1; J <= je; ++J) schur_tile<T>(tile_at<T>(F, s, I, J - I + s.bl), L.S, Up[J - K - 1]);
+      __syncthreads();
+    }
+  }
+}
+
+// Multi-launch variant for one large band matrix (the coarse problem):
+// step K = diag (1 WG), panels (bl + bu WGs), Schur (bl x bu WGs).
+template <int T>
+__global__ __launch_bounds__(256) void k_lu_step_diag(double *__restrict__ F, SubInfo s, int K, int *status) {
+  __shared__ LuLds<T> L;
+  lu_diag_tile<T>(tile_at<T>(F, s, K, s.bl), L, status);
+}
+template <int T>
+__global__ __launch_bounds__(256) void k_lu_step_panel(double *__restrict__ F, SubInfo s, int K) {
+  __shared__ LuLds<T> L;
+  load_diag_inverses<T>(tile_at<T>(F, s, K, s.bl), L);
+  const int b = blockIdx.x;
+  if (b < s.bl) {
+    const int I = K + 1 + b;
+    if (I < s.nt) panel_tile<T>(tile_at<T>(F, s, I, K - I + s.bl), L, true);
+  } else {
+    const int J = K + 1 + (b - s.bl);
+    if (J < s.nt) panel_tile<T>(tile_at<T>(F, s, K, J - K + s.bl), L, false);
+  }
+}
+template <int T>
+__global__ __launch_bounds__(256) void k_lu_step_schur(double *__restrict__ F, SubInfo s, int K) {
+  __shared__ double Sa[T][T + 1], Sb[T][T + 1];
+  const int I = K + 1 + blockIdx.x / s.bu, J = K + 1 + blockIdx.x % s.bu;
+  if (I >= s.nt || J >= s.nt) return;
+  const double *lik = tile_at<T>(F, s, I, K - I + s.bl);
+  const double *ukj = tile_at<T>(F, s, K, J - K + s.bl);
+  for (int e = threadIdx.x; e < T * T; e += 256) {
+    Sa[e / T][e % T] = lik[e];
+    Sb[e / T][e % T] = ukj[e];
+  }
+  __syncthreads();
+  schur_tile<T>(tile_at<T>(F, s, I, J - I + s.bl), Sa, Sb);
+}
+
+// ----------------------------------------------------------------------
+// Tile-band triangular solves (the subdomain apply A_i^{-1} r_i).
+// One workgroup per subdomain; the local vector x lives in LDS (dynamic)
+// or, for the big coarse system, in a global scratch vector.
+// Non-transposed: forward with L (tiles left of the diagonal, then the
+// unit-lower inverse), backward with U.  Transposed: forward with U^T,
+// backward with L^T.
+// ----------------------------------------------------------------------
+template <int T, class FT>
+__device__ inline const FT *ctile(const FT *F, const SubInfo &s, int K, int slot) {
+  return F + s.base + ((int64_t)K * (s.bl + s.bu + 1) + slot) * (T * T);
+}
+
+// acc[i] (for this thread's row) partial: sum_j A[i][j] * x[j] with 8 (T=32)
+// or 16 (T=16) lanes per row; result reduced within the lane group.
+template <int T, class FT>
+__device__ inline double row_dot(const FT *__restrict__ A, const double *__restrict__ xs, int i, int g, int G) {
+  double a = 0.0;
+#pragma unroll
+  for (int j = g; j < T; j += G) a += from_ft<FT>(A[i * T + j]) * xs[j];
+  return a;
+}
+template <int T, class FT>
+__device__ inline double col_dot(const FT *__restrict__ A, const double *__restrict__ xs, int i, int g, int G) {
+  // sum_j A[j][i] * x[j]
+  double a = 0.0;
+#pragma unroll
+  for (int j = g; j < T; j += G) a += from_ft<FT>(A[j * T + i]) * xs[j];
+  return a;
+}
+
+template <int G>
+__device__ inline double group_sum(double v) {
+  // lanes of one group are consecutive (row-major mapping)
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// mode: 0 = non-transposed, owned write z[g] = x (or z[g] += x if add)
+//       1 = transposed: masked gather, result written to the per-subdomain
+//           buffer yloc (summed over copies afterwards)
+template <int T, class FT, bool XLDS>
+__global__ __launch_bounds__(256) void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs,
+                                                    const int32_t *__restrict__ order, const int32_t *__restrict__ l2g,
+                                                    const uint8_t *__restrict__ owned, const double *__restrict__ r,
+                                                    double *__restrict__ z, int add, int transpose,
+                                                    double *__restrict__ yloc, double *__restrict__ xscratch,
+                                                    int64_t scratch_stride) {
+  extern __shared__ double xl_raw[];
+  __shared__ double acc_s[T];
+  constexpr int G = 256 / T;  // lanes per row
+  const int sidx = order ? order[blockIdx.x] : blockIdx.x;
+  const SubInfo s = subs[sidx];
+  double *x = XLDS ? xl_raw : (xscratch + (int64_t)blockIdx.x * scratch_stride);
+  const int tid = threadIdx.x;
+  const int npad = s.nt * T;
+  // gather r_i = R_i r (transposed: D_i R_i r)
+  for (int l = tid; l < npad; l += 256) {
+    double v = 0.0;
+    if (l < s.n_loc) {
+      const int32_t gi = s.l2g_off >= 0 ? l2g[s.l2g_off + l] : l;
+      v = r[gi];
+      if (transpose && s.l2g_off >= 0 && !owned[s.l2g_off + l]) v = 0.0;
+    }
+    x[l] = v;
+  }
+  __syncthreads();
+  const int i = tid / G, g = tid % G;
+  const int W = s.bl + s.bu + 1;
+  if (!transpose) {
+    // forward: y_K = Linv_KK (x_K - sum_{P<K} L_KP y_P)
+    for (int K = 0; K < s.nt; ++K) {
+      double a = 0.0;
+      const int p0 = max(0, K - s.bl);
+      for (int P = p0; P < K; ++P) a += row_dot<T, FT>(ctile<T, FT>(F, s, K, P - K + s.bl), x + P * T, i, g, G);
+      a = group_sum<G>(a);
+      if (g == 0) acc_s[i] = x[K * T + i] - a;
+      __syncthreads();
+      const FT *dk = ctile<T, FT>(F, s, K, s.bl);
+      double y = 0.0;
+      for (int j = g; j < i; j += G) y += from_ft<FT>(dk[i * T + j]) * acc_s[j];
+      y = group_sum<G>(y);
+      if (g == 0) x[K * T + i] = acc_s[i] + y;
+      __syncthreads();
+    }
+    // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J)
+    for (int K = s.nt - 1; K >= 0; --K) {
+      double a = 0.0;
+      const int je = min(K + s.bu, s.nt - 1);
+      for (int J = K + 1; J <= je; ++J) a += row_dot<T, FT>(ctile<T, FT>(F, s, K, J - K + s.bl), x + J * T, i, g, G);
+      a = group_sum<G>(a);
+      if (g == 0) acc_s[i] = x[K * T + i] - a;
+      __syncthreads();
+      const FT *dk = ctile<T, FT>(F, s, K, s.bl);
+      double y = 0.0;
+      for (int j = i + g; j < T; j += G) y += from_ft<FT>(dk[i * T + j]) * acc_s[j];
+      y = group_sum<G>(y);
+      if (g == 0) x[K * T + i] = y;
+      __syncthreads();
+    }
+  } else {
+    // transposed: forward with U^T: y_K = Uinv_KK^T (x_K - sum_{P<K} U_PK^T y_P)
+    // thread mapping for column access: column i = tid % T, group g = tid / T
+    const int ci = tid % T, cg = tid / T;
+    __shared__ double part_s[G][T];
+    for (int K = 0; K < s.nt; ++K) {
+      double a = 0.0;
+      const int p0 = max(0, K - s.bu);
+      for (int P = p0; P < K; ++P) a += col_dot<T, FT>(ctile<T, FT>(F, s, P, K - P + s.bl), x + P * T, ci, cg, G);
+      part_s[cg][ci] = a;
+      __syncthreads();
+      if (tid < T) {
+        double t = 0.0;
+        for (int q = 0; q < G; ++q) t += part_s[q][tid];
+        acc_s[tid] = x[K * T + tid] - t;
+      }
+      __syncthreads();
+      const FT *dk = ctile<T, FT>(F, s, K, s.bl);
+      // y_i = sum_{j <= i} Ui[j][i] acc_j
+      double y = 0.0;
+      for (int j = cg; j <= ci; j += G) y += from_ft<FT>(dk[j * T + ci]) * acc_s[j];
+      part_s[cg][ci] = y;
+      __syncthreads();
+      if (tid < T) {
+        double t = 0.0;
+        for (int q = 0; q < G; ++q) t += part_s[q][tid];
+        x[K * T + tid] = t;
+      }
+      __syncthreads();
+    }
+    // backward with L^T: x_K = Linv_KK^T (y_K - sum_{J>K} L_JK^T x_J)
+    for (int K = s.nt - 1; K >= 0; --K) {
+      double a = 0.0;
+      const int je = min(K + s.bl, s.nt - 1);
+      for (int J = K + 1; J <= je; ++J) a += col_dot<T, FT>(ctile<T, FT>(F, s, J, K - J + s.bl), x + J * T, ci, cg, G);
+      part_s[cg][ci] = a;
+      __syncthreads();
+      if (tid < T) {
+        double t = 0.0;
+        for (int q = 0; q < G; ++q) t += part_s[q][tid];
+        acc_s[tid] = x[K * T + tid] - t;
+      }
+      __syncthreads();
+      const FT *dk = ctile<T, FT>(F, s, K, s.bl);
+      // x_i = acc_i + sum_{j > i} Li[j][i] acc_j
+      double y = 0.0;
+      for (int j = ci + 1 + cg; j < T; j += G) y += from_ft<FT>(dk[j * T + ci]) * acc_s[j];
+      part_s[cg][ci] = y;
+      __syncthreads();
+      if (tid < T) {
+        double t = 0.0;
+        for (int q = 0; q < G; ++q) t += part_s[q][tid];
+        x[K * T + tid] = acc_s[tid] + t;
+      }
+      __syncthreads();
+    }
+  }
+  (void)W;
+  // scatter
+  if (!transpose) {
+    for (int l = tid; l < s.n_loc; l += 256) {
+      if (s.l2g_off >= 0) {
+        if (owned[s.l2g_off + l]) {
+          const int32_t gi = l2g[s.l2g_off + l];
+          z[gi] = add ? z[gi] + x[l] : x[l];
+        }
+      } else {
+        z[l] = add ? z[l] + x[l] : x[l];
+      }
+    }
+  } else {
+    for (int l = tid; l < s.n_loc; l += 256) {
+      if (s.l2g_off >= 0)
+        yloc[s.l2g_off + l] = x[l];
+      else
+        z[l] = add ? z[l] + x[l] : x[l];
+    }
+  }
+}
+
+// transposed RAS: z[g] (+)= sum over local copies of g (fixed order)
+__global__ void k_gather_copies(const int64_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
+                                const double *__restrict__ yloc, double *__restrict__ z, int add, int64_t N) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  double v = 0.0;
+  for (int64_t k = gptr[g]; k < gptr[g + 1]; ++k) v += yloc[gidx[k]];
+  z[g] = add ? z[g] + v : v;
+}
+
+// coarse restriction rc[perm(I)*5 + c] = sum_a Z_aI r[5a + c]
+__global__ void k_coarse_restrict(const int64_t *__restrict__ zt_ptr, const int32_t *__restrict__ zt_col,
+                                  const double *__restrict__ zt_val, const int32_t *__restrict__ cperm,
+                                  const double *__restrict__ r, double *__restrict__ rc, int64_t nc) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t k = zt_ptr[I]; k < zt_ptr[I + 1]; ++k) {
+    const int64_t a = zt_col[k];
+    const double w = zt_val[k];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) acc[c] += w * r[5 * a + c];
+  }
+  const int64_t p = cperm[I];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) rc[5 * p + c] = acc[c];
+}
+
+// coarse prolongation z[5a + c] += sum_I Z_aI xc[perm(I)*5 + c]
+__global__ void k_coarse_prolong(const int64_t *__restrict__ z_ptr, const int32_t *__restrict__ z_col,
+                                 const double *__restrict__ z_val, const int32_t *__restrict__ cperm,
+                                 const double *__restrict__ xc, double *__restrict__ z, int64_t n) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t k = z_ptr[a]; k < z_ptr[a + 1]; ++k) {
+    const int64_t p = cperm[z_col[k]];
+    const double w = z_val[k];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) acc[c] += w * xc[5 * p + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) z[5 * a + c] += acc[c];
+}
+
+// ----------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------
+static inline unsigned nblocks(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_residual(const MeshDev &m, const ParamsDev &P, const double *g, const double *u, const double *up,
+                     double dt, const double *src, double *F, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual, dim3(nblocks(m.n)), dim3(256), 0, st, m, P, g, u, up, dt, src, F);
+}
+void launch_jacobian(const MeshDev &m, const ParamsDev &P, const double *g, const double *u, double dt, double *diag,
+                     double *off, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobian, dim3(nblocks(m.n)), dim3(256), 0, st, m, P, g, u, dt, diag, off);
+}
+void launch_spmv(const MeshDev &m, const double *diag, const double *off, const double *x, const double *b, double *y,
+                 int transpose, hipStream_t st) {
+  if (transpose)
+    hipLaunchKernelGGL(k_spmv_t, dim3(nblocks(m.n)), dim3(256), 0, st, m, diag, off, x, b, y);
+  else
+    hipLaunchKernelGGL(k_spmv, dim3(nblocks(m.n)), dim3(256), 0, st, m, diag, off, x, b, y);
+}
+void launch_mdot(const double *V, int64_t ldv, int nv, const double *w, int64_t N, int with_self, double *partials,
+                 int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_mdot<KRYLOV_MAX>, dim3(nb), dim3(256), 0, st, V, ldv, nv, w, N, with_self, partials);
+}
+void launch_reduce(const double *partials, int nb, int nv, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(256), 0, st, partials, nb, out);
+}
+void launch_maxpy_norm(double *w, const double *V, int64_t ldv, const double *h, int nv, int64_t N, double *partials,
+                       int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_maxpy_norm<KRYLOV_MAX>, dim3(nb), dim3(256), 0, st, w, V, ldv, h, nv, N, partials);
+}
+void launch_gemv_update(double *x, const double *Z, int64_t ldz, const double *y, int nv, int64_t N, int nb,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_gemv_update<KRYLOV_MAX>, dim3(nb), dim3(256), 0, st, x, Z, ldz, y, nv, N);
+}
+void launch_axpby(double *y, const double *x, double a, const double *aptr, int ainv, double b, int64_t N, int nb,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, st, y, x, a, aptr, ainv, b, N);
+}
+void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm2_partials, dim3(nb), dim3(256), 0, st, x, scale, N, partials);
+}
+void launch_check_state(const double *u, int64_t n, int *flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_state, dim3(nblocks(n)), dim3(256), 0, st, u, n, flags);
+}
+
+template <int T>
+static void setup_factors_t(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st) {
+  HIPCHECK(hipMemsetAsync(fl.F, 0, sizeof(double) * fl.entries, st));
+  if (fl.nsub > 0) {
+    hipLaunchKernelGGL(k_pad_identity<T>, dim3(fl.nsub), dim3(256), 0, st, fl.F, fl.subs, fl.nsub);
+    if (fl.nent > 0)
+      hipLaunchKernelGGL(k_extract<T>, dim3(nblocks(fl.nent * 5)), dim3(256), 0, st, fl.F, fl.subs, fl.ent, fl.nent,
+                         diag, off, fl.status);
+    const size_t lds = (size_t)std::max(fl.max_bu, 1) * T * (T + 1) * sizeof(double);
+    hipLaunchKernelGGL(k_band_lu<T>, dim3(fl.nsub), dim3(256), lds, st, fl.F, fl.subs, fl.order, fl.status);
+  }
+  if (fl.coarse) {
+    hipLaunchKernelGGL(k_pad_identity<T>, dim3(1), dim3(256), 0, st, fl.F, fl.coarse_dev, 1);
+    hipLaunchKernelGGL(k_galerkin<T>, dim3(nblocks(fl.gal_nblk * 25)), dim3(256), 0, st, fl.F, fl.cs, fl.gp, fl.gq,
+                       fl.gptr, fl.gref, fl.gw, fl.gal_nblk, diag, off, fl.status);
+    const SubInfo cs = fl.cs;
+    for (int K = 0; K < cs.nt; ++K) {
+      hipLaunchKernelGGL(k_lu_step_diag<T>, dim3(1), dim3(256), 0, st, fl.F, cs, K, fl.status);
+      if (K + 1 < cs.nt) {
+        hipLaunchKernelGGL(k_lu_step_panel<T>, dim3(cs.bl + cs.bu), dim3(256), 0, st, fl.F, cs, K);
+        hipLaunchKernelGGL(k_lu_step_schur<T>, dim3(cs.bl * cs.bu), dim3(256), 0, st, fl.F, cs, K);
+      }
+    }
+  }
+}
+
+void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st) {
+  if (fl.tile == 32)
+    setup_factors_t<32>(fl, diag, off, st);
+  else
+    setup_factors_t<16>(fl, diag, off, st);
+}
+
+void launch_convert(void *dst, int prec, const double *src, int64_t N, hipStream_t st) {
+  const unsigned nb = 4096;
+  if (prec == 1)
+    hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(256), 0, st, (float *)dst, src, N);
+  else if (prec == 2)
+    hipLaunchKernelGGL(k_convert<__hip_bfloat16>, dim3(nb), dim3(256), 0, st, (__hip_bfloat16 *)dst, src, N);
+}
+
+template <int T, class FT>
+static void solve_t(const SolveLaunch &sl, hipStream_t st) {
+  const size_t lds = (size_t)sl.max_nt * T * sizeof(double);
+  if (sl.use_lds)
+    hipLaunchKernelGGL((k_band_solve<T, FT, true>), dim3(sl.nblocks), dim3(256), lds, st, (const FT *)sl.F, sl.subs,
+                       sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.transpose, sl.yloc, sl.scratch,
+                       sl.scratch_stride);
+  else
+    hipLaunchKernelGGL((k_band_solve<T, FT, false>), dim3(sl.nblocks), dim3(256), 0, st, (const FT *)sl.F, sl.subs,
+                       sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.transpose, sl.yloc, sl.scratch,
+                       sl.scratch_stride);
+}
+
+void launch_band_solve(const SolveLaunch &sl, hipStream_t st) {
+  if (sl.tile == 32) {
+    if (sl.prec == 0) solve_t<32, double>(sl, st);
+    else if (sl.prec == 1) solve_t<32, float>(sl, st);
+    else solve_t<32, __hip_bfloat16>(sl, st);
+  } else {
+    if (sl.prec == 0) solve_t<16, double>(sl, st);
+    else if (sl.prec == 1) solve_t<16, float>(sl, st);
+    else solve_t<16, __hip_bfloat16>(sl, st);
+  }
+}
+
+void launch_gather_copies(const int64_t *gptr, const int32_t *gidx, const double *yloc, double *z, int add, int64_t N,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_copies, dim3(nblocks(N)), dim3(256), 0, st, gptr, gidx, yloc, z, add, N);
+}
+void launch_coarse_restrict(const int64_t *zt_ptr, const int32_t *zt_col, const double *zt_val, const int32_t *cperm,
+                            const double *r, double *rc, int64_t nc, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_restrict, dim3(nblocks(nc)), dim3(256), 0, st, zt_ptr, zt_col, zt_val, cperm, r, rc, nc);
+}
+void launch_coarse_prolong(const int64_t *z_ptr, const int32_t *z_col, const double *z_val, const int32_t *cperm,
+                           const double *xc, double *z, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_prolong, dim3(nblocks(n)), dim3(256), 0, st, z_ptr, z_col, z_val, cperm, xc, z, n);
+}
+
+}  // namespace seird

@@ -1,0 +1,403 @@
+// Host-side setup of libseird: mesh checks, node graph, incidence records,
+// lumped mass (Section 2.2); subdomains, overlap, local ordering, tile-band
+// geometry, extraction maps (Section 3, Eq. RAS); nested P1 coarse space and
+// Galerkin maps (Section 3.1).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <queue>
+
+#include "internal.h"
+
+namespace seird {
+
+void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,
+                MeshHost &m) {
+  if (n <= 0 || nt <= 0 || !xy || !tri) fail(SEIRD_ERR_ARG, "empty mesh");
+  if (n > INT32_MAX / 8) fail(SEIRD_ERR_ARG, "too many nodes");
+  m.n = n;
+  m.nt = nt;
+  std::vector<double> K(nt * 6);  // Kaa, Kbb, Kcc, Kab, Kac, Kbc
+  m.mass.assign(n, 0.0);
+  std::vector<int32_t> deg(n, 0);
+  for (int64_t t = 0; t < nt; ++t) {
+    const int32_t a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= n || b >= n || c >= n)
+      fail(SEIRD_ERR_MESH, "triangle " + std::to_string(t) + " has an out-of-range vertex");
+    if (a == b || b == c || a == c)
+      fail(SEIRD_ERR_MESH, "triangle " + std::to_string(t) + " repeats a vertex");
+    const double x0 = xy[2 * a], y0 = xy[2 * a + 1];
+    const double x1 = xy[2 * b], y1 = xy[2 * b + 1];
+    const double x2 = xy[2 * c], y2 = xy[2 * c + 1];
+    const double det = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
+    const double scale = std::fabs((x1 - x0) * (y2 - y0)) + std::fabs((x2 - x0) * (y1 - y0));
+    if (!(std::fabs(det) > 1e-14 * scale) || !std::isfinite(det))
+      fail(SEIRD_ERR_MESH, "triangle " + std::to_string(t) + " has zero area");
+    const double area = 0.5 * std::fabs(det);
+    // grad phi_k = (y_{k+1} - y_{k+2}, x_{k+2} - x_{k+1}) / det
+    const double gx[3] = {(y1 - y2) / det, (y2 - y0) / det, (y0 - y1) / det};
+    const double gy[3] = {(x2 - x1) / det, (x0 - x2) / det, (x1 - x0) / det};
+    auto k = [&](int p, int q) { return area * (gx[p] * gx[q] + gy[p] * gy[q]); };
+    double *Kt = &K[6 * t];
+    Kt[0] = k(0, 0); Kt[1] = k(1, 1); Kt[2] = k(2, 2);
+    Kt[3] = k(0, 1); Kt[4] = k(0, 2); Kt[5] = k(1, 2);
+    m.mass[a] += area / 3.0;
+    m.mass[b] += area / 3.0;
+    m.mass[c] += area / 3.0;
+    deg[a] += 2; deg[b] += 2; deg[c] += 2;
+  }
+  // node graph: per-node neighbour lists, sorted unique
+  std::vector<int64_t> cp(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) cp[i + 1] = cp[i] + deg[i];
+  std::vector<int32_t> cand(cp[n]);
+  std::vector<int64_t> fill(cp.begin(), cp.end() - 1);
+  for (int64_t t = 0; t < nt; ++t) {
+    const int32_t v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+    for (int k = 0; k < 3; ++k) {
+      cand[fill[v[k]]++] = v[(k + 1) % 3];
+      cand[fill[v[k]]++] = v[(k + 2) % 3];
+    }
+  }
+  m.rowptr.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    auto b = cand.begin() + cp[i], e = cand.begin() + cp[i + 1];
+    std::sort(b, e);
+    m.rowptr[i + 1] = m.rowptr[i] + (std::unique(b, e) - b);
+  }
+  m.col.resize(m.rowptr[n]);
+  for (int64_t i = 0; i < n; ++i) {
+    std::copy(cand.begin() + cp[i], cand.begin() + cp[i] + (m.rowptr[i + 1] - m.rowptr[i]),
+              m.col.begin() + m.rowptr[i]);
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (m.rowptr[i + 1] == m.rowptr[i]) fail(SEIRD_ERR_MESH, "node " + std::to_string(i) + " belongs to no triangle");
+  auto slot_of = [&](int32_t i, int32_t j) -> int32_t {
+    auto b = m.col.begin() + m.rowptr[i], e = m.col.begin() + m.rowptr[i + 1];
+    auto it = std::lower_bound(b, e, j);
+    return static_cast<int32_t>(it - m.col.begin());
+  };
+  m.tslot.resize(m.col.size());
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) m.tslot[s] = slot_of(m.col[s], (int32_t)i);
+  // incidence records grouped by node
+  m.inc_ptr.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) m.inc_ptr[i + 1] = m.inc_ptr[i] + deg[i] / 2;
+  const int64_t ninc = m.inc_ptr[n];
+  m.inc_j.resize(ninc); m.inc_l.resize(ninc); m.inc_sj.resize(ninc); m.inc_sl.resize(ninc);
+  m.inc_K.resize(3 * ninc);
+  std::vector<int64_t> pos(m.inc_ptr.begin(), m.inc_ptr.end() - 1);
+  for (int64_t t = 0; t < nt; ++t) {
+    const int32_t v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+    const double *Kt = &K[6 * t];
+    // full symmetric 3x3 from the 6 unique entries
+    const double Kf[3][3] = {{Kt[0], Kt[3], Kt[4]}, {Kt[3], Kt[1], Kt[5]}, {Kt[4], Kt[5], Kt[2]}};
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+      const int32_t i = v[k];
+      const int64_t r = pos[i]++;
+      m.inc_j[r] = v[k1];
+      m.inc_l[r] = v[k2];
+      m.inc_sj[r] = slot_of(i, v[k1]);
+      m.inc_sl[r] = slot_of(i, v[k2]);
+      m.inc_K[3 * r + 0] = Kf[k][k];
+      m.inc_K[3 * r + 1] = Kf[k][k1];
+      m.inc_K[3 * r + 2] = Kf[k][k2];
+    }
+  }
+}
+
+// Reverse Cuthill-McKee ordering of an induced subgraph given as a local
+// CSR (adjacency excluding self).  Returns perm (position -> local node).
+static std::vector<int32_t> rcm(const std::vector<int32_t> &ptr, const std::vector<int32_t> &adj) {
+  const int32_t nn = (int32_t)ptr.size() - 1;
+  std::vector<int32_t> perm;
+  perm.reserve(nn);
+  std::vector<char> seen(nn, 0);
+  std::vector<int32_t> level(nn, -1);
+  auto degree = [&](int32_t v) { return ptr[v + 1] - ptr[v]; };
+  auto bfs_far = [&](int32_t s, std::vector<int32_t> &comp) {
+    // returns the last node of a BFS from s (a node of maximal level,
+    // smallest degree among those); fills comp with the component
+    comp.clear();
+    std::queue<int32_t> q;
+    q.push(s);
+    level[s] = 0;
+    comp.push_back(s);
+    while (!q.empty()) {
+      int32_t v = q.front();
+      q.pop();
+      for (int32_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+        int32_t w = adj[k];
+        if (level[w] < 0) {
+          level[w] = level[v] + 1;
+          q.push(w);
+          comp.push_back(w);
+        }
+      }
+    }
+    int32_t best = s;
+    for (int32_t v : comp)
+      if (level[v] > level[best] || (level[v] == level[best] && degree(v) < degree(best))) best = v;
+    int32_t ecc = level[best];
+    for (int32_t v : comp) level[v] = -1;
+    return std::make_pair(best, ecc);
+  };
+  std::vector<int32_t> comp;
+  for (int32_t s0 = 0; s0 < nn; ++s0) {
+    if (seen[s0]) continue;
+    // pseudo-peripheral start node (George-Liu style)
+    int32_t s = s0;
+    auto r = bfs_far(s, comp);
+    int32_t ecc = -1;
+    for (int it = 0; it < 4 && r.second > ecc; ++it) {
+      ecc = r.second;
+      s = r.first;
+      r = bfs_far(s, comp);
+    }
+    // Cuthill-McKee from s
+    std::vector<int32_t> cm;
+    cm.push_back(s);
+    seen[s] = 1;
+    std::vector<int32_t> nb;
+    for (size_t h = 0; h < cm.size(); ++h) {
+      int32_t v = cm[h];
+      nb.clear();
+      for (int32_t k = ptr[v]; k < ptr[v + 1]; ++k)
+        if (!seen[adj[k]]) {
+          nb.push_back(adj[k]);
+          seen[adj[k]] = 1;
+        }
+      std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
+        return degree(a) != degree(b) ? degree(a) < degree(b) : a < b;
+      });
+      cm.insert(cm.end(), nb.begin(), nb.end());
+    }
+    std::reverse(cm.begin(), cm.end());
+    perm.insert(perm.end(), cm.begin(), cm.end());
+  }
+  return perm;
+}
+
+static SubInfo tile_geometry(int32_t nn, int32_t bw, int tile) {
+  SubInfo si{};
+  si.n_loc = NC * nn;
+  const int32_t kl = NC * bw + NC - 1;
+  si.nt = (si.n_loc + tile - 1) / tile;
+  si.bl = std::min<int32_t>((kl + tile - 1) / tile, si.nt - 1);
+  si.bu = si.bl;
+  return si;
+}
+
+void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t *part,
+                   PrecondHost &ph) {
+  const int64_t n = m.n;
+  if (o.n_sub <= 0 || o.overlap < 0 || !part) fail(SEIRD_ERR_ARG, "bad Schwarz options");
+  if (o.tile != 16 && o.tile != 32) fail(SEIRD_ERR_ARG, "tile must be 16 or 32");
+  if (o.factor_prec < 0 || o.factor_prec > 2) fail(SEIRD_ERR_ARG, "factor_prec must be 0, 1 or 2");
+  ph.n_sub = o.n_sub;
+  ph.overlap = o.overlap;
+  ph.tile = o.tile;
+  ph.prec = o.factor_prec;
+  std::vector<std::vector<int32_t>> owned(o.n_sub);
+  for (int64_t i = 0; i < n; ++i) {
+    if (part[i] < 0 || part[i] >= o.n_sub) fail(SEIRD_ERR_ARG, "partition entry out of range");
+    owned[part[i]].push_back((int32_t)i);
+  }
+  for (int s = 0; s < o.n_sub; ++s)
+    if (owned[s].empty()) fail(SEIRD_ERR_ARG, "subdomain " + std::to_string(s) + " owns no node");
+  std::vector<int32_t> stamp(n, -1), lpos(n, -1);
+  const int t = o.tile;
+  int64_t base = 0;
+  for (int s = 0; s < o.n_sub; ++s) {
+    // overlap growth: `overlap` layers of graph neighbours
+    std::vector<int32_t> nodes = owned[s];
+    for (int32_t v : nodes) stamp[v] = s;
+    size_t front_b = 0;
+    for (int layer = 0; layer < o.overlap; ++layer) {
+      size_t front_e = nodes.size();
+      for (size_t h = front_b; h < front_e; ++h) {
+        int32_t v = nodes[h];
+        for (int64_t k = m.rowptr[v]; k < m.rowptr[v + 1]; ++k) {
+          int32_t w = m.col[k];
+          if (stamp[w] != s) {
+            stamp[w] = s;
+            nodes.push_back(w);
+          }
+        }
+      }
+      front_b = front_e;
+    }
+    std::sort(nodes.begin(), nodes.end());
+    const int32_t nn = (int32_t)nodes.size();
+    for (int32_t k = 0; k < nn; ++k) lpos[nodes[k]] = k;
+    // induced subgraph CSR
+    std::vector<int32_t> lp(nn + 1, 0), la;
+    for (int32_t k = 0; k < nn; ++k) {
+      int32_t v = nodes[k];
+      for (int64_t q = m.rowptr[v]; q < m.rowptr[v + 1]; ++q)
+        if (stamp[m.col[q]] == s) la.push_back(lpos[m.col[q]]);
+      lp[k + 1] = (int32_t)la.size();
+    }
+    std::vector<int32_t> perm = rcm(lp, la);
+    std::vector<int32_t> where(nn);
+    for (int32_t k = 0; k < nn; ++k) where[perm[k]] = k;
+    int32_t bw = 0;
+    for (int32_t k = 0; k < nn; ++k)
+      for (int32_t q = lp[k]; q < lp[k + 1]; ++q) bw = std::max(bw, std::abs(where[k] - where[la[q]]));
+    SubInfo si = tile_geometry(nn, bw, t);
+    si.base = base;
+    si.l2g_off = (int32_t)ph.l2g.size();
+    base += (int64_t)si.nt * (si.bl + si.bu + 1) * t * t;
+    ph.max_nodes = std::max(ph.max_nodes, nn);
+    ph.max_bw = std::max(ph.max_bw, bw);
+    ph.max_nloc = std::max(ph.max_nloc, si.n_loc);
+    // local unknown map and ownership, in the local (RCM) order
+    for (int32_t k = 0; k < nn; ++k) {
+      int32_t g = nodes[perm[k]];
+      for (int c = 0; c < NC; ++c) {
+        ph.l2g.push_back(NC * g + c);
+        ph.owned.push_back(part[g] == s ? 1 : 0);
+      }
+    }
+    // extraction entries (row block p, column block q)
+    for (int32_t k = 0; k < nn; ++k) {
+      int32_t g = nodes[perm[k]];
+      ph.extract.push_back({s, k, k, -g - 1});
+      for (int64_t q = m.rowptr[g]; q < m.rowptr[g + 1]; ++q) {
+        int32_t h = m.col[q];
+        if (stamp[h] == s) ph.extract.push_back({s, k, where[lpos[h]], (int32_t)q});
+      }
+    }
+    ph.subs.push_back(si);
+  }
+  ph.factor_entries = base;
+  // largest subdomains first (longest-processing-time order)
+  ph.order.resize(o.n_sub);
+  std::iota(ph.order.begin(), ph.order.end(), 0);
+  std::stable_sort(ph.order.begin(), ph.order.end(), [&](int a, int b) {
+    const SubInfo &x = ph.subs[a], &y = ph.subs[b];
+    return (int64_t)x.nt * (x.bl + x.bu + 1) > (int64_t)y.nt * (y.bl + y.bu + 1);
+  });
+
+  // ------------------------------------------------------------------
+  // two-grid coarse space (nested P1 interpolation, Galerkin product)
+  // ------------------------------------------------------------------
+  if (o.n_ref <= 0) return;
+  if (!o.level_n || !o.parents) fail(SEIRD_ERR_ARG, "two-level needs level_n and parents");
+  if (o.level_n[o.n_ref] != n) fail(SEIRD_ERR_ARG, "finest refinement level must match the mesh");
+  ph.two_level = true;
+  const int64_t nc = o.level_n[0];
+  if (nc <= 0) fail(SEIRD_ERR_ARG, "empty coarse level");
+  ph.nc = nc;
+  // Z rows as sparse vectors, level by level
+  std::vector<int64_t> zp(nc + 1);
+  std::vector<int32_t> zc(nc);
+  std::vector<double> zv(nc, 1.0);
+  for (int64_t i = 0; i <= nc; ++i) zp[i] = i;
+  for (int64_t i = 0; i < nc; ++i) zc[i] = (int32_t)i;
+  const int32_t *par = o.parents;
+  for (int r = 1; r <= o.n_ref; ++r) {
+    const int64_t nl = o.level_n[r], nprev = o.level_n[r - 1];
+    std::vector<int64_t> np(nl + 1, 0);
+    std::vector<int32_t> nc_;
+    std::vector<double> nv;
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t a = 0; a < nl; ++a) {
+      int32_t p = par[2 * a], q = par[2 * a + 1];
+      if (p < 0 || q < 0 || p >= nprev || q >= nprev) fail(SEIRD_ERR_ARG, "refinement record out of range");
+      row.clear();
+      for (int64_t k = zp[p]; k < zp[p + 1]; ++k) row.push_back({zc[k], 0.5 * zv[k]});
+      for (int64_t k = zp[q]; k < zp[q + 1]; ++k) row.push_back({zc[k], 0.5 * zv[k]});
+      std::sort(row.begin(), row.end());
+      for (size_t k = 0; k < row.size(); ++k) {
+        if (!nc_.empty() && (int64_t)nc_.size() > np[a] && nc_.back() == row[k].first)
+          nv.back() += row[k].second;
+        else {
+          nc_.push_back(row[k].first);
+          nv.push_back(row[k].second);
+        }
+      }
+      np[a + 1] = (int64_t)nc_.size();
+    }
+    par += 2 * nl;
+    zp.swap(np);
+    zc.swap(nc_);
+    zv.swap(nv);
+  }
+  ph.z_ptr = zp;
+  ph.z_col = zc;
+  ph.z_val = zv;
+  // Z^T
+  ph.zt_ptr.assign(nc + 1, 0);
+  for (int32_t c : zc) ph.zt_ptr[c + 1]++;
+  for (int64_t i = 0; i < nc; ++i) ph.zt_ptr[i + 1] += ph.zt_ptr[i];
+  ph.zt_col.resize(zc.size());
+  ph.zt_val.resize(zc.size());
+  {
+    std::vector<int64_t> f(ph.zt_ptr.begin(), ph.zt_ptr.end() - 1);
+    for (int64_t a = 0; a < n; ++a)
+      for (int64_t k = zp[a]; k < zp[a + 1]; ++k) {
+        ph.zt_col[f[zc[k]]] = (int32_t)a;
+        ph.zt_val[f[zc[k]]++] = zv[k];
+      }
+  }
+  // Galerkin contributions per coarse row I: for fine a in supp(I) and fine
+  // b in {a} U adj(a), every J in Z row b gets w = Z_aI Z_bJ times block (a,b)
+  std::vector<int64_t> cptr(nc + 1, 0);
+  std::vector<int32_t> cadj;  // coarse graph (including self)
+  struct Contrib { int32_t J; int32_t ref; double w; };
+  std::vector<std::vector<Contrib>> rows(nc);
+  std::vector<Contrib> tmp;
+  for (int64_t I = 0; I < nc; ++I) {
+    tmp.clear();
+    for (int64_t k = ph.zt_ptr[I]; k < ph.zt_ptr[I + 1]; ++k) {
+      const int32_t a = ph.zt_col[k];
+      const double wa = ph.zt_val[k];
+      for (int64_t kb = zp[a]; kb < zp[a + 1]; ++kb) tmp.push_back({zc[kb], -a - 1, wa * zv[kb]});
+      for (int64_t q = m.rowptr[a]; q < m.rowptr[a + 1]; ++q) {
+        const int32_t b = m.col[q];
+        for (int64_t kb = zp[b]; kb < zp[b + 1]; ++kb) tmp.push_back({zc[kb], (int32_t)q, wa * zv[kb]});
+      }
+    }
+    std::stable_sort(tmp.begin(), tmp.end(), [](const Contrib &x, const Contrib &y) { return x.J < y.J; });
+    rows[I] = tmp;
+    for (size_t k = 0; k < tmp.size(); ++k)
+      if (k == 0 || tmp[k].J != tmp[k - 1].J) cadj.push_back(tmp[k].J);
+    cptr[I + 1] = (int64_t)cadj.size();
+  }
+  // coarse RCM ordering over the coarse graph without self loops
+  std::vector<int32_t> lp(nc + 1, 0), la;
+  for (int64_t I = 0; I < nc; ++I) {
+    for (int64_t k = cptr[I]; k < cptr[I + 1]; ++k)
+      if (cadj[k] != I) la.push_back(cadj[k]);
+    lp[I + 1] = (int32_t)la.size();
+  }
+  std::vector<int32_t> perm = rcm(lp, la);
+  ph.c_perm.assign(nc, 0);
+  for (int64_t k = 0; k < nc; ++k) ph.c_perm[perm[k]] = (int32_t)k;
+  int32_t bw = 0;
+  for (int64_t I = 0; I < nc; ++I)
+    for (int64_t k = cptr[I]; k < cptr[I + 1]; ++k)
+      bw = std::max(bw, std::abs(ph.c_perm[I] - ph.c_perm[cadj[k]]));
+  ph.coarse = tile_geometry((int32_t)nc, bw, t);
+  ph.coarse.base = ph.factor_entries;
+  ph.coarse.l2g_off = -1;
+  ph.factor_entries += (int64_t)ph.coarse.nt * (ph.coarse.bl + ph.coarse.bu + 1) * t * t;
+  ph.gal_ptr.push_back(0);
+  for (int64_t I = 0; I < nc; ++I) {
+    const auto &rw = rows[I];
+    for (size_t k = 0; k < rw.size(); ++k) {
+      if (k == 0 || rw[k].J != rw[k - 1].J) {
+        if (k > 0) ph.gal_ptr.push_back((int64_t)ph.gal_ref.size());
+        ph.gal_p.push_back(ph.c_perm[I]);
+        ph.gal_q.push_back(ph.c_perm[rw[k].J]);
+      }
+      ph.gal_ref.push_back(rw[k].ref);
+      ph.gal_w.push_back(rw[k].w);
+    }
+    if (!rw.empty()) ph.gal_ptr.push_back((int64_t)ph.gal_ref.size());
+    std::vector<Contrib>().swap(rows[I]);
+  }
+}
+
+}  // namespace seird

@@ -192,6 +192,12 @@ def delaunay_polygon_mesh(poly: np.ndarray, n_target: int, seed: int):
     tri = Delaunay(pts).simplices
     cen = pts[tri].mean(1)
     tri = tri[_points_in_polygon(cen, poly)]
+    # collinear boundary points give zero-area slivers: drop them (they
+    # cover no area; a node left without triangles is removed below)
+    p = pts[tri]
+    det = np.abs((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+                 - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    tri = tri[det > 1e-6 * H * H]
     used = np.unique(tri)
     remap = -np.ones(len(pts), dtype=np.int64)
     remap[used] = np.arange(len(used))
