@@ -39,7 +39,7 @@ def build_workload(args):
     return cfg, coarse
 
 
-def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile):
+def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0):
     prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
     pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, tile=tile,
                     factor_prec=prec, coarse=coarse)
@@ -47,7 +47,7 @@ def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile):
     info = pc.info()
     u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
     kw = dict(tol=cfg.newton_tol, max_it=cfg.newton_max_it, restart=cfg.gmres_restart,
-              rtol=cfg.gmres_rtol, atol=cfg.gmres_atol, dtol=cfg.gmres_dtol)
+              rtol=cfg.gmres_rtol, atol=cfg.gmres_atol, dtol=cfg.gmres_dtol, pc_reuse=pc_reuse)
     for w in range(warmup):
         st = sk.step(prob, pc, u, cfg.dt, **kw)
         log(f"[bench] prec={prec} warmup step {w}: newton={st['newton_its']} gmres={st['gmres_its']}")
@@ -57,7 +57,7 @@ def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile):
     for k in range(steps):
         st = sk.step(prob, pc, u, cfg.dt, **kw)
         stats.append(st)
-        log(f"[bench] prec={prec} step {k}: newton={st['newton_its']} gmres={st['gmres_its']} "
+        log(f"[bench] prec={prec} reuse={pc_reuse} step {k}: newton={st['newton_its']} setups={st['pc_setups']} gmres={st['gmres_its']} "
             f"res={st['res_hist'][-1]:.2e} t(res/jac/setup/gmres)ms="
             f"{st['t_residual_ms']:.1f}/{st['t_jacobian_ms']:.1f}/{st['t_setup_ms']:.1f}/{st['t_gmres_ms']:.1f}")
     torch.cuda.synchronize()
@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--n-ref", type=int, default=4)
     ap.add_argument("--n-sub", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pc-reuse", type=int, default=0,
+                    help="Newton iterations a preconditioner setup is reused for (0: fresh every time)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path "
@@ -129,7 +131,7 @@ def main():
     args.full_nodes = cfg.n
     log(f"[bench] workload {cfg.name}: {cfg.n} nodes, {len(cfg.tri)} triangles, "
         f"{cfg.n_sub} subdomains, coarse {cfg.coarse_n} nodes ({time.perf_counter() - t:.1f} s)")
-    res = run_steps(sk, torch, cfg, coarse, args.prec, args.steps, args.warmup, args.tile)
+    res = run_steps(sk, torch, cfg, coarse, args.prec, args.steps, args.warmup, args.tile, args.pc_reuse)
     sec = res["seconds"]
     stats = res["stats"]
     value = args.steps / sec
@@ -161,8 +163,10 @@ def main():
                                 + (f"two-grid RAS {cfg.n_sub} subdomains overlap {cfg.overlap}, coarse "
                                    f"{cfg.coarse_n} nodes" if coarse else
                                    f"one-level RAS {cfg.n_sub} subdomains overlap {cfg.overlap}")),
-                   "unknowns": 5 * cfg.n, "tile": args.tile, "factor_prec": args.prec},
+                   "unknowns": 5 * cfg.n, "tile": args.tile, "factor_prec": args.prec,
+                   "pc_reuse": args.pc_reuse},
         "newton_its": [s["newton_its"] for s in stats],
+        "pc_setups": [s["pc_setups"] for s in stats], "pc_reuse": args.pc_reuse,
         "gmres_its": [s["gmres_its"] for s in stats],
         "phase_ms_per_step": phase,
         "precond": res["info"],
@@ -171,7 +175,7 @@ def main():
     if args.compare_prec:
         mixed = {}
         for p in (1, 2):
-            r2 = run_steps(sk, torch, cfg, coarse, p, args.steps, args.warmup, args.tile)
+            r2 = run_steps(sk, torch, cfg, coarse, p, args.steps, args.warmup, args.tile, args.pc_reuse)
             mixed[{1: "fp32", 2: "bf16"}[p]] = {
                 "steps_per_s": args.steps / r2["seconds"],
                 "speedup_vs_fp64": (args.steps / r2["seconds"]) / value,

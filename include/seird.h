@@ -114,10 +114,14 @@ typedef struct {
 } seird_krylov_stats;
 
 /* Newton options: stop when ||F(u^k)||_2 <= tol * ||M_L u^n||_2, at most
- * max_it linear solves. */
+ * max_it linear solves.  pc_reuse: a preconditioner setup serves this many
+ * further Newton iterations of the same step before it is rebuilt (0 = a
+ * fresh setup at every iteration; the converged root does not depend on
+ * it, only the GMRES iteration counts do). */
 typedef struct {
   double tol;
   int32_t max_it;
+  int32_t pc_reuse;
 } seird_newton_opts;
 
 #define SEIRD_MAX_NEWTON 32
@@ -128,6 +132,7 @@ typedef struct {
   double res_hist[SEIRD_MAX_NEWTON + 1]; /* scaled residuals */
   double eps;      /* ||u^{k+1}-u^k|| / ||u^n|| of the last update (Eq. picardtol) */
   int32_t reason;  /* SEIRD_OK or the failing status */
+  int32_t pc_setups; /* preconditioner setups done in this step */
   double t_residual_ms, t_jacobian_ms, t_setup_ms, t_gmres_ms;
   /* HIP-event time of the subdomain solve launches (the RAS apply kernel)
    * during this step, their count, and the bytes one launch reads/writes
@@ -195,6 +200,28 @@ void seird_precond_destroy(seird_precond pc);
 seird_status seird_precond_info(seird_precond pc, int64_t *factor_entries,
                                 int64_t *coarse_n, int32_t *max_local_nodes,
                                 int32_t *max_bandwidth);
+/* Host-only analysis of the Schwarz decomposition (no device calls):
+ * builds the mesh graph, subdomains, local orderings and tile-band
+ * geometry exactly as seird_precond_create does and reports their sizes.
+ * l2g_out [local_unknowns] (nullable) receives, subdomain after
+ * subdomain, the global unknown of every local unknown in local order;
+ * owned_out [local_unknowns] (nullable) its owner flag (D_i). */
+typedef struct {
+  int64_t factor_entries;   /* tile-band entries, subdomains + coarse */
+  int64_t local_unknowns;   /* sum of subdomain sizes (unknowns) */
+  int32_t max_local_nodes;
+  int32_t max_bandwidth;    /* node bandwidth of the local orderings */
+  double mean_bandwidth;
+  int64_t coarse_n;
+  int32_t coarse_bandwidth;
+} seird_schwarz_info;
+seird_status seird_analyze_schwarz(int64_t n_nodes, const double *xy,
+                                   int64_t n_tri, const int32_t *tri,
+                                   const seird_schwarz_opts *opts,
+                                   const int32_t *part,
+                                   seird_schwarz_info *info, int32_t *l2g_out,
+                                   uint8_t *owned_out);
+
 /* Enable (1) or disable (0) HIP-event timing of the subdomain solve
  * launches; the totals are reported in seird_step_stats (t_ras_kernel_ms,
  * n_ras_launches) and reset at the end of every seird_step. */

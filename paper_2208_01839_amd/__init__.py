@@ -57,7 +57,7 @@ class _KStats(ctypes.Structure):
 
 
 class _Newton(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int32)]
+    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int32), ("pc_reuse", ctypes.c_int32)]
 
 
 MAX_NEWTON = 32
@@ -68,10 +68,17 @@ class _SStats(ctypes.Structure):
                 ("gmres_its", ctypes.c_int32 * MAX_NEWTON),
                 ("res_hist", ctypes.c_double * (MAX_NEWTON + 1)),
                 ("eps", ctypes.c_double), ("reason", ctypes.c_int32),
-                ("t_residual_ms", ctypes.c_double), ("t_jacobian_ms", ctypes.c_double),
+                ("pc_setups", ctypes.c_int32), ("t_residual_ms", ctypes.c_double), ("t_jacobian_ms", ctypes.c_double),
                 ("t_setup_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
                 ("t_ras_kernel_ms", ctypes.c_double), ("n_ras_launches", ctypes.c_int32),
                 ("ras_bytes_per_launch", ctypes.c_double)]
+
+
+class _SInfo(ctypes.Structure):
+    _fields_ = [("factor_entries", ctypes.c_int64), ("local_unknowns", ctypes.c_int64),
+                ("max_local_nodes", ctypes.c_int32), ("max_bandwidth", ctypes.c_int32),
+                ("mean_bandwidth", ctypes.c_double), ("coarse_n", ctypes.c_int64),
+                ("coarse_bandwidth", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -97,6 +104,8 @@ _SIGS = {
     "seird_precond_info": ([_P, _I64P, _I64P, _I32P, _I32P], ctypes.c_int),
     "seird_precond_setup": ([_P, _P, _P], ctypes.c_int),
     "seird_precond_timing": ([_P, ctypes.c_int], ctypes.c_int),
+    "seird_analyze_schwarz": ([ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.POINTER(_Schwarz), _P,
+                               ctypes.POINTER(_SInfo), _P, _P], ctypes.c_int),
     "seird_precond_apply": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
     "seird_gmres": ([_P, _P, _P, _P, _P, ctypes.POINTER(_Krylov),
                      ctypes.POINTER(_KStats), ctypes.c_int, _P], ctypes.c_int),
@@ -232,6 +241,48 @@ class Problem:
         return out
 
 
+def _schwarz_opts(n_sub, overlap, tile, factor_prec, coarse):
+    o = _Schwarz()
+    o.n_sub, o.overlap, o.tile, o.factor_prec = int(n_sub), int(overlap), int(tile), int(factor_prec)
+    keep = []
+    if coarse is not None:
+        parents, n_coarse = coarse
+        level_n = np.array([n_coarse] + [len(p) for p in parents], dtype=np.int64)
+        par = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.int32).reshape(-1)
+                                                   for p in parents]), dtype=np.int32)
+        keep = [level_n, par]
+        o.n_ref = len(parents)
+        o.level_n = level_n.ctypes.data_as(_I64P)
+        o.parents = par.ctypes.data_as(_I32P)
+    else:
+        o.n_ref = 0
+    return o, keep
+
+
+def analyze_schwarz(xy, tri, part, n_sub, overlap, tile=32, coarse=None, maps=False):
+    """Host-only decomposition analysis (no GPU needed).  Returns a dict of
+    sizes; with maps=True also the local->global unknown map and owner flags
+    of every subdomain, concatenated in subdomain order."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    o, keep = _schwarz_opts(n_sub, overlap, tile, 0, coarse)
+    info = _SInfo()
+    _check(lib().seird_analyze_schwarz(len(xy), xy.ctypes.data, len(tri), tri.ctypes.data,
+                                       ctypes.byref(o), part.ctypes.data, ctypes.byref(info),
+                                       None, None))
+    out = {k: getattr(info, k) for k, _ in _SInfo._fields_}
+    if maps:
+        l2g = np.zeros(info.local_unknowns, dtype=np.int32)
+        owned = np.zeros(info.local_unknowns, dtype=np.uint8)
+        _check(lib().seird_analyze_schwarz(len(xy), xy.ctypes.data, len(tri), tri.ctypes.data,
+                                           ctypes.byref(o), part.ctypes.data, ctypes.byref(info),
+                                           l2g.ctypes.data, owned.ctypes.data))
+        out["l2g"], out["owned"] = l2g, owned
+    del keep
+    return out
+
+
 class Precond:
     """Restricted additive Schwarz (one-level, or multiplicative two-grid
     when ``coarse = (parents_list, n_coarse)`` is given)."""
@@ -242,20 +293,7 @@ class Precond:
         part = np.ascontiguousarray(part, dtype=np.int32)
         if len(part) != problem.n:
             raise ValueError("partition length must equal the node count")
-        o = _Schwarz()
-        o.n_sub, o.overlap, o.tile, o.factor_prec = int(n_sub), int(overlap), int(tile), int(factor_prec)
-        keep = []
-        if coarse is not None:
-            parents, n_coarse = coarse
-            level_n = np.array([n_coarse] + [len(p) for p in parents], dtype=np.int64)
-            par = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.int32).reshape(-1)
-                                                       for p in parents]), dtype=np.int32)
-            keep = [level_n, par]
-            o.n_ref = len(parents)
-            o.level_n = level_n.ctypes.data_as(_I64P)
-            o.parents = par.ctypes.data_as(_I32P)
-        else:
-            o.n_ref = 0
+        o, keep = _schwarz_opts(n_sub, overlap, tile, factor_prec, coarse)
         h = ctypes.c_void_p()
         _check(lib().seird_precond_create(problem.h, ctypes.byref(o), part.ctypes.data,
                                           ctypes.byref(h)))
@@ -306,9 +344,9 @@ def gmres(problem: Problem, pc, vals, b, transpose=False, x=None, **kw):
     return x, stats
 
 
-def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, **kw):
+def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, pc_reuse=0, **kw):
     """One implicit step in place on u (float64 CUDA [n,5]).  Returns stats."""
-    n = _Newton(float(tol), int(max_it))
+    n = _Newton(float(tol), int(max_it), int(pc_reuse))
     o = _krylov(**kw)
     s = _SStats()
     code = lib().seird_step(problem.h, pc.h if pc is not None else None,
@@ -316,7 +354,7 @@ def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, **kw):
                             ctypes.byref(n), ctypes.byref(o), ctypes.byref(s), _stream())
     k = s.newton_its
     stats = dict(newton_its=k, gmres_its=list(s.gmres_its[:k]), gmres_its_total=s.gmres_its_total,
-                 res_hist=list(s.res_hist[:k + 1]), eps=s.eps, reason=s.reason,
+                 res_hist=list(s.res_hist[:k + 1]), eps=s.eps, reason=s.reason, pc_setups=s.pc_setups,
                  t_residual_ms=s.t_residual_ms, t_jacobian_ms=s.t_jacobian_ms,
                  t_setup_ms=s.t_setup_ms, t_gmres_ms=s.t_gmres_ms,
                  t_ras_kernel_ms=s.t_ras_kernel_ms, n_ras_launches=s.n_ras_launches,

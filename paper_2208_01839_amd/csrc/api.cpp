@@ -98,8 +98,10 @@ struct seird_problem_s {
 struct seird_precond_s {
   seird_problem prob = nullptr;
   PrecondHost ph;
-  double *F64 = nullptr;
-  void *Flow = nullptr;
+  void *Fs = nullptr;        // subdomain factors as factorised (float64, or float32)
+  bool sub_float = false;
+  void *Fb = nullptr;        // bfloat16 copy for factor_prec 2, float32 copy for tile 16 + factor_prec 1
+  double *Fc = nullptr;      // coarse factors (float64)
   SubInfo *subs_dev = nullptr;
   int32_t *order_dev = nullptr;
   ExtractEntry *ent_dev = nullptr;
@@ -110,7 +112,6 @@ struct seird_precond_s {
   int32_t *g2l_idx = nullptr;
   double *yloc = nullptr;
   int max_nt = 0, max_bu = 0;
-  bool sub_lds = true;
   // coarse
   SubInfo *coarse_dev = nullptr;
   int32_t *gp = nullptr, *gq = nullptr, *gref = nullptr, *cperm = nullptr;
@@ -119,10 +120,14 @@ struct seird_precond_s {
   int64_t *z_ptr = nullptr, *zt_ptr = nullptr;
   int32_t *z_col = nullptr, *zt_col = nullptr;
   double *z_val = nullptr, *zt_val = nullptr;
-  double *rc = nullptr, *xc = nullptr, *cscratch = nullptr, *sscratch = nullptr;
+  double *rc = nullptr, *xc = nullptr, *cscratch = nullptr, *ybuf = nullptr;
   double *t1 = nullptr;
   const double *vals_setup = nullptr;  // Jacobian of the last setup (borrowed)
   bool ready = false;
+  // second stream (default priority) for the coarse factorisation, which
+  // runs concurrently with the subdomain factorisation
+  hipStream_t st_coarse = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // optional HIP-event timing of the subdomain solve launches
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -134,7 +139,7 @@ struct seird_precond_s {
     // algorithmic bytes of one subdomain-solve launch: every stored factor
     // entry once, plus per local unknown the index, the owner flag and the
     // gathered value, plus the owned results written
-    const int64_t nsubent = ph.two_level ? ph.coarse.base : ph.factor_entries;
+    const int64_t nsubent = ph.factor_entries;
     const double fsz = ph.prec == 0 ? 8.0 : (ph.prec == 1 ? 4.0 : 2.0);
     return nsubent * fsz + (double)ph.l2g.size() * (4 + 1 + 8) + (double)prob->N * 8;
   }
@@ -149,18 +154,26 @@ struct seird_precond_s {
   }
 
   ~seird_precond_s() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (st_coarse) (void)hipStreamDestroy(st_coarse);
     for (auto &e : ev) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
     }
-    dev_free(F64); dev_free(Flow); dev_free(subs_dev); dev_free(order_dev); dev_free(ent_dev); dev_free(l2g);
+    dev_free(Fs); dev_free(Fb); dev_free(Fc); dev_free(subs_dev); dev_free(order_dev); dev_free(ent_dev); dev_free(l2g);
     dev_free(owned); dev_free(status); dev_free(g2l_ptr); dev_free(g2l_idx); dev_free(yloc);
     dev_free(coarse_dev); dev_free(gp); dev_free(gq); dev_free(gref); dev_free(cperm); dev_free(gptr); dev_free(gw);
     dev_free(z_ptr); dev_free(zt_ptr); dev_free(z_col); dev_free(zt_col); dev_free(z_val); dev_free(zt_val);
-    dev_free(rc); dev_free(xc); dev_free(cscratch); dev_free(sscratch); dev_free(t1);
+    dev_free(rc); dev_free(xc); dev_free(cscratch); dev_free(ybuf); dev_free(t1);
   }
 
-  const void *factors() const { return ph.prec == 0 ? (const void *)F64 : Flow; }
+  // factors read by the subdomain solves, in the storage precision ph.prec
+  const void *factors() const {
+    if (ph.prec == 0) return Fs;
+    if (ph.prec == 1) return sub_float ? Fs : Fb;
+    return Fb;
+  }
 
   void ras(const double *r, double *z, int add, int transpose, hipStream_t st) {
     SolveLaunch sl;
@@ -170,8 +183,6 @@ struct seird_precond_s {
     sl.subs = subs_dev;
     sl.order = order_dev;
     sl.nblocks = ph.n_sub;
-    sl.max_nt = max_nt;
-    sl.use_lds = sub_lds;
     sl.l2g = l2g;
     sl.owned = owned;
     sl.r = r;
@@ -179,8 +190,7 @@ struct seird_precond_s {
     sl.add = add;
     sl.transpose = transpose;
     sl.yloc = yloc;
-    sl.scratch = sscratch;
-    sl.scratch_stride = (int64_t)max_nt * ph.tile;
+    sl.ybuf = ybuf;
     if (timing) {
       if (ev_used == ev.size()) {
         hipEvent_t a0, a1;
@@ -204,17 +214,15 @@ struct seird_precond_s {
     SolveLaunch sl;
     sl.tile = ph.tile;
     sl.prec = 0;  // the coarse factor is always float64
-    sl.F = F64;
+    sl.F = Fc;
     sl.subs = coarse_dev;
     sl.order = nullptr;
     sl.nblocks = 1;
-    sl.max_nt = ph.coarse.nt;
-    sl.use_lds = false;
+    sl.wide = true;
     sl.r = rc;
     sl.z = xc;
     sl.transpose = transpose;
-    sl.scratch = cscratch;
-    sl.scratch_stride = 0;
+    sl.ybuf = cscratch;
     launch_band_solve(sl, st);
     launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
   }
@@ -496,14 +504,25 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
       pc->max_nt = std::max(pc->max_nt, s.nt);
       pc->max_bu = std::max(pc->max_bu, s.bu);
     }
-    const size_t lu_lds = 4 * (size_t)T * (T + 1) * 8 + (size_t)pc->max_bu * T * (T + 1) * 8;
+    if (T == 32 && pc->max_bu > 16)
+      fail(SEIRD_ERR_ARG, "subdomain bandwidth above 16 tiles; use more subdomains");
+    pc->sub_float = (T == 32 && ph.prec > 0);
+    const size_t csz = pc->sub_float ? 4 : 8;
+    const size_t lu_lds = 4 * (size_t)T * (T + 1) * csz + (size_t)pc->max_bu * T * (T + 1) * csz;
     if (lu_lds > p->lds_limit)
       fail(SEIRD_ERR_ARG, "subdomain bandwidth too large for the LDS of this device (" + std::to_string(lu_lds) +
                               " > " + std::to_string(p->lds_limit) + " bytes); use more subdomains or tile 16");
-    pc->sub_lds = (size_t)pc->max_nt * T * 8 + 4096 <= p->lds_limit;
-    pc->F64 = dev_alloc<double>(ph.factor_entries);
-    if (ph.prec == 1) pc->Flow = dev_alloc<float>(ph.factor_entries);
-    if (ph.prec == 2) pc->Flow = dev_alloc<uint16_t>(ph.factor_entries);
+    for (const SubInfo &s : ph.subs)
+      if (s.bl >= 32 || s.bu >= 32) fail(SEIRD_ERR_ARG, "subdomain block bandwidth must be below 32 tiles");
+    if (ph.two_level && (ph.coarse.bl >= 32 || ph.coarse.bu >= 32))
+      fail(SEIRD_ERR_ARG, "coarse block bandwidth must be below 32 tiles; use a coarser level or tile 32");
+    if (pc->sub_float)
+      pc->Fs = dev_alloc<float>(ph.factor_entries);
+    else
+      pc->Fs = dev_alloc<double>(ph.factor_entries);
+    if (ph.prec == 1 && !pc->sub_float) pc->Fb = dev_alloc<float>(ph.factor_entries);
+    if (ph.prec == 2) pc->Fb = dev_alloc<uint16_t>(ph.factor_entries);
+    if (ph.two_level) pc->Fc = dev_alloc<double>(ph.coarse_entries);
     pc->subs_dev = dev_upload(ph.subs);
     pc->order_dev = dev_upload(ph.order);
     pc->ent_dev = dev_upload(ph.extract);
@@ -523,8 +542,7 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
       pc->g2l_idx = dev_upload(gidx);
       pc->yloc = dev_alloc<double>(ph.l2g.size());
     }
-    if (!pc->sub_lds)  // local vectors too large for LDS: one global scratch row per subdomain
-      pc->sscratch = dev_alloc<double>((size_t)ph.n_sub * pc->max_nt * T);
+    pc->ybuf = dev_alloc<double>(ph.l2g.size());
     if (ph.two_level) {
       pc->coarse_dev = dev_upload(std::vector<SubInfo>{ph.coarse});
       pc->gp = dev_upload(ph.gal_p);
@@ -545,6 +563,9 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
       pc->cscratch = dev_alloc<double>(cpad);
       HIPCHECK(hipMemset(pc->rc, 0, sizeof(double) * cpad));
       pc->t1 = dev_alloc<double>(p->N);
+      HIPCHECK(hipStreamCreateWithFlags(&pc->st_coarse, hipStreamNonBlocking));
+      HIPCHECK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
+      HIPCHECK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
     }
   } catch (...) {
     delete pc;
@@ -555,6 +576,27 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
 }
 
 void seird_precond_destroy(seird_precond pc) { delete pc; }
+
+seird_status seird_analyze_schwarz(int64_t n_nodes, const double *xy, int64_t n_tri, const int32_t *tri,
+                                   const seird_schwarz_opts *opts, const int32_t *part, seird_schwarz_info *info,
+                                   int32_t *l2g_out, uint8_t *owned_out) {
+  API_BEGIN
+  if (!opts || !info) fail(SEIRD_ERR_ARG, "null argument");
+  MeshHost mh;
+  build_mesh(n_nodes, xy, n_tri, tri, mh);
+  PrecondHost ph;
+  build_precond(mh, *opts, part, ph);
+  info->factor_entries = ph.factor_entries + ph.coarse_entries;
+  info->local_unknowns = (int64_t)ph.l2g.size();
+  info->max_local_nodes = ph.max_nodes;
+  info->max_bandwidth = ph.max_bw;
+  info->mean_bandwidth = ph.mean_bw;
+  info->coarse_n = ph.nc;
+  info->coarse_bandwidth = ph.coarse_bw;
+  if (l2g_out) std::memcpy(l2g_out, ph.l2g.data(), sizeof(int32_t) * ph.l2g.size());
+  if (owned_out) std::memcpy(owned_out, ph.owned.data(), ph.owned.size());
+  API_END
+}
 
 seird_status seird_precond_timing(seird_precond pc, int enable) {
   API_BEGIN
@@ -567,7 +609,7 @@ seird_status seird_precond_info(seird_precond pc, int64_t *factor_entries, int64
                                 int32_t *max_local_nodes, int32_t *max_bandwidth) {
   API_BEGIN
   if (!pc) fail(SEIRD_ERR_ARG, "null preconditioner");
-  if (factor_entries) *factor_entries = pc->ph.factor_entries;
+  if (factor_entries) *factor_entries = pc->ph.factor_entries + pc->ph.coarse_entries;
   if (coarse_n) *coarse_n = pc->ph.nc;
   if (max_local_nodes) *max_local_nodes = pc->ph.max_nodes;
   if (max_bandwidth) *max_bandwidth = pc->ph.max_bw;
@@ -580,8 +622,11 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
   HIPCHECK(hipMemsetAsync(pc->status, 0, sizeof(int), st));
   FactorLaunch fl;
   fl.tile = ph.tile;
-  fl.F = pc->F64;
-  fl.entries = ph.factor_entries;
+  fl.Fs = pc->Fs;
+  fl.sub_float = pc->sub_float;
+  fl.sub_entries = ph.factor_entries;
+  fl.Fc = pc->Fc;
+  fl.coarse_entries = ph.coarse_entries;
   fl.subs = pc->subs_dev;
   fl.nsub = ph.n_sub;
   fl.order = pc->order_dev;
@@ -600,13 +645,18 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
     fl.gw = pc->gw;
     fl.gal_nblk = (int64_t)ph.gal_p.size();
   }
-  launch_setup_factors(fl, P->diag(vals), P->off(vals), st);
-  HIPCHECK(hipGetLastError());
-  if (ph.prec != 0) {
-    // only the subdomain factors are used in reduced precision
-    const int64_t nsubent = ph.two_level ? ph.coarse.base : ph.factor_entries;
-    launch_convert(pc->Flow, ph.prec, pc->F64, nsubent, st);
+  if (ph.two_level) {
+    // fork: the coarse chain waits for everything already queued on st
+    HIPCHECK(hipEventRecord(pc->ev_fork, st));
+    HIPCHECK(hipStreamWaitEvent(pc->st_coarse, pc->ev_fork, 0));
+    launch_setup_factors(fl, P->diag(vals), P->off(vals), st, pc->st_coarse);
+    HIPCHECK(hipEventRecord(pc->ev_join, pc->st_coarse));
+    HIPCHECK(hipStreamWaitEvent(st, pc->ev_join, 0));
+  } else {
+    launch_setup_factors(fl, P->diag(vals), P->off(vals), st, st);
   }
+  HIPCHECK(hipGetLastError());
+  if (pc->Fb) launch_convert(pc->Fb, ph.prec, pc->Fs, pc->sub_float ? 1 : 0, ph.factor_entries, st);
   int status = 0;
   HIPCHECK(hipMemcpyAsync(&status, pc->status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
@@ -660,6 +710,7 @@ seird_status seird_step(seird_problem p, seird_precond pc, double *u, double dt,
   try {
     if (!p || !u || !nopts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
     if (nopts->max_it < 0 || nopts->max_it > SEIRD_MAX_NEWTON) fail(SEIRD_ERR_ARG, "Newton max_it out of range");
+    if (nopts->pc_reuse < 0) fail(SEIRD_ERR_ARG, "pc_reuse must be >= 0");
     hipStream_t st = (hipStream_t)stream;
     using clk = std::chrono::steady_clock;
     auto ms = [](clk::time_point a, clk::time_point b) {
@@ -680,6 +731,8 @@ seird_status seird_step(seird_problem p, seird_precond pc, double *u, double dt,
     const double scale = p->norm(p->u_prev, st, p->md.mass);
     const double unorm = p->norm(p->u_prev, st);
     double *diag = p->vals, *off = p->vals + 25 * p->mh.n;
+    int last_setup = 0, its_fresh = 0;
+    bool stale = false;
     for (int k = 0;; ++k) {
       auto t0 = clk::now();
       launch_residual(p->md, p->P, p->gfield, u, p->u_prev, dt, src, p->F, st);
@@ -693,13 +746,36 @@ seird_status seird_step(seird_problem p, seird_precond pc, double *u, double dt,
       launch_jacobian(p->md, p->P, p->gfield, u, dt, diag, off, st);
       HIPCHECK(hipStreamSynchronize(st));
       s.t_jacobian_ms += ms(t0, clk::now());
+      // preconditioner setup: fresh at the first iteration, then every
+      // pc_reuse + 1 iterations, or when the reused one was marked stale
       t0 = clk::now();
-      if (pc) precond_setup_impl(pc, p->vals, st);
+      bool fresh = false;
+      if (pc && (k == 0 || stale || (k - last_setup) > nopts->pc_reuse)) {
+        precond_setup_impl(pc, p->vals, st);
+        s.pc_setups++;
+        last_setup = k;
+        stale = false;
+        fresh = true;
+      }
       s.t_setup_ms += ms(t0, clk::now());
       t0 = clk::now();
       launch_axpby(p->rhs, p->F, -1.0, nullptr, 0, 0.0, N, p->nb, st);
       seird_krylov_stats ks{};
       int rc = gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, 0, st);
+      if (pc && !fresh && rc != SEIRD_OK) {
+        // a reused setup failed: rebuild it from the current Jacobian and retry
+        auto t1 = clk::now();
+        precond_setup_impl(pc, p->vals, st);
+        s.pc_setups++;
+        last_setup = k;
+        s.t_setup_ms += ms(t1, clk::now());
+        const int its_first = ks.its;
+        rc = gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, 0, st);
+        ks.its += its_first;
+        fresh = true;
+      }
+      if (fresh) its_fresh = ks.its;
+      else if (ks.its > 2 * its_fresh + 5) stale = true;  // reuse no longer pays
       s.t_gmres_ms += ms(t0, clk::now());
       if (pc && pc->timing) {
         HIPCHECK(hipStreamSynchronize(st));

@@ -52,6 +52,7 @@ void dev_free(void *p);
 // ---------------------------------------------------------------------
 struct MeshHost {
   int64_t n = 0, nt = 0;
+  std::vector<double> xy;       // node coordinates [n][2] (local orderings)
   std::vector<int64_t> rowptr;  // [n+1]
   std::vector<int32_t> col;     // [nslots]
   std::vector<int32_t> tslot;   // slot (i,j) -> slot (j,i)
@@ -108,9 +109,12 @@ struct PrecondHost {
   std::vector<uint8_t> owned;         // per local unknown: owned by the sub
   std::vector<ExtractEntry> extract;  // block entries
   std::vector<int32_t> order;         // subdomain processing order (LPT)
-  int64_t factor_entries = 0;
+  int64_t factor_entries = 0;   // subdomain tile-band entries
+  int64_t coarse_entries = 0;   // coarse tile-band entries (own buffer)
   int32_t max_nodes = 0, max_bw = 0;
   int32_t max_nloc = 0;
+  double mean_bw = 0.0;
+  int32_t coarse_bw = 0;
   // two-level
   bool two_level = false;
   int64_t nc = 0;                      // coarse nodes

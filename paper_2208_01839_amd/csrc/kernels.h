@@ -9,8 +9,11 @@ constexpr int KRYLOV_MAX = 32;  // max basis vectors handled by one Arnoldi kern
 
 struct FactorLaunch {
   int tile = 32;
-  double *F = nullptr;  // float64 tile-band storage (all subdomains + coarse)
-  int64_t entries = 0;
+  void *Fs = nullptr;       // subdomain tile-band storage (float64, or float32 if sub_float)
+  bool sub_float = false;   // factorise the subdomains in float32
+  int64_t sub_entries = 0;
+  double *Fc = nullptr;     // coarse tile-band storage (float64)
+  int64_t coarse_entries = 0;
   const SubInfo *subs = nullptr;  // device
   int nsub = 0;
   const int32_t *order = nullptr;
@@ -36,8 +39,7 @@ struct SolveLaunch {
   const SubInfo *subs = nullptr;
   const int32_t *order = nullptr;
   int nblocks = 0;
-  int max_nt = 0;
-  bool use_lds = true;
+  bool wide = false;  // 1024-thread workgroups (one large system)
   const int32_t *l2g = nullptr;
   const uint8_t *owned = nullptr;
   const double *r = nullptr;
@@ -45,8 +47,7 @@ struct SolveLaunch {
   int add = 0;
   int transpose = 0;
   double *yloc = nullptr;
-  double *scratch = nullptr;
-  int64_t scratch_stride = 0;
+  double *ybuf = nullptr;  // forward-sweep results, sum of n_loc (or coarse n_loc) doubles
 };
 
 void launch_residual(const MeshDev &m, const ParamsDev &P, const double *g, const double *u, const double *up,
@@ -66,8 +67,10 @@ void launch_axpby(double *y, const double *x, double a, const double *aptr, int 
                   hipStream_t st);
 void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st);
 void launch_check_state(const double *u, int64_t n, int *flags, hipStream_t st);
-void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st);
-void launch_convert(void *dst, int prec, const double *src, int64_t N, hipStream_t st);
+// the coarse factorisation goes to st_coarse (may equal st), the subdomains to st
+void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st,
+                          hipStream_t st_coarse);
+void launch_convert(void *dst, int dst_prec, const void *src, int src_float, int64_t N, hipStream_t st);
 void launch_band_solve(const SolveLaunch &sl, hipStream_t st);
 void launch_gather_copies(const int64_t *gptr, const int32_t *gidx, const double *yloc, double *z, int add, int64_t N,
                           hipStream_t st);

@@ -375,17 +375,17 @@ __device__ inline int64_t tile_entry_checked(const SubInfo &s, int32_t l, int32_
 }
 
 // identity on the padded diagonal of the last block row (storage zeroed before)
-template <int T>
-__global__ void k_pad_identity(double *__restrict__ F, const SubInfo *__restrict__ subs, int nsubs) {
+template <int T, class ET>
+__global__ void k_pad_identity(ET *__restrict__ F, const SubInfo *__restrict__ subs, int nsubs) {
   const int s = blockIdx.x;
   if (s >= nsubs) return;
   const SubInfo si = subs[s];
-  for (int32_t l = si.n_loc + threadIdx.x; l < si.nt * T; l += blockDim.x) F[tile_entry<T>(si, l, l)] = 1.0;
+  for (int32_t l = si.n_loc + threadIdx.x; l < si.nt * T; l += blockDim.x) F[tile_entry<T>(si, l, l)] = (ET)1.0;
 }
 
 // one thread per (entry, c): writes row 5p+c, columns 5q..5q+4
-template <int T>
-__global__ __launch_bounds__(256) void k_extract(double *__restrict__ F, const SubInfo *__restrict__ subs,
+template <int T, class ET>
+__global__ __launch_bounds__(256) void k_extract(ET *__restrict__ F, const SubInfo *__restrict__ subs,
                                                  const ExtractEntry *__restrict__ ent, int64_t nent,
                                                  const double *__restrict__ diag, const double *__restrict__ off,
                                                  int *status) {
@@ -408,40 +408,58 @@ __global__ __launch_bounds__(256) void k_extract(double *__restrict__ F, const S
       const double *o = off + 10 * (int64_t)e.ref;
       v = o[5 + c] + (cp == c ? o[c] : 0.0);
     }
-    F[at] = v;
+    F[at] = (ET)v;
   }
 }
 
 // Galerkin coarse matrix: coarse block k (local positions p, q) =
-// sum_j w_j * fine block(ref_j), written into the coarse tile-band storage
+// sum_j w_j * fine block(ref_j), written into the coarse tile-band storage.
+// One wave per coarse block: lanes stride over its contributions, each lane
+// accumulates the 25 entries, then a fixed-order wave reduction.
 template <int T>
 __global__ __launch_bounds__(256) void k_galerkin(double *__restrict__ F, SubInfo cs, const int32_t *__restrict__ gp,
                                                   const int32_t *__restrict__ gq, const int64_t *__restrict__ gptr,
                                                   const int32_t *__restrict__ gref, const double *__restrict__ gw,
                                                   int64_t nblk, const double *__restrict__ diag,
                                                   const double *__restrict__ off, int *status) {
-  // 25 threads per coarse block entry (c, c')
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nblk * 25) return;
-  const int64_t k = t / 25;
-  const int c = (int)(t % 25) / 5, cp = (int)(t % 5);
-  double acc = 0.0;
-  for (int64_t j = gptr[k]; j < gptr[k + 1]; ++j) {
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (k >= nblk) return;  // uniform per wave
+  double acc[25];
+#pragma unroll
+  for (int e = 0; e < 25; ++e) acc[e] = 0.0;
+  for (int64_t j = gptr[k] + lane; j < gptr[k + 1]; j += 64) {
     const int32_t ref = gref[j];
-    double v;
-    if (ref < 0)
-      v = diag[25 * (int64_t)(-ref - 1) + 5 * c + cp];
-    else {
+    const double w = gw[j];
+    if (ref < 0) {
+      const double *D = diag + 25 * (int64_t)(-ref - 1);
+#pragma unroll
+      for (int e = 0; e < 25; ++e) acc[e] += w * D[e];
+    } else {
       const double *o = off + 10 * (int64_t)ref;
-      v = o[5 + c] + (c == cp ? o[c] : 0.0);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const double b = w * o[5 + c];
+#pragma unroll
+        for (int cp = 0; cp < 5; ++cp) acc[5 * c + cp] += b;
+        acc[5 * c + c] += w * o[c];
+      }
     }
-    acc += gw[j] * v;
   }
-  const int64_t at = tile_entry_checked<T>(cs, 5 * gp[k] + c, 5 * gq[k] + cp);
-  if (at < 0)
-    atomicOr(status, 2);
-  else
-    F[at] = acc;
+#pragma unroll
+  for (int e = 0; e < 25; ++e) acc[e] = wave_sum(acc[e]);
+  if (lane < 25) {
+    double v = 0.0;
+#pragma unroll
+    for (int e = 0; e < 25; ++e)
+      if (e == lane) v = acc[e];
+    const int c = lane / 5, cp = lane % 5;
+    const int64_t at = tile_entry_checked<T>(cs, 5 * gp[k] + c, 5 * gq[k] + cp);
+    if (at < 0)
+      atomicOr(status, 2);
+    else
+      F[at] = v;
+  }
 }
 
 template <class FT>
@@ -461,11 +479,11 @@ __device__ inline double from_ft<float>(float v) { return (double)v; }
 template <>
 __device__ inline double from_ft<__hip_bfloat16>(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
 
-template <class FT>
-__global__ void k_convert(FT *__restrict__ dst, const double *__restrict__ src, int64_t N) {
+template <class FT, class ST>
+__global__ void k_convert(FT *__restrict__ dst, const ST *__restrict__ src, int64_t N) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride)
-    dst[idx] = to_ft<FT>(src[idx]);
+    dst[idx] = to_ft<FT>((double)src[idx]);
 }
 
 // ----------------------------------------------------------------------
@@ -473,25 +491,25 @@ __global__ void k_convert(FT *__restrict__ dst, const double *__restrict__ src, 
 // Device routines work on one tile operation with the whole workgroup
 // (256 threads).  LDS tiles are padded to T+1 columns.
 // ----------------------------------------------------------------------
-template <int T>
+template <int T, class CT = double>
 struct LuLds {
-  double D[T][T + 1];   // diagonal tile being factored
-  double Li[T][T + 1];  // L_KK^{-1} (unit lower)
-  double Ui[T][T + 1];  // U_KK^{-1} (upper)
-  double S[T][T + 1];   // staging
+  CT D[T][T + 1];   // diagonal tile being factored
+  CT Li[T][T + 1];  // L_KK^{-1} (unit lower)
+  CT Ui[T][T + 1];  // U_KK^{-1} (upper)
+  CT S[T][T + 1];   // staging
 };
 
 // Factor the diagonal tile at dk in place and replace it by (strict lower of
 // L^{-1}) + (upper of U^{-1}); keeps Li/Ui in LDS.  Raises *status on a bad pivot.
-template <int T>
-__device__ void lu_diag_tile(double *__restrict__ dk, LuLds<T> &L, int *status) {
+template <int T, class CT>
+__device__ void lu_diag_tile(CT *__restrict__ dk, LuLds<T, CT> &L, int *status) {
   const int tid = threadIdx.x;
   for (int e = tid; e < T * T; e += 256) L.D[e / T][e % T] = dk[e];
   __syncthreads();
   for (int k = 0; k < T; ++k) {
-    const double piv = L.D[k][k];
-    if (tid == 0 && (!isfinite(piv) || fabs(piv) < 1e-300)) atomicOr(status, 1);
-    const double rp = 1.0 / piv;
+    const CT piv = L.D[k][k];
+    if (tid == 0 && (!isfinite((double)piv) || fabs((double)piv) < 1e-300)) atomicOr(status, 1);
+    const CT rp = (CT)1 / piv;
     for (int i = k + 1 + tid; i < T; i += 256) L.D[i][k] *= rp;
     __syncthreads();
     const int w = T - k - 1;
@@ -512,7 +530,7 @@ __device__ void lu_diag_tile(double *__restrict__ dk, LuLds<T> &L, int *status) 
     // Li: rows i > k, columns j <= k: Li[i][j] -= L[i][k] Li[k][j]
     // Ui: row kk = T-1-k is final after scaling by 1/U[kk][kk]
     const int kk = T - 1 - k;
-    const double ud = 1.0 / L.D[kk][kk];
+    const CT ud = (CT)1 / L.D[kk][kk];
     for (int j = kk + tid; j < T; j += 256) L.Ui[kk][j] *= ud;
     __syncthreads();
     const int nl = (T - 1 - k) * (k + 1);
@@ -537,7 +555,7 @@ __device__ void lu_diag_tile(double *__restrict__ dk, LuLds<T> &L, int *status) 
 
 // load Li/Ui from a stored (inverted) diagonal tile
 template <int T>
-__device__ void load_diag_inverses(const double *__restrict__ dk, LuLds<T> &L) {
+__device__ void load_diag_inverses(const double *__restrict__ dk, LuLds<T, double> &L) {
   for (int e = threadIdx.x; e < T * T; e += 256) {
     const int i = e / T, j = e % T;
     const double v = dk[e];
@@ -549,7 +567,7 @@ __device__ void load_diag_inverses(const double *__restrict__ dk, LuLds<T> &L) {
 
 // X = A Ui (lower panel) or X = Li A (upper panel), in place at tile a
 template <int T>
-__device__ void panel_tile(double *__restrict__ a, LuLds<T> &L, bool lower) {
+__device__ void panel_tile(double *__restrict__ a, LuLds<T, double> &L, bool lower) {
   for (int e = threadIdx.x; e < T * T; e += 256) L.S[e / T][e % T] = a[e];
   __syncthreads();
   for (int e = threadIdx.x; e < T * T; e += 256) {
@@ -592,8 +610,8 @@ __device__ void schur_tile(double *__restrict__ C, const double (*Sa)[T + 1], co
   }
 }
 
-template <int T>
-__device__ inline double *tile_at(double *F, const SubInfo &s, int K, int slot) {
+template <int T, class CT = double>
+__device__ inline CT *tile_at(CT *F, const SubInfo &s, int K, int slot) {
   return F + s.base + ((int64_t)K * (s.bl + s.bu + 1) + slot) * (T * T);
 }
 
@@ -602,7 +620,7 @@ __device__ inline double *tile_at(double *F, const SubInfo &s, int K, int slot) 
 template <int T>
 __global__ __launch_bounds__(256) void k_band_lu(double *__restrict__ F, const SubInfo *__restrict__ subs,
                                                  const int32_t *__restrict__ order, int *status) {
-  __shared__ LuLds<T> L;
+  __shared__ LuLds<T, double> L;
   extern __shared__ double upanel_raw[];
   double(*Up)[T][T + 1] = reinterpret_cast<double(*)[T][T + 1]>(upanel_raw);
   const SubInfo s = subs[order[blockIdx.x]];
@@ -626,16 +644,154 @@ __global__ __launch_bounds__(256) void k_band_lu(double *__restrict__ F, const S
   }
 }
 
+// ----------------------------------------------------------------------
+// Tile-band LU with 32x32 tiles and the Schur update on MFMA.
+// One workgroup (4 waves) per subdomain.  Per block column K: the diagonal
+// tile is factored and inverted in LDS; the U panel (bu tiles) is staged in
+// LDS once and multiplied by L_KK^{-1}; then for every block row I below,
+// the C tiles of the whole strip (I, K+1..K+bu) are loaded into MFMA
+// accumulators at once, L_IK = A_IK U_KK^{-1} is formed, and the strip is
+// updated C -= L_IK U_K,* with 16x16x4 MFMAs (wave w owns tiles w, w+4, ..).
+// CT = double uses v_mfma_f64_16x16x4f64, CT = float v_mfma_f32_16x16x4f32.
+// MFMA operand layouts (16x16x4): A[i][k] in lane i + 16 k; B[k][j] in lane
+// j + 16 k.  Accumulator element v of lane l holds column l % 16 and row
+// 4 (l / 16) + v for f32, but row (l / 16) + 4 v for f64 (one-row groups).
+// ----------------------------------------------------------------------
+template <class CT>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int lk, int v) { return 4 * lk + v; }
+};
+
+template <class CT>
+__global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const SubInfo *__restrict__ subs,
+                                                   const int32_t *__restrict__ order, int *status) {
+  constexpr int T = 32;
+  typedef typename Mfma<CT>::v4 v4;
+  __shared__ LuLds<T, CT> L;
+  extern __shared__ __align__(16) unsigned char up_raw[];
+  CT(*Up)[T][T + 1] = reinterpret_cast<CT(*)[T][T + 1]>(up_raw);
+  const SubInfo s = subs[order[blockIdx.x]];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int K = 0; K < s.nt; ++K) {
+    lu_diag_tile<T, CT>(tile_at<T, CT>(F, s, K, s.bl), L, status);
+    const int je = min(K + s.bu, s.nt - 1), nu = je - K;
+    const int ie = min(K + s.bl, s.nt - 1);
+    // U panel: U_KJ = L_KK^{-1} A_KJ, kept in LDS for the whole step
+    for (int jj = 0; jj < nu; ++jj) {
+      const CT *a = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
+      for (int e = tid; e < T * T; e += 256) Up[jj][e / T][e % T] = a[e];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nu; ++jj) {
+      CT out[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int e = tid + 256 * m, i = e / T, j = e % T;
+        CT acc = Up[jj][i][j];
+        for (int k = 0; k < i; ++k) acc += L.Li[i][k] * Up[jj][k][j];
+        out[m] = acc;
+      }
+      __syncthreads();
+      CT *a = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int e = tid + 256 * m;
+        Up[jj][e / T][e % T] = out[m];
+        a[e] = out[m];
+      }
+    }
+    __syncthreads();
+    for (int I = K + 1; I <= ie; ++I) {
+      // C strip into accumulators (all loads issued before any use)
+      v4 acc[4][2][2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int jj = wave + 4 * q;
+        if (jj < nu) {
+          const CT *c = tile_at<T, CT>(F, s, I, K + 1 + jj - I + s.bl);
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[q][bi][bj][v] = c[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr];
+        }
+      }
+      CT *aik = tile_at<T, CT>(F, s, I, K - I + s.bl);
+      for (int e = tid; e < T * T; e += 256) L.S[e / T][e % T] = aik[e];
+      __syncthreads();
+      // L_IK = A_IK U_KK^{-1}
+      CT out[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int e = tid + 256 * m, i = e / T, j = e % T;
+        CT a = 0;
+        for (int k = 0; k <= j; ++k) a += L.S[i][k] * L.Ui[k][j];
+        out[m] = a;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int e = tid + 256 * m;
+        L.S[e / T][e % T] = out[m];
+        aik[e] = out[m];
+      }
+      __syncthreads();
+      // C -= L_IK U_KJ on MFMA
+#pragma unroll
+      for (int k0 = 0; k0 < T; k0 += 4) {
+        const CT a0 = -L.S[lr][k0 + lk], a1 = -L.S[16 + lr][k0 + lk];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int jj = wave + 4 * q;
+          if (jj < nu) {
+            const CT b0 = Up[jj][k0 + lk][lr], b1 = Up[jj][k0 + lk][16 + lr];
+            acc[q][0][0] = Mfma<CT>::op(a0, b0, acc[q][0][0]);
+            acc[q][0][1] = Mfma<CT>::op(a0, b1, acc[q][0][1]);
+            acc[q][1][0] = Mfma<CT>::op(a1, b0, acc[q][1][0]);
+            acc[q][1][1] = Mfma<CT>::op(a1, b1, acc[q][1][1]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int jj = wave + 4 * q;
+        if (jj < nu) {
+          CT *c = tile_at<T, CT>(F, s, I, K + 1 + jj - I + s.bl);
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) c[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr] = acc[q][bi][bj][v];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Multi-launch variant for one large band matrix (the coarse problem):
 // step K = diag (1 WG), panels (bl + bu WGs), Schur (bl x bu WGs).
 template <int T>
 __global__ __launch_bounds__(256) void k_lu_step_diag(double *__restrict__ F, SubInfo s, int K, int *status) {
-  __shared__ LuLds<T> L;
+  __shared__ LuLds<T, double> L;
   lu_diag_tile<T>(tile_at<T>(F, s, K, s.bl), L, status);
 }
 template <int T>
 __global__ __launch_bounds__(256) void k_lu_step_panel(double *__restrict__ F, SubInfo s, int K) {
-  __shared__ LuLds<T> L;
+  __shared__ LuLds<T, double> L;
   load_diag_inverses<T>(tile_at<T>(F, s, K, s.bl), L);
   const int b = blockIdx.x;
   if (b < s.bl) {
@@ -703,141 +859,254 @@ __device__ inline double group_sum(double v) {
 // mode: 0 = non-transposed, owned write z[g] = x (or z[g] += x if add)
 //       1 = transposed: masked gather, result written to the per-subdomain
 //           buffer yloc (summed over copies afterwards)
-template <int T, class FT, bool XLDS>
-__global__ __launch_bounds__(256) void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs,
-                                                    const int32_t *__restrict__ order, const int32_t *__restrict__ l2g,
-                                                    const uint8_t *__restrict__ owned, const double *__restrict__ r,
-                                                    double *__restrict__ z, int add, int transpose,
-                                                    double *__restrict__ yloc, double *__restrict__ xscratch,
-                                                    int64_t scratch_stride) {
-  extern __shared__ double xl_raw[];
+constexpr int RING = 32;  // block rows of the local vector kept in LDS (> bl, bu)
+// off-diagonal tiles per block row held in registers at once
+template <class FT>
+constexpr int solve_bmax() { return sizeof(FT) == 8 ? 6 : 8; }
+
+// Forward and backward sweeps of one subdomain (or of the coarse system).
+// Only a ring of RING block rows of the local vector lives in LDS; the
+// forward results go to a global scratch (ybuf) and are re-read by the
+// backward sweep.  For every block row, the tiles it needs are loaded into
+// registers (chunks of SOLVE_BMAX) before any arithmetic, so that their
+// loads are in flight together.
+//   mode non-transposed: z[g] = x (owned entries; or z[g] += x when add)
+//   mode transposed: input masked by D_i, output to yloc (summed later)
+template <int T, class FT, int NTHR, bool TRANS>
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(NTHR == 256 ? 4 : 1, 8)))
+void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, const int32_t *__restrict__ order,
+                  const int32_t *__restrict__ l2g, const uint8_t *__restrict__ owned, const double *__restrict__ r,
+                  double *__restrict__ z, int add, double *__restrict__ yloc, double *__restrict__ ybuf) {
+  constexpr bool transpose = TRANS;
+  constexpr int SOLVE_BMAX = solve_bmax<FT>();
+  constexpr int G = NTHR / T;   // lanes per row
+  constexpr int PER = T / G;    // elements of one tile row per lane
+  __shared__ double ring[RING][T];
   __shared__ double acc_s[T];
-  constexpr int G = 256 / T;  // lanes per row
+  __shared__ double part_s[G][T];
   const int sidx = order ? order[blockIdx.x] : blockIdx.x;
   const SubInfo s = subs[sidx];
-  double *x = XLDS ? xl_raw : (xscratch + (int64_t)blockIdx.x * scratch_stride);
+  const bool local = s.l2g_off >= 0;
+  const int64_t yo = local ? s.l2g_off : 0;
   const int tid = threadIdx.x;
-  const int npad = s.nt * T;
-  // gather r_i = R_i r (transposed: D_i R_i r)
-  for (int l = tid; l < npad; l += 256) {
-    double v = 0.0;
-    if (l < s.n_loc) {
-      const int32_t gi = s.l2g_off >= 0 ? l2g[s.l2g_off + l] : l;
-      v = r[gi];
-      if (transpose && s.l2g_off >= 0 && !owned[s.l2g_off + l]) v = 0.0;
-    }
-    x[l] = v;
-  }
-  __syncthreads();
-  const int i = tid / G, g = tid % G;
   const int W = s.bl + s.bu + 1;
-  if (!transpose) {
-    // forward: y_K = Linv_KK (x_K - sum_{P<K} L_KP y_P)
+  auto tile = [&](int K, int slot) -> const FT * { return F + s.base + ((int64_t)K * W + slot) * (T * T); };
+  auto rhs = [&](int l) -> double {
+    if (l >= s.n_loc) return 0.0;
+    if (!local) return r[l];
+    double v = r[l2g[s.l2g_off + l]];
+    if (transpose && !owned[s.l2g_off + l]) v = 0.0;
+    return v;
+  };
+  // gather the right-hand side R_i r (D_i R_i r when transposed) into ybuf
+  for (int l = tid; l < s.n_loc; l += NTHR) ybuf[yo + l] = rhs(l);
+  __syncthreads();
+  if constexpr (!TRANS) {
+    const int i = tid / G, g = tid % G;
+    // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P)
     for (int K = 0; K < s.nt; ++K) {
-      double a = 0.0;
       const int p0 = max(0, K - s.bl);
-      for (int P = p0; P < K; ++P) a += row_dot<T, FT>(ctile<T, FT>(F, s, K, P - K + s.bl), x + P * T, i, g, G);
+      const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
+      double a = 0.0;
+      for (int P0 = p0; P0 < K; P0 += SOLVE_BMAX) {
+        FT buf[SOLVE_BMAX][PER];
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (P0 + t < K) {
+            const FT *A = tile(K, P0 + t - K + s.bl);
+#pragma unroll
+            for (int m = 0; m < PER; ++m) buf[t][m] = A[i * T + g + m * G];
+          }
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (P0 + t < K) {
+            const double *xr = ring[(P0 + t) % RING];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g + m * G];
+          }
+      }
+      const FT *dk = tile(K, s.bl);
+      FT dv[PER];
+#pragma unroll
+      for (int m = 0; m < PER; ++m) dv[m] = dk[i * T + g + m * G];
       a = group_sum<G>(a);
-      if (g == 0) acc_s[i] = x[K * T + i] - a;
+      if (g == 0) acc_s[i] = bv - a;
       __syncthreads();
-      const FT *dk = ctile<T, FT>(F, s, K, s.bl);
       double y = 0.0;
-      for (int j = g; j < i; j += G) y += from_ft<FT>(dk[i * T + j]) * acc_s[j];
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = g + m * G;
+        if (j < i) y += from_ft<FT>(dv[m]) * acc_s[j];
+      }
       y = group_sum<G>(y);
-      if (g == 0) x[K * T + i] = acc_s[i] + y;
+      if (g == 0) {
+        const double v = acc_s[i] + y;
+        ring[K % RING][i] = v;
+        if (K * T + i < s.n_loc) ybuf[yo + K * T + i] = v;
+      }
       __syncthreads();
     }
     // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J)
     for (int K = s.nt - 1; K >= 0; --K) {
-      double a = 0.0;
       const int je = min(K + s.bu, s.nt - 1);
-      for (int J = K + 1; J <= je; ++J) a += row_dot<T, FT>(ctile<T, FT>(F, s, K, J - K + s.bl), x + J * T, i, g, G);
+      const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
+      double a = 0.0;
+      for (int J0 = K + 1; J0 <= je; J0 += SOLVE_BMAX) {
+        FT buf[SOLVE_BMAX][PER];
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (J0 + t <= je) {
+            const FT *A = tile(K, J0 + t - K + s.bl);
+#pragma unroll
+            for (int m = 0; m < PER; ++m) buf[t][m] = A[i * T + g + m * G];
+          }
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (J0 + t <= je) {
+            const double *xr = ring[(J0 + t) % RING];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g + m * G];
+          }
+      }
+      const FT *dk = tile(K, s.bl);
+      FT dv[PER];
+#pragma unroll
+      for (int m = 0; m < PER; ++m) dv[m] = dk[i * T + g + m * G];
       a = group_sum<G>(a);
-      if (g == 0) acc_s[i] = x[K * T + i] - a;
+      if (g == 0) acc_s[i] = bv - a;
       __syncthreads();
-      const FT *dk = ctile<T, FT>(F, s, K, s.bl);
       double y = 0.0;
-      for (int j = i + g; j < T; j += G) y += from_ft<FT>(dk[i * T + j]) * acc_s[j];
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = g + m * G;
+        if (j >= i) y += from_ft<FT>(dv[m]) * acc_s[j];
+      }
       y = group_sum<G>(y);
-      if (g == 0) x[K * T + i] = y;
+      if (g == 0) {
+        ring[K % RING][i] = y;
+        const int l = K * T + i;
+        if (l < s.n_loc) {
+          if (local) {
+            if (owned[s.l2g_off + l]) {
+              const int32_t gi = l2g[s.l2g_off + l];
+              z[gi] = add ? z[gi] + y : y;
+            }
+          } else {
+            z[l] = add ? z[l] + y : y;
+          }
+        }
+      }
       __syncthreads();
     }
   } else {
-    // transposed: forward with U^T: y_K = Uinv_KK^T (x_K - sum_{P<K} U_PK^T y_P)
-    // thread mapping for column access: column i = tid % T, group g = tid / T
+    // transposed: column access; column ci = tid % T, lane group cg = tid / T
     const int ci = tid % T, cg = tid / T;
-    __shared__ double part_s[G][T];
+    // forward with U^T: y_K = Uinv_KK^T (b_K - sum_{P<K} U_PK^T y_P)
     for (int K = 0; K < s.nt; ++K) {
-      double a = 0.0;
       const int p0 = max(0, K - s.bu);
-      for (int P = p0; P < K; ++P) a += col_dot<T, FT>(ctile<T, FT>(F, s, P, K - P + s.bl), x + P * T, ci, cg, G);
+      const double bv = (tid < T && K * T + tid < s.n_loc) ? ybuf[yo + K * T + tid] : 0.0;
+      double a = 0.0;
+      for (int P0 = p0; P0 < K; P0 += SOLVE_BMAX) {
+        FT buf[SOLVE_BMAX][PER];
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (P0 + t < K) {
+            const FT *A = tile(P0 + t, K - (P0 + t) + s.bl);
+#pragma unroll
+            for (int m = 0; m < PER; ++m) buf[t][m] = A[(cg + m * G) * T + ci];
+          }
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (P0 + t < K) {
+            const double *xr = ring[(P0 + t) % RING];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[cg + m * G];
+          }
+      }
+      const FT *dk = tile(K, s.bl);
+      FT dv[PER];
+#pragma unroll
+      for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
       part_s[cg][ci] = a;
       __syncthreads();
       if (tid < T) {
         double t = 0.0;
         for (int q = 0; q < G; ++q) t += part_s[q][tid];
-        acc_s[tid] = x[K * T + tid] - t;
+        acc_s[tid] = bv - t;
       }
       __syncthreads();
-      const FT *dk = ctile<T, FT>(F, s, K, s.bl);
-      // y_i = sum_{j <= i} Ui[j][i] acc_j
-      double y = 0.0;
-      for (int j = cg; j <= ci; j += G) y += from_ft<FT>(dk[j * T + ci]) * acc_s[j];
+      double y = 0.0;  // y_i = sum_{j <= i} Ui[j][i] acc_j
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = cg + m * G;
+        if (j <= ci) y += from_ft<FT>(dv[m]) * acc_s[j];
+      }
       part_s[cg][ci] = y;
       __syncthreads();
       if (tid < T) {
         double t = 0.0;
         for (int q = 0; q < G; ++q) t += part_s[q][tid];
-        x[K * T + tid] = t;
+        ring[K % RING][tid] = t;
+        if (K * T + tid < s.n_loc) ybuf[yo + K * T + tid] = t;
       }
       __syncthreads();
     }
     // backward with L^T: x_K = Linv_KK^T (y_K - sum_{J>K} L_JK^T x_J)
     for (int K = s.nt - 1; K >= 0; --K) {
-      double a = 0.0;
       const int je = min(K + s.bl, s.nt - 1);
-      for (int J = K + 1; J <= je; ++J) a += col_dot<T, FT>(ctile<T, FT>(F, s, J, K - J + s.bl), x + J * T, ci, cg, G);
+      const double bv = (tid < T && K * T + tid < s.n_loc) ? ybuf[yo + K * T + tid] : 0.0;
+      double a = 0.0;
+      for (int J0 = K + 1; J0 <= je; J0 += SOLVE_BMAX) {
+        FT buf[SOLVE_BMAX][PER];
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (J0 + t <= je) {
+            const FT *A = tile(J0 + t, K - (J0 + t) + s.bl);
+#pragma unroll
+            for (int m = 0; m < PER; ++m) buf[t][m] = A[(cg + m * G) * T + ci];
+          }
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (J0 + t <= je) {
+            const double *xr = ring[(J0 + t) % RING];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[cg + m * G];
+          }
+      }
+      const FT *dk = tile(K, s.bl);
+      FT dv[PER];
+#pragma unroll
+      for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
       part_s[cg][ci] = a;
       __syncthreads();
       if (tid < T) {
         double t = 0.0;
         for (int q = 0; q < G; ++q) t += part_s[q][tid];
-        acc_s[tid] = x[K * T + tid] - t;
+        acc_s[tid] = bv - t;
       }
       __syncthreads();
-      const FT *dk = ctile<T, FT>(F, s, K, s.bl);
-      // x_i = acc_i + sum_{j > i} Li[j][i] acc_j
-      double y = 0.0;
-      for (int j = ci + 1 + cg; j < T; j += G) y += from_ft<FT>(dk[j * T + ci]) * acc_s[j];
+      double y = 0.0;  // x_i = acc_i + sum_{j > i} Li[j][i] acc_j
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = cg + m * G;
+        if (j > ci) y += from_ft<FT>(dv[m]) * acc_s[j];
+      }
       part_s[cg][ci] = y;
       __syncthreads();
       if (tid < T) {
         double t = 0.0;
         for (int q = 0; q < G; ++q) t += part_s[q][tid];
-        x[K * T + tid] = acc_s[tid] + t;
+        const double v = acc_s[tid] + t;
+        ring[K % RING][tid] = v;
+        const int l = K * T + tid;
+        if (l < s.n_loc) {
+          if (local)
+            yloc[s.l2g_off + l] = v;
+          else
+            z[l] = add ? z[l] + v : v;
+        }
       }
       __syncthreads();
-    }
-  }
-  (void)W;
-  // scatter
-  if (!transpose) {
-    for (int l = tid; l < s.n_loc; l += 256) {
-      if (s.l2g_off >= 0) {
-        if (owned[s.l2g_off + l]) {
-          const int32_t gi = l2g[s.l2g_off + l];
-          z[gi] = add ? z[gi] + x[l] : x[l];
-        }
-      } else {
-        z[l] = add ? z[l] + x[l] : x[l];
-      }
-    }
-  } else {
-    for (int l = tid; l < s.n_loc; l += 256) {
-      if (s.l2g_off >= 0)
-        yloc[s.l2g_off + l] = x[l];
-      else
-        z[l] = add ? z[l] + x[l] : x[l];
     }
   }
 }
@@ -852,22 +1121,31 @@ __global__ void k_gather_copies(const int64_t *__restrict__ gptr, const int32_t 
   z[g] = add ? z[g] + v : v;
 }
 
-// coarse restriction rc[perm(I)*5 + c] = sum_a Z_aI r[5a + c]
-__global__ void k_coarse_restrict(const int64_t *__restrict__ zt_ptr, const int32_t *__restrict__ zt_col,
-                                  const double *__restrict__ zt_val, const int32_t *__restrict__ cperm,
-                                  const double *__restrict__ r, double *__restrict__ rc, int64_t nc) {
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
+// coarse restriction rc[perm(I)*5 + c] = sum_a Z_aI r[5a + c]: one wave
+// per coarse node, lanes over its fine nodes, fixed-order wave reduction
+__global__ __launch_bounds__(256) void k_coarse_restrict(const int64_t *__restrict__ zt_ptr,
+                                                         const int32_t *__restrict__ zt_col,
+                                                         const double *__restrict__ zt_val,
+                                                         const int32_t *__restrict__ cperm,
+                                                         const double *__restrict__ r, double *__restrict__ rc,
+                                                         int64_t nc) {
+  const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (I >= nc) return;  // uniform per wave
   double acc[5] = {0, 0, 0, 0, 0};
-  for (int64_t k = zt_ptr[I]; k < zt_ptr[I + 1]; ++k) {
+  for (int64_t k = zt_ptr[I] + lane; k < zt_ptr[I + 1]; k += 64) {
     const int64_t a = zt_col[k];
     const double w = zt_val[k];
 #pragma unroll
     for (int c = 0; c < 5; ++c) acc[c] += w * r[5 * a + c];
   }
-  const int64_t p = cperm[I];
 #pragma unroll
-  for (int c = 0; c < 5; ++c) rc[5 * p + c] = acc[c];
+  for (int c = 0; c < 5; ++c) acc[c] = wave_sum(acc[c]);
+  if (lane == 0) {
+    const int64_t p = cperm[I];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) rc[5 * p + c] = acc[c];
+  }
 }
 
 // coarse prolongation z[5a + c] += sum_I Z_aI xc[perm(I)*5 + c]
@@ -933,58 +1211,92 @@ void launch_check_state(const double *u, int64_t n, int *flags, hipStream_t st) 
   hipLaunchKernelGGL(k_check_state, dim3(nblocks(n)), dim3(256), 0, st, u, n, flags);
 }
 
+template <int T, class ET>
+static void extract_t(const FactorLaunch &fl, ET *F, const double *diag, const double *off, hipStream_t st) {
+  HIPCHECK(hipMemsetAsync(F, 0, sizeof(ET) * fl.sub_entries, st));
+  hipLaunchKernelGGL((k_pad_identity<T, ET>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.nsub);
+  if (fl.nent > 0)
+    hipLaunchKernelGGL((k_extract<T, ET>), dim3(nblocks(fl.nent * 5)), dim3(256), 0, st, F, fl.subs, fl.ent, fl.nent,
+                       diag, off, fl.status);
+}
+
 template <int T>
-static void setup_factors_t(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st) {
-  HIPCHECK(hipMemsetAsync(fl.F, 0, sizeof(double) * fl.entries, st));
-  if (fl.nsub > 0) {
-    hipLaunchKernelGGL(k_pad_identity<T>, dim3(fl.nsub), dim3(256), 0, st, fl.F, fl.subs, fl.nsub);
-    if (fl.nent > 0)
-      hipLaunchKernelGGL(k_extract<T>, dim3(nblocks(fl.nent * 5)), dim3(256), 0, st, fl.F, fl.subs, fl.ent, fl.nent,
-                         diag, off, fl.status);
-    const size_t lds = (size_t)std::max(fl.max_bu, 1) * T * (T + 1) * sizeof(double);
-    hipLaunchKernelGGL(k_band_lu<T>, dim3(fl.nsub), dim3(256), lds, st, fl.F, fl.subs, fl.order, fl.status);
-  }
-  if (fl.coarse) {
-    hipLaunchKernelGGL(k_pad_identity<T>, dim3(1), dim3(256), 0, st, fl.F, fl.coarse_dev, 1);
-    hipLaunchKernelGGL(k_galerkin<T>, dim3(nblocks(fl.gal_nblk * 25)), dim3(256), 0, st, fl.F, fl.cs, fl.gp, fl.gq,
-                       fl.gptr, fl.gref, fl.gw, fl.gal_nblk, diag, off, fl.status);
-    const SubInfo cs = fl.cs;
-    for (int K = 0; K < cs.nt; ++K) {
-      hipLaunchKernelGGL(k_lu_step_diag<T>, dim3(1), dim3(256), 0, st, fl.F, cs, K, fl.status);
-      if (K + 1 < cs.nt) {
-        hipLaunchKernelGGL(k_lu_step_panel<T>, dim3(cs.bl + cs.bu), dim3(256), 0, st, fl.F, cs, K);
-        hipLaunchKernelGGL(k_lu_step_schur<T>, dim3(cs.bl * cs.bu), dim3(256), 0, st, fl.F, cs, K);
-      }
+static void coarse_factor_t(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st) {
+  HIPCHECK(hipMemsetAsync(fl.Fc, 0, sizeof(double) * fl.coarse_entries, st));
+  hipLaunchKernelGGL((k_pad_identity<T, double>), dim3(1), dim3(256), 0, st, fl.Fc, fl.coarse_dev, 1);
+  hipLaunchKernelGGL(k_galerkin<T>, dim3(nblocks(fl.gal_nblk * 64)), dim3(256), 0, st, fl.Fc, fl.cs, fl.gp, fl.gq,
+                     fl.gptr, fl.gref, fl.gw, fl.gal_nblk, diag, off, fl.status);
+  const SubInfo cs = fl.cs;
+  for (int K = 0; K < cs.nt; ++K) {
+    hipLaunchKernelGGL(k_lu_step_diag<T>, dim3(1), dim3(256), 0, st, fl.Fc, cs, K, fl.status);
+    if (K + 1 < cs.nt) {
+      hipLaunchKernelGGL(k_lu_step_panel<T>, dim3(cs.bl + cs.bu), dim3(256), 0, st, fl.Fc, cs, K);
+      hipLaunchKernelGGL(k_lu_step_schur<T>, dim3(cs.bl * cs.bu), dim3(256), 0, st, fl.Fc, cs, K);
     }
   }
 }
 
-void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st) {
-  if (fl.tile == 32)
-    setup_factors_t<32>(fl, diag, off, st);
-  else
-    setup_factors_t<16>(fl, diag, off, st);
+void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st,
+                          hipStream_t st_coarse) {
+  if (fl.coarse) {
+    if (fl.tile == 32)
+      coarse_factor_t<32>(fl, diag, off, st_coarse);
+    else
+      coarse_factor_t<16>(fl, diag, off, st_coarse);
+  }
+  if (fl.nsub > 0) {
+    if (fl.tile == 32) {
+      if (fl.sub_float) {
+        extract_t<32, float>(fl, (float *)fl.Fs, diag, off, st);
+        const size_t lds = (size_t)std::max(fl.max_bu, 1) * 32 * 33 * sizeof(float);
+        hipLaunchKernelGGL(k_band_lu32<float>, dim3(fl.nsub), dim3(256), lds, st, (float *)fl.Fs, fl.subs, fl.order,
+                           fl.status);
+      } else {
+        extract_t<32, double>(fl, (double *)fl.Fs, diag, off, st);
+        const size_t lds = (size_t)std::max(fl.max_bu, 1) * 32 * 33 * sizeof(double);
+        hipLaunchKernelGGL(k_band_lu32<double>, dim3(fl.nsub), dim3(256), lds, st, (double *)fl.Fs, fl.subs,
+                           fl.order, fl.status);
+      }
+    } else {
+      extract_t<16, double>(fl, (double *)fl.Fs, diag, off, st);
+      const size_t lds = (size_t)std::max(fl.max_bu, 1) * 16 * 17 * sizeof(double);
+      hipLaunchKernelGGL(k_band_lu<16>, dim3(fl.nsub), dim3(256), lds, st, (double *)fl.Fs, fl.subs, fl.order,
+                         fl.status);
+    }
+  }
 }
 
-void launch_convert(void *dst, int prec, const double *src, int64_t N, hipStream_t st) {
+void launch_convert(void *dst, int dst_prec, const void *src, int src_float, int64_t N, hipStream_t st) {
   const unsigned nb = 4096;
-  if (prec == 1)
-    hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(256), 0, st, (float *)dst, src, N);
-  else if (prec == 2)
-    hipLaunchKernelGGL(k_convert<__hip_bfloat16>, dim3(nb), dim3(256), 0, st, (__hip_bfloat16 *)dst, src, N);
+  if (dst_prec == 1) {
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(nb), dim3(256), 0, st, (float *)dst, (const double *)src, N);
+  } else if (dst_prec == 2) {
+    if (src_float)
+      hipLaunchKernelGGL((k_convert<__hip_bfloat16, float>), dim3(nb), dim3(256), 0, st, (__hip_bfloat16 *)dst,
+                         (const float *)src, N);
+    else
+      hipLaunchKernelGGL((k_convert<__hip_bfloat16, double>), dim3(nb), dim3(256), 0, st, (__hip_bfloat16 *)dst,
+                         (const double *)src, N);
+  }
 }
 
+template <int T, class FT, bool TR>
+static void solve_tt(const SolveLaunch &sl, hipStream_t st) {
+  // the wide (1024-thread) form needs at least one element per lane: T >= 32
+  constexpr int WIDE = T * T >= 1024 ? 1024 : 256;
+  if (sl.wide && WIDE == 1024)
+    hipLaunchKernelGGL((k_band_solve<T, FT, WIDE, TR>), dim3(sl.nblocks), dim3(WIDE), 0, st, (const FT *)sl.F,
+                       sl.subs, sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf);
+  else
+    hipLaunchKernelGGL((k_band_solve<T, FT, 256, TR>), dim3(sl.nblocks), dim3(256), 0, st, (const FT *)sl.F, sl.subs,
+                       sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf);
+}
 template <int T, class FT>
 static void solve_t(const SolveLaunch &sl, hipStream_t st) {
-  const size_t lds = (size_t)sl.max_nt * T * sizeof(double);
-  if (sl.use_lds)
-    hipLaunchKernelGGL((k_band_solve<T, FT, true>), dim3(sl.nblocks), dim3(256), lds, st, (const FT *)sl.F, sl.subs,
-                       sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.transpose, sl.yloc, sl.scratch,
-                       sl.scratch_stride);
+  if (sl.transpose)
+    solve_tt<T, FT, true>(sl, st);
   else
-    hipLaunchKernelGGL((k_band_solve<T, FT, false>), dim3(sl.nblocks), dim3(256), 0, st, (const FT *)sl.F, sl.subs,
-                       sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.transpose, sl.yloc, sl.scratch,
-                       sl.scratch_stride);
+    solve_tt<T, FT, false>(sl, st);
 }
 
 void launch_band_solve(const SolveLaunch &sl, hipStream_t st) {
@@ -1005,7 +1317,8 @@ void launch_gather_copies(const int64_t *gptr, const int32_t *gidx, const double
 }
 void launch_coarse_restrict(const int64_t *zt_ptr, const int32_t *zt_col, const double *zt_val, const int32_t *cperm,
                             const double *r, double *rc, int64_t nc, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarse_restrict, dim3(nblocks(nc)), dim3(256), 0, st, zt_ptr, zt_col, zt_val, cperm, r, rc, nc);
+  hipLaunchKernelGGL(k_coarse_restrict, dim3(nblocks(nc * 64)), dim3(256), 0, st, zt_ptr, zt_col, zt_val, cperm, r, rc,
+                     nc);
 }
 void launch_coarse_prolong(const int64_t *z_ptr, const int32_t *z_col, const double *z_val, const int32_t *cperm,
                            const double *xc, double *z, int64_t n, hipStream_t st) {

@@ -17,6 +17,9 @@ void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,
   if (n > INT32_MAX / 8) fail(SEIRD_ERR_ARG, "too many nodes");
   m.n = n;
   m.nt = nt;
+  m.xy.assign(xy, xy + 2 * n);
+  for (int64_t i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(xy[i])) fail(SEIRD_ERR_MESH, "nonfinite node coordinate");
   std::vector<double> K(nt * 6);  // Kaa, Kbb, Kcc, Kab, Kac, Kbc
   m.mass.assign(n, 0.0);
   std::vector<int32_t> deg(n, 0);
@@ -178,6 +181,56 @@ static std::vector<int32_t> rcm(const std::vector<int32_t> &ptr, const std::vect
   return perm;
 }
 
+// Strip ordering: nodes sorted along the principal axis of their point
+// cloud (ties by the other coordinate, then by index).  On a compact 2D
+// patch its bandwidth is about the node count across the short side.
+static std::vector<int32_t> strip_order(const std::vector<double> &pts) {
+  const int32_t nn = (int32_t)(pts.size() / 2);
+  double mx = 0, my = 0;
+  for (int32_t k = 0; k < nn; ++k) { mx += pts[2 * k]; my += pts[2 * k + 1]; }
+  mx /= std::max(nn, 1); my /= std::max(nn, 1);
+  double sxx = 0, sxy = 0, syy = 0;
+  for (int32_t k = 0; k < nn; ++k) {
+    const double dx = pts[2 * k] - mx, dy = pts[2 * k + 1] - my;
+    sxx += dx * dx; sxy += dx * dy; syy += dy * dy;
+  }
+  // principal direction of the 2x2 covariance
+  const double th = 0.5 * std::atan2(2 * sxy, sxx - syy);
+  const double ux = std::cos(th), uy = std::sin(th);
+  std::vector<double> key(nn), key2(nn);
+  for (int32_t k = 0; k < nn; ++k) {
+    key[k] = ux * pts[2 * k] + uy * pts[2 * k + 1];
+    key2[k] = -uy * pts[2 * k] + ux * pts[2 * k + 1];
+  }
+  std::vector<int32_t> perm(nn);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+    if (key[a] != key[b]) return key[a] < key[b];
+    if (key2[a] != key2[b]) return key2[a] < key2[b];
+    return a < b;
+  });
+  return perm;
+}
+
+static int32_t bandwidth_of(const std::vector<int32_t> &perm, const std::vector<int32_t> &lp,
+                            const std::vector<int32_t> &la) {
+  const int32_t nn = (int32_t)perm.size();
+  std::vector<int32_t> where(nn);
+  for (int32_t k = 0; k < nn; ++k) where[perm[k]] = k;
+  int32_t bw = 0;
+  for (int32_t k = 0; k < nn; ++k)
+    for (int32_t q = lp[k]; q < lp[k + 1]; ++q) bw = std::max(bw, std::abs(where[k] - where[la[q]]));
+  return bw;
+}
+
+// the smaller-bandwidth one of reverse Cuthill-McKee and the strip ordering
+static std::vector<int32_t> band_order(const std::vector<int32_t> &lp, const std::vector<int32_t> &la,
+                                       const std::vector<double> &pts) {
+  std::vector<int32_t> a = rcm(lp, la);
+  std::vector<int32_t> b = strip_order(pts);
+  return bandwidth_of(b, lp, la) < bandwidth_of(a, lp, la) ? b : a;
+}
+
 static SubInfo tile_geometry(int32_t nn, int32_t bw, int tile) {
   SubInfo si{};
   si.n_loc = NC * nn;
@@ -238,7 +291,12 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
         if (stamp[m.col[q]] == s) la.push_back(lpos[m.col[q]]);
       lp[k + 1] = (int32_t)la.size();
     }
-    std::vector<int32_t> perm = rcm(lp, la);
+    std::vector<double> pts(2 * (size_t)nn);
+    for (int32_t k = 0; k < nn; ++k) {
+      pts[2 * k] = m.xy[2 * (size_t)nodes[k]];
+      pts[2 * k + 1] = m.xy[2 * (size_t)nodes[k] + 1];
+    }
+    std::vector<int32_t> perm = band_order(lp, la, pts);
     std::vector<int32_t> where(nn);
     for (int32_t k = 0; k < nn; ++k) where[perm[k]] = k;
     int32_t bw = 0;
@@ -250,6 +308,7 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
     base += (int64_t)si.nt * (si.bl + si.bu + 1) * t * t;
     ph.max_nodes = std::max(ph.max_nodes, nn);
     ph.max_bw = std::max(ph.max_bw, bw);
+    ph.mean_bw += (double)bw / o.n_sub;
     ph.max_nloc = std::max(ph.max_nloc, si.n_loc);
     // local unknown map and ownership, in the local (RCM) order
     for (int32_t k = 0; k < nn; ++k) {
@@ -372,7 +431,20 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
       if (cadj[k] != I) la.push_back(cadj[k]);
     lp[I + 1] = (int32_t)la.size();
   }
-  std::vector<int32_t> perm = rcm(lp, la);
+  // coarse node positions: Z-weighted mean of the fine nodes they support
+  std::vector<double> cpts(2 * (size_t)nc, 0.0);
+  for (int64_t I = 0; I < nc; ++I) {
+    double wsum = 0, x = 0, y = 0;
+    for (int64_t k = ph.zt_ptr[I]; k < ph.zt_ptr[I + 1]; ++k) {
+      const double w = ph.zt_val[k];
+      x += w * m.xy[2 * (size_t)ph.zt_col[k]];
+      y += w * m.xy[2 * (size_t)ph.zt_col[k] + 1];
+      wsum += w;
+    }
+    cpts[2 * I] = x / wsum;
+    cpts[2 * I + 1] = y / wsum;
+  }
+  std::vector<int32_t> perm = band_order(lp, la, cpts);
   ph.c_perm.assign(nc, 0);
   for (int64_t k = 0; k < nc; ++k) ph.c_perm[perm[k]] = (int32_t)k;
   int32_t bw = 0;
@@ -380,9 +452,10 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
     for (int64_t k = cptr[I]; k < cptr[I + 1]; ++k)
       bw = std::max(bw, std::abs(ph.c_perm[I] - ph.c_perm[cadj[k]]));
   ph.coarse = tile_geometry((int32_t)nc, bw, t);
-  ph.coarse.base = ph.factor_entries;
+  ph.coarse_bw = bw;
+  ph.coarse.base = 0;
   ph.coarse.l2g_off = -1;
-  ph.factor_entries += (int64_t)ph.coarse.nt * (ph.coarse.bl + ph.coarse.bu + 1) * t * t;
+  ph.coarse_entries = (int64_t)ph.coarse.nt * (ph.coarse.bl + ph.coarse.bu + 1) * t * t;
   ph.gal_ptr.push_back(0);
   for (int64_t I = 0; I < nc; ++I) {
     const auto &rw = rows[I];

@@ -277,6 +277,21 @@ def test_small_config_tight_solve_matches_every_field(small):
             assert np.abs(ug[:, c] - uo[:, c]).max() <= 1e-8 * m, (n, c)
 
 
+def test_lagged_preconditioner_reaches_the_same_root(small):
+    """Reusing one preconditioner setup for every Newton iteration of a step
+    changes GMRES iteration counts only: the root matches the oracle."""
+    cfg, prob, geo = small
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap)
+    u = T(cfg.u0.copy())
+    uo = cfg.u0.copy()
+    for n in range(3):
+        st = sk.step(prob, pc, u, cfg.dt, tol=1e-13, rtol=1e-9, pc_reuse=100)
+        assert st["pc_setups"] == 1
+        uo, _ = newton.newton_step(uo, cfg.dt, geo, cfg.params, tol=1e-14)
+    own, _ = _field_errors(H(u), uo)
+    assert own.max() < 1e-8, own
+
+
 def test_two_level_steps_match_oracle(nested):
     cfg, prob, geo = nested
     pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap,
