@@ -253,6 +253,42 @@ seird_status seird_step(seird_problem p, seird_precond pc, double *u,
                         const seird_krylov_opts *kopts,
                         seird_step_stats *stats, void *stream);
 
+/* ------------------------------------------------------------------
+ * Discrete adjoint of a case-count observation (reverse sweep with
+ * checkpointing).  Parameters theta = (g, nu): the transmission field g
+ * (seird_set_beta_field) and the five diffusion coefficients nu
+ * (seird_params).  Observation: c_r^n = sum_{j in r} m_j i_j^n for regions
+ * r = 0..n_regions-1 and steps n = 1..n_steps.  With lam^n solving
+ *   J_n^T lam^n = dL/du^n + M lam^{n+1}   (J_n = dF^n/du^n, lam^{N+1} = 0),
+ * the gradient of a loss L(c) is dL/dtheta = - sum_n (dF^n/dtheta)^T lam^n.
+ * ------------------------------------------------------------------ */
+typedef struct {
+  int32_t gmres_its_total;  /* transposed solves */
+  int32_t recomputed_steps;
+  double t_forward_ms, t_reverse_ms;
+} seird_adjoint_stats;
+
+/* Run n_steps implicit steps from u (in: u^0, out: u^{n_steps}), record
+ * checkpoints every ckpt_every steps (device memory owned by the problem;
+ * replaces any previous record) and write the counts [n_steps][n_regions]
+ * (device float64) .  region: host int32 [n_nodes], -1 = unobserved.
+ * Synchronising. */
+seird_status seird_forward_record(seird_problem p, seird_precond pc,
+                                  double *u, int32_t n_steps, double dt,
+                                  int32_t ckpt_every, const int32_t *region,
+                                  int32_t n_regions, double *counts,
+                                  const seird_newton_opts *nopts,
+                                  const seird_krylov_opts *kopts,
+                                  void *stream);
+/* Reverse sweep of the last record: grad_counts [n_steps][n_regions]
+ * (device, dL/dc), outputs grad_g [n_nodes] (device) and grad_nu [5]
+ * (host).  Transposed solves use GMRES with the transposed preconditioner
+ * (kopts).  Parameters must be those of the record.  Synchronising. */
+seird_status seird_adjoint(seird_problem p, seird_precond pc,
+                           const double *grad_counts, double *grad_g,
+                           double *grad_nu, const seird_krylov_opts *kopts,
+                           seird_adjoint_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,8 +13,8 @@ import os
 
 import numpy as np
 
-__all__ = ["Problem", "Precond", "SeirdError", "gmres", "step", "lib",
-           "library_path"]
+__all__ = ["Problem", "Precond", "SeirdError", "gmres", "step", "forward_record",
+           "adjoint", "SEIRDRun", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libseird.so")
@@ -81,6 +81,11 @@ class _SInfo(ctypes.Structure):
                 ("coarse_bandwidth", ctypes.c_int32)]
 
 
+class _AStats(ctypes.Structure):
+    _fields_ = [("gmres_its_total", ctypes.c_int32), ("recomputed_steps", ctypes.c_int32),
+                ("t_forward_ms", ctypes.c_double), ("t_reverse_ms", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _I64P = ctypes.POINTER(ctypes.c_int64)
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -111,6 +116,11 @@ _SIGS = {
                      ctypes.POINTER(_KStats), ctypes.c_int, _P], ctypes.c_int),
     "seird_step": ([_P, _P, _P, ctypes.c_double, _P, ctypes.POINTER(_Newton),
                     ctypes.POINTER(_Krylov), ctypes.POINTER(_SStats), _P], ctypes.c_int),
+    "seird_forward_record": ([_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
+                              ctypes.c_int32, _P, ctypes.POINTER(_Newton), ctypes.POINTER(_Krylov), _P],
+                             ctypes.c_int),
+    "seird_adjoint": ([_P, _P, _P, _P, _P, ctypes.POINTER(_Krylov), ctypes.POINTER(_AStats), _P],
+                      ctypes.c_int),
 }
 
 
@@ -361,3 +371,89 @@ def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, pc_reuse=0
                  ras_bytes_per_launch=s.ras_bytes_per_launch)
     _check(code)
     return stats
+
+
+def forward_record(problem: Problem, pc, u, n_steps, dt, region, n_regions, ckpt_every=10,
+                   tol=1e-10, max_it=20, pc_reuse=0, **kw):
+    """Run n_steps implicit steps in place on u, recording checkpoints for
+    ``adjoint``; returns the counts [n_steps, n_regions] (CUDA float64)."""
+    torch = _torch()
+    region = np.ascontiguousarray(region, dtype=np.int32)
+    if len(region) != problem.n:
+        raise ValueError("region must have one entry per node")
+    counts = torch.empty((int(n_steps), int(n_regions)), dtype=torch.float64, device=u.device)
+    nopt = _Newton(float(tol), int(max_it), int(pc_reuse))
+    kopt = _krylov(**kw)
+    _check(lib().seird_forward_record(problem.h, pc.h if pc is not None else None,
+                                      _dptr(u, problem.N, "u"), int(n_steps), float(dt),
+                                      int(ckpt_every), region.ctypes.data, int(n_regions),
+                                      _dptr(counts, None, "counts"), ctypes.byref(nopt),
+                                      ctypes.byref(kopt), _stream()))
+    return counts
+
+
+def adjoint(problem: Problem, pc, grad_counts, **kw):
+    """Reverse sweep of the last forward_record.  grad_counts: dL/dcounts
+    [n_steps, n_regions].  Returns (grad_g [n] CUDA, grad_nu [5] numpy,
+    stats)."""
+    torch = _torch()
+    gc = grad_counts.contiguous().to(torch.float64)
+    grad_g = torch.empty(problem.n, dtype=torch.float64, device=gc.device)
+    grad_nu = np.zeros(5, dtype=np.float64)
+    kopt = _krylov(**kw)
+    st = _AStats()
+    _check(lib().seird_adjoint(problem.h, pc.h if pc is not None else None, _dptr(gc, None, "grad_counts"),
+                               _dptr(grad_g, problem.n, "grad_g"), grad_nu.ctypes.data,
+                               ctypes.byref(kopt), ctypes.byref(st), _stream()))
+    return grad_g, grad_nu, dict(gmres_its_total=st.gmres_its_total,
+                                 recomputed_steps=st.recomputed_steps,
+                                 t_reverse_ms=st.t_reverse_ms)
+
+
+def _make_run_function():
+    torch = _torch()
+
+    class SEIRDRun(torch.autograd.Function):
+        """counts = SEIRDRun.apply(g, nu, problem, pc, u0, n_steps, dt,
+        region, n_regions, options) -- the infected counts of every region
+        at every step of an implicit run, differentiable with respect to the
+        transmission field g [n] and the diffusion coefficients nu [5]
+        through the library's discrete adjoint (reverse sweep with
+        checkpoints).  ``options`` is a dict with base_params (rates),
+        ckpt_every, tol and the forward/adjoint Krylov settings."""
+
+        @staticmethod
+        def forward(ctx, g, nu, problem, pc, u0, n_steps, dt, region, n_regions, options):
+            import copy
+            base = copy.copy(options["base_params"])
+            base.nu = tuple(float(x) for x in nu.detach().cpu().tolist())
+            problem.set_params(base)
+            problem.set_beta_field(g.detach().contiguous().to(torch.float64))
+            u = u0.detach().clone()
+            counts = forward_record(problem, pc, u, n_steps, dt, region, n_regions,
+                                    ckpt_every=options.get("ckpt_every", 10),
+                                    tol=options.get("tol", 1e-10), **options.get("krylov", {}))
+            ctx.problem, ctx.pc, ctx.options = problem, pc, options
+            ctx.nu_device = nu.device
+            return counts
+
+        @staticmethod
+        def backward(ctx, grad_counts):
+            grad_g, grad_nu, _ = adjoint(ctx.problem, ctx.pc, grad_counts,
+                                         **ctx.options.get("adjoint_krylov", {"rtol": 1e-10}))
+            gnu = torch.as_tensor(grad_nu, dtype=torch.float64, device=ctx.nu_device)
+            return grad_g, gnu, None, None, None, None, None, None, None, None
+
+    return SEIRDRun
+
+
+class _LazyRun:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyRun._cls is None:
+            _LazyRun._cls = _make_run_function()
+        return getattr(_LazyRun._cls, name)
+
+
+SEIRDRun = _LazyRun()

@@ -65,6 +65,30 @@ struct seird_problem_s {
   int kcap = 0;
   double *w1 = nullptr;  // scratch vector
   size_t lds_limit = 65536;
+  // adjoint record (checkpoints, last segment, regions)
+  struct Tape {
+    int n_steps = 0, every = 0, n_regions = 0;
+    double dt = 0.0;
+    seird_newton_opts nopts{};
+    seird_krylov_opts kopts{};
+    std::vector<double *> ckpt, seg;
+    int32_t *region = nullptr, *reg_nodes = nullptr;
+    int64_t *reg_ptr = nullptr;
+    double *lam = nullptr, *lam_next = nullptr, *rhs = nullptr, *partials = nullptr;
+    bool valid = false;
+    void release() {
+      for (double *q : ckpt) dev_free(q);
+      for (double *q : seg) dev_free(q);
+      ckpt.clear();
+      seg.clear();
+      dev_free(region); dev_free(reg_nodes); dev_free(reg_ptr);
+      dev_free(lam); dev_free(lam_next); dev_free(rhs); dev_free(partials);
+      region = reg_nodes = nullptr;
+      reg_ptr = nullptr;
+      lam = lam_next = rhs = partials = nullptr;
+      valid = false;
+    }
+  } tape;
 
   ~seird_problem_s() {
     dev_free(md.rowptr); dev_free(md.col); dev_free(md.tslot); dev_free(md.mass);
@@ -73,6 +97,7 @@ struct seird_problem_s {
     dev_free(gfield); dev_free(partials); dev_free(hdev); dev_free(ydev); dev_free(flags);
     dev_free(u_prev); dev_free(F); dev_free(rhs); dev_free(delta); dev_free(vals);
     dev_free(V); dev_free(Zb); dev_free(w1);
+    tape.release();
   }
   int64_t nvals() const { return 25 * mh.n + 10 * (int64_t)mh.col.size(); }
   const double *diag(const double *v) const { return v; }
@@ -358,6 +383,104 @@ static int gmres_impl(seird_problem P, seird_precond pc, const double *vals, con
     launch_axpby(V, V, 1.0 / beta, nullptr, 0, 0.0, N, nb, st);
   }
 }
+
+static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t st);
+
+static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, const double *src,
+                      const seird_newton_opts *nopts, const seird_krylov_opts *kopts, seird_step_stats &s,
+                      hipStream_t st) {
+  {
+    if (!p || !u || !nopts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
+    if (nopts->max_it < 0 || nopts->max_it > SEIRD_MAX_NEWTON) fail(SEIRD_ERR_ARG, "Newton max_it out of range");
+    if (nopts->pc_reuse < 0) fail(SEIRD_ERR_ARG, "pc_reuse must be >= 0");
+    using clk = std::chrono::steady_clock;
+    auto ms = [](clk::time_point a, clk::time_point b) {
+      return std::chrono::duration<double, std::milli>(b - a).count();
+    };
+    const int64_t N = p->N;
+    HIPCHECK(hipMemcpyAsync(p->u_prev, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    auto check_state = [&](const double *x) {
+      HIPCHECK(hipMemsetAsync(p->flags, 0, sizeof(int), st));
+      launch_check_state(x, p->mh.n, p->flags, st);
+      int f = 0;
+      HIPCHECK(hipMemcpyAsync(&f, p->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      if (f & 1) fail(SEIRD_ERR_NONFINITE, "nonfinite state");
+      if (f & 2) fail(SEIRD_ERR_STATE, "total density N <= 0 at a node");
+    };
+    check_state(u);
+    const double scale = p->norm(p->u_prev, st, p->md.mass);
+    const double unorm = p->norm(p->u_prev, st);
+    double *diag = p->vals, *off = p->vals + 25 * p->mh.n;
+    int last_setup = 0, its_fresh = 0;
+    bool stale = false;
+    for (int k = 0;; ++k) {
+      auto t0 = clk::now();
+      launch_residual(p->md, p->P, p->gfield, u, p->u_prev, dt, src, p->F, st);
+      const double fn = p->norm(p->F, st);
+      s.t_residual_ms += ms(t0, clk::now());
+      s.res_hist[k] = fn / scale;
+      if (!std::isfinite(fn)) fail(SEIRD_ERR_NONFINITE, "nonfinite residual");
+      if (fn <= nopts->tol * scale) break;
+      if (k >= nopts->max_it) fail(SEIRD_ERR_NOT_CONVERGED, "Newton did not converge");
+      t0 = clk::now();
+      launch_jacobian(p->md, p->P, p->gfield, u, dt, diag, off, st);
+      HIPCHECK(hipStreamSynchronize(st));
+      s.t_jacobian_ms += ms(t0, clk::now());
+      // preconditioner setup: fresh at the first iteration, then every
+      // pc_reuse + 1 iterations, or when the reused one was marked stale
+      t0 = clk::now();
+      bool fresh = false;
+      if (pc && (k == 0 || stale || (k - last_setup) > nopts->pc_reuse)) {
+        precond_setup_impl(pc, p->vals, st);
+        s.pc_setups++;
+        last_setup = k;
+        stale = false;
+        fresh = true;
+      }
+      s.t_setup_ms += ms(t0, clk::now());
+      t0 = clk::now();
+      launch_axpby(p->rhs, p->F, -1.0, nullptr, 0, 0.0, N, p->nb, st);
+      seird_krylov_stats ks{};
+      int rc = gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, 0, st);
+      if (pc && !fresh && rc != SEIRD_OK) {
+        // a reused setup failed: rebuild it from the current Jacobian and retry
+        auto t1 = clk::now();
+        precond_setup_impl(pc, p->vals, st);
+        s.pc_setups++;
+        last_setup = k;
+        s.t_setup_ms += ms(t1, clk::now());
+        const int its_first = ks.its;
+        rc = gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, 0, st);
+        ks.its += its_first;
+        fresh = true;
+      }
+      if (fresh) its_fresh = ks.its;
+      else if (ks.its > 2 * its_fresh + 5) stale = true;  // reuse no longer pays
+      s.t_gmres_ms += ms(t0, clk::now());
+      if (pc && pc->timing) {
+        HIPCHECK(hipStreamSynchronize(st));
+        pc->harvest();
+      }
+      s.gmres_its[k] = ks.its;
+      s.gmres_its_total += ks.its;
+      s.newton_its = k + 1;
+      if (rc == SEIRD_ERR_DIVERGED) fail(rc, "GMRES diverged");
+      // max_it without convergence: inexact Newton update is still taken
+      launch_axpby(u, p->delta, 1.0, nullptr, 0, 1.0, N, p->nb, st);
+      s.eps = p->norm(p->delta, st) / unorm;
+      check_state(u);
+    }
+    if (pc && pc->timing) {
+      s.t_ras_kernel_ms = pc->ras_ms;
+      s.n_ras_launches = pc->ras_count;
+      s.ras_bytes_per_launch = pc->ras_bytes();
+      pc->ras_ms = 0.0;
+      pc->ras_count = 0;
+    }
+  }
+}
+
 
 extern "C" {
 
@@ -701,108 +824,132 @@ seird_status seird_step(seird_problem p, seird_precond pc, double *u, double dt,
                         const seird_newton_opts *nopts, const seird_krylov_opts *kopts, seird_step_stats *stats,
                         void *stream) {
   seird_step_stats s{};
-  auto finish = [&](int code, const std::string &msg) {
-    s.reason = code;
-    if (stats) *stats = s;
-    if (code != SEIRD_OK) g_last_error = msg;
-    return code;
-  };
+  int code = SEIRD_OK;
   try {
-    if (!p || !u || !nopts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
-    if (nopts->max_it < 0 || nopts->max_it > SEIRD_MAX_NEWTON) fail(SEIRD_ERR_ARG, "Newton max_it out of range");
-    if (nopts->pc_reuse < 0) fail(SEIRD_ERR_ARG, "pc_reuse must be >= 0");
-    hipStream_t st = (hipStream_t)stream;
-    using clk = std::chrono::steady_clock;
-    auto ms = [](clk::time_point a, clk::time_point b) {
-      return std::chrono::duration<double, std::milli>(b - a).count();
-    };
-    const int64_t N = p->N;
-    HIPCHECK(hipMemcpyAsync(p->u_prev, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-    auto check_state = [&](const double *x) {
-      HIPCHECK(hipMemsetAsync(p->flags, 0, sizeof(int), st));
-      launch_check_state(x, p->mh.n, p->flags, st);
-      int f = 0;
-      HIPCHECK(hipMemcpyAsync(&f, p->flags, sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipStreamSynchronize(st));
-      if (f & 1) fail(SEIRD_ERR_NONFINITE, "nonfinite state");
-      if (f & 2) fail(SEIRD_ERR_STATE, "total density N <= 0 at a node");
-    };
-    check_state(u);
-    const double scale = p->norm(p->u_prev, st, p->md.mass);
-    const double unorm = p->norm(p->u_prev, st);
-    double *diag = p->vals, *off = p->vals + 25 * p->mh.n;
-    int last_setup = 0, its_fresh = 0;
-    bool stale = false;
-    for (int k = 0;; ++k) {
-      auto t0 = clk::now();
-      launch_residual(p->md, p->P, p->gfield, u, p->u_prev, dt, src, p->F, st);
-      const double fn = p->norm(p->F, st);
-      s.t_residual_ms += ms(t0, clk::now());
-      s.res_hist[k] = fn / scale;
-      if (!std::isfinite(fn)) fail(SEIRD_ERR_NONFINITE, "nonfinite residual");
-      if (fn <= nopts->tol * scale) break;
-      if (k >= nopts->max_it) fail(SEIRD_ERR_NOT_CONVERGED, "Newton did not converge");
-      t0 = clk::now();
-      launch_jacobian(p->md, p->P, p->gfield, u, dt, diag, off, st);
-      HIPCHECK(hipStreamSynchronize(st));
-      s.t_jacobian_ms += ms(t0, clk::now());
-      // preconditioner setup: fresh at the first iteration, then every
-      // pc_reuse + 1 iterations, or when the reused one was marked stale
-      t0 = clk::now();
-      bool fresh = false;
-      if (pc && (k == 0 || stale || (k - last_setup) > nopts->pc_reuse)) {
-        precond_setup_impl(pc, p->vals, st);
-        s.pc_setups++;
-        last_setup = k;
-        stale = false;
-        fresh = true;
-      }
-      s.t_setup_ms += ms(t0, clk::now());
-      t0 = clk::now();
-      launch_axpby(p->rhs, p->F, -1.0, nullptr, 0, 0.0, N, p->nb, st);
-      seird_krylov_stats ks{};
-      int rc = gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, 0, st);
-      if (pc && !fresh && rc != SEIRD_OK) {
-        // a reused setup failed: rebuild it from the current Jacobian and retry
-        auto t1 = clk::now();
-        precond_setup_impl(pc, p->vals, st);
-        s.pc_setups++;
-        last_setup = k;
-        s.t_setup_ms += ms(t1, clk::now());
-        const int its_first = ks.its;
-        rc = gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, 0, st);
-        ks.its += its_first;
-        fresh = true;
-      }
-      if (fresh) its_fresh = ks.its;
-      else if (ks.its > 2 * its_fresh + 5) stale = true;  // reuse no longer pays
-      s.t_gmres_ms += ms(t0, clk::now());
-      if (pc && pc->timing) {
-        HIPCHECK(hipStreamSynchronize(st));
-        pc->harvest();
-      }
-      s.gmres_its[k] = ks.its;
-      s.gmres_its_total += ks.its;
-      s.newton_its = k + 1;
-      if (rc == SEIRD_ERR_DIVERGED) fail(rc, "GMRES diverged");
-      // max_it without convergence: inexact Newton update is still taken
-      launch_axpby(u, p->delta, 1.0, nullptr, 0, 1.0, N, p->nb, st);
-      s.eps = p->norm(p->delta, st) / unorm;
-      check_state(u);
-    }
-    if (pc && pc->timing) {
-      s.t_ras_kernel_ms = pc->ras_ms;
-      s.n_ras_launches = pc->ras_count;
-      s.ras_bytes_per_launch = pc->ras_bytes();
-      pc->ras_ms = 0.0;
-      pc->ras_count = 0;
-    }
-    return finish(SEIRD_OK, "");
+    step_impl(p, pc, u, dt, src, nopts, kopts, s, (hipStream_t)stream);
   } catch (const Error &e) {
-    return finish(e.code, e.msg);
+    code = e.code;
+    g_last_error = e.msg;
   } catch (const std::exception &e) {
-    return finish(SEIRD_ERR_ARG, std::string("internal: ") + e.what());
+    code = SEIRD_ERR_ARG;
+    g_last_error = std::string("internal: ") + e.what();
   }
+  s.reason = code;
+  if (stats) *stats = s;
+  return code;
+}
+
+seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, int32_t n_steps, double dt,
+                                  int32_t ckpt_every, const int32_t *region, int32_t n_regions, double *counts,
+                                  const seird_newton_opts *nopts, const seird_krylov_opts *kopts, void *stream) {
+  API_BEGIN
+  if (!p || !u || !region || !counts || !nopts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
+  if (n_steps <= 0 || ckpt_every <= 0 || n_regions < 0) fail(SEIRD_ERR_ARG, "bad record sizes");
+  hipStream_t st = (hipStream_t)stream;
+  auto &T = p->tape;
+  T.release();
+  const int64_t n = p->mh.n, N = p->N;
+  // regions: per-node id and CSR of the nodes of each region
+  std::vector<int64_t> rp(n_regions + 1, 0);
+  for (int64_t j = 0; j < n; ++j) {
+    if (region[j] >= n_regions) fail(SEIRD_ERR_ARG, "region id out of range");
+    if (region[j] >= 0) rp[region[j] + 1]++;
+  }
+  for (int r = 0; r < n_regions; ++r) rp[r + 1] += rp[r];
+  std::vector<int32_t> rn(rp[n_regions]);
+  {
+    std::vector<int64_t> f(rp.begin(), rp.end() - 1);
+    for (int64_t j = 0; j < n; ++j)
+      if (region[j] >= 0) rn[f[region[j]]++] = (int32_t)j;
+  }
+  T.region = dev_upload(std::vector<int32_t>(region, region + n));
+  T.reg_ptr = dev_upload(rp);
+  T.reg_nodes = dev_upload(rn);
+  T.n_steps = n_steps;
+  T.every = ckpt_every;
+  T.n_regions = n_regions;
+  T.dt = dt;
+  T.nopts = *nopts;
+  T.kopts = *kopts;
+  const int n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
+  const int last0 = (n_seg - 1) * ckpt_every;  // first step index of the last segment
+  for (int s = 0; s < n_seg; ++s) T.ckpt.push_back(dev_alloc<double>(N));
+  for (int k = 0; k <= ckpt_every; ++k) T.seg.push_back(dev_alloc<double>(N));
+  HIPCHECK(hipMemcpyAsync(T.ckpt[0], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+  if (last0 == 0) HIPCHECK(hipMemcpyAsync(T.seg[0], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+  for (int k = 1; k <= n_steps; ++k) {
+    seird_step_stats s{};
+    step_impl(p, pc, u, dt, nullptr, nopts, kopts, s, st);
+    launch_region_counts(T.reg_ptr, T.reg_nodes, p->md.mass, u, counts + (int64_t)(k - 1) * n_regions, n_regions, st);
+    if (k % ckpt_every == 0 && k / ckpt_every < n_seg)
+      HIPCHECK(hipMemcpyAsync(T.ckpt[k / ckpt_every], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    if (k >= last0) HIPCHECK(hipMemcpyAsync(T.seg[k - last0], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHECK(hipStreamSynchronize(st));
+  T.valid = true;
+  API_END
+}
+
+seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad_counts, double *grad_g,
+                           double *grad_nu, const seird_krylov_opts *kopts, seird_adjoint_stats *stats, void *stream) {
+  API_BEGIN
+  if (!p || !grad_counts || !grad_g || !grad_nu || !kopts) fail(SEIRD_ERR_ARG, "null argument");
+  auto &T = p->tape;
+  if (!T.valid) fail(SEIRD_ERR_ARG, "no forward record");
+  hipStream_t st = (hipStream_t)stream;
+  using clk = std::chrono::steady_clock;
+  auto t_start = clk::now();
+  seird_adjoint_stats as{};
+  const int64_t n = p->mh.n, N = p->N;
+  if (!T.lam) {
+    T.lam = dev_alloc<double>(N);
+    T.lam_next = dev_alloc<double>(N);
+    T.rhs = dev_alloc<double>(N);
+    T.partials = dev_alloc<double>(5 * ((n + 255) / 256) + 8);
+  }
+  HIPCHECK(hipMemsetAsync(T.lam_next, 0, sizeof(double) * N, st));
+  HIPCHECK(hipMemsetAsync(grad_g, 0, sizeof(double) * n, st));
+  double gnu[5] = {0, 0, 0, 0, 0};
+  double *diag = p->vals, *off = p->vals + 25 * n;
+  const int n_seg = (int)T.ckpt.size();
+  std::vector<double> part;
+  for (int s = n_seg - 1; s >= 0; --s) {
+    const int n0 = s * T.every, n1 = std::min(T.n_steps, n0 + T.every);
+    if (s < n_seg - 1) {  // recompute the states of this segment from its checkpoint
+      HIPCHECK(hipMemcpyAsync(T.seg[0], T.ckpt[s], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+      for (int k = n0 + 1; k <= n1; ++k) {
+        HIPCHECK(hipMemcpyAsync(T.seg[k - n0], T.seg[k - n0 - 1], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        seird_step_stats ss{};
+        step_impl(p, pc, T.seg[k - n0], T.dt, nullptr, &T.nopts, &T.kopts, ss, st);
+        as.recomputed_steps++;
+      }
+    }
+    for (int k = n1; k > n0; --k) {
+      const double *uk = T.seg[k - n0];
+      launch_jacobian(p->md, p->P, p->gfield, uk, T.dt, diag, off, st);
+      if (pc) precond_setup_impl(pc, p->vals, st);
+      launch_adjoint_rhs(p->md.mass, T.region, grad_counts + (int64_t)(k - 1) * T.n_regions, T.lam_next, T.rhs, n, st);
+      seird_krylov_stats ks{};
+      int rc = gmres_impl(p, pc, p->vals, T.rhs, T.lam, *kopts, ks, 1, st);
+      as.gmres_its_total += ks.its;
+      if (rc != SEIRD_OK) fail(rc, "transposed GMRES failed in the adjoint sweep");
+      const int nb = launch_adjoint_grad(p->md, p->P, uk, T.lam, T.dt, grad_g, T.partials, st);
+      part.resize(5 * (size_t)nb);
+      HIPCHECK(hipMemcpyAsync(part.data(), T.partials, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      for (int c = 0; c < 5; ++c) {
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t += part[(size_t)c * nb + b];
+        gnu[c] -= T.dt * t;
+      }
+      std::swap(T.lam, T.lam_next);
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(st));
+  for (int c = 0; c < 5; ++c) grad_nu[c] = gnu[c];
+  as.t_reverse_ms = std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
+  if (stats) *stats = as;
+  API_END
 }
 
 }  // extern "C"

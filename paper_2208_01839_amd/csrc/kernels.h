@@ -79,4 +79,12 @@ void launch_coarse_restrict(const int64_t *zt_ptr, const int32_t *zt_col, const 
 void launch_coarse_prolong(const int64_t *z_ptr, const int32_t *z_col, const double *z_val, const int32_t *cperm,
                            const double *xc, double *z, int64_t n, hipStream_t st);
 
+void launch_region_counts(const int64_t *reg_ptr, const int32_t *reg_nodes, const double *mass, const double *u,
+                          double *counts, int n_regions, hipStream_t st);
+void launch_adjoint_rhs(const double *mass, const int32_t *region, const double *gc, const double *lam_next,
+                        double *rhs, int64_t n, hipStream_t st);
+// returns the number of blocks (nu partial sums per component)
+int launch_adjoint_grad(const MeshDev &m, const ParamsDev &P, const double *u, const double *lam, double dt,
+                        double *grad_g, double *partials, hipStream_t st);
+
 }  // namespace seird

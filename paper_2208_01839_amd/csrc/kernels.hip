@@ -1166,6 +1166,97 @@ __global__ void k_coarse_prolong(const int64_t *__restrict__ z_ptr, const int32_
 }
 
 // ----------------------------------------------------------------------
+// Discrete adjoint support (counts, adjoint right-hand side, parameter
+// gradients).  With lam^n the adjoint state of step n:
+//   rhs = dJ/du^n + M lam^{n+1},  dJ/dc_r^n = gc[r],  c_r = sum_{j in r} m_j i_j
+//   grad_g[j] -= (lam_S - lam_E)_j dt m_j a_j (beta_I i_j + beta_E e_j) s_j
+//   grad_nu[c] -= dt sum_i lam_{c,i} sum_T Nbar_T sum_k K^T_ik u_{c,k}
+// ----------------------------------------------------------------------
+// counts[r] = sum over the nodes of region r (CSR reg_ptr/reg_nodes) of m_j i_j
+__global__ __launch_bounds__(256) void k_region_counts(const int64_t *__restrict__ reg_ptr,
+                                                       const int32_t *__restrict__ reg_nodes,
+                                                       const double *__restrict__ mass, const double *__restrict__ u,
+                                                       double *__restrict__ counts) {
+  __shared__ double lds4[4];
+  const int r = blockIdx.x;
+  double a = 0.0;
+  for (int64_t k = reg_ptr[r] + threadIdx.x; k < reg_ptr[r + 1]; k += 256) {
+    const int64_t j = reg_nodes[k];
+    a += mass[j] * u[5 * j + 2];
+  }
+  const double t = block_sum(a, lds4);
+  if (threadIdx.x == 0) counts[r] = t;
+}
+
+__global__ __launch_bounds__(256) void k_adjoint_rhs(const double *__restrict__ mass, const int32_t *__restrict__ region,
+                                                     const double *__restrict__ gc, const double *__restrict__ lam_next,
+                                                     double *__restrict__ rhs, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double m = mass[j];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) rhs[5 * j + c] = m * lam_next[5 * j + c];
+  const int32_t r = region[j];
+  if (r >= 0) rhs[5 * j + 2] += gc[r] * m;
+}
+
+// gradient contributions of one step; nu partial sums per block in
+// partials[c * nb + block]
+__global__ __launch_bounds__(256) void k_adjoint_grad(MeshDev m, ParamsDev P, const double *__restrict__ u,
+                                                      const double *__restrict__ lam, double dt,
+                                                      double *__restrict__ grad_g, double *__restrict__ partials) {
+  __shared__ double lds4[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double pc[5] = {0, 0, 0, 0, 0};
+  if (i < m.n) {
+    double ui[5];
+    load5(u + 5 * i, ui);
+    const double Ni = ui[0] + ui[1] + ui[2] + ui[3] + ui[4];
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t k = m.inc_ptr[i]; k < m.inc_ptr[i + 1]; ++k) {
+      const int32_t j = m.inc_j[k], l = m.inc_l[k];
+      const double Kii = m.inc_K[3 * k], Kij = m.inc_K[3 * k + 1], Kil = m.inc_K[3 * k + 2];
+      double uj[5], ul[5];
+      load5(u + 5 * (int64_t)j, uj);
+      load5(u + 5 * (int64_t)l, ul);
+      const double Nbar = (Ni + (uj[0] + uj[1] + uj[2] + uj[3] + uj[4]) + (ul[0] + ul[1] + ul[2] + ul[3] + ul[4])) *
+                          (1.0 / 3.0);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) acc[c] += Nbar * (Kii * ui[c] + Kij * uj[c] + Kil * ul[c]);
+    }
+    double li[5];
+    load5(lam + 5 * i, li);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) pc[c] = li[c] * acc[c];
+    const double a = 1.0 - P.A / Ni;
+    const double dFs = dt * m.mass[i] * a * (P.bI * ui[2] + P.bE * ui[1]) * ui[0];
+    grad_g[i] -= (li[0] - li[1]) * dFs;
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double t = block_sum(pc[c], lds4);
+    if (threadIdx.x == 0) partials[(int64_t)c * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+void launch_region_counts(const int64_t *reg_ptr, const int32_t *reg_nodes, const double *mass, const double *u,
+                          double *counts, int n_regions, hipStream_t st) {
+  if (n_regions > 0)
+    hipLaunchKernelGGL(k_region_counts, dim3(n_regions), dim3(256), 0, st, reg_ptr, reg_nodes, mass, u, counts);
+}
+void launch_adjoint_rhs(const double *mass, const int32_t *region, const double *gc, const double *lam_next,
+                        double *rhs, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint_rhs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, mass, region, gc, lam_next,
+                     rhs, n);
+}
+int launch_adjoint_grad(const MeshDev &m, const ParamsDev &P, const double *u, const double *lam, double dt,
+                        double *grad_g, double *partials, hipStream_t st) {
+  const unsigned nb = (unsigned)((m.n + 255) / 256);
+  hipLaunchKernelGGL(k_adjoint_grad, dim3(nb), dim3(256), 0, st, m, P, u, lam, dt, grad_g, partials);
+  return (int)nb;
+}
+
+// ----------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------
 static inline unsigned nblocks(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
