@@ -65,6 +65,50 @@ def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0):
     return dict(seconds=t1 - t0, stats=stats, info=info, u=u)
 
 
+def adjoint_bench(sk, torch, args, cfg, coarse):
+    """One gradient of the case-count misfit (forward record + reverse
+    sweep) with respect to the per-node transmission field and the five
+    diffusion coefficients; checkpoints every 10 steps (5 for short runs)."""
+    import numpy as np
+    import seird_inputs as si
+    if args.adjoint_full:
+        cfg = si.config_differentiation()
+        coarse = (cfg.coarse_parents, cfg.coarse_n)
+        steps, every = cfg.steps, 10
+    else:
+        steps = args.adjoint_steps
+        every = 10 if steps >= 20 else 5
+    region = si.voronoi_regions(cfg.xy, 40, seed=8)
+    prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, tile=args.tile, coarse=coarse)
+    kw = dict(tol=cfg.newton_tol, pc_reuse=args.pc_reuse, rtol=cfg.gmres_rtol)
+    # synthetic truth: the same run with the perturbed transmission field
+    g_true = torch.tensor(si.bump_field(cfg.xy, seed=7), device="cuda")
+    prob.set_beta_field(g_true)
+    u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
+    truth = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=every, **kw)
+    prob.set_beta_field(torch.ones(cfg.n, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
+    counts = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=every, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    grad_g, grad_nu, st = sk.adjoint(prob, pc, 2 * (counts - truth), rtol=1e-8)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"[bench] adjoint: forward {t1 - t0:.2f} s, reverse {t2 - t1:.2f} s, {st}")
+    return {"metric": "adjoint gradients/s", "value": 1.0 / (t2 - t0), "unit": "grads/s",
+            "workload": (f"{cfg.name}: {cfg.n} nodes ({5 * cfg.n} unknowns), {steps} daily steps, "
+                         f"checkpoint every {every}, 40 Voronoi regions, gradient w.r.t. the per-node "
+                         f"transmission field and 5 diffusion coefficients"),
+            "forward_s": t1 - t0, "reverse_s": t2 - t1,
+            "transposed_gmres_its": st["gmres_its_total"], "recomputed_steps": st["recomputed_steps"],
+            "misfit": float(((counts - truth) ** 2).sum().item()),
+            "grad_nu": [float(x) for x in grad_nu],
+            "grad_g_norm": float(grad_g.norm().item())}
+
+
 def cpu_baseline(args):
     """The oracle as it stands, timed on the host on a bounded sample."""
     import numpy as np
@@ -115,8 +159,12 @@ def main():
     ap.add_argument("--n-ref", type=int, default=4)
     ap.add_argument("--n-sub", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--pc-reuse", type=int, default=0,
+    ap.add_argument("--pc-reuse", type=int, default=100,
                     help="Newton iterations a preconditioner setup is reused for (0: fresh every time)")
+    ap.add_argument("--adjoint-steps", type=int, default=10,
+                    help="implicit steps of the adjoint-gradient measurement (0: skip)")
+    ap.add_argument("--adjoint-full", action="store_true",
+                    help="measure the gradient on the ~2M-node, 60-step differentiation workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path "
@@ -184,6 +232,8 @@ def main():
                                                / res["u"].abs().max()).item()),
             }
         out["mixed"] = mixed
+    if args.adjoint_steps > 0 or args.adjoint_full:
+        out["adjoint"] = adjoint_bench(sk, torch, args, cfg, coarse)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on its bounded sample")
         out["cpu_baseline"] = cpu_baseline(args)

@@ -500,3 +500,49 @@ def config_realistic(n_base: int = 3900, n_ref: int = 4, n_sub: int = 1024,
 
 def random_vector(n: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(n)
+
+
+# --------------------------------------------------------------------------
+# differentiation workload
+# --------------------------------------------------------------------------
+def voronoi_regions(xy: np.ndarray, n_regions: int, seed: int,
+                    poly: Optional[np.ndarray] = None) -> np.ndarray:
+    """Observation regions: Voronoi cells of ``n_regions`` seeded points
+    (uniform in the mesh's bounding box, or in ``poly``); region id per
+    node."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    lo, hi = xy.min(0), xy.max(0)
+    pts = []
+    while len(pts) < n_regions:
+        c = rng.uniform(lo, hi, (4 * n_regions, 2))
+        if poly is not None:
+            c = c[_points_in_polygon(c, poly)]
+        pts.extend(list(c))
+    pts = np.array(pts[:n_regions])
+    _, idx = cKDTree(pts).query(xy)
+    return idx.astype(np.int32)
+
+
+def bump_field(xy: np.ndarray, seed: int, n_bumps: int = 8,
+               amp: float = 0.2, width: float = 40.0) -> np.ndarray:
+    """Seeded smooth perturbation 1 + amp * tanh(sum of n_bumps Gaussian
+    bumps with random signs): the 'truth' transmission multiplier."""
+    rng = np.random.default_rng(seed)
+    lo, hi = xy.min(0), xy.max(0)
+    c = rng.uniform(lo, hi, (n_bumps, 2))
+    sgn = rng.choice([-1.0, 1.0], n_bumps)
+    w = rng.uniform(0.5, 1.5, n_bumps) * width
+    xi = np.zeros(len(xy))
+    for k in range(n_bumps):
+        xi += sgn[k] * np.exp(-((xy - c[k]) ** 2).sum(1) / (2 * w[k] ** 2))
+    return 1.0 + amp * np.tanh(xi)
+
+
+def config_differentiation(n_base: int = 7800, n_ref: int = 4, n_sub: int = 2048,
+                           steps: int = 60, seed: int = 6) -> Config:
+    """Differentiation case: realistic-type mesh of about 2M nodes (10M
+    unknowns), 60 daily steps, two-grid RAS; regions and truth field are
+    built by ``voronoi_regions`` (40 regions, seed 8) and ``bump_field``
+    (seed 7)."""
+    return config_realistic(n_base=n_base, n_ref=n_ref, n_sub=n_sub, steps=steps, seed=seed)

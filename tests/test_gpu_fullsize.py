@@ -1,0 +1,102 @@
+"""Parity at the realistic workload's full size (about 1.01M nodes, 5.04M
+unknowns; two-grid RAS with 1024 subdomains, overlap 2) in the launch
+configuration the benchmark times.
+
+The oracle cannot assemble or factor the whole 5M-unknown system quickly,
+so it checks outputs it can compute one by one:
+* residual rows everywhere (vectorised numpy) and Jacobian rows of sampled
+  nodes (oracle Jacobian of the triangles incident to the sample, which is
+  exact for the sampled rows);
+* the RAS output on the owned nodes of sampled subdomains (the oracle's
+  exact local solve of R_i A R_i^T);
+and properties that hold at any size for a full implicit step: the oracle
+residual of the GPU state is below the tolerance, population is
+conserved, densities stay positive."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import seird_inputs as si
+from oracle import fem, krylov
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2208_01839_amd as sk  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def big():
+    cfg = si.config_realistic()
+    prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+    geo = fem.Geometry(cfg.xy, cfg.tri)
+    return cfg, prob, geo
+
+
+def _incident(tri, nodes):
+    mask = np.zeros(tri.max() + 1, dtype=bool)
+    mask[nodes] = True
+    return tri[mask[tri].any(1)]
+
+
+def test_fullsize_residual_and_sampled_jacobian_rows(big):
+    cfg, prob, geo = big
+    rng = np.random.default_rng(0)
+    u = cfg.u0 * rng.uniform(0.9, 1.1, cfg.u0.shape)
+    F = prob.residual(torch.tensor(u, device="cuda"), torch.tensor(cfg.u0, device="cuda"), cfg.dt)
+    Fo = fem.residual(u, cfg.u0, cfg.dt, geo, cfg.params)
+    Fg = F.cpu().numpy()
+    assert np.linalg.norm(Fg - Fo) <= 1e-13 * np.linalg.norm(Fo)
+    # Jacobian rows of 2000 sampled nodes
+    vals = prob.jacobian(torch.tensor(u, device="cuda"), cfg.dt)
+    x = rng.standard_normal(5 * cfg.n)
+    y = prob.spmv(vals, torch.tensor(x, device="cuda")).cpu().numpy()
+    sample = rng.choice(cfg.n, 2000, replace=False)
+    sub = fem.Geometry(cfg.xy, _incident(cfg.tri, sample))
+    Js = fem.jacobian(u, cfg.dt, sub, cfg.params)
+    rows = (5 * sample[:, None] + np.arange(5)[None, :]).ravel()
+    yo = Js[rows] @ x
+    assert np.linalg.norm(y[rows] - yo) <= 1e-13 * np.linalg.norm(yo)
+
+
+def test_fullsize_ras_on_sampled_subdomains(big):
+    cfg, prob, geo = big
+    rng = np.random.default_rng(1)
+    u = cfg.u0
+    vals = prob.jacobian(torch.tensor(u, device="cuda"), cfg.dt)
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap)  # one-level: RAS alone
+    pc.setup(vals)
+    r = rng.standard_normal(5 * cfg.n)
+    z = pc.apply(torch.tensor(r, device="cuda")).cpu().numpy()
+    G = fem.node_graph(geo)
+    for s in rng.choice(cfg.n_sub, 6, replace=False):
+        owned = np.nonzero(cfg.part == s)[0]
+        nodes = krylov.grow_overlap(G, owned, cfg.overlap)
+        subg = fem.Geometry(cfg.xy, _incident(cfg.tri, nodes))
+        Js = fem.jacobian(u, cfg.dt, subg, cfg.params).tocsr()
+        idx = krylov.unknowns_of(nodes)
+        Ai = Js[idx][:, idx].tocsc()
+        zi = spla.splu(Ai).solve(r[idx])
+        own = np.repeat(cfg.part[nodes] == s, 5)
+        zo = zi[own]
+        zg = z[idx[own]]
+        assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo), s
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_fullsize_step_solves_the_oracle_residual(big, prec):
+    cfg, prob, geo = big
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, factor_prec=prec,
+                    coarse=(cfg.coarse_parents, cfg.coarse_n))
+    u = torch.tensor(cfg.u0, device="cuda")
+    st = sk.step(prob, pc, u, cfg.dt, tol=cfg.newton_tol, pc_reuse=100)
+    ug = u.cpu().numpy()
+    Fo = fem.residual(ug, cfg.u0, cfg.dt, geo, cfg.params)
+    scale = np.linalg.norm(geo.mass[:, None] * cfg.u0)
+    assert np.linalg.norm(Fo) <= 1.01 * cfg.newton_tol * scale, st
+    P0 = fem.total_population(cfg.u0, geo)
+    assert abs(fem.total_population(ug, geo) - P0) <= 1e-9 * P0
+    assert ug[:, 0].min() > 0 and ug.sum(1).min() > 0
