@@ -236,6 +236,11 @@ struct seird_precond_s {
   // z += Z A_c^{-1} Z^T r  (or the transposed coarse operator)
   void coarse_add(const double *r, double *z, int transpose, hipStream_t st) {
     launch_coarse_restrict(zt_ptr, zt_col, zt_val, cperm, r, rc, ph.nc, st);
+    if (!transpose && ph.tile == 32 && ph.coarse.bl <= 16 && ph.coarse.bu <= 16) {
+      launch_coarse_solve(Fc, coarse_dev, rc, xc, cscratch, st);
+      launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
+      return;
+    }
     SolveLaunch sl;
     sl.tile = ph.tile;
     sl.prec = 0;  // the coarse factor is always float64

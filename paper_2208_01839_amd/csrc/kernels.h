@@ -87,4 +87,8 @@ void launch_adjoint_rhs(const double *mass, const int32_t *region, const double 
 int launch_adjoint_grad(const MeshDev &m, const ParamsDev &P, const double *u, const double *lam, double dt,
                         double *grad_g, double *partials, hipStream_t st);
 
+// one large band system (coarse, FP64, tile 32, bl, bu <= 16), non-transposed
+void launch_coarse_solve(const double *F, const SubInfo *sp, const double *r, double *z, double *ybuf,
+                         hipStream_t st);
+
 }  // namespace seird

@@ -848,6 +848,15 @@ __device__ inline double col_dot(const FT *__restrict__ A, const double *__restr
   return a;
 }
 
+// Barrier for workgroups that communicate through LDS only: it waits for
+// the wave's LDS operations, not for its outstanding global loads/stores,
+// so prefetched tile loads stay in flight across it.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int G>
 __device__ inline double group_sum(double v) {
   // lanes of one group are consecutive (row-major mapping)
@@ -861,8 +870,18 @@ __device__ inline double group_sum(double v) {
 //           buffer yloc (summed over copies afterwards)
 constexpr int RING = 32;  // block rows of the local vector kept in LDS (> bl, bu)
 // off-diagonal tiles per block row held in registers at once
-template <class FT>
+template <class FT, int NTHR>
 constexpr int solve_bmax() { return sizeof(FT) == 8 ? 6 : 8; }
+
+// PER consecutive elements of one tile row (aligned to PER elements), read
+// as one or two vector loads
+template <class FT, int PER>
+__device__ inline void load_chunk(const FT *__restrict__ p, FT (&out)[PER]) {
+  struct alignas(PER * sizeof(FT)) Chunk { FT v[PER]; };
+  const Chunk c = *reinterpret_cast<const Chunk *>(p);
+#pragma unroll
+  for (int m = 0; m < PER; ++m) out[m] = c.v[m];
+}
 
 // Forward and backward sweeps of one subdomain (or of the coarse system).
 // Only a ring of RING block rows of the local vector lives in LDS; the
@@ -878,7 +897,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
                   const int32_t *__restrict__ l2g, const uint8_t *__restrict__ owned, const double *__restrict__ r,
                   double *__restrict__ z, int add, double *__restrict__ yloc, double *__restrict__ ybuf) {
   constexpr bool transpose = TRANS;
-  constexpr int SOLVE_BMAX = solve_bmax<FT>();
+  constexpr int SOLVE_BMAX = solve_bmax<FT, NTHR>();
   constexpr int G = NTHR / T;   // lanes per row
   constexpr int PER = T / G;    // elements of one tile row per lane
   __shared__ double ring[RING][T];
@@ -914,28 +933,26 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (P0 + t < K) {
             const FT *A = tile(K, P0 + t - K + s.bl);
-#pragma unroll
-            for (int m = 0; m < PER; ++m) buf[t][m] = A[i * T + g + m * G];
+            load_chunk<FT, PER>(A + i * T + g * PER, buf[t]);
           }
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (P0 + t < K) {
             const double *xr = ring[(P0 + t) % RING];
 #pragma unroll
-            for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g + m * G];
+            for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g * PER + m];
           }
       }
       const FT *dk = tile(K, s.bl);
       FT dv[PER];
-#pragma unroll
-      for (int m = 0; m < PER; ++m) dv[m] = dk[i * T + g + m * G];
+      load_chunk<FT, PER>(dk + i * T + g * PER, dv);
       a = group_sum<G>(a);
       if (g == 0) acc_s[i] = bv - a;
-      __syncthreads();
+      lds_barrier();
       double y = 0.0;
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
-        const int j = g + m * G;
+        const int j = g * PER + m;
         if (j < i) y += from_ft<FT>(dv[m]) * acc_s[j];
       }
       y = group_sum<G>(y);
@@ -944,7 +961,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
         ring[K % RING][i] = v;
         if (K * T + i < s.n_loc) ybuf[yo + K * T + i] = v;
       }
-      __syncthreads();
+      lds_barrier();
     }
     // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J)
     for (int K = s.nt - 1; K >= 0; --K) {
@@ -957,28 +974,26 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (J0 + t <= je) {
             const FT *A = tile(K, J0 + t - K + s.bl);
-#pragma unroll
-            for (int m = 0; m < PER; ++m) buf[t][m] = A[i * T + g + m * G];
+            load_chunk<FT, PER>(A + i * T + g * PER, buf[t]);
           }
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (J0 + t <= je) {
             const double *xr = ring[(J0 + t) % RING];
 #pragma unroll
-            for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g + m * G];
+            for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g * PER + m];
           }
       }
       const FT *dk = tile(K, s.bl);
       FT dv[PER];
-#pragma unroll
-      for (int m = 0; m < PER; ++m) dv[m] = dk[i * T + g + m * G];
+      load_chunk<FT, PER>(dk + i * T + g * PER, dv);
       a = group_sum<G>(a);
       if (g == 0) acc_s[i] = bv - a;
-      __syncthreads();
+      lds_barrier();
       double y = 0.0;
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
-        const int j = g + m * G;
+        const int j = g * PER + m;
         if (j >= i) y += from_ft<FT>(dv[m]) * acc_s[j];
       }
       y = group_sum<G>(y);
@@ -996,7 +1011,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
   } else {
     // transposed: column access; column ci = tid % T, lane group cg = tid / T
@@ -1028,13 +1043,13 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
 #pragma unroll
       for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
       part_s[cg][ci] = a;
-      __syncthreads();
+      lds_barrier();
       if (tid < T) {
         double t = 0.0;
         for (int q = 0; q < G; ++q) t += part_s[q][tid];
         acc_s[tid] = bv - t;
       }
-      __syncthreads();
+      lds_barrier();
       double y = 0.0;  // y_i = sum_{j <= i} Ui[j][i] acc_j
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
@@ -1042,14 +1057,14 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
         if (j <= ci) y += from_ft<FT>(dv[m]) * acc_s[j];
       }
       part_s[cg][ci] = y;
-      __syncthreads();
+      lds_barrier();
       if (tid < T) {
         double t = 0.0;
         for (int q = 0; q < G; ++q) t += part_s[q][tid];
         ring[K % RING][tid] = t;
         if (K * T + tid < s.n_loc) ybuf[yo + K * T + tid] = t;
       }
-      __syncthreads();
+      lds_barrier();
     }
     // backward with L^T: x_K = Linv_KK^T (y_K - sum_{J>K} L_JK^T x_J)
     for (int K = s.nt - 1; K >= 0; --K) {
@@ -1078,13 +1093,13 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
 #pragma unroll
       for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
       part_s[cg][ci] = a;
-      __syncthreads();
+      lds_barrier();
       if (tid < T) {
         double t = 0.0;
         for (int q = 0; q < G; ++q) t += part_s[q][tid];
         acc_s[tid] = bv - t;
       }
-      __syncthreads();
+      lds_barrier();
       double y = 0.0;  // x_i = acc_i + sum_{j > i} Li[j][i] acc_j
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
@@ -1092,7 +1107,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
         if (j > ci) y += from_ft<FT>(dv[m]) * acc_s[j];
       }
       part_s[cg][ci] = y;
-      __syncthreads();
+      lds_barrier();
       if (tid < T) {
         double t = 0.0;
         for (int q = 0; q < G; ++q) t += part_s[q][tid];
@@ -1106,7 +1121,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
             z[l] = add ? z[l] + v : v;
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
 }
@@ -1163,6 +1178,89 @@ __global__ void k_coarse_prolong(const int64_t *__restrict__ z_ptr, const int32_
   }
 #pragma unroll
   for (int c = 0; c < 5; ++c) z[5 * a + c] += acc[c];
+}
+
+// ----------------------------------------------------------------------
+// Coarse-system solve (one large band system, FP64, non-transposed): one
+// 1024-thread workgroup, one tile column per lane (32 lanes per row).  The
+// tiles of block row K+1 (K-1 in the backward sweep) are loaded while block
+// row K is computed, so the chain of dependent block rows pays the memory
+// latency once instead of once per row.  Requires bl, bu <= 16.
+// ----------------------------------------------------------------------
+constexpr int CS_B = 16;
+__global__ __launch_bounds__(1024) void k_coarse_solve(const double *__restrict__ F, const SubInfo *__restrict__ sp,
+                                                       const double *__restrict__ r, double *__restrict__ z,
+                                                       double *__restrict__ ybuf) {
+  constexpr int T = 32, G = 32;
+  __shared__ double ring[RING][T];
+  __shared__ double acc_s[T];
+  const SubInfo s = *sp;
+  const int tid = threadIdx.x, i = tid / G, g = tid % G;
+  const int W = s.bl + s.bu + 1;
+  auto at = [&](int K, int slot) -> const double * { return F + s.base + ((int64_t)K * W + slot) * (T * T) + i * T + g; };
+  double cur[CS_B + 1], nxt[CS_B + 1];
+  // forward: off-diagonal tiles of block row K are slots t = 0..bl-1 (P = K - bl + t)
+  auto load_fwd = [&](int K, double (&b)[CS_B + 1]) {
+#pragma unroll
+    for (int t = 0; t < CS_B; ++t)
+      if (t < s.bl && K - s.bl + t >= 0) b[t] = *at(K, t);
+    b[CS_B] = *at(K, s.bl);
+  };
+  load_fwd(0, cur);
+  for (int K = 0; K < s.nt; ++K) {
+    const double bv = (g == 0 && K * T + i < s.n_loc) ? r[K * T + i] : 0.0;
+    if (K + 1 < s.nt) load_fwd(K + 1, nxt);
+    double a = 0.0;
+#pragma unroll
+    for (int t = 0; t < CS_B; ++t)
+      if (t < s.bl && K - s.bl + t >= 0) a += cur[t] * ring[(K - s.bl + t) % RING][g];
+    a = group_sum<G>(a);
+    if (g == 0) acc_s[i] = bv - a;
+    lds_barrier();
+    double y = (g < i) ? cur[CS_B] * acc_s[g] : 0.0;
+    y = group_sum<G>(y);
+    if (g == 0) {
+      const double v = acc_s[i] + y;
+      ring[K % RING][i] = v;
+      if (K * T + i < s.n_loc) ybuf[K * T + i] = v;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int t = 0; t <= CS_B; ++t) cur[t] = nxt[t];
+  }
+  // backward: off-diagonal tiles of block row K are slots bl+1+t (J = K + 1 + t)
+  auto load_bwd = [&](int K, double (&b)[CS_B + 1]) {
+#pragma unroll
+    for (int t = 0; t < CS_B; ++t)
+      if (t < s.bu && K + 1 + t < s.nt) b[t] = *at(K, s.bl + 1 + t);
+    b[CS_B] = *at(K, s.bl);
+  };
+  load_bwd(s.nt - 1, cur);
+  for (int K = s.nt - 1; K >= 0; --K) {
+    const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[K * T + i] : 0.0;
+    if (K > 0) load_bwd(K - 1, nxt);
+    double a = 0.0;
+#pragma unroll
+    for (int t = 0; t < CS_B; ++t)
+      if (t < s.bu && K + 1 + t < s.nt) a += cur[t] * ring[(K + 1 + t) % RING][g];
+    a = group_sum<G>(a);
+    if (g == 0) acc_s[i] = bv - a;
+    lds_barrier();
+    double y = (g >= i) ? cur[CS_B] * acc_s[g] : 0.0;
+    y = group_sum<G>(y);
+    if (g == 0) {
+      ring[K % RING][i] = y;
+      if (K * T + i < s.n_loc) z[K * T + i] = y;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int t = 0; t <= CS_B; ++t) cur[t] = nxt[t];
+  }
+}
+
+void launch_coarse_solve(const double *F, const SubInfo *sp, const double *r, double *z, double *ybuf,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(1024), 0, st, F, sp, r, z, ybuf);
 }
 
 // ----------------------------------------------------------------------
