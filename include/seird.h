@@ -254,6 +254,43 @@ seird_status seird_step(seird_problem p, seird_precond pc, double *u,
                         seird_step_stats *stats, void *stream);
 
 /* ------------------------------------------------------------------
+ * Batches: several independent problems (uneven meshes, their own rates
+ * and diffusion coefficients) stepped together.  The instances are laid
+ * side by side as one block-diagonal system, so every kernel (assembly,
+ * SpMV, every Schwarz subdomain factorisation and solve, in
+ * largest-first order) is one launch over all instances, while every
+ * reduction, GMRES coefficient, stopping test and Newton iteration is kept
+ * per instance: each instance's result is the one it gets alone (bitwise
+ * for pc_reuse = 0).  One-level RAS.
+ * ------------------------------------------------------------------ */
+typedef struct seird_batch_s *seird_batch;
+/* n_inst instances; per instance k: n_nodes[k], xy[k] (host [n][2]),
+ * n_tri[k], tri[k] (host [n_tri][3], local numbering), params[k],
+ * part[k] (host [n_nodes[k]] owner subdomain in [0, n_sub[k])).  overlap,
+ * tile and factor_prec as in seird_schwarz_opts.  Host arrays are copied. */
+seird_status seird_batch_create(int32_t n_inst, const int64_t *n_nodes,
+                                const double *const *xy,
+                                const int64_t *n_tri,
+                                const int32_t *const *tri,
+                                const seird_params *params,
+                                const int32_t *const *part,
+                                const int32_t *n_sub, int32_t overlap,
+                                int32_t tile, int32_t factor_prec,
+                                seird_batch *out);
+void seird_batch_destroy(seird_batch b);
+/* node_offsets [n_inst + 1] (host): instance k owns nodes
+ * [node_offsets[k], node_offsets[k+1]) of the batch state. */
+seird_status seird_batch_info(seird_batch b, int64_t *node_offsets);
+/* One implicit step of every instance: u is the device float64 state
+ * [total_nodes][5], instance after instance.  per_instance[n_inst]
+ * (nullable) receives each instance's Newton/GMRES statistics.
+ * Synchronising. */
+seird_status seird_batch_step(seird_batch b, double *u, double dt,
+                              const seird_newton_opts *nopts,
+                              const seird_krylov_opts *kopts,
+                              seird_step_stats *per_instance, void *stream);
+
+/* ------------------------------------------------------------------
  * Discrete adjoint of a case-count observation (reverse sweep with
  * checkpointing).  Parameters theta = (g, nu): the transmission field g
  * (seird_set_beta_field) and the five diffusion coefficients nu

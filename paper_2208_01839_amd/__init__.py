@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Problem", "Precond", "SeirdError", "gmres", "step", "forward_record",
+__all__ = ["Problem", "Precond", "Batch", "SeirdError", "gmres", "step", "forward_record",
            "adjoint", "SEIRDRun", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -121,6 +121,12 @@ _SIGS = {
                              ctypes.c_int),
     "seird_adjoint": ([_P, _P, _P, _P, _P, ctypes.POINTER(_Krylov), ctypes.POINTER(_AStats), _P],
                       ctypes.c_int),
+    "seird_batch_create": ([ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
+    "seird_batch_destroy": ([_P], None),
+    "seird_batch_info": ([_P, _P], ctypes.c_int),
+    "seird_batch_step": ([_P, _P, ctypes.c_double, ctypes.POINTER(_Newton), ctypes.POINTER(_Krylov),
+                          _P, _P], ctypes.c_int),
 }
 
 
@@ -457,3 +463,58 @@ class _LazyRun:
 
 
 SEIRDRun = _LazyRun()
+
+
+class Batch:
+    """Independent problems stepped together (one-level RAS).  instances: a
+    list of (xy, tri, params, part, n_sub).  The batch state is the
+    concatenation of the instances' [n_k, 5] states."""
+
+    def __init__(self, instances, overlap=2, tile=32, factor_prec=0):
+        K = len(instances)
+        keep = []
+        nn = np.array([len(x[0]) for x in instances], dtype=np.int64)
+        nt = np.array([len(x[1]) for x in instances], dtype=np.int64)
+        xys = [np.ascontiguousarray(x[0], dtype=np.float64) for x in instances]
+        tris = [np.ascontiguousarray(x[1], dtype=np.int32) for x in instances]
+        parts = [np.ascontiguousarray(x[3], dtype=np.int32) for x in instances]
+        keep += xys + tris + parts
+        P = (_Params * K)(*[_params(x[2]) for x in instances])
+        xyp = (ctypes.c_void_p * K)(*[a.ctypes.data for a in xys])
+        trp = (ctypes.c_void_p * K)(*[a.ctypes.data for a in tris])
+        pap = (ctypes.c_void_p * K)(*[a.ctypes.data for a in parts])
+        nsub = np.array([x[4] for x in instances], dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().seird_batch_create(K, nn.ctypes.data, ctypes.cast(xyp, ctypes.c_void_p),
+                                        nt.ctypes.data, ctypes.cast(trp, ctypes.c_void_p),
+                                        ctypes.cast(P, ctypes.c_void_p), ctypes.cast(pap, ctypes.c_void_p),
+                                        nsub.ctypes.data, int(overlap), int(tile), int(factor_prec),
+                                        ctypes.byref(h)))
+        del keep
+        self.h = h
+        self.K = K
+        off = np.zeros(K + 1, dtype=np.int64)
+        _check(lib().seird_batch_info(self.h, off.ctypes.data))
+        self.node_offsets = off
+        self.n = int(off[-1])
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.seird_batch_destroy(self.h)
+            self.h = None
+
+    def step(self, u, dt, tol=1e-10, max_it=20, pc_reuse=0, **kw):
+        """One implicit step of every instance, in place on u [n_total, 5].
+        Returns a list of per-instance statistics."""
+        n = _Newton(float(tol), int(max_it), int(pc_reuse))
+        o = _krylov(**kw)
+        st = (_SStats * self.K)()
+        code = lib().seird_batch_step(self.h, _dptr(u, 5 * self.n, "u"), float(dt), ctypes.byref(n),
+                                      ctypes.byref(o), ctypes.cast(st, ctypes.c_void_p), _stream())
+        _check(code)
+        out = []
+        for s in st:
+            k = s.newton_its
+            out.append(dict(newton_its=k, gmres_its=list(s.gmres_its[:k]),
+                            res_hist=list(s.res_hist[:k + 1]), pc_setups=s.pc_setups))
+        return out

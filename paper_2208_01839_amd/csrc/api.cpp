@@ -65,6 +65,14 @@ struct seird_problem_s {
   int kcap = 0;
   double *w1 = nullptr;  // scratch vector
   size_t lds_limit = 65536;
+  // segments of the unknown vector (one per instance of a batch; one for a
+  // single problem), per-segment masks and scalars
+  static constexpr int HLD = KRYLOV_MAX + 8;
+  SegHost seg, seg_act, seg_re;  // no mask / active mask / second mask
+  uint8_t *d_mask = nullptr, *d_mask2 = nullptr;
+  double *d_svec = nullptr;
+  int32_t *d_inst = nullptr;
+  ParamsDev *d_Pinst = nullptr;
   // adjoint record (checkpoints, last segment, regions)
   struct Tape {
     int n_steps = 0, every = 0, n_regions = 0;
@@ -97,19 +105,71 @@ struct seird_problem_s {
     dev_free(gfield); dev_free(partials); dev_free(hdev); dev_free(ydev); dev_free(flags);
     dev_free(u_prev); dev_free(F); dev_free(rhs); dev_free(delta); dev_free(vals);
     dev_free(V); dev_free(Zb); dev_free(w1);
+    dev_free(seg.d_seg_start); dev_free(seg.d_blk_start); dev_free(seg.d_block_seg);
+    dev_free(d_mask); dev_free(d_mask2); dev_free(d_svec); dev_free(d_inst); dev_free(d_Pinst);
     tape.release();
+  }
+
+  // segments from instance node offsets (node_start[S+1], node_start[S] = n)
+  void setup_segments(const std::vector<int64_t> &node_start) {
+    dev_free(seg.d_seg_start); dev_free(seg.d_blk_start); dev_free(seg.d_block_seg);
+    SegHost g;
+    g.S = (int)node_start.size() - 1;
+    g.seg_start.resize(g.S + 1);
+    g.blk_start.assign(g.S + 1, 0);
+    for (int s = 0; s <= g.S; ++s) g.seg_start[s] = 5 * node_start[s];
+    for (int s = 0; s < g.S; ++s) {
+      const int64_t len = g.seg_start[s + 1] - g.seg_start[s];
+      g.blk_start[s + 1] = g.blk_start[s] + std::max<int64_t>(1, (len + SEG_CH - 1) / SEG_CH);
+    }
+    g.B = (int)g.blk_start[g.S];
+    g.block_seg.resize(g.B);
+    for (int s = 0; s < g.S; ++s)
+      for (int64_t b = g.blk_start[s]; b < g.blk_start[s + 1]; ++b) g.block_seg[b] = s;
+    g.d_seg_start = dev_upload(g.seg_start);
+    g.d_blk_start = dev_upload(g.blk_start);
+    g.d_block_seg = dev_upload(g.block_seg);
+    seg = g;
+    dev_free(d_mask); dev_free(d_mask2); dev_free(d_svec);
+    d_mask = dev_alloc<uint8_t>(g.S);
+    d_mask2 = dev_alloc<uint8_t>(g.S);
+    d_svec = dev_alloc<double>(g.S);
+    seg_act = g;
+    seg_act.d_active = d_mask;
+    seg_re = g;
+    seg_re.d_active = d_mask2;
+    dev_free(partials); dev_free(hdev); dev_free(ydev);
+    partials = dev_alloc<double>((size_t)g.B * (KRYLOV_MAX + 2));
+    hdev = dev_alloc<double>((size_t)g.S * HLD);
+    ydev = dev_alloc<double>((size_t)g.S * HLD);
+  }
+  // per-segment 2-norms (scale: optional per-node weights)
+  std::vector<double> seg_norms(const double *x, hipStream_t st, const double *scale = nullptr) {
+    launch_seg_norm2(seg, x, scale, partials, st);
+    launch_seg_reduce(seg, partials, 1, hdev, HLD, 0, st);
+    std::vector<double> h((size_t)seg.S * HLD);
+    HIPCHECK(hipMemcpyAsync(h.data(), hdev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    std::vector<double> out(seg.S);
+    for (int s = 0; s < seg.S; ++s) out[s] = std::sqrt(h[(size_t)s * HLD]);
+    return out;
+  }
+  void upload_mask(uint8_t *d, const std::vector<uint8_t> &m, hipStream_t st) {
+    HIPCHECK(hipMemcpyAsync(d, m.data(), m.size(), hipMemcpyHostToDevice, st));
+  }
+  void upload_scalars(const std::vector<double> &v, hipStream_t st) {
+    HIPCHECK(hipMemcpyAsync(d_svec, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, st));
   }
   int64_t nvals() const { return 25 * mh.n + 10 * (int64_t)mh.col.size(); }
   const double *diag(const double *v) const { return v; }
   const double *off(const double *v) const { return v + 25 * mh.n; }
 
   double norm(const double *x, hipStream_t st, const double *scale = nullptr) {
-    launch_norm2_partials(x, scale, N, partials, nb, st);
-    launch_reduce(partials, nb, 1, hdev, st);
-    double h;
-    HIPCHECK(hipMemcpyAsync(&h, hdev, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    return std::sqrt(h);
+    // the norm of the whole vector (all segments)
+    const std::vector<double> v = seg_norms(x, st, scale);
+    double t = 0.0;
+    for (double e : v) t += e * e;
+    return std::sqrt(t);
   }
   void ensure_krylov(int m) {
     if (kcap >= m) return;
@@ -274,218 +334,340 @@ struct seird_precond_s {
 };
 
 // ------------------------------------------------------------------------
-// GMRES (right preconditioned, restarted, CGS + one conditional DGKS pass)
+// GMRES (right preconditioned, restarted, CGS + one conditional DGKS pass),
+// run independently on every active segment (instance): per-segment
+// Hessenberg, Givens rotations, stopping and restarts; the segments still
+// running advance in lockstep through shared kernel launches that mask the
+// others.  A single problem is one segment.
 // ------------------------------------------------------------------------
-static int gmres_impl(seird_problem P, seird_precond pc, const double *vals, const double *b, double *x,
-                      const seird_krylov_opts &o, seird_krylov_stats &stats, int transpose, hipStream_t st) {
+static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, const double *b, double *x,
+                       const seird_krylov_opts &o, std::vector<seird_krylov_stats> &stats,
+                       const std::vector<uint8_t> &active_in, int transpose, hipStream_t st) {
   const int64_t N = P->N;
+  const int S = P->seg.S;
+  const int HLD = P->HLD;
   const int m = o.restart;
   if (m < 1 || m > KRYLOV_MAX - 1) fail(SEIRD_ERR_ARG, "restart must be in [1, 31]");
   if (o.max_it < 0) fail(SEIRD_ERR_ARG, "max_it must be >= 0");
   P->ensure_krylov(m);
-  const int nb = P->nb;
   double *V = P->V, *Zb = P->Zb;
+  stats.assign(S, seird_krylov_stats{});
   HIPCHECK(hipMemsetAsync(x, 0, sizeof(double) * N, st));
-  const double bnorm = P->norm(b, st);
-  stats = seird_krylov_stats{0, 0, bnorm, bnorm};
-  if (!std::isfinite(bnorm)) fail(SEIRD_ERR_NONFINITE, "nonfinite right-hand side");
-  const double target = std::max(o.rtol * bnorm, o.atol);
-  if (bnorm <= target) {
-    stats.reason = 1;
-    return SEIRD_OK;
+  const std::vector<double> bnorm = P->seg_norms(b, st);
+  std::vector<uint8_t> act(S, 0);
+  std::vector<double> target(S, 0.0), beta(S, 0.0), sc(S, 0.0);
+  std::vector<int> its(S, 0);
+  for (int s = 0; s < S; ++s) {
+    stats[s].bnorm = stats[s].resid = bnorm[s];
+    if (!active_in[s]) continue;
+    if (!std::isfinite(bnorm[s])) fail(SEIRD_ERR_NONFINITE, "nonfinite right-hand side");
+    target[s] = std::max(o.rtol * bnorm[s], o.atol);
+    if (bnorm[s] <= target[s]) {
+      stats[s].reason = 1;
+      continue;
+    }
+    act[s] = 1;
+    beta[s] = bnorm[s];
+    sc[s] = 1.0 / beta[s];
   }
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hbuf(KRYLOV_MAX + 4);
-  double beta = bnorm;
-  launch_axpby(V, b, 1.0 / beta, nullptr, 0, 0.0, N, nb, st);
-  int its = 0;
+  auto any = [](const std::vector<uint8_t> &v) {
+    for (uint8_t e : v)
+      if (e) return true;
+    return false;
+  };
+  if (!any(act)) return;
+  P->upload_mask(P->d_mask, act, st);
+  P->upload_scalars(sc, st);
+  launch_seg_axpby(P->seg_act, V, b, P->d_svec, 0.0, st);
+  std::vector<double> H((size_t)S * (m + 1) * m), cs((size_t)S * m), sn((size_t)S * m), g((size_t)S * (m + 1));
+  std::vector<double> hbuf((size_t)S * HLD), ybuf((size_t)S * HLD);
   const double eta = 1.0 / std::sqrt(2.0);
-  while (true) {
+  auto Hs = [&](int s, int i, int j) -> double & { return H[(size_t)s * (m + 1) * m + (size_t)i * m + j]; };
+  // x += Z y for the segments in `fin`, each with k columns
+  auto update = [&](const std::vector<uint8_t> &fin, int k) {
+    for (int s = 0; s < S; ++s) {
+      if (!fin[s]) continue;
+      double *y = &ybuf[(size_t)s * HLD];
+      for (int i = k - 1; i >= 0; --i) {
+        double t = g[(size_t)s * (m + 1) + i];
+        for (int l = i + 1; l < k; ++l) t -= Hs(s, i, l) * y[l];
+        y[i] = t / Hs(s, i, i);
+      }
+    }
+    HIPCHECK(hipMemcpyAsync(P->ydev, ybuf.data(), sizeof(double) * ybuf.size(), hipMemcpyHostToDevice, st));
+    P->upload_mask(P->d_mask2, fin, st);
+    launch_seg_gemv_update(P->seg_re, x, Zb, N, P->ydev, HLD, k, st);
+  };
+  while (any(act)) {
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
-    int reason = 0;
-    for (int j = 0; j < m; ++j) {
+    for (int s = 0; s < S; ++s)
+      if (act[s]) g[(size_t)s * (m + 1)] = beta[s];
+    std::vector<uint8_t> cyc = act;  // segments running in this cycle
+    int j = 0;
+    for (; j < m && any(cyc); ++j) {
       double *vj = V + (int64_t)j * N, *zj = Zb + (int64_t)j * N, *w = V + (int64_t)(j + 1) * N;
       if (pc)
         pc->apply(vals, vj, zj, transpose, st);
       else
         HIPCHECK(hipMemcpyAsync(zj, vj, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
       launch_spmv(P->md, P->diag(vals), P->off(vals), zj, nullptr, w, transpose, st);
-      // h = V^T w, plus w.w
-      launch_mdot(V, N, j + 1, w, N, 1, P->partials, nb, st);
-      launch_reduce(P->partials, nb, j + 2, P->hdev, st);
-      launch_maxpy_norm(w, V, N, P->hdev, j + 1, N, P->partials, nb, st);
-      launch_reduce(P->partials, nb, 1, P->hdev + j + 2, st);
-      HIPCHECK(hipMemcpyAsync(hbuf.data(), P->hdev, sizeof(double) * (j + 3), hipMemcpyDeviceToHost, st));
+      P->upload_mask(P->d_mask, cyc, st);
+      launch_seg_mdot(P->seg_act, V, N, j + 1, w, 1, P->partials, st);
+      launch_seg_reduce(P->seg, P->partials, j + 2, P->hdev, HLD, 0, st);
+      launch_seg_maxpy_norm(P->seg_act, w, V, N, P->hdev, HLD, j + 1, P->partials, st);
+      launch_seg_reduce(P->seg, P->partials, 1, P->hdev, HLD, j + 2, st);
+      HIPCHECK(hipMemcpyAsync(hbuf.data(), P->hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
-      for (int i = 0; i <= j; ++i) H[i * m + j] = hbuf[i];
-      const double wn0 = std::sqrt(hbuf[j + 1]);
-      double wn = std::sqrt(hbuf[j + 2]);
-      if (!std::isfinite(wn) || !std::isfinite(wn0)) fail(SEIRD_ERR_NONFINITE, "nonfinite Arnoldi vector");
-      if (wn < eta * wn0) {  // DGKS: one reorthogonalisation pass
-        launch_mdot(V, N, j + 1, w, N, 0, P->partials, nb, st);
-        launch_reduce(P->partials, nb, j + 1, P->hdev, st);
-        launch_maxpy_norm(w, V, N, P->hdev, j + 1, N, P->partials, nb, st);
-        launch_reduce(P->partials, nb, 1, P->hdev + j + 1, st);
-        HIPCHECK(hipMemcpyAsync(hbuf.data(), P->hdev, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, st));
+      std::vector<uint8_t> re(S, 0);
+      std::vector<double> wn(S, 0.0);
+      bool any_re = false;
+      for (int s = 0; s < S; ++s) {
+        if (!cyc[s]) continue;
+        for (int i = 0; i <= j; ++i) Hs(s, i, j) = hbuf[(size_t)s * HLD + i];
+        const double wn0 = std::sqrt(hbuf[(size_t)s * HLD + j + 1]);
+        wn[s] = std::sqrt(hbuf[(size_t)s * HLD + j + 2]);
+        if (!std::isfinite(wn[s]) || !std::isfinite(wn0)) fail(SEIRD_ERR_NONFINITE, "nonfinite Arnoldi vector");
+        if (wn[s] < eta * wn0) {
+          re[s] = 1;
+          any_re = true;
+        }
+      }
+      if (any_re) {  // DGKS: one reorthogonalisation pass for those segments
+        P->upload_mask(P->d_mask2, re, st);
+        launch_seg_mdot(P->seg_re, V, N, j + 1, w, 0, P->partials, st);
+        launch_seg_reduce(P->seg, P->partials, j + 1, P->hdev, HLD, 0, st);
+        launch_seg_maxpy_norm(P->seg_re, w, V, N, P->hdev, HLD, j + 1, P->partials, st);
+        launch_seg_reduce(P->seg, P->partials, 1, P->hdev, HLD, j + 1, st);
+        HIPCHECK(hipMemcpyAsync(hbuf.data(), P->hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
-        for (int i = 0; i <= j; ++i) H[i * m + j] += hbuf[i];
-        wn = std::sqrt(hbuf[j + 1]);
+        for (int s = 0; s < S; ++s) {
+          if (!re[s]) continue;
+          for (int i = 0; i <= j; ++i) Hs(s, i, j) += hbuf[(size_t)s * HLD + i];
+          wn[s] = std::sqrt(hbuf[(size_t)s * HLD + j + 1]);
+        }
       }
-      H[(j + 1) * m + j] = wn;
-      if (wn > 0.0) launch_axpby(w, w, 1.0 / wn, nullptr, 0, 0.0, N, nb, st);
-      // Givens rotations
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-        H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-        H[i * m + j] = t;
+      for (int s = 0; s < S; ++s) sc[s] = (cyc[s] && wn[s] > 0.0) ? 1.0 / wn[s] : 0.0;
+      P->upload_scalars(sc, st);
+      launch_seg_axpby(P->seg_act, w, w, P->d_svec, 0.0, st);
+      std::vector<uint8_t> fin(S, 0);
+      std::vector<int> kfin(S, 0);
+      bool any_fin = false;
+      for (int s = 0; s < S; ++s) {
+        if (!cyc[s]) continue;
+        Hs(s, j + 1, j) = wn[s];
+        double *c = &cs[(size_t)s * m], *sn_ = &sn[(size_t)s * m], *gg = &g[(size_t)s * (m + 1)];
+        for (int i = 0; i < j; ++i) {
+          const double t = c[i] * Hs(s, i, j) + sn_[i] * Hs(s, i + 1, j);
+          Hs(s, i + 1, j) = -sn_[i] * Hs(s, i, j) + c[i] * Hs(s, i + 1, j);
+          Hs(s, i, j) = t;
+        }
+        const double den = std::hypot(Hs(s, j, j), Hs(s, j + 1, j));
+        int reason = 0;
+        if (den == 0.0) {
+          reason = 2;  // exact breakdown: the first j columns hold the solution
+          kfin[s] = j;
+        } else {
+          c[j] = Hs(s, j, j) / den;
+          sn_[j] = Hs(s, j + 1, j) / den;
+          Hs(s, j, j) = den;
+          Hs(s, j + 1, j) = 0.0;
+          gg[j + 1] = -sn_[j] * gg[j];
+          gg[j] = c[j] * gg[j];
+          ++its[s];
+          kfin[s] = j + 1;
+          const double res = std::fabs(gg[j + 1]);
+          stats[s].resid = res;
+          if (res < target[s]) reason = 1;
+          else if (res > o.dtol * bnorm[s]) reason = SEIRD_ERR_DIVERGED;
+          else if (its[s] >= o.max_it) reason = SEIRD_ERR_NOT_CONVERGED;
+          else if (wn[s] == 0.0) reason = 2;
+        }
+        if (reason != 0) {
+          stats[s].reason = reason;
+          stats[s].its = its[s];
+          fin[s] = 1;
+          any_fin = true;
+        }
       }
-      const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-      if (den == 0.0) {
-        reason = 2;
-        break;
+      if (any_fin) {
+        for (int kk : {j + 1, j}) {
+          std::vector<uint8_t> f(S, 0);
+          bool anyf = false;
+          for (int s = 0; s < S; ++s)
+            if (fin[s] && kfin[s] == kk) {
+              f[s] = 1;
+              anyf = true;
+            }
+          if (anyf && kk > 0) update(f, kk);
+        }
+        for (int s = 0; s < S; ++s)
+          if (fin[s]) {
+            cyc[s] = 0;
+            act[s] = 0;
+          }
       }
-      cs[j] = H[j * m + j] / den;
-      sn[j] = H[(j + 1) * m + j] / den;
-      H[j * m + j] = den;
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++its;
-      k = j + 1;
-      const double res = std::fabs(g[j + 1]);
-      stats.resid = res;
-      if (res < target) { reason = 1; break; }
-      if (res > o.dtol * bnorm) { reason = SEIRD_ERR_DIVERGED; break; }
-      if (its >= o.max_it) { reason = SEIRD_ERR_NOT_CONVERGED; break; }
-      if (wn == 0.0) { reason = 2; break; }
     }
-    if (k > 0) {
-      for (int i = k - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int l = i + 1; l < k; ++l) s -= H[i * m + l] * y[l];
-        y[i] = s / H[i * m + i];
+    // segments that completed a full cycle: update, restart from the true residual
+    if (any(cyc)) {
+      update(cyc, m);
+      P->upload_mask(P->d_mask, cyc, st);
+      launch_spmv(P->md, P->diag(vals), P->off(vals), x, b, V, transpose, st);
+      const std::vector<double> bt = P->seg_norms(V, st);
+      for (int s = 0; s < S; ++s) {
+        if (!cyc[s]) continue;
+        beta[s] = bt[s];
+        stats[s].resid = bt[s];
+        if (bt[s] <= target[s]) {
+          stats[s].reason = 1;
+          stats[s].its = its[s];
+          act[s] = 0;
+          cyc[s] = 0;
+        }
+        sc[s] = cyc[s] ? 1.0 / bt[s] : 0.0;
       }
-      HIPCHECK(hipMemcpyAsync(P->ydev, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
-      launch_gemv_update(x, Zb, N, P->ydev, k, N, nb, st);
+      if (any(cyc)) {
+        P->upload_mask(P->d_mask, cyc, st);
+        P->upload_scalars(sc, st);
+        launch_seg_axpby(P->seg_act, V, V, P->d_svec, 0.0, st);
+      }
     }
-    if (reason != 0) {
-      stats.its = its;
-      stats.reason = reason;
-      HIPCHECK(hipStreamSynchronize(st));
-      return reason > 0 ? SEIRD_OK : reason;
-    }
-    // restart from the true residual
-    launch_spmv(P->md, P->diag(vals), P->off(vals), x, b, V, transpose, st);
-    beta = P->norm(V, st);
-    stats.resid = beta;
-    if (beta <= target) {
-      stats.its = its;
-      stats.reason = 1;
-      return SEIRD_OK;
-    }
-    launch_axpby(V, V, 1.0 / beta, nullptr, 0, 0.0, N, nb, st);
   }
+  HIPCHECK(hipStreamSynchronize(st));
 }
 
 static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t st);
 
+// One implicit step on every segment (instance) of u: each segment runs its
+// own Newton iteration (own residual scale, stopping test and counters); a
+// converged segment is frozen while the others continue.  The
+// preconditioner is shared: its setup schedule (first iteration, then every
+// pc_reuse + 1 iterations, or when a reused setup failed or stopped paying)
+// applies to all segments together.
 static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, const double *src,
-                      const seird_newton_opts *nopts, const seird_krylov_opts *kopts, seird_step_stats &s,
-                      hipStream_t st) {
-  {
-    if (!p || !u || !nopts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
-    if (nopts->max_it < 0 || nopts->max_it > SEIRD_MAX_NEWTON) fail(SEIRD_ERR_ARG, "Newton max_it out of range");
-    if (nopts->pc_reuse < 0) fail(SEIRD_ERR_ARG, "pc_reuse must be >= 0");
-    using clk = std::chrono::steady_clock;
-    auto ms = [](clk::time_point a, clk::time_point b) {
-      return std::chrono::duration<double, std::milli>(b - a).count();
-    };
-    const int64_t N = p->N;
-    HIPCHECK(hipMemcpyAsync(p->u_prev, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-    auto check_state = [&](const double *x) {
-      HIPCHECK(hipMemsetAsync(p->flags, 0, sizeof(int), st));
-      launch_check_state(x, p->mh.n, p->flags, st);
-      int f = 0;
-      HIPCHECK(hipMemcpyAsync(&f, p->flags, sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipStreamSynchronize(st));
-      if (f & 1) fail(SEIRD_ERR_NONFINITE, "nonfinite state");
-      if (f & 2) fail(SEIRD_ERR_STATE, "total density N <= 0 at a node");
-    };
-    check_state(u);
-    const double scale = p->norm(p->u_prev, st, p->md.mass);
-    const double unorm = p->norm(p->u_prev, st);
-    double *diag = p->vals, *off = p->vals + 25 * p->mh.n;
-    int last_setup = 0, its_fresh = 0;
-    bool stale = false;
-    for (int k = 0;; ++k) {
-      auto t0 = clk::now();
-      launch_residual(p->md, p->P, p->gfield, u, p->u_prev, dt, src, p->F, st);
-      const double fn = p->norm(p->F, st);
-      s.t_residual_ms += ms(t0, clk::now());
-      s.res_hist[k] = fn / scale;
-      if (!std::isfinite(fn)) fail(SEIRD_ERR_NONFINITE, "nonfinite residual");
-      if (fn <= nopts->tol * scale) break;
-      if (k >= nopts->max_it) fail(SEIRD_ERR_NOT_CONVERGED, "Newton did not converge");
-      t0 = clk::now();
-      launch_jacobian(p->md, p->P, p->gfield, u, dt, diag, off, st);
-      HIPCHECK(hipStreamSynchronize(st));
-      s.t_jacobian_ms += ms(t0, clk::now());
-      // preconditioner setup: fresh at the first iteration, then every
-      // pc_reuse + 1 iterations, or when the reused one was marked stale
-      t0 = clk::now();
-      bool fresh = false;
-      if (pc && (k == 0 || stale || (k - last_setup) > nopts->pc_reuse)) {
-        precond_setup_impl(pc, p->vals, st);
-        s.pc_setups++;
-        last_setup = k;
-        stale = false;
-        fresh = true;
-      }
-      s.t_setup_ms += ms(t0, clk::now());
-      t0 = clk::now();
-      launch_axpby(p->rhs, p->F, -1.0, nullptr, 0, 0.0, N, p->nb, st);
-      seird_krylov_stats ks{};
-      int rc = gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, 0, st);
-      if (pc && !fresh && rc != SEIRD_OK) {
-        // a reused setup failed: rebuild it from the current Jacobian and retry
-        auto t1 = clk::now();
-        precond_setup_impl(pc, p->vals, st);
-        s.pc_setups++;
-        last_setup = k;
-        s.t_setup_ms += ms(t1, clk::now());
-        const int its_first = ks.its;
-        rc = gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, 0, st);
-        ks.its += its_first;
-        fresh = true;
-      }
-      if (fresh) its_fresh = ks.its;
-      else if (ks.its > 2 * its_fresh + 5) stale = true;  // reuse no longer pays
-      s.t_gmres_ms += ms(t0, clk::now());
-      if (pc && pc->timing) {
-        HIPCHECK(hipStreamSynchronize(st));
-        pc->harvest();
-      }
-      s.gmres_its[k] = ks.its;
-      s.gmres_its_total += ks.its;
-      s.newton_its = k + 1;
-      if (rc == SEIRD_ERR_DIVERGED) fail(rc, "GMRES diverged");
-      // max_it without convergence: inexact Newton update is still taken
-      launch_axpby(u, p->delta, 1.0, nullptr, 0, 1.0, N, p->nb, st);
-      s.eps = p->norm(p->delta, st) / unorm;
-      check_state(u);
+                      const seird_newton_opts *nopts, const seird_krylov_opts *kopts,
+                      std::vector<seird_step_stats> &stats, hipStream_t st) {
+  if (!p || !u || !nopts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
+  if (nopts->max_it < 0 || nopts->max_it > SEIRD_MAX_NEWTON) fail(SEIRD_ERR_ARG, "Newton max_it out of range");
+  if (nopts->pc_reuse < 0) fail(SEIRD_ERR_ARG, "pc_reuse must be >= 0");
+  using clk = std::chrono::steady_clock;
+  auto ms = [](clk::time_point a0, clk::time_point b0) {
+    return std::chrono::duration<double, std::milli>(b0 - a0).count();
+  };
+  const int S = p->seg.S;
+  stats.assign(S, seird_step_stats{});
+  const int64_t N = p->N;
+  HIPCHECK(hipMemcpyAsync(p->u_prev, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+  auto check_state = [&](const double *x) {
+    HIPCHECK(hipMemsetAsync(p->flags, 0, sizeof(int), st));
+    launch_check_state(x, p->mh.n, p->flags, st);
+    int f = 0;
+    HIPCHECK(hipMemcpyAsync(&f, p->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    if (f & 1) fail(SEIRD_ERR_NONFINITE, "nonfinite state");
+    if (f & 2) fail(SEIRD_ERR_STATE, "total density N <= 0 at a node");
+  };
+  check_state(u);
+  const std::vector<double> scale = p->seg_norms(p->u_prev, st, p->md.mass);
+  const std::vector<double> unorm = p->seg_norms(p->u_prev, st);
+  double *diag = p->vals, *off = p->vals + 25 * p->mh.n;
+  std::vector<uint8_t> act(S, 1);
+  int last_setup = 0, its_fresh = 0;
+  bool stale = false;
+  std::vector<seird_krylov_stats> ks;
+  double t_res = 0, t_jac = 0, t_set = 0, t_gm = 0;
+  int setups = 0;
+  for (int k = 0;; ++k) {
+    auto t0 = clk::now();
+    launch_residual(p->md, p->P, p->gfield, u, p->u_prev, dt, src, p->F, st);
+    const std::vector<double> fn = p->seg_norms(p->F, st);
+    t_res += ms(t0, clk::now());
+    bool any_act = false;
+    for (int s = 0; s < S; ++s) {
+      if (!act[s]) continue;
+      stats[s].res_hist[k] = fn[s] / scale[s];
+      if (!std::isfinite(fn[s])) fail(SEIRD_ERR_NONFINITE, "nonfinite residual");
+      if (fn[s] <= nopts->tol * scale[s])
+        act[s] = 0;
+      else
+        any_act = true;
     }
+    if (!any_act) break;
+    if (k >= nopts->max_it) fail(SEIRD_ERR_NOT_CONVERGED, "Newton did not converge");
+    t0 = clk::now();
+    launch_jacobian(p->md, p->P, p->gfield, u, dt, diag, off, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    t_jac += ms(t0, clk::now());
+    t0 = clk::now();
+    bool fresh = false;
+    if (pc && (k == 0 || stale || (k - last_setup) > nopts->pc_reuse)) {
+      precond_setup_impl(pc, p->vals, st);
+      ++setups;
+      last_setup = k;
+      stale = false;
+      fresh = true;
+    }
+    t_set += ms(t0, clk::now());
+    t0 = clk::now();
+    launch_axpby(p->rhs, p->F, -1.0, nullptr, 0, 0.0, N, reduction_blocks(N), st);
+    gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, act, 0, st);
+    bool failed = false;
+    for (int s = 0; s < S; ++s)
+      if (act[s] && ks[s].reason < 0) failed = true;
+    std::vector<int> its_first(S, 0);
+    if (pc && !fresh && failed) {
+      // a reused setup failed: rebuild it from the current Jacobian and retry
+      auto t1 = clk::now();
+      precond_setup_impl(pc, p->vals, st);
+      ++setups;
+      last_setup = k;
+      t_set += ms(t1, clk::now());
+      for (int s = 0; s < S; ++s) its_first[s] = ks[s].its;
+      gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, act, 0, st);
+      fresh = true;
+    }
+    int its_max = 0;
+    for (int s = 0; s < S; ++s)
+      if (act[s]) its_max = std::max(its_max, ks[s].its + its_first[s]);
+    if (fresh) its_fresh = its_max;
+    else if (its_max > 2 * its_fresh + 5) stale = true;  // reuse no longer pays
+    t_gm += ms(t0, clk::now());
     if (pc && pc->timing) {
-      s.t_ras_kernel_ms = pc->ras_ms;
-      s.n_ras_launches = pc->ras_count;
-      s.ras_bytes_per_launch = pc->ras_bytes();
-      pc->ras_ms = 0.0;
-      pc->ras_count = 0;
+      HIPCHECK(hipStreamSynchronize(st));
+      pc->harvest();
     }
+    for (int s = 0; s < S; ++s) {
+      if (!act[s]) continue;
+      stats[s].gmres_its[k] = ks[s].its + its_first[s];
+      stats[s].gmres_its_total += ks[s].its + its_first[s];
+      stats[s].newton_its = k + 1;
+      if (ks[s].reason == SEIRD_ERR_DIVERGED) fail(SEIRD_ERR_DIVERGED, "GMRES diverged");
+    }
+    // max_it without convergence: the inexact Newton update is still taken;
+    // frozen segments have a zero update
+    launch_axpby(u, p->delta, 1.0, nullptr, 0, 1.0, N, reduction_blocks(N), st);
+    const std::vector<double> dn = p->seg_norms(p->delta, st);
+    for (int s = 0; s < S; ++s)
+      if (act[s]) stats[s].eps = dn[s] / unorm[s];
+    check_state(u);
+  }
+  for (int s = 0; s < S; ++s) {
+    stats[s].pc_setups = setups;
+    stats[s].t_residual_ms = t_res;
+    stats[s].t_jacobian_ms = t_jac;
+    stats[s].t_setup_ms = t_set;
+    stats[s].t_gmres_ms = t_gm;
+  }
+  if (pc && pc->timing) {
+    for (int s = 0; s < S; ++s) {
+      stats[s].t_ras_kernel_ms = pc->ras_ms;
+      stats[s].n_ras_launches = pc->ras_count;
+      stats[s].ras_bytes_per_launch = pc->ras_bytes();
+    }
+    pc->ras_ms = 0.0;
+    pc->ras_count = 0;
   }
 }
-
 
 extern "C" {
 
@@ -520,9 +702,7 @@ seird_status seird_problem_create(int64_t n_nodes, const double *xy, int64_t n_t
     P->md.inc_K = dev_upload(m.inc_K);
     P->N = 5 * m.n;
     P->nb = reduction_blocks(P->N);
-    P->partials = dev_alloc<double>((size_t)P->nb * (KRYLOV_MAX + 2));
-    P->hdev = dev_alloc<double>(KRYLOV_MAX + 8);
-    P->ydev = dev_alloc<double>(KRYLOV_MAX + 8);
+    P->setup_segments({0, m.n});
     P->flags = dev_alloc<int>(4);
     P->u_prev = dev_alloc<double>(P->N);
     P->F = dev_alloc<double>(P->N);
@@ -815,9 +995,10 @@ seird_status seird_gmres(seird_problem p, seird_precond pc, const double *vals, 
                          const seird_krylov_opts *opts, seird_krylov_stats *stats, int transpose, void *stream) {
   API_BEGIN
   if (!p || !vals || !b || !x || !opts) fail(SEIRD_ERR_ARG, "null argument");
-  seird_krylov_stats s{};
-  int rc = gmres_impl(p, pc, vals, b, x, *opts, s, transpose, (hipStream_t)stream);
-  if (stats) *stats = s;
+  std::vector<seird_krylov_stats> all;
+  gmres_impl(p, pc, vals, b, x, *opts, all, std::vector<uint8_t>(p->seg.S, 1), transpose, (hipStream_t)stream);
+  const int rc = all[0].reason < 0 ? all[0].reason : SEIRD_OK;
+  if (stats) *stats = all[0];
   if (rc != SEIRD_OK) {
     g_last_error = rc == SEIRD_ERR_DIVERGED ? "GMRES diverged" : "GMRES reached max_it";
     return rc;
@@ -831,7 +1012,9 @@ seird_status seird_step(seird_problem p, seird_precond pc, double *u, double dt,
   seird_step_stats s{};
   int code = SEIRD_OK;
   try {
-    step_impl(p, pc, u, dt, src, nopts, kopts, s, (hipStream_t)stream);
+    std::vector<seird_step_stats> all;
+    step_impl(p, pc, u, dt, src, nopts, kopts, all, (hipStream_t)stream);
+    if (!all.empty()) s = all[0];
   } catch (const Error &e) {
     code = e.code;
     g_last_error = e.msg;
@@ -883,7 +1066,7 @@ seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, 
   HIPCHECK(hipMemcpyAsync(T.ckpt[0], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
   if (last0 == 0) HIPCHECK(hipMemcpyAsync(T.seg[0], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
   for (int k = 1; k <= n_steps; ++k) {
-    seird_step_stats s{};
+    std::vector<seird_step_stats> s;
     step_impl(p, pc, u, dt, nullptr, nopts, kopts, s, st);
     launch_region_counts(T.reg_ptr, T.reg_nodes, p->md.mass, u, counts + (int64_t)(k - 1) * n_regions, n_regions, st);
     if (k % ckpt_every == 0 && k / ckpt_every < n_seg)
@@ -924,7 +1107,7 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
       HIPCHECK(hipMemcpyAsync(T.seg[0], T.ckpt[s], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
       for (int k = n0 + 1; k <= n1; ++k) {
         HIPCHECK(hipMemcpyAsync(T.seg[k - n0], T.seg[k - n0 - 1], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-        seird_step_stats ss{};
+        std::vector<seird_step_stats> ss;
         step_impl(p, pc, T.seg[k - n0], T.dt, nullptr, &T.nopts, &T.kopts, ss, st);
         as.recomputed_steps++;
       }
@@ -934,10 +1117,12 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
       launch_jacobian(p->md, p->P, p->gfield, uk, T.dt, diag, off, st);
       if (pc) precond_setup_impl(pc, p->vals, st);
       launch_adjoint_rhs(p->md.mass, T.region, grad_counts + (int64_t)(k - 1) * T.n_regions, T.lam_next, T.rhs, n, st);
-      seird_krylov_stats ks{};
-      int rc = gmres_impl(p, pc, p->vals, T.rhs, T.lam, *kopts, ks, 1, st);
-      as.gmres_its_total += ks.its;
-      if (rc != SEIRD_OK) fail(rc, "transposed GMRES failed in the adjoint sweep");
+      std::vector<seird_krylov_stats> ks;
+      gmres_impl(p, pc, p->vals, T.rhs, T.lam, *kopts, ks, std::vector<uint8_t>(p->seg.S, 1), 1, st);
+      for (const auto &e : ks) {
+        as.gmres_its_total += e.its;
+        if (e.reason < 0) fail(e.reason, "transposed GMRES failed in the adjoint sweep");
+      }
       const int nb = launch_adjoint_grad(p->md, p->P, uk, T.lam, T.dt, grad_g, T.partials, st);
       part.resize(5 * (size_t)nb);
       HIPCHECK(hipMemcpyAsync(part.data(), T.partials, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
@@ -954,6 +1139,103 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
   for (int c = 0; c < 5; ++c) grad_nu[c] = gnu[c];
   as.t_reverse_ms = std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
   if (stats) *stats = as;
+  API_END
+}
+
+struct seird_batch_s {
+  seird_problem prob = nullptr;
+  seird_precond pc = nullptr;
+  std::vector<int64_t> node_off;
+  ~seird_batch_s() {
+    delete pc;
+    delete prob;
+  }
+};
+
+seird_status seird_batch_create(int32_t n_inst, const int64_t *n_nodes, const double *const *xy, const int64_t *n_tri,
+                                const int32_t *const *tri, const seird_params *params, const int32_t *const *part,
+                                const int32_t *n_sub, int32_t overlap, int32_t tile, int32_t factor_prec,
+                                seird_batch *out) {
+  API_BEGIN
+  if (n_inst <= 0 || !n_nodes || !xy || !n_tri || !tri || !params || !part || !n_sub || !out)
+    fail(SEIRD_ERR_ARG, "null argument");
+  *out = nullptr;
+  auto B = new seird_batch_s();
+  try {
+    // concatenate the instances
+    B->node_off.assign(n_inst + 1, 0);
+    int64_t nt_total = 0;
+    for (int k = 0; k < n_inst; ++k) {
+      if (n_nodes[k] <= 0 || n_tri[k] <= 0) fail(SEIRD_ERR_ARG, "empty instance");
+      B->node_off[k + 1] = B->node_off[k] + n_nodes[k];
+      nt_total += n_tri[k];
+    }
+    const int64_t n = B->node_off[n_inst];
+    std::vector<double> XY(2 * n);
+    std::vector<int32_t> TRI(3 * nt_total), PART(n), INST(n);
+    std::vector<ParamsDev> PI(n_inst);
+    int64_t to = 0;
+    int32_t so = 0;
+    for (int k = 0; k < n_inst; ++k) {
+      const int64_t o = B->node_off[k];
+      std::copy(xy[k], xy[k] + 2 * n_nodes[k], XY.begin() + 2 * o);
+      for (int64_t t = 0; t < 3 * n_tri[k]; ++t) {
+        const int32_t v = tri[k][t];
+        if (v < 0 || v >= n_nodes[k]) fail(SEIRD_ERR_MESH, "instance " + std::to_string(k) + ": vertex out of range");
+        TRI[3 * to + t] = (int32_t)(v + o);
+      }
+      to += n_tri[k];
+      for (int64_t j = 0; j < n_nodes[k]; ++j) {
+        if (part[k][j] < 0 || part[k][j] >= n_sub[k]) fail(SEIRD_ERR_ARG, "partition entry out of range");
+        PART[o + j] = part[k][j] + so;
+        INST[o + j] = k;
+      }
+      so += n_sub[k];
+      PI[k] = to_dev(params[k]);
+    }
+    seird_problem P = nullptr;
+    int rc = seird_problem_create(n, XY.data(), nt_total, TRI.data(), &params[0], &P);
+    if (rc != SEIRD_OK) fail(rc, g_last_error);
+    B->prob = P;
+    P->d_inst = dev_upload(INST);
+    P->d_Pinst = dev_upload(PI);
+    P->md.inst = P->d_inst;
+    P->md.Pinst = P->d_Pinst;
+    P->setup_segments(B->node_off);
+    seird_schwarz_opts o{};
+    o.n_sub = so;
+    o.overlap = overlap;
+    o.tile = tile;
+    o.factor_prec = factor_prec;
+    o.n_ref = 0;
+    seird_precond pc = nullptr;
+    rc = seird_precond_create(P, &o, PART.data(), &pc);
+    if (rc != SEIRD_OK) fail(rc, g_last_error);
+    B->pc = pc;
+  } catch (...) {
+    delete B;
+    throw;
+  }
+  *out = B;
+  API_END
+}
+
+void seird_batch_destroy(seird_batch b) { delete b; }
+
+seird_status seird_batch_info(seird_batch b, int64_t *node_offsets) {
+  API_BEGIN
+  if (!b || !node_offsets) fail(SEIRD_ERR_ARG, "null argument");
+  std::copy(b->node_off.begin(), b->node_off.end(), node_offsets);
+  API_END
+}
+
+seird_status seird_batch_step(seird_batch b, double *u, double dt, const seird_newton_opts *nopts,
+                              const seird_krylov_opts *kopts, seird_step_stats *per_instance, void *stream) {
+  API_BEGIN
+  if (!b || !u) fail(SEIRD_ERR_ARG, "null argument");
+  std::vector<seird_step_stats> all;
+  step_impl(b->prob, b->pc, u, dt, nullptr, nopts, kopts, all, (hipStream_t)stream);
+  if (per_instance) std::copy(all.begin(), all.end(), per_instance);
   API_END
 }
 

@@ -71,6 +71,10 @@ struct MeshDev {
   int64_t *inc_ptr = nullptr;
   int32_t *inc_j = nullptr, *inc_l = nullptr, *inc_sj = nullptr, *inc_sl = nullptr;
   double *inc_K = nullptr;
+  // batches: instance of every node and the parameters of every instance
+  // (both null for a single problem)
+  const int32_t *inst = nullptr;
+  const struct ParamsDev *Pinst = nullptr;
 };
 
 struct ParamsDev {

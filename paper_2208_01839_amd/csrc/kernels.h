@@ -6,6 +6,20 @@
 namespace seird {
 
 constexpr int KRYLOV_MAX = 32;  // max basis vectors handled by one Arnoldi kernel
+constexpr int SEG_CH = 1024;    // entries per block of a segmented reduction
+
+struct SegView;
+// Segments of a vector (instances of a batch; one segment for a single
+// problem) and their reduction blocks, on host and device.
+struct SegHost {
+  int S = 0, B = 0;
+  std::vector<int64_t> seg_start, blk_start;
+  std::vector<int32_t> block_seg;
+  int64_t *d_seg_start = nullptr, *d_blk_start = nullptr;
+  int32_t *d_block_seg = nullptr;
+  uint8_t *d_active = nullptr;  // nullable: all active
+  SegView view() const;
+};
 
 struct FactorLaunch {
   int tile = 32;
@@ -90,5 +104,16 @@ int launch_adjoint_grad(const MeshDev &m, const ParamsDev &P, const double *u, c
 // one large band system (coarse, FP64, tile 32, bl, bu <= 16), non-transposed
 void launch_coarse_solve(const double *F, const SubInfo *sp, const double *r, double *z, double *ybuf,
                          hipStream_t st);
+
+void launch_seg_mdot(const SegHost &g, const double *V, int64_t ldv, int nv, const double *w, int with_self,
+                     double *partials, hipStream_t st);
+void launch_seg_reduce(const SegHost &g, const double *partials, int nrows, double *out, int ldo, int row_off,
+                       hipStream_t st);
+void launch_seg_maxpy_norm(const SegHost &g, double *w, const double *V, int64_t ldv, const double *h, int ldh, int nv,
+                           double *partials, hipStream_t st);
+void launch_seg_gemv_update(const SegHost &g, double *x, const double *Z, int64_t ldz, const double *y, int ldy, int nv,
+                            hipStream_t st);
+void launch_seg_axpby(const SegHost &g, double *y, const double *x, const double *a, double b, hipStream_t st);
+void launch_seg_norm2(const SegHost &g, const double *x, const double *scale, double *partials, hipStream_t st);
 
 }  // namespace seird

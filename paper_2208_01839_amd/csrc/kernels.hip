@@ -70,11 +70,12 @@ __device__ inline void load5(const double *p, double v[5]) {
 // ----------------------------------------------------------------------
 // residual: one thread per node
 // ----------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_residual(MeshDev m, ParamsDev P, const double *__restrict__ gfield,
+__global__ __launch_bounds__(256) void k_residual(MeshDev m, ParamsDev P0, const double *__restrict__ gfield,
                                                   const double *__restrict__ u, const double *__restrict__ up,
                                                   double dt, const double *__restrict__ src, double *__restrict__ F) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m.n) return;
+  const ParamsDev P = m.inst ? m.Pinst[m.inst[i]] : P0;
   double ui[5];
   load5(u + 5 * i, ui);
   const double Ni = ui[0] + ui[1] + ui[2] + ui[3] + ui[4];
@@ -108,11 +109,12 @@ __global__ __launch_bounds__(256) void k_residual(MeshDev m, ParamsDev P, const 
 //                    + dt nu_c (1/3) sum_T sum_k K_ik u_c,k
 //   off[s] = (a[5], b[5]): a_c = dt nu_c sum_T Nbar K_ij ; b_c = dt nu_c (1/3) sum_T sum_k K_ik u_c,k
 // ----------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P, const double *__restrict__ gfield,
+__global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const double *__restrict__ gfield,
                                                   const double *__restrict__ u, double dt, double *__restrict__ diag,
                                                   double *__restrict__ off) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m.n) return;
+  const ParamsDev P = m.inst ? m.Pinst[m.inst[i]] : P0;
   for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s)
 #pragma unroll
     for (int q = 0; q < 10; ++q) off[10 * s + q] = 0.0;
@@ -255,10 +257,12 @@ __global__ __launch_bounds__(256) void k_mdot(const double *__restrict__ V, int6
     acc[NVMAX] += wv * wv;
   }
   const int nb = gridDim.x;
+#pragma unroll
   for (int k = 0; k < NVMAX; ++k) {
-    if (k >= nv) break;
-    double r = block_sum(acc[k], lds4);
-    if (threadIdx.x == 0) partials[(int64_t)k * nb + blockIdx.x] = r;
+    if (k < nv) {  // uniform over the block
+      double r = block_sum(acc[k], lds4);
+      if (threadIdx.x == 0) partials[(int64_t)k * nb + blockIdx.x] = r;
+    }
   }
   if (with_self) {
     double r = block_sum(acc[NVMAX], lds4);
@@ -353,6 +357,153 @@ __global__ __launch_bounds__(256) void k_check_state(const double *__restrict__ 
   for (int c = 0; c < 5; ++c) bad_nf |= !isfinite(v[c]);
   if (bad_nf) atomicOr(flags, 1);
   else if (!(N > 0.0)) atomicOr(flags, 2);
+}
+
+// ----------------------------------------------------------------------
+// Segmented reductions.  A vector of N entries is split into segments (one
+// per problem instance; a single problem is one segment).  Every segment is
+// cut into chunks of SEG_CH entries, one block per chunk; block b sums its
+// chunk (thread t: entries t, t+256, ...) and writes a partial; the partials
+// of a segment are then summed by one block in a fixed order.  The result
+// for a segment therefore does not depend on the other segments.
+// ----------------------------------------------------------------------
+struct SegView {
+  const int64_t *seg_start;   // [S+1] entry offsets
+  const int64_t *blk_start;   // [S+1] block offsets
+  const int32_t *block_seg;   // [B] segment of each block
+  const uint8_t *active;      // [S] (nullable: all active)
+  int S, B;
+};
+
+SegView SegHost::view() const { return SegView{d_seg_start, d_blk_start, d_block_seg, d_active, S, B}; }
+
+__device__ inline void seg_range(const SegView &v, int b, int &sg, int64_t &lo, int64_t &hi) {
+  sg = v.block_seg[b];
+  lo = v.seg_start[sg] + (int64_t)(b - v.blk_start[sg]) * SEG_CH;
+  hi = min(lo + (int64_t)SEG_CH, v.seg_start[sg + 1]);
+}
+
+// partials[k * B + b] = chunk sum of V_k . w (k < nv); with_self: row nv = w . w
+template <int NVMAX>
+__global__ __launch_bounds__(256) void k_seg_mdot(SegView v, const double *__restrict__ V, int64_t ldv, int nv,
+                                                  const double *__restrict__ w, int with_self,
+                                                  double *__restrict__ partials) {
+  __shared__ double lds4[4];
+  int sg;
+  int64_t lo, hi;
+  seg_range(v, blockIdx.x, sg, lo, hi);
+  double acc[NVMAX + 1];
+#pragma unroll
+  for (int k = 0; k <= NVMAX; ++k) acc[k] = 0.0;
+  if (!v.active || v.active[sg]) {
+    for (int64_t idx = lo + threadIdx.x; idx < hi; idx += 256) {
+      const double wv = w[idx];
+#pragma unroll
+      for (int k = 0; k < NVMAX; ++k)
+        if (k < nv) acc[k] += V[k * ldv + idx] * wv;
+      acc[NVMAX] += wv * wv;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NVMAX; ++k) {
+    if (k < nv) {
+      const double r = block_sum(acc[k], lds4);
+      if (threadIdx.x == 0) partials[(int64_t)k * v.B + blockIdx.x] = r;
+    }
+  }
+  if (with_self) {
+    const double r = block_sum(acc[NVMAX], lds4);
+    if (threadIdx.x == 0) partials[(int64_t)nv * v.B + blockIdx.x] = r;
+  }
+}
+
+// out[sg * ldo + k] = sum of the partials of segment sg, row k (one block per (sg, k))
+__global__ __launch_bounds__(256) void k_seg_reduce(SegView v, const double *__restrict__ partials, int nrows,
+                                                    double *__restrict__ out, int ldo, int row_off) {
+  __shared__ double lds4[4];
+  const int sg = blockIdx.x / nrows, k = blockIdx.x % nrows;
+  double a = 0.0;
+  const int64_t b0 = v.blk_start[sg], b1 = v.blk_start[sg + 1];
+  for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) a += partials[(int64_t)k * v.B + b];
+  const double r = block_sum(a, lds4);
+  if (threadIdx.x == 0) out[(int64_t)sg * ldo + row_off + k] = r;
+}
+
+// w -= sum_k h[sg][k] V_k on active segments; partial ||w||^2
+template <int NVMAX>
+__global__ __launch_bounds__(256) void k_seg_maxpy_norm(SegView v, double *__restrict__ w, const double *__restrict__ V,
+                                                        int64_t ldv, const double *__restrict__ h, int ldh, int nv,
+                                                        double *__restrict__ partials) {
+  __shared__ double lds4[4];
+  __shared__ double hs[NVMAX];
+  int sg;
+  int64_t lo, hi;
+  seg_range(v, blockIdx.x, sg, lo, hi);
+  const bool act = !v.active || v.active[sg];
+  if (threadIdx.x < NVMAX) hs[threadIdx.x] = (act && threadIdx.x < nv) ? h[(int64_t)sg * ldh + threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc = 0.0;
+  if (act) {
+    for (int64_t idx = lo + threadIdx.x; idx < hi; idx += 256) {
+      double x = w[idx];
+#pragma unroll
+      for (int k = 0; k < NVMAX; ++k)
+        if (k < nv) x -= hs[k] * V[k * ldv + idx];
+      w[idx] = x;
+      acc += x * x;
+    }
+  }
+  const double r = block_sum(acc, lds4);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// x += sum_k y[sg][k] Z_k on active segments
+template <int NVMAX>
+__global__ __launch_bounds__(256) void k_seg_gemv_update(SegView v, double *__restrict__ x, const double *__restrict__ Z,
+                                                         int64_t ldz, const double *__restrict__ y, int ldy, int nv) {
+  __shared__ double ys[NVMAX];
+  int sg;
+  int64_t lo, hi;
+  seg_range(v, blockIdx.x, sg, lo, hi);
+  const bool act = !v.active || v.active[sg];
+  if (threadIdx.x < NVMAX) ys[threadIdx.x] = (act && threadIdx.x < nv) ? y[(int64_t)sg * ldy + threadIdx.x] : 0.0;
+  __syncthreads();
+  if (!act) return;
+  for (int64_t idx = lo + threadIdx.x; idx < hi; idx += 256) {
+    double t = x[idx];
+#pragma unroll
+    for (int k = 0; k < NVMAX; ++k)
+      if (k < nv) t += ys[k] * Z[k * ldz + idx];
+    x[idx] = t;
+  }
+}
+
+// y = a[sg] * x + b * y on active segments (a per segment, from device memory)
+__global__ __launch_bounds__(256) void k_seg_axpby(SegView v, double *__restrict__ y, const double *__restrict__ x,
+                                                   const double *__restrict__ a, double b) {
+  int sg;
+  int64_t lo, hi;
+  seg_range(v, blockIdx.x, sg, lo, hi);
+  if (v.active && !v.active[sg]) return;
+  const double aa = a[sg];
+  for (int64_t idx = lo + threadIdx.x; idx < hi; idx += 256) y[idx] = aa * x[idx] + (b != 0.0 ? b * y[idx] : 0.0);
+}
+
+// partial sum of (scale[idx/5] x[idx])^2 per block (scale nullable)
+__global__ __launch_bounds__(256) void k_seg_norm2(SegView v, const double *__restrict__ x,
+                                                   const double *__restrict__ scale, double *__restrict__ partials) {
+  __shared__ double lds4[4];
+  int sg;
+  int64_t lo, hi;
+  seg_range(v, blockIdx.x, sg, lo, hi);
+  double acc = 0.0;
+  for (int64_t idx = lo + threadIdx.x; idx < hi; idx += 256) {
+    double t = x[idx];
+    if (scale) t *= scale[idx / 5];
+    acc += t * t;
+  }
+  const double r = block_sum(acc, lds4);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
 }
 
 // ----------------------------------------------------------------------
@@ -1300,13 +1451,14 @@ __global__ __launch_bounds__(256) void k_adjoint_rhs(const double *__restrict__ 
 
 // gradient contributions of one step; nu partial sums per block in
 // partials[c * nb + block]
-__global__ __launch_bounds__(256) void k_adjoint_grad(MeshDev m, ParamsDev P, const double *__restrict__ u,
+__global__ __launch_bounds__(256) void k_adjoint_grad(MeshDev m, ParamsDev P0, const double *__restrict__ u,
                                                       const double *__restrict__ lam, double dt,
                                                       double *__restrict__ grad_g, double *__restrict__ partials) {
   __shared__ double lds4[4];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double pc[5] = {0, 0, 0, 0, 0};
   if (i < m.n) {
+    const ParamsDev P = m.inst ? m.Pinst[m.inst[i]] : P0;
     double ui[5];
     load5(u + 5 * i, ui);
     const double Ni = ui[0] + ui[1] + ui[2] + ui[3] + ui[4];
@@ -1356,6 +1508,31 @@ int launch_adjoint_grad(const MeshDev &m, const ParamsDev &P, const double *u, c
 
 // ----------------------------------------------------------------------
 // launchers
+
+void launch_seg_mdot(const SegHost &g, const double *V, int64_t ldv, int nv, const double *w, int with_self,
+                     double *partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_mdot<KRYLOV_MAX>, dim3(g.B), dim3(256), 0, st, g.view(), V, ldv, nv, w, with_self,
+                     partials);
+}
+void launch_seg_reduce(const SegHost &g, const double *partials, int nrows, double *out, int ldo, int row_off,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_reduce, dim3(g.S * nrows), dim3(256), 0, st, g.view(), partials, nrows, out, ldo, row_off);
+}
+void launch_seg_maxpy_norm(const SegHost &g, double *w, const double *V, int64_t ldv, const double *h, int ldh, int nv,
+                           double *partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_maxpy_norm<KRYLOV_MAX>, dim3(g.B), dim3(256), 0, st, g.view(), w, V, ldv, h, ldh, nv,
+                     partials);
+}
+void launch_seg_gemv_update(const SegHost &g, double *x, const double *Z, int64_t ldz, const double *y, int ldy, int nv,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_gemv_update<KRYLOV_MAX>, dim3(g.B), dim3(256), 0, st, g.view(), x, Z, ldz, y, ldy, nv);
+}
+void launch_seg_axpby(const SegHost &g, double *y, const double *x, const double *a, double b, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_axpby, dim3(g.B), dim3(256), 0, st, g.view(), y, x, a, b);
+}
+void launch_seg_norm2(const SegHost &g, const double *x, const double *scale, double *partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_norm2, dim3(g.B), dim3(256), 0, st, g.view(), x, scale, partials);
+}
 // ----------------------------------------------------------------------
 static inline unsigned nblocks(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
