@@ -9,11 +9,13 @@ coarser, Galerkin coarse matrix) and GMRES(30) to rtol 1e-5, until the
 scaled residual is below 1e-10.  Inputs are resident in HBM before timing.
 
 Prints ONE JSON line (rank 0).  --prec selects the storage precision of the
-subdomain factors (0 FP64, 1 FP32, 2 BF16); --compare-prec runs the FP64
-path and then the FP32/BF16 paths on the same steps and reports them in
-"mixed".  The CPU baseline is the FP64 oracle (numpy/scipy) timed on a
-bounded sample of the same workload (a nested mesh of the same kind with
-32x fewer nodes, same subdomain size), scaled to 5M unknowns by the unknown ratio.
+subdomain factors of the main leg (0 FP64, 1 FP32, 2 BF16); unless
+--no-compare-prec, FP32 and BF16 legs on the same steps follow and are
+reported in "mixed".  The ensemble leg ("batch") steps 48 uneven instances
+together; the adjoint leg ("adjoint") times one misfit gradient.  The CPU
+baseline is the FP64 oracle (numpy/scipy) timed on a bounded sample of the
+same workload (a nested mesh of the same kind with 32x fewer nodes, same
+subdomain size), scaled to 5M unknowns by the unknown ratio.
 """
 import argparse
 import json
@@ -109,6 +111,83 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
             "grad_g_norm": float(grad_g.norm().item())}
 
 
+def batch_bench(sk, torch, args):
+    """Ensemble leg: independent realistic-type instances of uneven size
+    (log-uniform 50k-400k nodes, ~9.3M nodes in all) with their own
+    transmission and diffusion rates, stepped together as one block-diagonal
+    system (per-instance Newton and GMRES in lockstep, one-level RAS with
+    ~1000-node subdomains, overlap 2).  FP32 subdomain factors: FP64 ones
+    would take ~255 GB of the 288 GB."""
+    import numpy as np
+    import seird_inputs as si
+    t = time.perf_counter()
+    log(f"[bench] building the ensemble of {args.batch_instances} instances")
+    bc = si.config_batch(n_inst=args.batch_instances)
+    t_gen = time.perf_counter() - t
+    log(f"[bench] ensemble {bc.name}: {bc.n} nodes, "
+        f"{sum(c.n_sub for c in bc.instances)} subdomains ({t_gen:.1f} s)")
+    t = time.perf_counter()
+    b = sk.Batch([(c.xy, c.tri, c.params, c.part, c.n_sub) for c in bc.instances],
+                 overlap=bc.overlap, tile=args.tile, factor_prec=args.batch_prec)
+    t_create = time.perf_counter() - t
+    b.precond.enable_timing(True)
+    info = b.precond.info()
+    log(f"[bench] batch created ({t_create:.1f} s): {info}")
+    u = torch.tensor(np.concatenate([c.u0 for c in bc.instances]), device="cuda")
+    c0 = bc.instances[0]
+    kw = dict(tol=c0.newton_tol, max_it=c0.newton_max_it, restart=c0.gmres_restart,
+              rtol=c0.gmres_rtol, atol=c0.gmres_atol, dtol=c0.gmres_dtol, pc_reuse=args.pc_reuse)
+
+    def summary(per):
+        return (f"newton max {max(p['newton_its'] for p in per)} "
+                f"mean {np.mean([p['newton_its'] for p in per]):.2f}, gmres/instance max "
+                f"{max(sum(p['gmres_its']) for p in per)} mean "
+                f"{np.mean([sum(p['gmres_its']) for p in per]):.1f}, setups {per[0]['pc_setups']}")
+
+    for w in range(args.warmup):
+        per = b.step(u, bc.dt, **kw)
+        log(f"[bench] batch warmup step {w}: {summary(per)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    allper = []
+    for k in range(args.batch_steps):
+        per = b.step(u, bc.dt, **kw)
+        allper.append(per)
+        log(f"[bench] batch step {k}: {summary(per)} t(res/jac/setup/gmres)ms="
+            f"{per[0]['t_residual_ms']:.0f}/{per[0]['t_jacobian_ms']:.0f}/"
+            f"{per[0]['t_setup_ms']:.0f}/{per[0]['t_gmres_ms']:.0f}")
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ras_ms = sum(p[0]["t_ras_kernel_ms"] for p in allper)
+    ras_n = sum(p[0]["n_ras_launches"] for p in allper)
+    ras_bytes = allper[0][0]["ras_bytes_per_launch"] if allper else 0.0
+    roof = None
+    if ras_n > 0:
+        achieved = ras_bytes / (ras_ms / ras_n / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": "k_band_solve (subdomain solves of one RAS apply, FP32 factors)",
+                "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "avg_launch_ms": ras_ms / ras_n,
+                "launches": ras_n, "bytes_per_launch": ras_bytes}
+    sizes = [c.n for c in bc.instances]
+    return {"metric": "ensemble implicit steps/s (every instance advanced one step)",
+            "value": args.batch_steps / sec, "unit": "steps/s",
+            "instance_steps_per_s": len(sizes) * args.batch_steps / sec,
+            "unknowns": 5 * bc.n, "ms_per_step": 1e3 * sec / args.batch_steps,
+            "steps": args.batch_steps,
+            "workload": (f"{bc.name}: {len(sizes)} seeded realistic-type instances of "
+                         f"{min(sizes)}-{max(sizes)} nodes ({5 * bc.n} unknowns), beta and nu_c "
+                         f"x U(0.7,1.3) per instance, dt 1 day, Newton tol {c0.newton_tol}, "
+                         f"GMRES({c0.gmres_restart}) rtol {c0.gmres_rtol}, one-level RAS "
+                         f"{sum(c.n_sub for c in bc.instances)} subdomains overlap {bc.overlap}, "
+                         f"factor_prec {args.batch_prec}, pc_reuse {args.pc_reuse}"),
+            "newton_its_max": [max(p["newton_its"] for p in per) for per in allper],
+            "gmres_its_per_instance_max": [max(sum(p["gmres_its"]) for p in per) for per in allper],
+            "gmres_its_per_instance_mean": [float(np.mean([sum(p["gmres_its"]) for p in per]))
+                                            for per in allper],
+            "roofline": roof, "precond": info,
+            "generate_s": t_gen, "create_s": t_create}
+
+
 def cpu_baseline(args):
     """The oracle as it stands, timed on the host on a bounded sample."""
     import numpy as np
@@ -153,12 +232,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["realistic", "small"], default="realistic")
     ap.add_argument("--prec", type=int, default=0, choices=[0, 1, 2])
-    ap.add_argument("--compare-prec", action="store_true")
+    ap.add_argument("--no-compare-prec", dest="compare_prec", action="store_false",
+                    help="skip the FP32/BF16-factor legs")
     ap.add_argument("--tile", type=int, default=32)
     ap.add_argument("--n-base", type=int, default=3900)
     ap.add_argument("--n-ref", type=int, default=4)
     ap.add_argument("--n-sub", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=2,
+                    help="timed steps of the ensemble leg (0: skip)")
+    ap.add_argument("--batch-instances", type=int, default=48)
+    ap.add_argument("--batch-prec", type=int, default=1, choices=[0, 1, 2])
     ap.add_argument("--pc-reuse", type=int, default=100,
                     help="Newton iterations a preconditioner setup is reused for (0: fresh every time)")
     ap.add_argument("--adjoint-steps", type=int, default=10,
@@ -232,6 +316,11 @@ def main():
                                                / res["u"].abs().max()).item()),
             }
         out["mixed"] = mixed
+    if args.batch_steps > 0:
+        del res
+        torch.cuda.empty_cache()
+        out["batch"] = batch_bench(sk, torch, args)
+        torch.cuda.empty_cache()
     if args.adjoint_steps > 0 or args.adjoint_full:
         out["adjoint"] = adjoint_bench(sk, torch, args, cfg, coarse)
     if not args.no_cpu:

@@ -140,6 +140,10 @@ typedef struct {
   double t_ras_kernel_ms;
   int32_t n_ras_launches;
   double ras_bytes_per_launch;
+  /* halvings of Newton updates in this step: an update after which the
+   * total density N is <= 0 at some node is halved (at most 10 times per
+   * update, else SEIRD_ERR_STATE) */
+  int32_t backtracks;
 } seird_step_stats;
 
 const char *seird_last_error(void);
@@ -281,6 +285,10 @@ void seird_batch_destroy(seird_batch b);
 /* node_offsets [n_inst + 1] (host): instance k owns nodes
  * [node_offsets[k], node_offsets[k+1]) of the batch state. */
 seird_status seird_batch_info(seird_batch b, int64_t *node_offsets);
+/* The batch's preconditioner (one-level RAS over the subdomains of every
+ * instance), borrowed: owned by the batch and valid until
+ * seird_batch_destroy.  For seird_precond_timing / seird_precond_info. */
+seird_status seird_batch_precond(seird_batch b, seird_precond *out);
 /* One implicit step of every instance: u is the device float64 state
  * [total_nodes][5], instance after instance.  per_instance[n_inst]
  * (nullable) receives each instance's Newton/GMRES statistics.

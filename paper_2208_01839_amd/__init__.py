@@ -71,7 +71,7 @@ class _SStats(ctypes.Structure):
                 ("pc_setups", ctypes.c_int32), ("t_residual_ms", ctypes.c_double), ("t_jacobian_ms", ctypes.c_double),
                 ("t_setup_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
                 ("t_ras_kernel_ms", ctypes.c_double), ("n_ras_launches", ctypes.c_int32),
-                ("ras_bytes_per_launch", ctypes.c_double)]
+                ("ras_bytes_per_launch", ctypes.c_double), ("backtracks", ctypes.c_int32)]
 
 
 class _SInfo(ctypes.Structure):
@@ -125,6 +125,7 @@ _SIGS = {
                             ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
     "seird_batch_destroy": ([_P], None),
     "seird_batch_info": ([_P, _P], ctypes.c_int),
+    "seird_batch_precond": ([_P, _P], ctypes.c_int),
     "seird_batch_step": ([_P, _P, ctypes.c_double, ctypes.POINTER(_Newton), ctypes.POINTER(_Krylov),
                           _P, _P], ctypes.c_int),
 }
@@ -374,7 +375,7 @@ def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, pc_reuse=0
                  t_residual_ms=s.t_residual_ms, t_jacobian_ms=s.t_jacobian_ms,
                  t_setup_ms=s.t_setup_ms, t_gmres_ms=s.t_gmres_ms,
                  t_ras_kernel_ms=s.t_ras_kernel_ms, n_ras_launches=s.n_ras_launches,
-                 ras_bytes_per_launch=s.ras_bytes_per_launch)
+                 ras_bytes_per_launch=s.ras_bytes_per_launch, backtracks=s.backtracks)
     _check(code)
     return stats
 
@@ -465,6 +466,20 @@ class _LazyRun:
 SEIRDRun = _LazyRun()
 
 
+class _BorrowedPrecond:
+    """A preconditioner owned by another handle (timing and info only)."""
+
+    def __init__(self, h, owner):
+        self.h = h
+        self._owner = owner
+
+    def info(self):
+        return Precond.info(self)
+
+    def enable_timing(self, on=True):
+        Precond.enable_timing(self, on)
+
+
 class Batch:
     """Independent problems stepped together (one-level RAS).  instances: a
     list of (xy, tri, params, part, n_sub).  The batch state is the
@@ -497,6 +512,9 @@ class Batch:
         _check(lib().seird_batch_info(self.h, off.ctypes.data))
         self.node_offsets = off
         self.n = int(off[-1])
+        ph = ctypes.c_void_p()
+        _check(lib().seird_batch_precond(self.h, ctypes.byref(ph)))
+        self.precond = _BorrowedPrecond(ph, self)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -516,5 +534,9 @@ class Batch:
         for s in st:
             k = s.newton_its
             out.append(dict(newton_its=k, gmres_its=list(s.gmres_its[:k]),
-                            res_hist=list(s.res_hist[:k + 1]), pc_setups=s.pc_setups))
+                            res_hist=list(s.res_hist[:k + 1]), eps=s.eps, pc_setups=s.pc_setups,
+                            t_residual_ms=s.t_residual_ms, t_jacobian_ms=s.t_jacobian_ms,
+                            t_setup_ms=s.t_setup_ms, t_gmres_ms=s.t_gmres_ms,
+                            t_ras_kernel_ms=s.t_ras_kernel_ms, n_ras_launches=s.n_ras_launches,
+                            ras_bytes_per_launch=s.ras_bytes_per_launch, backtracks=s.backtracks))
         return out

@@ -108,6 +108,10 @@ struct seird_problem_s {
     dev_free(seg.d_seg_start); dev_free(seg.d_blk_start); dev_free(seg.d_block_seg);
     dev_free(d_mask); dev_free(d_mask2); dev_free(d_svec); dev_free(d_inst); dev_free(d_Pinst);
     tape.release();
+    if (stage) {
+      (void)hipStreamSynchronize(stage_st);
+      (void)hipHostFree(stage);
+    }
   }
 
   // segments from instance node offsets (node_start[S+1], node_start[S] = n)
@@ -130,7 +134,8 @@ struct seird_problem_s {
     g.d_blk_start = dev_upload(g.blk_start);
     g.d_block_seg = dev_upload(g.block_seg);
     seg = g;
-    dev_free(d_mask); dev_free(d_mask2); dev_free(d_svec);
+    dev_free(d_mask); dev_free(d_mask2); dev_free(d_svec); dev_free(flags);
+    flags = dev_alloc<int>(g.S);
     d_mask = dev_alloc<uint8_t>(g.S);
     d_mask2 = dev_alloc<uint8_t>(g.S);
     d_svec = dev_alloc<double>(g.S);
@@ -154,11 +159,34 @@ struct seird_problem_s {
     for (int s = 0; s < seg.S; ++s) out[s] = std::sqrt(h[(size_t)s * HLD]);
     return out;
   }
-  void upload_mask(uint8_t *d, const std::vector<uint8_t> &m, hipStream_t st) {
-    HIPCHECK(hipMemcpyAsync(d, m.data(), m.size(), hipMemcpyHostToDevice, st));
+  // Small host->device uploads (masks, scalars, GMRES coefficients) go
+  // through a pinned staging arena: each upload copies its bytes into a
+  // fresh slice, so the source may change as soon as the call returns, and
+  // a slice is reused only after a synchronisation of the stream(s) that
+  // read it (when the arena is full or the stream changes).
+  uint8_t *stage = nullptr;
+  size_t stage_cap = 0, stage_off = 0;
+  hipStream_t stage_st = nullptr;
+  void upload(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (stage_off > 0 && (st != stage_st || stage_off + need > stage_cap)) {
+      HIPCHECK(hipStreamSynchronize(stage_st));
+      stage_off = 0;
+    }
+    if (need > stage_cap) {
+      if (stage) HIPCHECK(hipHostFree(stage));
+      stage = nullptr;
+      stage_cap = std::max<size_t>(need, (size_t)1 << 20);
+      HIPCHECK(hipHostMalloc((void **)&stage, stage_cap, hipHostMallocDefault));
+    }
+    std::memcpy(stage + stage_off, src, bytes);
+    HIPCHECK(hipMemcpyAsync(dst, stage + stage_off, bytes, hipMemcpyHostToDevice, st));
+    stage_off += need;
+    stage_st = st;
   }
+  void upload_mask(uint8_t *d, const std::vector<uint8_t> &m, hipStream_t st) { upload(d, m.data(), m.size(), st); }
   void upload_scalars(const std::vector<double> &v, hipStream_t st) {
-    HIPCHECK(hipMemcpyAsync(d_svec, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, st));
+    upload(d_svec, v.data(), sizeof(double) * v.size(), st);
   }
   int64_t nvals() const { return 25 * mh.n + 10 * (int64_t)mh.col.size(); }
   const double *diag(const double *v) const { return v; }
@@ -394,7 +422,7 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
         y[i] = t / Hs(s, i, i);
       }
     }
-    HIPCHECK(hipMemcpyAsync(P->ydev, ybuf.data(), sizeof(double) * ybuf.size(), hipMemcpyHostToDevice, st));
+    P->upload(P->ydev, ybuf.data(), sizeof(double) * ybuf.size(), st);
     P->upload_mask(P->d_mask2, fin, st);
     launch_seg_gemv_update(P->seg_re, x, Zb, N, P->ydev, HLD, k, st);
   };
@@ -558,16 +586,23 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
   stats.assign(S, seird_step_stats{});
   const int64_t N = p->N;
   HIPCHECK(hipMemcpyAsync(p->u_prev, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-  auto check_state = [&](const double *x) {
-    HIPCHECK(hipMemsetAsync(p->flags, 0, sizeof(int), st));
-    launch_check_state(x, p->mh.n, p->flags, st);
-    int f = 0;
-    HIPCHECK(hipMemcpyAsync(&f, p->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  // per-instance state flags: bit 0 a nonfinite entry, bit 1 N <= 0 at a node
+  auto state_flags = [&](const double *x) {
+    HIPCHECK(hipMemsetAsync(p->flags, 0, sizeof(int) * S, st));
+    launch_check_state(x, p->mh.n, p->md.inst, p->flags, st);
+    std::vector<int> f(S, 0);
+    HIPCHECK(hipMemcpyAsync(f.data(), p->flags, sizeof(int) * S, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
-    if (f & 1) fail(SEIRD_ERR_NONFINITE, "nonfinite state");
-    if (f & 2) fail(SEIRD_ERR_STATE, "total density N <= 0 at a node");
+    return f;
   };
-  check_state(u);
+  auto where = [&](int s) { return S > 1 ? " in instance " + std::to_string(s) : std::string(); };
+  {
+    const std::vector<int> f = state_flags(u);
+    for (int s = 0; s < S; ++s) {
+      if (f[s] & 1) fail(SEIRD_ERR_NONFINITE, "nonfinite state" + where(s));
+      if (f[s] & 2) fail(SEIRD_ERR_STATE, "total density N <= 0 at a node" + where(s));
+    }
+  }
   const std::vector<double> scale = p->seg_norms(p->u_prev, st, p->md.mass);
   const std::vector<double> unorm = p->seg_norms(p->u_prev, st);
   double *diag = p->vals, *off = p->vals + 25 * p->mh.n;
@@ -610,7 +645,12 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
     t_set += ms(t0, clk::now());
     t0 = clk::now();
     launch_axpby(p->rhs, p->F, -1.0, nullptr, 0, 0.0, N, reduction_blocks(N), st);
-    gmres_impl(p, pc, p->vals, p->rhs, p->delta, *kopts, ks, act, 0, st);
+    // A reused setup gets an iteration budget of twice the last fresh count
+    // plus 5 (at least 10): beyond it the setup counts as failed and is
+    // rebuilt, instead of letting a stale preconditioner run to max_it.
+    seird_krylov_opts ko = *kopts;
+    if (pc && !fresh && its_fresh > 0) ko.max_it = std::min(kopts->max_it, std::max(10, 2 * its_fresh + 5));
+    gmres_impl(p, pc, p->vals, p->rhs, p->delta, ko, ks, act, 0, st);
     bool failed = false;
     for (int s = 0; s < S; ++s)
       if (act[s] && ks[s].reason < 0) failed = true;
@@ -646,10 +686,42 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
     // max_it without convergence: the inexact Newton update is still taken;
     // frozen segments have a zero update
     launch_axpby(u, p->delta, 1.0, nullptr, 0, 1.0, N, reduction_blocks(N), st);
+    // Positivity safeguard: an instance whose new iterate has N <= 0 at a
+    // node gets its update halved (u -= delta / 2, delta /= 2), at most
+    // MAX_HALVINGS times.  The root is unchanged; only the path to it.
+    constexpr int MAX_HALVINGS = 10;
+    for (int bt = 0;; ++bt) {
+      const std::vector<int> f = state_flags(u);
+      std::vector<uint8_t> bad(S, 0);
+      bool any_bad = false;
+      for (int s = 0; s < S; ++s) {
+        auto diag_msg = [&]() {
+          std::string h;
+          for (int i = 0; i <= k; ++i) h += (i ? ", " : "") + std::to_string(stats[s].res_hist[i]);
+          return where(s) + " after Newton iteration " + std::to_string(k + 1) + " (GMRES its " +
+                 std::to_string(ks[s].its) + ", reason " + std::to_string(ks[s].reason) + "; scaled residuals " +
+                 h + ")";
+        };
+        if (f[s] & 1) fail(SEIRD_ERR_NONFINITE, "nonfinite state" + diag_msg());
+        if (f[s] & 2) {
+          if (bt == MAX_HALVINGS)
+            fail(SEIRD_ERR_STATE, "total density N <= 0 at a node" + diag_msg() + " after " +
+                                      std::to_string(MAX_HALVINGS) + " halvings");
+          bad[s] = 1;
+          any_bad = true;
+          ++stats[s].backtracks;
+        }
+      }
+      if (!any_bad) break;
+      p->upload_mask(p->d_mask2, bad, st);
+      p->upload_scalars(std::vector<double>(S, -0.5), st);
+      launch_seg_axpby(p->seg_re, u, p->delta, p->d_svec, 1.0, st);
+      p->upload_scalars(std::vector<double>(S, 0.5), st);
+      launch_seg_axpby(p->seg_re, p->delta, p->delta, p->d_svec, 0.0, st);
+    }
     const std::vector<double> dn = p->seg_norms(p->delta, st);
     for (int s = 0; s < S; ++s)
       if (act[s]) stats[s].eps = dn[s] / unorm[s];
-    check_state(u);
   }
   for (int s = 0; s < S; ++s) {
     stats[s].pc_setups = setups;
@@ -703,7 +775,6 @@ seird_status seird_problem_create(int64_t n_nodes, const double *xy, int64_t n_t
     P->N = 5 * m.n;
     P->nb = reduction_blocks(P->N);
     P->setup_segments({0, m.n});
-    P->flags = dev_alloc<int>(4);
     P->u_prev = dev_alloc<double>(P->N);
     P->F = dev_alloc<double>(P->N);
     P->rhs = dev_alloc<double>(P->N);
@@ -1226,6 +1297,13 @@ seird_status seird_batch_info(seird_batch b, int64_t *node_offsets) {
   API_BEGIN
   if (!b || !node_offsets) fail(SEIRD_ERR_ARG, "null argument");
   std::copy(b->node_off.begin(), b->node_off.end(), node_offsets);
+  API_END
+}
+
+seird_status seird_batch_precond(seird_batch b, seird_precond *out) {
+  API_BEGIN
+  if (!b || !out) fail(SEIRD_ERR_ARG, "null argument");
+  *out = b->pc;
   API_END
 }
 

@@ -80,7 +80,8 @@ void launch_gemv_update(double *x, const double *Z, int64_t ldz, const double *y
 void launch_axpby(double *y, const double *x, double a, const double *aptr, int ainv, double b, int64_t N, int nb,
                   hipStream_t st);
 void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st);
-void launch_check_state(const double *u, int64_t n, int *flags, hipStream_t st);
+// per-instance flags (inst nullable: one instance), flags[S] zeroed by the caller
+void launch_check_state(const double *u, int64_t n, const int32_t *inst, int *flags, hipStream_t st);
 // the coarse factorisation goes to st_coarse (may equal st), the subdomains to st
 void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st,
                           hipStream_t st_coarse);

@@ -346,9 +346,12 @@ __global__ __launch_bounds__(256) void k_norm2_partials(const double *__restrict
 }
 
 // state check: count of nodes with N <= 0 or any nonfinite entry
-__global__ __launch_bounds__(256) void k_check_state(const double *__restrict__ u, int64_t n, int *__restrict__ flags) {
+// flags[instance of node]: bit 0 nonfinite entry, bit 1 total density <= 0
+__global__ __launch_bounds__(256) void k_check_state(const double *__restrict__ u, int64_t n,
+                                                     const int32_t *__restrict__ inst, int *__restrict__ flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (inst) flags += inst[i];
   double v[5];
   load5(u + 5 * i, v);
   const double N = v[0] + v[1] + v[2] + v[3] + v[4];
@@ -1573,8 +1576,8 @@ void launch_axpby(double *y, const double *x, double a, const double *aptr, int 
 void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2_partials, dim3(nb), dim3(256), 0, st, x, scale, N, partials);
 }
-void launch_check_state(const double *u, int64_t n, int *flags, hipStream_t st) {
-  hipLaunchKernelGGL(k_check_state, dim3(nblocks(n)), dim3(256), 0, st, u, n, flags);
+void launch_check_state(const double *u, int64_t n, const int32_t *inst, int *flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_state, dim3(nblocks(n)), dim3(256), 0, st, u, n, inst, flags);
 }
 
 template <int T, class ET>

@@ -376,7 +376,7 @@ def gaussian_bump_state(xy: np.ndarray, seed: int, N0: float = 1.0,
 
 def urban_density_state(xy: np.ndarray, poly_seed: int, noise_seed: int,
                         peak_seed: int, n_peaks: int = 12, n_seeded: int = 5,
-                        clip: float = 3.0):
+                        clip: float = 3.0, a: float = 300.0, b: float = 200.0):
     """u0 [n,5] for the realistic configuration.
 
     Density N0 = exp(Z) + sum_k a_k exp(-|x-c_k|^2 / (2 rho_k^2)) with Z iid
@@ -385,7 +385,7 @@ def urban_density_state(xy: np.ndarray, poly_seed: int, noise_seed: int,
     1e-3 * N0 * sum_{k < n_seeded} exp(-|x-c_k|^2/(2 rho_k^2)) (the
     Gaussian-pulse initial state of Section 4.3, with the exponent's minus
     sign), s = N0 - i."""
-    poly = star_polygon(poly_seed)
+    poly = star_polygon(poly_seed, a=a, b=b)
     rng_z = np.random.default_rng(noise_seed)
     Z = np.clip(rng_z.standard_normal(len(xy)), -clip, clip)
     rng = np.random.default_rng(peak_seed)
@@ -537,6 +537,71 @@ def bump_field(xy: np.ndarray, seed: int, n_bumps: int = 8,
     for k in range(n_bumps):
         xi += sgn[k] * np.exp(-((xy - c[k]) ** 2).sum(1) / (2 * w[k] ** 2))
     return 1.0 + amp * np.tanh(xi)
+
+
+@dataclasses.dataclass
+class BatchConfig:
+    """An ensemble of independent instances stepped together."""
+    name: str
+    instances: list           # Config records (one-level, no coarse space)
+    dt: float
+    steps: int
+    overlap: int
+
+    @property
+    def n(self):
+        return sum(c.n for c in self.instances)
+
+
+def config_batch(n_inst: int = 48, n_min: float = 50_000, n_max: float = 400_000,
+                 seed: int = 4, param_seed: int = 5, nodes_per_sub: int = 1000,
+                 overlap: int = 2, n_ref: int = 2, steps: int = 30,
+                 ref_nodes: float = 1.0e6, beta_base: float = 0.006) -> BatchConfig:
+    """Ensemble case: ``n_inst`` realistic-type instances whose target node
+    counts are log-uniform in [n_min, n_max] (``seed``).
+
+    Instance k: star polygon seeded 100 + k with both semi-axes scaled by
+    sqrt(n_k / ref_nodes), so that its node density matches the realistic
+    case (about 1M nodes on the unscaled polygon); Delaunay base mesh of
+    n_k / 4^n_ref nodes red-refined n_ref times; density and urban peaks as
+    in the realistic case (seeds 100 + k, 101 + k, 102 + k), with the number
+    of peaks (12, 5 of them seeded with infection, on the unscaled polygon)
+    scaled by the area so that peaks per km^2 match it; Ontario rates
+    with the transmission rates (beta_I = beta_E = beta_base times one
+    U(0.7, 1.3) draw) and each diffusion coefficient nu_c scaled by its own
+    U(0.7, 1.3) draw (``param_seed``).  beta_base is below the realistic
+    case's 0.01 so that dt * beta * max N stays below 1 on every instance
+    (as it does in the realistic case): beyond 1 + dt (sigma + gamma_E) the
+    exposed equation's backward-Euler root turns negative.  RCB subdomains of about ``nodes_per_sub`` nodes,
+    overlap 2; dt 1 day."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_inst))
+    prng = np.random.default_rng(param_seed)
+    fb = prng.uniform(0.7, 1.3, n_inst)
+    fnu = prng.uniform(0.7, 1.3, (n_inst, NCOMP))
+    base = params_ontario()
+    out = []
+    for k in range(n_inst):
+        sc = math.sqrt(sizes[k] / ref_nodes)
+        a, b = 300.0 * sc, 200.0 * sc
+        nm = nested_polygon_mesh(100 + k, max(16, int(sizes[k] / 4 ** n_ref)), n_ref, a=a, b=b)
+        n_sub = max(1, int(round(len(nm.xy) / nodes_per_sub)))
+        order, part = rcb_order(nm.xy, n_sub)
+        nm.renumber_finest(order)
+        part = part[order]
+        xy, tri = nm.xy, nm.tri
+        n_peaks = max(1, int(round(12 * sc * sc)))
+        u0 = urban_density_state(xy, poly_seed=100 + k, noise_seed=101 + k,
+                                 peak_seed=102 + k, a=a, b=b, n_peaks=n_peaks,
+                                 n_seeded=max(1, int(round(n_peaks * 5 / 12))))
+        p = Params(**{**base.__dict__, "beta_I": beta_base * fb[k],
+                      "beta_E": beta_base * fb[k],
+                      "nu": tuple(np.array(base.nu) * fnu[k])})
+        out.append(Config(name=f"inst{k}_{len(xy)}", xy=xy, tri=tri, u0=u0, params=p,
+                          dt=1.0, steps=steps, part=part, n_sub=n_sub, overlap=overlap))
+    tot = sum(c.n for c in out)
+    return BatchConfig(name=f"ensemble{n_inst}x{tot}", instances=out, dt=1.0,
+                       steps=steps, overlap=overlap)
 
 
 def config_differentiation(n_base: int = 7800, n_ref: int = 4, n_sub: int = 2048,

@@ -68,3 +68,26 @@ def test_batch_matches_oracle():
         uo, _ = newton.newton_step(x[5], dt, geo, x[2], tol=1e-14)
         err = np.linalg.norm(ub[off[k]:off[k + 1]] - uo) / np.linalg.norm(uo)
         assert err < 1e-10, (k, err)
+
+
+def test_generated_ensemble_equals_solo_runs_and_solves_the_oracle_residual():
+    bc = si.config_batch(n_inst=5, n_min=3000, n_max=12000, nodes_per_sub=400, n_ref=1)
+    inst = bc.instances
+    b = sk.Batch([(c.xy, c.tri, c.params, c.part, c.n_sub) for c in inst],
+                 overlap=bc.overlap, factor_prec=1)
+    u = torch.tensor(np.concatenate([c.u0 for c in inst]), device="cuda")
+    per = b.step(u, bc.dt, tol=1e-10)
+    ub = u.cpu().numpy()
+    off = b.node_offsets
+    for k, c in enumerate(inst):
+        prob = sk.Problem(c.xy, c.tri, c.params)
+        pc = sk.Precond(prob, c.part, c.n_sub, c.overlap, factor_prec=1)
+        us = torch.tensor(c.u0, device="cuda")
+        st = sk.step(prob, pc, us, c.dt, tol=1e-10)
+        assert st["gmres_its"] == per[k]["gmres_its"], k
+        uk = ub[off[k]:off[k + 1]]
+        assert np.array_equal(us.cpu().numpy(), uk), k
+        geo = fem.Geometry(c.xy, c.tri)
+        Fo = fem.residual(uk, c.u0, c.dt, geo, c.params)
+        scale = np.linalg.norm(geo.mass[:, None] * c.u0)
+        assert np.linalg.norm(Fo) <= 1.01e-10 * scale, k

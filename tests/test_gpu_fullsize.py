@@ -100,3 +100,35 @@ def test_fullsize_step_solves_the_oracle_residual(big, prec):
     P0 = fem.total_population(cfg.u0, geo)
     assert abs(fem.total_population(ug, geo) - P0) <= 1e-9 * P0
     assert ug[:, 0].min() > 0 and ug.sum(1).min() > 0
+
+
+def test_fullsize_ensemble_step():
+    """The 48-instance ensemble (about 9.3M nodes, 46.7M unknowns) in the
+    benchmark's configuration (FP32 factors, lagged setup): on sampled
+    instances the oracle residual of the GPU state is below the tolerance;
+    on all instances population is conserved and densities stay positive."""
+    bc = si.config_batch()
+    inst = bc.instances
+    b = sk.Batch([(c.xy, c.tri, c.params, c.part, c.n_sub) for c in inst],
+                 overlap=bc.overlap, factor_prec=1)
+    u = torch.tensor(np.concatenate([c.u0 for c in inst]), device="cuda")
+    tol = inst[0].newton_tol
+    per = b.step(u, bc.dt, tol=tol, pc_reuse=100)
+    print("ensemble step: newton", [p["newton_its"] for p in per], "gmres",
+          [sum(p["gmres_its"]) for p in per], "halvings", [p["backtracks"] for p in per], flush=True)
+    ub = u.cpu().numpy()
+    off = b.node_offsets
+    sizes = [c.n for c in inst]
+    rng = np.random.default_rng(3)
+    sample = {int(np.argmin(sizes)), int(np.argmax(sizes)), int(rng.integers(len(inst)))}
+    for k, c in enumerate(inst):
+        uk = ub[off[k]:off[k + 1]]
+        geo = fem.Geometry(c.xy, c.tri)
+        P0 = fem.total_population(c.u0, geo)
+        assert abs(fem.total_population(uk, geo) - P0) <= 1e-9 * P0, k
+        assert uk[:, 0].min() > 0 and uk.sum(1).min() > 0, k
+        assert per[k]["res_hist"][-1] <= tol, k
+        if k in sample:
+            Fo = fem.residual(uk, c.u0, c.dt, geo, c.params)
+            scale = np.linalg.norm(geo.mass[:, None] * c.u0)
+            assert np.linalg.norm(Fo) <= 1.01 * tol * scale, (k, per[k])
