@@ -99,11 +99,17 @@ typedef struct {
 /* GMRES options (Section 3.3): right preconditioning, x0 = 0, restart
  * length, total iteration cap, convergence ||r|| < max(rtol ||b||, atol),
  * divergence ||r|| > dtol ||b||.  Classical Gram-Schmidt with one
- * conditional reorthogonalisation pass. */
+ * conditional reorthogonalisation pass.
+ * graphs = 1: the launches of every Arnoldi step (preconditioner apply,
+ * SpMV, projections) are captured once per basis index into a HIP graph,
+ * cached on the preconditioner, and replayed; results are identical to
+ * direct launches (graphs = 0).  Ignored while preconditioner timing is on
+ * or without a preconditioner. */
 typedef struct {
   int32_t restart;
   int32_t max_it;
   double rtol, atol, dtol;
+  int32_t graphs;
 } seird_krylov_opts;
 
 typedef struct {

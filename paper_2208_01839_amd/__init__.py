@@ -48,7 +48,7 @@ class _Schwarz(ctypes.Structure):
 class _Krylov(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_it", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
-                ("dtol", ctypes.c_double)]
+                ("dtol", ctypes.c_double), ("graphs", ctypes.c_int32)]
 
 
 class _KStats(ctypes.Structure):
@@ -186,8 +186,8 @@ def _params(p) -> _Params:
     return c
 
 
-def _krylov(restart=30, max_it=200, rtol=1e-5, atol=1e-50, dtol=1e5):
-    return _Krylov(int(restart), int(max_it), float(rtol), float(atol), float(dtol))
+def _krylov(restart=30, max_it=200, rtol=1e-5, atol=1e-50, dtol=1e5, graphs=0):
+    return _Krylov(int(restart), int(max_it), float(rtol), float(atol), float(dtol), int(bool(graphs)))
 
 
 class Problem:

@@ -4,6 +4,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 
 #include "kernels.h"
 
@@ -224,6 +226,7 @@ struct seird_precond_s {
   int64_t *g2l_ptr = nullptr;
   int32_t *g2l_idx = nullptr;
   double *yloc = nullptr;
+  int32_t *sub_seg = nullptr;  // instance of every subdomain (batches)
   int max_nt = 0, max_bu = 0;
   // coarse
   SubInfo *coarse_dev = nullptr;
@@ -243,6 +246,42 @@ struct seird_precond_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // optional HIP-event timing of the subdomain solve launches
   bool timing = false;
+  // captured Arnoldi-step graphs, keyed by what they bake in
+  struct GraphKey {
+    const void *prob, *V, *Zb, *vals;
+    int j, transpose, masked;
+    bool operator<(const GraphKey &o) const {
+      return std::tie(prob, V, Zb, vals, j, transpose, masked) <
+             std::tie(o.prob, o.V, o.Zb, o.vals, o.j, o.transpose, o.masked);
+    }
+  };
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  hipStream_t st_capture = nullptr;
+  // replay the graph of `key`, capturing `launches` (on a private stream)
+  // the first time
+  template <class Fn>
+  void run_graph(const GraphKey &key, Fn &&launches, hipStream_t st) {
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+      if (!st_capture) HIPCHECK(hipStreamCreateWithFlags(&st_capture, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      HIPCHECK(hipStreamBeginCapture(st_capture, hipStreamCaptureModeThreadLocal));
+      try {
+        launches(st_capture);
+      } catch (...) {
+        (void)hipStreamEndCapture(st_capture, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIPCHECK(hipStreamEndCapture(st_capture, &g));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHECK(e);
+      it = graphs.emplace(key, ex).first;
+    }
+    HIPCHECK(hipGraphLaunch(it->second, st));
+  }
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   size_t ev_used = 0;
   double ras_ms = 0.0;
@@ -267,6 +306,8 @@ struct seird_precond_s {
   }
 
   ~seird_precond_s() {
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (st_capture) (void)hipStreamDestroy(st_capture);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (st_coarse) (void)hipStreamDestroy(st_coarse);
@@ -275,7 +316,7 @@ struct seird_precond_s {
       (void)hipEventDestroy(e.second);
     }
     dev_free(Fs); dev_free(Fb); dev_free(Fc); dev_free(subs_dev); dev_free(order_dev); dev_free(ent_dev); dev_free(l2g);
-    dev_free(owned); dev_free(status); dev_free(g2l_ptr); dev_free(g2l_idx); dev_free(yloc);
+    dev_free(owned); dev_free(status); dev_free(g2l_ptr); dev_free(g2l_idx); dev_free(yloc); dev_free(sub_seg);
     dev_free(coarse_dev); dev_free(gp); dev_free(gq); dev_free(gref); dev_free(cperm); dev_free(gptr); dev_free(gw);
     dev_free(z_ptr); dev_free(zt_ptr); dev_free(z_col); dev_free(zt_col); dev_free(z_val); dev_free(zt_val);
     dev_free(rc); dev_free(xc); dev_free(cscratch); dev_free(ybuf); dev_free(t1);
@@ -288,8 +329,12 @@ struct seird_precond_s {
     return Fb;
   }
 
-  void ras(const double *r, double *z, int add, int transpose, hipStream_t st) {
+  void ras(const double *r, double *z, int add, int transpose, hipStream_t st, const uint8_t *seg_active = nullptr) {
     SolveLaunch sl;
+    if (seg_active && sub_seg) {
+      sl.sub_seg = sub_seg;
+      sl.seg_active = seg_active;
+    }
     sl.tile = ph.tile;
     sl.prec = ph.prec;
     sl.F = factors();
@@ -345,11 +390,14 @@ struct seird_precond_s {
     launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
   }
 
-  void apply(const double *vals, const double *r, double *z, int transpose, hipStream_t st) {
+  // seg_active (device, nullable): active flag per instance of a batch;
+  // the subdomain solves of inactive instances are skipped (one-level only)
+  void apply(const double *vals, const double *r, double *z, int transpose, hipStream_t st,
+             const uint8_t *seg_active = nullptr) {
     if (!ready) fail(SEIRD_ERR_ARG, "preconditioner used before setup");
     seird_problem P = prob;
     if (!ph.two_level) {
-      ras(r, z, 0, transpose, st);
+      ras(r, z, 0, transpose, st, seg_active);
       return;
     }
     // multiplicative two-grid: pre-smooth, coarse correction, post-smooth
@@ -435,16 +483,23 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
     int j = 0;
     for (; j < m && any(cyc); ++j) {
       double *vj = V + (int64_t)j * N, *zj = Zb + (int64_t)j * N, *w = V + (int64_t)(j + 1) * N;
-      if (pc)
-        pc->apply(vals, vj, zj, transpose, st);
-      else
-        HIPCHECK(hipMemcpyAsync(zj, vj, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-      launch_spmv(P->md, P->diag(vals), P->off(vals), zj, nullptr, w, transpose, st);
       P->upload_mask(P->d_mask, cyc, st);
-      launch_seg_mdot(P->seg_act, V, N, j + 1, w, 1, P->partials, st);
-      launch_seg_reduce(P->seg, P->partials, j + 2, P->hdev, HLD, 0, st);
-      launch_seg_maxpy_norm(P->seg_act, w, V, N, P->hdev, HLD, j + 1, P->partials, st);
-      launch_seg_reduce(P->seg, P->partials, 1, P->hdev, HLD, j + 2, st);
+      // z_j = M^{-1} v_j, w = A z_j, then h = V^T w, w -= V h, |w|^2
+      auto step_launches = [&](hipStream_t s) {
+        if (pc)
+          pc->apply(vals, vj, zj, transpose, s, S > 1 ? P->d_mask : nullptr);
+        else
+          HIPCHECK(hipMemcpyAsync(zj, vj, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        launch_spmv(P->md, P->diag(vals), P->off(vals), zj, nullptr, w, transpose, s);
+        launch_seg_mdot(P->seg_act, V, N, j + 1, w, 1, P->partials, s);
+        launch_seg_reduce(P->seg, P->partials, j + 2, P->hdev, HLD, 0, s);
+        launch_seg_maxpy_norm(P->seg_act, w, V, N, P->hdev, HLD, j + 1, P->partials, s);
+        launch_seg_reduce(P->seg, P->partials, 1, P->hdev, HLD, j + 2, s);
+      };
+      if (pc && o.graphs && !pc->timing)
+        pc->run_graph({P, V, Zb, vals, j, transpose, S > 1}, step_launches, st);
+      else
+        step_launches(st);
       HIPCHECK(hipMemcpyAsync(hbuf.data(), P->hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
       std::vector<uint8_t> re(S, 0);
@@ -1283,6 +1338,10 @@ seird_status seird_batch_create(int32_t n_inst, const int64_t *n_nodes, const do
     rc = seird_precond_create(P, &o, PART.data(), &pc);
     if (rc != SEIRD_OK) fail(rc, g_last_error);
     B->pc = pc;
+    std::vector<int32_t> sub_seg(so);
+    for (int k = 0, s0 = 0; k < n_inst; s0 += n_sub[k], ++k)
+      for (int j = 0; j < n_sub[k]; ++j) sub_seg[s0 + j] = k;
+    pc->sub_seg = dev_upload(sub_seg);
   } catch (...) {
     delete B;
     throw;

@@ -62,6 +62,10 @@ struct SolveLaunch {
   int transpose = 0;
   double *yloc = nullptr;
   double *ybuf = nullptr;  // forward-sweep results, sum of n_loc (or coarse n_loc) doubles
+  // optional: instance of every subdomain and the active flag of every
+  // instance; subdomains of inactive instances are skipped
+  const int32_t *sub_seg = nullptr;
+  const uint8_t *seg_active = nullptr;
 };
 
 void launch_residual(const MeshDev &m, const ParamsDev &P, const double *g, const double *u, const double *up,

@@ -1049,7 +1049,8 @@ template <int T, class FT, int NTHR, bool TRANS>
 __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(NTHR == 256 ? 4 : 1, 8)))
 void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, const int32_t *__restrict__ order,
                   const int32_t *__restrict__ l2g, const uint8_t *__restrict__ owned, const double *__restrict__ r,
-                  double *__restrict__ z, int add, double *__restrict__ yloc, double *__restrict__ ybuf) {
+                  double *__restrict__ z, int add, double *__restrict__ yloc, double *__restrict__ ybuf,
+                  const int32_t *__restrict__ sub_seg, const uint8_t *__restrict__ seg_active) {
   constexpr bool transpose = TRANS;
   constexpr int SOLVE_BMAX = solve_bmax<FT, NTHR>();
   constexpr int G = NTHR / T;   // lanes per row
@@ -1058,6 +1059,9 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
   __shared__ double acc_s[T];
   __shared__ double part_s[G][T];
   const int sidx = order ? order[blockIdx.x] : blockIdx.x;
+  // subdomains of inactive instances (converged in a batch) are skipped;
+  // their part of z is left as it was
+  if (seg_active && !seg_active[sub_seg[sidx]]) return;
   const SubInfo s = subs[sidx];
   const bool local = s.l2g_off >= 0;
   const int64_t yo = local ? s.l2g_off : 0;
@@ -1655,10 +1659,12 @@ static void solve_tt(const SolveLaunch &sl, hipStream_t st) {
   constexpr int WIDE = T * T >= 1024 ? 1024 : 256;
   if (sl.wide && WIDE == 1024)
     hipLaunchKernelGGL((k_band_solve<T, FT, WIDE, TR>), dim3(sl.nblocks), dim3(WIDE), 0, st, (const FT *)sl.F,
-                       sl.subs, sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf);
+                       sl.subs, sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf, sl.sub_seg,
+                       sl.seg_active);
   else
     hipLaunchKernelGGL((k_band_solve<T, FT, 256, TR>), dim3(sl.nblocks), dim3(256), 0, st, (const FT *)sl.F, sl.subs,
-                       sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf);
+                       sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf, sl.sub_seg,
+                       sl.seg_active);
 }
 template <int T, class FT>
 static void solve_t(const SolveLaunch &sl, hipStream_t st) {
