@@ -43,8 +43,20 @@ def build_workload(args):
 
 def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0):
     prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+    threads, tune = 256, None
+    if tile == "auto":
+        # launch shapes chosen by the autotuner on the first Jacobian (untimed)
+        vals = prob.jacobian(torch.tensor(cfg.u0, dtype=torch.float64, device="cuda"), cfg.dt)
+        tune = sk.autotune(prob, cfg.part, cfg.n_sub, cfg.overlap, vals, factor_prec=prec,
+                           coarse=coarse, applies_per_setup=15, reps=3)
+        del vals
+        tile, threads = tune["tile"], tune["solve_threads"]
+        log(f"[bench] prec={prec} autotune: tile {tile}, solve threads {threads}; "
+            + ", ".join(f"({c['tile']},{c['solve_threads']}): "
+                        + (f"setup {c['setup_ms']:.1f} apply {c['apply_ms']:.2f} ms" if c["status"] == 0
+                           else f"status {c['status']}") for c in tune["candidates"]))
     pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, tile=tile,
-                    factor_prec=prec, coarse=coarse)
+                    factor_prec=prec, coarse=coarse, solve_threads=threads)
     pc.enable_timing(True)
     info = pc.info()
     u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
@@ -64,7 +76,7 @@ def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0):
             f"{st['t_residual_ms']:.1f}/{st['t_jacobian_ms']:.1f}/{st['t_setup_ms']:.1f}/{st['t_gmres_ms']:.1f}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return dict(seconds=t1 - t0, stats=stats, info=info, u=u)
+    return dict(seconds=t1 - t0, stats=stats, info=info, u=u, tile=tile, solve_threads=threads, tune=tune)
 
 
 def adjoint_bench(sk, torch, args, cfg, coarse):
@@ -82,7 +94,9 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
         every = 10 if steps >= 20 else 5
     region = si.voronoi_regions(cfg.xy, 40, seed=8)
     prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
-    pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, tile=args.tile, coarse=coarse)
+    tile, threads = args.tuned.get(0, (32, 256))
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, tile=tile, coarse=coarse,
+                    solve_threads=threads)
     kw = dict(tol=cfg.newton_tol, pc_reuse=args.pc_reuse, rtol=cfg.gmres_rtol)
     # synthetic truth: the same run with the perturbed transmission field
     g_true = torch.tensor(si.bump_field(cfg.xy, seed=7), device="cuda")
@@ -128,8 +142,13 @@ def batch_bench(sk, torch, args):
         f"{sum(c.n_sub for c in bc.instances)} subdomains ({t_gen:.1f} s)")
     t = time.perf_counter()
     b = sk.Batch([(c.xy, c.tri, c.params, c.part, c.n_sub) for c in bc.instances],
-                 overlap=bc.overlap, tile=args.tile, factor_prec=args.batch_prec)
+                 overlap=bc.overlap, tile=32, factor_prec=args.batch_prec)
     t_create = time.perf_counter() - t
+    # the ensemble's factors are float32 in tile-32 storage (tile 16 would
+    # factor in float64 first); its solve width follows the autotuned choice
+    # of the realistic leg with the same factor precision, if that was tile 32
+    t_, threads = args.tuned.get(args.batch_prec, (32, 256))
+    b.precond.set_solve_threads(threads if t_ == 32 else 256)
     b.precond.enable_timing(True)
     info = b.precond.info()
     log(f"[bench] batch created ({t_create:.1f} s): {info}")
@@ -184,7 +203,7 @@ def batch_bench(sk, torch, args):
             "gmres_its_per_instance_max": [max(sum(p["gmres_its"]) for p in per) for per in allper],
             "gmres_its_per_instance_mean": [float(np.mean([sum(p["gmres_its"]) for p in per]))
                                             for per in allper],
-            "roofline": roof, "precond": info,
+            "roofline": roof, "precond": info, "solve_threads": threads if t_ == 32 else 256,
             "generate_s": t_gen, "create_s": t_create}
 
 
@@ -234,7 +253,8 @@ def main():
     ap.add_argument("--prec", type=int, default=0, choices=[0, 1, 2])
     ap.add_argument("--no-compare-prec", dest="compare_prec", action="store_false",
                     help="skip the FP32/BF16-factor legs")
-    ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--tile", default="auto", choices=["auto", "16", "32"],
+                    help="tile size of the subdomain band storage (auto: chosen by the autotuner)")
     ap.add_argument("--n-base", type=int, default=3900)
     ap.add_argument("--n-ref", type=int, default=4)
     ap.add_argument("--n-sub", type=int, default=1024)
@@ -250,6 +270,8 @@ def main():
     ap.add_argument("--adjoint-full", action="store_true",
                     help="measure the gradient on the ~2M-node, 60-step differentiation workload")
     args = ap.parse_args()
+    if args.tile != "auto":
+        args.tile = int(args.tile)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path "
               "is not part of this build", file=sys.stderr)
@@ -263,7 +285,9 @@ def main():
     args.full_nodes = cfg.n
     log(f"[bench] workload {cfg.name}: {cfg.n} nodes, {len(cfg.tri)} triangles, "
         f"{cfg.n_sub} subdomains, coarse {cfg.coarse_n} nodes ({time.perf_counter() - t:.1f} s)")
+    args.tuned = {}
     res = run_steps(sk, torch, cfg, coarse, args.prec, args.steps, args.warmup, args.tile, args.pc_reuse)
+    args.tuned[args.prec] = (res["tile"], res["solve_threads"])
     sec = res["seconds"]
     stats = res["stats"]
     value = args.steps / sec
@@ -295,25 +319,29 @@ def main():
                                 + (f"two-grid RAS {cfg.n_sub} subdomains overlap {cfg.overlap}, coarse "
                                    f"{cfg.coarse_n} nodes" if coarse else
                                    f"one-level RAS {cfg.n_sub} subdomains overlap {cfg.overlap}")),
-                   "unknowns": 5 * cfg.n, "tile": args.tile, "factor_prec": args.prec,
+                   "unknowns": 5 * cfg.n, "tile": res["tile"], "solve_threads": res["solve_threads"],
+                   "factor_prec": args.prec,
                    "pc_reuse": args.pc_reuse},
         "newton_its": [s["newton_its"] for s in stats],
         "pc_setups": [s["pc_setups"] for s in stats], "pc_reuse": args.pc_reuse,
         "gmres_its": [s["gmres_its"] for s in stats],
         "phase_ms_per_step": phase,
         "precond": res["info"],
+        "autotune": res["tune"],
         "roofline": roofline,
     }
     if args.compare_prec:
         mixed = {}
         for p in (1, 2):
             r2 = run_steps(sk, torch, cfg, coarse, p, args.steps, args.warmup, args.tile, args.pc_reuse)
+            args.tuned[p] = (r2["tile"], r2["solve_threads"])
             mixed[{1: "fp32", 2: "bf16"}[p]] = {
                 "steps_per_s": args.steps / r2["seconds"],
                 "speedup_vs_fp64": (args.steps / r2["seconds"]) / value,
                 "gmres_its": [s["gmres_its"] for s in r2["stats"]],
                 "max_rel_diff_vs_fp64": float(((r2["u"] - res["u"]).abs().max()
                                                / res["u"].abs().max()).item()),
+                "tile": r2["tile"], "solve_threads": r2["solve_threads"],
             }
         out["mixed"] = mixed
     if args.batch_steps > 0:

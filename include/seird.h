@@ -141,8 +141,10 @@ typedef struct {
   int32_t pc_setups; /* preconditioner setups done in this step */
   double t_residual_ms, t_jacobian_ms, t_setup_ms, t_gmres_ms;
   /* HIP-event time of the subdomain solve launches (the RAS apply kernel)
-   * during this step, their count, and the bytes one launch reads/writes
-   * by the algorithm (factor storage + local vectors). */
+   * during this step, their count, and the bytes a launch reads/writes by
+   * the algorithm (factor storage + local vectors), averaged over the
+   * launches (in a batch, subdomains of converged instances are skipped
+   * and not counted). */
   double t_ras_kernel_ms;
   int32_t n_ras_launches;
   double ras_bytes_per_launch;
@@ -236,6 +238,40 @@ seird_status seird_analyze_schwarz(int64_t n_nodes, const double *xy,
  * launches; the totals are reported in seird_step_stats (t_ras_kernel_ms,
  * n_ras_launches) and reset at the end of every seird_step. */
 seird_status seird_precond_timing(seird_precond pc, int enable);
+/* Workgroup size of the subdomain solves: 256 (any tile), 512 or 1024
+ * (tile 32 only).  A launch choice: each row's sums are split over 8, 16
+ * or 32 lanes (float64 accumulation), so results agree to rounding.
+ * Default 256; SEIRD_ERR_ARG for other values. */
+seird_status seird_precond_set_solve_threads(seird_precond pc, int32_t threads);
+
+/* Autotuner of the Schwarz launch shapes on the caller's own problem: the
+ * tile size of the band storage (16 or 32; `opts->tile` is overridden) and
+ * the subdomain-solve workgroup size.  For every tile it builds the
+ * preconditioner from `opts` and `part`, factors `vals` twice (a warm-up,
+ * then a host-timed setup), and for every workgroup size times `reps`
+ * applications to a fixed vector with HIP events.  The score of a
+ * candidate is setup_ms / applies_per_setup + apply_ms: the cost per
+ * Krylov iteration when one setup serves applies_per_setup iterations.  A
+ * candidate the problem does not admit (e.g. a band too wide for tile 16)
+ * is reported with its status and skipped.  The candidate preconditioners
+ * are destroyed before return (peak device memory: one preconditioner).
+ * Synchronising; SEIRD_ERR_ARG if no candidate could be built. */
+#define SEIRD_TUNE_MAX 8
+typedef struct {
+  int32_t tile, solve_threads;
+  int32_t status; /* SEIRD_OK, or why the candidate was skipped */
+  double setup_ms, apply_ms, score_ms;
+} seird_tune_candidate;
+typedef struct {
+  int32_t best_tile, best_solve_threads;
+  int32_t n_candidates;
+  seird_tune_candidate cand[SEIRD_TUNE_MAX];
+} seird_tune_report;
+seird_status seird_autotune_schwarz(seird_problem p,
+                                    const seird_schwarz_opts *opts,
+                                    const int32_t *part, const double *vals,
+                                    int32_t applies_per_setup, int32_t reps,
+                                    seird_tune_report *report, void *stream);
 /* Extract R_i A R_i^T from the Jacobian `vals`, factor every local matrix
  * (and the Galerkin coarse matrix) by LU without pivoting.  Synchronising;
  * returns SEIRD_ERR_BREAKDOWN on a zero/nonfinite pivot. */

@@ -13,8 +13,8 @@ import os
 
 import numpy as np
 
-__all__ = ["Problem", "Precond", "Batch", "SeirdError", "gmres", "step", "forward_record",
-           "adjoint", "SEIRDRun", "lib", "library_path"]
+__all__ = ["Problem", "Precond", "Batch", "SeirdError", "autotune", "gmres", "step",
+           "forward_record", "adjoint", "SEIRDRun", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libseird.so")
@@ -86,6 +86,19 @@ class _AStats(ctypes.Structure):
                 ("t_forward_ms", ctypes.c_double), ("t_reverse_ms", ctypes.c_double)]
 
 
+class _TuneCand(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("solve_threads", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("setup_ms", ctypes.c_double), ("apply_ms", ctypes.c_double), ("score_ms", ctypes.c_double)]
+
+
+TUNE_MAX = 8
+
+
+class _TuneReport(ctypes.Structure):
+    _fields_ = [("best_tile", ctypes.c_int32), ("best_solve_threads", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32), ("cand", _TuneCand * TUNE_MAX)]
+
+
 _P = ctypes.c_void_p
 _I64P = ctypes.POINTER(ctypes.c_int64)
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -109,6 +122,9 @@ _SIGS = {
     "seird_precond_info": ([_P, _I64P, _I64P, _I32P, _I32P], ctypes.c_int),
     "seird_precond_setup": ([_P, _P, _P], ctypes.c_int),
     "seird_precond_timing": ([_P, ctypes.c_int], ctypes.c_int),
+    "seird_precond_set_solve_threads": ([_P, ctypes.c_int32], ctypes.c_int),
+    "seird_autotune_schwarz": ([_P, ctypes.POINTER(_Schwarz), _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.POINTER(_TuneReport), _P], ctypes.c_int),
     "seird_analyze_schwarz": ([ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.POINTER(_Schwarz), _P,
                                ctypes.POINTER(_SInfo), _P, _P], ctypes.c_int),
     "seird_precond_apply": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
@@ -305,7 +321,7 @@ class Precond:
     when ``coarse = (parents_list, n_coarse)`` is given)."""
 
     def __init__(self, problem: Problem, part, n_sub, overlap, tile=32,
-                 factor_prec=0, coarse=None):
+                 factor_prec=0, coarse=None, solve_threads=256):
         self.problem = problem
         part = np.ascontiguousarray(part, dtype=np.int32)
         if len(part) != problem.n:
@@ -317,6 +333,8 @@ class Precond:
         del keep
         self.h = h
         self._vals = None
+        if solve_threads != 256:
+            self.set_solve_threads(solve_threads)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -334,6 +352,10 @@ class Precond:
     def enable_timing(self, on=True):
         _check(lib().seird_precond_timing(self.h, int(bool(on))))
 
+    def set_solve_threads(self, threads):
+        """Workgroup size of the subdomain solves (256; 512 or 1024 with tile 32)."""
+        _check(lib().seird_precond_set_solve_threads(self.h, int(threads)))
+
     def setup(self, vals):
         _check(lib().seird_precond_setup(self.h, _dptr(vals, self.problem.nvals, "vals"), _stream()))
         self._vals = vals  # the two-grid apply reads it
@@ -344,6 +366,23 @@ class Precond:
         _check(lib().seird_precond_apply(self.h, _dptr(r, N, "r"), _dptr(out, N, "z"),
                                          int(bool(transpose)), _stream()))
         return out
+
+
+def autotune(problem: Problem, part, n_sub, overlap, vals, factor_prec=0, coarse=None,
+             applies_per_setup=15, reps=3):
+    """Choose the tile size and the subdomain-solve workgroup size for this
+    problem by timing every candidate on the Jacobian ``vals`` (see
+    seird_autotune_schwarz).  Returns dict(tile, solve_threads, candidates)."""
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    o, keep = _schwarz_opts(n_sub, overlap, 32, factor_prec, coarse)
+    rep = _TuneReport()
+    _check(lib().seird_autotune_schwarz(problem.h, ctypes.byref(o), part.ctypes.data,
+                                        _dptr(vals, problem.nvals, "vals"), int(applies_per_setup),
+                                        int(reps), ctypes.byref(rep), _stream()))
+    del keep
+    cands = [dict(tile=c.tile, solve_threads=c.solve_threads, status=c.status, setup_ms=c.setup_ms,
+                  apply_ms=c.apply_ms, score_ms=c.score_ms) for c in rep.cand[:rep.n_candidates]]
+    return dict(tile=rep.best_tile, solve_threads=rep.best_solve_threads, candidates=cands)
 
 
 def gmres(problem: Problem, pc, vals, b, transpose=False, x=None, **kw):
@@ -478,6 +517,9 @@ class _BorrowedPrecond:
 
     def enable_timing(self, on=True):
         Precond.enable_timing(self, on)
+
+    def set_solve_threads(self, threads):
+        Precond.set_solve_threads(self, threads)
 
 
 class Batch:

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <tuple>
 
 #include "kernels.h"
@@ -227,6 +228,7 @@ struct seird_precond_s {
   int32_t *g2l_idx = nullptr;
   double *yloc = nullptr;
   int32_t *sub_seg = nullptr;  // instance of every subdomain (batches)
+  int solve_threads = 256;     // workgroup size of the subdomain solves
   int max_nt = 0, max_bu = 0;
   // coarse
   SubInfo *coarse_dev = nullptr;
@@ -295,6 +297,22 @@ struct seird_precond_s {
     const double fsz = ph.prec == 0 ? 8.0 : (ph.prec == 1 ? 4.0 : 2.0);
     return nsubent * fsz + (double)ph.l2g.size() * (4 + 1 + 8) + (double)prob->N * 8;
   }
+  // the same per instance of a batch (subdomains of that instance only)
+  std::vector<double> seg_bytes;
+  void set_instances(const std::vector<int32_t> &sub_seg_host, int n_inst) {
+    sub_seg = dev_upload(sub_seg_host);
+    const double fsz = ph.prec == 0 ? 8.0 : (ph.prec == 1 ? 4.0 : 2.0);
+    const int T = ph.tile;
+    seg_bytes.assign(n_inst, 0.0);
+    for (int i = 0; i < ph.n_sub; ++i) {
+      const SubInfo &q = ph.subs[i];
+      int64_t owned_n = 0;
+      for (int l = 0; l < q.n_loc; ++l) owned_n += ph.owned[q.l2g_off + l];
+      seg_bytes[sub_seg_host[i]] += (double)q.nt * (q.bl + q.bu + 1) * T * T * fsz +
+                                    (double)q.n_loc * (4 + 1 + 8) + (double)owned_n * 8;
+    }
+  }
+  double ras_bytes_acc = 0.0;  // algorithmic bytes of the timed launches
   void harvest() {
     for (size_t k = 0; k < ev_used; ++k) {
       float t = 0.f;
@@ -329,7 +347,10 @@ struct seird_precond_s {
     return Fb;
   }
 
-  void ras(const double *r, double *z, int add, int transpose, hipStream_t st, const uint8_t *seg_active = nullptr) {
+  // seg_active / seg_active_host: device and host copies of the active
+  // flags of a batch's instances (nullable)
+  void ras(const double *r, double *z, int add, int transpose, hipStream_t st, const uint8_t *seg_active = nullptr,
+           const std::vector<uint8_t> *seg_active_host = nullptr) {
     SolveLaunch sl;
     if (seg_active && sub_seg) {
       sl.sub_seg = sub_seg;
@@ -349,6 +370,7 @@ struct seird_precond_s {
     sl.transpose = transpose;
     sl.yloc = yloc;
     sl.ybuf = ybuf;
+    sl.threads = solve_threads;
     if (timing) {
       if (ev_used == ev.size()) {
         hipEvent_t a0, a1;
@@ -360,6 +382,12 @@ struct seird_precond_s {
       launch_band_solve(sl, st);
       HIPCHECK(hipEventRecord(ev[ev_used].second, st));
       ev_used++;
+      if (sl.seg_active && seg_active_host) {
+        for (size_t k = 0; k < seg_bytes.size() && k < seg_active_host->size(); ++k)
+          if ((*seg_active_host)[k]) ras_bytes_acc += seg_bytes[k];
+      } else {
+        ras_bytes_acc += ras_bytes();
+      }
     } else {
       launch_band_solve(sl, st);
     }
@@ -393,11 +421,11 @@ struct seird_precond_s {
   // seg_active (device, nullable): active flag per instance of a batch;
   // the subdomain solves of inactive instances are skipped (one-level only)
   void apply(const double *vals, const double *r, double *z, int transpose, hipStream_t st,
-             const uint8_t *seg_active = nullptr) {
+             const uint8_t *seg_active = nullptr, const std::vector<uint8_t> *seg_active_host = nullptr) {
     if (!ready) fail(SEIRD_ERR_ARG, "preconditioner used before setup");
     seird_problem P = prob;
     if (!ph.two_level) {
-      ras(r, z, 0, transpose, st, seg_active);
+      ras(r, z, 0, transpose, st, seg_active, seg_active_host);
       return;
     }
     // multiplicative two-grid: pre-smooth, coarse correction, post-smooth
@@ -487,7 +515,7 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
       // z_j = M^{-1} v_j, w = A z_j, then h = V^T w, w -= V h, |w|^2
       auto step_launches = [&](hipStream_t s) {
         if (pc)
-          pc->apply(vals, vj, zj, transpose, s, S > 1 ? P->d_mask : nullptr);
+          pc->apply(vals, vj, zj, transpose, s, S > 1 ? P->d_mask : nullptr, S > 1 ? &cyc : nullptr);
         else
           HIPCHECK(hipMemcpyAsync(zj, vj, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
         launch_spmv(P->md, P->diag(vals), P->off(vals), zj, nullptr, w, transpose, s);
@@ -789,10 +817,11 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
     for (int s = 0; s < S; ++s) {
       stats[s].t_ras_kernel_ms = pc->ras_ms;
       stats[s].n_ras_launches = pc->ras_count;
-      stats[s].ras_bytes_per_launch = pc->ras_bytes();
+      stats[s].ras_bytes_per_launch = pc->ras_count ? pc->ras_bytes_acc / pc->ras_count : pc->ras_bytes();
     }
     pc->ras_ms = 0.0;
     pc->ras_count = 0;
+    pc->ras_bytes_acc = 0.0;
   }
 }
 
@@ -1039,6 +1068,15 @@ seird_status seird_precond_timing(seird_precond pc, int enable) {
   API_END
 }
 
+seird_status seird_precond_set_solve_threads(seird_precond pc, int32_t threads) {
+  API_BEGIN
+  if (!pc) fail(SEIRD_ERR_ARG, "null preconditioner");
+  const bool ok = threads == 256 || (pc->ph.tile == 32 && (threads == 512 || threads == 1024));
+  if (!ok) fail(SEIRD_ERR_ARG, "solve workgroup size must be 256, or 512/1024 with tile 32");
+  pc->solve_threads = threads;
+  API_END
+}
+
 seird_status seird_precond_info(seird_precond pc, int64_t *factor_entries, int64_t *coarse_n,
                                 int32_t *max_local_nodes, int32_t *max_bandwidth) {
   API_BEGIN
@@ -1104,6 +1142,93 @@ seird_status seird_precond_setup(seird_precond pc, const double *vals, void *str
   API_BEGIN
   if (!pc || !vals) fail(SEIRD_ERR_ARG, "null argument");
   precond_setup_impl(pc, vals, (hipStream_t)stream);
+  API_END
+}
+
+seird_status seird_autotune_schwarz(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
+                                    const double *vals, int32_t applies_per_setup, int32_t reps,
+                                    seird_tune_report *report, void *stream) {
+  API_BEGIN
+  if (!p || !opts || !part || !vals || !report) fail(SEIRD_ERR_ARG, "null argument");
+  if (applies_per_setup < 1 || reps < 1) fail(SEIRD_ERR_ARG, "applies_per_setup and reps must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  using clk = std::chrono::steady_clock;
+  *report = seird_tune_report{};
+  std::vector<double> h(p->N);
+  for (int64_t i = 0; i < p->N; ++i) h[i] = 1.0 + 0.5 * std::sin(0.37 * (double)i);
+  struct Buffers {
+    double *r = nullptr, *z = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Buffers() {
+      dev_free(r);
+      dev_free(z);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } B;
+  B.r = dev_upload(h);
+  B.z = dev_alloc<double>(p->N);
+  HIPCHECK(hipEventCreate(&B.e0));
+  HIPCHECK(hipEventCreate(&B.e1));
+  double best = 0.0;
+  int first_err = SEIRD_OK;
+  std::string first_msg;
+  auto add = [&](int tile, int th, int status, double set_ms, double app_ms) {
+    if (report->n_candidates >= SEIRD_TUNE_MAX) return;
+    seird_tune_candidate &c = report->cand[report->n_candidates++];
+    c.tile = tile;
+    c.solve_threads = th;
+    c.status = status;
+    c.setup_ms = set_ms;
+    c.apply_ms = app_ms;
+    c.score_ms = status == SEIRD_OK ? set_ms / applies_per_setup + app_ms : 0.0;
+    if (status == SEIRD_OK && (report->best_tile == 0 || c.score_ms < best)) {
+      best = c.score_ms;
+      report->best_tile = tile;
+      report->best_solve_threads = th;
+    }
+  };
+  for (int tile : {32, 16}) {
+    const std::vector<int> widths = tile == 32 ? std::vector<int>{256, 512, 1024} : std::vector<int>{256};
+    seird_schwarz_opts o = *opts;
+    o.tile = tile;
+    seird_precond pc = nullptr;
+    const int rc = seird_precond_create(p, &o, part, &pc);
+    if (rc != SEIRD_OK) {
+      if (first_err == SEIRD_OK) {
+        first_err = rc;
+        first_msg = g_last_error;
+      }
+      for (int th : widths) add(tile, th, rc, 0.0, 0.0);
+      continue;
+    }
+    std::unique_ptr<seird_precond_s> guard(pc);
+    try {
+      precond_setup_impl(pc, vals, st);  // warm-up (first launches load code)
+      const auto t0 = clk::now();
+      precond_setup_impl(pc, vals, st);  // synchronising
+      const double set_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+      for (int th : widths) {
+        pc->solve_threads = th;
+        pc->apply(vals, B.r, B.z, 0, st);
+        HIPCHECK(hipEventRecord(B.e0, st));
+        for (int k = 0; k < reps; ++k) pc->apply(vals, B.r, B.z, 0, st);
+        HIPCHECK(hipEventRecord(B.e1, st));
+        HIPCHECK(hipEventSynchronize(B.e1));
+        float t = 0.f;
+        HIPCHECK(hipEventElapsedTime(&t, B.e0, B.e1));
+        add(tile, th, SEIRD_OK, set_ms, (double)t / reps);
+      }
+    } catch (const Error &e) {
+      if (e.code == SEIRD_ERR_HIP) throw;
+      if (first_err == SEIRD_OK) {
+        first_err = e.code;
+        first_msg = e.msg;
+      }
+      for (int th : widths) add(tile, th, e.code, 0.0, 0.0);
+    }
+  }
+  if (report->best_tile == 0) fail(SEIRD_ERR_ARG, "autotune: no candidate could be built (" + first_msg + ")");
   API_END
 }
 
@@ -1341,7 +1466,7 @@ seird_status seird_batch_create(int32_t n_inst, const int64_t *n_nodes, const do
     std::vector<int32_t> sub_seg(so);
     for (int k = 0, s0 = 0; k < n_inst; s0 += n_sub[k], ++k)
       for (int j = 0; j < n_sub[k]; ++j) sub_seg[s0 + j] = k;
-    pc->sub_seg = dev_upload(sub_seg);
+    pc->set_instances(sub_seg, n_inst);
   } catch (...) {
     delete B;
     throw;

@@ -54,6 +54,7 @@ struct SolveLaunch {
   const int32_t *order = nullptr;
   int nblocks = 0;
   bool wide = false;  // 1024-thread workgroups (one large system)
+  int threads = 256;  // workgroup size of the subdomain solves (256; 512, 1024 for tile 32)
   const int32_t *l2g = nullptr;
   const uint8_t *owned = nullptr;
   const double *r = nullptr;

@@ -1024,8 +1024,15 @@ __device__ inline double group_sum(double v) {
 //           buffer yloc (summed over copies afterwards)
 constexpr int RING = 32;  // block rows of the local vector kept in LDS (> bl, bu)
 // off-diagonal tiles per block row held in registers at once
-template <class FT, int NTHR>
-constexpr int solve_bmax() { return sizeof(FT) == 8 ? 6 : 8; }
+// (the summation order does not depend on it)
+template <int T, class FT, int NTHR>
+constexpr int solve_bmax() {
+  if (T == 32 && NTHR == 256) return sizeof(FT) == 8 ? 6 : 8;
+  constexpr int per = T * T / NTHR;  // tile elements per lane
+  constexpr int regs = per * (sizeof(FT) >= 4 ? (int)sizeof(FT) / 4 : 1);
+  constexpr int b = 48 / regs;
+  return b > 16 ? 16 : (b < 1 ? 1 : b);
+}
 
 // PER consecutive elements of one tile row (aligned to PER elements), read
 // as one or two vector loads
@@ -1052,7 +1059,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
                   double *__restrict__ z, int add, double *__restrict__ yloc, double *__restrict__ ybuf,
                   const int32_t *__restrict__ sub_seg, const uint8_t *__restrict__ seg_active) {
   constexpr bool transpose = TRANS;
-  constexpr int SOLVE_BMAX = solve_bmax<FT, NTHR>();
+  constexpr int SOLVE_BMAX = solve_bmax<T, FT, NTHR>();
   constexpr int G = NTHR / T;   // lanes per row
   constexpr int PER = T / G;    // elements of one tile row per lane
   __shared__ double ring[RING][T];
@@ -1653,18 +1660,20 @@ void launch_convert(void *dst, int dst_prec, const void *src, int src_float, int
   }
 }
 
+template <int T, class FT, bool TR, int NTHR>
+static void solve_launch(const SolveLaunch &sl, hipStream_t st) {
+  hipLaunchKernelGGL((k_band_solve<T, FT, NTHR, TR>), dim3(sl.nblocks), dim3(NTHR), 0, st, (const FT *)sl.F, sl.subs,
+                     sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf, sl.sub_seg, sl.seg_active);
+}
 template <int T, class FT, bool TR>
 static void solve_tt(const SolveLaunch &sl, hipStream_t st) {
-  // the wide (1024-thread) form needs at least one element per lane: T >= 32
-  constexpr int WIDE = T * T >= 1024 ? 1024 : 256;
-  if (sl.wide && WIDE == 1024)
-    hipLaunchKernelGGL((k_band_solve<T, FT, WIDE, TR>), dim3(sl.nblocks), dim3(WIDE), 0, st, (const FT *)sl.F,
-                       sl.subs, sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf, sl.sub_seg,
-                       sl.seg_active);
-  else
-    hipLaunchKernelGGL((k_band_solve<T, FT, 256, TR>), dim3(sl.nblocks), dim3(256), 0, st, (const FT *)sl.F, sl.subs,
-                       sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf, sl.sub_seg,
-                       sl.seg_active);
+  // wider forms need at least one tile element per lane: T = 32 only
+  const int thr = sl.wide ? 1024 : sl.threads;
+  if constexpr (T == 32) {
+    if (thr == 1024) return solve_launch<T, FT, TR, 1024>(sl, st);
+    if (thr == 512) return solve_launch<T, FT, TR, 512>(sl, st);
+  }
+  solve_launch<T, FT, TR, 256>(sl, st);
 }
 template <int T, class FT>
 static void solve_t(const SolveLaunch &sl, hipStream_t st) {

@@ -1,0 +1,84 @@
+"""Launch-shape choices: the subdomain-solve workgroup sizes give the same
+results up to the rounding of a different summation split, and the autotuner reports valid candidates whose best
+one builds a preconditioner that solves the oracle's problem."""
+import numpy as np
+import pytest
+
+import seird_inputs as si
+from oracle import fem, newton
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2208_01839_amd as sk  # noqa: E402
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("two_level", [False, True])
+def test_solve_widths_agree_to_rounding(prec, two_level):
+    cfg = si.config_nested_square(n_base=8, n_ref=2, n_sub=16)
+    prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+    coarse = (cfg.coarse_parents, cfg.coarse_n) if two_level else None
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, 2, factor_prec=prec, coarse=coarse)
+    vals = prob.jacobian(torch.tensor(cfg.u0, device="cuda"), 1.0)
+    pc.setup(vals)
+    r = torch.tensor(np.random.default_rng(2).standard_normal(prob.N), device="cuda")
+    out = {}
+    for th in (256, 512, 1024):
+        pc.set_solve_threads(th)
+        out[th] = (pc.apply(r).cpu().numpy(), pc.apply(r, transpose=True).cpu().numpy())
+    for th in (512, 1024):
+        for k in (0, 1):  # apply and transposed apply
+            a, b = out[th][k], out[256][k]
+            assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b), (th, k)
+    # repeated applications at one width are bitwise reproducible
+    pc.set_solve_threads(512)
+    assert np.array_equal(pc.apply(r).cpu().numpy(), out[512][0])
+
+
+def test_solve_width_rejected_for_tile16():
+    cfg = si.config_small()
+    prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, 1, tile=16)
+    with pytest.raises(sk.SeirdError):
+        pc.set_solve_threads(512)
+    with pytest.raises(sk.SeirdError):
+        pc.set_solve_threads(300)
+
+
+def test_autotune_picks_a_valid_fastest_candidate():
+    cfg = si.config_nested_square(n_base=8, n_ref=2, n_sub=16)
+    prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+    coarse = (cfg.coarse_parents, cfg.coarse_n)
+    u0 = si.gaussian_bump_state(cfg.xy, 4, peak=0.05, width=0.2)
+    vals = prob.jacobian(torch.tensor(u0, device="cuda"), 1.0)
+    rep = sk.autotune(prob, cfg.part, cfg.n_sub, 1, vals, coarse=coarse, applies_per_setup=10, reps=3)
+    ok = [c for c in rep["candidates"] if c["status"] == 0]
+    assert {(c["tile"], c["solve_threads"]) for c in rep["candidates"]} == {(32, 256), (32, 512), (32, 1024), (16, 256)}
+    assert ok and all(c["apply_ms"] > 0 and c["setup_ms"] > 0 for c in ok)
+    best = min(ok, key=lambda c: c["score_ms"])
+    assert (rep["tile"], rep["solve_threads"]) == (best["tile"], best["solve_threads"])
+    for c in ok:
+        assert abs(c["score_ms"] - (c["setup_ms"] / 10 + c["apply_ms"])) < 1e-9 * c["score_ms"]
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, 1, tile=rep["tile"], coarse=coarse,
+                    solve_threads=rep["solve_threads"])
+    u = torch.tensor(u0, device="cuda")
+    sk.step(prob, pc, u, 1.0, tol=1e-13, rtol=1e-10)
+    geo = fem.Geometry(cfg.xy, cfg.tri)
+    uo, _ = newton.newton_step(u0, 1.0, geo, cfg.params, tol=1e-14)
+    assert np.linalg.norm(u.cpu().numpy() - uo) <= 1e-10 * np.linalg.norm(uo)
+
+
+def test_autotune_fails_cleanly_when_no_candidate_is_admitted():
+    # one subdomain of a 128x128 square: its band (about 650 scalars) is too
+    # wide for both tile sizes
+    xy, tri = si.square_mesh(128)
+    prob = sk.Problem(xy, tri, si.params_square())
+    u0 = si.gaussian_bump_state(xy, 0)
+    vals = prob.jacobian(torch.tensor(u0, device="cuda"), 0.1)
+    with pytest.raises(sk.SeirdError) as e:
+        sk.autotune(prob, np.zeros(len(xy), dtype=np.int32), 1, 0, vals, reps=1)
+    assert e.value.code == -1
