@@ -238,6 +238,14 @@ seird_status seird_analyze_schwarz(int64_t n_nodes, const double *xy,
  * launches; the totals are reported in seird_step_stats (t_ras_kernel_ms,
  * n_ras_launches) and reset at the end of every seird_step. */
 seird_status seird_precond_timing(seird_precond pc, int enable);
+/* Coarse solver of a two-level preconditioner.  1: the coarse factors' block
+ * triangular inverses X = L^{-1}, W = U^{-1} are formed at every setup
+ * (FP64 MFMA, on the coarse stream) and A_c^{-1} r = W (X r) is two dense
+ * triangular mat-vecs over the whole device; the default with tile 32 when
+ * both fit 16 GB (nt(nt+1) tiles of 8 KB for nt coarse tile rows).  0: the
+ * band forward/backward sweeps over the factors (one workgroup).  Results
+ * agree to rounding.  SEIRD_ERR_ARG for 1 without inverses. */
+seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver);
 /* Workgroup size of the subdomain solves: 256 (any tile), 512 or 1024
  * (tile 32 only).  A launch choice: each row's sums are split over 8, 16
  * or 32 lanes (float64 accumulation), so results agree to rounding.

@@ -123,6 +123,7 @@ _SIGS = {
     "seird_precond_setup": ([_P, _P, _P], ctypes.c_int),
     "seird_precond_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "seird_precond_set_solve_threads": ([_P, ctypes.c_int32], ctypes.c_int),
+    "seird_precond_set_coarse_solver": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_autotune_schwarz": ([_P, ctypes.POINTER(_Schwarz), _P, _P, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.POINTER(_TuneReport), _P], ctypes.c_int),
     "seird_analyze_schwarz": ([ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.POINTER(_Schwarz), _P,
@@ -355,6 +356,10 @@ class Precond:
     def set_solve_threads(self, threads):
         """Workgroup size of the subdomain solves (256; 512 or 1024 with tile 32)."""
         _check(lib().seird_precond_set_solve_threads(self.h, int(threads)))
+
+    def set_coarse_solver(self, solver):
+        """1: explicit triangular inverses of the coarse factors; 0: band sweeps."""
+        _check(lib().seird_precond_set_coarse_solver(self.h, int(solver)))
 
     def setup(self, vals):
         _check(lib().seird_precond_setup(self.h, _dptr(vals, self.problem.nvals, "vals"), _stream()))

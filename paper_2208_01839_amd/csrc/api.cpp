@@ -211,6 +211,10 @@ struct seird_problem_s {
   }
 };
 
+// both packed triangular inverses of a coarse band with nt tile rows (tile 32)
+static inline double coarse_inverse_bytes(int64_t nt) { return 2.0 * (double)(nt * (nt + 1) / 2) * 1024 * 8; }
+constexpr double COARSE_INVERSE_BUDGET = 16.0e9;
+
 struct seird_precond_s {
   seird_problem prob = nullptr;
   PrecondHost ph;
@@ -239,6 +243,10 @@ struct seird_precond_s {
   int32_t *z_col = nullptr, *zt_col = nullptr;
   double *z_val = nullptr, *zt_val = nullptr;
   double *rc = nullptr, *xc = nullptr, *cscratch = nullptr, *ybuf = nullptr;
+  // explicit inverses of the coarse triangular factors (tile 32, when they
+  // fit the budget); coarse_solver 1 uses them, 0 the band sweeps
+  double *Xc = nullptr, *Wc = nullptr;
+  int coarse_solver = 0;
   double *t1 = nullptr;
   const double *vals_setup = nullptr;  // Jacobian of the last setup (borrowed)
   bool ready = false;
@@ -337,7 +345,7 @@ struct seird_precond_s {
     dev_free(owned); dev_free(status); dev_free(g2l_ptr); dev_free(g2l_idx); dev_free(yloc); dev_free(sub_seg);
     dev_free(coarse_dev); dev_free(gp); dev_free(gq); dev_free(gref); dev_free(cperm); dev_free(gptr); dev_free(gw);
     dev_free(z_ptr); dev_free(zt_ptr); dev_free(z_col); dev_free(zt_col); dev_free(z_val); dev_free(zt_val);
-    dev_free(rc); dev_free(xc); dev_free(cscratch); dev_free(ybuf); dev_free(t1);
+    dev_free(rc); dev_free(xc); dev_free(cscratch); dev_free(ybuf); dev_free(t1); dev_free(Xc); dev_free(Wc);
   }
 
   // factors read by the subdomain solves, in the storage precision ph.prec
@@ -397,6 +405,11 @@ struct seird_precond_s {
   // z += Z A_c^{-1} Z^T r  (or the transposed coarse operator)
   void coarse_add(const double *r, double *z, int transpose, hipStream_t st) {
     launch_coarse_restrict(zt_ptr, zt_col, zt_val, cperm, r, rc, ph.nc, st);
+    if (coarse_solver == 1) {
+      launch_coarse_inverse_apply(Xc, Wc, ph.coarse.nt, rc, xc, cscratch, transpose, st);
+      launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
+      return;
+    }
     if (!transpose && ph.tile == 32 && ph.coarse.bl <= 16 && ph.coarse.bu <= 16) {
       launch_coarse_solve(Fc, coarse_dev, rc, xc, cscratch, st);
       launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
@@ -1026,6 +1039,12 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
       pc->cscratch = dev_alloc<double>(cpad);
       HIPCHECK(hipMemset(pc->rc, 0, sizeof(double) * cpad));
       pc->t1 = dev_alloc<double>(p->N);
+      if (T == 32 && coarse_inverse_bytes(ph.coarse.nt) <= COARSE_INVERSE_BUDGET) {
+        const int64_t nt = ph.coarse.nt;
+        pc->Xc = dev_alloc<double>((size_t)(nt * (nt + 1) / 2) * 1024);
+        pc->Wc = dev_alloc<double>((size_t)(nt * (nt + 1) / 2) * 1024);
+        pc->coarse_solver = 1;
+      }
       HIPCHECK(hipStreamCreateWithFlags(&pc->st_coarse, hipStreamNonBlocking));
       HIPCHECK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
       HIPCHECK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
@@ -1065,6 +1084,15 @@ seird_status seird_precond_timing(seird_precond pc, int enable) {
   API_BEGIN
   if (!pc) fail(SEIRD_ERR_ARG, "null preconditioner");
   pc->timing = enable != 0;
+  API_END
+}
+
+seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver) {
+  API_BEGIN
+  if (!pc) fail(SEIRD_ERR_ARG, "null preconditioner");
+  if (solver != 0 && solver != 1) fail(SEIRD_ERR_ARG, "coarse solver must be 0 or 1");
+  if (solver == 1 && !pc->Xc) fail(SEIRD_ERR_ARG, "no coarse inverses for this preconditioner");
+  pc->coarse_solver = solver;
   API_END
 }
 
@@ -1122,6 +1150,7 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
     HIPCHECK(hipEventRecord(pc->ev_fork, st));
     HIPCHECK(hipStreamWaitEvent(pc->st_coarse, pc->ev_fork, 0));
     launch_setup_factors(fl, P->diag(vals), P->off(vals), st, pc->st_coarse);
+    if (pc->Xc) launch_coarse_inverse(pc->Fc, ph.coarse, pc->Xc, pc->Wc, pc->st_coarse);
     HIPCHECK(hipEventRecord(pc->ev_join, pc->st_coarse));
     HIPCHECK(hipStreamWaitEvent(st, pc->ev_join, 0));
   } else {

@@ -1429,6 +1429,207 @@ void launch_coarse_solve(const double *F, const SubInfo *sp, const double *r, do
 }
 
 // ----------------------------------------------------------------------
+// Explicit inverses of the coarse block-triangular factors.  With A_c =
+// L U in tile-band storage (L block unit-lower: diagonal tiles L_KK unit
+// lower, whose inverse's strict lower part is stored in the diagonal tile;
+// U block upper: the diagonal tile's upper part holds U_KK^{-1}), tile
+// column c of X = L^{-1} satisfies
+//   X_cc = L_cc^{-1},   X_Kc = -L_KK^{-1} sum_{P=max(c,K-bl)}^{K-1} L_KP X_Pc  (K > c)
+// and tile column c of W = U^{-1}
+//   W_cc = U_cc^{-1},   W_Kc = -U_KK^{-1} sum_{J=K+1}^{min(c,K+bu)} U_KJ W_Jc  (K < c).
+// The coarse solve is then two dense triangular mat-vecs, x = W (X r),
+// which stream the inverses with the whole chip instead of running the
+// dependent band sweeps in one workgroup.
+//
+// Packed tile storage, row-major 32x32 tiles: X tile (K, c), c <= K, at
+// K(K+1)/2 + c; W tile (K, c), c >= K, at K nt - K(K-1)/2 + (c - K).  A
+// tile row of either matrix is contiguous.
+// ----------------------------------------------------------------------
+__host__ __device__ inline int64_t lower_packed(int K, int c) { return (int64_t)K * (K + 1) / 2 + c; }
+__host__ __device__ inline int64_t upper_packed(int K, int c, int nt) {
+  return (int64_t)K * nt - (int64_t)K * (K - 1) / 2 + (c - K);
+}
+
+constexpr int INV_CHUNK = 4;  // factor/inverse tile pairs staged in LDS per round
+
+// One workgroup per tile column (longest columns first); each of the four
+// waves owns one 16x16 quadrant of the output tile and accumulates it on
+// FP64 MFMA.
+template <bool UPPER>
+__global__ __launch_bounds__(256) void k_coarse_tri_inverse(const double *__restrict__ F, SubInfo s,
+                                                            double *__restrict__ X) {
+  constexpr int T = 32;
+  typedef Mfma<double>::v4 v4;
+  __shared__ double As[INV_CHUNK][T][T + 1];
+  __shared__ double Bs[INV_CHUNK][T][T + 1];
+  const int nt = s.nt;
+  const int c = UPPER ? nt - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int qi = wave >> 1, qj = wave & 1;
+  const int W = s.bl + s.bu + 1;
+  auto fac = [&](int K, int slot) { return F + s.base + ((int64_t)K * W + slot) * (T * T); };
+  auto out = [&](int K) -> double * {
+    return X + (UPPER ? upper_packed(K, c, nt) : lower_packed(K, c)) * (T * T);
+  };
+  for (int it = 0; it < (UPPER ? c + 1 : nt - c); ++it) {
+    const int K = UPPER ? c - it : c + it;
+    const int p_lo = UPPER ? K + 1 : max(c, K - s.bl);
+    const int p_hi = UPPER ? min(c, K + s.bu) : K - 1;
+    v4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int P0 = p_lo; P0 <= p_hi; P0 += INV_CHUNK) {
+      const int np = min(INV_CHUNK, p_hi - P0 + 1);
+      // all loads of the round in flight before the LDS stores
+      double ra[INV_CHUNK][4], rb[INV_CHUNK][4];
+#pragma unroll
+      for (int q = 0; q < INV_CHUNK; ++q)
+        if (q < np) {
+          const double *a = fac(K, P0 + q - K + s.bl);
+          const double *b = out(P0 + q);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            ra[q][m] = a[tid + 256 * m];
+            rb[q][m] = b[tid + 256 * m];
+          }
+        }
+      __syncthreads();  // the previous round's operands are consumed
+#pragma unroll
+      for (int q = 0; q < INV_CHUNK; ++q)
+        if (q < np) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int e = tid + 256 * m;
+            As[q][e / T][e % T] = ra[q][m];
+            Bs[q][e / T][e % T] = rb[q][m];
+          }
+        }
+      __syncthreads();
+      for (int q = 0; q < np; ++q)
+#pragma unroll
+        for (int k0 = 0; k0 < T; k0 += 4)
+          acc = Mfma<double>::op(As[q][16 * qi + lr][k0 + lk], Bs[q][k0 + lk][16 * qj + lr], acc);
+    }
+    __syncthreads();
+    // S (the sum, or -I on the diagonal so that X_cc = -D (-I)) into Bs[0];
+    // D = L_KK^{-1} (unit lower) or U_KK^{-1} (upper) into As[0]
+    const double *d = fac(K, s.bl);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * qi + Mfma<double>::row(lk, v), j = 16 * qj + lr;
+      Bs[0][i][j] = K == c ? (i == j ? -1.0 : 0.0) : acc[v];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = tid + 256 * m, i = e / T, j = e % T;
+      const double dv = d[e];
+      As[0][i][j] = UPPER ? (j >= i ? dv : 0.0) : (j < i ? dv : (i == j ? 1.0 : 0.0));
+    }
+    __syncthreads();
+    v4 r = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < T; k0 += 4) r = Mfma<double>::op(As[0][16 * qi + lr][k0 + lk], Bs[0][k0 + lk][16 * qj + lr], r);
+    double *o = out(K);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) o[(16 * qi + Mfma<double>::row(lk, v)) * T + 16 * qj + lr] = -r[v];
+    // the next rows read this tile back through the cache: make the stores
+    // visible to the whole workgroup
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// y = M x for a packed triangular tile matrix M (X: lower, W: upper), or
+// y = M^T x (TRANS).  One workgroup per output tile row, longest rows
+// first.  Non-transposed: thread = (row i, 4-column chunk g) of every tile
+// of the row; transposed: thread = (column j, 4-row group g) of every tile
+// of the column.  FP64 throughout.
+template <bool UPPER, bool TRANS>
+__global__ __launch_bounds__(256) void k_coarse_tri_gemv(const double *__restrict__ M, int nt,
+                                                         const double *__restrict__ x, double *__restrict__ y) {
+  constexpr int T = 32;
+  __shared__ double red[8][T];
+  const int tid = threadIdx.x;
+  // the stored tiles of output row K: lower non-transposed and upper
+  // transposed rows hold K + 1 tiles (longest at K = nt - 1)
+  const bool grows = (!UPPER) != TRANS;
+  const int K = grows ? nt - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const int c_lo = grows ? 0 : K, c_hi = grows ? K : nt - 1;
+  auto tile = [&](int c) -> const double * {
+    // tile (row, col) of M: M_Kc, or M_cK when transposed
+    const int r0 = TRANS ? c : K, c0 = TRANS ? K : c;
+    return M + (UPPER ? upper_packed(r0, c0, nt) : lower_packed(r0, c0)) * (T * T);
+  };
+  double acc = 0.0;
+  if constexpr (!TRANS) {
+    const int i = tid >> 3, g = tid & 7;
+    int c = c_lo;
+    for (; c + 3 <= c_hi; c += 4) {
+      double4 a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = *reinterpret_cast<const double4 *>(tile(c + u) + i * T + 4 * g);
+        b[u] = *reinterpret_cast<const double4 *>(x + (int64_t)(c + u) * T + 4 * g);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += a[u].x * b[u].x + a[u].y * b[u].y + a[u].z * b[u].z + a[u].w * b[u].w;
+    }
+    for (; c <= c_hi; ++c) {
+      const double4 a = *reinterpret_cast<const double4 *>(tile(c) + i * T + 4 * g);
+      const double4 b = *reinterpret_cast<const double4 *>(x + (int64_t)c * T + 4 * g);
+      acc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+    }
+    // sum the 8 chunks of row i (consecutive lanes)
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) acc += __shfl_xor(acc, o, 8);
+    if (g == 0) y[(int64_t)K * T + i] = acc;
+  } else {
+    const int j = tid & 31, g = tid >> 5;  // rows 4g .. 4g+3 of each tile
+    int c = c_lo;
+    for (; c + 1 <= c_hi; c += 2) {
+      double a[2][4], b[2][4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          a[u][m] = tile(c + u)[(4 * g + m) * T + j];
+          b[u][m] = x[(int64_t)(c + u) * T + 4 * g + m];
+        }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc += a[u][m] * b[u][m];
+    }
+    for (; c <= c_hi; ++c)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc += tile(c)[(4 * g + m) * T + j] * x[(int64_t)c * T + 4 * g + m];
+    red[g][j] = acc;
+    __syncthreads();
+    if (tid < T) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t += red[q][tid];
+      y[(int64_t)K * T + tid] = t;
+    }
+  }
+}
+
+void launch_coarse_inverse(const double *F, const SubInfo &cs, double *X, double *W, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_tri_inverse<false>, dim3(cs.nt), dim3(256), 0, st, F, cs, X);
+  hipLaunchKernelGGL(k_coarse_tri_inverse<true>, dim3(cs.nt), dim3(256), 0, st, F, cs, W);
+}
+
+void launch_coarse_inverse_apply(const double *X, const double *W, int nt, const double *r, double *z, double *tmp,
+                                 int transpose, hipStream_t st) {
+  if (!transpose) {  // z = W (X r)
+    hipLaunchKernelGGL((k_coarse_tri_gemv<false, false>), dim3(nt), dim3(256), 0, st, X, nt, r, tmp);
+    hipLaunchKernelGGL((k_coarse_tri_gemv<true, false>), dim3(nt), dim3(256), 0, st, W, nt, tmp, z);
+  } else {  // z = X^T (W^T r)
+    hipLaunchKernelGGL((k_coarse_tri_gemv<true, true>), dim3(nt), dim3(256), 0, st, W, nt, r, tmp);
+    hipLaunchKernelGGL((k_coarse_tri_gemv<false, true>), dim3(nt), dim3(256), 0, st, X, nt, tmp, z);
+  }
+}
+
+// ----------------------------------------------------------------------
 // Discrete adjoint support (counts, adjoint right-hand side, parameter
 // gradients).  With lam^n the adjoint state of step n:
 //   rhs = dJ/du^n + M lam^{n+1},  dJ/dc_r^n = gc[r],  c_r = sum_{j in r} m_j i_j

@@ -82,3 +82,23 @@ def test_autotune_fails_cleanly_when_no_candidate_is_admitted():
     with pytest.raises(sk.SeirdError) as e:
         sk.autotune(prob, np.zeros(len(xy), dtype=np.int32), 1, 0, vals, reps=1)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("n_base,n_sub", [(8, 16), (24, 64)])
+def test_coarse_inverse_agrees_with_band_sweeps(n_base, n_sub):
+    cfg = si.config_nested_square(n_base=n_base, n_ref=2, n_sub=n_sub)
+    prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, 2, coarse=(cfg.coarse_parents, cfg.coarse_n))
+    u0 = si.gaussian_bump_state(cfg.xy, 4, peak=0.05, width=0.2)
+    vals = prob.jacobian(torch.tensor(u0, device="cuda"), 1.0)
+    pc.setup(vals)
+    r = torch.tensor(np.random.default_rng(5).standard_normal(prob.N), device="cuda")
+    out = {}
+    for solver in (1, 0):
+        pc.set_coarse_solver(solver)
+        out[solver] = (pc.apply(r).cpu().numpy(), pc.apply(r, transpose=True).cpu().numpy())
+    for k in (0, 1):
+        a, b = out[1][k], out[0][k]
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b), k
+    with pytest.raises(sk.SeirdError):
+        pc.set_coarse_solver(2)
