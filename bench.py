@@ -41,9 +41,9 @@ def build_workload(args):
     return cfg, coarse
 
 
-def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0):
+def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0, threads=256):
     prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
-    threads, tune = 256, None
+    tune = None
     if tile == "auto":
         # launch shapes chosen by the autotuner on the first Jacobian (untimed)
         vals = prob.jacobian(torch.tensor(cfg.u0, dtype=torch.float64, device="cuda"), cfg.dt)
@@ -255,6 +255,8 @@ def main():
                     help="skip the FP32/BF16-factor legs")
     ap.add_argument("--tile", default="auto", choices=["auto", "16", "32"],
                     help="tile size of the subdomain band storage (auto: chosen by the autotuner)")
+    ap.add_argument("--solve-threads", type=int, default=256, choices=[256, 512, 1024],
+                    help="subdomain-solve workgroup size when --tile is given")
     ap.add_argument("--n-base", type=int, default=3900)
     ap.add_argument("--n-ref", type=int, default=4)
     ap.add_argument("--n-sub", type=int, default=1024)
@@ -286,7 +288,8 @@ def main():
     log(f"[bench] workload {cfg.name}: {cfg.n} nodes, {len(cfg.tri)} triangles, "
         f"{cfg.n_sub} subdomains, coarse {cfg.coarse_n} nodes ({time.perf_counter() - t:.1f} s)")
     args.tuned = {}
-    res = run_steps(sk, torch, cfg, coarse, args.prec, args.steps, args.warmup, args.tile, args.pc_reuse)
+    res = run_steps(sk, torch, cfg, coarse, args.prec, args.steps, args.warmup, args.tile, args.pc_reuse,
+                    args.solve_threads)
     args.tuned[args.prec] = (res["tile"], res["solve_threads"])
     sec = res["seconds"]
     stats = res["stats"]
@@ -333,7 +336,8 @@ def main():
     if args.compare_prec:
         mixed = {}
         for p in (1, 2):
-            r2 = run_steps(sk, torch, cfg, coarse, p, args.steps, args.warmup, args.tile, args.pc_reuse)
+            r2 = run_steps(sk, torch, cfg, coarse, p, args.steps, args.warmup, args.tile, args.pc_reuse,
+                           args.solve_threads)
             args.tuned[p] = (r2["tile"], r2["solve_threads"])
             mixed[{1: "fp32", 2: "bf16"}[p]] = {
                 "steps_per_s": args.steps / r2["seconds"],

@@ -826,48 +826,153 @@ struct Mfma<float> {
   __device__ static inline int row(int lk, int v) { return 4 * lk + v; }
 };
 
+// LU without pivoting of the diagonal tile in Dl, by wave 0 alone (no
+// workgroup barriers: the LDS accesses of one wave are processed in order).
+// Raises *status on a zero or nonfinite pivot.
+template <class CT>
+__device__ void lu_diag_wave(const CT *__restrict__ dk, CT (*Dl)[33], int *status) {
+  constexpr int T = 32;
+  const int lane = threadIdx.x & 63;
+  for (int e = lane; e < T * T; e += 64) Dl[e / T][e % T] = dk[e];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int k = 0; k < T; ++k) {
+    const CT piv = Dl[k][k];
+    if (lane == 0 && (!isfinite((double)piv) || fabs((double)piv) < 1e-300)) atomicOr(status, 1);
+    const CT rp = (CT)1 / piv;
+    if (lane < T - 1 - k) Dl[k + 1 + lane][k] *= rp;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int w = T - 1 - k;
+    for (int e = lane; e < w * w; e += 64) {
+      const int i = k + 1 + e / w, j = k + 1 + e % w;
+      Dl[i][j] -= Dl[i][k] * Dl[k][j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Explicit inverses of the factored diagonal tile (all 256 threads), dense
+// in LDS: Li = L^{-1} (unit lower) by forward elimination over columns k,
+// Ui = U^{-1} by backward elimination over rows kk = 31 - k, both in the
+// same 32 steps with one barrier each.  In step t, Li's rows i > k take
+// -L_ik Li[k][.] (row k is final), and Ui's rows i < kk take -U_i,kk X_kk
+// with X_kk = Ui[kk][.] / U_kk,kk formed on the fly; the scaled row kk is
+// written one step later, when no thread reads it any more.  The tile is
+// replaced in memory by (strict lower of Li) + (upper of Ui).
+template <class CT>
+__device__ void inv_diag_tile(CT *__restrict__ dk, CT (*Dl)[33], CT (*Li)[33], CT (*Ui)[33]) {
+  constexpr int T = 32;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < T * T; e += 256) {
+    const int i = e / T, j = e % T;
+    Li[i][j] = (i == j) ? (CT)1 : (CT)0;
+    Ui[i][j] = (i == j) ? (CT)1 : (CT)0;
+  }
+  __syncthreads();
+  for (int t = 0; t < T; ++t) {
+    const int k = t, kk = T - 1 - t;
+    const int nl = (T - 1 - k) * (k + 1);
+    for (int e = tid; e < nl; e += 256) {
+      const int i = k + 1 + e / (k + 1), j = e % (k + 1);
+      Li[i][j] -= Dl[i][k] * Li[k][j];
+    }
+    const CT ud = (CT)1 / Dl[kk][kk];
+    const int nu = kk * (T - kk);
+    for (int e = tid; e < nu; e += 256) {
+      const int i = e / (T - kk), j = kk + e % (T - kk);
+      Ui[i][j] -= Dl[i][kk] * (Ui[kk][j] * ud);
+    }
+    if (t > 0) {
+      const CT u1 = (CT)1 / Dl[kk + 1][kk + 1];
+      for (int j = kk + 1 + tid; j < T; j += 256) Ui[kk + 1][j] *= u1;
+    }
+    __syncthreads();
+  }
+  {
+    const CT u0 = (CT)1 / Dl[0][0];
+    for (int j = tid; j < T; j += 256) Ui[0][j] *= u0;
+  }
+  __syncthreads();
+  for (int e = tid; e < T * T; e += 256) {
+    const int i = e / T, j = e % T;
+    dk[e] = (i > j) ? Li[i][j] : Ui[i][j];
+  }
+}
+
 template <class CT>
 __global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const SubInfo *__restrict__ subs,
                                                    const int32_t *__restrict__ order, int *status) {
   constexpr int T = 32;
   typedef typename Mfma<CT>::v4 v4;
-  __shared__ LuLds<T, CT> L;
+  __shared__ CT Dl[T][T + 1];  // diagonal tile being factored
+  __shared__ CT Li[T][T + 1];  // L_KK^{-1}, dense unit lower
+  __shared__ CT Ui[T][T + 1];  // U_KK^{-1}, dense upper
+  __shared__ CT Sa[T][T + 1];  // A_IK
+  __shared__ CT Sb[T][T + 1];  // L_IK = A_IK U_KK^{-1}
   extern __shared__ __align__(16) unsigned char up_raw[];
-  CT(*Up)[T][T + 1] = reinterpret_cast<CT(*)[T][T + 1]>(up_raw);
+  CT(*Up)[T][T + 1] = reinterpret_cast<CT(*)[T][T + 1]>(up_raw);  // U panel of the step
   const SubInfo s = subs[order[blockIdx.x]];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
+  const int qi = wave >> 1, qj = wave & 1;
   for (int K = 0; K < s.nt; ++K) {
-    lu_diag_tile<T, CT>(tile_at<T, CT>(F, s, K, s.bl), L, status);
     const int je = min(K + s.bu, s.nt - 1), nu = je - K;
     const int ie = min(K + s.bl, s.nt - 1);
-    // U panel: U_KJ = L_KK^{-1} A_KJ, kept in LDS for the whole step
-    for (int jj = 0; jj < nu; ++jj) {
-      const CT *a = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
-      for (int e = tid; e < T * T; e += 256) Up[jj][e / T][e % T] = a[e];
-    }
-    __syncthreads();
-    for (int jj = 0; jj < nu; ++jj) {
-      CT out[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int e = tid + 256 * m, i = e / T, j = e % T;
-        CT acc = Up[jj][i][j];
-        for (int k = 0; k < i; ++k) acc += L.Li[i][k] * Up[jj][k][j];
-        out[m] = acc;
-      }
-      __syncthreads();
-      CT *a = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int e = tid + 256 * m;
-        Up[jj][e / T][e % T] = out[m];
-        a[e] = out[m];
+    // (1) wave 0 factors the diagonal tile while waves 1..3 stage the
+    // U-panel tiles A_KJ into LDS; then all waves form its inverses
+    if (wave == 0) {
+      lu_diag_wave<CT>(tile_at<T, CT>(F, s, K, s.bl), Dl, status);
+    } else {
+      for (int jj = 0; jj < nu; ++jj) {
+        const CT *a = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
+        for (int e = tid - 64; e < T * T; e += 192) Up[jj][e / T][e % T] = a[e];
       }
     }
     __syncthreads();
+    inv_diag_tile<CT>(tile_at<T, CT>(F, s, K, s.bl), Dl, Li, Ui);
+    __syncthreads();
+    // (2) U panel on MFMA: U_KJ = L_KK^{-1} A_KJ.  Wave w owns tiles w, w+4,
+    // ..; only the owner reads a tile, so it is updated in place one tile at
+    // a time (the LDS accesses of one wave are processed in order)
+#pragma unroll 1
+    for (int jj = wave; jj < nu; jj += 4) {
+      v4 acc[2][2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4{0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 0; k0 < T; k0 += 4) {
+        const CT a0 = Li[lr][k0 + lk], a1 = Li[16 + lr][k0 + lk];
+        const CT b0 = Up[jj][k0 + lk][lr], b1 = Up[jj][k0 + lk][16 + lr];
+        acc[0][0] = Mfma<CT>::op(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<CT>::op(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<CT>::op(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<CT>::op(a1, b1, acc[1][1]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      CT *g = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * bi + Mfma<CT>::row(lk, v), jc = 16 * bj + lr;
+            Up[jj][i][jc] = acc[bi][bj][v];
+            g[i * T + jc] = acc[bi][bj][v];
+          }
+    }
+    // (3) block rows below: L_IK = A_IK U_KK^{-1}, then C_I* -= L_IK U_K*
     for (int I = K + 1; I <= ie; ++I) {
-      // C strip into accumulators (all loads issued before any use)
+      // C strip into accumulators and A_IK into registers (all loads in flight)
       v4 acc[4][2][2];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -883,29 +988,30 @@ __global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const Sub
         }
       }
       CT *aik = tile_at<T, CT>(F, s, I, K - I + s.bl);
-      for (int e = tid; e < T * T; e += 256) L.S[e / T][e % T] = aik[e];
-      __syncthreads();
-      // L_IK = A_IK U_KK^{-1}
-      CT out[4];
+      CT ra[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int e = tid + 256 * m, i = e / T, j = e % T;
-        CT a = 0;
-        for (int k = 0; k <= j; ++k) a += L.S[i][k] * L.Ui[k][j];
-        out[m] = a;
-      }
-      __syncthreads();
+      for (int m = 0; m < 4; ++m) ra[m] = aik[tid + 256 * m];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int e = tid + 256 * m;
-        L.S[e / T][e % T] = out[m];
-        aik[e] = out[m];
+        Sa[e / T][e % T] = ra[m];
       }
-      __syncthreads();
+      __syncthreads();  // Sa staged (and the U panel written, for the first I)
+      // quadrant (qi, qj) of L_IK on MFMA
+      v4 l = {0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 0; k0 < T; k0 += 4) l = Mfma<CT>::op(Sa[16 * qi + lr][k0 + lk], Ui[k0 + lk][16 * qj + lr], l);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * qi + Mfma<CT>::row(lk, v), jc = 16 * qj + lr;
+        Sb[i][jc] = l[v];
+        aik[i * T + jc] = l[v];
+      }
+      __syncthreads();  // L_IK staged
       // C -= L_IK U_KJ on MFMA
 #pragma unroll
       for (int k0 = 0; k0 < T; k0 += 4) {
-        const CT a0 = -L.S[lr][k0 + lk], a1 = -L.S[16 + lr][k0 + lk];
+        const CT a0 = -Sb[lr][k0 + lk], a1 = -Sb[16 + lr][k0 + lk];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int jj = wave + 4 * q;
@@ -931,8 +1037,11 @@ __global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const Sub
               for (int v = 0; v < 4; ++v) c[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr] = acc[q][bi][bj][v];
         }
       }
-      __syncthreads();
     }
+    // the next step's diagonal tile, U panel and C strips were written by
+    // other waves of this workgroup: make the stores visible before reuse
+    __threadfence_block();
+    __syncthreads();
   }
 }
 
