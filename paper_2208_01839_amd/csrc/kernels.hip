@@ -1047,22 +1047,56 @@ __global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const Sub
 
 // Multi-launch variant for one large band matrix (the coarse problem):
 // step K = diag (1 WG), panels (bl + bu WGs), Schur (bl x bu WGs).
+// With tile 32 the steps use the single-wave diagonal factorisation, the
+// one-barrier-per-step inverses and MFMA tile products, and stay within
+// 25 KB of LDS so that they fit beside a subdomain-factorisation workgroup
+// on the same compute unit (the coarse chain runs on its own stream while
+// the subdomains are factored).
 template <int T>
 __global__ __launch_bounds__(256) void k_lu_step_diag(double *__restrict__ F, SubInfo s, int K, int *status) {
-  __shared__ LuLds<T, double> L;
-  lu_diag_tile<T>(tile_at<T>(F, s, K, s.bl), L, status);
+  if constexpr (T == 32) {
+    __shared__ double Dl[T][T + 1], Li[T][T + 1], Ui[T][T + 1];
+    double *dk = tile_at<T>(F, s, K, s.bl);
+    if ((threadIdx.x >> 6) == 0) lu_diag_wave<double>(dk, Dl, status);
+    __syncthreads();
+    inv_diag_tile<double>(dk, Dl, Li, Ui);
+  } else {
+    __shared__ LuLds<T, double> L;
+    lu_diag_tile<T>(tile_at<T>(F, s, K, s.bl), L, status);
+  }
 }
 template <int T>
 __global__ __launch_bounds__(256) void k_lu_step_panel(double *__restrict__ F, SubInfo s, int K) {
-  __shared__ LuLds<T, double> L;
-  load_diag_inverses<T>(tile_at<T>(F, s, K, s.bl), L);
   const int b = blockIdx.x;
-  if (b < s.bl) {
-    const int I = K + 1 + b;
-    if (I < s.nt) panel_tile<T>(tile_at<T>(F, s, I, K - I + s.bl), L, true);
+  const bool lower = b < s.bl;
+  const int IJ = K + 1 + (lower ? b : b - s.bl);
+  if (IJ >= s.nt) return;
+  double *a = lower ? tile_at<T>(F, s, IJ, K - IJ + s.bl) : tile_at<T>(F, s, K, IJ - K + s.bl);
+  if constexpr (T == 32) {
+    // lower panel X = A U_KK^{-1}, upper panel X = L_KK^{-1} A, on MFMA
+    typedef Mfma<double>::v4 v4;
+    __shared__ double Dm[T][T + 1], Sa[T][T + 1];
+    const double *dk = tile_at<T>(F, s, K, s.bl);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4, qi = wave >> 1, qj = wave & 1;
+    for (int e = tid; e < T * T; e += 256) {
+      const int i = e / T, j = e % T;
+      const double d = dk[e];
+      Dm[i][j] = lower ? (i <= j ? d : 0.0) : (i > j ? d : (i == j ? 1.0 : 0.0));
+      Sa[i][j] = a[e];
+    }
+    __syncthreads();
+    v4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < T; k0 += 4)
+      x = lower ? Mfma<double>::op(Sa[16 * qi + lr][k0 + lk], Dm[k0 + lk][16 * qj + lr], x)
+                : Mfma<double>::op(Dm[16 * qi + lr][k0 + lk], Sa[k0 + lk][16 * qj + lr], x);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a[(16 * qi + Mfma<double>::row(lk, v)) * T + 16 * qj + lr] = x[v];
   } else {
-    const int J = K + 1 + (b - s.bl);
-    if (J < s.nt) panel_tile<T>(tile_at<T>(F, s, K, J - K + s.bl), L, false);
+    __shared__ LuLds<T, double> L;
+    load_diag_inverses<T>(tile_at<T>(F, s, K, s.bl), L);
+    panel_tile<T>(a, L, lower);
   }
 }
 template <int T>
@@ -1072,12 +1106,32 @@ __global__ __launch_bounds__(256) void k_lu_step_schur(double *__restrict__ F, S
   if (I >= s.nt || J >= s.nt) return;
   const double *lik = tile_at<T>(F, s, I, K - I + s.bl);
   const double *ukj = tile_at<T>(F, s, K, J - K + s.bl);
-  for (int e = threadIdx.x; e < T * T; e += 256) {
-    Sa[e / T][e % T] = lik[e];
-    Sb[e / T][e % T] = ukj[e];
+  double *c = tile_at<T>(F, s, I, J - I + s.bl);
+  if constexpr (T == 32) {
+    // C -= L_IK U_KJ on MFMA, one 16x16 quadrant per wave
+    typedef Mfma<double>::v4 v4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4, qi = wave >> 1, qj = wave & 1;
+    v4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = c[(16 * qi + Mfma<double>::row(lk, v)) * T + 16 * qj + lr];
+    for (int e = tid; e < T * T; e += 256) {
+      Sa[e / T][e % T] = -lik[e];
+      Sb[e / T][e % T] = ukj[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k0 = 0; k0 < T; k0 += 4) acc = Mfma<double>::op(Sa[16 * qi + lr][k0 + lk], Sb[k0 + lk][16 * qj + lr], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[(16 * qi + Mfma<double>::row(lk, v)) * T + 16 * qj + lr] = acc[v];
+  } else {
+    for (int e = threadIdx.x; e < T * T; e += 256) {
+      Sa[e / T][e % T] = lik[e];
+      Sb[e / T][e % T] = ukj[e];
+    }
+    __syncthreads();
+    schur_tile<T>(c, Sa, Sb);
   }
-  __syncthreads();
-  schur_tile<T>(tile_at<T>(F, s, I, J - I + s.bl), Sa, Sb);
 }
 
 // ----------------------------------------------------------------------
@@ -1559,84 +1613,99 @@ __host__ __device__ inline int64_t upper_packed(int K, int c, int nt) {
   return (int64_t)K * nt - (int64_t)K * (K - 1) / 2 + (c - K);
 }
 
-constexpr int INV_CHUNK = 4;  // factor/inverse tile pairs staged in LDS per round
+constexpr int INV_PF = 2;  // tile pairs loaded ahead into registers
 
-// One workgroup per tile column (longest columns first); each of the four
-// waves owns one 16x16 quadrant of the output tile and accumulates it on
-// FP64 MFMA.
-template <bool UPPER>
+// One launch forms both inverses: block b handles tile column b / 2 of X
+// (even b) or column nt - 1 - b / 2 of W (odd b), so the longest columns
+// of both start first.  Each of the four waves owns one 16x16 quadrant of
+// the output tile and accumulates it on FP64 MFMA; one factor/inverse tile
+// pair at a time is staged in LDS (17 KB, which fits beside a
+// subdomain-factorisation workgroup), with the next INV_PF pairs' loads in
+// flight in registers.
 __global__ __launch_bounds__(256) void k_coarse_tri_inverse(const double *__restrict__ F, SubInfo s,
-                                                            double *__restrict__ X) {
+                                                            double *__restrict__ X, double *__restrict__ Wm) {
   constexpr int T = 32;
   typedef Mfma<double>::v4 v4;
-  __shared__ double As[INV_CHUNK][T][T + 1];
-  __shared__ double Bs[INV_CHUNK][T][T + 1];
+  __shared__ double As[T][T + 1];
+  __shared__ double Bs[T][T + 1];
   const int nt = s.nt;
-  const int c = UPPER ? nt - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const bool upper = (blockIdx.x & 1) != 0;
+  const int c = upper ? nt - 1 - (int)(blockIdx.x >> 1) : (int)(blockIdx.x >> 1);
+  double *const M = upper ? Wm : X;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int qi = wave >> 1, qj = wave & 1;
   const int W = s.bl + s.bu + 1;
   auto fac = [&](int K, int slot) { return F + s.base + ((int64_t)K * W + slot) * (T * T); };
   auto out = [&](int K) -> double * {
-    return X + (UPPER ? upper_packed(K, c, nt) : lower_packed(K, c)) * (T * T);
+    return M + (upper ? upper_packed(K, c, nt) : lower_packed(K, c)) * (T * T);
   };
-  for (int it = 0; it < (UPPER ? c + 1 : nt - c); ++it) {
-    const int K = UPPER ? c - it : c + it;
-    const int p_lo = UPPER ? K + 1 : max(c, K - s.bl);
-    const int p_hi = UPPER ? min(c, K + s.bu) : K - 1;
+  const int rows = upper ? c + 1 : nt - c;
+  for (int it = 0; it < rows; ++it) {
+    const int K = upper ? c - it : c + it;
+    const int p_lo = upper ? K + 1 : max(c, K - s.bl);
+    const int p_hi = upper ? min(c, K + s.bu) : K - 1;
     v4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int P0 = p_lo; P0 <= p_hi; P0 += INV_CHUNK) {
-      const int np = min(INV_CHUNK, p_hi - P0 + 1);
-      // all loads of the round in flight before the LDS stores
-      double ra[INV_CHUNK][4], rb[INV_CHUNK][4];
+    double ca[INV_PF][4], cb[INV_PF][4];
+    auto load_group = [&](int P0, double (&ga)[INV_PF][4], double (&gb)[INV_PF][4]) {
 #pragma unroll
-      for (int q = 0; q < INV_CHUNK; ++q)
-        if (q < np) {
+      for (int q = 0; q < INV_PF; ++q)
+        if (P0 + q <= p_hi) {
           const double *a = fac(K, P0 + q - K + s.bl);
           const double *b = out(P0 + q);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            ra[q][m] = a[tid + 256 * m];
-            rb[q][m] = b[tid + 256 * m];
+            ga[q][m] = a[tid + 256 * m];
+            gb[q][m] = b[tid + 256 * m];
           }
         }
-      __syncthreads();  // the previous round's operands are consumed
+    };
+    load_group(p_lo, ca, cb);
+    for (int P0 = p_lo; P0 <= p_hi; P0 += INV_PF) {
+      double na[INV_PF][4], nb[INV_PF][4];
+      load_group(P0 + INV_PF, na, nb);
 #pragma unroll
-      for (int q = 0; q < INV_CHUNK; ++q)
-        if (q < np) {
+      for (int q = 0; q < INV_PF; ++q)
+        if (P0 + q <= p_hi) {
+          __syncthreads();  // the previous pair is consumed
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
             const int e = tid + 256 * m;
-            As[q][e / T][e % T] = ra[q][m];
-            Bs[q][e / T][e % T] = rb[q][m];
+            As[e / T][e % T] = ca[q][m];
+            Bs[e / T][e % T] = cb[q][m];
           }
-        }
-      __syncthreads();
-      for (int q = 0; q < np; ++q)
+          __syncthreads();
 #pragma unroll
-        for (int k0 = 0; k0 < T; k0 += 4)
-          acc = Mfma<double>::op(As[q][16 * qi + lr][k0 + lk], Bs[q][k0 + lk][16 * qj + lr], acc);
+          for (int k0 = 0; k0 < T; k0 += 4)
+            acc = Mfma<double>::op(As[16 * qi + lr][k0 + lk], Bs[k0 + lk][16 * qj + lr], acc);
+        }
+#pragma unroll
+      for (int q = 0; q < INV_PF; ++q)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          ca[q][m] = na[q][m];
+          cb[q][m] = nb[q][m];
+        }
     }
     __syncthreads();
-    // S (the sum, or -I on the diagonal so that X_cc = -D (-I)) into Bs[0];
-    // D = L_KK^{-1} (unit lower) or U_KK^{-1} (upper) into As[0]
+    // S (the sum, or -I on the diagonal so that the diagonal tile is -D (-I))
+    // into Bs; D = L_KK^{-1} (unit lower) or U_KK^{-1} (upper) into As
     const double *d = fac(K, s.bl);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = 16 * qi + Mfma<double>::row(lk, v), j = 16 * qj + lr;
-      Bs[0][i][j] = K == c ? (i == j ? -1.0 : 0.0) : acc[v];
+      Bs[i][j] = K == c ? (i == j ? -1.0 : 0.0) : acc[v];
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int e = tid + 256 * m, i = e / T, j = e % T;
       const double dv = d[e];
-      As[0][i][j] = UPPER ? (j >= i ? dv : 0.0) : (j < i ? dv : (i == j ? 1.0 : 0.0));
+      As[i][j] = upper ? (j >= i ? dv : 0.0) : (j < i ? dv : (i == j ? 1.0 : 0.0));
     }
     __syncthreads();
     v4 r = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k0 = 0; k0 < T; k0 += 4) r = Mfma<double>::op(As[0][16 * qi + lr][k0 + lk], Bs[0][k0 + lk][16 * qj + lr], r);
+    for (int k0 = 0; k0 < T; k0 += 4) r = Mfma<double>::op(As[16 * qi + lr][k0 + lk], Bs[k0 + lk][16 * qj + lr], r);
     double *o = out(K);
 #pragma unroll
     for (int v = 0; v < 4; ++v) o[(16 * qi + Mfma<double>::row(lk, v)) * T + 16 * qj + lr] = -r[v];
@@ -1723,8 +1792,7 @@ __global__ __launch_bounds__(256) void k_coarse_tri_gemv(const double *__restric
 }
 
 void launch_coarse_inverse(const double *F, const SubInfo &cs, double *X, double *W, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarse_tri_inverse<false>, dim3(cs.nt), dim3(256), 0, st, F, cs, X);
-  hipLaunchKernelGGL(k_coarse_tri_inverse<true>, dim3(cs.nt), dim3(256), 0, st, F, cs, W);
+  hipLaunchKernelGGL(k_coarse_tri_inverse, dim3(2 * cs.nt), dim3(256), 0, st, F, cs, X, W);
 }
 
 void launch_coarse_inverse_apply(const double *X, const double *W, int nt, const double *r, double *z, double *tmp,
@@ -1928,12 +1996,9 @@ static void coarse_factor_t(const FactorLaunch &fl, const double *diag, const do
 
 void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st,
                           hipStream_t st_coarse) {
-  if (fl.coarse) {
-    if (fl.tile == 32)
-      coarse_factor_t<32>(fl, diag, off, st_coarse);
-    else
-      coarse_factor_t<16>(fl, diag, off, st_coarse);
-  }
+  // the subdomain extraction and factorisation are queued first: the host
+  // then spends a while queueing the coarse chain (a few launches per tile
+  // row), which the device runs beside the subdomain work
   if (fl.nsub > 0) {
     if (fl.tile == 32) {
       if (fl.sub_float) {
@@ -1953,6 +2018,12 @@ void launch_setup_factors(const FactorLaunch &fl, const double *diag, const doub
       hipLaunchKernelGGL(k_band_lu<16>, dim3(fl.nsub), dim3(256), lds, st, (double *)fl.Fs, fl.subs, fl.order,
                          fl.status);
     }
+  }
+  if (fl.coarse) {
+    if (fl.tile == 32)
+      coarse_factor_t<32>(fl, diag, off, st_coarse);
+    else
+      coarse_factor_t<16>(fl, diag, off, st_coarse);
   }
 }
 
