@@ -1994,6 +1994,10 @@ static void coarse_factor_t(const FactorLaunch &fl, const double *diag, const do
   }
 }
 
+// LDS of a factorisation workgroup (static + dynamic) above which only one
+// fits on a 160 KB compute unit
+constexpr size_t FACTOR_LDS_ONE_PER_CU = 80 * 1024 + 256;
+
 void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st,
                           hipStream_t st_coarse) {
   // the subdomain extraction and factorisation are queued first: the host
@@ -2003,7 +2007,11 @@ void launch_setup_factors(const FactorLaunch &fl, const double *diag, const doub
     if (fl.tile == 32) {
       if (fl.sub_float) {
         extract_t<32, float>(fl, (float *)fl.Fs, diag, off, st);
-        const size_t lds = (size_t)std::max(fl.max_bu, 1) * 32 * 33 * sizeof(float);
+        size_t lds = (size_t)std::max(fl.max_bu, 1) * 32 * 33 * sizeof(float);
+        // with a coarse chain beside it, hold the float32 factorisation to
+        // one workgroup per compute unit (by its LDS request) so that the
+        // coarse kernels find room on every compute unit
+        if (fl.coarse) lds = std::max(lds, FACTOR_LDS_ONE_PER_CU - 5 * 32 * 33 * sizeof(float));
         hipLaunchKernelGGL(k_band_lu32<float>, dim3(fl.nsub), dim3(256), lds, st, (float *)fl.Fs, fl.subs, fl.order,
                            fl.status);
       } else {
