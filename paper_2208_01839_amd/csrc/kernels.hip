@@ -1254,6 +1254,9 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     for (int K = 0; K < s.nt; ++K) {
       const int p0 = max(0, K - s.bl);
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
+      // the diagonal tile's loads go out with the first off-diagonal chunk
+      FT dv[PER];
+      load_chunk<FT, PER>(tile(K, s.bl) + i * T + g * PER, dv);
       double a = 0.0;
       for (int P0 = p0; P0 < K; P0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
@@ -1271,9 +1274,6 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
             for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g * PER + m];
           }
       }
-      const FT *dk = tile(K, s.bl);
-      FT dv[PER];
-      load_chunk<FT, PER>(dk + i * T + g * PER, dv);
       a = group_sum<G>(a);
       if (g == 0) acc_s[i] = bv - a;
       lds_barrier();
@@ -1295,6 +1295,8 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     for (int K = s.nt - 1; K >= 0; --K) {
       const int je = min(K + s.bu, s.nt - 1);
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
+      FT dv[PER];
+      load_chunk<FT, PER>(tile(K, s.bl) + i * T + g * PER, dv);
       double a = 0.0;
       for (int J0 = K + 1; J0 <= je; J0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
@@ -1312,9 +1314,6 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
             for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g * PER + m];
           }
       }
-      const FT *dk = tile(K, s.bl);
-      FT dv[PER];
-      load_chunk<FT, PER>(dk + i * T + g * PER, dv);
       a = group_sum<G>(a);
       if (g == 0) acc_s[i] = bv - a;
       lds_barrier();
@@ -1348,6 +1347,12 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     for (int K = 0; K < s.nt; ++K) {
       const int p0 = max(0, K - s.bu);
       const double bv = (tid < T && K * T + tid < s.n_loc) ? ybuf[yo + K * T + tid] : 0.0;
+      FT dv[PER];
+      {
+        const FT *dk = tile(K, s.bl);
+#pragma unroll
+        for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
+      }
       double a = 0.0;
       for (int P0 = p0; P0 < K; P0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
@@ -1366,10 +1371,6 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
             for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[cg + m * G];
           }
       }
-      const FT *dk = tile(K, s.bl);
-      FT dv[PER];
-#pragma unroll
-      for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
       part_s[cg][ci] = a;
       lds_barrier();
       if (tid < T) {
@@ -1398,6 +1399,12 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     for (int K = s.nt - 1; K >= 0; --K) {
       const int je = min(K + s.bl, s.nt - 1);
       const double bv = (tid < T && K * T + tid < s.n_loc) ? ybuf[yo + K * T + tid] : 0.0;
+      FT dv[PER];
+      {
+        const FT *dk = tile(K, s.bl);
+#pragma unroll
+        for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
+      }
       double a = 0.0;
       for (int J0 = K + 1; J0 <= je; J0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
@@ -1416,10 +1423,6 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
             for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[cg + m * G];
           }
       }
-      const FT *dk = tile(K, s.bl);
-      FT dv[PER];
-#pragma unroll
-      for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
       part_s[cg][ci] = a;
       lds_barrier();
       if (tid < T) {
