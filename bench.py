@@ -24,6 +24,11 @@ import sys
 import time
 
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the subdomain-solve kernel from rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE, copy-calibrated) of the current kernel, by
+# (factor precision, tile); the table and commands are in
+# profiles/traffic_realistic_fp64.md.  Legs without a measurement report null.
+MEASURED_SOLVE_TRAFFIC = {(0, 32): (28.355 + 0.178) * 1e9}
 
 
 def log(*a):
@@ -303,7 +308,9 @@ def main():
         achieved = ras_bytes / avg_s / 1e9
         roofline = {"bound": "hbm", "kernel": "k_band_solve (subdomain solves of one RAS apply)",
                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                    "frac": achieved / PEAK_HBM_GBS,
+                    "traffic": MEASURED_SOLVE_TRAFFIC.get((args.prec, res["tile"])),
+                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     "avg_launch_ms": ras_ms / ras_n, "launches": ras_n,
                     "bytes_per_launch": ras_bytes}
     phase = {k: sum(s[k] for s in stats) / max(1, len(stats)) for k in
