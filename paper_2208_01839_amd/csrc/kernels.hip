@@ -826,46 +826,21 @@ struct Mfma<float> {
   __device__ static inline int row(int lk, int v) { return 4 * lk + v; }
 };
 
-// LU without pivoting of the diagonal tile in Dl, by wave 0 alone (no
-// workgroup barriers: the LDS accesses of one wave are processed in order).
-// Raises *status on a zero or nonfinite pivot.
+// LU without pivoting of the tile in Dl and the explicit inverses of both
+// factors in one forward sweep of 32 steps (all 256 threads, one barrier
+// per step).  Step k uses the unscaled column k, l_ik = a_ik / a_kk formed
+// on the fly, and row k of U (final at step k):
+//   trailing update   a_ij -= l_ik a_kj                 (i, j > k)
+//   X = L^{-1}         X_ij -= l_ik X_kj                (i > k, j <= k)
+//   Z = (U^T)^{-1}     Z_ij -= U_ki (Z_kj / U_kk)       (i > k, j <= k)
+// (the last two are forward elimination applied to the identity); the
+// multipliers of column k - 1 and the row k - 1 of Z are scaled one step
+// later, when no thread reads them.  Z lives in Ui and is transposed in
+// place at the end (Ui = Z^T = U^{-1}); the tile is replaced in memory by
+// (strict lower of L^{-1}) + (upper of U^{-1}).  Raises *status on a zero or
+// nonfinite pivot.
 template <class CT>
-__device__ void lu_diag_wave(const CT *__restrict__ dk, CT (*Dl)[33], int *status) {
-  constexpr int T = 32;
-  const int lane = threadIdx.x & 63;
-  for (int e = lane; e < T * T; e += 64) Dl[e / T][e % T] = dk[e];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int k = 0; k < T; ++k) {
-    const CT piv = Dl[k][k];
-    if (lane == 0 && (!isfinite((double)piv) || fabs((double)piv) < 1e-300)) atomicOr(status, 1);
-    const CT rp = (CT)1 / piv;
-    if (lane < T - 1 - k) Dl[k + 1 + lane][k] *= rp;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int w = T - 1 - k;
-    for (int e = lane; e < w * w; e += 64) {
-      const int i = k + 1 + e / w, j = k + 1 + e % w;
-      Dl[i][j] -= Dl[i][k] * Dl[k][j];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-}
-
-// Explicit inverses of the factored diagonal tile (all 256 threads), dense
-// in LDS: Li = L^{-1} (unit lower) by forward elimination over columns k,
-// Ui = U^{-1} by backward elimination over rows kk = 31 - k, both in the
-// same 32 steps with one barrier each.  In step t, Li's rows i > k take
-// -L_ik Li[k][.] (row k is final), and Ui's rows i < kk take -U_i,kk X_kk
-// with X_kk = Ui[kk][.] / U_kk,kk formed on the fly; the scaled row kk is
-// written one step later, when no thread reads it any more.  The tile is
-// replaced in memory by (strict lower of Li) + (upper of Ui).
-template <class CT>
-__device__ void inv_diag_tile(CT *__restrict__ dk, CT (*Dl)[33], CT (*Li)[33], CT (*Ui)[33]) {
+__device__ void lu_inv_diag_block(CT *__restrict__ dk, CT (*Dl)[33], CT (*Li)[33], CT (*Ui)[33], int *status) {
   constexpr int T = 32;
   const int tid = threadIdx.x;
   for (int e = tid; e < T * T; e += 256) {
@@ -874,34 +849,48 @@ __device__ void inv_diag_tile(CT *__restrict__ dk, CT (*Dl)[33], CT (*Li)[33], C
     Ui[i][j] = (i == j) ? (CT)1 : (CT)0;
   }
   __syncthreads();
-  for (int t = 0; t < T; ++t) {
-    const int k = t, kk = T - 1 - t;
-    const int nl = (T - 1 - k) * (k + 1);
-    for (int e = tid; e < nl; e += 256) {
+  for (int k = 0; k < T; ++k) {
+    const CT piv = Dl[k][k];
+    if (tid == 0 && (!isfinite((double)piv) || fabs((double)piv) < 1e-300)) atomicOr(status, 1);
+    const CT rp = (CT)1 / piv;
+    const int w = T - 1 - k;
+    for (int e = tid; e < w * w; e += 256) {
+      const int i = k + 1 + e / w, j = k + 1 + e % w;
+      Dl[i][j] -= (Dl[i][k] * rp) * Dl[k][j];
+    }
+    const int nx = w * (k + 1);
+    for (int e = tid; e < nx; e += 256) {
       const int i = k + 1 + e / (k + 1), j = e % (k + 1);
-      Li[i][j] -= Dl[i][k] * Li[k][j];
+      Li[i][j] -= (Dl[i][k] * rp) * Li[k][j];
+      Ui[i][j] -= Dl[k][i] * (Ui[k][j] * rp);
     }
-    const CT ud = (CT)1 / Dl[kk][kk];
-    const int nu = kk * (T - kk);
-    for (int e = tid; e < nu; e += 256) {
-      const int i = e / (T - kk), j = kk + e % (T - kk);
-      Ui[i][j] -= Dl[i][kk] * (Ui[kk][j] * ud);
-    }
-    if (t > 0) {
-      const CT u1 = (CT)1 / Dl[kk + 1][kk + 1];
-      for (int j = kk + 1 + tid; j < T; j += 256) Ui[kk + 1][j] *= u1;
+    if (k > 0) {
+      const CT rq = (CT)1 / Dl[k - 1][k - 1];
+      if (tid < T - k) Dl[k + tid][k - 1] *= rq;                  // multipliers of column k - 1
+      else if (tid >= 64 && tid < 64 + k) Ui[k - 1][tid - 64] *= rq;  // row k - 1 of Z
     }
     __syncthreads();
   }
   {
-    const CT u0 = (CT)1 / Dl[0][0];
-    for (int j = tid; j < T; j += 256) Ui[0][j] *= u0;
+    const CT rq = (CT)1 / Dl[T - 1][T - 1];
+    if (tid < T) Ui[T - 1][tid] *= rq;
   }
   __syncthreads();
-  for (int e = tid; e < T * T; e += 256) {
-    const int i = e / T, j = e % T;
-    dk[e] = (i > j) ? Li[i][j] : Ui[i][j];
+  // Ui = Z^T (upper), in place through registers
+  CT zt[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int e = tid + 256 * m, i = e / T, j = e % T;
+    zt[m] = (i <= j) ? Ui[j][i] : (CT)0;
   }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int e = tid + 256 * m, i = e / T, j = e % T;
+    Ui[i][j] = zt[m];
+    dk[e] = (i > j) ? Li[i][j] : zt[m];
+  }
+  __syncthreads();
 }
 
 template <class CT>
@@ -923,19 +912,18 @@ __global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const Sub
   for (int K = 0; K < s.nt; ++K) {
     const int je = min(K + s.bu, s.nt - 1), nu = je - K;
     const int ie = min(K + s.bl, s.nt - 1);
-    // (1) wave 0 factors the diagonal tile while waves 1..3 stage the
-    // U-panel tiles A_KJ into LDS; then all waves form its inverses
-    if (wave == 0) {
-      lu_diag_wave<CT>(tile_at<T, CT>(F, s, K, s.bl), Dl, status);
-    } else {
+    // (1) stage the diagonal tile and the U-panel tiles A_KJ into LDS, then
+    // factor the diagonal tile and form its inverses in one sweep
+    {
+      CT *dk = tile_at<T, CT>(F, s, K, s.bl);
+      for (int e = tid; e < T * T; e += 256) Dl[e / T][e % T] = dk[e];
       for (int jj = 0; jj < nu; ++jj) {
         const CT *a = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
-        for (int e = tid - 64; e < T * T; e += 192) Up[jj][e / T][e % T] = a[e];
+        for (int e = tid; e < T * T; e += 256) Up[jj][e / T][e % T] = a[e];
       }
+      __syncthreads();
+      lu_inv_diag_block<CT>(dk, Dl, Li, Ui, status);
     }
-    __syncthreads();
-    inv_diag_tile<CT>(tile_at<T, CT>(F, s, K, s.bl), Dl, Li, Ui);
-    __syncthreads();
     // (2) U panel on MFMA: U_KJ = L_KK^{-1} A_KJ.  Wave w owns tiles w, w+4,
     // ..; only the owner reads a tile, so it is updated in place one tile at
     // a time (the LDS accesses of one wave are processed in order)
@@ -1057,9 +1045,9 @@ __global__ __launch_bounds__(256) void k_lu_step_diag(double *__restrict__ F, Su
   if constexpr (T == 32) {
     __shared__ double Dl[T][T + 1], Li[T][T + 1], Ui[T][T + 1];
     double *dk = tile_at<T>(F, s, K, s.bl);
-    if ((threadIdx.x >> 6) == 0) lu_diag_wave<double>(dk, Dl, status);
+    for (int e = threadIdx.x; e < T * T; e += 256) Dl[e / T][e % T] = dk[e];
     __syncthreads();
-    inv_diag_tile<double>(dk, Dl, Li, Ui);
+    lu_inv_diag_block<double>(dk, Dl, Li, Ui, status);
   } else {
     __shared__ LuLds<T, double> L;
     lu_diag_tile<T>(tile_at<T>(F, s, K, s.bl), L, status);
