@@ -1604,7 +1604,7 @@ __host__ __device__ inline int64_t upper_packed(int K, int c, int nt) {
   return (int64_t)K * nt - (int64_t)K * (K - 1) / 2 + (c - K);
 }
 
-constexpr int INV_PF = 2;  // tile pairs loaded ahead into registers
+constexpr int INV_PF = 1;  // tile pairs loaded ahead into registers
 
 // One launch forms both inverses: block b handles tile column b / 2 of X
 // (even b) or column nt - 1 - b / 2 of W (odd b), so the longest columns
