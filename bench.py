@@ -107,7 +107,9 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
     g_true = torch.tensor(si.bump_field(cfg.xy, seed=7), device="cuda")
     prob.set_beta_field(g_true)
     u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
+    log(f"[bench] adjoint: {cfg.name}, {steps} steps; truth run")
     truth = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=every, **kw)
+    log("[bench] adjoint: timed forward record")
     prob.set_beta_field(torch.ones(cfg.n, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -115,6 +117,7 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
     counts = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=every, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"[bench] adjoint: forward {t1 - t0:.2f} s; reverse sweep")
     grad_g, grad_nu, st = sk.adjoint(prob, pc, 2 * (counts - truth), rtol=1e-8)
     torch.cuda.synchronize()
     t2 = time.perf_counter()

@@ -724,7 +724,17 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
         any_act = true;
     }
     if (!any_act) break;
-    if (k >= nopts->max_it) fail(SEIRD_ERR_NOT_CONVERGED, "Newton did not converge");
+    if (k >= nopts->max_it) {
+      std::string msg = "Newton did not converge in " + std::to_string(nopts->max_it) + " iterations";
+      for (int s = 0; s < S; ++s) {
+        if (!act[s]) continue;
+        msg += where(s) + " (scaled residuals";
+        for (int i = std::max(0, k - 4); i <= k; ++i) msg += " " + std::to_string(stats[s].res_hist[i]);
+        msg += ", tolerance " + std::to_string(nopts->tol) + ")";
+        break;
+      }
+      fail(SEIRD_ERR_NOT_CONVERGED, msg);
+    }
     t0 = clk::now();
     launch_jacobian(p->md, p->P, p->gfield, u, dt, diag, off, st);
     HIPCHECK(hipStreamSynchronize(st));
