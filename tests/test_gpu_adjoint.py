@@ -1,6 +1,6 @@
 """GPU discrete adjoint against the oracle's adjoint and against central
-finite differences of GPU forward runs (the spec check: h = 1e-6,
-random directions, 1e-5 relative)."""
+finite differences of GPU forward runs (h = 1e-6, random directions,
+1e-5 relative)."""
 import numpy as np
 import pytest
 
