@@ -67,13 +67,28 @@ __device__ inline void load5(const double *p, double v[5]) {
   for (int c = 0; c < 5; ++c) v[c] = p[c];
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+// Node-indexed kernels remap the hardware block index so that every XCD
+// gets one contiguous range of node blocks: neighbouring nodes (whose
+// values the gathers share) then meet in the same L2.  A bijection on
+// [0, nb) whatever the dispatch order.
+constexpr int N_XCD = 8;
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b % N_XCD, idx = b / N_XCD;
+  const int64_t per = nb / N_XCD, rem = nb % N_XCD;
+  return x * per + (x < rem ? x : rem) + idx;
+}
+__device__ inline int64_t xcd_thread() {
+  return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+
 // ----------------------------------------------------------------------
 // residual: one thread per node
 // ----------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_residual(MeshDev m, ParamsDev P0, const double *__restrict__ gfield,
                                                   const double *__restrict__ u, const double *__restrict__ up,
                                                   double dt, const double *__restrict__ src, double *__restrict__ F) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = xcd_thread();
   if (i >= m.n) return;
   const ParamsDev P = m.inst ? m.Pinst[m.inst[i]] : P0;
   double ui[5];
@@ -112,7 +127,7 @@ __global__ __launch_bounds__(256) void k_residual(MeshDev m, ParamsDev P0, const
 __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const double *__restrict__ gfield,
                                                   const double *__restrict__ u, double dt, double *__restrict__ diag,
                                                   double *__restrict__ off) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = xcd_thread();
   if (i >= m.n) return;
   const ParamsDev P = m.inst ? m.Pinst[m.inst[i]] : P0;
   for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s)
@@ -162,7 +177,7 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
 __global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restrict__ diag,
                                               const double *__restrict__ off, const double *__restrict__ x,
                                               const double *__restrict__ b, double *__restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = xcd_thread();
   if (i >= m.n) return;
   double xi[5], acc[5];
   load5(x + 5 * i, xi);
@@ -191,7 +206,7 @@ __global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restric
 __global__ __launch_bounds__(256) void k_spmv_t(MeshDev m, const double *__restrict__ diag,
                                                 const double *__restrict__ off, const double *__restrict__ x,
                                                 const double *__restrict__ b, double *__restrict__ y) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = xcd_thread();
   if (j >= m.n) return;
   double xj[5], acc[5];
   load5(x + 5 * j, xj);
