@@ -1251,7 +1251,109 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
   // gather the right-hand side R_i r (D_i R_i r when transposed) into ybuf
   for (int l = tid; l < s.n_loc; l += NTHR) ybuf[yo + l] = rhs(l);
   __syncthreads();
-  if constexpr (!TRANS) {
+  constexpr bool XPF = (SOLVE_BMAX + 1) * PER * (((int)sizeof(FT) + 3) / 4) <= 40;
+  if constexpr (!TRANS && XPF) {
+    const int i = tid / G, g = tid % G;
+    // A block row's first chunk of off-diagonal tiles and its diagonal tile,
+    // in registers.  When two such sets fit the register budget, the next
+    // row's set is loaded while the current row computes (its loads do not
+    // depend on the solution); further chunks of a wide band are loaded in
+    // the row itself.  The summation order is the same either way.
+    struct RowRegs {
+      FT buf[SOLVE_BMAX][PER];
+      FT dv[PER];
+    };
+    auto load_row = [&](int K, int c0, int c1, RowRegs &R) {  // off-diagonal tile columns c0 .. c1
+      load_chunk<FT, PER>(tile(K, s.bl) + i * T + g * PER, R.dv);
+#pragma unroll
+      for (int t = 0; t < SOLVE_BMAX; ++t)
+        if (c0 + t <= c1) load_chunk<FT, PER>(tile(K, c0 + t - K + s.bl) + i * T + g * PER, R.buf[t]);
+    };
+    // sum over the off-diagonal tile columns c0 .. c1 of row K (first chunk
+    // from R) against the ring
+    auto off_sum = [&](int K, int c0, int c1, const RowRegs &R) {
+      double a = 0.0;
+#pragma unroll
+      for (int t = 0; t < SOLVE_BMAX; ++t)
+        if (c0 + t <= c1) {
+          const double *xr = ring[(c0 + t) % RING];
+#pragma unroll
+          for (int m = 0; m < PER; ++m) a += from_ft<FT>(R.buf[t][m]) * xr[g * PER + m];
+        }
+      for (int C0 = c0 + SOLVE_BMAX; C0 <= c1; C0 += SOLVE_BMAX) {
+        FT buf[SOLVE_BMAX][PER];
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (C0 + t <= c1) load_chunk<FT, PER>(tile(K, C0 + t - K + s.bl) + i * T + g * PER, buf[t]);
+#pragma unroll
+        for (int t = 0; t < SOLVE_BMAX; ++t)
+          if (C0 + t <= c1) {
+            const double *xr = ring[(C0 + t) % RING];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g * PER + m];
+          }
+      }
+      return a;
+    };
+    RowRegs cur, nxt;
+    // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P), P = max(0, K - bl) .. K - 1
+    if (s.nt > 0) load_row(0, 0, -1, cur);
+    for (int K = 0; K < s.nt; ++K) {
+      if (K + 1 < s.nt) load_row(K + 1, max(0, K + 1 - s.bl), K, nxt);
+      const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
+      double a = off_sum(K, max(0, K - s.bl), K - 1, cur);
+      a = group_sum<G>(a);
+      if (g == 0) acc_s[i] = bv - a;
+      lds_barrier();
+      double y = 0.0;
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = g * PER + m;
+        if (j < i) y += from_ft<FT>(cur.dv[m]) * acc_s[j];
+      }
+      y = group_sum<G>(y);
+      if (g == 0) {
+        const double v = acc_s[i] + y;
+        ring[K % RING][i] = v;
+        if (K * T + i < s.n_loc) ybuf[yo + K * T + i] = v;
+      }
+      lds_barrier();
+      cur = nxt;
+    }
+    // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J), J = K + 1 .. min(K + bu, nt - 1)
+    if (s.nt > 0) load_row(s.nt - 1, s.nt, s.nt - 1, cur);
+    for (int K = s.nt - 1; K >= 0; --K) {
+      if (K > 0) load_row(K - 1, K, min(K - 1 + s.bu, s.nt - 1), nxt);
+      const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
+      double a = off_sum(K, K + 1, min(K + s.bu, s.nt - 1), cur);
+      a = group_sum<G>(a);
+      if (g == 0) acc_s[i] = bv - a;
+      lds_barrier();
+      double y = 0.0;
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = g * PER + m;
+        if (j >= i) y += from_ft<FT>(cur.dv[m]) * acc_s[j];
+      }
+      y = group_sum<G>(y);
+      if (g == 0) {
+        ring[K % RING][i] = y;
+        const int l = K * T + i;
+        if (l < s.n_loc) {
+          if (local) {
+            if (owned[s.l2g_off + l]) {
+              const int32_t gi = l2g[s.l2g_off + l];
+              z[gi] = add ? z[gi] + y : y;
+            }
+          } else {
+            z[l] = add ? z[l] + y : y;
+          }
+        }
+      }
+      lds_barrier();
+      cur = nxt;
+    }
+  } else if constexpr (!TRANS) {
     const int i = tid / G, g = tid % G;
     // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P)
     for (int K = 0; K < s.nt; ++K) {
