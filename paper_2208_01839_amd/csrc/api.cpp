@@ -994,8 +994,10 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
       fail(SEIRD_ERR_ARG, "subdomain bandwidth above 16 tiles; use more subdomains");
     pc->sub_float = (T == 32 && ph.prec > 0);
     const size_t csz = pc->sub_float ? 4 : 8;
-    // factorisation LDS: 5 staging tiles (tile 32; 4 for tile 16) + the U panel
-    const size_t lu_lds = (T == 32 ? 5 : 4) * (size_t)T * (T + 1) * csz + (size_t)pc->max_bu * T * (T + 1) * csz;
+    // factorisation LDS: tile 32 three tiles (its U panel stays in
+    // registers); tile 16 four staging tiles and the U panel
+    const size_t lu_lds = T == 32 ? 3 * (size_t)T * (T + 1) * csz
+                                  : 4 * (size_t)T * (T + 1) * csz + (size_t)pc->max_bu * T * (T + 1) * csz;
     if (lu_lds > p->lds_limit)
       fail(SEIRD_ERR_ARG, "subdomain bandwidth too large for the LDS of this device (" + std::to_string(lu_lds) +
                               " > " + std::to_string(p->lds_limit) + " bytes); use more subdomains or tile 16");

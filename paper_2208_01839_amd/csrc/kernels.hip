@@ -841,145 +841,175 @@ struct Mfma<float> {
   __device__ static inline int row(int lk, int v) { return 4 * lk + v; }
 };
 
-// LU without pivoting of the tile in Dl and the explicit inverses of both
-// factors in one forward sweep of 32 steps (all 256 threads, one barrier
-// per step).  Step k uses the unscaled column k, l_ik = a_ik / a_kk formed
-// on the fly, and row k of U (final at step k):
+// LU without pivoting of a 32x32 tile and the explicit inverses of both
+// factors in one forward sweep of 32 steps.  Step k uses the unscaled
+// column k, l_ik = a_ik / a_kk formed on the fly, and row k of U (final at
+// step k):
 //   trailing update   a_ij -= l_ik a_kj                 (i, j > k)
 //   X = L^{-1}         X_ij -= l_ik X_kj                (i > k, j <= k)
 //   Z = (U^T)^{-1}     Z_ij -= U_ki (Z_kj / U_kk)       (i > k, j <= k)
-// (the last two are forward elimination applied to the identity); the
-// multipliers of column k - 1 and the row k - 1 of Z are scaled one step
-// later, when no thread reads them.  Z lives in Ui and is transposed in
-// place at the end (Ui = Z^T = U^{-1}); the tile is replaced in memory by
-// (strict lower of L^{-1}) + (upper of U^{-1}).  Raises *status on a zero or
-// nonfinite pivot.
-template <class CT>
-__device__ void lu_inv_diag_block(CT *__restrict__ dk, CT (*Dl)[33], CT (*Li)[33], CT (*Ui)[33], int *status) {
-  constexpr int T = 32;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < T * T; e += 256) {
-    const int i = e / T, j = e % T;
-    Li[i][j] = (i == j) ? (CT)1 : (CT)0;
-    Ui[i][j] = (i == j) ? (CT)1 : (CT)0;
+// (the last two are forward elimination applied to the identity), and
+// U^{-1} = Z^T.  The tile is held in registers: thread (ti, tj) =
+// (tid / 32, tid % 32) owns column tj of rows ti + (NT / 32) h of A, X and
+// Z, and each step only row k of A, X, Z and column k of A pass through LDS
+// (double-buffered by step parity, one barrier per step).  dk: the tile in
+// global memory (read, then replaced by the strict lower of L^{-1} and the
+// upper of U^{-1}); Li, Ui: LDS tiles that receive L^{-1} (dense unit lower)
+// and U^{-1} (dense upper).  Raises *status on a zero or nonfinite pivot.
+template <class CT, int NT>
+__device__ void lu_inv_diag_regs(CT *__restrict__ dk, CT (*Li)[33], CT (*Ui)[33], int *status) {
+  constexpr int T = 32, RS = NT / T, R = T / RS;
+  static_assert(NT % T == 0 && R >= 1 && R <= 4, "workgroup size");
+  __shared__ CT pub[2][4][T];  // [parity][row A, row X, row Z, column A]
+  const int tid = threadIdx.x, ti = tid / T, tj = tid % T;
+  CT a[R], x[R], z[R];
+#pragma unroll
+  for (int h = 0; h < R; ++h) {
+    const int i = ti + RS * h;
+    a[h] = dk[i * T + tj];
+    x[h] = (i == tj) ? (CT)1 : (CT)0;
+    z[h] = x[h];
   }
+  auto publish = [&](int kn, int p) {
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+      const int i = ti + RS * h;
+      if (i == kn) {
+        pub[p][0][tj] = a[h];
+        pub[p][1][tj] = x[h];
+        pub[p][2][tj] = z[h];
+      }
+      if (tj == kn) pub[p][3][i] = a[h];
+    }
+  };
+  publish(0, 0);
   __syncthreads();
   for (int k = 0; k < T; ++k) {
-    const CT piv = Dl[k][k];
+    const int p = k & 1;
+    // every LDS operand of the step is read up front (one wait); the
+    // updates below are selects, not branches
+    const CT piv = pub[p][0][k];
+    const CT akj = pub[p][0][tj], xkj = pub[p][1][tj], zkj = pub[p][2][tj];
+    CT cik[R], uki[R];
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+      cik[h] = pub[p][3][ti + RS * h];
+      uki[h] = pub[p][0][ti + RS * h];
+    }
     if (tid == 0 && (!isfinite((double)piv) || fabs((double)piv) < 1e-300)) atomicOr(status, 1);
     const CT rp = (CT)1 / piv;
-    const int w = T - 1 - k;
-    for (int e = tid; e < w * w; e += 256) {
-      const int i = k + 1 + e / w, j = k + 1 + e % w;
-      Dl[i][j] -= (Dl[i][k] * rp) * Dl[k][j];
+    const CT zs = zkj * rp;
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+      const int i = ti + RS * h;
+      const bool below = i > k, left = tj <= k;
+      const CT l = cik[h] * rp;
+      const CT an = a[h] - l * akj, xn = x[h] - l * xkj, zn = z[h] - uki[h] * zs;
+      a[h] = below ? (left ? (tj == k ? l : a[h]) : an) : a[h];
+      x[h] = (below && left) ? xn : x[h];
+      z[h] = (below && left) ? zn : ((i == k && left) ? z[h] * rp : z[h]);  // row k of Z is final
     }
-    const int nx = w * (k + 1);
-    for (int e = tid; e < nx; e += 256) {
-      const int i = k + 1 + e / (k + 1), j = e % (k + 1);
-      Li[i][j] -= (Dl[i][k] * rp) * Li[k][j];
-      Ui[i][j] -= Dl[k][i] * (Ui[k][j] * rp);
-    }
-    if (k > 0) {
-      const CT rq = (CT)1 / Dl[k - 1][k - 1];
-      if (tid < T - k) Dl[k + tid][k - 1] *= rq;                  // multipliers of column k - 1
-      else if (tid >= 64 && tid < 64 + k) Ui[k - 1][tid - 64] *= rq;  // row k - 1 of Z
-    }
+    if (k + 1 < T) publish(k + 1, p ^ 1);
     __syncthreads();
   }
-  {
-    const CT rq = (CT)1 / Dl[T - 1][T - 1];
-    if (tid < T) Ui[T - 1][tid] *= rq;
-  }
-  __syncthreads();
-  // Ui = Z^T (upper), in place through registers
-  CT zt[4];
+  // Li = X (lower), Ui = Z^T (upper); then the tile from LDS, coalesced
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int e = tid + 256 * m, i = e / T, j = e % T;
-    zt[m] = (i <= j) ? Ui[j][i] : (CT)0;
+  for (int h = 0; h < R; ++h) {
+    const int i = ti + RS * h;
+    Li[i][tj] = (i >= tj) ? x[h] : (CT)0;
+    Ui[tj][i] = (i >= tj) ? z[h] : (CT)0;
   }
   __syncthreads();
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int e = tid + 256 * m, i = e / T, j = e % T;
-    Ui[i][j] = zt[m];
-    dk[e] = (i > j) ? Li[i][j] : zt[m];
+  for (int e = tid; e < T * T; e += NT) {
+    const int i = e / T, j = e % T;
+    dk[e] = (i > j) ? Li[i][j] : Ui[i][j];
   }
-  __syncthreads();
 }
 
-template <class CT>
-__global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const SubInfo *__restrict__ subs,
-                                                   const int32_t *__restrict__ order, int *status) {
-  constexpr int T = 32;
+// Banded LU of one subdomain per workgroup (tile 32, NW waves), right-
+// looking by block rows.  Step K:
+//   (1) the diagonal tile is factored and both factors inverted (register
+//       sweep above);
+//   (2) U panel U_KJ = L_KK^{-1} A_KJ on MFMA.  Wave w owns the panel tiles
+//       jj = w + NW q (q < QW) and keeps them in registers for the whole
+//       step: the accumulator layout of a 16x16 MFMA result is the B-operand
+//       layout of a later product whose k index runs over the result rows
+//       (in the accumulator's own row order), so U never goes through LDS;
+//   (3) for each block row I below: L_IK = A_IK U_KK^{-1} (four waves, one
+//       16x16 quadrant each, A_IK read straight into the A-operand layout),
+//       staged in one of two LDS buffers (one barrier per row), and the
+//       C strip C_IJ -= L_IK U_KJ of the wave's own tiles on MFMA.
+// LDS: U_KK^{-1} and the two row buffers, the second of which holds
+// L_KK^{-1} during (1)-(2).
+template <class CT, int NW, int QW>
+__global__ __launch_bounds__(64 * NW) void k_band_lu32(CT *__restrict__ F, const SubInfo *__restrict__ subs,
+                                                       const int32_t *__restrict__ order, int *status) {
+  constexpr int T = 32, NT = 64 * NW;
   typedef typename Mfma<CT>::v4 v4;
-  __shared__ CT Dl[T][T + 1];  // diagonal tile being factored
-  __shared__ CT Li[T][T + 1];  // L_KK^{-1}, dense unit lower
-  __shared__ CT Ui[T][T + 1];  // U_KK^{-1}, dense upper
-  __shared__ CT Sa[T][T + 1];  // A_IK
-  __shared__ CT Sb[T][T + 1];  // L_IK = A_IK U_KK^{-1}
-  extern __shared__ __align__(16) unsigned char up_raw[];
-  CT(*Up)[T][T + 1] = reinterpret_cast<CT(*)[T][T + 1]>(up_raw);  // U panel of the step
+  __shared__ CT Ui[T][T + 1];     // U_KK^{-1}, dense upper
+  __shared__ CT Sx[2][T][T + 1];  // L_KK^{-1} (in Sx[1]) in (1)-(2); L_IK buffers in (3)
   const SubInfo s = subs[order[blockIdx.x]];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int qi = wave >> 1, qj = wave & 1;
+  const int qi = (wave >> 1) & 1, qj = wave & 1;
   for (int K = 0; K < s.nt; ++K) {
     const int je = min(K + s.bu, s.nt - 1), nu = je - K;
     const int ie = min(K + s.bl, s.nt - 1);
-    // (1) stage the diagonal tile and the U-panel tiles A_KJ into LDS, then
-    // factor the diagonal tile and form its inverses in one sweep
-    {
-      CT *dk = tile_at<T, CT>(F, s, K, s.bl);
-      for (int e = tid; e < T * T; e += 256) Dl[e / T][e % T] = dk[e];
-      for (int jj = 0; jj < nu; ++jj) {
-        const CT *a = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
-        for (int e = tid; e < T * T; e += 256) Up[jj][e / T][e % T] = a[e];
-      }
-      __syncthreads();
-      lu_inv_diag_block<CT>(dk, Dl, Li, Ui, status);
-    }
-    // (2) U panel on MFMA: U_KJ = L_KK^{-1} A_KJ.  Wave w owns tiles w, w+4,
-    // ..; only the owner reads a tile, so it is updated in place one tile at
-    // a time (the LDS accesses of one wave are processed in order)
-#pragma unroll 1
-    for (int jj = wave; jj < nu; jj += 4) {
-      v4 acc[2][2];
+    // (1) diagonal tile: LU and both inverses in one sweep
+    lu_inv_diag_regs<CT, NT>(tile_at<T, CT>(F, s, K, s.bl), Sx[1], Ui, status);
+    // (2) the wave's U-panel tiles, kept as B operands: ub[q][bj][4 bi + v]
+    // holds U_KJ[16 bi + row(lk, v)][16 bj + lr]
+    CT ub[QW][2][8];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+    for (int q = 0; q < QW; ++q) {
+      const int jj = wave + NW * q;
+      if (jj < nu) {
+        CT *g = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
+        CT bl[8][2];
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4{0, 0, 0, 0};
+        for (int m = 0; m < 8; ++m)
 #pragma unroll
-      for (int k0 = 0; k0 < T; k0 += 4) {
-        const CT a0 = Li[lr][k0 + lk], a1 = Li[16 + lr][k0 + lk];
-        const CT b0 = Up[jj][k0 + lk][lr], b1 = Up[jj][k0 + lk][16 + lr];
-        acc[0][0] = Mfma<CT>::op(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<CT>::op(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<CT>::op(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<CT>::op(a1, b1, acc[1][1]);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      CT *g = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
+          for (int bj = 0; bj < 2; ++bj) bl[m][bj] = g[(4 * m + lk) * T + 16 * bj + lr];
+        v4 acc[2][2];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+          for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4{0, 0, 0, 0};
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = 16 * bi + Mfma<CT>::row(lk, v), jc = 16 * bj + lr;
-            Up[jj][i][jc] = acc[bi][bj][v];
-            g[i * T + jc] = acc[bi][bj][v];
+        for (int m = 0; m < 8; ++m) {
+          const CT a0 = Sx[1][lr][4 * m + lk], a1 = Sx[1][16 + lr][4 * m + lk];
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            acc[0][bj] = Mfma<CT>::op(a0, bl[m][bj], acc[0][bj]);
+            acc[1][bj] = Mfma<CT>::op(a1, bl[m][bj], acc[1][bj]);
           }
-    }
-    // (3) block rows below: L_IK = A_IK U_KK^{-1}, then C_I* -= L_IK U_K*
-    for (int I = K + 1; I <= ie; ++I) {
-      // C strip into accumulators and A_IK into registers (all loads in flight)
-      v4 acc[4][2][2];
+        }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int jj = wave + 4 * q;
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              ub[q][bj][4 * bi + v] = acc[bi][bj][v];
+              g[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr] = acc[bi][bj][v];
+            }
+      }
+    }
+    // (3) block rows below
+    for (int I = K + 1; I <= ie; ++I) {
+      const int buf = (I - K - 1) & 1;
+      CT *aik = tile_at<T, CT>(F, s, I, K - I + s.bl);
+      // A_IK quadrant rows in the A-operand layout (issued first: the
+      // quadrant product waits on these loads only)
+      CT ra[8];
+      if (wave < 4) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) ra[m] = aik[(16 * qi + lr) * T + 4 * m + lk];
+      }
+      v4 acc[QW][2][2];
+#pragma unroll
+      for (int q = 0; q < QW; ++q) {
+        const int jj = wave + NW * q;
         if (jj < nu) {
           const CT *c = tile_at<T, CT>(F, s, I, K + 1 + jj - I + s.bl);
 #pragma unroll
@@ -990,46 +1020,39 @@ __global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const Sub
               for (int v = 0; v < 4; ++v) acc[q][bi][bj][v] = c[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr];
         }
       }
-      CT *aik = tile_at<T, CT>(F, s, I, K - I + s.bl);
-      CT ra[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) ra[m] = aik[tid + 256 * m];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int e = tid + 256 * m;
-        Sa[e / T][e % T] = ra[m];
-      }
-      __syncthreads();  // Sa staged (and the U panel written, for the first I)
-      // quadrant (qi, qj) of L_IK on MFMA
       v4 l = {0, 0, 0, 0};
+      if (wave < 4) {
 #pragma unroll
-      for (int k0 = 0; k0 < T; k0 += 4) l = Mfma<CT>::op(Sa[16 * qi + lr][k0 + lk], Ui[k0 + lk][16 * qj + lr], l);
+        for (int m = 0; m < 8; ++m) l = Mfma<CT>::op(ra[m], Ui[4 * m + lk][16 * qj + lr], l);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * qi + Mfma<CT>::row(lk, v), jc = 16 * qj + lr;
-        Sb[i][jc] = l[v];
-        aik[i * T + jc] = l[v];
+        for (int v = 0; v < 4; ++v) Sx[buf][16 * qi + Mfma<CT>::row(lk, v)][16 * qj + lr] = l[v];
       }
-      __syncthreads();  // L_IK staged
-      // C -= L_IK U_KJ on MFMA
+      __syncthreads();  // L_IK staged; every wave has read A_IK
+      if (wave < 4) {
 #pragma unroll
-      for (int k0 = 0; k0 < T; k0 += 4) {
-        const CT a0 = -Sb[lr][k0 + lk], a1 = -Sb[16 + lr][k0 + lk];
+        for (int v = 0; v < 4; ++v) aik[(16 * qi + Mfma<CT>::row(lk, v)) * T + 16 * qj + lr] = l[v];
+      }
+      // C_IJ -= L_IK U_KJ; the k index of step (bi, v) is 16 bi + row(lk, v)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int jj = wave + 4 * q;
-          if (jj < nu) {
-            const CT b0 = Up[jj][k0 + lk][lr], b1 = Up[jj][k0 + lk][16 + lr];
-            acc[q][0][0] = Mfma<CT>::op(a0, b0, acc[q][0][0]);
-            acc[q][0][1] = Mfma<CT>::op(a0, b1, acc[q][0][1]);
-            acc[q][1][0] = Mfma<CT>::op(a1, b0, acc[q][1][0]);
-            acc[q][1][1] = Mfma<CT>::op(a1, b1, acc[q][1][1]);
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int kc = 16 * bi + Mfma<CT>::row(lk, v);
+          const CT a0 = -Sx[buf][lr][kc], a1 = -Sx[buf][16 + lr][kc];
+#pragma unroll
+          for (int q = 0; q < QW; ++q) {
+            const int jj = wave + NW * q;
+            if (jj < nu) {
+              acc[q][0][0] = Mfma<CT>::op(a0, ub[q][0][4 * bi + v], acc[q][0][0]);
+              acc[q][0][1] = Mfma<CT>::op(a0, ub[q][1][4 * bi + v], acc[q][0][1]);
+              acc[q][1][0] = Mfma<CT>::op(a1, ub[q][0][4 * bi + v], acc[q][1][0]);
+              acc[q][1][1] = Mfma<CT>::op(a1, ub[q][1][4 * bi + v], acc[q][1][1]);
+            }
           }
         }
-      }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int jj = wave + 4 * q;
+      for (int q = 0; q < QW; ++q) {
+        const int jj = wave + NW * q;
         if (jj < nu) {
           CT *c = tile_at<T, CT>(F, s, I, K + 1 + jj - I + s.bl);
 #pragma unroll
@@ -1041,8 +1064,8 @@ __global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const Sub
         }
       }
     }
-    // the next step's diagonal tile, U panel and C strips were written by
-    // other waves of this workgroup: make the stores visible before reuse
+    // the next step's diagonal tile and U panel were written by other waves
+    // of this workgroup: make the stores visible before they are read
     __threadfence_block();
     __syncthreads();
   }
@@ -1055,21 +1078,22 @@ __global__ __launch_bounds__(256) void k_band_lu32(CT *__restrict__ F, const Sub
 // 25 KB of LDS so that they fit beside a subdomain-factorisation workgroup
 // on the same compute unit (the coarse chain runs on its own stream while
 // the subdomains are factored).
+// The coarse step kernels run beside the subdomain factorisation, which
+// leaves about 64 VGPRs per SIMD lane free: they are held to 64 (8 waves
+// per SIMD) so that they fit there.
 template <int T>
-__global__ __launch_bounds__(256) void k_lu_step_diag(double *__restrict__ F, SubInfo s, int K, int *status) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_lu_step_diag(
+    double *__restrict__ F, SubInfo s, int K, int *status) {
   if constexpr (T == 32) {
-    __shared__ double Dl[T][T + 1], Li[T][T + 1], Ui[T][T + 1];
-    double *dk = tile_at<T>(F, s, K, s.bl);
-    for (int e = threadIdx.x; e < T * T; e += 256) Dl[e / T][e % T] = dk[e];
-    __syncthreads();
-    lu_inv_diag_block<double>(dk, Dl, Li, Ui, status);
+    __shared__ double Li[T][T + 1], Ui[T][T + 1];
+    lu_inv_diag_regs<double, 256>(tile_at<T>(F, s, K, s.bl), Li, Ui, status);
   } else {
     __shared__ LuLds<T, double> L;
     lu_diag_tile<T>(tile_at<T>(F, s, K, s.bl), L, status);
   }
 }
 template <int T>
-__global__ __launch_bounds__(256) void k_lu_step_panel(double *__restrict__ F, SubInfo s, int K) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_lu_step_panel(double *__restrict__ F, SubInfo s, int K) {
   const int b = blockIdx.x;
   const bool lower = b < s.bl;
   const int IJ = K + 1 + (lower ? b : b - s.bl);
@@ -1103,7 +1127,7 @@ __global__ __launch_bounds__(256) void k_lu_step_panel(double *__restrict__ F, S
   }
 }
 template <int T>
-__global__ __launch_bounds__(256) void k_lu_step_schur(double *__restrict__ F, SubInfo s, int K) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_lu_step_schur(double *__restrict__ F, SubInfo s, int K) {
   __shared__ double Sa[T][T + 1], Sb[T][T + 1];
   const int I = K + 1 + blockIdx.x / s.bu, J = K + 1 + blockIdx.x % s.bu;
   if (I >= s.nt || J >= s.nt) return;
@@ -1194,6 +1218,9 @@ constexpr int RING = 32;  // block rows of the local vector kept in LDS (> bl, b
 template <int T, class FT, int NTHR>
 constexpr int solve_bmax() {
   if (T == 32 && NTHR == 256) return sizeof(FT) == 8 ? 6 : 8;
+  // float64 at 512 threads: 8 tiles (a typical band), so that two block
+  // rows' first chunks fit the cross-row prefetch budget
+  if (T == 32 && NTHR == 512 && sizeof(FT) == 8) return 8;
   constexpr int per = T * T / NTHR;  // tile elements per lane
   constexpr int regs = per * (sizeof(FT) >= 4 ? (int)sizeof(FT) / 4 : 1);
   constexpr int b = 48 / regs;
@@ -2102,9 +2129,20 @@ static void coarse_factor_t(const FactorLaunch &fl, const double *diag, const do
   }
 }
 
-// LDS of a factorisation workgroup (static + dynamic) above which only one
-// fits on a 160 KB compute unit
-constexpr size_t FACTOR_LDS_ONE_PER_CU = 80 * 1024 + 256;
+// Subdomain factorisation launch (waves x panel tiles per wave): 4 x 2 when
+// every U panel fits; else 8 x 2, except float32 beside a coarse chain,
+// where 4 x 3 (two workgroups of 220 VGPRs per compute unit) leaves the
+// 64 VGPRs per SIMD lane that the coarse kernels need, while two 8 x 2
+// workgroups of 128 would fill the register file.
+template <class CT>
+static void band_lu32(const FactorLaunch &fl, CT *F, hipStream_t st) {
+  if (fl.max_bu <= 8)
+    hipLaunchKernelGGL((k_band_lu32<CT, 4, 2>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.order, fl.status);
+  else if (sizeof(CT) == 4 && fl.coarse && fl.max_bu <= 12)
+    hipLaunchKernelGGL((k_band_lu32<CT, 4, 3>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.order, fl.status);
+  else
+    hipLaunchKernelGGL((k_band_lu32<CT, 8, 2>), dim3(fl.nsub), dim3(512), 0, st, F, fl.subs, fl.order, fl.status);
+}
 
 void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st,
                           hipStream_t st_coarse) {
@@ -2115,18 +2153,10 @@ void launch_setup_factors(const FactorLaunch &fl, const double *diag, const doub
     if (fl.tile == 32) {
       if (fl.sub_float) {
         extract_t<32, float>(fl, (float *)fl.Fs, diag, off, st);
-        size_t lds = (size_t)std::max(fl.max_bu, 1) * 32 * 33 * sizeof(float);
-        // with a coarse chain beside it, hold the float32 factorisation to
-        // one workgroup per compute unit (by its LDS request) so that the
-        // coarse kernels find room on every compute unit
-        if (fl.coarse) lds = std::max(lds, FACTOR_LDS_ONE_PER_CU - 5 * 32 * 33 * sizeof(float));
-        hipLaunchKernelGGL(k_band_lu32<float>, dim3(fl.nsub), dim3(256), lds, st, (float *)fl.Fs, fl.subs, fl.order,
-                           fl.status);
+        band_lu32<float>(fl, (float *)fl.Fs, st);
       } else {
         extract_t<32, double>(fl, (double *)fl.Fs, diag, off, st);
-        const size_t lds = (size_t)std::max(fl.max_bu, 1) * 32 * 33 * sizeof(double);
-        hipLaunchKernelGGL(k_band_lu32<double>, dim3(fl.nsub), dim3(256), lds, st, (double *)fl.Fs, fl.subs,
-                           fl.order, fl.status);
+        band_lu32<double>(fl, (double *)fl.Fs, st);
       }
     } else {
       extract_t<16, double>(fl, (double *)fl.Fs, diag, off, st);
