@@ -26,9 +26,9 @@ import time
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the subdomain-solve kernel from rocprofv3 counters
 # (FETCH_SIZE and WRITE_SIZE, copy-calibrated) of the current kernel, by
-# (factor precision, tile); the table and commands are in
+# (factor precision, tile, solve threads); the table and commands are in
 # profiles/traffic_realistic_fp64.md.  Legs without a measurement report null.
-MEASURED_SOLVE_TRAFFIC = {(0, 32): (28.355 + 0.178) * 1e9}
+MEASURED_SOLVE_TRAFFIC = {(0, 32, 512): (28.338 + 0.180) * 1e9}
 
 
 def log(*a):
@@ -312,7 +312,7 @@ def main():
         roofline = {"bound": "hbm", "kernel": "k_band_solve (subdomain solves of one RAS apply)",
                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": achieved / PEAK_HBM_GBS,
-                    "traffic": MEASURED_SOLVE_TRAFFIC.get((args.prec, res["tile"])),
+                    "traffic": MEASURED_SOLVE_TRAFFIC.get((args.prec, res["tile"], res["solve_threads"])),
                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     "avg_launch_ms": ras_ms / ras_n, "launches": ras_n,
                     "bytes_per_launch": ras_bytes}
