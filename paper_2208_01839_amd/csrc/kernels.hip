@@ -1161,6 +1161,99 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   }
 }
 
+// One launch per block column K of the coarse factorisation (tile 32),
+// replacing the panel and Schur launches and the next diagonal launch.
+// Blocks [0, bl bu): Schur tile (I, J) = (K + 1 + b / bu, K + 1 + b % bu)
+// forms L_IK = A_IK U_KK^{-1} and U_KJ = L_KK^{-1} A_KJ itself from the
+// unmodified panel tiles (each panel tile is formed by every Schur block
+// that needs it), updates C_IJ -= L_IK U_KJ, and the block of tile
+// (K + 1, K + 1) then factors that tile.  Blocks [bl bu, bl bu + bl + bu):
+// write the panel tiles of step K - 1 in place; no block of this launch
+// reads those tiles, and their unmodified values are no longer needed.
+// Launch K = nt - 1 only writes the panels of step nt - 2; the diagonal
+// tile of step 0 is factored by k_lu_step_diag first.  Panel operands are
+// read from global memory straight into the MFMA operand layouts and the
+// diagonal inverses are masked out of the stored diagonal tile, so a block
+// needs two LDS tiles (19 KB with the sweep's row buffers) and 64 VGPRs.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_lu_step_fused(
+    double *__restrict__ F, SubInfo s, int K, int *status) {
+  constexpr int T = 32;
+  typedef Mfma<double>::v4 v4;
+  __shared__ double X0[T][T + 1], X1[T][T + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4, qi = wave >> 1, qj = wave & 1;
+  const int nschur = s.bl * s.bu;
+  const int b = blockIdx.x;
+  // stored diagonal tile of step k into X0: strict lower of L_kk^{-1},
+  // upper of U_kk^{-1}
+  auto load_diag = [&](int k) {
+    const double *dk = tile_at<T>(F, s, k, s.bl);
+    for (int e = tid; e < T * T; e += 256) X0[e / T][e % T] = dk[e];
+  };
+  auto ui = [&](int k, int j) { return k <= j ? X0[k][j] : 0.0; };                     // U_kk^{-1}
+  auto li = [&](int i, int k) { return i > k ? X0[i][k] : (i == k ? 1.0 : 0.0); };  // L_kk^{-1}
+  // quadrant (qi, qj) of A Ui (A-operand rows of A from global) or of
+  // Li A (B-operand columns of A from global)
+  auto right_ui = [&](const double *A) {
+    v4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < T; k0 += 4)
+      x = Mfma<double>::op(A[(16 * qi + lr) * T + k0 + lk], ui(k0 + lk, 16 * qj + lr), x);
+    return x;
+  };
+  auto left_li = [&](const double *A) {
+    v4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < T; k0 += 4)
+      x = Mfma<double>::op(li(16 * qi + lr, k0 + lk), A[(k0 + lk) * T + 16 * qj + lr], x);
+    return x;
+  };
+  if (b >= nschur) {
+    // panel tile of step K - 1, in place
+    const int Kp = K - 1, m = b - nschur;
+    if (Kp < 0) return;
+    const bool lower = m < s.bl;
+    const int IJ = Kp + 1 + (lower ? m : m - s.bl);
+    if (IJ >= s.nt) return;
+    double *a = lower ? tile_at<T>(F, s, IJ, Kp - IJ + s.bl) : tile_at<T>(F, s, Kp, IJ - Kp + s.bl);
+    load_diag(Kp);
+    __syncthreads();
+    const v4 x = lower ? right_ui(a) : left_li(a);
+    __syncthreads();  // every wave has read the tile
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a[(16 * qi + Mfma<double>::row(lk, v)) * T + 16 * qj + lr] = x[v];
+    return;
+  }
+  const int I = K + 1 + b / s.bu, J = K + 1 + b % s.bu;
+  if (I >= s.nt || J >= s.nt) return;
+  double *c = tile_at<T>(F, s, I, J - I + s.bl);
+  load_diag(K);
+  __syncthreads();
+  const v4 l = right_ui(tile_at<T>(F, s, I, K - I + s.bl));
+  const v4 u = left_li(tile_at<T>(F, s, K, J - K + s.bl));
+  __syncthreads();  // X0 free
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * qi + Mfma<double>::row(lk, v), j = 16 * qj + lr;
+    X0[i][j] = -l[v];
+    X1[i][j] = u[v];
+  }
+  v4 acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = c[(16 * qi + Mfma<double>::row(lk, v)) * T + 16 * qj + lr];
+  __syncthreads();
+#pragma unroll
+  for (int k0 = 0; k0 < T; k0 += 4) acc = Mfma<double>::op(X0[16 * qi + lr][k0 + lk], X1[k0 + lk][16 * qj + lr], acc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) c[(16 * qi + Mfma<double>::row(lk, v)) * T + 16 * qj + lr] = acc[v];
+  if (I == K + 1 && J == K + 1) {
+    // the next diagonal tile is final: factor it (read back by this block)
+    __threadfence_block();
+    __syncthreads();
+    lu_inv_diag_regs<double, 256>(c, X0, X1, status);
+  }
+}
+
 // ----------------------------------------------------------------------
 // Tile-band triangular solves (the subdomain apply A_i^{-1} r_i).
 // One workgroup per subdomain; the local vector x lives in LDS (dynamic)
@@ -2120,11 +2213,18 @@ static void coarse_factor_t(const FactorLaunch &fl, const double *diag, const do
   hipLaunchKernelGGL(k_galerkin<T>, dim3(nblocks(fl.gal_nblk * 64)), dim3(256), 0, st, fl.Fc, fl.cs, fl.gp, fl.gq,
                      fl.gptr, fl.gref, fl.gw, fl.gal_nblk, diag, off, fl.status);
   const SubInfo cs = fl.cs;
-  for (int K = 0; K < cs.nt; ++K) {
-    hipLaunchKernelGGL(k_lu_step_diag<T>, dim3(1), dim3(256), 0, st, fl.Fc, cs, K, fl.status);
-    if (K + 1 < cs.nt) {
-      hipLaunchKernelGGL(k_lu_step_panel<T>, dim3(cs.bl + cs.bu), dim3(256), 0, st, fl.Fc, cs, K);
-      hipLaunchKernelGGL(k_lu_step_schur<T>, dim3(cs.bl * cs.bu), dim3(256), 0, st, fl.Fc, cs, K);
+  if constexpr (T == 32) {
+    hipLaunchKernelGGL(k_lu_step_diag<T>, dim3(1), dim3(256), 0, st, fl.Fc, cs, 0, fl.status);
+    for (int K = 0; K < cs.nt; ++K)
+      hipLaunchKernelGGL(k_lu_step_fused, dim3(cs.bl * cs.bu + cs.bl + cs.bu), dim3(256), 0, st, fl.Fc, cs, K,
+                         fl.status);
+  } else {
+    for (int K = 0; K < cs.nt; ++K) {
+      hipLaunchKernelGGL(k_lu_step_diag<T>, dim3(1), dim3(256), 0, st, fl.Fc, cs, K, fl.status);
+      if (K + 1 < cs.nt) {
+        hipLaunchKernelGGL(k_lu_step_panel<T>, dim3(cs.bl + cs.bu), dim3(256), 0, st, fl.Fc, cs, K);
+        hipLaunchKernelGGL(k_lu_step_schur<T>, dim3(cs.bl * cs.bu), dim3(256), 0, st, fl.Fc, cs, K);
+      }
     }
   }
 }
