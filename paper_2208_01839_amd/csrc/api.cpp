@@ -227,6 +227,7 @@ struct seird_precond_s {
   ExtractEntry *ent_dev = nullptr;
   int32_t *l2g = nullptr;
   uint8_t *owned = nullptr;
+  int32_t *env_row = nullptr, *env_lo = nullptr;  // subdomain row tables
   int *status = nullptr;
   int64_t *g2l_ptr = nullptr;
   int32_t *g2l_idx = nullptr;
@@ -316,7 +317,8 @@ struct seird_precond_s {
       const SubInfo &q = ph.subs[i];
       int64_t owned_n = 0;
       for (int l = 0; l < q.n_loc; ++l) owned_n += ph.owned[q.l2g_off + l];
-      seg_bytes[sub_seg_host[i]] += (double)q.nt * (q.bl + q.bu + 1) * T * T * fsz +
+      const int64_t tiles = q.env_off >= 0 ? ph.env_row[q.env_off + q.nt] : (int64_t)q.nt * (q.bl + q.bu + 1);
+      seg_bytes[sub_seg_host[i]] += (double)tiles * T * T * fsz +
                                     (double)q.n_loc * (4 + 1 + 8) + (double)owned_n * 8;
     }
   }
@@ -342,6 +344,7 @@ struct seird_precond_s {
       (void)hipEventDestroy(e.second);
     }
     dev_free(Fs); dev_free(Fb); dev_free(Fc); dev_free(subs_dev); dev_free(order_dev); dev_free(ent_dev); dev_free(l2g);
+    dev_free(env_row); dev_free(env_lo);
     dev_free(owned); dev_free(status); dev_free(g2l_ptr); dev_free(g2l_idx); dev_free(yloc); dev_free(sub_seg);
     dev_free(coarse_dev); dev_free(gp); dev_free(gq); dev_free(gref); dev_free(cperm); dev_free(gptr); dev_free(gw);
     dev_free(z_ptr); dev_free(zt_ptr); dev_free(z_col); dev_free(zt_col); dev_free(z_val); dev_free(zt_val);
@@ -372,6 +375,8 @@ struct seird_precond_s {
     sl.nblocks = ph.n_sub;
     sl.l2g = l2g;
     sl.owned = owned;
+    sl.erow = env_row;
+    sl.elo = env_lo;
     sl.r = r;
     sl.z = z;
     sl.add = add;
@@ -1017,6 +1022,8 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
     pc->ent_dev = dev_upload(ph.extract);
     pc->l2g = dev_upload(ph.l2g);
     pc->owned = dev_upload(ph.owned);
+    pc->env_row = dev_upload(ph.env_row);
+    pc->env_lo = dev_upload(ph.env_lo);
     pc->status = dev_alloc<int>(1);
     // transposed-apply gather lists: global unknown -> local copies
     {
@@ -1141,6 +1148,8 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
   fl.Fc = pc->Fc;
   fl.coarse_entries = ph.coarse_entries;
   fl.subs = pc->subs_dev;
+  fl.erow = pc->env_row;
+  fl.elo = pc->env_lo;
   fl.nsub = ph.n_sub;
   fl.order = pc->order_dev;
   fl.ent = pc->ent_dev;

@@ -91,13 +91,21 @@ struct ParamsDev {
 // and upper part of U_KK^{-1}), slots BL+1.. = U_{K,K+1..K+BU}.  Tiles are
 // row-major t*t.  Padded rows (n_loc..NT*t-1) carry an identity diagonal.
 // ---------------------------------------------------------------------
+// Factor storage of one system in 32x32 (or 16x16) row-major tiles.
+// Envelope layout (env_off >= 0, the subdomains): tile row K holds tile
+// columns lo_K .. hi_K contiguously, from tile offset row_K; lo is
+// nondecreasing and the envelope is symmetric (tile (K, J), J > K, is
+// stored iff lo_J <= K), so LU without pivoting keeps its fill inside it.
+// row_K and lo_K are in the row table at env_off + K (nt + 1 entries).
+// Band layout (env_off < 0, the coarse system): row K holds tile columns
+// K - bl .. K + bu at slots 0 .. bl + bu.
 struct SubInfo {
   int64_t base;     // offset (entries) of the factor storage
   int32_t n_loc;    // local unknowns (5 * local nodes)
   int32_t nt;       // number of tile rows
-  int32_t bl, bu;   // block bandwidths
+  int32_t bl, bu;   // block bandwidths (largest extent left / right of the diagonal)
   int32_t l2g_off;  // offset into the local->global unknown map
-  int32_t pad;
+  int32_t env_off;  // offset into the row table, or -1 for the band layout
 };
 
 struct ExtractEntry {  // one node block of R_i A R_i^T
@@ -113,7 +121,8 @@ struct PrecondHost {
   std::vector<uint8_t> owned;         // per local unknown: owned by the sub
   std::vector<ExtractEntry> extract;  // block entries
   std::vector<int32_t> order;         // subdomain processing order (LPT)
-  int64_t factor_entries = 0;   // subdomain tile-band entries
+  std::vector<int32_t> env_row, env_lo;  // subdomain row tables (tile offset, first tile column)
+  int64_t factor_entries = 0;   // subdomain tile-envelope entries
   int64_t coarse_entries = 0;   // coarse tile-band entries (own buffer)
   int32_t max_nodes = 0, max_bw = 0;
   int32_t max_nloc = 0;

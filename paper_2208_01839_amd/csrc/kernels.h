@@ -29,6 +29,7 @@ struct FactorLaunch {
   double *Fc = nullptr;     // coarse tile-band storage (float64)
   int64_t coarse_entries = 0;
   const SubInfo *subs = nullptr;  // device
+  const int32_t *erow = nullptr, *elo = nullptr;  // subdomain row tables (device)
   int nsub = 0;
   const int32_t *order = nullptr;
   const ExtractEntry *ent = nullptr;
@@ -51,6 +52,7 @@ struct SolveLaunch {
   int prec = 0;
   const void *F = nullptr;
   const SubInfo *subs = nullptr;
+  const int32_t *erow = nullptr, *elo = nullptr;  // row tables of envelope-layout systems
   const int32_t *order = nullptr;
   int nblocks = 0;
   bool wide = false;  // 1024-thread workgroups (one large system)

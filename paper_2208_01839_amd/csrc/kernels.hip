@@ -527,6 +527,38 @@ __global__ __launch_bounds__(256) void k_seg_norm2(SegView v, const double *__re
 // ----------------------------------------------------------------------
 // Tile-band storage: init, extraction of R_i A R_i^T, conversion
 // ----------------------------------------------------------------------
+// Tile addressing of one system's factor storage (envelope layout when the
+// row table is given, else band layout; see SubInfo).
+struct TileRows {
+  int64_t base;
+  int32_t nt, bl, bu;
+  const int32_t *row, *lo;
+  template <int T>
+  __device__ inline int64_t at(int K, int J) const {  // entry offset of tile (K, J)
+    return base + (row ? (int64_t)row[K] + (J - lo[K]) : (int64_t)K * (bl + bu + 1) + (J - K + bl)) * (T * T);
+  }
+  __device__ inline int first(int K) const { return row ? lo[K] : max(0, K - bl); }
+  __device__ inline int last(int K) const { return row ? lo[K] + (row[K + 1] - row[K]) - 1 : min(nt - 1, K + bu); }
+};
+__device__ inline TileRows tile_rows(const SubInfo &s, const int32_t *erow, const int32_t *elo) {
+  TileRows r;
+  r.base = s.base;
+  r.nt = s.nt;
+  r.bl = s.bl;
+  r.bu = s.bu;
+  r.row = s.env_off >= 0 ? erow + s.env_off : nullptr;
+  r.lo = s.env_off >= 0 ? elo + s.env_off : nullptr;
+  return r;
+}
+// entry (l, lp) of a system's matrix, or -1 when it lies outside the
+// stored tiles
+template <int T>
+__device__ inline int64_t tile_entry_rows(const TileRows &R, int32_t l, int32_t lp) {
+  const int32_t K = l / T, J = lp / T;
+  if (l < 0 || lp < 0 || K >= R.nt || J < R.first(K) || J > R.last(K)) return -1;
+  return R.at<T>(K, J) + (l % T) * T + (lp % T);
+}
+
 template <int T>
 __device__ inline int64_t tile_entry(const SubInfo &s, int32_t l, int32_t lp) {
   const int32_t K = l / T, J = lp / T;
@@ -545,16 +577,19 @@ __device__ inline int64_t tile_entry_checked(const SubInfo &s, int32_t l, int32_
 
 // identity on the padded diagonal of the last block row (storage zeroed before)
 template <int T, class ET>
-__global__ void k_pad_identity(ET *__restrict__ F, const SubInfo *__restrict__ subs, int nsubs) {
+__global__ void k_pad_identity(ET *__restrict__ F, const SubInfo *__restrict__ subs, const int32_t *__restrict__ erow,
+                               const int32_t *__restrict__ elo, int nsubs) {
   const int s = blockIdx.x;
   if (s >= nsubs) return;
   const SubInfo si = subs[s];
-  for (int32_t l = si.n_loc + threadIdx.x; l < si.nt * T; l += blockDim.x) F[tile_entry<T>(si, l, l)] = (ET)1.0;
+  const TileRows R = tile_rows(si, erow, elo);
+  for (int32_t l = si.n_loc + threadIdx.x; l < si.nt * T; l += blockDim.x) F[tile_entry_rows<T>(R, l, l)] = (ET)1.0;
 }
 
 // one thread per (entry, c): writes row 5p+c, columns 5q..5q+4
 template <int T, class ET>
 __global__ __launch_bounds__(256) void k_extract(ET *__restrict__ F, const SubInfo *__restrict__ subs,
+                                                 const int32_t *__restrict__ erow, const int32_t *__restrict__ elo,
                                                  const ExtractEntry *__restrict__ ent, int64_t nent,
                                                  const double *__restrict__ diag, const double *__restrict__ off,
                                                  int *status) {
@@ -562,10 +597,10 @@ __global__ __launch_bounds__(256) void k_extract(ET *__restrict__ F, const SubIn
   if (t >= nent * 5) return;
   const ExtractEntry e = ent[t / 5];
   const int c = (int)(t % 5);
-  const SubInfo si = subs[e.sub];
+  const TileRows R = tile_rows(subs[e.sub], erow, elo);
   const int32_t row = 5 * e.p + c;
   for (int cp = 0; cp < 5; ++cp) {
-    const int64_t at = tile_entry_checked<T>(si, row, 5 * e.q + cp);
+    const int64_t at = tile_entry_rows<T>(R, row, 5 * e.q + cp);
     if (at < 0) {
       atomicOr(status, 2);
       continue;
@@ -788,26 +823,30 @@ __device__ inline CT *tile_at(CT *F, const SubInfo &s, int K, int slot) {
 // Dynamic LDS holds the U panel (bu tiles).
 template <int T>
 __global__ __launch_bounds__(256) void k_band_lu(double *__restrict__ F, const SubInfo *__restrict__ subs,
+                                                 const int32_t *__restrict__ erow, const int32_t *__restrict__ elo,
                                                  const int32_t *__restrict__ order, int *status) {
   __shared__ LuLds<T, double> L;
   extern __shared__ double upanel_raw[];
   double(*Up)[T][T + 1] = reinterpret_cast<double(*)[T][T + 1]>(upanel_raw);
   const SubInfo s = subs[order[blockIdx.x]];
+  const TileRows R = tile_rows(s, erow, elo);
+  auto tile = [&](int I, int J) { return F + R.at<T>(I, J); };
   for (int K = 0; K < s.nt; ++K) {
-    lu_diag_tile<T>(tile_at<T>(F, s, K, s.bl), L, status);
-    const int ie = min(K + s.bl, s.nt - 1), je = min(K + s.bu, s.nt - 1);
-    for (int I = K + 1; I <= ie; ++I) panel_tile<T>(tile_at<T>(F, s, I, K - I + s.bl), L, true);
+    lu_diag_tile<T>(tile(K, K), L, status);
+    // the envelope is symmetric: rows K + 1 .. last(K) have a tile in column K
+    const int ie = R.last(K), je = ie;
+    for (int I = K + 1; I <= ie; ++I) panel_tile<T>(tile(I, K), L, true);
     for (int J = K + 1; J <= je; ++J) {
-      double *a = tile_at<T>(F, s, K, J - K + s.bl);
+      double *a = tile(K, J);
       panel_tile<T>(a, L, false);
       for (int e = threadIdx.x; e < T * T; e += 256) Up[J - K - 1][e / T][e % T] = a[e];
     }
     __syncthreads();
     for (int I = K + 1; I <= ie; ++I) {
-      const double *lik = tile_at<T>(F, s, I, K - I + s.bl);
+      const double *lik = tile(I, K);
       for (int e = threadIdx.x; e < T * T; e += 256) L.S[e / T][e % T] = lik[e];
       __syncthreads();
-      for (int J = K + 1; J <= je; ++J) schur_tile<T>(tile_at<T>(F, s, I, J - I + s.bl), L.S, Up[J - K - 1]);
+      for (int J = K + 1; J <= je; ++J) schur_tile<T>(tile(I, J), L.S, Up[J - K - 1]);
       __syncthreads();
     }
   }
@@ -943,20 +982,25 @@ __device__ void lu_inv_diag_regs(CT *__restrict__ dk, CT (*Li)[33], CT (*Ui)[33]
 // L_KK^{-1} during (1)-(2).
 template <class CT, int NW, int QW>
 __global__ __launch_bounds__(64 * NW) void k_band_lu32(CT *__restrict__ F, const SubInfo *__restrict__ subs,
+                                                       const int32_t *__restrict__ erow,
+                                                       const int32_t *__restrict__ elo,
                                                        const int32_t *__restrict__ order, int *status) {
   constexpr int T = 32, NT = 64 * NW;
   typedef typename Mfma<CT>::v4 v4;
   __shared__ CT Ui[T][T + 1];     // U_KK^{-1}, dense upper
   __shared__ CT Sx[2][T][T + 1];  // L_KK^{-1} (in Sx[1]) in (1)-(2); L_IK buffers in (3)
   const SubInfo s = subs[order[blockIdx.x]];
+  const TileRows R = tile_rows(s, erow, elo);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int qi = (wave >> 1) & 1, qj = wave & 1;
   for (int K = 0; K < s.nt; ++K) {
-    const int je = min(K + s.bu, s.nt - 1), nu = je - K;
-    const int ie = min(K + s.bl, s.nt - 1);
+    // the envelope is symmetric: row K's U tiles and the rows below with a
+    // tile in column K both end at last(K)
+    const int je = R.last(K), nu = je - K;
+    const int ie = je;
     // (1) diagonal tile: LU and both inverses in one sweep
-    lu_inv_diag_regs<CT, NT>(tile_at<T, CT>(F, s, K, s.bl), Sx[1], Ui, status);
+    lu_inv_diag_regs<CT, NT>(F + R.at<T>(K, K), Sx[1], Ui, status);
     // (2) the wave's U-panel tiles, kept as B operands: ub[q][bj][4 bi + v]
     // holds U_KJ[16 bi + row(lk, v)][16 bj + lr]
     CT ub[QW][2][8];
@@ -964,7 +1008,7 @@ __global__ __launch_bounds__(64 * NW) void k_band_lu32(CT *__restrict__ F, const
     for (int q = 0; q < QW; ++q) {
       const int jj = wave + NW * q;
       if (jj < nu) {
-        CT *g = tile_at<T, CT>(F, s, K, s.bl + 1 + jj);
+        CT *g = F + R.at<T>(K, K + 1 + jj);
         CT bl[8][2];
 #pragma unroll
         for (int m = 0; m < 8; ++m)
@@ -998,7 +1042,7 @@ __global__ __launch_bounds__(64 * NW) void k_band_lu32(CT *__restrict__ F, const
     // (3) block rows below
     for (int I = K + 1; I <= ie; ++I) {
       const int buf = (I - K - 1) & 1;
-      CT *aik = tile_at<T, CT>(F, s, I, K - I + s.bl);
+      CT *aik = F + R.at<T>(I, K);
       // A_IK quadrant rows in the A-operand layout (issued first: the
       // quadrant product waits on these loads only)
       CT ra[8];
@@ -1011,7 +1055,7 @@ __global__ __launch_bounds__(64 * NW) void k_band_lu32(CT *__restrict__ F, const
       for (int q = 0; q < QW; ++q) {
         const int jj = wave + NW * q;
         if (jj < nu) {
-          const CT *c = tile_at<T, CT>(F, s, I, K + 1 + jj - I + s.bl);
+          const CT *c = F + R.at<T>(I, K + 1 + jj);
 #pragma unroll
           for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1054,7 +1098,7 @@ __global__ __launch_bounds__(64 * NW) void k_band_lu32(CT *__restrict__ F, const
       for (int q = 0; q < QW; ++q) {
         const int jj = wave + NW * q;
         if (jj < nu) {
-          CT *c = tile_at<T, CT>(F, s, I, K + 1 + jj - I + s.bl);
+          CT *c = F + R.at<T>(I, K + 1 + jj);
 #pragma unroll
           for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1255,36 +1299,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 }
 
 // ----------------------------------------------------------------------
-// Tile-band triangular solves (the subdomain apply A_i^{-1} r_i).
+// Tile triangular solves (the subdomain apply A_i^{-1} r_i).
 // One workgroup per subdomain; the local vector x lives in LDS (dynamic)
 // or, for the big coarse system, in a global scratch vector.
 // Non-transposed: forward with L (tiles left of the diagonal, then the
 // unit-lower inverse), backward with U.  Transposed: forward with U^T,
 // backward with L^T.
 // ----------------------------------------------------------------------
-template <int T, class FT>
-__device__ inline const FT *ctile(const FT *F, const SubInfo &s, int K, int slot) {
-  return F + s.base + ((int64_t)K * (s.bl + s.bu + 1) + slot) * (T * T);
-}
-
-// acc[i] (for this thread's row) partial: sum_j A[i][j] * x[j] with 8 (T=32)
-// or 16 (T=16) lanes per row; result reduced within the lane group.
-template <int T, class FT>
-__device__ inline double row_dot(const FT *__restrict__ A, const double *__restrict__ xs, int i, int g, int G) {
-  double a = 0.0;
-#pragma unroll
-  for (int j = g; j < T; j += G) a += from_ft<FT>(A[i * T + j]) * xs[j];
-  return a;
-}
-template <int T, class FT>
-__device__ inline double col_dot(const FT *__restrict__ A, const double *__restrict__ xs, int i, int g, int G) {
-  // sum_j A[j][i] * x[j]
-  double a = 0.0;
-#pragma unroll
-  for (int j = g; j < T; j += G) a += from_ft<FT>(A[j * T + i]) * xs[j];
-  return a;
-}
-
 // Barrier for workgroups that communicate through LDS only: it waits for
 // the wave's LDS operations, not for its outstanding global loads/stores,
 // so prefetched tile loads stay in flight across it.
@@ -1340,7 +1361,8 @@ __device__ inline void load_chunk(const FT *__restrict__ p, FT (&out)[PER]) {
 //   mode transposed: input masked by D_i, output to yloc (summed later)
 template <int T, class FT, int NTHR, bool TRANS>
 __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(NTHR == 256 ? 4 : 1, 8)))
-void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, const int32_t *__restrict__ order,
+void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, const int32_t *__restrict__ erow,
+                  const int32_t *__restrict__ elo, const int32_t *__restrict__ order,
                   const int32_t *__restrict__ l2g, const uint8_t *__restrict__ owned, const double *__restrict__ r,
                   double *__restrict__ z, int add, double *__restrict__ yloc, double *__restrict__ ybuf,
                   const int32_t *__restrict__ sub_seg, const uint8_t *__restrict__ seg_active) {
@@ -1359,8 +1381,8 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
   const bool local = s.l2g_off >= 0;
   const int64_t yo = local ? s.l2g_off : 0;
   const int tid = threadIdx.x;
-  const int W = s.bl + s.bu + 1;
-  auto tile = [&](int K, int slot) -> const FT * { return F + s.base + ((int64_t)K * W + slot) * (T * T); };
+  const TileRows R = tile_rows(s, erow, elo);
+  auto tile = [&](int K, int J) -> const FT * { return F + R.at<T>(K, J); };  // tile (K, J), J a tile column
   auto rhs = [&](int l) -> double {
     if (l >= s.n_loc) return 0.0;
     if (!local) return r[l];
@@ -1383,28 +1405,28 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
       FT buf[SOLVE_BMAX][PER];
       FT dv[PER];
     };
-    auto load_row = [&](int K, int c0, int c1, RowRegs &R) {  // off-diagonal tile columns c0 .. c1
-      load_chunk<FT, PER>(tile(K, s.bl) + i * T + g * PER, R.dv);
+    auto load_row = [&](int K, int c0, int c1, RowRegs &Rr) {  // off-diagonal tile columns c0 .. c1
+      load_chunk<FT, PER>(tile(K, K) + i * T + g * PER, Rr.dv);
 #pragma unroll
       for (int t = 0; t < SOLVE_BMAX; ++t)
-        if (c0 + t <= c1) load_chunk<FT, PER>(tile(K, c0 + t - K + s.bl) + i * T + g * PER, R.buf[t]);
+        if (c0 + t <= c1) load_chunk<FT, PER>(tile(K, c0 + t) + i * T + g * PER, Rr.buf[t]);
     };
     // sum over the off-diagonal tile columns c0 .. c1 of row K (first chunk
     // from R) against the ring
-    auto off_sum = [&](int K, int c0, int c1, const RowRegs &R) {
+    auto off_sum = [&](int K, int c0, int c1, const RowRegs &Rr) {
       double a = 0.0;
 #pragma unroll
       for (int t = 0; t < SOLVE_BMAX; ++t)
         if (c0 + t <= c1) {
           const double *xr = ring[(c0 + t) % RING];
 #pragma unroll
-          for (int m = 0; m < PER; ++m) a += from_ft<FT>(R.buf[t][m]) * xr[g * PER + m];
+          for (int m = 0; m < PER; ++m) a += from_ft<FT>(Rr.buf[t][m]) * xr[g * PER + m];
         }
       for (int C0 = c0 + SOLVE_BMAX; C0 <= c1; C0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
-          if (C0 + t <= c1) load_chunk<FT, PER>(tile(K, C0 + t - K + s.bl) + i * T + g * PER, buf[t]);
+          if (C0 + t <= c1) load_chunk<FT, PER>(tile(K, C0 + t) + i * T + g * PER, buf[t]);
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (C0 + t <= c1) {
@@ -1416,12 +1438,12 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
       return a;
     };
     RowRegs cur, nxt;
-    // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P), P = max(0, K - bl) .. K - 1
+    // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P), P = first(K) .. K - 1
     if (s.nt > 0) load_row(0, 0, -1, cur);
     for (int K = 0; K < s.nt; ++K) {
-      if (K + 1 < s.nt) load_row(K + 1, max(0, K + 1 - s.bl), K, nxt);
+      if (K + 1 < s.nt) load_row(K + 1, R.first(K + 1), K, nxt);
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
-      double a = off_sum(K, max(0, K - s.bl), K - 1, cur);
+      double a = off_sum(K, R.first(K), K - 1, cur);
       a = group_sum<G>(a);
       if (g == 0) acc_s[i] = bv - a;
       lds_barrier();
@@ -1440,12 +1462,12 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
       lds_barrier();
       cur = nxt;
     }
-    // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J), J = K + 1 .. min(K + bu, nt - 1)
+    // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J), J = K + 1 .. last(K)
     if (s.nt > 0) load_row(s.nt - 1, s.nt, s.nt - 1, cur);
     for (int K = s.nt - 1; K >= 0; --K) {
-      if (K > 0) load_row(K - 1, K, min(K - 1 + s.bu, s.nt - 1), nxt);
+      if (K > 0) load_row(K - 1, K, R.last(K - 1), nxt);
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
-      double a = off_sum(K, K + 1, min(K + s.bu, s.nt - 1), cur);
+      double a = off_sum(K, K + 1, R.last(K), cur);
       a = group_sum<G>(a);
       if (g == 0) acc_s[i] = bv - a;
       lds_barrier();
@@ -1477,18 +1499,18 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     const int i = tid / G, g = tid % G;
     // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P)
     for (int K = 0; K < s.nt; ++K) {
-      const int p0 = max(0, K - s.bl);
+      const int p0 = R.first(K);
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
       // the diagonal tile's loads go out with the first off-diagonal chunk
       FT dv[PER];
-      load_chunk<FT, PER>(tile(K, s.bl) + i * T + g * PER, dv);
+      load_chunk<FT, PER>(tile(K, K) + i * T + g * PER, dv);
       double a = 0.0;
       for (int P0 = p0; P0 < K; P0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (P0 + t < K) {
-            const FT *A = tile(K, P0 + t - K + s.bl);
+            const FT *A = tile(K, P0 + t);
             load_chunk<FT, PER>(A + i * T + g * PER, buf[t]);
           }
 #pragma unroll
@@ -1518,17 +1540,17 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     }
     // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J)
     for (int K = s.nt - 1; K >= 0; --K) {
-      const int je = min(K + s.bu, s.nt - 1);
+      const int je = R.last(K);
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
       FT dv[PER];
-      load_chunk<FT, PER>(tile(K, s.bl) + i * T + g * PER, dv);
+      load_chunk<FT, PER>(tile(K, K) + i * T + g * PER, dv);
       double a = 0.0;
       for (int J0 = K + 1; J0 <= je; J0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (J0 + t <= je) {
-            const FT *A = tile(K, J0 + t - K + s.bl);
+            const FT *A = tile(K, J0 + t);
             load_chunk<FT, PER>(A + i * T + g * PER, buf[t]);
           }
 #pragma unroll
@@ -1570,11 +1592,11 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     const int ci = tid % T, cg = tid / T;
     // forward with U^T: y_K = Uinv_KK^T (b_K - sum_{P<K} U_PK^T y_P)
     for (int K = 0; K < s.nt; ++K) {
-      const int p0 = max(0, K - s.bu);
+      const int p0 = R.first(K);  // rows P < K with a tile in column K (symmetric envelope)
       const double bv = (tid < T && K * T + tid < s.n_loc) ? ybuf[yo + K * T + tid] : 0.0;
       FT dv[PER];
       {
-        const FT *dk = tile(K, s.bl);
+        const FT *dk = tile(K, K);
 #pragma unroll
         for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
       }
@@ -1584,7 +1606,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (P0 + t < K) {
-            const FT *A = tile(P0 + t, K - (P0 + t) + s.bl);
+            const FT *A = tile(P0 + t, K);
 #pragma unroll
             for (int m = 0; m < PER; ++m) buf[t][m] = A[(cg + m * G) * T + ci];
           }
@@ -1622,11 +1644,11 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     }
     // backward with L^T: x_K = Linv_KK^T (y_K - sum_{J>K} L_JK^T x_J)
     for (int K = s.nt - 1; K >= 0; --K) {
-      const int je = min(K + s.bl, s.nt - 1);
+      const int je = R.last(K);  // rows J > K with a tile in column K
       const double bv = (tid < T && K * T + tid < s.n_loc) ? ybuf[yo + K * T + tid] : 0.0;
       FT dv[PER];
       {
-        const FT *dk = tile(K, s.bl);
+        const FT *dk = tile(K, K);
 #pragma unroll
         for (int m = 0; m < PER; ++m) dv[m] = dk[(cg + m * G) * T + ci];
       }
@@ -1636,7 +1658,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (J0 + t <= je) {
-            const FT *A = tile(J0 + t, K - (J0 + t) + s.bl);
+            const FT *A = tile(J0 + t, K);
 #pragma unroll
             for (int m = 0; m < PER; ++m) buf[t][m] = A[(cg + m * G) * T + ci];
           }
@@ -2200,16 +2222,18 @@ void launch_check_state(const double *u, int64_t n, const int32_t *inst, int *fl
 template <int T, class ET>
 static void extract_t(const FactorLaunch &fl, ET *F, const double *diag, const double *off, hipStream_t st) {
   HIPCHECK(hipMemsetAsync(F, 0, sizeof(ET) * fl.sub_entries, st));
-  hipLaunchKernelGGL((k_pad_identity<T, ET>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.nsub);
+  hipLaunchKernelGGL((k_pad_identity<T, ET>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo, fl.nsub);
   if (fl.nent > 0)
-    hipLaunchKernelGGL((k_extract<T, ET>), dim3(nblocks(fl.nent * 5)), dim3(256), 0, st, F, fl.subs, fl.ent, fl.nent,
+    hipLaunchKernelGGL((k_extract<T, ET>), dim3(nblocks(fl.nent * 5)), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo,
+                       fl.ent, fl.nent,
                        diag, off, fl.status);
 }
 
 template <int T>
 static void coarse_factor_t(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st) {
   HIPCHECK(hipMemsetAsync(fl.Fc, 0, sizeof(double) * fl.coarse_entries, st));
-  hipLaunchKernelGGL((k_pad_identity<T, double>), dim3(1), dim3(256), 0, st, fl.Fc, fl.coarse_dev, 1);
+  hipLaunchKernelGGL((k_pad_identity<T, double>), dim3(1), dim3(256), 0, st, fl.Fc, fl.coarse_dev, nullptr, nullptr,
+                     1);
   hipLaunchKernelGGL(k_galerkin<T>, dim3(nblocks(fl.gal_nblk * 64)), dim3(256), 0, st, fl.Fc, fl.cs, fl.gp, fl.gq,
                      fl.gptr, fl.gref, fl.gw, fl.gal_nblk, diag, off, fl.status);
   const SubInfo cs = fl.cs;
@@ -2237,11 +2261,14 @@ static void coarse_factor_t(const FactorLaunch &fl, const double *diag, const do
 template <class CT>
 static void band_lu32(const FactorLaunch &fl, CT *F, hipStream_t st) {
   if (fl.max_bu <= 8)
-    hipLaunchKernelGGL((k_band_lu32<CT, 4, 2>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.order, fl.status);
+    hipLaunchKernelGGL((k_band_lu32<CT, 4, 2>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo, fl.order,
+                       fl.status);
   else if (sizeof(CT) == 4 && fl.coarse && fl.max_bu <= 12)
-    hipLaunchKernelGGL((k_band_lu32<CT, 4, 3>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.order, fl.status);
+    hipLaunchKernelGGL((k_band_lu32<CT, 4, 3>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo, fl.order,
+                       fl.status);
   else
-    hipLaunchKernelGGL((k_band_lu32<CT, 8, 2>), dim3(fl.nsub), dim3(512), 0, st, F, fl.subs, fl.order, fl.status);
+    hipLaunchKernelGGL((k_band_lu32<CT, 8, 2>), dim3(fl.nsub), dim3(512), 0, st, F, fl.subs, fl.erow, fl.elo, fl.order,
+                       fl.status);
 }
 
 void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st,
@@ -2261,8 +2288,8 @@ void launch_setup_factors(const FactorLaunch &fl, const double *diag, const doub
     } else {
       extract_t<16, double>(fl, (double *)fl.Fs, diag, off, st);
       const size_t lds = (size_t)std::max(fl.max_bu, 1) * 16 * 17 * sizeof(double);
-      hipLaunchKernelGGL(k_band_lu<16>, dim3(fl.nsub), dim3(256), lds, st, (double *)fl.Fs, fl.subs, fl.order,
-                         fl.status);
+      hipLaunchKernelGGL(k_band_lu<16>, dim3(fl.nsub), dim3(256), lds, st, (double *)fl.Fs, fl.subs, fl.erow, fl.elo,
+                         fl.order, fl.status);
     }
   }
   if (fl.coarse) {
@@ -2290,7 +2317,8 @@ void launch_convert(void *dst, int dst_prec, const void *src, int src_float, int
 template <int T, class FT, bool TR, int NTHR>
 static void solve_launch(const SolveLaunch &sl, hipStream_t st) {
   hipLaunchKernelGGL((k_band_solve<T, FT, NTHR, TR>), dim3(sl.nblocks), dim3(NTHR), 0, st, (const FT *)sl.F, sl.subs,
-                     sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf, sl.sub_seg, sl.seg_active);
+                     sl.erow, sl.elo, sl.order, sl.l2g, sl.owned, sl.r, sl.z, sl.add, sl.yloc, sl.ybuf, sl.sub_seg,
+                     sl.seg_active);
 }
 template <int T, class FT, bool TR>
 static void solve_tt(const SolveLaunch &sl, hipStream_t st) {

@@ -238,7 +238,42 @@ static SubInfo tile_geometry(int32_t nn, int32_t bw, int tile) {
   si.nt = (si.n_loc + tile - 1) / tile;
   si.bl = std::min<int32_t>((kl + tile - 1) / tile, si.nt - 1);
   si.bu = si.bl;
+  si.env_off = -1;
   return si;
+}
+
+// Tile envelope of a subdomain matrix in the local order (node position k
+// holds unknowns 5k .. 5k + 4, full 5x5 node blocks): lo[K] = first tile
+// column of tile row K, made nondecreasing (suffix minimum) so that the
+// envelope is closed under elimination; row[K] = tile offset of row K,
+// whose tiles are the columns lo[K] .. hi[K] with hi[K] = max{J : lo[J] <=
+// K}.  Sets si.bl = si.bu to the largest extent.
+static void tile_envelope(const std::vector<int32_t> &lp, const std::vector<int32_t> &la,
+                          const std::vector<int32_t> &perm, const std::vector<int32_t> &where, int tile,
+                          SubInfo &si, std::vector<int32_t> &lo, std::vector<int32_t> &row) {
+  const int32_t nn = (int32_t)perm.size(), nt = si.nt;
+  lo.assign(nt, 0);
+  for (int32_t K = 0; K < nt; ++K) lo[K] = K;
+  for (int32_t k = 0; k < nn; ++k) {
+    int32_t left = k;
+    for (int32_t q = lp[perm[k]]; q < lp[perm[k] + 1]; ++q) left = std::min(left, where[la[q]]);
+    const int32_t K = (NC * k) / tile, K2 = (NC * k + NC - 1) / tile;  // tile rows of the node's unknowns
+    const int32_t J = (NC * left) / tile;
+    lo[K] = std::min(lo[K], J);
+    lo[K2] = std::min(lo[K2], J);
+  }
+  for (int32_t K = nt - 2; K >= 0; --K) lo[K] = std::min(lo[K], lo[K + 1]);
+  row.assign(nt + 1, 0);
+  int32_t bl = 0, bu = 0, J = 0;
+  for (int32_t K = 0; K < nt; ++K) {
+    while (J + 1 < nt && lo[J + 1] <= K) ++J;
+    const int32_t hi = std::max(J, K);
+    row[K + 1] = row[K] + (hi - lo[K] + 1);
+    bl = std::max(bl, K - lo[K]);
+    bu = std::max(bu, hi - K);
+  }
+  si.bl = bl;
+  si.bu = bu;
 }
 
 void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t *part,
@@ -303,9 +338,15 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
     for (int32_t k = 0; k < nn; ++k)
       for (int32_t q = lp[k]; q < lp[k + 1]; ++q) bw = std::max(bw, std::abs(where[k] - where[la[q]]));
     SubInfo si = tile_geometry(nn, bw, t);
+    std::vector<int32_t> elo, erow;
+    tile_envelope(lp, la, perm, where, t, si, elo, erow);
     si.base = base;
     si.l2g_off = (int32_t)ph.l2g.size();
-    base += (int64_t)si.nt * (si.bl + si.bu + 1) * t * t;
+    si.env_off = (int32_t)ph.env_row.size();
+    ph.env_row.insert(ph.env_row.end(), erow.begin(), erow.end());
+    ph.env_lo.insert(ph.env_lo.end(), elo.begin(), elo.end());
+    ph.env_lo.push_back(0);  // same length as the row offsets
+    base += (int64_t)erow[si.nt] * t * t;
     ph.max_nodes = std::max(ph.max_nodes, nn);
     ph.max_bw = std::max(ph.max_bw, bw);
     ph.mean_bw += (double)bw / o.n_sub;
@@ -334,8 +375,10 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
   ph.order.resize(o.n_sub);
   std::iota(ph.order.begin(), ph.order.end(), 0);
   std::stable_sort(ph.order.begin(), ph.order.end(), [&](int a, int b) {
+    // work ~ stored tiles times the band width
     const SubInfo &x = ph.subs[a], &y = ph.subs[b];
-    return (int64_t)x.nt * (x.bl + x.bu + 1) > (int64_t)y.nt * (y.bl + y.bu + 1);
+    const int64_t tx = ph.env_row[x.env_off + x.nt], ty = ph.env_row[y.env_off + y.nt];
+    return tx * (x.bu + 1) > ty * (y.bu + 1);
   });
 
   // ------------------------------------------------------------------
