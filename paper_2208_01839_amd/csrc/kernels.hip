@@ -130,9 +130,6 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
   const int64_t i = xcd_thread();
   if (i >= m.n) return;
   const ParamsDev P = m.inst ? m.Pinst[m.inst[i]] : P0;
-  for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s)
-#pragma unroll
-    for (int q = 0; q < 10; ++q) off[10 * s + q] = 0.0;
   double ui[5];
   load5(u + 5 * i, ui);
   const double Ni = ui[0] + ui[1] + ui[2] + ui[3] + ui[4];
@@ -140,25 +137,46 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
   double coef[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) coef[c] = dt * P.nu[c];
-  for (int64_t k = m.inc_ptr[i]; k < m.inc_ptr[i + 1]; ++k) {
+  const int64_t k0 = m.inc_ptr[i], k1 = m.inc_ptr[i + 1];
+  // element k's coupling of node i with its other two vertices j, l
+  auto element = [&](int64_t k, double &Nbar, double (&G3)[5]) {
     const int32_t j = m.inc_j[k], l = m.inc_l[k];
-    const int64_t sj = m.inc_sj[k], sl = m.inc_sl[k];
     const double Kii = m.inc_K[3 * k], Kij = m.inc_K[3 * k + 1], Kil = m.inc_K[3 * k + 2];
     double uj[5], ul[5];
     load5(u + 5 * (int64_t)j, uj);
     load5(u + 5 * (int64_t)l, ul);
-    const double Nbar = (Ni + (uj[0] + uj[1] + uj[2] + uj[3] + uj[4]) + (ul[0] + ul[1] + ul[2] + ul[3] + ul[4])) *
-                        (1.0 / 3.0);
+    Nbar = (Ni + (uj[0] + uj[1] + uj[2] + uj[3] + uj[4]) + (ul[0] + ul[1] + ul[2] + ul[3] + ul[4])) * (1.0 / 3.0);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) G3[c] = coef[c] * (Kii * ui[c] + Kij * uj[c] + Kil * ul[c]) * (1.0 / 3.0);
+  };
+  for (int64_t k = k0; k < k1; ++k) {
+    double Nbar, G3[5];
+    element(k, Nbar, G3);
+    const double Kii = m.inc_K[3 * k];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      const double G3 = coef[c] * (Kii * ui[c] + Kij * uj[c] + Kil * ul[c]) * (1.0 / 3.0);
       da[c] += coef[c] * Nbar * Kii;
-      db[c] += G3;
-      off[10 * sj + c] += coef[c] * Nbar * Kij;
-      off[10 * sj + 5 + c] += G3;
-      off[10 * sl + c] += coef[c] * Nbar * Kil;
-      off[10 * sl + 5 + c] += G3;
+      db[c] += G3[c];
     }
+  }
+  // each off-diagonal slot of row i: its 10 values summed over the
+  // elements that share the edge (in element order) and stored once
+  for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
+    double o[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t k = k0; k < k1; ++k) {
+      const bool atj = m.inc_sj[k] == s, atl = m.inc_sl[k] == s;
+      if (!atj && !atl) continue;
+      double Nbar, G3[5];
+      element(k, Nbar, G3);
+      const double Kx = atj ? m.inc_K[3 * k + 1] : m.inc_K[3 * k + 2];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        o[c] += coef[c] * Nbar * Kx;
+        o[5 + c] += G3[c];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) off[10 * s + q] = o[q];
   }
   const double g = gfield ? gfield[i] : 1.0;
   double JR[5][5];
