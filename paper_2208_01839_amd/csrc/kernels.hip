@@ -1401,6 +1401,20 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
   const int tid = threadIdx.x;
   const TileRows R = tile_rows(s, erow, elo);
   auto tile = [&](int K, int J) -> const FT * { return F + R.at<T>(K, J); };  // tile (K, J), J a tile column
+  // this lane's chunk (row i, elements g PER ..) of the diagonal tile of row
+  // K; the forward sweep uses its strict lower part (L_KK^{-1}), the
+  // backward sweep its upper part (U_KK^{-1}), so a chunk with no element
+  // in the half in use is not loaded (in float64 that skips about half the
+  // tile's cache lines)
+  auto load_diag = [&](int K, bool lower, int i, int g, FT (&dv)[PER]) {
+    const bool used = lower ? (g * PER < i) : (g * PER + PER - 1 >= i);
+    if (used) {
+      load_chunk<FT, PER>(tile(K, K) + i * T + g * PER, dv);
+    } else {
+#pragma unroll
+      for (int m = 0; m < PER; ++m) dv[m] = (FT)0;
+    }
+  };
   auto rhs = [&](int l) -> double {
     if (l >= s.n_loc) return 0.0;
     if (!local) return r[l];
@@ -1423,8 +1437,8 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
       FT buf[SOLVE_BMAX][PER];
       FT dv[PER];
     };
-    auto load_row = [&](int K, int c0, int c1, RowRegs &Rr) {  // off-diagonal tile columns c0 .. c1
-      load_chunk<FT, PER>(tile(K, K) + i * T + g * PER, Rr.dv);
+    auto load_row = [&](int K, int c0, int c1, bool lower, RowRegs &Rr) {  // off-diagonal tile columns c0 .. c1
+      load_diag(K, lower, i, g, Rr.dv);
 #pragma unroll
       for (int t = 0; t < SOLVE_BMAX; ++t)
         if (c0 + t <= c1) load_chunk<FT, PER>(tile(K, c0 + t) + i * T + g * PER, Rr.buf[t]);
@@ -1457,9 +1471,9 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     };
     RowRegs cur, nxt;
     // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P), P = first(K) .. K - 1
-    if (s.nt > 0) load_row(0, 0, -1, cur);
+    if (s.nt > 0) load_row(0, 0, -1, true, cur);
     for (int K = 0; K < s.nt; ++K) {
-      if (K + 1 < s.nt) load_row(K + 1, R.first(K + 1), K, nxt);
+      if (K + 1 < s.nt) load_row(K + 1, R.first(K + 1), K, true, nxt);
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
       double a = off_sum(K, R.first(K), K - 1, cur);
       a = group_sum<G>(a);
@@ -1481,9 +1495,9 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
       cur = nxt;
     }
     // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J), J = K + 1 .. last(K)
-    if (s.nt > 0) load_row(s.nt - 1, s.nt, s.nt - 1, cur);
+    if (s.nt > 0) load_row(s.nt - 1, s.nt, s.nt - 1, false, cur);
     for (int K = s.nt - 1; K >= 0; --K) {
-      if (K > 0) load_row(K - 1, K, R.last(K - 1), nxt);
+      if (K > 0) load_row(K - 1, K, R.last(K - 1), false, nxt);
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
       double a = off_sum(K, K + 1, R.last(K), cur);
       a = group_sum<G>(a);
@@ -1521,7 +1535,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
       // the diagonal tile's loads go out with the first off-diagonal chunk
       FT dv[PER];
-      load_chunk<FT, PER>(tile(K, K) + i * T + g * PER, dv);
+      load_diag(K, true, i, g, dv);
       double a = 0.0;
       for (int P0 = p0; P0 < K; P0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
@@ -1561,7 +1575,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
       const int je = R.last(K);
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
       FT dv[PER];
-      load_chunk<FT, PER>(tile(K, K) + i * T + g * PER, dv);
+      load_diag(K, false, i, g, dv);
       double a = 0.0;
       for (int J0 = K + 1; J0 <= je; J0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
