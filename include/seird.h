@@ -72,7 +72,11 @@ typedef struct {
  *  n_sub, part: node partition into owner subdomains (part[node] in
  *    [0, n_sub)); subdomain i is its owner set grown by `overlap` layers of
  *    mesh-graph neighbours; D_i is the Boolean owner indicator (Eq. RAS).
- *  tile: tile edge of the banded local factors (16 or 32).
+ *  tile: tile edge of the local factors' storage (16 or 32).  Each
+ *    subdomain's factors are kept in its tile envelope: tile row K stores
+ *    the tiles from its first nonzero tile column (nondecreasing down the
+ *    rows, so that LU without pivoting fills only inside) to the symmetric
+ *    upper extent.
  *  factor_prec: storage precision of the local factors used by the
  *    preconditioner apply: 0 = float64, 1 = float32, 2 = bfloat16.  The
  *    factorisation itself runs in float64; vectors and accumulations of
@@ -213,13 +217,13 @@ seird_status seird_precond_info(seird_precond pc, int64_t *factor_entries,
                                 int64_t *coarse_n, int32_t *max_local_nodes,
                                 int32_t *max_bandwidth);
 /* Host-only analysis of the Schwarz decomposition (no device calls):
- * builds the mesh graph, subdomains, local orderings and tile-band
- * geometry exactly as seird_precond_create does and reports their sizes.
+ * builds the mesh graph, subdomains, local orderings and tile
+ * envelopes exactly as seird_precond_create does and reports their sizes.
  * l2g_out [local_unknowns] (nullable) receives, subdomain after
  * subdomain, the global unknown of every local unknown in local order;
  * owned_out [local_unknowns] (nullable) its owner flag (D_i). */
 typedef struct {
-  int64_t factor_entries;   /* tile-band entries, subdomains + coarse */
+  int64_t factor_entries;   /* stored tile entries: subdomain envelopes + coarse band */
   int64_t local_unknowns;   /* sum of subdomain sizes (unknowns) */
   int32_t max_local_nodes;
   int32_t max_bandwidth;    /* node bandwidth of the local orderings */
@@ -253,7 +257,7 @@ seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver);
 seird_status seird_precond_set_solve_threads(seird_precond pc, int32_t threads);
 
 /* Autotuner of the Schwarz launch shapes on the caller's own problem: the
- * tile size of the band storage (16 or 32; `opts->tile` is overridden) and
+ * tile size of the factor storage (16 or 32; `opts->tile` is overridden) and
  * the subdomain-solve workgroup size.  For every tile it builds the
  * preconditioner from `opts` and `part`, factors `vals` twice (a warm-up,
  * then a host-timed setup), and for every workgroup size times `reps`

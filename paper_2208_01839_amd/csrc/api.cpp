@@ -1185,7 +1185,7 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
   HIPCHECK(hipStreamSynchronize(st));
   pc->ready = true;
   pc->vals_setup = vals;
-  if (status & 2) fail(SEIRD_ERR_ARG, "internal: local matrix entry outside the tile band");
+  if (status & 2) fail(SEIRD_ERR_ARG, "internal: local matrix entry outside the stored tiles");
   if (status) fail(SEIRD_ERR_BREAKDOWN, "zero or nonfinite pivot in a local LU factorisation");
 }
 

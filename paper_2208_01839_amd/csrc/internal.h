@@ -83,13 +83,12 @@ struct ParamsDev {
 };
 
 // ---------------------------------------------------------------------
-// Subdomain tile-band geometry.  Local unknowns l = 5*p + c for local node
-// p (local ordering by reverse Cuthill-McKee).  Scalar lower/upper
-// bandwidth kl = ku = 5*bw + 4 for node bandwidth bw.  Tiles t x t; block
-// row K holds BL + 1 + BU tiles: slots 0..BL-1 = L_{K,K-BL..K-1}, slot BL =
-// the diagonal tile (after factorisation: strictly-lower part of L_KK^{-1}
-// and upper part of U_KK^{-1}), slots BL+1.. = U_{K,K+1..K+BU}.  Tiles are
-// row-major t*t.  Padded rows (n_loc..NT*t-1) carry an identity diagonal.
+// Subdomain matrices: local unknowns l = 5*p + c for local node p (local
+// ordering by reverse Cuthill-McKee or a strip sort, whichever has the
+// smaller bandwidth).  After factorisation the diagonal tile of a row holds
+// the strictly-lower part of L_KK^{-1} and the upper part of U_KK^{-1}; the
+// other tiles hold L (left of the diagonal) and U (right of it).  Padded
+// rows (n_loc .. nt*t - 1) carry an identity diagonal.
 // ---------------------------------------------------------------------
 // Factor storage of one system in 32x32 (or 16x16) row-major tiles.
 // Envelope layout (env_off >= 0, the subdomains): tile row K holds tile
@@ -123,7 +122,7 @@ struct PrecondHost {
   std::vector<int32_t> order;         // subdomain processing order (LPT)
   std::vector<int32_t> env_row, env_lo;  // subdomain row tables (tile offset, first tile column)
   int64_t factor_entries = 0;   // subdomain tile-envelope entries
-  int64_t coarse_entries = 0;   // coarse tile-band entries (own buffer)
+  int64_t coarse_entries = 0;   // coarse band entries (own buffer)
   int32_t max_nodes = 0, max_bw = 0;
   int32_t max_nloc = 0;
   double mean_bw = 0.0;

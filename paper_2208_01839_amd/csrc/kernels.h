@@ -23,7 +23,7 @@ struct SegHost {
 
 struct FactorLaunch {
   int tile = 32;
-  void *Fs = nullptr;       // subdomain tile-band storage (float64, or float32 if sub_float)
+  void *Fs = nullptr;       // subdomain tile-envelope storage (float64, or float32 if sub_float)
   bool sub_float = false;   // factorise the subdomains in float32
   int64_t sub_entries = 0;
   double *Fc = nullptr;     // coarse tile-band storage (float64)

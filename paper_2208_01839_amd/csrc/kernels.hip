@@ -543,7 +543,8 @@ __global__ __launch_bounds__(256) void k_seg_norm2(SegView v, const double *__re
 }
 
 // ----------------------------------------------------------------------
-// Tile-band storage: init, extraction of R_i A R_i^T, conversion
+// Tile storage (subdomain envelopes, coarse band): init, extraction of
+// R_i A R_i^T, conversion
 // ----------------------------------------------------------------------
 // Tile addressing of one system's factor storage (envelope layout when the
 // row table is given, else band layout; see SubInfo).
@@ -709,7 +710,8 @@ __global__ void k_convert(FT *__restrict__ dst, const ST *__restrict__ src, int6
 }
 
 // ----------------------------------------------------------------------
-// Tile-band LU without pivoting (right-looking, block version).
+// Tile LU without pivoting (right-looking, block version; tile 16 and the
+// coarse band).
 // Device routines work on one tile operation with the whole workgroup
 // (256 threads).  LDS tiles are padded to T+1 columns.
 // ----------------------------------------------------------------------
@@ -871,13 +873,7 @@ __global__ __launch_bounds__(256) void k_band_lu(double *__restrict__ F, const S
 }
 
 // ----------------------------------------------------------------------
-// Tile-band LU with 32x32 tiles and the Schur update on MFMA.
-// One workgroup (4 waves) per subdomain.  Per block column K: the diagonal
-// tile is factored and inverted in LDS; the U panel (bu tiles) is staged in
-// LDS once and multiplied by L_KK^{-1}; then for every block row I below,
-// the C tiles of the whole strip (I, K+1..K+bu) are loaded into MFMA
-// accumulators at once, L_IK = A_IK U_KK^{-1} is formed, and the strip is
-// updated C -= L_IK U_K,* with 16x16x4 MFMAs (wave w owns tiles w, w+4, ..).
+// LU with 32x32 tiles and the tile products on MFMA.
 // CT = double uses v_mfma_f64_16x16x4f64, CT = float v_mfma_f32_16x16x4f32.
 // MFMA operand layouts (16x16x4): A[i][k] in lane i + 16 k; B[k][j] in lane
 // j + 16 k.  Accumulator element v of lane l holds column l % 16 and row
@@ -983,7 +979,7 @@ __device__ void lu_inv_diag_regs(CT *__restrict__ dk, CT (*Li)[33], CT (*Ui)[33]
   }
 }
 
-// Banded LU of one subdomain per workgroup (tile 32, NW waves), right-
+// LU of one subdomain per workgroup (tile 32, NW waves), right-
 // looking by block rows.  Step K:
 //   (1) the diagonal tile is factored and both factors inverted (register
 //       sweep above);

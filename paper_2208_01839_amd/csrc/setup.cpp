@@ -1,6 +1,6 @@
 // Host-side setup of libseird: mesh checks, node graph, incidence records,
-// lumped mass (Section 2.2); subdomains, overlap, local ordering, tile-band
-// geometry, extraction maps (Section 3, Eq. RAS); nested P1 coarse space and
+// lumped mass (Section 2.2); subdomains, overlap, local ordering, tile
+// envelopes, extraction maps (Section 3, Eq. RAS); nested P1 coarse space and
 // Galerkin maps (Section 3.1).
 #include <algorithm>
 #include <cmath>
