@@ -242,14 +242,26 @@ seird_status seird_analyze_schwarz(int64_t n_nodes, const double *xy,
  * launches; the totals are reported in seird_step_stats (t_ras_kernel_ms,
  * n_ras_launches) and reset at the end of every seird_step. */
 seird_status seird_precond_timing(seird_precond pc, int enable);
-/* Coarse solver of a two-level preconditioner.  1: the coarse factors' block
- * triangular inverses X = L^{-1}, W = U^{-1} are formed at every setup
- * (FP64 MFMA, on the coarse stream) and A_c^{-1} r = W (X r) is two dense
- * triangular mat-vecs over the whole device; the default with tile 32 when
- * both fit 16 GB (nt(nt+1) tiles of 8 KB for nt coarse tile rows).  0: the
- * band forward/backward sweeps over the factors (one workgroup).  Results
- * agree to rounding.  SEIRD_ERR_ARG for 1 without inverses. */
+/* Coarse solver of a two-level preconditioner.  1: the inverses of the
+ * diagonal super-blocks of the coarse factors, X_II = L_II^{-1} and
+ * W_II = U_II^{-1}, are formed at every setup (FP64 MFMA, on the coarse
+ * stream) and A_c^{-1} r is a block forward/backward sweep: per block a
+ * dense triangular mat-vec over the device plus a coupling update from the
+ * neighbouring block (see seird_precond_set_coarse_block); the default with
+ * tile 32 when the storage fits 16 GB (nt(nt+1) tiles of 8 KB for nt coarse
+ * tile rows, whatever the block size).  0: the band forward/backward sweeps
+ * over the factors (one workgroup).  Results agree to rounding.
+ * SEIRD_ERR_ARG for 1 without inverses. */
 seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver);
+/* Super-block size of the coarse inverses, in coarse tile rows (takes effect
+ * at the next seird_precond_setup).  0: one block, the full inverses
+ * X = L^{-1}, W = U^{-1} (the solve is two triangular mat-vecs).  Smaller
+ * blocks shorten the setup (no inverse column recurrence is longer than a
+ * block) and lengthen the solve (two steps per block).  Default 128, raised
+ * to the coarse band width.  SEIRD_ERR_ARG when no inverses exist or the
+ * size is below the coarse band width in tiles (the blocks must couple only
+ * with their neighbours). */
+seird_status seird_precond_set_coarse_block(seird_precond pc, int32_t tiles);
 /* Workgroup size of the subdomain solves: 256 (any tile), 512 or 1024
  * (tile 32 only).  A launch choice: each row's sums are split over 8, 16
  * or 32 lanes (float64 accumulation), so results agree to rounding.

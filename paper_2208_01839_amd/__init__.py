@@ -124,6 +124,7 @@ _SIGS = {
     "seird_precond_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "seird_precond_set_solve_threads": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_precond_set_coarse_solver": ([_P, ctypes.c_int32], ctypes.c_int),
+    "seird_precond_set_coarse_block": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_autotune_schwarz": ([_P, ctypes.POINTER(_Schwarz), _P, _P, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.POINTER(_TuneReport), _P], ctypes.c_int),
     "seird_analyze_schwarz": ([ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.POINTER(_Schwarz), _P,
@@ -358,8 +359,14 @@ class Precond:
         _check(lib().seird_precond_set_solve_threads(self.h, int(threads)))
 
     def set_coarse_solver(self, solver):
-        """1: explicit triangular inverses of the coarse factors; 0: band sweeps."""
+        """1: block sweep over inverted diagonal super-blocks of the coarse
+        factors; 0: band sweeps."""
         _check(lib().seird_precond_set_coarse_solver(self.h, int(solver)))
+
+    def set_coarse_block(self, tiles):
+        """Super-block size of the coarse inverses in tile rows (0: full
+        inverses); takes effect at the next setup."""
+        _check(lib().seird_precond_set_coarse_block(self.h, int(tiles)))
 
     def setup(self, vals):
         _check(lib().seird_precond_setup(self.h, _dptr(vals, self.problem.nvals, "vals"), _stream()))

@@ -212,6 +212,12 @@ struct seird_problem_s {
 };
 
 // both packed triangular inverses of a coarse band with nt tile rows (tile 32)
+// default super-block of the coarse inverses (tile rows): column chains of
+// at most 128 rows at setup, against 2 ceil(nt / 128) block steps per solve
+// (on the realistic coarse grid, 633 tile rows, 128 gives the shortest
+// setup plus 16 solves per step; 64 and 32 shorten the setup a little and
+// lengthen the solves more)
+constexpr int COARSE_BLOCK = 128;
 static inline double coarse_inverse_bytes(int64_t nt) { return 2.0 * (double)(nt * (nt + 1) / 2) * 1024 * 8; }
 constexpr double COARSE_INVERSE_BUDGET = 16.0e9;
 
@@ -248,6 +254,7 @@ struct seird_precond_s {
   // fit the budget); coarse_solver 1 uses them, 0 the band sweeps
   double *Xc = nullptr, *Wc = nullptr;
   int coarse_solver = 0;
+  int coarse_block = 0;  // super-block of the inverses, in tile rows (set at creation)
   double *t1 = nullptr;
   const double *vals_setup = nullptr;  // Jacobian of the last setup (borrowed)
   bool ready = false;
@@ -411,7 +418,7 @@ struct seird_precond_s {
   void coarse_add(const double *r, double *z, int transpose, hipStream_t st) {
     launch_coarse_restrict(zt_ptr, zt_col, zt_val, cperm, r, rc, ph.nc, st);
     if (coarse_solver == 1) {
-      launch_coarse_inverse_apply(Xc, Wc, ph.coarse.nt, rc, xc, cscratch, transpose, st);
+      launch_coarse_inverse_apply(Xc, Wc, Fc, ph.coarse, coarse_block, rc, xc, cscratch, transpose, st);
       launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
       return;
     }
@@ -1061,9 +1068,11 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
       pc->t1 = dev_alloc<double>(p->N);
       if (T == 32 && coarse_inverse_bytes(ph.coarse.nt) <= COARSE_INVERSE_BUDGET) {
         const int64_t nt = ph.coarse.nt;
+        // sized for the full inverses, so that any super-block size fits
         pc->Xc = dev_alloc<double>((size_t)(nt * (nt + 1) / 2) * 1024);
         pc->Wc = dev_alloc<double>((size_t)(nt * (nt + 1) / 2) * 1024);
         pc->coarse_solver = 1;
+        pc->coarse_block = (int)std::min<int64_t>(nt, std::max({COARSE_BLOCK, ph.coarse.bl, ph.coarse.bu}));
       }
       HIPCHECK(hipStreamCreateWithFlags(&pc->st_coarse, hipStreamNonBlocking));
       HIPCHECK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
@@ -1113,6 +1122,20 @@ seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver) {
   if (solver != 0 && solver != 1) fail(SEIRD_ERR_ARG, "coarse solver must be 0 or 1");
   if (solver == 1 && !pc->Xc) fail(SEIRD_ERR_ARG, "no coarse inverses for this preconditioner");
   pc->coarse_solver = solver;
+  API_END
+}
+
+seird_status seird_precond_set_coarse_block(seird_precond pc, int32_t tiles) {
+  API_BEGIN
+  if (!pc) fail(SEIRD_ERR_ARG, "null preconditioner");
+  if (!pc->Xc) fail(SEIRD_ERR_ARG, "no coarse inverses for this preconditioner");
+  const SubInfo &cs = pc->ph.coarse;
+  if (tiles < 0) fail(SEIRD_ERR_ARG, "coarse block must be >= 0");
+  const int S = tiles == 0 ? cs.nt : std::min(tiles, cs.nt);
+  if (S < std::max(cs.bl, cs.bu))
+    fail(SEIRD_ERR_ARG, "coarse block below the coarse band width (" + std::to_string(std::max(cs.bl, cs.bu)) +
+                            " tile rows)");
+  pc->coarse_block = S;
   API_END
 }
 
@@ -1172,7 +1195,7 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
     HIPCHECK(hipEventRecord(pc->ev_fork, st));
     HIPCHECK(hipStreamWaitEvent(pc->st_coarse, pc->ev_fork, 0));
     launch_setup_factors(fl, P->diag(vals), P->off(vals), st, pc->st_coarse);
-    if (pc->Xc) launch_coarse_inverse(pc->Fc, ph.coarse, pc->Xc, pc->Wc, pc->st_coarse);
+    if (pc->Xc) launch_coarse_inverse(pc->Fc, ph.coarse, pc->coarse_block, pc->Xc, pc->Wc, pc->st_coarse);
     HIPCHECK(hipEventRecord(pc->ev_join, pc->st_coarse));
     HIPCHECK(hipStreamWaitEvent(st, pc->ev_join, 0));
   } else {

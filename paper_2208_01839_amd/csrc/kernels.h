@@ -112,12 +112,14 @@ int launch_adjoint_grad(const MeshDev &m, const ParamsDev &P, const double *u, c
 // one large band system (coarse, FP64, tile 32, bl, bu <= 16), non-transposed
 void launch_coarse_solve(const double *F, const SubInfo *sp, const double *r, double *z, double *ybuf,
                          hipStream_t st);
-// explicit inverses X = L^{-1}, W = U^{-1} of the factored coarse band
-// (tile 32), packed triangular tile storage of nt(nt+1)/2 tiles each
-void launch_coarse_inverse(const double *F, const SubInfo &cs, double *X, double *W, hipStream_t st);
-// z = W X r (or X^T W^T r); r, z, tmp: nt * 32 doubles
-void launch_coarse_inverse_apply(const double *X, const double *W, int nt, const double *r, double *z, double *tmp,
-                                 int transpose, hipStream_t st);
+// inverses X_II = L_II^{-1}, W_II = U_II^{-1} of the diagonal super-blocks
+// of S tile rows of the factored coarse band (tile 32), packed triangular
+// tile storage block after block (at most nt(nt+1)/2 tiles each)
+void launch_coarse_inverse(const double *F, const SubInfo &cs, int S, double *X, double *W, hipStream_t st);
+// coarse solve z = A_c^{-1} r (or A_c^{-T} r) by the block sweep over those
+// super-blocks; r (overwritten), z, tmp: nt * 32 doubles
+void launch_coarse_inverse_apply(const double *X, const double *W, const double *F, const SubInfo &cs, int S,
+                                 double *r, double *z, double *tmp, int transpose, hipStream_t st);
 
 void launch_seg_mdot(const SegHost &g, const double *V, int64_t ldv, int nv, const double *w, int with_self,
                      double *partials, hipStream_t st);

@@ -12,6 +12,8 @@
 
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace seird {
 
 // ----------------------------------------------------------------------
@@ -1878,13 +1880,20 @@ void launch_coarse_solve(const double *F, const SubInfo *sp, const double *r, do
 //   X_cc = L_cc^{-1},   X_Kc = -L_KK^{-1} sum_{P=max(c,K-bl)}^{K-1} L_KP X_Pc  (K > c)
 // and tile column c of W = U^{-1}
 //   W_cc = U_cc^{-1},   W_Kc = -U_KK^{-1} sum_{J=K+1}^{min(c,K+bu)} U_KJ W_Jc  (K < c).
-// The coarse solve is then two dense triangular mat-vecs, x = W (X r),
-// which stream the inverses with the whole chip instead of running the
-// dependent band sweeps in one workgroup.
+// Only the diagonal super-blocks of X and W are formed: tile rows are cut
+// into blocks of S (the last one shorter), and the recurrences above run
+// inside a block (X_II = L_II^{-1}, W_II = U_II^{-1}), so no column chain is
+// longer than S.  With S >= bl, bu the factors couple only neighbouring
+// blocks, and the coarse solve is a block sweep: forward y_I = X_II (r_I -
+// L_{I,I-1} y_{I-1}), backward x_I = W_II (y_I - U_{I,I+1} x_{I+1}), each
+// step a dense triangular mat-vec over the block plus a small coupling
+// update; S = nt is the full inverse and the solve two mat-vecs.
 //
-// Packed tile storage, row-major 32x32 tiles: X tile (K, c), c <= K, at
-// K(K+1)/2 + c; W tile (K, c), c >= K, at K nt - K(K-1)/2 + (c - K).  A
-// tile row of either matrix is contiguous.
+// Packed tile storage, row-major 32x32 tiles, block after block (every
+// earlier block holding S(S+1)/2 tiles): inside a block of nb rows, X tile
+// (K, c), c <= K, at K(K+1)/2 + c; W tile (K, c), c >= K, at
+// K nb - K(K-1)/2 + (c - K) (block-local indices).  A tile row is
+// contiguous.
 // ----------------------------------------------------------------------
 __host__ __device__ inline int64_t lower_packed(int K, int c) { return (int64_t)K * (K + 1) / 2 + c; }
 __host__ __device__ inline int64_t upper_packed(int K, int c, int nt) {
@@ -1900,7 +1909,7 @@ constexpr int INV_PF = 1;  // tile pairs loaded ahead into registers
 // pair at a time is staged in LDS (17 KB, which fits beside a
 // subdomain-factorisation workgroup), with the next INV_PF pairs' loads in
 // flight in registers.
-__global__ __launch_bounds__(256) void k_coarse_tri_inverse(const double *__restrict__ F, SubInfo s,
+__global__ __launch_bounds__(256) void k_coarse_tri_inverse(const double *__restrict__ F, SubInfo s, int S,
                                                             double *__restrict__ X, double *__restrict__ Wm) {
   constexpr int T = 32;
   typedef Mfma<double>::v4 v4;
@@ -1910,15 +1919,19 @@ __global__ __launch_bounds__(256) void k_coarse_tri_inverse(const double *__rest
   const bool upper = (blockIdx.x & 1) != 0;
   const int c = upper ? nt - 1 - (int)(blockIdx.x >> 1) : (int)(blockIdx.x >> 1);
   double *const M = upper ? Wm : X;
+  // the diagonal super-block of tile rows s0 .. s1 - 1 that holds column c,
+  // and the packed storage of its inverse (every earlier block has S rows)
+  const int sb = c / S, s0 = sb * S, s1 = min(s0 + S, nt), nb = s1 - s0;
+  const int64_t boff = (int64_t)sb * S * (S + 1) / 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int qi = wave >> 1, qj = wave & 1;
   const int W = s.bl + s.bu + 1;
   auto fac = [&](int K, int slot) { return F + s.base + ((int64_t)K * W + slot) * (T * T); };
   auto out = [&](int K) -> double * {
-    return M + (upper ? upper_packed(K, c, nt) : lower_packed(K, c)) * (T * T);
+    return M + (boff + (upper ? upper_packed(K - s0, c - s0, nb) : lower_packed(K - s0, c - s0))) * (T * T);
   };
-  const int rows = upper ? c + 1 : nt - c;
+  const int rows = upper ? c - s0 + 1 : s1 - c;
   for (int it = 0; it < rows; ++it) {
     const int K = upper ? c - it : c + it;
     const int p_lo = upper ? K + 1 : max(c, K - s.bl);
@@ -2069,18 +2082,91 @@ __global__ __launch_bounds__(256) void k_coarse_tri_gemv(const double *__restric
   }
 }
 
-void launch_coarse_inverse(const double *F, const SubInfo &cs, double *X, double *W, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarse_tri_inverse, dim3(2 * cs.nt), dim3(256), 0, st, F, cs, X, W);
+// Coupling step of the coarse block sweep: v_K -= (tiles of row K of the
+// factor that lie in the neighbouring block) x (that block's solution sol).
+//   L (forward):      K in [s0, s0 + bl),  v_K -= sum_{P = K-bl}^{s0-1} L_KP sol_P
+//   U (backward):     K in [s1 - bu, s1),  v_K -= sum_{J = s1}^{K+bu} U_KJ sol_J
+//   U^T (forward):    K in [s0, s0 + bu),  v_K -= sum_{P = K-bu}^{s0-1} U_PK^T sol_P
+//   L^T (backward):   K in [s1 - bl, s1),  v_K -= sum_{J = s1}^{K+bl} L_JK^T sol_J
+// for the block of tile rows s0 .. s1 - 1.  One workgroup per tile row K.
+template <bool UPPER, bool TRANS>
+__global__ __launch_bounds__(256) void k_coarse_couple(const double *__restrict__ F, SubInfo s, int S, int sb,
+                                                       double *__restrict__ v, const double *__restrict__ sol) {
+  constexpr int T = 32;
+  __shared__ double red[8][T];
+  const int nt = s.nt, s0 = sb * S, s1 = min(s0 + S, nt);
+  constexpr bool fwd = UPPER == TRANS;
+  const int w = UPPER ? s.bu : s.bl;
+  const int K = fwd ? s0 + (int)blockIdx.x : s1 - 1 - (int)blockIdx.x;
+  if (fwd ? (K >= min(s0 + w, s1)) : (K < max(s1 - w, s0))) return;  // uniform per workgroup
+  const int lo = fwd ? max(K - w, 0) : s1, hi = fwd ? s0 - 1 : min(K + w, nt - 1);
+  const int Wd = s.bl + s.bu + 1;
+  auto tile = [&](int r, int c) { return F + s.base + ((int64_t)r * Wd + (c - r + s.bl)) * (T * T); };
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  if constexpr (!TRANS) {
+    const int i = tid >> 3, g = tid & 7;
+    for (int c = lo; c <= hi; ++c) {
+      const double4 a = *reinterpret_cast<const double4 *>(tile(K, c) + i * T + 4 * g);
+      const double4 b = *reinterpret_cast<const double4 *>(sol + (int64_t)c * T + 4 * g);
+      acc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) acc += __shfl_xor(acc, o, 8);
+    if (g == 0) v[(int64_t)K * T + i] -= acc;
+  } else {
+    const int j = tid & 31, g = tid >> 5;  // rows 4g .. 4g+3 of each tile
+    for (int c = lo; c <= hi; ++c) {
+      const double *a = tile(c, K);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc += a[(4 * g + m) * T + j] * sol[(int64_t)c * T + 4 * g + m];
+    }
+    red[g][j] = acc;
+    __syncthreads();
+    if (tid < T) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t += red[q][tid];
+      v[(int64_t)K * T + tid] -= t;
+    }
+  }
 }
 
-void launch_coarse_inverse_apply(const double *X, const double *W, int nt, const double *r, double *z, double *tmp,
-                                 int transpose, hipStream_t st) {
-  if (!transpose) {  // z = W (X r)
-    hipLaunchKernelGGL((k_coarse_tri_gemv<false, false>), dim3(nt), dim3(256), 0, st, X, nt, r, tmp);
-    hipLaunchKernelGGL((k_coarse_tri_gemv<true, false>), dim3(nt), dim3(256), 0, st, W, nt, tmp, z);
-  } else {  // z = X^T (W^T r)
-    hipLaunchKernelGGL((k_coarse_tri_gemv<true, true>), dim3(nt), dim3(256), 0, st, W, nt, r, tmp);
-    hipLaunchKernelGGL((k_coarse_tri_gemv<false, true>), dim3(nt), dim3(256), 0, st, X, nt, tmp, z);
+void launch_coarse_inverse(const double *F, const SubInfo &cs, int S, double *X, double *W, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_tri_inverse, dim3(2 * cs.nt), dim3(256), 0, st, F, cs, S, X, W);
+}
+
+void launch_coarse_inverse_apply(const double *X, const double *W, const double *F, const SubInfo &cs, int S,
+                                 double *r, double *z, double *tmp, int transpose, hipStream_t st) {
+  constexpr int T = 32;
+  const int nt = cs.nt, NS = (nt + S - 1) / S;
+  auto gemv = [&](auto kern, const double *M, int sb, const double *x, double *y) {
+    const int s0 = sb * S, nb = std::min(S, nt - s0);
+    const int64_t off = (int64_t)sb * S * (S + 1) / 2 * (T * T);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, M + off, nb, x + (int64_t)s0 * T, y + (int64_t)s0 * T);
+  };
+  if (!transpose) {  // L y = r (y in tmp) forward, then U z = y backward
+    for (int sb = 0; sb < NS; ++sb) {
+      if (sb > 0)
+        hipLaunchKernelGGL((k_coarse_couple<false, false>), dim3(cs.bl), dim3(256), 0, st, F, cs, S, sb, r, tmp);
+      gemv(k_coarse_tri_gemv<false, false>, X, sb, r, tmp);
+    }
+    for (int sb = NS - 1; sb >= 0; --sb) {
+      if (sb < NS - 1)
+        hipLaunchKernelGGL((k_coarse_couple<true, false>), dim3(cs.bu), dim3(256), 0, st, F, cs, S, sb, tmp, z);
+      gemv(k_coarse_tri_gemv<true, false>, W, sb, tmp, z);
+    }
+  } else {  // U^T y = r forward, then L^T z = y backward
+    for (int sb = 0; sb < NS; ++sb) {
+      if (sb > 0)
+        hipLaunchKernelGGL((k_coarse_couple<true, true>), dim3(cs.bu), dim3(256), 0, st, F, cs, S, sb, r, tmp);
+      gemv(k_coarse_tri_gemv<true, true>, W, sb, r, tmp);
+    }
+    for (int sb = NS - 1; sb >= 0; --sb) {
+      if (sb < NS - 1)
+        hipLaunchKernelGGL((k_coarse_couple<false, true>), dim3(cs.bl), dim3(256), 0, st, F, cs, S, sb, tmp, z);
+      gemv(k_coarse_tri_gemv<false, true>, X, sb, tmp, z);
+    }
   }
 }
 
