@@ -193,63 +193,56 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
 
 // ----------------------------------------------------------------------
 // SpMV with the node-block Jacobian: y = J x, or y = b - J x when b != 0.
+// Five lanes per node, lane c producing row c of the node's block row (of
+// block column c for J^T): consecutive lanes then read consecutive matrix
+// entries and write consecutive outputs.  Each output sums its terms in the
+// order diagonal block, then slots in CSR order.
 // ----------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restrict__ diag,
-                                              const double *__restrict__ off, const double *__restrict__ x,
-                                              const double *__restrict__ b, double *__restrict__ y) {
-  const int64_t i = xcd_thread();
+constexpr int SPMV_NODES = 64;  // nodes per workgroup (5 lanes each)
+
+__global__ __launch_bounds__(5 * SPMV_NODES) void k_spmv(MeshDev m, const double *__restrict__ diag,
+                                                         const double *__restrict__ off,
+                                                         const double *__restrict__ x, const double *__restrict__ b,
+                                                         double *__restrict__ y) {
+  const int t = threadIdx.x, c = t % 5;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * SPMV_NODES + t / 5;
   if (i >= m.n) return;
-  double xi[5], acc[5];
+  double xi[5];
   load5(x + 5 * i, xi);
-  const double *D = diag + 25 * i;
+  const double *D = diag + 25 * i + 5 * c;
+  double acc = 0.0;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    double a = 0.0;
-#pragma unroll
-    for (int cp = 0; cp < 5; ++cp) a += D[5 * c + cp] * xi[cp];
-    acc[c] = a;
-  }
+  for (int cp = 0; cp < 5; ++cp) acc += D[cp] * xi[cp];
   for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
-    const int64_t j = m.col[s];
-    double xj[5];
-    load5(x + 5 * j, xj);
+    const double *xj = x + 5 * (int64_t)m.col[s];
     const double S = xj[0] + xj[1] + xj[2] + xj[3] + xj[4];
     const double *o = off + 10 * s;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) acc[c] += o[c] * xj[c] + o[5 + c] * S;
+    acc += o[c] * xj[c] + o[5 + c] * S;
   }
-#pragma unroll
-  for (int c = 0; c < 5; ++c) y[5 * i + c] = b ? b[5 * i + c] - acc[c] : acc[c];
+  y[5 * i + c] = b ? b[5 * i + c] - acc : acc;
 }
 
 // y = J^T x (or b - J^T x): column j of J gathered through the transposed slots
-__global__ __launch_bounds__(256) void k_spmv_t(MeshDev m, const double *__restrict__ diag,
-                                                const double *__restrict__ off, const double *__restrict__ x,
-                                                const double *__restrict__ b, double *__restrict__ y) {
-  const int64_t j = xcd_thread();
+__global__ __launch_bounds__(5 * SPMV_NODES) void k_spmv_t(MeshDev m, const double *__restrict__ diag,
+                                                           const double *__restrict__ off,
+                                                           const double *__restrict__ x, const double *__restrict__ b,
+                                                           double *__restrict__ y) {
+  const int t = threadIdx.x, cp = t % 5;
+  const int64_t j = xcd_block(blockIdx.x, gridDim.x) * SPMV_NODES + t / 5;
   if (j >= m.n) return;
-  double xj[5], acc[5];
+  double xj[5];
   load5(x + 5 * j, xj);
-  const double *D = diag + 25 * j;
+  const double *D = diag + 25 * j + cp;
+  double acc = 0.0;
 #pragma unroll
-  for (int cp = 0; cp < 5; ++cp) {
-    double a = 0.0;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) a += D[5 * c + cp] * xj[c];
-    acc[cp] = a;
-  }
+  for (int c = 0; c < 5; ++c) acc += D[5 * c] * xj[c];
   for (int64_t s = m.rowptr[j]; s < m.rowptr[j + 1]; ++s) {
-    const int64_t i = m.col[s];
-    const int64_t ts = m.tslot[s];  // block (i, j) lives at slot ts of row i
-    double xi[5];
-    load5(x + 5 * i, xi);
-    const double *o = off + 10 * ts;
+    const double *xi = x + 5 * (int64_t)m.col[s];
+    const double *o = off + 10 * (int64_t)m.tslot[s];  // block (i, j) lives at slot tslot of row i
     const double bsum = o[5] * xi[0] + o[6] * xi[1] + o[7] * xi[2] + o[8] * xi[3] + o[9] * xi[4];
-#pragma unroll
-    for (int cp = 0; cp < 5; ++cp) acc[cp] += o[cp] * xi[cp] + bsum;
+    acc += o[cp] * xi[cp] + bsum;
   }
-#pragma unroll
-  for (int c = 0; c < 5; ++c) y[5 * j + c] = b ? b[5 * j + c] - acc[c] : acc[c];
+  y[5 * j + cp] = b ? b[5 * j + cp] - acc : acc;
 }
 
 // ----------------------------------------------------------------------
@@ -2303,9 +2296,9 @@ void launch_jacobian(const MeshDev &m, const ParamsDev &P, const double *g, cons
 void launch_spmv(const MeshDev &m, const double *diag, const double *off, const double *x, const double *b, double *y,
                  int transpose, hipStream_t st) {
   if (transpose)
-    hipLaunchKernelGGL(k_spmv_t, dim3(nblocks(m.n)), dim3(256), 0, st, m, diag, off, x, b, y);
+    hipLaunchKernelGGL(k_spmv_t, dim3(nblocks(m.n, SPMV_NODES)), dim3(5 * SPMV_NODES), 0, st, m, diag, off, x, b, y);
   else
-    hipLaunchKernelGGL(k_spmv, dim3(nblocks(m.n)), dim3(256), 0, st, m, diag, off, x, b, y);
+    hipLaunchKernelGGL(k_spmv, dim3(nblocks(m.n, SPMV_NODES)), dim3(5 * SPMV_NODES), 0, st, m, diag, off, x, b, y);
 }
 void launch_mdot(const double *V, int64_t ldv, int nv, const double *w, int64_t N, int with_self, double *partials,
                  int nb, hipStream_t st) {
