@@ -231,6 +231,7 @@ struct seird_precond_s {
   SubInfo *subs_dev = nullptr;
   int32_t *order_dev = nullptr;
   ExtractEntry *ent_dev = nullptr;
+  int32_t *ent_ptr = nullptr, *trow_ptr = nullptr, *trow_sub = nullptr;  // extraction entry and tile-row maps
   int32_t *l2g = nullptr;
   uint8_t *owned = nullptr;
   int32_t *env_row = nullptr, *env_lo = nullptr;  // subdomain row tables
@@ -351,7 +352,7 @@ struct seird_precond_s {
       (void)hipEventDestroy(e.second);
     }
     dev_free(Fs); dev_free(Fb); dev_free(Fc); dev_free(subs_dev); dev_free(order_dev); dev_free(ent_dev); dev_free(l2g);
-    dev_free(env_row); dev_free(env_lo);
+    dev_free(env_row); dev_free(env_lo); dev_free(ent_ptr); dev_free(trow_ptr); dev_free(trow_sub);
     dev_free(owned); dev_free(status); dev_free(g2l_ptr); dev_free(g2l_idx); dev_free(yloc); dev_free(sub_seg);
     dev_free(coarse_dev); dev_free(gp); dev_free(gq); dev_free(gref); dev_free(cperm); dev_free(gptr); dev_free(gw);
     dev_free(z_ptr); dev_free(zt_ptr); dev_free(z_col); dev_free(zt_col); dev_free(z_val); dev_free(zt_val);
@@ -1027,6 +1028,9 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
     pc->subs_dev = dev_upload(ph.subs);
     pc->order_dev = dev_upload(ph.order);
     pc->ent_dev = dev_upload(ph.extract);
+    pc->ent_ptr = dev_upload(ph.ent_ptr);
+    pc->trow_ptr = dev_upload(ph.trow_ptr);
+    pc->trow_sub = dev_upload(ph.trow_sub);
     pc->l2g = dev_upload(ph.l2g);
     pc->owned = dev_upload(ph.owned);
     pc->env_row = dev_upload(ph.env_row);
@@ -1176,7 +1180,10 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
   fl.nsub = ph.n_sub;
   fl.order = pc->order_dev;
   fl.ent = pc->ent_dev;
-  fl.nent = (int64_t)ph.extract.size();
+  fl.ent_ptr = pc->ent_ptr;
+  fl.trow_ptr = pc->trow_ptr;
+  fl.trow_sub = pc->trow_sub;
+  fl.ntrows = ph.trow_ptr.back();
   fl.max_bu = pc->max_bu;
   fl.status = pc->status;
   if (ph.two_level) {

@@ -118,7 +118,10 @@ struct PrecondHost {
   std::vector<SubInfo> subs;          // subdomains (then, if two-level, coarse)
   std::vector<int32_t> l2g;           // local unknown -> global unknown
   std::vector<uint8_t> owned;         // per local unknown: owned by the sub
-  std::vector<ExtractEntry> extract;  // block entries
+  std::vector<ExtractEntry> extract;  // block entries, grouped by (subdomain, local node)
+  std::vector<int32_t> ent_ptr;       // first entry of each local node (all subdomains in order) [+1]
+  std::vector<int32_t> trow_ptr;      // first tile row of each subdomain in a global count [n_sub+1]
+  std::vector<int32_t> trow_sub;      // subdomain of each such tile row
   std::vector<int32_t> order;         // subdomain processing order (LPT)
   std::vector<int32_t> env_row, env_lo;  // subdomain row tables (tile offset, first tile column)
   int64_t factor_entries = 0;   // subdomain tile-envelope entries

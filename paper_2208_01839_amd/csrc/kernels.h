@@ -32,8 +32,11 @@ struct FactorLaunch {
   const int32_t *erow = nullptr, *elo = nullptr;  // subdomain row tables (device)
   int nsub = 0;
   const int32_t *order = nullptr;
-  const ExtractEntry *ent = nullptr;
-  int64_t nent = 0;
+  const ExtractEntry *ent = nullptr;  // grouped by (subdomain, local node)
+  const int32_t *ent_ptr = nullptr;   // first entry of each local node
+  const int32_t *trow_ptr = nullptr;  // first global tile row of each subdomain [nsub+1]
+  const int32_t *trow_sub = nullptr;  // subdomain of each global tile row [ntrows]
+  int64_t ntrows = 0;                 // tile rows over all subdomains
   int max_bu = 0;
   int *status = nullptr;
   // coarse

@@ -600,33 +600,108 @@ __global__ void k_pad_identity(ET *__restrict__ F, const SubInfo *__restrict__ s
   for (int32_t l = si.n_loc + threadIdx.x; l < si.nt * T; l += blockDim.x) F[tile_entry_rows<T>(R, l, l)] = (ET)1.0;
 }
 
-// one thread per (entry, c): writes row 5p+c, columns 5q..5q+4
+// Subdomain matrices A_i = R_i A R_i^T (Eq. RAS) written into the tile
+// envelope.  One workgroup per subdomain tile row writes every stored entry
+// of that row exactly once: the matrix entry, zero, or 1 on the padded
+// diagonal, so the storage needs no clearing beforehand.  A thread owns one
+// row of a tile and 4 consecutive columns; the nonzero node blocks of its
+// row are the extraction entries of its local node.  Node-block values:
+// diagonal blocks from diag, off-diagonal block (c, c') = b_c + a_c [c = c'].
 template <int T, class ET>
-__global__ __launch_bounds__(256) void k_extract(ET *__restrict__ F, const SubInfo *__restrict__ subs,
-                                                 const int32_t *__restrict__ erow, const int32_t *__restrict__ elo,
-                                                 const ExtractEntry *__restrict__ ent, int64_t nent,
-                                                 const double *__restrict__ diag, const double *__restrict__ off,
-                                                 int *status) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nent * 5) return;
-  const ExtractEntry e = ent[t / 5];
-  const int c = (int)(t % 5);
-  const TileRows R = tile_rows(subs[e.sub], erow, elo);
-  const int32_t row = 5 * e.p + c;
-  for (int cp = 0; cp < 5; ++cp) {
-    const int64_t at = tile_entry_rows<T>(R, row, 5 * e.q + cp);
-    if (at < 0) {
-      atomicOr(status, 2);
-      continue;
+__global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const SubInfo *__restrict__ subs,
+                                                       const int32_t *__restrict__ trow_ptr,
+                                                       const int32_t *__restrict__ trow_sub,
+                                                       const int32_t *__restrict__ erow,
+                                                       const int32_t *__restrict__ elo,
+                                                       const ExtractEntry *__restrict__ ent,
+                                                       const int32_t *__restrict__ ent_ptr,
+                                                       const double *__restrict__ diag,
+                                                       const double *__restrict__ off) {
+  constexpr int CH = T / 4;          // 4-column chunks per tile row
+  constexpr int PER = T * CH;        // threads per tile
+  constexpr int TPP = 256 / PER;     // tiles per pass
+  const int gK = blockIdx.x;
+  const int s0 = trow_sub[gK];  // trow_ptr[s0] <= gK < trow_ptr[s0 + 1]
+  const SubInfo si = subs[s0];
+  const TileRows R = tile_rows(si, erow, elo);
+  const int K = gK - trow_ptr[s0];
+  const int tid = threadIdx.x, tt = tid / PER, a = (tid % PER) / CH, g = tid % CH;
+  const int32_t l = K * T + a;  // local row
+  const int32_t p = l / 5, c = l % 5;
+  const bool real = l < si.n_loc;
+  int32_t e0 = 0, e1 = 0;
+  if (real) {
+    const int64_t nb = si.l2g_off / 5 + p;
+    e0 = ent_ptr[nb];
+    e1 = ent_ptr[nb + 1];
+  }
+  // the row's node blocks held in registers (column node, value reference);
+  // nodes with more blocks than that search the entry list in memory
+  constexpr int MAXE = 16;
+  const int32_t ne = e1 - e0;
+  const bool inreg = ne <= MAXE;
+  int32_t qv[MAXE], rv[MAXE], qlo = INT32_MAX, qhi = -1;
+#pragma unroll
+  for (int k = 0; k < MAXE; ++k) {
+    const bool have = inreg && k < ne;
+    qv[k] = have ? ent[e0 + k].q : -1;
+    rv[k] = have ? ent[e0 + k].ref : 0;
+    if (have) {
+      qlo = min(qlo, qv[k]);
+      qhi = max(qhi, qv[k]);
     }
-    double v;
-    if (e.ref < 0)
-      v = diag[25 * (int64_t)(-e.ref - 1) + 5 * c + cp];
-    else {
-      const double *o = off + 10 * (int64_t)e.ref;
-      v = o[5 + c] + (cp == c ? o[c] : 0.0);
+  }
+  auto value = [&](int32_t ref, int cp) -> double {
+    if (ref < 0) return diag[25 * (int64_t)(-ref - 1) + 5 * c + cp];
+    const double *o = off + 10 * (int64_t)ref;
+    return o[5 + c] + (cp == c ? o[c] : 0.0);
+  };
+  const int J1 = R.last(K);
+  for (int J = R.first(K) + tt; J <= J1; J += TPP) {
+    const int32_t lb0 = J * T + 4 * g;  // first column of the chunk
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (real && inreg) {
+      // columns lb0 .. lb0 + 3 belong to at most two node blocks qa, qb
+      const int32_t qa = lb0 / 5, qb = (lb0 + 3) / 5;
+      if (qb >= qlo && qa <= qhi) {
+        int32_t ra = 0, rb = 0;
+        bool ha = false, hb = false;
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          if (qv[k] == qa) {
+            ha = true;
+            ra = rv[k];
+          }
+          if (qv[k] == qb) {
+            hb = true;
+            rb = rv[k];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool inb = lb0 + u >= 5 * qb;
+          if (inb ? hb : ha) v[u] = value(inb ? rb : ra, lb0 + u - 5 * (inb ? qb : qa));
+        }
+      }
+    } else if (real) {
+      for (int32_t k = e0; k < e1; ++k) {
+        const int32_t d0 = lb0 - 5 * ent[k].q;  // chunk start relative to node block q
+        if (d0 <= -4 || d0 >= 5) continue;
+        const int32_t ref = ent[k].ref;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (d0 + u >= 0 && d0 + u < 5) v[u] = value(ref, d0 + u);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (lb0 + u == l) v[u] = 1.0;
     }
-    F[at] = (ET)v;
+    ET *dst = F + R.at<T>(K, J) + a * T + 4 * g;
+    if constexpr (sizeof(ET) == 8)
+      *reinterpret_cast<double4 *>(dst) = make_double4(v[0], v[1], v[2], v[3]);
+    else
+      *reinterpret_cast<float4 *>(dst) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
   }
 }
 
@@ -2328,12 +2403,9 @@ void launch_check_state(const double *u, int64_t n, const int32_t *inst, int *fl
 
 template <int T, class ET>
 static void extract_t(const FactorLaunch &fl, ET *F, const double *diag, const double *off, hipStream_t st) {
-  HIPCHECK(hipMemsetAsync(F, 0, sizeof(ET) * fl.sub_entries, st));
-  hipLaunchKernelGGL((k_pad_identity<T, ET>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo, fl.nsub);
-  if (fl.nent > 0)
-    hipLaunchKernelGGL((k_extract<T, ET>), dim3(nblocks(fl.nent * 5)), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo,
-                       fl.ent, fl.nent,
-                       diag, off, fl.status);
+  if (fl.ntrows > 0)
+    hipLaunchKernelGGL((k_extract_tiles<T, ET>), dim3((unsigned)fl.ntrows), dim3(256), 0, st, F, fl.subs, fl.trow_ptr,
+                       fl.trow_sub, fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
 }
 
 template <int T>

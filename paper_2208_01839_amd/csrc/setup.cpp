@@ -296,6 +296,7 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
   std::vector<int32_t> stamp(n, -1), lpos(n, -1);
   const int t = o.tile;
   int64_t base = 0;
+  ph.trow_ptr.assign(1, 0);
   for (int s = 0; s < o.n_sub; ++s) {
     // overlap growth: `overlap` layers of graph neighbours
     std::vector<int32_t> nodes = owned[s];
@@ -359,18 +360,30 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
         ph.owned.push_back(part[g] == s ? 1 : 0);
       }
     }
-    // extraction entries (row block p, column block q)
+    // extraction entries (row block p, column block q), node by node; each
+    // block must lie inside the stored tiles of its rows
     for (int32_t k = 0; k < nn; ++k) {
       int32_t g = nodes[perm[k]];
+      ph.ent_ptr.push_back((int32_t)ph.extract.size());
       ph.extract.push_back({s, k, k, -g - 1});
       for (int64_t q = m.rowptr[g]; q < m.rowptr[g + 1]; ++q) {
         int32_t h = m.col[q];
         if (stamp[h] == s) ph.extract.push_back({s, k, where[lpos[h]], (int32_t)q});
       }
+      for (size_t e = ph.ent_ptr.back(); e < ph.extract.size(); ++e) {
+        const int32_t J0 = NC * ph.extract[e].q / t, J1 = (NC * ph.extract[e].q + NC - 1) / t;
+        for (int32_t K = NC * k / t; K <= (NC * k + NC - 1) / t; ++K)
+          if (J0 < elo[K] || J1 >= elo[K] + (erow[K + 1] - erow[K]))
+            fail(SEIRD_ERR_ARG, "internal: local matrix entry outside the stored tiles");
+      }
+      if (ph.extract.size() >= (size_t)INT32_MAX) fail(SEIRD_ERR_ARG, "too many local matrix blocks");
     }
+    ph.trow_ptr.push_back(ph.trow_ptr.back() + si.nt);
+    ph.trow_sub.insert(ph.trow_sub.end(), si.nt, s);
     ph.subs.push_back(si);
   }
   ph.factor_entries = base;
+  ph.ent_ptr.push_back((int32_t)ph.extract.size());
   // largest subdomains first (longest-processing-time order)
   ph.order.resize(o.n_sub);
   std::iota(ph.order.begin(), ph.order.end(), 0);
