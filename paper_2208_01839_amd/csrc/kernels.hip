@@ -2450,11 +2450,22 @@ static void band_lu32(const FactorLaunch &fl, CT *F, hipStream_t st) {
                        fl.status);
 }
 
+static void coarse_factor(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st) {
+  if (fl.tile == 32)
+    coarse_factor_t<32>(fl, diag, off, st);
+  else
+    coarse_factor_t<16>(fl, diag, off, st);
+}
+
 void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st,
                           hipStream_t st_coarse) {
-  // the subdomain extraction and factorisation are queued first: the host
-  // then spends a while queueing the coarse chain (a few launches per tile
-  // row), which the device runs beside the subdomain work
+  // The two chains run side by side; the one on the critical path is queued
+  // first, because the host spends a while queueing the coarse chain (one
+  // launch per coarse tile row) and the device starts each chain as its
+  // launches arrive.  Float64 subdomain factors take longer than the coarse
+  // chain; with float32 factors the coarse chain is the longer one.
+  const bool coarse_first = fl.coarse && fl.sub_float;
+  if (coarse_first) coarse_factor(fl, diag, off, st_coarse);
   if (fl.nsub > 0) {
     if (fl.tile == 32) {
       if (fl.sub_float) {
@@ -2471,12 +2482,7 @@ void launch_setup_factors(const FactorLaunch &fl, const double *diag, const doub
                          fl.order, fl.status);
     }
   }
-  if (fl.coarse) {
-    if (fl.tile == 32)
-      coarse_factor_t<32>(fl, diag, off, st_coarse);
-    else
-      coarse_factor_t<16>(fl, diag, off, st_coarse);
-  }
+  if (fl.coarse && !coarse_first) coarse_factor(fl, diag, off, st_coarse);
 }
 
 void launch_convert(void *dst, int dst_prec, const void *src, int src_float, int64_t N, hipStream_t st) {
