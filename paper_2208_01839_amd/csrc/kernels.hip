@@ -198,15 +198,18 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
 // entries and write consecutive outputs.  Each output sums its terms in the
 // order diagonal block, then slots in CSR order.
 // ----------------------------------------------------------------------
-constexpr int SPMV_NODES = 64;  // nodes per workgroup (5 lanes each)
+constexpr int SPMV_NODES = 64;  // nodes per workgroup of k_spmv_t (5 lanes each)
+constexpr int SPMV_WAVE_NODES = 12;  // nodes per wave of k_spmv (lanes 60..63 idle)
 
-__global__ __launch_bounds__(5 * SPMV_NODES) void k_spmv(MeshDev m, const double *__restrict__ diag,
-                                                         const double *__restrict__ off,
-                                                         const double *__restrict__ x, const double *__restrict__ b,
-                                                         double *__restrict__ y) {
-  const int t = threadIdx.x, c = t % 5;
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * SPMV_NODES + t / 5;
-  if (i >= m.n) return;
+// Forward product: a wave holds 12 whole nodes, so the five lanes of a node
+// exchange their neighbour components with shuffles (each lane loads one).
+__global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restrict__ diag,
+                                              const double *__restrict__ off, const double *__restrict__ x,
+                                              const double *__restrict__ b, double *__restrict__ y) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane % 5, g0 = lane - c;  // first lane of this node's group
+  const int64_t i = (xcd_block(blockIdx.x, gridDim.x) * 4 + w) * SPMV_WAVE_NODES + lane / 5;
+  if (lane >= 5 * SPMV_WAVE_NODES || i >= m.n) return;
   double xi[5];
   load5(x + 5 * i, xi);
   const double *D = diag + 25 * i + 5 * c;
@@ -214,10 +217,11 @@ __global__ __launch_bounds__(5 * SPMV_NODES) void k_spmv(MeshDev m, const double
 #pragma unroll
   for (int cp = 0; cp < 5; ++cp) acc += D[cp] * xi[cp];
   for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
-    const double *xj = x + 5 * (int64_t)m.col[s];
-    const double S = xj[0] + xj[1] + xj[2] + xj[3] + xj[4];
+    const double xjc = x[5 * (int64_t)m.col[s] + c];
+    const double S = __shfl(xjc, g0, 64) + __shfl(xjc, g0 + 1, 64) + __shfl(xjc, g0 + 2, 64) +
+                     __shfl(xjc, g0 + 3, 64) + __shfl(xjc, g0 + 4, 64);
     const double *o = off + 10 * s;
-    acc += o[c] * xj[c] + o[5 + c] * S;
+    acc += o[c] * xjc + o[5 + c] * S;
   }
   y[5 * i + c] = b ? b[5 * i + c] - acc : acc;
 }
@@ -2373,7 +2377,7 @@ void launch_spmv(const MeshDev &m, const double *diag, const double *off, const 
   if (transpose)
     hipLaunchKernelGGL(k_spmv_t, dim3(nblocks(m.n, SPMV_NODES)), dim3(5 * SPMV_NODES), 0, st, m, diag, off, x, b, y);
   else
-    hipLaunchKernelGGL(k_spmv, dim3(nblocks(m.n, SPMV_NODES)), dim3(5 * SPMV_NODES), 0, st, m, diag, off, x, b, y);
+    hipLaunchKernelGGL(k_spmv, dim3(nblocks(m.n, 4 * SPMV_WAVE_NODES)), dim3(256), 0, st, m, diag, off, x, b, y);
 }
 void launch_mdot(const double *V, int64_t ldv, int nv, const double *w, int64_t N, int with_self, double *partials,
                  int nb, hipStream_t st) {
