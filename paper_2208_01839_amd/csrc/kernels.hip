@@ -198,11 +198,10 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
 // entries and write consecutive outputs.  Each output sums its terms in the
 // order diagonal block, then slots in CSR order.
 // ----------------------------------------------------------------------
-constexpr int SPMV_NODES = 64;  // nodes per workgroup of k_spmv_t (5 lanes each)
-constexpr int SPMV_WAVE_NODES = 12;  // nodes per wave of k_spmv (lanes 60..63 idle)
+constexpr int SPMV_WAVE_NODES = 12;  // nodes per wave (lanes 60..63 idle)
 
-// Forward product: a wave holds 12 whole nodes, so the five lanes of a node
-// exchange their neighbour components with shuffles (each lane loads one).
+// A wave holds 12 whole nodes, so the five lanes of a node exchange their
+// neighbour components with shuffles (each lane loads one).
 __global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restrict__ diag,
                                               const double *__restrict__ off, const double *__restrict__ x,
                                               const double *__restrict__ b, double *__restrict__ y) {
@@ -226,14 +225,17 @@ __global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restric
   y[5 * i + c] = b ? b[5 * i + c] - acc : acc;
 }
 
-// y = J^T x (or b - J^T x): column j of J gathered through the transposed slots
-__global__ __launch_bounds__(5 * SPMV_NODES) void k_spmv_t(MeshDev m, const double *__restrict__ diag,
-                                                           const double *__restrict__ off,
-                                                           const double *__restrict__ x, const double *__restrict__ b,
-                                                           double *__restrict__ y) {
-  const int t = threadIdx.x, cp = t % 5;
-  const int64_t j = xcd_block(blockIdx.x, gridDim.x) * SPMV_NODES + t / 5;
-  if (j >= m.n) return;
+// y = J^T x (or b - J^T x): column j of J gathered through the transposed
+// slots, with the same lane layout; lane c' of node j loads component c' of
+// the neighbour's x, and the five lanes share their products for the
+// rank-one term b . x_i.
+__global__ __launch_bounds__(256) void k_spmv_t(MeshDev m, const double *__restrict__ diag,
+                                                const double *__restrict__ off, const double *__restrict__ x,
+                                                const double *__restrict__ b, double *__restrict__ y) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cp = lane % 5, g0 = lane - cp;  // first lane of this node's group
+  const int64_t j = (xcd_block(blockIdx.x, gridDim.x) * 4 + w) * SPMV_WAVE_NODES + lane / 5;
+  if (lane >= 5 * SPMV_WAVE_NODES || j >= m.n) return;
   double xj[5];
   load5(x + 5 * j, xj);
   const double *D = diag + 25 * j + cp;
@@ -241,10 +243,12 @@ __global__ __launch_bounds__(5 * SPMV_NODES) void k_spmv_t(MeshDev m, const doub
 #pragma unroll
   for (int c = 0; c < 5; ++c) acc += D[5 * c] * xj[c];
   for (int64_t s = m.rowptr[j]; s < m.rowptr[j + 1]; ++s) {
-    const double *xi = x + 5 * (int64_t)m.col[s];
+    const double xic = x[5 * (int64_t)m.col[s] + cp];
     const double *o = off + 10 * (int64_t)m.tslot[s];  // block (i, j) lives at slot tslot of row i
-    const double bsum = o[5] * xi[0] + o[6] * xi[1] + o[7] * xi[2] + o[8] * xi[3] + o[9] * xi[4];
-    acc += o[cp] * xi[cp] + bsum;
+    const double pr = o[5 + cp] * xic;
+    const double bsum = __shfl(pr, g0, 64) + __shfl(pr, g0 + 1, 64) + __shfl(pr, g0 + 2, 64) +
+                        __shfl(pr, g0 + 3, 64) + __shfl(pr, g0 + 4, 64);
+    acc += o[cp] * xic + bsum;
   }
   y[5 * j + cp] = b ? b[5 * j + cp] - acc : acc;
 }
@@ -2375,7 +2379,7 @@ void launch_jacobian(const MeshDev &m, const ParamsDev &P, const double *g, cons
 void launch_spmv(const MeshDev &m, const double *diag, const double *off, const double *x, const double *b, double *y,
                  int transpose, hipStream_t st) {
   if (transpose)
-    hipLaunchKernelGGL(k_spmv_t, dim3(nblocks(m.n, SPMV_NODES)), dim3(5 * SPMV_NODES), 0, st, m, diag, off, x, b, y);
+    hipLaunchKernelGGL(k_spmv_t, dim3(nblocks(m.n, 4 * SPMV_WAVE_NODES)), dim3(256), 0, st, m, diag, off, x, b, y);
   else
     hipLaunchKernelGGL(k_spmv, dim3(nblocks(m.n, 4 * SPMV_WAVE_NODES)), dim3(256), 0, st, m, diag, off, x, b, y);
 }
