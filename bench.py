@@ -356,6 +356,8 @@ def main():
                 "max_rel_diff_vs_fp64": float(((r2["u"] - res["u"]).abs().max()
                                                / res["u"].abs().max()).item()),
                 "tile": r2["tile"], "solve_threads": r2["solve_threads"],
+                "phase_ms_per_step": {k: sum(st[k] for st in r2["stats"]) / max(1, len(r2["stats"])) for k in
+                                      ("t_residual_ms", "t_jacobian_ms", "t_setup_ms", "t_gmres_ms")},
             }
         out["mixed"] = mixed
     if args.batch_steps > 0:
