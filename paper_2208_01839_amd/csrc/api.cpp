@@ -1184,6 +1184,7 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
   fl.trow_ptr = pc->trow_ptr;
   fl.trow_sub = pc->trow_sub;
   fl.ntrows = ph.trow_ptr.back();
+  fl.max_node_blocks = ph.max_node_blocks;
   fl.max_bu = pc->max_bu;
   fl.status = pc->status;
   if (ph.two_level) {

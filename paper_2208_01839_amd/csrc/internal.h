@@ -122,6 +122,7 @@ struct PrecondHost {
   std::vector<int32_t> ent_ptr;       // first entry of each local node (all subdomains in order) [+1]
   std::vector<int32_t> trow_ptr;      // first tile row of each subdomain in a global count [n_sub+1]
   std::vector<int32_t> trow_sub;      // subdomain of each such tile row
+  int32_t max_node_blocks = 0;        // most extraction entries of one local node
   std::vector<int32_t> order;         // subdomain processing order (LPT)
   std::vector<int32_t> env_row, env_lo;  // subdomain row tables (tile offset, first tile column)
   int64_t factor_entries = 0;   // subdomain tile-envelope entries

@@ -37,6 +37,7 @@ struct FactorLaunch {
   const int32_t *trow_ptr = nullptr;  // first global tile row of each subdomain [nsub+1]
   const int32_t *trow_sub = nullptr;  // subdomain of each global tile row [ntrows]
   int64_t ntrows = 0;                 // tile rows over all subdomains
+  int max_node_blocks = 0;            // most extraction entries of one local node
   int max_bu = 0;
   int *status = nullptr;
   // coarse

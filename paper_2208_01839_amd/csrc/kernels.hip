@@ -615,7 +615,7 @@ __global__ void k_pad_identity(ET *__restrict__ F, const SubInfo *__restrict__ s
 // row of a tile and 4 consecutive columns; the nonzero node blocks of its
 // row are the extraction entries of its local node.  Node-block values:
 // diagonal blocks from diag, off-diagonal block (c, c') = b_c + a_c [c = c'].
-template <int T, class ET>
+template <int T, class ET, int MAXE>
 __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const SubInfo *__restrict__ subs,
                                                        const int32_t *__restrict__ trow_ptr,
                                                        const int32_t *__restrict__ trow_sub,
@@ -643,9 +643,8 @@ __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const
     e0 = ent_ptr[nb];
     e1 = ent_ptr[nb + 1];
   }
-  // the row's node blocks held in registers (column node, value reference);
-  // nodes with more blocks than that search the entry list in memory
-  constexpr int MAXE = 16;
+  // the row's node blocks held in MAXE registers (column node, value
+  // reference); nodes with more blocks search the entry list in memory
   const int32_t ne = e1 - e0;
   const bool inreg = ne <= MAXE;
   int32_t qv[MAXE], rv[MAXE], qlo = INT32_MAX, qhi = -1;
@@ -2411,9 +2410,14 @@ void launch_check_state(const double *u, int64_t n, const int32_t *inst, int *fl
 
 template <int T, class ET>
 static void extract_t(const FactorLaunch &fl, ET *F, const double *diag, const double *off, hipStream_t st) {
-  if (fl.ntrows > 0)
-    hipLaunchKernelGGL((k_extract_tiles<T, ET>), dim3((unsigned)fl.ntrows), dim3(256), 0, st, F, fl.subs, fl.trow_ptr,
-                       fl.trow_sub, fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
+  if (fl.ntrows <= 0) return;
+  // a register slot per node block: 10 covers P1 meshes of node degree <= 9
+  if (fl.max_node_blocks <= 10)
+    hipLaunchKernelGGL((k_extract_tiles<T, ET, 10>), dim3((unsigned)fl.ntrows), dim3(256), 0, st, F, fl.subs,
+                       fl.trow_ptr, fl.trow_sub, fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
+  else
+    hipLaunchKernelGGL((k_extract_tiles<T, ET, 16>), dim3((unsigned)fl.ntrows), dim3(256), 0, st, F, fl.subs,
+                       fl.trow_ptr, fl.trow_sub, fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
 }
 
 template <int T>

@@ -377,6 +377,7 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
             fail(SEIRD_ERR_ARG, "internal: local matrix entry outside the stored tiles");
       }
       if (ph.extract.size() >= (size_t)INT32_MAX) fail(SEIRD_ERR_ARG, "too many local matrix blocks");
+      ph.max_node_blocks = std::max(ph.max_node_blocks, (int32_t)(ph.extract.size() - ph.ent_ptr.back()));
     }
     ph.trow_ptr.push_back(ph.trow_ptr.back() + si.nt);
     ph.trow_sub.insert(ph.trow_sub.end(), si.nt, s);

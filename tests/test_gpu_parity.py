@@ -150,6 +150,46 @@ def test_ras_apply_matches_oracle(small, tile, overlap):
     assert relerr(H(pc.apply(T(r), transpose=True)), ras.apply_T(r)) < 1e-11
 
 
+def _wheel_mesh(rings=8, spokes=24):
+    """Polar mesh: a centre node of degree `spokes` inside rings of `spokes`
+    nodes (every other node has degree <= 6); triangles counter-clockwise."""
+    xy = [(0.0, 0.0)]
+    for r in range(1, rings + 1):
+        for k in range(spokes):
+            t = 2 * np.pi * k / spokes
+            xy.append((r * np.cos(t), r * np.sin(t)))
+    node = lambda r, k: 1 + (r - 1) * spokes + k % spokes  # noqa: E731
+    tri = [(0, node(1, k), node(1, k + 1)) for k in range(spokes)]
+    for r in range(1, rings):
+        for k in range(spokes):
+            a, b, c, d = node(r, k), node(r, k + 1), node(r + 1, k + 1), node(r + 1, k)
+            tri += [(a, c, b), (a, d, c)]
+    return np.array(xy), np.array(tri, dtype=np.int32)
+
+
+@pytest.mark.parametrize("tile", [16, 32])
+@pytest.mark.parametrize("overlap", [1, 2])
+def test_ras_apply_with_a_high_degree_node(small, tile, overlap):
+    """A node with more blocks than the extraction holds in registers (its
+    rows search the entry list in memory) still gives the oracle's RAS."""
+    cfg = small[0]
+    xy, tri = _wheel_mesh()
+    n = len(xy)
+    part = (((np.arctan2(xy[:, 1], xy[:, 0]) + np.pi) / (2 * np.pi) * 4).astype(np.int32)) % 4
+    prob = sk.Problem(xy, tri, cfg.params)
+    geo = fem.Geometry(xy, tri)
+    rng = np.random.default_rng(11)
+    u = np.abs(cfg.u0[:n]) * rng.uniform(0.8, 1.2, (n, 5)) + rng.uniform(0.01, 0.1, (n, 5))
+    vals = prob.jacobian(T(u), cfg.dt)
+    pc = sk.Precond(prob, part, 4, overlap, tile=tile)
+    pc.setup(vals)
+    Jo = fem.jacobian(u, cfg.dt, geo, cfg.params)
+    ras = krylov.RAS(Jo, fem.node_graph(geo), part, 4, overlap)
+    r = rng.standard_normal(5 * n)
+    assert relerr(H(pc.apply(T(r))), ras.apply(r)) < 1e-11
+    assert relerr(H(pc.apply(T(r), transpose=True)), ras.apply_T(r)) < 1e-11
+
+
 @pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 3e-2)])
 def test_reduced_precision_factors_stay_close(small, prec, tol):
     cfg, prob, geo = small
