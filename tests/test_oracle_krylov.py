@@ -105,3 +105,127 @@ def test_newton_gmres_ras_reaches_direct_root():
     u2, _ = newton.newton_step(cfg.u0, cfg.dt, geo, cfg.params)
     assert np.abs(u1 - u2).max() <= 1e-9 * np.abs(u2).max()
     assert all(li["reason"] == "converged" for li in info["lin"])
+
+
+# ---------------------------------------------------------------------------
+# Pins of the restricted prolongation (Eq. RAS: Boolean D_i) and of the
+# three-step two-grid operator (Eqs. presmoother, coarsecorrection,
+# postsmoother), each with a planted mistake that the pin must catch.
+# ---------------------------------------------------------------------------
+
+def _decoupled_system(overlap):
+    """Jacobian of the small square with every coupling between nodes of
+    different owner subdomains removed: the matrix is block diagonal over
+    the partition, while the subdomains still overlap in the mesh graph."""
+    cfg = si.config_small(nx=16)
+    geo, J, b = _system(cfg)
+    node = np.arange(J.shape[0]) // krylov.NC
+    Jc = J.tocoo()
+    keep = cfg.part[node[Jc.row]] == cfg.part[node[Jc.col]]
+    Jd = sp.coo_matrix((Jc.data[keep], (Jc.row[keep], Jc.col[keep])), shape=J.shape).tocsr()
+    ras = krylov.RAS(Jd, fem.node_graph(geo), cfg.part, cfg.n_sub, overlap)
+    return Jd, ras, b
+
+
+def _asm_apply(ras, r):
+    """Additive Schwarz without the restriction D_i: every local copy is
+    added back (the mistake the owner-only prolongation must not make)."""
+    z = np.zeros_like(r)
+    for idx, own, lu in ras.subs:
+        z[idx] += lu.solve(r[idx])
+    return z
+
+
+def _ras_error_on_decoupled(apply, overlap):
+    Jd, ras, b = _decoupled_system(overlap)
+    x = spla.spsolve(Jd.tocsc(), b)
+    return np.linalg.norm(apply(ras, b) - x) / np.linalg.norm(x)
+
+
+def test_ras_is_exact_on_a_matrix_decoupled_along_the_partition():
+    """With A block diagonal over the owner sets, each local matrix splits
+    into the owned block and an unrelated overlap block, so the owned part of
+    A_i^{-1} R_i r is exactly (A^{-1} r) on the owned nodes: RAS (D_i = owner
+    indicator) returns A^{-1} r.  Adding every copy (ASM) does not."""
+    for overlap in (1, 2):
+        assert _ras_error_on_decoupled(krylov.RAS.apply, overlap) <= 1e-12
+        assert _ras_error_on_decoupled(_asm_apply, overlap) >= 1e-3
+
+
+def test_planted_asm_prolongation_is_caught(monkeypatch):
+    """Plant the ASM prolongation in the oracle's RAS: the decoupled-matrix
+    pin fails, and so does the transposed operator's adjointness."""
+    monkeypatch.setattr(krylov.RAS, "apply", lambda self, r: _asm_apply(self, r))
+    assert _ras_error_on_decoupled(krylov.RAS.apply, 1) > 1e-3
+    cfg = si.config_small(nx=16)
+    geo, J, _ = _system(cfg)
+    ras = krylov.RAS(J, fem.node_graph(geo), cfg.part, cfg.n_sub, 2)
+    rng = np.random.default_rng(5)
+    x, y = rng.standard_normal(J.shape[0]), rng.standard_normal(J.shape[0])
+    lhs, rhs = np.dot(ras.apply_T(x), y), np.dot(x, ras.apply(y))
+    assert abs(lhs - rhs) > 1e-6 * abs(rhs)
+
+
+def _dense(op, n):
+    return np.stack([op(e) for e in np.eye(n)], 1)
+
+
+def _two_level_pieces():
+    # dt = 10: diffusion strong enough that one RAS sweep is far from exact,
+    # so every stage of the recurrence leaves a visible mark on the operator
+    cfg = si.config_nested_square(n_base=4, n_ref=2, n_sub=16)
+    geo = fem.Geometry(cfg.xy, cfg.tri)
+    J = fem.jacobian(cfg.u0, 10.0, geo, cfg.params)
+    ras = krylov.RAS(J, fem.node_graph(geo), cfg.part, cfg.n_sub, cfg.overlap)
+    Zn = krylov.nested_interpolation(cfg.coarse_parents, cfg.coarse_n)
+    tl = krylov.TwoLevel(J, ras, Zn)
+    A = J.toarray()
+    n = A.shape[0]
+    Z = sp.kron(Zn, sp.identity(krylov.NC)).toarray()
+    Q = Z @ np.linalg.solve(Z.T @ A @ Z, Z.T)          # R_0^T A_c^{-1} R_0
+    M = _dense(ras.apply, n)
+    return tl, A, M, Q, n
+
+
+def _two_level_defects(apply):
+    """Distances of the dense two-grid operator M2 = [apply] from (a) the
+    error propagator (I - M A)(I - Q A)(I - M A) of the three-step recurrence
+    and (b) the operator P5 = P4 + P3 - P3 A P4, P4 = P1 + P2 - P2 A P1 with
+    P1 = P3 = M_RAS^{-1}, P2 = Q, as the substitution in Section 3.1 states."""
+    tl, A, M, Q, n = _two_level_pieces()
+    M2 = _dense(lambda r: apply(tl, r), n)
+    I = np.eye(n)
+    prop = (I - M @ A) @ (I - Q @ A) @ (I - M @ A)
+    P4 = M + Q - Q @ A @ M
+    P5 = P4 + M - M @ A @ P4
+    scale = np.abs(M2).max()
+    return (np.abs((I - M2 @ A) - prop).max(), np.abs(M2 - P5).max() / scale)
+
+
+def test_two_level_operator_matches_the_three_step_recurrence():
+    """Non-trivial nested coarse space (Z != I): the oracle's two-grid
+    operator is the multiplicative fine-coarse-fine correction."""
+    e_prop, e_p5 = _two_level_defects(krylov.TwoLevel.apply)
+    assert e_prop <= 1e-10
+    assert e_p5 <= 1e-12
+
+
+def test_planted_two_level_mistakes_are_caught():
+    """A dropped post-smoother, a dropped pre-smoother and an additive
+    (residual not updated) coarse correction each break the pin above."""
+    def no_post(tl, r):
+        z1 = tl.ras.apply(r)
+        return z1 + tl.coarse(r - tl.A @ z1)
+
+    def no_pre(tl, r):
+        z2 = tl.coarse(r)
+        return z2 + tl.ras.apply(r - tl.A @ z2)
+
+    def additive_coarse(tl, r):
+        z1 = tl.ras.apply(r)
+        z2 = z1 + tl.coarse(r)
+        return z2 + tl.ras.apply(r - tl.A @ z2)
+
+    for bad in (no_post, no_pre, additive_coarse):
+        e_prop, e_p5 = _two_level_defects(bad)
+        assert e_prop > 1e-2 and e_p5 > 1e-2, bad.__name__
