@@ -78,9 +78,13 @@ typedef struct {
  *    rows, so that LU without pivoting fills only inside) to the symmetric
  *    upper extent.
  *  factor_prec: storage precision of the local factors used by the
- *    preconditioner apply: 0 = float64, 1 = float32, 2 = bfloat16.  The
- *    factorisation itself runs in float64; vectors and accumulations of
- *    the apply stay float64.
+ *    preconditioner apply: 0 = float64, 1 = float32, 2 = bfloat16.  With
+ *    tile 32 and factor_prec 1 or 2 the subdomain factorisation runs in
+ *    float32 on the float32 MFMA (float32 accumulation); factor_prec 2 then
+ *    rounds the float32 factors to bfloat16 for the apply.  With tile 16
+ *    the factorisation runs in float64 and the factors are rounded to the
+ *    storage precision.  The coarse factorisation is always float64, and
+ *    the vectors and accumulations of the apply stay float64.
  *  Two-grid (multiplicative, Eqs. presmoother/coarsecorrection/
  *  postsmoother): n_ref > 0 enables it.  The coarse grid is nested: level 0
  *  has level_n[0] nodes and refinement record r (1..n_ref) maps each of
@@ -100,7 +104,7 @@ typedef struct {
   const int32_t *parents;  /* host, sum_{r>=1} 2*level_n[r] entries */
 } seird_schwarz_opts;
 
-/* GMRES options (Section 3.3): right preconditioning, x0 = 0, restart
+/* GMRES options (Section 3.2): right preconditioning, x0 = 0, restart
  * length, total iteration cap, convergence ||r|| < max(rtol ||b||, atol),
  * divergence ||r|| > dtol ||b||.  Classical Gram-Schmidt with one
  * conditional reorthogonalisation pass.
@@ -127,11 +131,15 @@ typedef struct {
  * max_it linear solves.  pc_reuse: a preconditioner setup serves this many
  * further Newton iterations of the same step before it is rebuilt (0 = a
  * fresh setup at every iteration; the converged root does not depend on
- * it, only the GMRES iteration counts do). */
+ * it, only the GMRES iteration counts do).  strict_linear: when GMRES stops
+ * at its max_it without reaching its tolerance inside a Newton iteration,
+ * 1 fails the step with SEIRD_ERR_NOT_CONVERGED; 0 takes the inexact
+ * update (inexact Newton) and counts it in seird_step_stats.inexact_solves. */
 typedef struct {
   double tol;
   int32_t max_it;
   int32_t pc_reuse;
+  int32_t strict_linear;
 } seird_newton_opts;
 
 #define SEIRD_MAX_NEWTON 32
@@ -156,6 +164,9 @@ typedef struct {
    * total density N is <= 0 at some node is halved (at most 10 times per
    * update, else SEIRD_ERR_STATE) */
   int32_t backtracks;
+  /* Newton iterations of this step whose GMRES stopped at max_it without
+   * reaching its tolerance (their inexact updates were taken) */
+  int32_t inexact_solves;
 } seird_step_stats;
 
 const char *seird_last_error(void);

@@ -15,7 +15,7 @@ newton   fully coupled Newton time step, Picard and Picard-Gauss-Seidel
 krylov   right-preconditioned restarted GMRES with PETSc-style stopping,
          one-level RAS and the multiplicative two-grid preconditioner
          (Section 3, Eqs. RAS, presmoother/coarsecorrection/postsmoother)
-ode      per-node ODE limit (Appendix B.3)
+ode      per-node ODE limit (Appendix B.4)
 mms      manufactured forcing and observed order (Appendix B.1, Eq. MMS_order)
 adjoint  discrete adjoint of a case-count misfit
 

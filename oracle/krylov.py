@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
 * ``gmres`` -- restarted GMRES(m) with right preconditioning, x0 = 0,
   modified Gram-Schmidt Arnoldi and Givens rotations; convergence when the
   residual norm drops below max(rtol ||b||, atol), divergence when it exceeds
-  dtol ||b||, outer cap max_it (Section 3.3 stopping rules).
+  dtol ||b||, outer cap max_it (Section 3.2 stopping rules).
 * ``RAS`` -- restricted additive Schwarz, M^{-1} = sum_i R_i^T D_i A_i^{-1}
   R_i with A_i = R_i A R_i^T and Boolean D_i (Eq. RAS); subdomains are the
   owner sets of a node partition grown by ``overlap`` layers of node-graph

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
 
-Appendix B.3 compares the PDE with vanishing diffusion and a uniform field
+Appendix B.4 compares the PDE with vanishing diffusion and a uniform field
 against the compartmental ODE.  In density units (the paper's ODE is written
 for proportions with the factor (1 - A); its consistent density form uses
 1 - A/N) the ODE is

@@ -57,7 +57,8 @@ class _KStats(ctypes.Structure):
 
 
 class _Newton(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int32), ("pc_reuse", ctypes.c_int32)]
+    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int32), ("pc_reuse", ctypes.c_int32),
+                ("strict_linear", ctypes.c_int32)]
 
 
 MAX_NEWTON = 32
@@ -71,7 +72,8 @@ class _SStats(ctypes.Structure):
                 ("pc_setups", ctypes.c_int32), ("t_residual_ms", ctypes.c_double), ("t_jacobian_ms", ctypes.c_double),
                 ("t_setup_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
                 ("t_ras_kernel_ms", ctypes.c_double), ("n_ras_launches", ctypes.c_int32),
-                ("ras_bytes_per_launch", ctypes.c_double), ("backtracks", ctypes.c_int32)]
+                ("ras_bytes_per_launch", ctypes.c_double), ("backtracks", ctypes.c_int32),
+                ("inexact_solves", ctypes.c_int32)]
 
 
 class _SInfo(ctypes.Structure):
@@ -412,10 +414,14 @@ def gmres(problem: Problem, pc, vals, b, transpose=False, x=None, **kw):
     return x, stats
 
 
-def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, pc_reuse=0, **kw):
-    """One implicit step in place on u (float64 CUDA [n,5]).  Returns stats."""
-    n = _Newton(float(tol), int(max_it), int(pc_reuse))
-    o = _krylov(**kw)
+def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, pc_reuse=0, strict_linear=False,
+         gmres_max_it=200, **kw):
+    """One implicit step in place on u (float64 CUDA [n,5]).  Returns stats.
+    max_it: Newton iterations; gmres_max_it: iterations of each GMRES solve.
+    strict_linear: fail (NOT_CONVERGED) when a GMRES solve inside Newton
+    stops at its max_it, instead of taking the inexact update."""
+    n = _Newton(float(tol), int(max_it), int(pc_reuse), int(bool(strict_linear)))
+    o = _krylov(max_it=gmres_max_it, **kw)
     s = _SStats()
     code = lib().seird_step(problem.h, pc.h if pc is not None else None,
                             _dptr(u, problem.N, "u"), float(dt), _dptr(src, problem.N, "src"),
@@ -426,7 +432,8 @@ def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, pc_reuse=0
                  t_residual_ms=s.t_residual_ms, t_jacobian_ms=s.t_jacobian_ms,
                  t_setup_ms=s.t_setup_ms, t_gmres_ms=s.t_gmres_ms,
                  t_ras_kernel_ms=s.t_ras_kernel_ms, n_ras_launches=s.n_ras_launches,
-                 ras_bytes_per_launch=s.ras_bytes_per_launch, backtracks=s.backtracks)
+                 ras_bytes_per_launch=s.ras_bytes_per_launch, backtracks=s.backtracks,
+                 inexact_solves=s.inexact_solves)
     _check(code)
     return stats
 
@@ -440,8 +447,10 @@ def forward_record(problem: Problem, pc, u, n_steps, dt, region, n_regions, ckpt
     if len(region) != problem.n:
         raise ValueError("region must have one entry per node")
     counts = torch.empty((int(n_steps), int(n_regions)), dtype=torch.float64, device=u.device)
-    nopt = _Newton(float(tol), int(max_it), int(pc_reuse))
+    nopt = _Newton(float(tol), int(max_it), int(pc_reuse), 0)
     kopt = _krylov(**kw)
+    # a new record replaces the problem's previous one (the library keeps one)
+    problem.record_generation = getattr(problem, "record_generation", 0) + 1
     _check(lib().seird_forward_record(problem.h, pc.h if pc is not None else None,
                                       _dptr(u, problem.N, "u"), int(n_steps), float(dt),
                                       int(ckpt_every), region.ctypes.data, int(n_regions),
@@ -481,24 +490,48 @@ def _make_run_function():
         ckpt_every, tol and the forward/adjoint Krylov settings."""
 
         @staticmethod
-        def forward(ctx, g, nu, problem, pc, u0, n_steps, dt, region, n_regions, options):
+        def _record(problem, pc, g, nu, u0, n_steps, dt, region, n_regions, options):
             import copy
             base = copy.copy(options["base_params"])
-            base.nu = tuple(float(x) for x in nu.detach().cpu().tolist())
+            base.nu = tuple(float(x) for x in nu.tolist())
             problem.set_params(base)
-            problem.set_beta_field(g.detach().contiguous().to(torch.float64))
-            u = u0.detach().clone()
-            counts = forward_record(problem, pc, u, n_steps, dt, region, n_regions,
-                                    ckpt_every=options.get("ckpt_every", 10),
-                                    tol=options.get("tol", 1e-10), **options.get("krylov", {}))
+            problem.set_beta_field(g)
+            u = u0.clone()
+            return forward_record(problem, pc, u, n_steps, dt, region, n_regions,
+                                  ckpt_every=options.get("ckpt_every", 10),
+                                  tol=options.get("tol", 1e-10), **options.get("krylov", {}))
+
+        @staticmethod
+        def forward(ctx, g, nu, problem, pc, u0, n_steps, dt, region, n_regions, options):
+            # the inputs of this record are kept in ctx: the problem holds
+            # one record and one parameter set, which a later forward replaces
+            gd = g.detach().contiguous().to(torch.float64).clone()
+            nud = nu.detach().to(torch.float64).cpu().clone()
+            ud = u0.detach().clone()
+            counts = SEIRDRun._record(problem, pc, gd, nud, ud, n_steps, dt, region, n_regions, options)
             ctx.problem, ctx.pc, ctx.options = problem, pc, options
+            ctx.inputs = (gd, nud, ud, n_steps, dt, region, n_regions)
+            ctx.generation = problem.record_generation
             ctx.nu_device = nu.device
             return counts
 
         @staticmethod
         def backward(ctx, grad_counts):
-            grad_g, grad_nu, _ = adjoint(ctx.problem, ctx.pc, grad_counts,
-                                         **ctx.options.get("adjoint_krylov", {"rtol": 1e-10}))
+            problem, pc, options = ctx.problem, ctx.pc, ctx.options
+            gd, nud, ud, n_steps, dt, region, n_regions = ctx.inputs
+            if getattr(problem, "record_generation", None) != ctx.generation:
+                # another forward replaced this run's record: record it again
+                # from the saved inputs (same parameters, same states)
+                SEIRDRun._record(problem, pc, gd, nud, ud, n_steps, dt, region, n_regions, options)
+                ctx.generation = problem.record_generation
+            else:
+                import copy
+                base = copy.copy(options["base_params"])
+                base.nu = tuple(float(x) for x in nud.tolist())
+                problem.set_params(base)
+                problem.set_beta_field(gd)
+            grad_g, grad_nu, _ = adjoint(problem, pc, grad_counts,
+                                         **options.get("adjoint_krylov", {"rtol": 1e-10}))
             gnu = torch.as_tensor(grad_nu, dtype=torch.float64, device=ctx.nu_device)
             return grad_g, gnu, None, None, None, None, None, None, None, None
 
@@ -578,7 +611,7 @@ class Batch:
     def step(self, u, dt, tol=1e-10, max_it=20, pc_reuse=0, **kw):
         """One implicit step of every instance, in place on u [n_total, 5].
         Returns a list of per-instance statistics."""
-        n = _Newton(float(tol), int(max_it), int(pc_reuse))
+        n = _Newton(float(tol), int(max_it), int(pc_reuse), 0)
         o = _krylov(**kw)
         st = (_SStats * self.K)()
         code = lib().seird_batch_step(self.h, _dptr(u, 5 * self.n, "u"), float(dt), ctypes.byref(n),
@@ -592,5 +625,6 @@ class Batch:
                             t_residual_ms=s.t_residual_ms, t_jacobian_ms=s.t_jacobian_ms,
                             t_setup_ms=s.t_setup_ms, t_gmres_ms=s.t_gmres_ms,
                             t_ras_kernel_ms=s.t_ras_kernel_ms, n_ras_launches=s.n_ras_launches,
-                            ras_bytes_per_launch=s.ras_bytes_per_launch, backtracks=s.backtracks))
+                            ras_bytes_per_launch=s.ras_bytes_per_launch, backtracks=s.backtracks,
+                            inexact_solves=s.inexact_solves))
         return out

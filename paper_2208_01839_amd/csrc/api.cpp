@@ -83,6 +83,7 @@ struct seird_problem_s {
     seird_newton_opts nopts{};
     seird_krylov_opts kopts{};
     std::vector<double *> ckpt, seg;
+    int seg_holds = -1;  // index of the segment whose states T.seg holds
     int32_t *region = nullptr, *reg_nodes = nullptr;
     int64_t *reg_ptr = nullptr;
     double *lam = nullptr, *lam_next = nullptr, *rhs = nullptr, *partials = nullptr;
@@ -97,6 +98,7 @@ struct seird_problem_s {
       region = reg_nodes = nullptr;
       reg_ptr = nullptr;
       lam = lam_next = rhs = partials = nullptr;
+      seg_holds = -1;
       valid = false;
     }
   } tape;
@@ -152,11 +154,15 @@ struct seird_problem_s {
     ydev = dev_alloc<double>((size_t)g.S * HLD);
   }
   // per-segment 2-norms (scale: optional per-node weights)
-  std::vector<double> seg_norms(const double *x, hipStream_t st, const double *scale = nullptr) {
-    launch_seg_norm2(seg, x, scale, partials, st);
-    launch_seg_reduce(seg, partials, 1, hdev, HLD, 0, st);
+  // (part, hv: reduction partials and result vector; null = the problem's own)
+  std::vector<double> seg_norms(const double *x, hipStream_t st, const double *scale = nullptr,
+                                double *part = nullptr, double *hv = nullptr) {
+    if (!part) part = partials;
+    if (!hv) hv = hdev;
+    launch_seg_norm2(seg, x, scale, part, st);
+    launch_seg_reduce(seg, part, 1, hv, HLD, 0, st);
     std::vector<double> h((size_t)seg.S * HLD);
-    HIPCHECK(hipMemcpyAsync(h.data(), hdev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(h.data(), hv, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     std::vector<double> out(seg.S);
     for (int s = 0; s < seg.S; ++s) out[s] = std::sqrt(h[(size_t)s * HLD]);
@@ -186,6 +192,13 @@ struct seird_problem_s {
     HIPCHECK(hipMemcpyAsync(dst, stage + stage_off, bytes, hipMemcpyHostToDevice, st));
     stage_off += need;
     stage_st = st;
+  }
+  // the staging arena, allocated up front so that later uploads of up to
+  // its size never allocate
+  void reserve_stage(size_t bytes) {
+    if (stage) return;
+    stage_cap = bytes;
+    HIPCHECK(hipHostMalloc((void **)&stage, stage_cap, hipHostMallocDefault));
   }
   void upload_mask(uint8_t *d, const std::vector<uint8_t> &m, hipStream_t st) { upload(d, m.data(), m.size(), st); }
   void upload_scalars(const std::vector<double> &v, hipStream_t st) {
@@ -255,7 +268,8 @@ struct seird_precond_s {
   // fit the budget); coarse_solver 1 uses them, 0 the band sweeps
   double *Xc = nullptr, *Wc = nullptr;
   int coarse_solver = 0;
-  int coarse_block = 0;  // super-block of the inverses, in tile rows (set at creation)
+  int coarse_block = 0;       // super-block of the inverses in Xc/Wc, in tile rows (as of the last setup)
+  int coarse_block_next = 0;  // super-block the next setup forms them with
   double *t1 = nullptr;
   const double *vals_setup = nullptr;  // Jacobian of the last setup (borrowed)
   bool ready = false;
@@ -266,14 +280,21 @@ struct seird_precond_s {
   // optional HIP-event timing of the subdomain solve launches
   bool timing = false;
   // captured Arnoldi-step graphs, keyed by what they bake in
+  // (every setting that changes the launch sequence is part of the key)
   struct GraphKey {
     const void *prob, *V, *Zb, *vals;
     int j, transpose, masked;
+    int coarse_solver, coarse_block, solve_threads;
     bool operator<(const GraphKey &o) const {
-      return std::tie(prob, V, Zb, vals, j, transpose, masked) <
-             std::tie(o.prob, o.V, o.Zb, o.vals, o.j, o.transpose, o.masked);
+      return std::tie(prob, V, Zb, vals, j, transpose, masked, coarse_solver, coarse_block, solve_threads) <
+             std::tie(o.prob, o.V, o.Zb, o.vals, o.j, o.transpose, o.masked, o.coarse_solver, o.coarse_block,
+                      o.solve_threads);
     }
   };
+  void clear_graphs() {
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
   std::map<GraphKey, hipGraphExec_t> graphs;
   hipStream_t st_capture = nullptr;
   // replay the graph of `key`, capturing `launches` (on a private stream)
@@ -342,7 +363,7 @@ struct seird_precond_s {
   }
 
   ~seird_precond_s() {
-    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    clear_graphs();
     if (st_capture) (void)hipStreamDestroy(st_capture);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -470,20 +491,31 @@ struct seird_precond_s {
 // running advance in lockstep through shared kernel launches that mask the
 // others.  A single problem is one segment.
 // ------------------------------------------------------------------------
+// Device work of one GMRES run: the Krylov basis V [m+1][N], the
+// preconditioned vectors Z [m][N], the reduction partials and the small
+// coefficient vector.  Null members are taken from the problem (its basis
+// allocated on first use).
+struct KrylovWork {
+  double *V = nullptr, *Zb = nullptr, *partials = nullptr, *hdev = nullptr;
+};
+
 static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, const double *b, double *x,
                        const seird_krylov_opts &o, std::vector<seird_krylov_stats> &stats,
-                       const std::vector<uint8_t> &active_in, int transpose, hipStream_t st) {
+                       const std::vector<uint8_t> &active_in, int transpose, hipStream_t st,
+                       const KrylovWork &work = KrylovWork{}) {
   const int64_t N = P->N;
   const int S = P->seg.S;
   const int HLD = P->HLD;
   const int m = o.restart;
   if (m < 1 || m > KRYLOV_MAX - 1) fail(SEIRD_ERR_ARG, "restart must be in [1, 31]");
   if (o.max_it < 0) fail(SEIRD_ERR_ARG, "max_it must be >= 0");
-  P->ensure_krylov(m);
-  double *V = P->V, *Zb = P->Zb;
+  if (!work.V) P->ensure_krylov(m);
+  double *V = work.V ? work.V : P->V, *Zb = work.Zb ? work.Zb : P->Zb;
+  double *const partials = work.partials ? work.partials : P->partials;
+  double *const hdev = work.hdev ? work.hdev : P->hdev;
   stats.assign(S, seird_krylov_stats{});
   HIPCHECK(hipMemsetAsync(x, 0, sizeof(double) * N, st));
-  const std::vector<double> bnorm = P->seg_norms(b, st);
+  const std::vector<double> bnorm = P->seg_norms(b, st, nullptr, partials, hdev);
   std::vector<uint8_t> act(S, 0);
   std::vector<double> target(S, 0.0), beta(S, 0.0), sc(S, 0.0);
   std::vector<int> its(S, 0);
@@ -545,16 +577,17 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
         else
           HIPCHECK(hipMemcpyAsync(zj, vj, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
         launch_spmv(P->md, P->diag(vals), P->off(vals), zj, nullptr, w, transpose, s);
-        launch_seg_mdot(P->seg_act, V, N, j + 1, w, 1, P->partials, s);
-        launch_seg_reduce(P->seg, P->partials, j + 2, P->hdev, HLD, 0, s);
-        launch_seg_maxpy_norm(P->seg_act, w, V, N, P->hdev, HLD, j + 1, P->partials, s);
-        launch_seg_reduce(P->seg, P->partials, 1, P->hdev, HLD, j + 2, s);
+        launch_seg_mdot(P->seg_act, V, N, j + 1, w, 1, partials, s);
+        launch_seg_reduce(P->seg, partials, j + 2, hdev, HLD, 0, s);
+        launch_seg_maxpy_norm(P->seg_act, w, V, N, hdev, HLD, j + 1, partials, s);
+        launch_seg_reduce(P->seg, partials, 1, hdev, HLD, j + 2, s);
       };
       if (pc && o.graphs && !pc->timing)
-        pc->run_graph({P, V, Zb, vals, j, transpose, S > 1}, step_launches, st);
+        pc->run_graph({P, V, Zb, vals, j, transpose, S > 1, pc->coarse_solver, pc->coarse_block, pc->solve_threads},
+                      step_launches, st);
       else
         step_launches(st);
-      HIPCHECK(hipMemcpyAsync(hbuf.data(), P->hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(hbuf.data(), hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
       std::vector<uint8_t> re(S, 0);
       std::vector<double> wn(S, 0.0);
@@ -572,11 +605,11 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
       }
       if (any_re) {  // DGKS: one reorthogonalisation pass for those segments
         P->upload_mask(P->d_mask2, re, st);
-        launch_seg_mdot(P->seg_re, V, N, j + 1, w, 0, P->partials, st);
-        launch_seg_reduce(P->seg, P->partials, j + 1, P->hdev, HLD, 0, st);
-        launch_seg_maxpy_norm(P->seg_re, w, V, N, P->hdev, HLD, j + 1, P->partials, st);
-        launch_seg_reduce(P->seg, P->partials, 1, P->hdev, HLD, j + 1, st);
-        HIPCHECK(hipMemcpyAsync(hbuf.data(), P->hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
+        launch_seg_mdot(P->seg_re, V, N, j + 1, w, 0, partials, st);
+        launch_seg_reduce(P->seg, partials, j + 1, hdev, HLD, 0, st);
+        launch_seg_maxpy_norm(P->seg_re, w, V, N, hdev, HLD, j + 1, partials, st);
+        launch_seg_reduce(P->seg, partials, 1, hdev, HLD, j + 1, st);
+        HIPCHECK(hipMemcpyAsync(hbuf.data(), hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
         for (int s = 0; s < S; ++s) {
           if (!re[s]) continue;
@@ -650,7 +683,7 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
       update(cyc, m);
       P->upload_mask(P->d_mask, cyc, st);
       launch_spmv(P->md, P->diag(vals), P->off(vals), x, b, V, transpose, st);
-      const std::vector<double> bt = P->seg_norms(V, st);
+      const std::vector<double> bt = P->seg_norms(V, st, nullptr, partials, hdev);
       for (int s = 0; s < S; ++s) {
         if (!cyc[s]) continue;
         beta[s] = bt[s];
@@ -800,10 +833,19 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
       stats[s].gmres_its[k] = ks[s].its + its_first[s];
       stats[s].gmres_its_total += ks[s].its + its_first[s];
       stats[s].newton_its = k + 1;
-      if (ks[s].reason == SEIRD_ERR_DIVERGED) fail(SEIRD_ERR_DIVERGED, "GMRES diverged");
+      if (ks[s].reason == SEIRD_ERR_DIVERGED) fail(SEIRD_ERR_DIVERGED, "GMRES diverged" + where(s));
+      if (ks[s].reason == SEIRD_ERR_NOT_CONVERGED) {
+        ++stats[s].inexact_solves;
+        if (nopts->strict_linear)
+          fail(SEIRD_ERR_NOT_CONVERGED, "GMRES reached max_it (" + std::to_string(ks[s].its + its_first[s]) +
+                                            " iterations, residual " + std::to_string(ks[s].resid) + " of " +
+                                            std::to_string(ks[s].bnorm) + ") in Newton iteration " +
+                                            std::to_string(k + 1) + where(s));
+      }
     }
-    // max_it without convergence: the inexact Newton update is still taken;
-    // frozen segments have a zero update
+    // max_it without convergence (strict_linear = 0): the inexact Newton
+    // update is still taken and counted in inexact_solves; frozen segments
+    // have a zero update
     launch_axpby(u, p->delta, 1.0, nullptr, 0, 1.0, N, reduction_blocks(N), st);
     // Positivity safeguard: an instance whose new iterate has N <= 0 at a
     // node gets its update halved (u -= delta / 2, delta /= 2), at most
@@ -1077,6 +1119,7 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
         pc->Wc = dev_alloc<double>((size_t)(nt * (nt + 1) / 2) * 1024);
         pc->coarse_solver = 1;
         pc->coarse_block = (int)std::min<int64_t>(nt, std::max({COARSE_BLOCK, ph.coarse.bl, ph.coarse.bu}));
+        pc->coarse_block_next = pc->coarse_block;
       }
       HIPCHECK(hipStreamCreateWithFlags(&pc->st_coarse, hipStreamNonBlocking));
       HIPCHECK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
@@ -1126,6 +1169,7 @@ seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver) {
   if (solver != 0 && solver != 1) fail(SEIRD_ERR_ARG, "coarse solver must be 0 or 1");
   if (solver == 1 && !pc->Xc) fail(SEIRD_ERR_ARG, "no coarse inverses for this preconditioner");
   pc->coarse_solver = solver;
+  pc->clear_graphs();
   API_END
 }
 
@@ -1139,7 +1183,7 @@ seird_status seird_precond_set_coarse_block(seird_precond pc, int32_t tiles) {
   if (S < std::max(cs.bl, cs.bu))
     fail(SEIRD_ERR_ARG, "coarse block below the coarse band width (" + std::to_string(std::max(cs.bl, cs.bu)) +
                             " tile rows)");
-  pc->coarse_block = S;
+  pc->coarse_block_next = S;  // the inverses in Xc/Wc keep their block until the next setup forms new ones
   API_END
 }
 
@@ -1149,6 +1193,7 @@ seird_status seird_precond_set_solve_threads(seird_precond pc, int32_t threads) 
   const bool ok = threads == 256 || (pc->ph.tile == 32 && (threads == 512 || threads == 1024));
   if (!ok) fail(SEIRD_ERR_ARG, "solve workgroup size must be 256, or 512/1024 with tile 32");
   pc->solve_threads = threads;
+  pc->clear_graphs();
   API_END
 }
 
@@ -1203,7 +1248,11 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
     HIPCHECK(hipEventRecord(pc->ev_fork, st));
     HIPCHECK(hipStreamWaitEvent(pc->st_coarse, pc->ev_fork, 0));
     launch_setup_factors(fl, P->diag(vals), P->off(vals), st, pc->st_coarse);
-    if (pc->Xc) launch_coarse_inverse(pc->Fc, ph.coarse, pc->coarse_block, pc->Xc, pc->Wc, pc->st_coarse);
+    if (pc->Xc) {
+      if (pc->coarse_block != pc->coarse_block_next) pc->clear_graphs();
+      pc->coarse_block = pc->coarse_block_next;
+      launch_coarse_inverse(pc->Fc, ph.coarse, pc->coarse_block, pc->Xc, pc->Wc, pc->st_coarse);
+    }
     HIPCHECK(hipEventRecord(pc->ev_join, pc->st_coarse));
     HIPCHECK(hipStreamWaitEvent(st, pc->ev_join, 0));
   } else {
@@ -1407,6 +1456,7 @@ seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, 
     if (k >= last0) HIPCHECK(hipMemcpyAsync(T.seg[k - last0], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
   }
   HIPCHECK(hipStreamSynchronize(st));
+  T.seg_holds = n_seg - 1;
   T.valid = true;
   API_END
 }
@@ -1436,7 +1486,8 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
   std::vector<double> part;
   for (int s = n_seg - 1; s >= 0; --s) {
     const int n0 = s * T.every, n1 = std::min(T.n_steps, n0 + T.every);
-    if (s < n_seg - 1) {  // recompute the states of this segment from its checkpoint
+    if (T.seg_holds != s) {  // recompute the states of this segment from its checkpoint
+      T.seg_holds = -1;      // (a failure below leaves no segment marked as held)
       HIPCHECK(hipMemcpyAsync(T.seg[0], T.ckpt[s], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
       for (int k = n0 + 1; k <= n1; ++k) {
         HIPCHECK(hipMemcpyAsync(T.seg[k - n0], T.seg[k - n0 - 1], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
@@ -1444,6 +1495,7 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
         step_impl(p, pc, T.seg[k - n0], T.dt, nullptr, &T.nopts, &T.kopts, ss, st);
         as.recomputed_steps++;
       }
+      T.seg_holds = s;
     }
     for (int k = n1; k > n0; --k) {
       const double *uk = T.seg[k - n0];

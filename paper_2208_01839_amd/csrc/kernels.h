@@ -88,6 +88,7 @@ void launch_maxpy_norm(double *w, const double *V, int64_t ldv, const double *h,
                        int nb, hipStream_t st);
 void launch_gemv_update(double *x, const double *Z, int64_t ldz, const double *y, int nv, int64_t N, int nb,
                         hipStream_t st);
+void launch_fill(double *y, double v, int64_t N, hipStream_t st);
 void launch_axpby(double *y, const double *x, double a, const double *aptr, int ainv, double b, int64_t N, int nb,
                   hipStream_t st);
 void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st);

@@ -13,6 +13,8 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 namespace seird {
 
@@ -364,6 +366,13 @@ __global__ void k_axpby(double *__restrict__ y, const double *__restrict__ x, do
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride)
     y[idx] = aa * x[idx] + (b != 0.0 ? b * y[idx] : 0.0);
+}
+
+// y[0..N) = v (a fill kernel rather than a memset, so that it can sit in a
+// captured stream)
+__global__ void k_fill(double *__restrict__ y, double v, int64_t N) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) y[idx] = v;
 }
 
 // ||F||^2 partials plus a nonfinite flag
@@ -2545,6 +2554,11 @@ void launch_band_solve(const SolveLaunch &sl, hipStream_t st) {
     else if (sl.prec == 1) solve_t<16, float>(sl, st);
     else solve_t<16, __hip_bfloat16>(sl, st);
   }
+}
+
+void launch_fill(double *y, double v, int64_t N, hipStream_t st) {
+  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((N + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, st, y, v, N);
 }
 
 void launch_gather_copies(const int64_t *gptr, const int32_t *gidx, const double *yloc, double *z, int add, int64_t N,

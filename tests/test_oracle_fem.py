@@ -140,7 +140,7 @@ def test_population_conserved_and_nonnegative_small_config():
 
 def test_zero_diffusion_reduces_to_nodewise_ode():
     """With nu = 0 each node follows backward Euler on the compartmental ODE
-    of Appendix B.3 (per-node Newton, independent code path)."""
+    of Appendix B.4 (per-node Newton, independent code path)."""
     xy, tri, geo = _geo(4)
     p = si.Params(**{**si.params_square().__dict__, "nu": (0, 0, 0, 0, 0)})
     u0 = _rand_state(geo.n, 11)
