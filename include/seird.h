@@ -325,6 +325,31 @@ seird_status seird_gmres(seird_problem p, seird_precond pc, const double *vals,
                          seird_krylov_stats *stats, int transpose,
                          void *stream);
 
+/* Allocation-free GMRES, for callers that cannot allocate device memory
+ * (serving loops with a fixed memory budget, harnesses that forbid
+ * hipMalloc during a run).  The same solve as seird_gmres, with the same
+ * arguments, kernels and results, except that its scratch -- the Krylov
+ * basis V [restart+1][N], the preconditioned vectors Z [restart][N], the
+ * reduction partials and the Arnoldi coefficients -- lives in a fixed
+ * device array of SEIRD_STATIC_SCRATCH_BYTES compiled into the library:
+ * one per GPU, held from the library's first use on that GPU until the
+ * process ends.  The call allocates no device memory (the problem and
+ * the preconditioner were created beforehand; the problem's pinned staging
+ * buffer is reserved at its creation), and HIP graphs are not used
+ * (opts->graphs is ignored).  Limits: (2 restart + 1) * N * 8 bytes plus a
+ * few KB must fit the array, else SEIRD_ERR_ARG (N = 5 n_nodes; restart 30
+ * admits about 137k unknowns); a single problem (not a batch's);
+ * preconditioner timing must be off (SEIRD_ERR_ARG).  Every call on one GPU
+ * shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (other host threads, other streams) race and must be
+ * serialised by the caller.  Synchronising, like seird_gmres. */
+#define SEIRD_STATIC_SCRATCH_BYTES (64LL << 20)
+seird_status seird_gmres_noalloc(seird_problem p, seird_precond pc,
+                                 const double *vals, const double *b,
+                                 double *x, const seird_krylov_opts *opts,
+                                 seird_krylov_stats *stats, int transpose,
+                                 void *stream);
+
 /* One implicit step: u (in: u^n, out: u^{n+1}).  Newton iterations: F,
  * J, preconditioner setup, GMRES, update.  Synchronising.  On failure u is
  * unspecified and stats->reason holds the status. */

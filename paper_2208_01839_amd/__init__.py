@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Problem", "Precond", "Batch", "SeirdError", "autotune", "gmres", "step",
+__all__ = ["Problem", "Precond", "Batch", "SeirdError", "autotune", "gmres", "gmres_noalloc", "step",
            "forward_record", "adjoint", "SEIRDRun", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -134,6 +134,8 @@ _SIGS = {
     "seird_precond_apply": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
     "seird_gmres": ([_P, _P, _P, _P, _P, ctypes.POINTER(_Krylov),
                      ctypes.POINTER(_KStats), ctypes.c_int, _P], ctypes.c_int),
+    "seird_gmres_noalloc": ([_P, _P, _P, _P, _P, ctypes.POINTER(_Krylov),
+                             ctypes.POINTER(_KStats), ctypes.c_int, _P], ctypes.c_int),
     "seird_step": ([_P, _P, _P, ctypes.c_double, _P, ctypes.POINTER(_Newton),
                     ctypes.POINTER(_Krylov), ctypes.POINTER(_SStats), _P], ctypes.c_int),
     "seird_forward_record": ([_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
@@ -412,6 +414,25 @@ def gmres(problem: Problem, pc, vals, b, transpose=False, x=None, **kw):
     if code not in (0, -7):
         _check(code)
     return x, stats
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def gmres_noalloc(problem: Problem, pc, vals, b, x, transpose=False, **kw):
+    """seird_gmres_noalloc: the solve of ``gmres`` with its Krylov scratch in
+    the library's fixed per-GPU array (no device allocation in the call).
+    ``x`` (the output) must be given.  Returns the stats dict."""
+    o = _krylov(**kw)
+    s = _KStats()
+    code = lib().seird_gmres_noalloc(problem.h, pc.h if pc is not None else None,
+                                     _dptr(vals, problem.nvals, "vals"), _dptr(b, problem.N, "b"),
+                                     _dptr(x, problem.N, "x"), ctypes.byref(o), ctypes.byref(s),
+                                     int(bool(transpose)), _stream())
+    stats = dict(its=s.its, reason=s.reason, resid=s.resid, bnorm=s.bnorm, status=code)
+    if code not in (0, -7):
+        _check(code)
+    return stats
 
 
 def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, pc_reuse=0, strict_linear=False,

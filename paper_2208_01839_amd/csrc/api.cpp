@@ -514,7 +514,7 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
   double *const partials = work.partials ? work.partials : P->partials;
   double *const hdev = work.hdev ? work.hdev : P->hdev;
   stats.assign(S, seird_krylov_stats{});
-  HIPCHECK(hipMemsetAsync(x, 0, sizeof(double) * N, st));
+  launch_fill(x, 0.0, N, st);
   const std::vector<double> bnorm = P->seg_norms(b, st, nullptr, partials, hdev);
   std::vector<uint8_t> act(S, 0);
   std::vector<double> target(S, 0.0), beta(S, 0.0), sc(S, 0.0);
@@ -943,6 +943,8 @@ seird_status seird_problem_create(int64_t n_nodes, const double *xy, int64_t n_t
     P->delta = dev_alloc<double>(P->N);
     P->w1 = dev_alloc<double>(P->N);
     P->vals = dev_alloc<double>(P->nvals());
+    P->reserve_stage((size_t)1 << 20);
+    (void)static_scratch();  // this device's scratch address, looked up once
   } catch (...) {
     delete P;
     throw;
@@ -1379,6 +1381,47 @@ seird_status seird_gmres(seird_problem p, seird_precond pc, const double *vals, 
   if (!p || !vals || !b || !x || !opts) fail(SEIRD_ERR_ARG, "null argument");
   std::vector<seird_krylov_stats> all;
   gmres_impl(p, pc, vals, b, x, *opts, all, std::vector<uint8_t>(p->seg.S, 1), transpose, (hipStream_t)stream);
+  const int rc = all[0].reason < 0 ? all[0].reason : SEIRD_OK;
+  if (stats) *stats = all[0];
+  if (rc != SEIRD_OK) {
+    g_last_error = rc == SEIRD_ERR_DIVERGED ? "GMRES diverged" : "GMRES reached max_it";
+    return rc;
+  }
+  API_END
+}
+
+seird_status seird_gmres_noalloc(seird_problem p, seird_precond pc, const double *vals, const double *b, double *x,
+                                 const seird_krylov_opts *opts, seird_krylov_stats *stats, int transpose,
+                                 void *stream) {
+  API_BEGIN
+  if (!p || !vals || !b || !x || !opts) fail(SEIRD_ERR_ARG, "null argument");
+  if (p->seg.S != 1) fail(SEIRD_ERR_ARG, "seird_gmres_noalloc takes a single problem");
+  if (pc && pc->timing) fail(SEIRD_ERR_ARG, "seird_gmres_noalloc needs preconditioner timing off");
+  const int m = opts->restart;
+  if (m < 1 || m > KRYLOV_MAX - 1) fail(SEIRD_ERR_ARG, "restart must be in [1, 31]");
+  // carve the static scratch: coefficient vector, reduction partials,
+  // V [m+1][N], Z [m][N], each 256-byte aligned
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t hbytes = up(sizeof(double) * (size_t)p->HLD);
+  const size_t pbytes = up(sizeof(double) * (size_t)p->seg.B * (KRYLOV_MAX + 2));
+  const size_t vbytes = up(sizeof(double) * (size_t)(m + 1) * (size_t)p->N);
+  const size_t zbytes = up(sizeof(double) * (size_t)m * (size_t)p->N);
+  const size_t need = hbytes + pbytes + vbytes + zbytes;
+  if (need > STATIC_SCRATCH_BYTES)
+    fail(SEIRD_ERR_ARG, "seird_gmres_noalloc: restart " + std::to_string(m) + " with " + std::to_string(p->N) +
+                            " unknowns needs " + std::to_string(need) + " bytes of scratch, above the " +
+                            std::to_string((size_t)STATIC_SCRATCH_BYTES) +
+                            " bytes of SEIRD_STATIC_SCRATCH_BYTES ((2 restart + 1) N 8 bytes plus a few KB)");
+  unsigned char *base = (unsigned char *)static_scratch();
+  KrylovWork w;
+  w.hdev = (double *)base;
+  w.partials = (double *)(base + hbytes);
+  w.V = (double *)(base + hbytes + pbytes);
+  w.Zb = (double *)(base + hbytes + pbytes + vbytes);
+  seird_krylov_opts o = *opts;
+  o.graphs = 0;  // graph instantiation allocates
+  std::vector<seird_krylov_stats> all;
+  gmres_impl(p, pc, vals, b, x, o, all, std::vector<uint8_t>(1, 1), transpose, (hipStream_t)stream, w);
   const int rc = all[0].reason < 0 ? all[0].reason : SEIRD_OK;
   if (stats) *stats = all[0];
   if (rc != SEIRD_OK) {

@@ -6,6 +6,11 @@
 namespace seird {
 
 constexpr int KRYLOV_MAX = 32;  // max basis vectors handled by one Arnoldi kernel
+// size of the per-device static scratch of the allocation-free entry points
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)SEIRD_STATIC_SCRATCH_BYTES;
+// device address of this device's static scratch (looked up once per
+// device, with that device current; valid until the process ends)
+void *static_scratch();
 constexpr int SEG_CH = 1024;    // entries per block of a segmented reduction
 
 struct SegView;

@@ -2561,6 +2561,32 @@ void launch_fill(double *y, double v, int64_t N, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, st, y, v, N);
 }
 
+// ----------------------------------------------------------------------
+// Fixed device scratch of the allocation-free entry points: one array per
+// GPU, resident from the first load of this code object until the process
+// ends.  Host code never passes the array's name to a kernel (on the host
+// it is only a stand-in for the symbol): its device address is looked up
+// once per device with hipGetSymbolAddress, with that device current, and
+// that address is what kernels receive.
+// ----------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+void *static_scratch() {
+  static std::mutex mu;
+  static std::vector<void *> addr;  // per device
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void *ptr = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(SEIRD_ERR_HIP, "no device address for the static scratch");
+    addr[dev] = ptr;
+  }
+  return addr[dev];
+}
+
 void launch_gather_copies(const int64_t *gptr, const int32_t *gidx, const double *yloc, double *z, int add, int64_t N,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_gather_copies, dim3(nblocks(N)), dim3(256), 0, st, gptr, gidx, yloc, z, add, N);
