@@ -11,11 +11,15 @@ scaled residual is below 1e-10.  Inputs are resident in HBM before timing.
 Prints ONE JSON line (rank 0).  --prec selects the storage precision of the
 subdomain factors of the main leg (0 FP64, 1 FP32, 2 BF16); unless
 --no-compare-prec, FP32 and BF16 legs on the same steps follow and are
-reported in "mixed".  The ensemble leg ("batch") steps 48 uneven instances
-together; the adjoint leg ("adjoint") times one misfit gradient.  The CPU
-baseline is the FP64 oracle (numpy/scipy) timed on a bounded sample of the
-same workload (a nested mesh of the same kind with 32x fewer nodes, same
-subdomain size), scaled to 5M unknowns by the unknown ratio.
+reported in "mixed", with each field's error at step 30 against the FP64
+leg and, on the 32x smaller nested instance of the same recipe, against the
+oracle's stored step-30 state.  The ensemble leg ("batch") steps 48 uneven
+instances together; the adjoint leg ("adjoint") times one misfit gradient of
+the differentiation workload (~2M nodes, 60 daily steps, checkpoints every
+10 steps).  The CPU baseline is the FP64 oracle (numpy/scipy) timed on the
+host's cores on a bounded sample of the same workload (independent steps
+of the nested instance, one per worker process), scaled to 5M unknowns by
+the unknown ratio.
 """
 import argparse
 import json
@@ -35,6 +39,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+FIELDS = ("S", "E", "I", "R", "D")
+
+
+def per_field_errors(u, ref):
+    """Relative error of every compartment: max norm and 2-norm."""
+    import numpy as np
+    u = np.asarray(u).reshape(-1, 5)
+    ref = np.asarray(ref).reshape(-1, 5)
+    out = {}
+    for c, name in enumerate(FIELDS):
+        d, r = u[:, c] - ref[:, c], ref[:, c]
+        out[name] = {"linf_rel": float(np.abs(d).max() / max(np.abs(r).max(), 1e-300)),
+                     "l2_rel": float(np.linalg.norm(d) / max(np.linalg.norm(r), 1e-300))}
+    return out
+
+
 def build_workload(args):
     import seird_inputs as si
     if args.workload == "small":
@@ -46,7 +66,7 @@ def build_workload(args):
     return cfg, coarse
 
 
-def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0, threads=256):
+def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0, threads=256, until=0):
     prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
     tune = None
     if tile == "auto":
@@ -81,7 +101,13 @@ def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0, thr
             f"{st['t_residual_ms']:.1f}/{st['t_jacobian_ms']:.1f}/{st['t_setup_ms']:.1f}/{st['t_gmres_ms']:.1f}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return dict(seconds=t1 - t0, stats=stats, info=info, u=u, tile=tile, solve_threads=threads, tune=tune)
+    perf = pc.perf(reset=True)
+    # untimed steps up to `until` (the precision comparison is at step 30)
+    for k in range(warmup + steps, until):
+        sk.step(prob, pc, u, cfg.dt, **kw)
+    torch.cuda.synchronize()
+    return dict(seconds=t1 - t0, stats=stats, info=info, u=u, tile=tile, solve_threads=threads, tune=tune,
+                perf=perf, prob=prob, pc=pc, steps_done=max(until, warmup + steps))
 
 
 def adjoint_bench(sk, torch, args, cfg, coarse):
@@ -90,10 +116,12 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
     diffusion coefficients; checkpoints every 10 steps (5 for short runs)."""
     import numpy as np
     import seird_inputs as si
-    if args.adjoint_full:
+    if args.adjoint == "full":
+        t = time.perf_counter()
         cfg = si.config_differentiation()
         coarse = (cfg.coarse_parents, cfg.coarse_n)
         steps, every = cfg.steps, 10
+        log(f"[bench] adjoint workload {cfg.name} built ({time.perf_counter() - t:.1f} s)")
     else:
         steps = args.adjoint_steps
         every = 10 if steps >= 20 else 5
@@ -125,7 +153,10 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
     return {"metric": "adjoint gradients/s", "value": 1.0 / (t2 - t0), "unit": "grads/s",
             "workload": (f"{cfg.name}: {cfg.n} nodes ({5 * cfg.n} unknowns), {steps} daily steps, "
                          f"checkpoint every {every}, 40 Voronoi regions, gradient w.r.t. the per-node "
-                         f"transmission field and 5 diffusion coefficients"),
+                         f"transmission field and 5 diffusion coefficients, two-grid RAS {cfg.n_sub} "
+                         f"subdomains, base transmission beta_I = beta_E = {cfg.params.beta_I}"
+                         + (" (0.006 instead of 0.01 keeps dt*beta*g*max N below 1 on this mesh)"
+                            if args.adjoint == "full" else "")),
             "forward_s": t1 - t0, "reverse_s": t2 - t1,
             "transposed_gmres_its": st["gmres_its_total"], "recomputed_steps": st["recomputed_steps"],
             "misfit": float(((counts - truth) ** 2).sum().item()),
@@ -202,8 +233,9 @@ def batch_bench(sk, torch, args):
             "unknowns": 5 * bc.n, "ms_per_step": 1e3 * sec / args.batch_steps,
             "steps": args.batch_steps,
             "workload": (f"{bc.name}: {len(sizes)} seeded realistic-type instances of "
-                         f"{min(sizes)}-{max(sizes)} nodes ({5 * bc.n} unknowns), beta and nu_c "
-                         f"x U(0.7,1.3) per instance, dt 1 day, Newton tol {c0.newton_tol}, "
+                         f"{min(sizes)}-{max(sizes)} nodes ({5 * bc.n} unknowns), beta = 0.006 and "
+                         f"nu_c each x U(0.7,1.3) per instance (base 0.006 keeps dt*beta*max N below 1 on "
+                         f"every instance), dt 1 day, Newton tol {c0.newton_tol}, "
                          f"GMRES({c0.gmres_restart}) rtol {c0.gmres_rtol}, one-level RAS "
                          f"{sum(c.n_sub for c in bc.instances)} subdomains overlap {bc.overlap}, "
                          f"factor_prec {args.batch_prec}, pc_reuse {args.pc_reuse}"),
@@ -215,41 +247,151 @@ def batch_bench(sk, torch, args):
             "generate_s": t_gen, "create_s": t_create}
 
 
-def cpu_baseline(args):
-    """The oracle as it stands, timed on the host on a bounded sample."""
-    import numpy as np
+def _oracle_sample_worker(args_tuple):
+    """One worker of the CPU baseline: build the nested sample and time
+    ``n_steps`` oracle steps on it (BLAS limited to one thread)."""
+    n_base, n_ref, n_sub, n_steps = args_tuple
+    import time as _t
+    from threadpoolctl import threadpool_limits
     import seird_inputs as si
     from oracle import fem, krylov, newton
-    # same nesting depth and subdomain size, 32x fewer base nodes
-    cfg = si.config_realistic(n_base=max(40, args.n_base // 32), n_ref=args.n_ref,
-                              n_sub=max(1, args.n_sub // 32))
-    geo = fem.Geometry(cfg.xy, cfg.tri)
-    ls = krylov.make_linsolve(geo, cfg.part, cfg.n_sub, cfg.overlap,
-                              coarse=(cfg.coarse_parents, cfg.coarse_n),
-                              restart=cfg.gmres_restart, rtol=cfg.gmres_rtol)
+    with threadpool_limits(limits=1):
+        cfg = si.config_realistic(n_base=n_base, n_ref=n_ref, n_sub=n_sub)
+        geo = fem.Geometry(cfg.xy, cfg.tri)
+        ls = krylov.make_linsolve(geo, cfg.part, cfg.n_sub, cfg.overlap,
+                                  coarse=(cfg.coarse_parents, cfg.coarse_n),
+                                  restart=cfg.gmres_restart, rtol=cfg.gmres_rtol)
+        u = cfg.u0.copy()
+        t0 = _t.perf_counter()
+        its = []
+        for _ in range(n_steps):
+            u, info = newton.newton_step(u, cfg.dt, geo, cfg.params, tol=cfg.newton_tol, linsolve=ls)
+            its.append(info["newton_its"])
+        return _t.perf_counter() - t0, cfg.n, its
+
+
+def cpu_baseline(args):
+    """The oracle as it stands, timed on the host's cores on a bounded
+    sample: every worker process runs ``--cpu-steps`` implicit steps of the
+    nested instance of the same recipe (32x fewer nodes, same refinement
+    depth and subdomain size, two-grid RAS, subdomain sparse LU) with BLAS
+    on one thread; the machine's rate is the sum of the workers' rates,
+    scaled to the full workload by the unknown ratio."""
+    import multiprocessing as mp
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except Exception:  # pragma: no cover
+        avail = os.cpu_count() or 1
+    workers = max(1, min(args.cpu_workers, avail))
+    job = (max(40, args.n_base // 32), args.n_ref, max(1, args.n_sub // 32), args.cpu_steps)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
     t0 = time.perf_counter()
-    u1, info = newton.newton_step(cfg.u0, cfg.dt, geo, cfg.params, tol=cfg.newton_tol, linsolve=ls)
-    dt = time.perf_counter() - t0
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_sample_worker, [job] * workers)
+    wall = time.perf_counter() - t0
+    n_sample = res[0][1]
     full_unknowns = 5 * args.full_nodes
-    steps_per_s = (1.0 / dt) * (5 * cfg.n) / full_unknowns
+    rate = sum(args.cpu_steps / r[0] for r in res)  # sample steps/s over all workers
+    cpu_model = ""
     try:
-        threads = len(os.sched_getaffinity(0))
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count()
-    try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        blas_threads = None
-    return {"value": steps_per_s, "unit": "steps/s", "cores": 1,
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    return {"value": rate * (5 * n_sample) / full_unknowns, "unit": "steps/s", "cores": workers,
             "kind": "oracle",
-            "sample": (f"first implicit step of a {cfg.n}-node ({5 * cfg.n} unknowns) nested "
-                       f"polygon mesh of the same kind ({cfg.n_sub} subdomains of the same size, "
-                       f"two-grid RAS, subdomain sparse LU), {dt:.2f} s, Newton its "
-                       f"{info['newton_its']}; steps/s scaled to {full_unknowns} unknowns by the "
-                       f"unknown ratio (linear-cost assumption)"),
-            "host_threads_available": threads, "blas_threads": blas_threads,
-            "seconds": dt}
+            "sample": (f"{workers} worker processes (one core each, BLAS on one thread), each timing "
+                       f"{args.cpu_steps} implicit steps of a {n_sample}-node ({5 * n_sample} unknowns) "
+                       f"nested polygon mesh of the same recipe (32x fewer nodes, same subdomain size, "
+                       f"two-grid RAS with subdomain sparse LU, Newton tol 1e-10, GMRES rtol 1e-5); "
+                       f"step times {', '.join(f'{r[0] / args.cpu_steps:.2f}' for r in res[:4])}"
+                       f"{'...' if len(res) > 4 else ''} s; the summed rate is scaled to {full_unknowns} "
+                       f"unknowns by the unknown ratio (linear-cost assumption)"),
+            "cpu_model": cpu_model, "host_cores_available": avail, "wall_s": wall,
+            "newton_its": res[0][2]}
+
+
+def oracle_precision_leg(sk, torch, args):
+    """Precision workload at the nested instance (32x fewer nodes, same
+    recipe and refinement depth): 30 daily steps on the GPU with FP64, FP32
+    and BF16 subdomain factors, every field's error at step 30 against the
+    oracle's stored over-converged state (written by
+    tests/golden/make_oracle_states.py), at the workload's tolerances."""
+    import numpy as np
+    import seird_inputs as si
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                        "oracle_polygon32217_r30.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    cfg = si.config_realistic(n_base=int(ref["n_base"]), n_ref=int(ref["n_ref"]), n_sub=32)
+    coarse = (cfg.coarse_parents, cfg.coarse_n)
+    out = {"workload": (f"{cfg.name}: nested instance of the realistic recipe, {cfg.n} nodes "
+                        f"({5 * cfg.n} unknowns), 32 subdomains, two-grid RAS, 30 daily steps, Newton "
+                        f"tol {cfg.newton_tol}, GMRES rtol {cfg.gmres_rtol}; reference: the oracle's "
+                        f"state at step 30 (Newton with direct solves to scaled residual "
+                        f"{float(ref['tol'])})")}
+    for prec, name in ((0, "fp64"), (1, "fp32"), (2, "bf16")):
+        prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+        pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, factor_prec=prec, coarse=coarse)
+        u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
+        its = []
+        for _ in range(int(ref["steps"])):
+            st = sk.step(prob, pc, u, cfg.dt, tol=cfg.newton_tol, rtol=cfg.gmres_rtol, pc_reuse=args.pc_reuse)
+            its.append(sum(st["gmres_its"]))
+        torch.cuda.synchronize()
+        out[name] = {"per_field": per_field_errors(u.cpu().numpy(), ref["u30"]), "gmres_its_total": sum(its)}
+    return out
+
+
+PEAK_MFMA_TFLOPS = {0: 78.6, 1: 157.3, 2: 157.3}  # FP64, FP32 (BF16 factors are factored in FP32)
+
+
+def factor_roofline(perf, prec):
+    """Subdomain factorisation against the matrix-core peak of its
+    arithmetic: flops of the tile products per setup over the HIP-event time
+    of the factorisation launch, averaged over the timed setups."""
+    if not perf or perf["setups"] <= 0:
+        return None
+    ms = perf["t_lu_ms"] / perf["setups"]
+    achieved = perf["lu_mfma_flops"] / (ms * 1e-3) / 1e12
+    peak = PEAK_MFMA_TFLOPS[prec]
+    return {"bound": "mfma", "kernel": "k_band_lu32 (subdomain LU of one setup, "
+                                       + ("FP64" if prec == 0 else "FP32") + " MFMA)",
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "useful_tflops": perf["lu_useful_flops"] / (ms * 1e-3) / 1e12,
+            "flops_per_launch": perf["lu_mfma_flops"], "useful_flops_per_launch": perf["lu_useful_flops"],
+            "avg_launch_ms": ms, "launches": perf["setups"],
+            "extract_ms": perf["t_extract_ms"] / perf["setups"],
+            "traffic": None}
+
+
+def spmv_roofline(sk, torch, prob, u, dt, reps=50):
+    """k_spmv on the Jacobian at the final state: algorithmic bytes (the
+    node-block matrix once, its index arrays once, x gathered once per node,
+    y written) over the HIP-event time per launch on the launch stream."""
+    vals = prob.jacobian(u, dt)
+    x = torch.randn(prob.N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        prob.spmv(vals, x, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        prob.spmv(vals, x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = prob.n * (25 * 8 + 8 + 40 + 40) + prob.nslots * (10 * 8 + 4)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "k_spmv (node-block Jacobian times a vector)", "achieved": achieved,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "avg_launch_ms": ms, "launches": reps, "bytes_per_launch": nbytes,
+            "traffic": None}
 
 
 def main():
@@ -275,10 +417,18 @@ def main():
     ap.add_argument("--batch-prec", type=int, default=1, choices=[0, 1, 2])
     ap.add_argument("--pc-reuse", type=int, default=100,
                     help="Newton iterations a preconditioner setup is reused for (0: fresh every time)")
+    ap.add_argument("--adjoint", choices=["full", "short", "none"], default="full",
+                    help="adjoint-gradient leg: the ~2M-node, 60-step differentiation workload "
+                         "(full), --adjoint-steps steps of the realistic mesh (short), or none")
     ap.add_argument("--adjoint-steps", type=int, default=10,
-                    help="implicit steps of the adjoint-gradient measurement (0: skip)")
-    ap.add_argument("--adjoint-full", action="store_true",
-                    help="measure the gradient on the ~2M-node, 60-step differentiation workload")
+                    help="implicit steps of the short adjoint leg")
+    ap.add_argument("--p-steps", type=int, default=30,
+                    help="step at which the precision legs compare their fields (untimed steps are "
+                         "added after the timed ones to reach it)")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="worker processes of the CPU baseline (capped by the cores available)")
+    ap.add_argument("--cpu-steps", type=int, default=3,
+                    help="oracle steps per CPU-baseline worker")
     args = ap.parse_args()
     if args.tile != "auto":
         args.tile = int(args.tile)
@@ -297,7 +447,7 @@ def main():
         f"{cfg.n_sub} subdomains, coarse {cfg.coarse_n} nodes ({time.perf_counter() - t:.1f} s)")
     args.tuned = {}
     res = run_steps(sk, torch, cfg, coarse, args.prec, args.steps, args.warmup, args.tile, args.pc_reuse,
-                    args.solve_threads)
+                    args.solve_threads, until=args.p_steps if args.compare_prec else 0)
     args.tuned[args.prec] = (res["tile"], res["solve_threads"])
     sec = res["seconds"]
     stats = res["stats"]
@@ -318,6 +468,11 @@ def main():
                     "bytes_per_launch": ras_bytes}
     phase = {k: sum(s[k] for s in stats) / max(1, len(stats)) for k in
              ("t_residual_ms", "t_jacobian_ms", "t_setup_ms", "t_gmres_ms")}
+    kernels = [roofline] if roofline else []
+    lu = factor_roofline(res["perf"], args.prec)
+    if lu:
+        kernels.append(lu)
+    kernels.append(spmv_roofline(sk, torch, res["prob"], res["u"], cfg.dt))
     out = {
         "metric": "SEIRD implicit steps/s at 5M DOF: FP64 vs mixed RAS; adjoint grads/s",
         "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
@@ -342,12 +497,13 @@ def main():
         "precond": res["info"],
         "autotune": res["tune"],
         "roofline": roofline,
+        "roofline_kernels": kernels,
     }
     if args.compare_prec:
         mixed = {}
         for p in (1, 2):
             r2 = run_steps(sk, torch, cfg, coarse, p, args.steps, args.warmup, args.tile, args.pc_reuse,
-                           args.solve_threads)
+                           args.solve_threads, until=args.p_steps)
             args.tuned[p] = (r2["tile"], r2["solve_threads"])
             mixed[{1: "fp32", 2: "bf16"}[p]] = {
                 "steps_per_s": args.steps / r2["seconds"],
@@ -355,17 +511,22 @@ def main():
                 "gmres_its": [s["gmres_its"] for s in r2["stats"]],
                 "max_rel_diff_vs_fp64": float(((r2["u"] - res["u"]).abs().max()
                                                / res["u"].abs().max()).item()),
+                "per_field_vs_fp64": {"step": r2["steps_done"],
+                                      "errors": per_field_errors(r2["u"].cpu().numpy(), res["u"].cpu().numpy())},
+                "setup_lu_ms": (r2["perf"]["t_lu_ms"] / r2["perf"]["setups"]) if r2["perf"]["setups"] else None,
                 "tile": r2["tile"], "solve_threads": r2["solve_threads"],
                 "phase_ms_per_step": {k: sum(st[k] for st in r2["stats"]) / max(1, len(r2["stats"])) for k in
                                       ("t_residual_ms", "t_jacobian_ms", "t_setup_ms", "t_gmres_ms")},
             }
+        log("[bench] precision legs on the nested instance against the oracle's step-30 state")
+        mixed["vs_oracle_nested"] = oracle_precision_leg(sk, torch, args)
         out["mixed"] = mixed
     if args.batch_steps > 0:
         del res
         torch.cuda.empty_cache()
         out["batch"] = batch_bench(sk, torch, args)
         torch.cuda.empty_cache()
-    if args.adjoint_steps > 0 or args.adjoint_full:
+    if args.adjoint != "none":
         out["adjoint"] = adjoint_bench(sk, torch, args, cfg, coarse)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on its bounded sample")

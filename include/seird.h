@@ -241,6 +241,8 @@ typedef struct {
   double mean_bandwidth;
   int64_t coarse_n;
   int32_t coarse_bandwidth;
+  /* flops of one subdomain factorisation (see seird_precond_perf) */
+  double lu_mfma_flops, lu_useful_flops;
 } seird_schwarz_info;
 seird_status seird_analyze_schwarz(int64_t n_nodes, const double *xy,
                                    int64_t n_tri, const int32_t *tri,
@@ -253,6 +255,24 @@ seird_status seird_analyze_schwarz(int64_t n_nodes, const double *xy,
  * launches; the totals are reported in seird_step_stats (t_ras_kernel_ms,
  * n_ras_launches) and reset at the end of every seird_step. */
 seird_status seird_precond_timing(seird_precond pc, int enable);
+/* Work figures of the preconditioner and, while timing is on
+ * (seird_precond_timing), HIP-event times of its setups: the extraction of
+ * the local matrices and the subdomain factorisation, summed over the
+ * setups since the last reset (reset != 0 clears them after reading).
+ * lu_mfma_flops: flops of one subdomain factorisation as the matrix cores
+ * execute them (every tile product at 2 T^3); lu_useful_flops: the same
+ * with the triangular panel products at T^3, plus the diagonal tiles' LU
+ * and inverses (4/3 T^3 each).  factor_bytes: bytes of the subdomain
+ * factors as factorised; solve_bytes: algorithmic bytes of one subdomain
+ * solve launch (factors in the storage precision plus local vectors). */
+typedef struct {
+  double lu_mfma_flops, lu_useful_flops;
+  double factor_bytes, solve_bytes;
+  int32_t setups;
+  double t_extract_ms, t_lu_ms;
+} seird_precond_perf_report;
+seird_status seird_precond_perf(seird_precond pc, seird_precond_perf_report *r,
+                                int reset);
 /* Coarse solver of a two-level preconditioner.  1: the inverses of the
  * diagonal super-blocks of the coarse factors, X_II = L_II^{-1} and
  * W_II = U_II^{-1}, are formed at every setup (FP64 MFMA, on the coarse

@@ -80,7 +80,14 @@ class _SInfo(ctypes.Structure):
     _fields_ = [("factor_entries", ctypes.c_int64), ("local_unknowns", ctypes.c_int64),
                 ("max_local_nodes", ctypes.c_int32), ("max_bandwidth", ctypes.c_int32),
                 ("mean_bandwidth", ctypes.c_double), ("coarse_n", ctypes.c_int64),
-                ("coarse_bandwidth", ctypes.c_int32)]
+                ("coarse_bandwidth", ctypes.c_int32), ("lu_mfma_flops", ctypes.c_double),
+                ("lu_useful_flops", ctypes.c_double)]
+
+
+class _PerfReport(ctypes.Structure):
+    _fields_ = [("lu_mfma_flops", ctypes.c_double), ("lu_useful_flops", ctypes.c_double),
+                ("factor_bytes", ctypes.c_double), ("solve_bytes", ctypes.c_double),
+                ("setups", ctypes.c_int32), ("t_extract_ms", ctypes.c_double), ("t_lu_ms", ctypes.c_double)]
 
 
 class _AStats(ctypes.Structure):
@@ -124,6 +131,7 @@ _SIGS = {
     "seird_precond_info": ([_P, _I64P, _I64P, _I32P, _I32P], ctypes.c_int),
     "seird_precond_setup": ([_P, _P, _P], ctypes.c_int),
     "seird_precond_timing": ([_P, ctypes.c_int], ctypes.c_int),
+    "seird_precond_perf": ([_P, ctypes.POINTER(_PerfReport), ctypes.c_int], ctypes.c_int),
     "seird_precond_set_solve_threads": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_precond_set_coarse_solver": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_precond_set_coarse_block": ([_P, ctypes.c_int32], ctypes.c_int),
@@ -358,6 +366,13 @@ class Precond:
     def enable_timing(self, on=True):
         _check(lib().seird_precond_timing(self.h, int(bool(on))))
 
+    def perf(self, reset=False):
+        """Factorisation flop counts, factor bytes and (timing on) the
+        HIP-event times of the setups since the last reset."""
+        r = _PerfReport()
+        _check(lib().seird_precond_perf(self.h, ctypes.byref(r), int(bool(reset))))
+        return {k: getattr(r, k) for k, _ in _PerfReport._fields_}
+
     def set_solve_threads(self, threads):
         """Workgroup size of the subdomain solves (256; 512 or 1024 with tile 32)."""
         _check(lib().seird_precond_set_solve_threads(self.h, int(threads)))
@@ -583,6 +598,9 @@ class _BorrowedPrecond:
 
     def enable_timing(self, on=True):
         Precond.enable_timing(self, on)
+
+    def perf(self, reset=False):
+        return Precond.perf(self, reset)
 
     def set_solve_threads(self, threads):
         Precond.set_solve_threads(self, threads)

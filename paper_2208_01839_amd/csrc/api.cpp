@@ -326,6 +326,10 @@ struct seird_precond_s {
   size_t ev_used = 0;
   double ras_ms = 0.0;
   int ras_count = 0;
+  // setup timing (when timing is on): extraction and subdomain factorisation
+  hipEvent_t ev_set[3] = {nullptr, nullptr, nullptr};
+  int set_count = 0;
+  double set_extract_ms = 0.0, set_lu_ms = 0.0;
 
   double ras_bytes() const {
     // algorithmic bytes of one subdomain-solve launch: every stored factor
@@ -372,6 +376,8 @@ struct seird_precond_s {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
     }
+    for (hipEvent_t e : ev_set)
+      if (e) (void)hipEventDestroy(e);
     dev_free(Fs); dev_free(Fb); dev_free(Fc); dev_free(subs_dev); dev_free(order_dev); dev_free(ent_dev); dev_free(l2g);
     dev_free(env_row); dev_free(env_lo); dev_free(ent_ptr); dev_free(trow_ptr); dev_free(trow_sub);
     dev_free(owned); dev_free(status); dev_free(g2l_ptr); dev_free(g2l_idx); dev_free(yloc); dev_free(sub_seg);
@@ -1153,6 +1159,8 @@ seird_status seird_analyze_schwarz(int64_t n_nodes, const double *xy, int64_t n_
   info->mean_bandwidth = ph.mean_bw;
   info->coarse_n = ph.nc;
   info->coarse_bandwidth = ph.coarse_bw;
+  info->lu_mfma_flops = ph.lu_mfma_flops;
+  info->lu_useful_flops = ph.lu_useful_flops;
   if (l2g_out) std::memcpy(l2g_out, ph.l2g.data(), sizeof(int32_t) * ph.l2g.size());
   if (owned_out) std::memcpy(owned_out, ph.owned.data(), ph.owned.size());
   API_END
@@ -1210,6 +1218,24 @@ seird_status seird_precond_info(seird_precond pc, int64_t *factor_entries, int64
   API_END
 }
 
+seird_status seird_precond_perf(seird_precond pc, seird_precond_perf_report *r, int reset) {
+  API_BEGIN
+  if (!pc || !r) fail(SEIRD_ERR_ARG, "null argument");
+  const PrecondHost &ph = pc->ph;
+  r->lu_mfma_flops = ph.lu_mfma_flops;
+  r->lu_useful_flops = ph.lu_useful_flops;
+  r->solve_bytes = pc->ras_bytes();
+  r->factor_bytes = (double)ph.factor_entries * (pc->sub_float ? 4.0 : 8.0);
+  r->setups = pc->set_count;
+  r->t_extract_ms = pc->set_extract_ms;
+  r->t_lu_ms = pc->set_lu_ms;
+  if (reset) {
+    pc->set_count = 0;
+    pc->set_extract_ms = pc->set_lu_ms = 0.0;
+  }
+  API_END
+}
+
 static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t st) {
   seird_problem P = pc->prob;
   PrecondHost &ph = pc->ph;
@@ -1245,6 +1271,13 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
     fl.gw = pc->gw;
     fl.gal_nblk = (int64_t)ph.gal_p.size();
   }
+  if (pc->timing) {
+    for (hipEvent_t &e : pc->ev_set)
+      if (!e) HIPCHECK(hipEventCreate(&e));
+    fl.ev_extract = pc->ev_set[0];
+    fl.ev_lu = pc->ev_set[1];
+    fl.ev_lu_end = pc->ev_set[2];
+  }
   if (ph.two_level) {
     // fork: the coarse chain waits for everything already queued on st
     HIPCHECK(hipEventRecord(pc->ev_fork, st));
@@ -1265,6 +1298,14 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
   int status = 0;
   HIPCHECK(hipMemcpyAsync(&status, pc->status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
+  if (fl.ev_extract && ph.n_sub > 0) {
+    float a = 0.f, b = 0.f;
+    HIPCHECK(hipEventElapsedTime(&a, fl.ev_extract, fl.ev_lu));
+    HIPCHECK(hipEventElapsedTime(&b, fl.ev_lu, fl.ev_lu_end));
+    pc->set_extract_ms += a;
+    pc->set_lu_ms += b;
+    pc->set_count++;
+  }
   pc->ready = true;
   pc->vals_setup = vals;
   if (status & 2) fail(SEIRD_ERR_ARG, "internal: local matrix entry outside the stored tiles");

@@ -115,6 +115,7 @@ struct ExtractEntry {  // one node block of R_i A R_i^T
 
 struct PrecondHost {
   int n_sub = 0, overlap = 0, tile = 32, prec = 0;
+  int bs = NC;                        // unknowns per node: 5 (coupled) or 1 (one compartment)
   std::vector<SubInfo> subs;          // subdomains (then, if two-level, coarse)
   std::vector<int32_t> l2g;           // local unknown -> global unknown
   std::vector<uint8_t> owned;         // per local unknown: owned by the sub
@@ -126,6 +127,12 @@ struct PrecondHost {
   std::vector<int32_t> order;         // subdomain processing order (LPT)
   std::vector<int32_t> env_row, env_lo;  // subdomain row tables (tile offset, first tile column)
   int64_t factor_entries = 0;   // subdomain tile-envelope entries
+  // flops of the subdomain factorisation over the tile envelopes: tile
+  // products as the matrix cores execute them (dense 2 T^3 per product:
+  // the U and L panel tiles and every Schur update), and the useful count
+  // (triangular-times-dense panel products at T^3) plus the diagonal tiles'
+  // LU and two triangular inverses (4/3 T^3 each, vector ALUs)
+  double lu_mfma_flops = 0.0, lu_useful_flops = 0.0;
   int64_t coarse_entries = 0;   // coarse band entries (own buffer)
   int32_t max_nodes = 0, max_bw = 0;
   int32_t max_nloc = 0;
@@ -151,7 +158,7 @@ struct PrecondHost {
 
 void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,
                 MeshHost &m);
-void build_precond(const MeshHost &m, const seird_schwarz_opts &o,
-                   const int32_t *part, PrecondHost &ph);
+void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t *part,
+                   PrecondHost &ph, int bs = NC);
 
 }  // namespace seird

@@ -28,6 +28,7 @@ struct SegHost {
 
 struct FactorLaunch {
   int tile = 32;
+  int bs = 5;               // unknowns per node of the extracted matrix (5: node-block Jacobian; 1: scalar)
   void *Fs = nullptr;       // subdomain tile-envelope storage (float64, or float32 if sub_float)
   bool sub_float = false;   // factorise the subdomains in float32
   int64_t sub_entries = 0;
@@ -54,6 +55,9 @@ struct FactorLaunch {
   const int32_t *gref = nullptr;
   const double *gw = nullptr;
   int64_t gal_nblk = 0;
+  // optional timing events on st: before the extraction, between the
+  // extraction and the subdomain factorisation, after the factorisation
+  hipEvent_t ev_extract = nullptr, ev_lu = nullptr, ev_lu_end = nullptr;
 };
 
 struct SolveLaunch {

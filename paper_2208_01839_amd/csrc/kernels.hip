@@ -622,9 +622,11 @@ __global__ void k_pad_identity(ET *__restrict__ F, const SubInfo *__restrict__ s
 // of that row exactly once: the matrix entry, zero, or 1 on the padded
 // diagonal, so the storage needs no clearing beforehand.  A thread owns one
 // row of a tile and 4 consecutive columns; the nonzero node blocks of its
-// row are the extraction entries of its local node.  Node-block values:
-// diagonal blocks from diag, off-diagonal block (c, c') = b_c + a_c [c = c'].
-template <int T, class ET, int MAXE>
+// row are the extraction entries of its local node.  BS = 5 (the coupled
+// Jacobian): diagonal blocks from diag [n][25], off-diagonal block
+// (c, c') = b_c + a_c [c = c'] from off [slots][10].  BS = 1 (one
+// compartment's scalar matrix): diag [n] and off [slots].
+template <int T, class ET, int MAXE, int BS = 5>
 __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const SubInfo *__restrict__ subs,
                                                        const int32_t *__restrict__ trow_ptr,
                                                        const int32_t *__restrict__ trow_sub,
@@ -644,11 +646,11 @@ __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const
   const int K = gK - trow_ptr[s0];
   const int tid = threadIdx.x, tt = tid / PER, a = (tid % PER) / CH, g = tid % CH;
   const int32_t l = K * T + a;  // local row
-  const int32_t p = l / 5, c = l % 5;
+  const int32_t p = l / BS, c = l % BS;
   const bool real = l < si.n_loc;
   int32_t e0 = 0, e1 = 0;
   if (real) {
-    const int64_t nb = si.l2g_off / 5 + p;
+    const int64_t nb = si.l2g_off / BS + p;
     e0 = ent_ptr[nb];
     e1 = ent_ptr[nb + 1];
   }
@@ -668,15 +670,43 @@ __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const
     }
   }
   auto value = [&](int32_t ref, int cp) -> double {
-    if (ref < 0) return diag[25 * (int64_t)(-ref - 1) + 5 * c + cp];
-    const double *o = off + 10 * (int64_t)ref;
-    return o[5 + c] + (cp == c ? o[c] : 0.0);
+    if constexpr (BS == 1) {
+      return ref < 0 ? diag[-(int64_t)ref - 1] : off[ref];
+    } else {
+      if (ref < 0) return diag[25 * (int64_t)(-ref - 1) + 5 * c + cp];
+      const double *o = off + 10 * (int64_t)ref;
+      return o[5 + c] + (cp == c ? o[c] : 0.0);
+    }
   };
   const int J1 = R.last(K);
   for (int J = R.first(K) + tt; J <= J1; J += TPP) {
     const int32_t lb0 = J * T + 4 * g;  // first column of the chunk
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (real && inreg) {
+    if constexpr (BS == 1) {
+      // every column is its own node block: look each one up
+      if (real && inreg) {
+        if (lb0 + 3 >= qlo && lb0 <= qhi) {
+#pragma unroll
+          for (int k = 0; k < MAXE; ++k)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (qv[k] == lb0 + u) v[u] = value(rv[k], 0);
+        }
+      } else if (real) {
+        for (int32_t k = e0; k < e1; ++k) {
+          const int32_t d0 = ent[k].q - lb0;
+          if (d0 >= 0 && d0 < 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (u == d0) v[u] = value(ent[k].ref, 0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (lb0 + u == l) v[u] = 1.0;
+      }
+    } else if (real && inreg) {
       // columns lb0 .. lb0 + 3 belong to at most two node blocks qa, qb
       const int32_t qa = lb0 / 5, qb = (lb0 + 3) / 5;
       if (qb >= qlo && qa <= qhi) {
@@ -2421,12 +2451,21 @@ template <int T, class ET>
 static void extract_t(const FactorLaunch &fl, ET *F, const double *diag, const double *off, hipStream_t st) {
   if (fl.ntrows <= 0) return;
   // a register slot per node block: 10 covers P1 meshes of node degree <= 9
-  if (fl.max_node_blocks <= 10)
-    hipLaunchKernelGGL((k_extract_tiles<T, ET, 10>), dim3((unsigned)fl.ntrows), dim3(256), 0, st, F, fl.subs,
-                       fl.trow_ptr, fl.trow_sub, fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
-  else
-    hipLaunchKernelGGL((k_extract_tiles<T, ET, 16>), dim3((unsigned)fl.ntrows), dim3(256), 0, st, F, fl.subs,
-                       fl.trow_ptr, fl.trow_sub, fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
+  const dim3 g((unsigned)fl.ntrows);
+  if (fl.bs == 1) {
+    if (fl.max_node_blocks <= 10)
+      hipLaunchKernelGGL((k_extract_tiles<T, ET, 10, 1>), g, dim3(256), 0, st, F, fl.subs, fl.trow_ptr, fl.trow_sub,
+                         fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
+    else
+      hipLaunchKernelGGL((k_extract_tiles<T, ET, 16, 1>), g, dim3(256), 0, st, F, fl.subs, fl.trow_ptr, fl.trow_sub,
+                         fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
+  } else if (fl.max_node_blocks <= 10) {
+    hipLaunchKernelGGL((k_extract_tiles<T, ET, 10>), g, dim3(256), 0, st, F, fl.subs, fl.trow_ptr, fl.trow_sub,
+                       fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
+  } else {
+    hipLaunchKernelGGL((k_extract_tiles<T, ET, 16>), g, dim3(256), 0, st, F, fl.subs, fl.trow_ptr, fl.trow_sub,
+                       fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
+  }
 }
 
 template <int T>
@@ -2488,20 +2527,28 @@ void launch_setup_factors(const FactorLaunch &fl, const double *diag, const doub
   const bool coarse_first = fl.coarse && fl.sub_float;
   if (coarse_first) coarse_factor(fl, diag, off, st_coarse);
   if (fl.nsub > 0) {
+    auto mark = [&](hipEvent_t e) {
+      if (e) HIPCHECK(hipEventRecord(e, st));
+    };
+    mark(fl.ev_extract);
     if (fl.tile == 32) {
       if (fl.sub_float) {
         extract_t<32, float>(fl, (float *)fl.Fs, diag, off, st);
+        mark(fl.ev_lu);
         band_lu32<float>(fl, (float *)fl.Fs, st);
       } else {
         extract_t<32, double>(fl, (double *)fl.Fs, diag, off, st);
+        mark(fl.ev_lu);
         band_lu32<double>(fl, (double *)fl.Fs, st);
       }
     } else {
       extract_t<16, double>(fl, (double *)fl.Fs, diag, off, st);
+      mark(fl.ev_lu);
       const size_t lds = (size_t)std::max(fl.max_bu, 1) * 16 * 17 * sizeof(double);
       hipLaunchKernelGGL(k_band_lu<16>, dim3(fl.nsub), dim3(256), lds, st, (double *)fl.Fs, fl.subs, fl.erow, fl.elo,
                          fl.order, fl.status);
     }
+    mark(fl.ev_lu_end);
   }
   if (fl.coarse && !coarse_first) coarse_factor(fl, diag, off, st_coarse);
 }

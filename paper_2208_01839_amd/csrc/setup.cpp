@@ -231,10 +231,10 @@ static std::vector<int32_t> band_order(const std::vector<int32_t> &lp, const std
   return bandwidth_of(b, lp, la) < bandwidth_of(a, lp, la) ? b : a;
 }
 
-static SubInfo tile_geometry(int32_t nn, int32_t bw, int tile) {
+static SubInfo tile_geometry(int32_t nn, int32_t bw, int tile, int bs = NC) {
   SubInfo si{};
-  si.n_loc = NC * nn;
-  const int32_t kl = NC * bw + NC - 1;
+  si.n_loc = bs * nn;
+  const int32_t kl = bs * bw + bs - 1;
   si.nt = (si.n_loc + tile - 1) / tile;
   si.bl = std::min<int32_t>((kl + tile - 1) / tile, si.nt - 1);
   si.bu = si.bl;
@@ -243,22 +243,23 @@ static SubInfo tile_geometry(int32_t nn, int32_t bw, int tile) {
 }
 
 // Tile envelope of a subdomain matrix in the local order (node position k
-// holds unknowns 5k .. 5k + 4, full 5x5 node blocks): lo[K] = first tile
+// holds unknowns bs k .. bs k + bs - 1, full bs x bs node blocks; bs = 5 for
+// the coupled system, 1 for one compartment): lo[K] = first tile
 // column of tile row K, made nondecreasing (suffix minimum) so that the
 // envelope is closed under elimination; row[K] = tile offset of row K,
 // whose tiles are the columns lo[K] .. hi[K] with hi[K] = max{J : lo[J] <=
 // K}.  Sets si.bl = si.bu to the largest extent.
 static void tile_envelope(const std::vector<int32_t> &lp, const std::vector<int32_t> &la,
                           const std::vector<int32_t> &perm, const std::vector<int32_t> &where, int tile,
-                          SubInfo &si, std::vector<int32_t> &lo, std::vector<int32_t> &row) {
+                          SubInfo &si, std::vector<int32_t> &lo, std::vector<int32_t> &row, int bs) {
   const int32_t nn = (int32_t)perm.size(), nt = si.nt;
   lo.assign(nt, 0);
   for (int32_t K = 0; K < nt; ++K) lo[K] = K;
   for (int32_t k = 0; k < nn; ++k) {
     int32_t left = k;
     for (int32_t q = lp[perm[k]]; q < lp[perm[k] + 1]; ++q) left = std::min(left, where[la[q]]);
-    const int32_t K = (NC * k) / tile, K2 = (NC * k + NC - 1) / tile;  // tile rows of the node's unknowns
-    const int32_t J = (NC * left) / tile;
+    const int32_t K = (bs * k) / tile, K2 = (bs * k + bs - 1) / tile;  // tile rows of the node's unknowns
+    const int32_t J = (bs * left) / tile;
     lo[K] = std::min(lo[K], J);
     lo[K2] = std::min(lo[K2], J);
   }
@@ -277,8 +278,11 @@ static void tile_envelope(const std::vector<int32_t> &lp, const std::vector<int3
 }
 
 void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t *part,
-                   PrecondHost &ph) {
+                   PrecondHost &ph, int bs) {
   const int64_t n = m.n;
+  if (bs != NC && bs != 1) fail(SEIRD_ERR_ARG, "internal: block size must be 1 or 5");
+  if (bs != NC && o.n_ref > 0) fail(SEIRD_ERR_ARG, "the compartment-wise preconditioner is one-level");
+  ph.bs = bs;
   if (o.n_sub <= 0 || o.overlap < 0 || !part) fail(SEIRD_ERR_ARG, "bad Schwarz options");
   if (o.tile != 16 && o.tile != 32) fail(SEIRD_ERR_ARG, "tile must be 16 or 32");
   if (o.factor_prec < 0 || o.factor_prec > 2) fail(SEIRD_ERR_ARG, "factor_prec must be 0, 1 or 2");
@@ -338,9 +342,9 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
     int32_t bw = 0;
     for (int32_t k = 0; k < nn; ++k)
       for (int32_t q = lp[k]; q < lp[k + 1]; ++q) bw = std::max(bw, std::abs(where[k] - where[la[q]]));
-    SubInfo si = tile_geometry(nn, bw, t);
+    SubInfo si = tile_geometry(nn, bw, t, bs);
     std::vector<int32_t> elo, erow;
-    tile_envelope(lp, la, perm, where, t, si, elo, erow);
+    tile_envelope(lp, la, perm, where, t, si, elo, erow, bs);
     si.base = base;
     si.l2g_off = (int32_t)ph.l2g.size();
     si.env_off = (int32_t)ph.env_row.size();
@@ -355,8 +359,8 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
     // local unknown map and ownership, in the local (RCM) order
     for (int32_t k = 0; k < nn; ++k) {
       int32_t g = nodes[perm[k]];
-      for (int c = 0; c < NC; ++c) {
-        ph.l2g.push_back(NC * g + c);
+      for (int c = 0; c < bs; ++c) {
+        ph.l2g.push_back(bs * g + c);
         ph.owned.push_back(part[g] == s ? 1 : 0);
       }
     }
@@ -371,13 +375,23 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
         if (stamp[h] == s) ph.extract.push_back({s, k, where[lpos[h]], (int32_t)q});
       }
       for (size_t e = ph.ent_ptr.back(); e < ph.extract.size(); ++e) {
-        const int32_t J0 = NC * ph.extract[e].q / t, J1 = (NC * ph.extract[e].q + NC - 1) / t;
-        for (int32_t K = NC * k / t; K <= (NC * k + NC - 1) / t; ++K)
+        const int32_t J0 = bs * ph.extract[e].q / t, J1 = (bs * ph.extract[e].q + bs - 1) / t;
+        for (int32_t K = bs * k / t; K <= (bs * k + bs - 1) / t; ++K)
           if (J0 < elo[K] || J1 >= elo[K] + (erow[K + 1] - erow[K]))
             fail(SEIRD_ERR_ARG, "internal: local matrix entry outside the stored tiles");
       }
       if (ph.extract.size() >= (size_t)INT32_MAX) fail(SEIRD_ERR_ARG, "too many local matrix blocks");
       ph.max_node_blocks = std::max(ph.max_node_blocks, (int32_t)(ph.extract.size() - ph.ent_ptr.back()));
+    }
+    {
+      // step K: panels of nu tiles right of the diagonal and nu below it
+      // (the envelope is symmetric), then nu x nu Schur products
+      const double T3 = (double)t * t * t;
+      for (int32_t K = 0; K < si.nt; ++K) {
+        const double nu = (double)(elo[K] + (erow[K + 1] - erow[K]) - 1 - K);
+        ph.lu_mfma_flops += 2.0 * T3 * (2.0 * nu + nu * nu);
+        ph.lu_useful_flops += T3 * (2.0 * nu + 2.0 * nu * nu) + 4.0 / 3.0 * T3;
+      }
     }
     ph.trow_ptr.push_back(ph.trow_ptr.back() + si.nt);
     ph.trow_sub.insert(ph.trow_sub.end(), si.nt, s);
