@@ -332,6 +332,14 @@ seird_status seird_autotune_schwarz(seird_problem p,
  * returns SEIRD_ERR_BREAKDOWN on a zero/nonfinite pivot. */
 seird_status seird_precond_setup(seird_precond pc, const double *vals,
                                  void *stream);
+/* Setup of a compartment-wise (scalar) preconditioner, such as the one of
+ * seird_pgs_precond, from a scalar matrix on the node graph: diag [n_nodes]
+ * and off [n_slots] (slot order of seird_pattern), device float64.  Its
+ * apply then maps vectors of n_nodes entries.  Synchronising;
+ * SEIRD_ERR_BREAKDOWN on a zero or nonfinite pivot, SEIRD_ERR_ARG for a
+ * coupled (node-block) preconditioner. */
+seird_status seird_precond_setup_scalar(seird_precond pc, const double *diag,
+                                        const double *off, void *stream);
 /* z = M^{-1} r (transpose = 0) or M^{-T} r (transpose = 1), with M the
  * one-level RAS (Eq. RAS) or the multiplicative two-grid operator.  Async. */
 seird_status seird_precond_apply(seird_precond pc, const double *r, double *z,
@@ -378,6 +386,56 @@ seird_status seird_step(seird_problem p, seird_precond pc, double *u,
                         const seird_newton_opts *nopts,
                         const seird_krylov_opts *kopts,
                         seird_step_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------
+ * Decoupled Picard-Gauss-Seidel step (the paper's own nonlinear solver,
+ * Section 2.2 Eq. weak_vec_implicit with the per-compartment weak forms of
+ * Appendix A and the stopping rule of Eq. picardtol).  A sweep lags the
+ * diffusion coefficient N and the Allee factor (1 - A/N) at the sweep's
+ * start and solves the compartments S, E, I, R, D one after the other as
+ * scalar systems on the node graph (lumped mass, exact P1 diffusion with
+ * the element-mean lagged density), each using the compartments already
+ * updated in the sweep; vital dynamics enter as loss rate mu on the
+ * diagonal and birth alpha N (lagged) on the right-hand side.  Each system
+ * is solved in correction form, A_c delta = rhs_c - A_c u_c, by GMRES with a
+ * one-level RAS over scalar subdomains (a compartment with nu_c = 0 is
+ * diagonal and is solved directly).  The sweeps stop when
+ * epsilon = ||u^{k+1} - u^k||_2 / ||u^n||_2 <= tol.  The fixed point is the
+ * root of the coupled residual that seird_step reaches (only the iteration
+ * differs); res_scaled reports ||F(u)||_2 / ||M_L u^n||_2 at the result.
+ * ------------------------------------------------------------------ */
+typedef struct seird_pgs_s *seird_pgs;
+#define SEIRD_MAX_PGS 64
+typedef struct {
+  double tol;          /* epsilon tolerance of Eq. picardtol */
+  int32_t max_sweeps;  /* 1 .. SEIRD_MAX_PGS */
+  int32_t strict_linear; /* 1: a GMRES solve stopping at max_it fails the step */
+} seird_pgs_opts;
+typedef struct {
+  int32_t sweeps;
+  int32_t gmres_its[5];      /* per compartment, summed over the sweeps */
+  double eps_hist[SEIRD_MAX_PGS];
+  double res_scaled;         /* coupled residual of the result, scaled */
+  int32_t pc_setups, inexact_solves;
+  int32_t reason;
+  double t_setup_ms, t_gmres_ms, t_total_ms;
+} seird_pgs_stats;
+/* The solver of problem p with scalar subdomains from the partition and
+ * opts (n_sub, overlap, tile, factor_prec; n_ref must be 0).  Device work
+ * arrays are allocated here. */
+seird_status seird_pgs_create(seird_problem p, const seird_schwarz_opts *opts,
+                              const int32_t *part, seird_pgs *out);
+void seird_pgs_destroy(seird_pgs g);
+/* Its scalar preconditioner, borrowed (seird_precond_info / _timing /
+ * _set_solve_threads). */
+seird_status seird_pgs_precond(seird_pgs g, seird_precond *out);
+/* One implicit step by Picard-Gauss-Seidel sweeps, u in: u^n, out: u^{n+1}.
+ * Synchronising.  SEIRD_ERR_NOT_CONVERGED when max_sweeps do not reach tol;
+ * on failure u is unspecified and stats->reason holds the status. */
+seird_status seird_pgs_step(seird_pgs g, double *u, double dt,
+                            const seird_pgs_opts *popts,
+                            const seird_krylov_opts *kopts,
+                            seird_pgs_stats *stats, void *stream);
 
 /* ------------------------------------------------------------------
  * Batches: several independent problems (uneven meshes, their own rates

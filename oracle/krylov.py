@@ -110,15 +110,16 @@ def grow_overlap(G: sp.csr_matrix, nodes: np.ndarray, layers: int) -> np.ndarray
     return np.nonzero(mask)[0]
 
 
-def unknowns_of(nodes: np.ndarray) -> np.ndarray:
-    return (NC * nodes[:, None] + np.arange(NC)[None, :]).ravel()
+def unknowns_of(nodes: np.ndarray, bs: int = NC) -> np.ndarray:
+    return (bs * nodes[:, None] + np.arange(bs)[None, :]).ravel()
 
 
 class RAS:
-    """One-level restricted additive Schwarz with exact local solves."""
+    """One-level restricted additive Schwarz with exact local solves.  bs:
+    unknowns per node (5 for the coupled system, 1 for one compartment)."""
 
     def __init__(self, A: sp.csr_matrix, G: sp.csr_matrix, part: np.ndarray,
-                 n_sub: int, overlap: int):
+                 n_sub: int, overlap: int, bs: int = NC):
         self.A = A.tocsr()
         self.subs = []
         for i in range(n_sub):
@@ -126,8 +127,8 @@ class RAS:
             if len(owned) == 0:
                 continue
             nodes = grow_overlap(G, owned, overlap)
-            idx = unknowns_of(nodes)
-            own = np.repeat(part[nodes] == i, NC)
+            idx = unknowns_of(nodes, bs)
+            own = np.repeat(part[nodes] == i, bs)
             Ai = self.A[idx][:, idx].tocsc()
             lu = spla.splu(Ai)
             self.subs.append((idx, own, lu))

@@ -126,7 +126,11 @@ def picard_step(u_prev, dt, geo, p, g=None, tol=1e-12, max_it=200):
 
 
 def picard_gs_step(u_prev, dt, geo, p, g=None, tol=1e-12, max_it=500):
-    """Decoupled Picard sweep of Appendix A (alpha = mu = 0), lumped mass."""
+    """Decoupled Picard sweep of Appendix A, lumped mass.  Appendix A drops
+    the vital dynamics (alpha = mu = 0); with them, mu is a loss on every
+    compartment's diagonal except D's and the births alpha N enter the
+    susceptible right-hand side with N lagged, which leaves the fixed point
+    equal to the root of the coupled residual (Eq. vec_component2)."""
     n = geo.n
     m = geo.mass
     gg = np.ones(n) if g is None else g
@@ -135,30 +139,32 @@ def picard_gs_step(u_prev, dt, geo, p, g=None, tol=1e-12, max_it=500):
     unorm = np.linalg.norm(u_prev)
     sn, en, in_, rn, dn = u_prev.T
     Mdiag = sp.diags(m)
+    eps_hist = []
     for k in range(1, max_it + 1):
         s, e, i, r, d = u.T.copy()
         N = s + e + i + r + d
         a = 1.0 - p.A / N
         Kn = _stiffness(geo, N[geo.tri].mean(1))
         # susceptible
-        A = Mdiag + sp.diags(dt * m * a * gg * (p.beta_I * i + p.beta_E * e)) + dt * nu[0] * Kn
-        s1 = spla.spsolve(A.tocsc(), m * sn)
+        A = Mdiag + sp.diags(dt * m * (a * gg * (p.beta_I * i + p.beta_E * e) + p.mu)) + dt * nu[0] * Kn
+        s1 = spla.spsolve(A.tocsc(), m * sn + dt * m * p.alpha * N)
         # exposed
         A = Mdiag - sp.diags(dt * m * a * gg * p.beta_E * s1) + \
-            sp.diags(dt * m * (p.sigma + p.gamma_E) * np.ones(n)) + dt * nu[1] * Kn
+            sp.diags(dt * m * (p.sigma + p.gamma_E + p.mu) * np.ones(n)) + dt * nu[1] * Kn
         e1 = spla.spsolve(A.tocsc(), m * en + dt * m * a * gg * p.beta_I * s1 * i)
         # infected
-        A = Mdiag + sp.diags(dt * m * (p.gamma_D + p.gamma_R) * np.ones(n)) + dt * nu[2] * Kn
+        A = Mdiag + sp.diags(dt * m * (p.gamma_D + p.gamma_R + p.mu) * np.ones(n)) + dt * nu[2] * Kn
         i1 = spla.spsolve(A.tocsc(), m * in_ + dt * m * p.sigma * e1)
         # recovered
-        A = Mdiag + dt * nu[3] * Kn
+        A = Mdiag + sp.diags(dt * m * p.mu * np.ones(n)) + dt * nu[3] * Kn
         r1 = spla.spsolve(A.tocsc(), m * rn + dt * m * (p.gamma_R * i1 + p.gamma_E * e1))
         # deceased (no diffusion unless nu_D != 0)
         A = Mdiag + dt * nu[4] * Kn
         d1 = spla.spsolve(A.tocsc(), m * dn + dt * m * p.gamma_D * i1)
         un = np.stack([s1, e1, i1, r1, d1], 1)
         eps = np.linalg.norm(un - u) / unorm
+        eps_hist.append(eps)
         u = un
         if eps <= tol:
-            return u, dict(its=k, eps=eps)
+            return u, dict(its=k, eps=eps, eps_hist=eps_hist)
     raise NotConverged("Picard-GS")

@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Problem", "Precond", "Batch", "SeirdError", "autotune", "gmres", "gmres_noalloc", "step",
+__all__ = ["Problem", "Precond", "PicardGS", "Batch", "SeirdError", "autotune", "gmres", "gmres_noalloc", "step",
            "forward_record", "adjoint", "SEIRDRun", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -90,6 +90,20 @@ class _PerfReport(ctypes.Structure):
                 ("setups", ctypes.c_int32), ("t_extract_ms", ctypes.c_double), ("t_lu_ms", ctypes.c_double)]
 
 
+MAX_PGS = 64
+
+
+class _PgsOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("strict_linear", ctypes.c_int32)]
+
+
+class _PgsStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("gmres_its", ctypes.c_int32 * 5),
+                ("eps_hist", ctypes.c_double * MAX_PGS), ("res_scaled", ctypes.c_double),
+                ("pc_setups", ctypes.c_int32), ("inexact_solves", ctypes.c_int32), ("reason", ctypes.c_int32),
+                ("t_setup_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+
 class _AStats(ctypes.Structure):
     _fields_ = [("gmres_its_total", ctypes.c_int32), ("recomputed_steps", ctypes.c_int32),
                 ("t_forward_ms", ctypes.c_double), ("t_reverse_ms", ctypes.c_double)]
@@ -130,6 +144,7 @@ _SIGS = {
     "seird_precond_destroy": ([_P], None),
     "seird_precond_info": ([_P, _I64P, _I64P, _I32P, _I32P], ctypes.c_int),
     "seird_precond_setup": ([_P, _P, _P], ctypes.c_int),
+    "seird_precond_setup_scalar": ([_P, _P, _P, _P], ctypes.c_int),
     "seird_precond_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "seird_precond_perf": ([_P, ctypes.POINTER(_PerfReport), ctypes.c_int], ctypes.c_int),
     "seird_precond_set_solve_threads": ([_P, ctypes.c_int32], ctypes.c_int),
@@ -151,6 +166,11 @@ _SIGS = {
                              ctypes.c_int),
     "seird_adjoint": ([_P, _P, _P, _P, _P, ctypes.POINTER(_Krylov), ctypes.POINTER(_AStats), _P],
                       ctypes.c_int),
+    "seird_pgs_create": ([_P, ctypes.POINTER(_Schwarz), _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "seird_pgs_destroy": ([_P], None),
+    "seird_pgs_precond": ([_P, _P], ctypes.c_int),
+    "seird_pgs_step": ([_P, _P, ctypes.c_double, ctypes.POINTER(_PgsOpts), ctypes.POINTER(_Krylov),
+                        ctypes.POINTER(_PgsStats), _P], ctypes.c_int),
     "seird_batch_create": ([ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
                             ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
     "seird_batch_destroy": ([_P], None),
@@ -604,6 +624,61 @@ class _BorrowedPrecond:
 
     def set_solve_threads(self, threads):
         Precond.set_solve_threads(self, threads)
+
+    def setup_scalar(self, diag, off):
+        """Scalar preconditioners: factor the subdomain matrices of the
+        scalar matrix (diag [n], off [n_slots] on the node graph)."""
+        prob = self._owner.problem
+        _check(lib().seird_precond_setup_scalar(self.h, _dptr(diag, prob.n, "diag"),
+                                                _dptr(off, prob.nslots, "off"), _stream()))
+
+    def apply(self, r, transpose=False, out=None):
+        out = _torch().empty_like(r) if out is None else out
+        _check(lib().seird_precond_apply(self.h, _dptr(r, None, "r"), _dptr(out, r.numel(), "z"),
+                                         int(bool(transpose)), _stream()))
+        return out
+
+
+class PicardGS:
+    """The paper's decoupled Picard-Gauss-Seidel solver (Appendix A): one
+    implicit step is a sequence of sweeps over the compartments, each a
+    scalar system solved by GMRES with a one-level RAS of scalar subdomains
+    (the partition and overlap given here)."""
+
+    def __init__(self, problem: Problem, part, n_sub, overlap, tile=32, factor_prec=0):
+        self.problem = problem
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        if len(part) != problem.n:
+            raise ValueError("partition length must equal the node count")
+        o, keep = _schwarz_opts(n_sub, overlap, tile, factor_prec, None)
+        h = ctypes.c_void_p()
+        _check(lib().seird_pgs_create(problem.h, ctypes.byref(o), part.ctypes.data, ctypes.byref(h)))
+        del keep
+        self.h = h
+        ph = ctypes.c_void_p()
+        _check(lib().seird_pgs_precond(self.h, ctypes.byref(ph)))
+        self.precond = _BorrowedPrecond(ph, self)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.seird_pgs_destroy(self.h)
+            self.h = None
+
+    def step(self, u, dt, tol=1e-10, max_sweeps=50, strict_linear=False, gmres_max_it=200, **kw):
+        """One implicit step in place on u (float64 CUDA [n, 5]); sweeps
+        until epsilon (Eq. picardtol) <= tol.  Returns the statistics."""
+        po = _PgsOpts(float(tol), int(max_sweeps), int(bool(strict_linear)))
+        o = _krylov(max_it=gmres_max_it, **kw)
+        s = _PgsStats()
+        code = lib().seird_pgs_step(self.h, _dptr(u, self.problem.N, "u"), float(dt), ctypes.byref(po),
+                                    ctypes.byref(o), ctypes.byref(s), _stream())
+        k = s.sweeps
+        stats = dict(sweeps=k, gmres_its=list(s.gmres_its), eps_hist=list(s.eps_hist[:k]),
+                     res_scaled=s.res_scaled, pc_setups=s.pc_setups, inexact_solves=s.inexact_solves,
+                     reason=s.reason, t_setup_ms=s.t_setup_ms, t_gmres_ms=s.t_gmres_ms,
+                     t_total_ms=s.t_total_ms)
+        _check(code)
+        return stats
 
 
 class Batch:

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <tuple>
@@ -155,16 +156,18 @@ struct seird_problem_s {
   }
   // per-segment 2-norms (scale: optional per-node weights)
   // (part, hv: reduction partials and result vector; null = the problem's own)
+  // (g: the segments of x; null = the problem's unknown vector)
   std::vector<double> seg_norms(const double *x, hipStream_t st, const double *scale = nullptr,
-                                double *part = nullptr, double *hv = nullptr) {
+                                double *part = nullptr, double *hv = nullptr, const SegHost *g = nullptr) {
     if (!part) part = partials;
     if (!hv) hv = hdev;
-    launch_seg_norm2(seg, x, scale, part, st);
-    launch_seg_reduce(seg, part, 1, hv, HLD, 0, st);
-    std::vector<double> h((size_t)seg.S * HLD);
+    const SegHost &sg = g ? *g : seg;
+    launch_seg_norm2(sg, x, scale, part, st);
+    launch_seg_reduce(sg, part, 1, hv, HLD, 0, st);
+    std::vector<double> h((size_t)sg.S * HLD);
     HIPCHECK(hipMemcpyAsync(h.data(), hv, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
-    std::vector<double> out(seg.S);
+    std::vector<double> out(sg.S);
     for (int s = 0; s < seg.S; ++s) out[s] = std::sqrt(h[(size_t)s * HLD]);
     return out;
   }
@@ -237,6 +240,7 @@ constexpr double COARSE_INVERSE_BUDGET = 16.0e9;
 struct seird_precond_s {
   seird_problem prob = nullptr;
   PrecondHost ph;
+  int64_t nvec = 0;          // length of the vectors it applies to (bs * n_nodes)
   void *Fs = nullptr;        // subdomain factors as factorised (float64, or float32)
   bool sub_float = false;
   void *Fb = nullptr;        // bfloat16 copy for factor_prec 2, float32 copy for tile 16 + factor_prec 1
@@ -337,7 +341,7 @@ struct seird_precond_s {
     // gathered value, plus the owned results written
     const int64_t nsubent = ph.factor_entries;
     const double fsz = ph.prec == 0 ? 8.0 : (ph.prec == 1 ? 4.0 : 2.0);
-    return nsubent * fsz + (double)ph.l2g.size() * (4 + 1 + 8) + (double)prob->N * 8;
+    return nsubent * fsz + (double)ph.l2g.size() * (4 + 1 + 8) + (double)nvec * 8;
   }
   // the same per instance of a batch (subdomains of that instance only)
   std::vector<double> seg_bytes;
@@ -439,7 +443,7 @@ struct seird_precond_s {
     } else {
       launch_band_solve(sl, st);
     }
-    if (transpose) launch_gather_copies(g2l_ptr, g2l_idx, yloc, z, add, prob->N, st);
+    if (transpose) launch_gather_copies(g2l_ptr, g2l_idx, yloc, z, add, nvec, st);
   }
 
   // z += Z A_c^{-1} Z^T r  (or the transposed coarse operator)
@@ -505,12 +509,54 @@ struct KrylovWork {
   double *V = nullptr, *Zb = nullptr, *partials = nullptr, *hdev = nullptr;
 };
 
+// The linear system GMRES runs on: vector length, the segments of its
+// vectors (plain, active-masked, second mask), y = A x or y = b - A x, and
+// z = M^{-1} r (null: no preconditioner; masks for a batch's instances).
+// Graph capture of the Arnoldi steps is available only through `pc`.
+struct GmresOps {
+  int64_t N = 0;
+  const SegHost *seg = nullptr, *seg_act = nullptr, *seg_re = nullptr;
+  std::function<void(const double *x, const double *b, double *y, hipStream_t)> spmv;
+  std::function<void(const double *r, double *z, hipStream_t, const uint8_t *, const std::vector<uint8_t> *)> prec;
+  seird_precond pc = nullptr;  // for graph capture (coupled systems only)
+  const double *vals = nullptr;
+  int transpose = 0;
+};
+
+static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, double *x, const seird_krylov_opts &o,
+                       std::vector<seird_krylov_stats> &stats, const std::vector<uint8_t> &active_in, hipStream_t st,
+                       const KrylovWork &work);
+
 static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, const double *b, double *x,
                        const seird_krylov_opts &o, std::vector<seird_krylov_stats> &stats,
                        const std::vector<uint8_t> &active_in, int transpose, hipStream_t st,
                        const KrylovWork &work = KrylovWork{}) {
-  const int64_t N = P->N;
-  const int S = P->seg.S;
+  GmresOps ops;
+  ops.N = P->N;
+  ops.seg = &P->seg;
+  ops.seg_act = &P->seg_act;
+  ops.seg_re = &P->seg_re;
+  ops.spmv = [P, vals, transpose](const double *xx, const double *bb, double *y, hipStream_t s) {
+    launch_spmv(P->md, P->diag(vals), P->off(vals), xx, bb, y, transpose, s);
+  };
+  if (pc)
+    ops.prec = [pc, vals, transpose](const double *r, double *z, hipStream_t s, const uint8_t *dm,
+                                     const std::vector<uint8_t> *hm) { pc->apply(vals, r, z, transpose, s, dm, hm); };
+  ops.pc = pc;
+  ops.vals = vals;
+  ops.transpose = transpose;
+  gmres_core(P, ops, b, x, o, stats, active_in, st, work);
+}
+
+static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, double *x, const seird_krylov_opts &o,
+                       std::vector<seird_krylov_stats> &stats, const std::vector<uint8_t> &active_in, hipStream_t st,
+                       const KrylovWork &work) {
+  const int64_t N = ops.N;
+  const SegHost &seg = *ops.seg, &seg_act = *ops.seg_act, &seg_re = *ops.seg_re;
+  const seird_precond pc = ops.pc;
+  const double *vals = ops.vals;
+  const int transpose = ops.transpose;
+  const int S = seg.S;
   const int HLD = P->HLD;
   const int m = o.restart;
   if (m < 1 || m > KRYLOV_MAX - 1) fail(SEIRD_ERR_ARG, "restart must be in [1, 31]");
@@ -521,7 +567,7 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
   double *const hdev = work.hdev ? work.hdev : P->hdev;
   stats.assign(S, seird_krylov_stats{});
   launch_fill(x, 0.0, N, st);
-  const std::vector<double> bnorm = P->seg_norms(b, st, nullptr, partials, hdev);
+  const std::vector<double> bnorm = P->seg_norms(b, st, nullptr, partials, hdev, &seg);
   std::vector<uint8_t> act(S, 0);
   std::vector<double> target(S, 0.0), beta(S, 0.0), sc(S, 0.0);
   std::vector<int> its(S, 0);
@@ -546,7 +592,7 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
   if (!any(act)) return;
   P->upload_mask(P->d_mask, act, st);
   P->upload_scalars(sc, st);
-  launch_seg_axpby(P->seg_act, V, b, P->d_svec, 0.0, st);
+  launch_seg_axpby(seg_act, V, b, P->d_svec, 0.0, st);
   std::vector<double> H((size_t)S * (m + 1) * m), cs((size_t)S * m), sn((size_t)S * m), g((size_t)S * (m + 1));
   std::vector<double> hbuf((size_t)S * HLD), ybuf((size_t)S * HLD);
   const double eta = 1.0 / std::sqrt(2.0);
@@ -564,7 +610,7 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
     }
     P->upload(P->ydev, ybuf.data(), sizeof(double) * ybuf.size(), st);
     P->upload_mask(P->d_mask2, fin, st);
-    launch_seg_gemv_update(P->seg_re, x, Zb, N, P->ydev, HLD, k, st);
+    launch_seg_gemv_update(seg_re, x, Zb, N, P->ydev, HLD, k, st);
   };
   while (any(act)) {
     std::fill(H.begin(), H.end(), 0.0);
@@ -578,15 +624,15 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
       P->upload_mask(P->d_mask, cyc, st);
       // z_j = M^{-1} v_j, w = A z_j, then h = V^T w, w -= V h, |w|^2
       auto step_launches = [&](hipStream_t s) {
-        if (pc)
-          pc->apply(vals, vj, zj, transpose, s, S > 1 ? P->d_mask : nullptr, S > 1 ? &cyc : nullptr);
+        if (ops.prec)
+          ops.prec(vj, zj, s, S > 1 ? P->d_mask : nullptr, S > 1 ? &cyc : nullptr);
         else
           HIPCHECK(hipMemcpyAsync(zj, vj, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-        launch_spmv(P->md, P->diag(vals), P->off(vals), zj, nullptr, w, transpose, s);
-        launch_seg_mdot(P->seg_act, V, N, j + 1, w, 1, partials, s);
-        launch_seg_reduce(P->seg, partials, j + 2, hdev, HLD, 0, s);
-        launch_seg_maxpy_norm(P->seg_act, w, V, N, hdev, HLD, j + 1, partials, s);
-        launch_seg_reduce(P->seg, partials, 1, hdev, HLD, j + 2, s);
+        ops.spmv(zj, nullptr, w, s);
+        launch_seg_mdot(seg_act, V, N, j + 1, w, 1, partials, s);
+        launch_seg_reduce(seg, partials, j + 2, hdev, HLD, 0, s);
+        launch_seg_maxpy_norm(seg_act, w, V, N, hdev, HLD, j + 1, partials, s);
+        launch_seg_reduce(seg, partials, 1, hdev, HLD, j + 2, s);
       };
       if (pc && o.graphs && !pc->timing)
         pc->run_graph({P, V, Zb, vals, j, transpose, S > 1, pc->coarse_solver, pc->coarse_block, pc->solve_threads},
@@ -611,10 +657,10 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
       }
       if (any_re) {  // DGKS: one reorthogonalisation pass for those segments
         P->upload_mask(P->d_mask2, re, st);
-        launch_seg_mdot(P->seg_re, V, N, j + 1, w, 0, partials, st);
-        launch_seg_reduce(P->seg, partials, j + 1, hdev, HLD, 0, st);
-        launch_seg_maxpy_norm(P->seg_re, w, V, N, hdev, HLD, j + 1, partials, st);
-        launch_seg_reduce(P->seg, partials, 1, hdev, HLD, j + 1, st);
+        launch_seg_mdot(seg_re, V, N, j + 1, w, 0, partials, st);
+        launch_seg_reduce(seg, partials, j + 1, hdev, HLD, 0, st);
+        launch_seg_maxpy_norm(seg_re, w, V, N, hdev, HLD, j + 1, partials, st);
+        launch_seg_reduce(seg, partials, 1, hdev, HLD, j + 1, st);
         HIPCHECK(hipMemcpyAsync(hbuf.data(), hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
         for (int s = 0; s < S; ++s) {
@@ -625,7 +671,7 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
       }
       for (int s = 0; s < S; ++s) sc[s] = (cyc[s] && wn[s] > 0.0) ? 1.0 / wn[s] : 0.0;
       P->upload_scalars(sc, st);
-      launch_seg_axpby(P->seg_act, w, w, P->d_svec, 0.0, st);
+      launch_seg_axpby(seg_act, w, w, P->d_svec, 0.0, st);
       std::vector<uint8_t> fin(S, 0);
       std::vector<int> kfin(S, 0);
       bool any_fin = false;
@@ -688,8 +734,8 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
     if (any(cyc)) {
       update(cyc, m);
       P->upload_mask(P->d_mask, cyc, st);
-      launch_spmv(P->md, P->diag(vals), P->off(vals), x, b, V, transpose, st);
-      const std::vector<double> bt = P->seg_norms(V, st, nullptr, partials, hdev);
+      ops.spmv(x, b, V, st);
+      const std::vector<double> bt = P->seg_norms(V, st, nullptr, partials, hdev, &seg);
       for (int s = 0; s < S; ++s) {
         if (!cyc[s]) continue;
         beta[s] = bt[s];
@@ -705,7 +751,7 @@ static void gmres_impl(seird_problem P, seird_precond pc, const double *vals, co
       if (any(cyc)) {
         P->upload_mask(P->d_mask, cyc, st);
         P->upload_scalars(sc, st);
-        launch_seg_axpby(P->seg_act, V, V, P->d_svec, 0.0, st);
+        launch_seg_axpby(seg_act, V, V, P->d_svec, 0.0, st);
       }
     }
   }
@@ -1038,15 +1084,27 @@ seird_status seird_spmv(seird_problem p, const double *vals, const double *x, do
   API_END
 }
 
+static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
+                                         int bs);
+
 seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
                                   seird_precond *out) {
   API_BEGIN
   if (!p || !opts || !out) fail(SEIRD_ERR_ARG, "null argument");
   *out = nullptr;
+  *out = precond_create_impl(p, opts, part, NC);
+  API_END
+}
+
+// Schwarz preconditioner of the coupled node-block Jacobian (bs = 5) or of
+// one compartment's scalar matrix on the node graph (bs = 1, one-level).
+static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
+                                         int bs) {
   auto pc = new seird_precond_s();
   try {
     pc->prob = p;
-    build_precond(p->mh, *opts, part, pc->ph);
+    pc->nvec = (int64_t)bs * p->mh.n;
+    build_precond(p->mh, *opts, part, pc->ph, bs);
     PrecondHost &ph = pc->ph;
     const int T = ph.tile;
     for (const SubInfo &s : ph.subs) {
@@ -1088,7 +1146,7 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
     pc->status = dev_alloc<int>(1);
     // transposed-apply gather lists: global unknown -> local copies
     {
-      const int64_t N = p->N;
+      const int64_t N = pc->nvec;
       std::vector<int64_t> gptr(N + 1, 0);
       for (int32_t gidx : ph.l2g) gptr[gidx + 1]++;
       for (int64_t i = 0; i < N; ++i) gptr[i + 1] += gptr[i];
@@ -1137,8 +1195,7 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
     delete pc;
     throw;
   }
-  *out = pc;
-  API_END
+  return pc;
 }
 
 void seird_precond_destroy(seird_precond pc) { delete pc; }
@@ -1236,12 +1293,22 @@ seird_status seird_precond_perf(seird_precond pc, seird_precond_perf_report *r, 
   API_END
 }
 
+static void precond_setup_raw(seird_precond pc, const double *diag, const double *off, hipStream_t st);
+
 static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t st) {
   seird_problem P = pc->prob;
+  pc->vals_setup = vals;
+  precond_setup_raw(pc, P->diag(vals), P->off(vals), st);
+}
+
+// setup from the matrix in node-block form (bs = 5: diag [n][25], off
+// [slots][10]) or scalar form (bs = 1: diag [n], off [slots])
+static void precond_setup_raw(seird_precond pc, const double *diag, const double *off, hipStream_t st) {
   PrecondHost &ph = pc->ph;
   HIPCHECK(hipMemsetAsync(pc->status, 0, sizeof(int), st));
   FactorLaunch fl;
   fl.tile = ph.tile;
+  fl.bs = ph.bs;
   fl.Fs = pc->Fs;
   fl.sub_float = pc->sub_float;
   fl.sub_entries = ph.factor_entries;
@@ -1282,7 +1349,7 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
     // fork: the coarse chain waits for everything already queued on st
     HIPCHECK(hipEventRecord(pc->ev_fork, st));
     HIPCHECK(hipStreamWaitEvent(pc->st_coarse, pc->ev_fork, 0));
-    launch_setup_factors(fl, P->diag(vals), P->off(vals), st, pc->st_coarse);
+    launch_setup_factors(fl, diag, off, st, pc->st_coarse);
     if (pc->Xc) {
       if (pc->coarse_block != pc->coarse_block_next) pc->clear_graphs();
       pc->coarse_block = pc->coarse_block_next;
@@ -1291,7 +1358,7 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
     HIPCHECK(hipEventRecord(pc->ev_join, pc->st_coarse));
     HIPCHECK(hipStreamWaitEvent(st, pc->ev_join, 0));
   } else {
-    launch_setup_factors(fl, P->diag(vals), P->off(vals), st, st);
+    launch_setup_factors(fl, diag, off, st, st);
   }
   HIPCHECK(hipGetLastError());
   if (pc->Fb) launch_convert(pc->Fb, ph.prec, pc->Fs, pc->sub_float ? 1 : 0, ph.factor_entries, st);
@@ -1307,14 +1374,22 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
     pc->set_count++;
   }
   pc->ready = true;
-  pc->vals_setup = vals;
   if (status & 2) fail(SEIRD_ERR_ARG, "internal: local matrix entry outside the stored tiles");
   if (status) fail(SEIRD_ERR_BREAKDOWN, "zero or nonfinite pivot in a local LU factorisation");
+}
+
+seird_status seird_precond_setup_scalar(seird_precond pc, const double *diag, const double *off, void *stream) {
+  API_BEGIN
+  if (!pc || !diag || !off) fail(SEIRD_ERR_ARG, "null argument");
+  if (pc->ph.bs != 1) fail(SEIRD_ERR_ARG, "not a scalar (compartment-wise) preconditioner");
+  precond_setup_raw(pc, diag, off, (hipStream_t)stream);
+  API_END
 }
 
 seird_status seird_precond_setup(seird_precond pc, const double *vals, void *stream) {
   API_BEGIN
   if (!pc || !vals) fail(SEIRD_ERR_ARG, "null argument");
+  if (pc->ph.bs != NC) fail(SEIRD_ERR_ARG, "a scalar preconditioner is set up with seird_precond_setup_scalar");
   precond_setup_impl(pc, vals, (hipStream_t)stream);
   API_END
 }
@@ -1611,6 +1686,108 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
   API_END
 }
 
+// ------------------------------------------------------------------------
+// Decoupled Picard-Gauss-Seidel step (Appendix A, Eqs. weak_vec_implicit and
+// picardtol): per sweep, the lagged scalar stiffness, then the compartments
+// S, E, I, R, D one after the other, each a scalar system on the node graph
+// solved in correction form by GMRES with a one-level RAS of scalar
+// subdomains (a diagonal system, nu_c = 0, directly); stop when the sweep's
+// update epsilon = ||u^{k+1} - u^k|| / ||u^n|| is at most tol.
+// ------------------------------------------------------------------------
+struct seird_pgs_s {
+  seird_problem prob = nullptr;
+  seird_precond pc = nullptr;  // bs = 1
+  SegHost seg, seg_act, seg_re;  // one segment of n entries
+  double *uk = nullptr, *Kd = nullptr, *Ko = nullptr, *sdiag = nullptr, *soff = nullptr, *r = nullptr,
+         *delta = nullptr;
+  ~seird_pgs_s() {
+    delete pc;
+    dev_free(seg.d_seg_start); dev_free(seg.d_blk_start); dev_free(seg.d_block_seg);
+    dev_free(uk); dev_free(Kd); dev_free(Ko); dev_free(sdiag); dev_free(soff); dev_free(r); dev_free(delta);
+  }
+};
+
+static void pgs_step_impl(seird_pgs g, double *u, double dt, const seird_pgs_opts &po, const seird_krylov_opts &ko,
+                          seird_pgs_stats &stats, hipStream_t st) {
+  using clk = std::chrono::steady_clock;
+  const auto t_start = clk::now();
+  seird_problem p = g->prob;
+  if (p->seg.S != 1) fail(SEIRD_ERR_ARG, "Picard-Gauss-Seidel steps take a single problem");
+  if (po.max_sweeps < 1 || po.max_sweeps > SEIRD_MAX_PGS) fail(SEIRD_ERR_ARG, "max_sweeps out of range");
+  const int64_t n = p->mh.n, N = p->N;
+  stats = seird_pgs_stats{};
+  HIPCHECK(hipMemcpyAsync(p->u_prev, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+  {
+    HIPCHECK(hipMemsetAsync(p->flags, 0, sizeof(int), st));
+    launch_check_state(u, n, nullptr, p->flags, st);
+    int f = 0;
+    HIPCHECK(hipMemcpyAsync(&f, p->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    if (f & 1) fail(SEIRD_ERR_NONFINITE, "nonfinite state");
+    if (f & 2) fail(SEIRD_ERR_STATE, "total density N <= 0 at a node");
+  }
+  const double unorm = p->seg_norms(p->u_prev, st)[0];
+  GmresOps ops;
+  ops.N = n;
+  ops.seg = &g->seg;
+  ops.seg_act = &g->seg_act;
+  ops.seg_re = &g->seg_re;
+  ops.spmv = [g](const double *x, const double *b, double *y, hipStream_t s) {
+    launch_scalar_spmv(g->prob->md, g->sdiag, g->soff, x, b, y, s);
+  };
+  ops.prec = [g](const double *r, double *z, hipStream_t s, const uint8_t *, const std::vector<uint8_t> *) {
+    g->pc->apply(nullptr, r, z, 0, s);
+  };
+  seird_krylov_opts o = ko;
+  o.graphs = 0;
+  std::vector<seird_krylov_stats> ks;
+  for (int k = 1;; ++k) {
+    HIPCHECK(hipMemcpyAsync(g->uk, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    launch_pgs_stiffness(p->md, g->uk, g->Kd, g->Ko, st);
+    for (int c = 0; c < NC; ++c) {
+      launch_pgs_system(p->md, p->P, p->gfield, c, dt, u, g->uk, p->u_prev, g->Kd, g->Ko, g->sdiag, g->soff, g->r,
+                        st);
+      if (p->P.nu[c] == 0.0) {  // lumped mass only: a diagonal system
+        launch_pgs_update(u, c, g->r, g->sdiag, n, st);
+        continue;
+      }
+      auto t0 = clk::now();
+      precond_setup_raw(g->pc, g->sdiag, g->soff, st);
+      stats.pc_setups++;
+      stats.t_setup_ms += std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+      t0 = clk::now();
+      gmres_core(p, ops, g->r, g->delta, o, ks, std::vector<uint8_t>(1, 1), st, KrylovWork{});
+      stats.t_gmres_ms += std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+      stats.gmres_its[c] += ks[0].its;
+      if (ks[0].reason == SEIRD_ERR_DIVERGED) fail(SEIRD_ERR_DIVERGED, "GMRES diverged in compartment " + std::to_string(c));
+      if (ks[0].reason == SEIRD_ERR_NOT_CONVERGED) {
+        stats.inexact_solves++;
+        if (po.strict_linear)
+          fail(SEIRD_ERR_NOT_CONVERGED, "GMRES reached max_it in compartment " + std::to_string(c) + " of sweep " +
+                                            std::to_string(k));
+      }
+      launch_pgs_update(u, c, g->delta, nullptr, n, st);
+    }
+    // epsilon of Eq. picardtol: ||u^{k+1} - u^k|| / ||u^n||
+    HIPCHECK(hipMemcpyAsync(p->w1, g->uk, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    launch_axpby(p->w1, u, 1.0, nullptr, 0, -1.0, N, reduction_blocks(N), st);
+    const double eps = p->seg_norms(p->w1, st)[0] / unorm;
+    stats.eps_hist[k - 1] = eps;
+    stats.sweeps = k;
+    if (!std::isfinite(eps)) fail(SEIRD_ERR_NONFINITE, "nonfinite Picard-Gauss-Seidel update");
+    if (eps <= po.tol) break;
+    if (k >= po.max_sweeps)
+      fail(SEIRD_ERR_NOT_CONVERGED, "Picard-Gauss-Seidel did not reach epsilon " + std::to_string(po.tol) + " in " +
+                                        std::to_string(k) + " sweeps (last " + std::to_string(eps) + ")");
+  }
+  // the coupled residual of the result, scaled as the Newton stopping test
+  launch_residual(p->md, p->P, p->gfield, u, p->u_prev, dt, nullptr, p->F, st);
+  const double fn = p->seg_norms(p->F, st)[0];
+  const double scale = p->seg_norms(p->u_prev, st, p->md.mass)[0];
+  stats.res_scaled = fn / scale;
+  stats.t_total_ms = std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
+}
+
 struct seird_batch_s {
   seird_problem prob = nullptr;
   seird_precond pc = nullptr;
@@ -1620,6 +1797,74 @@ struct seird_batch_s {
     delete prob;
   }
 };
+
+seird_status seird_pgs_create(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part, seird_pgs *out) {
+  API_BEGIN
+  if (!p || !opts || !part || !out) fail(SEIRD_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (p->seg.S != 1) fail(SEIRD_ERR_ARG, "Picard-Gauss-Seidel steps take a single problem");
+  if (opts->n_ref != 0) fail(SEIRD_ERR_ARG, "the compartment-wise preconditioner is one-level (n_ref = 0)");
+  auto g = new seird_pgs_s();
+  try {
+    g->prob = p;
+    g->pc = precond_create_impl(p, opts, part, 1);
+    const int64_t n = p->mh.n, ns = (int64_t)p->mh.col.size();
+    SegHost sg;
+    sg.S = 1;
+    sg.seg_start = {0, n};
+    sg.blk_start = {0, std::max<int64_t>(1, (n + SEG_CH - 1) / SEG_CH)};
+    sg.B = (int)sg.blk_start[1];
+    sg.block_seg.assign(sg.B, 0);
+    sg.d_seg_start = dev_upload(sg.seg_start);
+    sg.d_blk_start = dev_upload(sg.blk_start);
+    sg.d_block_seg = dev_upload(sg.block_seg);
+    g->seg = sg;
+    g->seg_act = sg;
+    g->seg_act.d_active = p->d_mask;
+    g->seg_re = sg;
+    g->seg_re.d_active = p->d_mask2;
+    g->uk = dev_alloc<double>(p->N);
+    g->Kd = dev_alloc<double>(n);
+    g->Ko = dev_alloc<double>(ns);
+    g->sdiag = dev_alloc<double>(n);
+    g->soff = dev_alloc<double>(ns);
+    g->r = dev_alloc<double>(n);
+    g->delta = dev_alloc<double>(n);
+  } catch (...) {
+    delete g;
+    throw;
+  }
+  *out = g;
+  API_END
+}
+
+void seird_pgs_destroy(seird_pgs g) { delete g; }
+
+seird_status seird_pgs_precond(seird_pgs g, seird_precond *out) {
+  API_BEGIN
+  if (!g || !out) fail(SEIRD_ERR_ARG, "null argument");
+  *out = g->pc;
+  API_END
+}
+
+seird_status seird_pgs_step(seird_pgs g, double *u, double dt, const seird_pgs_opts *popts,
+                            const seird_krylov_opts *kopts, seird_pgs_stats *stats, void *stream) {
+  seird_pgs_stats s{};
+  int code = SEIRD_OK;
+  try {
+    if (!g || !u || !popts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
+    pgs_step_impl(g, u, dt, *popts, *kopts, s, (hipStream_t)stream);
+  } catch (const Error &e) {
+    code = e.code;
+    g_last_error = e.msg;
+  } catch (const std::exception &e) {
+    code = SEIRD_ERR_ARG;
+    g_last_error = std::string("internal: ") + e.what();
+  }
+  s.reason = code;
+  if (stats) *stats = s;
+  return code;
+}
 
 seird_status seird_batch_create(int32_t n_inst, const int64_t *n_nodes, const double *const *xy, const int64_t *n_tri,
                                 const int32_t *const *tri, const seird_params *params, const int32_t *const *part,

@@ -101,6 +101,15 @@ void launch_fill(double *y, double v, int64_t N, hipStream_t st);
 void launch_axpby(double *y, const double *x, double a, const double *aptr, int ainv, double b, int64_t N, int nb,
                   hipStream_t st);
 void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st);
+// decoupled Picard-Gauss-Seidel sweep: lagged scalar stiffness, one
+// compartment's scalar system (correction form), scalar SpMV, update
+void launch_pgs_stiffness(const MeshDev &m, const double *uk, double *Kd, double *Ko, hipStream_t st);
+void launch_pgs_system(const MeshDev &m, const ParamsDev &P, const double *g, int c, double dt, const double *u,
+                       const double *uk, const double *un, const double *Kd, const double *Ko, double *sdiag,
+                       double *soff, double *r, hipStream_t st);
+void launch_scalar_spmv(const MeshDev &m, const double *sdiag, const double *soff, const double *x, const double *b,
+                        double *y, hipStream_t st);
+void launch_pgs_update(double *u, int c, const double *delta, const double *sdiag, int64_t n, hipStream_t st);
 // per-instance flags (inst nullable: one instance), flags[S] zeroed by the caller
 void launch_check_state(const double *u, int64_t n, const int32_t *inst, int *flags, hipStream_t st);
 // the coarse factorisation goes to st_coarse (may equal st), the subdomains to st

@@ -408,6 +408,121 @@ __global__ __launch_bounds__(256) void k_check_state(const double *__restrict__ 
 }
 
 // ----------------------------------------------------------------------
+// Decoupled Picard-Gauss-Seidel sweep (Appendix A, Eq. weak_vec_implicit):
+// the compartments are solved one after the other as scalar systems whose
+// diffusion coefficient N and Allee factor a = 1 - A/N are lagged at the
+// sweep's start (uk) while the compartments already updated in the sweep
+// enter with their new values.  Compartment c's system is
+//   A_c = diag(m_i (1 + dt q_c,i)) + dt nu_c Ksc(N^k),
+//   rhs_c = m (u^n_c + dt f_c),
+// with Ksc the scalar P1 stiffness weighted by the element-mean lagged
+// density, q_c the loss rate of compartment c and f_c its gain:
+//   S: q = a g (bI i + bE e) + mu,        f = alpha N^k
+//   E: q = sigma + gE + mu - a g bE s,    f = a g bI s i
+//   I: q = gR + gD + mu,                  f = sigma e
+//   R: q = mu,                            f = gE e + gR i
+//   D: q = 0,                             f = gD i
+// (s, e, i from the current state; at the fixed point every lagged value
+// equals the new one and u solves the coupled residual).
+// ----------------------------------------------------------------------
+// Ksc: Kd[i] = sum_{T ni i} Nbar_T K^T_ii, Ko[s] = sum over the triangles of
+// edge (i, j) of Nbar_T K^T_ij (slot s = (i, j) of the node graph), each
+// entry written once by the thread of node i.
+constexpr int PGS_MAXINC = 16;  // element means held in registers per node
+__global__ __launch_bounds__(256) void k_pgs_stiffness(MeshDev m, const double *__restrict__ uk,
+                                                       double *__restrict__ Kd, double *__restrict__ Ko) {
+  const int64_t i = xcd_thread();
+  if (i >= m.n) return;
+  double ui[5];
+  load5(uk + 5 * i, ui);
+  const double Ni = ui[0] + ui[1] + ui[2] + ui[3] + ui[4];
+  const int64_t k0 = m.inc_ptr[i], k1 = m.inc_ptr[i + 1];
+  auto nbar = [&](int64_t k) {
+    double uj[5], ul[5];
+    load5(uk + 5 * (int64_t)m.inc_j[k], uj);
+    load5(uk + 5 * (int64_t)m.inc_l[k], ul);
+    return (Ni + (uj[0] + uj[1] + uj[2] + uj[3] + uj[4]) + (ul[0] + ul[1] + ul[2] + ul[3] + ul[4])) * (1.0 / 3.0);
+  };
+  double nb[PGS_MAXINC];
+  double kd = 0.0;
+  for (int64_t k = k0; k < k1; ++k) {
+    const double b = nbar(k);
+    if (k - k0 < PGS_MAXINC) nb[k - k0] = b;
+    kd += b * m.inc_K[3 * k];
+  }
+  Kd[i] = kd;
+  for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
+    double o = 0.0;
+    for (int64_t k = k0; k < k1; ++k) {
+      const bool atj = m.inc_sj[k] == s, atl = m.inc_sl[k] == s;
+      if (!atj && !atl) continue;
+      const double b = k - k0 < PGS_MAXINC ? nb[k - k0] : nbar(k);
+      o += b * (atj ? m.inc_K[3 * k + 1] : m.inc_K[3 * k + 2]);
+    }
+    Ko[s] = o;
+  }
+}
+
+// Compartment c's system: sdiag, soff (slot values) and, in correction
+// form, r = rhs_c - A_c u_c (the update solves A_c delta = r).
+__global__ __launch_bounds__(256) void k_pgs_system(MeshDev m, ParamsDev P, const double *__restrict__ gfield,
+                                                    int c, double dt, const double *__restrict__ u,
+                                                    const double *__restrict__ uk, const double *__restrict__ un,
+                                                    const double *__restrict__ Kd, const double *__restrict__ Ko,
+                                                    double *__restrict__ sdiag, double *__restrict__ soff,
+                                                    double *__restrict__ r) {
+  const int64_t i = xcd_thread();
+  if (i >= m.n) return;
+  double v[5], w[5];
+  load5(u + 5 * i, v);
+  load5(uk + 5 * i, w);
+  const double Nk = w[0] + w[1] + w[2] + w[3] + w[4];
+  const double a = 1.0 - P.A / Nk;
+  const double g = gfield ? gfield[i] : 1.0;
+  const double s = v[0], e = v[1], ii = v[2];
+  double q, f;
+  switch (c) {
+    case 0: q = a * g * (P.bI * ii + P.bE * e) + P.mu; f = P.alpha * Nk; break;
+    case 1: q = P.sigma + P.gE + P.mu - a * g * P.bE * s; f = a * g * P.bI * s * ii; break;
+    case 2: q = P.gR + P.gD + P.mu; f = P.sigma * e; break;
+    case 3: q = P.mu; f = P.gE * e + P.gR * ii; break;
+    default: q = 0.0; f = P.gD * ii; break;
+  }
+  const double mi = m.mass[i];
+  const double sc = dt * P.nu[c];
+  const double di = mi * (1.0 + dt * q) + sc * Kd[i];
+  sdiag[i] = di;
+  double Au = di * v[c];
+  for (int64_t t = m.rowptr[i]; t < m.rowptr[i + 1]; ++t) {
+    const double o = sc * Ko[t];
+    soff[t] = o;
+    Au += o * u[5 * (int64_t)m.col[t] + c];
+  }
+  r[i] = mi * (un[5 * i + c] + dt * f) - Au;
+}
+
+// y = A x (b == nullptr) or y = b - A x for a scalar matrix on the node
+// graph (diagonal + one value per slot); one thread per row, terms summed
+// diagonal first, then slots in order.
+__global__ __launch_bounds__(256) void k_scalar_spmv(MeshDev m, const double *__restrict__ sdiag,
+                                                     const double *__restrict__ soff, const double *__restrict__ x,
+                                                     const double *__restrict__ b, double *__restrict__ y) {
+  const int64_t i = xcd_thread();
+  if (i >= m.n) return;
+  double acc = sdiag[i] * x[i];
+  for (int64_t t = m.rowptr[i]; t < m.rowptr[i + 1]; ++t) acc += soff[t] * x[m.col[t]];
+  y[i] = b ? b[i] - acc : acc;
+}
+
+// u_c += delta (dinv == nullptr) or u_c += r / sdiag (a diagonal system)
+__global__ __launch_bounds__(256) void k_pgs_update(double *__restrict__ u, int c, const double *__restrict__ delta,
+                                                    const double *__restrict__ sdiag, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  u[5 * i + c] += sdiag ? delta[i] / sdiag[i] : delta[i];
+}
+
+// ----------------------------------------------------------------------
 // Segmented reductions.  A vector of N entries is split into segments (one
 // per problem instance; a single problem is one segment).  Every segment is
 // cut into chunks of SEG_CH entries, one block per chunk; block b sums its
@@ -2443,6 +2558,23 @@ void launch_axpby(double *y, const double *x, double a, const double *aptr, int 
 void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2_partials, dim3(nb), dim3(256), 0, st, x, scale, N, partials);
 }
+void launch_pgs_stiffness(const MeshDev &m, const double *uk, double *Kd, double *Ko, hipStream_t st) {
+  hipLaunchKernelGGL(k_pgs_stiffness, dim3(nblocks(m.n)), dim3(256), 0, st, m, uk, Kd, Ko);
+}
+void launch_pgs_system(const MeshDev &m, const ParamsDev &P, const double *g, int c, double dt, const double *u,
+                       const double *uk, const double *un, const double *Kd, const double *Ko, double *sdiag,
+                       double *soff, double *r, hipStream_t st) {
+  hipLaunchKernelGGL(k_pgs_system, dim3(nblocks(m.n)), dim3(256), 0, st, m, P, g, c, dt, u, uk, un, Kd, Ko, sdiag,
+                     soff, r);
+}
+void launch_scalar_spmv(const MeshDev &m, const double *sdiag, const double *soff, const double *x, const double *b,
+                        double *y, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_spmv, dim3(nblocks(m.n)), dim3(256), 0, st, m, sdiag, soff, x, b, y);
+}
+void launch_pgs_update(double *u, int c, const double *delta, const double *sdiag, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_pgs_update, dim3(nblocks(n)), dim3(256), 0, st, u, c, delta, sdiag, n);
+}
+
 void launch_check_state(const double *u, int64_t n, const int32_t *inst, int *flags, hipStream_t st) {
   hipLaunchKernelGGL(k_check_state, dim3(nblocks(n)), dim3(256), 0, st, u, n, inst, flags);
 }

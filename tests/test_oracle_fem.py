@@ -184,6 +184,25 @@ def test_picard_and_picard_gs_reach_the_newton_root():
     assert np.abs(ug - un).max() <= 1e-11
 
 
+def test_picard_gs_with_vital_dynamics_and_nu_d_reaches_the_newton_root():
+    """With births, deaths, a diffusing D and a transmission field, the
+    Appendix A sweep (mu on the diagonals, alpha N lagged on the S
+    right-hand side) still converges to the coupled Newton root; dropping
+    the births from the sweep moves its fixed point off the root."""
+    xy, tri, geo = _geo(8)
+    p = si.Params(**{**si.params_square().__dict__, "nu": (0.01, 0.012, 0.005, 0.01, 0.004),
+                     "alpha": 0.02, "mu": 0.01})
+    u0 = si.gaussian_bump_state(xy, 3, peak=0.05, width=0.2)
+    g = np.random.default_rng(1).uniform(0.7, 1.3, geo.n)
+    un, _ = newton.newton_step(u0, 0.3, geo, p, g, tol=1e-13)
+    ug, info = newton.picard_gs_step(u0, 0.3, geo, p, g, tol=1e-14)
+    assert np.abs(ug - un).max() <= 1e-11 * np.abs(un).max()
+    assert info["eps_hist"][-1] <= 1e-14 and info["its"] >= 3
+    p0 = si.Params(**{**p.__dict__, "alpha": 0.0})
+    ug0, _ = newton.picard_gs_step(u0, 0.3, geo, p0, g, tol=1e-14)
+    assert np.abs(ug0 - un).max() > 1e-6
+
+
 def _golden_orders():
     out = {}
     with open(os.path.join(GOLDEN, "paper_mms_orders.txt")) as f:

@@ -229,3 +229,25 @@ def test_planted_two_level_mistakes_are_caught():
     for bad in (no_post, no_pre, additive_coarse):
         e_prop, e_p5 = _two_level_defects(bad)
         assert e_prop > 1e-2 and e_p5 > 1e-2, bad.__name__
+
+
+def test_scalar_ras_pins():
+    """One-compartment RAS (one unknown per node): a single subdomain is the
+    exact inverse, and on a matrix decoupled along the partition the owner-
+    restricted prolongation is exact while adding every copy is not."""
+    cfg = si.config_small(nx=16)
+    geo = fem.Geometry(cfg.xy, cfg.tri)
+    G = fem.node_graph(geo)
+    Nbar = np.linspace(0.5, 1.5, len(geo.tri))
+    A = (sp.diags(geo.mass) + 0.3 * newton._stiffness(geo, Nbar)).tocsr()
+    b = np.random.default_rng(4).standard_normal(geo.n)
+    x = spla.spsolve(A.tocsc(), b)
+    one = krylov.RAS(A, G, np.zeros(geo.n, np.int32), 1, 0, bs=1)
+    assert np.linalg.norm(one.apply(b) - x) <= 1e-12 * np.linalg.norm(x)
+    Ac = A.tocoo()
+    keep = cfg.part[Ac.row] == cfg.part[Ac.col]
+    Ad = sp.coo_matrix((Ac.data[keep], (Ac.row[keep], Ac.col[keep])), shape=A.shape).tocsr()
+    xd = spla.spsolve(Ad.tocsc(), b)
+    ras = krylov.RAS(Ad, G, cfg.part, cfg.n_sub, 2, bs=1)
+    assert np.linalg.norm(ras.apply(b) - xd) <= 1e-12 * np.linalg.norm(xd)
+    assert np.linalg.norm(_asm_apply(ras, b) - xd) >= 1e-3 * np.linalg.norm(xd)
