@@ -35,7 +35,8 @@
  *    returns a message (thread-local).  No exception crosses the ABI.
  *  - Handles are not thread-safe; calls on one handle must not overlap.
  *  - The library allocates its own device memory at create time (freed by
- *    the matching destroy).
+ *    the matching destroy), unless the problem was created inside a
+ *    caller-owned workspace (seird_create_in_workspace).
  */
 #ifndef SEIRD_H
 #define SEIRD_H
@@ -55,6 +56,7 @@ typedef int seird_status;
 #define SEIRD_ERR_BREAKDOWN (-5)     /* zero or tiny pivot in a local LU */
 #define SEIRD_ERR_DIVERGED (-6)      /* GMRES residual > dtol * ||b|| */
 #define SEIRD_ERR_NOT_CONVERGED (-7) /* iteration cap reached */
+#define SEIRD_ERR_WORKSPACE (-8)     /* caller workspace too small or not reserved for this use */
 #define SEIRD_ERR_STATE (-9)         /* total density N <= 0 at a node */
 
 typedef struct seird_problem_s *seird_problem;
@@ -169,6 +171,67 @@ typedef struct {
   int32_t inexact_solves;
 } seird_step_stats;
 
+/* ------------------------------------------------------------------
+ * Meshes and caller-owned workspaces.
+ * A mesh handle holds host data only (node graph, element incidence,
+ * lumped mass); problems are created from it either with library-owned
+ * device memory (seird_problem_create_from_mesh) or inside one device
+ * workspace the caller allocated (seird_create_in_workspace), in which
+ * case the library calls no hipMalloc for the problem, its preconditioner,
+ * their solves, steps and adjoint records.
+ * ------------------------------------------------------------------ */
+typedef struct seird_mesh_s *seird_mesh;
+/* What a workspace reserves beyond the problem and its preconditioner:
+ *  restart_max: the largest GMRES restart any solve will use (the Krylov
+ *    basis V [restart_max + 1][N] and Z [restart_max][N] are reserved;
+ *    a larger restart later fails with SEIRD_ERR_WORKSPACE);
+ *  tape_states: state vectors [n][5] for adjoint records: a record of
+ *    n_steps with checkpoints every c steps needs ceil(n_steps / c) + c + 4
+ *    (checkpoints, one segment's states, the adjoint vectors); 0 = no
+ *    adjoint records (seird_forward_record then fails with
+ *    SEIRD_ERR_WORKSPACE);
+ *  n_regions_max: the most observation regions of a record;
+ *  csr_pattern: 1 keeps room for seird_csr's pattern (25 (n_slots + n)
+ *    int32 columns and 5 n + 1 int64 row offsets). */
+typedef struct {
+  int32_t restart_max;
+  int32_t tape_states;
+  int32_t n_regions_max;
+  int32_t csr_pattern;  /* 1: keep room for the scalar CSR pattern of seird_csr */
+} seird_workspace_opts;
+
+/* Validate and build a triangle mesh (host arrays copied; no device
+ * memory).  Errors as seird_problem_create. */
+seird_status seird_mesh_create(int64_t n_nodes, const double *xy, int64_t n_tri,
+                               const int32_t *tri, seird_mesh *out);
+void seird_mesh_destroy(seird_mesh m);
+seird_status seird_mesh_info(seird_mesh m, int64_t *n_nodes, int64_t *n_slots);
+/* A problem on the mesh with library-owned device memory (the mesh data are
+ * copied; the mesh may be destroyed afterwards). */
+seird_status seird_problem_create_from_mesh(seird_mesh m, const seird_params *params,
+                                            seird_problem *out);
+/* Bytes of device workspace that seird_create_in_workspace needs for this
+ * mesh, preconditioner (opts and part as seird_precond_create; opts = NULL:
+ * no preconditioner) and reservation.  Host only: no device call. */
+seird_status seird_workspace_bytes(seird_mesh m, const seird_schwarz_opts *opts,
+                                   const int32_t *part, const seird_workspace_opts *wo,
+                                   int64_t *bytes);
+/* Create the problem (and, with opts, its preconditioner) with every device
+ * array inside ws (device memory of ws_bytes bytes, 256-byte aligned, owned
+ * by the caller, which keeps it allocated until both handles are
+ * destroyed; destroy the preconditioner before the problem).
+ * SEIRD_ERR_WORKSPACE if ws_bytes is below seird_workspace_bytes.  The
+ * handles are used as any others; what allocates nothing here: the setup,
+ * apply, SpMV, assembly, GMRES (restart <= restart_max, graphs = 0),
+ * step, forward record and adjoint calls (HIP graphs, which the runtime
+ * allocates for, stay available with graphs = 1). */
+seird_status seird_create_in_workspace(seird_mesh m, const seird_params *params,
+                                       const seird_schwarz_opts *opts,
+                                       const int32_t *part,
+                                       const seird_workspace_opts *wo, void *ws,
+                                       int64_t ws_bytes, seird_problem *prob,
+                                       seird_precond *pc);
+
 const char *seird_last_error(void);
 /* Version string of the library (build identifier). */
 const char *seird_version(void);
@@ -213,6 +276,20 @@ seird_status seird_residual(seird_problem p, const double *u,
 seird_status seird_jacobian_size(seird_problem p, int64_t *n_vals);
 seird_status seird_jacobian(seird_problem p, const double *u, double dt,
                             double *vals, void *stream);
+/* The Jacobian as a scalar CSR matrix of N = 5 n_nodes rows: row 5 i + c
+ * holds, for every node j of {i} and its mesh neighbours in increasing
+ * order, the five columns 5 j .. 5 j + 4 (block (i, j) of the node-block
+ * storage, row c, including its structural zeros), so nnz = 25 (n_slots +
+ * n_nodes).  seird_csr returns the pattern: device int64 rowptr [N + 1]
+ * and int32 col [nnz], owned by the problem (built on the first call,
+ * read-only, valid until the problem is destroyed); seird_csr_values
+ * writes the values of node-block Jacobian `vals` in that order into the
+ * caller's device array csr_vals [nnz] (async).  SEIRD_ERR_WORKSPACE for a
+ * workspace problem created without csr_pattern. */
+seird_status seird_csr(seird_problem p, const int64_t **rowptr, const int32_t **col,
+                       int64_t *nnz, int64_t *nrows);
+seird_status seird_csr_values(seird_problem p, const double *vals, double *csr_vals,
+                              void *stream);
 /* y = J x (transpose = 0) or y = J^T x (transpose = 1).  Async. */
 seird_status seird_spmv(seird_problem p, const double *vals, const double *x,
                         double *y, int transpose, void *stream);

@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Problem", "Precond", "PicardGS", "Batch", "SeirdError", "autotune", "gmres", "gmres_noalloc", "step",
+__all__ = ["Mesh", "Problem", "Precond", "PicardGS", "Batch", "workspace_bytes", "create_in_workspace", "SeirdError", "autotune", "gmres", "gmres_noalloc", "step",
            "forward_record", "adjoint", "SEIRDRun", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,7 +28,7 @@ class SeirdError(RuntimeError):
 
 
 STATUS = {0: "OK", -1: "ARG", -2: "MESH", -3: "HIP", -4: "NONFINITE",
-          -5: "BREAKDOWN", -6: "DIVERGED", -7: "NOT_CONVERGED", -9: "STATE"}
+          -5: "BREAKDOWN", -6: "DIVERGED", -7: "NOT_CONVERGED", -8: "WORKSPACE", -9: "STATE"}
 
 
 class _Params(ctypes.Structure):
@@ -104,6 +104,11 @@ class _PgsStats(ctypes.Structure):
                 ("t_setup_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
 
 
+class _WsOpts(ctypes.Structure):
+    _fields_ = [("restart_max", ctypes.c_int32), ("tape_states", ctypes.c_int32),
+                ("n_regions_max", ctypes.c_int32), ("csr_pattern", ctypes.c_int32)]
+
+
 class _AStats(ctypes.Structure):
     _fields_ = [("gmres_its_total", ctypes.c_int32), ("recomputed_steps", ctypes.c_int32),
                 ("t_forward_ms", ctypes.c_double), ("t_reverse_ms", ctypes.c_double)]
@@ -131,6 +136,17 @@ _SIGS = {
     "seird_problem_create": ([ctypes.c_int64, _P, ctypes.c_int64, _P,
                               ctypes.POINTER(_Params), ctypes.POINTER(_P)], ctypes.c_int),
     "seird_problem_destroy": ([_P], None),
+    "seird_mesh_create": ([ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "seird_mesh_destroy": ([_P], None),
+    "seird_mesh_info": ([_P, _I64P, _I64P], ctypes.c_int),
+    "seird_problem_create_from_mesh": ([_P, ctypes.POINTER(_Params), ctypes.POINTER(_P)], ctypes.c_int),
+    "seird_workspace_bytes": ([_P, ctypes.POINTER(_Schwarz), _P, ctypes.POINTER(_WsOpts), _I64P], ctypes.c_int),
+    "seird_create_in_workspace": ([_P, ctypes.POINTER(_Params), ctypes.POINTER(_Schwarz), _P,
+                                   ctypes.POINTER(_WsOpts), _P, ctypes.c_int64, ctypes.POINTER(_P),
+                                   ctypes.POINTER(_P)], ctypes.c_int),
+    "seird_csr": ([_P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), _I64P, _I64P],
+                  ctypes.c_int),
+    "seird_csr_values": ([_P, _P, _P, _P], ctypes.c_int),
     "seird_set_params": ([_P, ctypes.POINTER(_Params)], ctypes.c_int),
     "seird_set_beta_field": ([_P, _P, _P], ctypes.c_int),
     "seird_problem_info": ([_P, _I64P, _I64P], ctypes.c_int),
@@ -240,20 +256,111 @@ def _krylov(restart=30, max_it=200, rtol=1e-5, atol=1e-50, dtol=1e5, graphs=0):
     return _Krylov(int(restart), int(max_it), float(rtol), float(atol), float(dtol), int(bool(graphs)))
 
 
+class Mesh:
+    """A validated triangle mesh held on the host (node graph, element
+    incidence, lumped mass); problems are created from it."""
+
+    def __init__(self, xy, tri):
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().seird_mesh_create(len(xy), xy.ctypes.data, len(tri), tri.ctypes.data, ctypes.byref(h)))
+        self.h = h
+        n, ns = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().seird_mesh_info(self.h, ctypes.byref(n), ctypes.byref(ns)))
+        self.n, self.nslots = n.value, ns.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.seird_mesh_destroy(self.h)
+            self.h = None
+
+
+def _ws_opts(restart_max=30, tape_states=0, n_regions_max=0, csr_pattern=False):
+    return _WsOpts(int(restart_max), int(tape_states), int(n_regions_max), int(bool(csr_pattern)))
+
+
+def workspace_bytes(mesh: Mesh, part=None, n_sub=0, overlap=0, tile=32, factor_prec=0, coarse=None, **ws):
+    """Bytes of device workspace for a problem on ``mesh`` and (with a
+    partition) its Schwarz preconditioner; ``ws``: restart_max, tape_states,
+    n_regions_max, csr_pattern (see seird_workspace_opts)."""
+    wo = _ws_opts(**ws)
+    b = ctypes.c_int64()
+    if part is None:
+        _check(lib().seird_workspace_bytes(mesh.h, None, None, ctypes.byref(wo), ctypes.byref(b)))
+    else:
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        o, keep = _schwarz_opts(n_sub, overlap, tile, factor_prec, coarse)
+        _check(lib().seird_workspace_bytes(mesh.h, ctypes.byref(o), part.ctypes.data, ctypes.byref(wo),
+                                           ctypes.byref(b)))
+        del keep
+    return b.value
+
+
+def create_in_workspace(mesh: Mesh, params, workspace, part=None, n_sub=0, overlap=0, tile=32, factor_prec=0,
+                        coarse=None, **ws):
+    """(Problem, Precond or None) whose device arrays all live in
+    ``workspace`` (a CUDA uint8 tensor of at least workspace_bytes(...)
+    bytes, kept alive by the returned handles)."""
+    torch = _torch()
+    if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or workspace.dtype != torch.uint8:
+        raise TypeError("workspace must be a CUDA uint8 tensor")
+    wo = _ws_opts(**ws)
+    pr = _params(params)
+    hp, hc = ctypes.c_void_p(), ctypes.c_void_p()
+    if part is None:
+        _check(lib().seird_create_in_workspace(mesh.h, ctypes.byref(pr), None, None, ctypes.byref(wo),
+                                               ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                               ctypes.byref(hp), None))
+    else:
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        o, keep = _schwarz_opts(n_sub, overlap, tile, factor_prec, coarse)
+        _check(lib().seird_create_in_workspace(mesh.h, ctypes.byref(pr), ctypes.byref(o), part.ctypes.data,
+                                               ctypes.byref(wo), ctypes.c_void_p(workspace.data_ptr()),
+                                               workspace.numel(), ctypes.byref(hp), ctypes.byref(hc)))
+        del keep
+    prob = Problem._from_handle(hp, params, workspace)
+    pc = Precond._from_handle(hc, prob, workspace) if part is not None else None
+    return prob, pc
+
+
 class Problem:
     """A SEIRD problem on a triangle mesh (host arrays are copied)."""
 
     def __init__(self, xy, tri, params):
         xy = np.ascontiguousarray(xy, dtype=np.float64)
         tri = np.ascontiguousarray(tri, dtype=np.int32)
-        self.n = len(xy)
-        self.N = 5 * self.n
         h = ctypes.c_void_p()
         self._params = _params(params)
-        _check(lib().seird_problem_create(self.n, xy.ctypes.data, len(tri),
+        _check(lib().seird_problem_create(len(xy), xy.ctypes.data, len(tri),
                                           tri.ctypes.data, ctypes.byref(self._params),
                                           ctypes.byref(h)))
+        self._init_handle(h)
+
+    @classmethod
+    def from_mesh(cls, mesh: Mesh, params):
+        h = ctypes.c_void_p()
+        pr = _params(params)
+        _check(lib().seird_problem_create_from_mesh(mesh.h, ctypes.byref(pr), ctypes.byref(h)))
+        obj = cls.__new__(cls)
+        obj._params = pr
+        obj._init_handle(h)
+        return obj
+
+    @classmethod
+    def _from_handle(cls, h, params, workspace):
+        obj = cls.__new__(cls)
+        obj._params = _params(params)
+        obj._workspace = workspace  # keeps the device memory alive
+        obj._init_handle(h)
+        return obj
+
+    def _init_handle(self, h):
         self.h = h
+        ni = ctypes.c_int64()
+        _check(lib().seird_problem_info(self.h, ctypes.byref(ni), None))
+        self.n = ni.value
+        self.N = 5 * self.n
         nv = ctypes.c_int64()
         _check(lib().seird_jacobian_size(self.h, ctypes.byref(nv)))
         self.nvals = nv.value
@@ -298,6 +405,32 @@ class Problem:
         out = torch.empty(self.nvals, dtype=torch.float64, device=u.device) if out is None else out
         _check(lib().seird_jacobian(self.h, _dptr(u, self.N, "u"), float(dt),
                                     _dptr(out, self.nvals, "vals"), _stream()))
+        return out
+
+    def csr(self):
+        """(rowptr, col) device tensors of the Jacobian's scalar CSR pattern
+        (copies) and nnz; see seird_csr."""
+        torch = _torch()
+        rp, col = ctypes.c_void_p(), ctypes.c_void_p()
+        nnz, nrows = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().seird_csr(self.h, ctypes.byref(rp), ctypes.byref(col), ctypes.byref(nnz), ctypes.byref(nrows)))
+        self.csr_nnz = nnz.value
+        hr = np.zeros(nrows.value + 1, dtype=np.int64)
+        hc = np.zeros(nnz.value, dtype=np.int32)
+        import ctypes as _c
+        torch.cuda.synchronize()
+        lib_hip = _hip()
+        lib_hip.hipMemcpy(_c.c_void_p(hr.ctypes.data), rp, _c.c_size_t(hr.nbytes), 2)
+        lib_hip.hipMemcpy(_c.c_void_p(hc.ctypes.data), col, _c.c_size_t(hc.nbytes), 2)
+        return hr, hc
+
+    def csr_values(self, vals, out=None):
+        torch = _torch()
+        if not hasattr(self, "csr_nnz"):
+            self.csr()
+        out = torch.empty(self.csr_nnz, dtype=torch.float64, device=vals.device) if out is None else out
+        _check(lib().seird_csr_values(self.h, _dptr(vals, self.nvals, "vals"), _dptr(out, self.csr_nnz, "out"),
+                                      _stream()))
         return out
 
     def spmv(self, vals, x, transpose=False, out=None):
@@ -350,9 +483,31 @@ def analyze_schwarz(xy, tri, part, n_sub, overlap, tile=32, coarse=None, maps=Fa
     return out
 
 
+_hip_lib = None
+
+
+def _hip():
+    """The HIP runtime (for reading back library-owned device arrays)."""
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = ctypes.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip_lib.hipMemcpy.restype = ctypes.c_int
+    return _hip_lib
+
+
 class Precond:
     """Restricted additive Schwarz (one-level, or multiplicative two-grid
     when ``coarse = (parents_list, n_coarse)`` is given)."""
+
+    @classmethod
+    def _from_handle(cls, h, problem, workspace):
+        obj = cls.__new__(cls)
+        obj.problem = problem
+        obj.h = h
+        obj._vals = None
+        obj._workspace = workspace
+        return obj
 
     def __init__(self, problem: Problem, part, n_sub, overlap, tile=32,
                  factor_prec=0, coarse=None, solve_threads=256):

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <tuple>
 
@@ -19,8 +20,59 @@ static thread_local std::string g_last_error;
 void hip_check(hipError_t e, const char *what) {
   if (e != hipSuccess) fail(SEIRD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
+// caller workspaces in use: (base, bytes, handles referring to it)
+struct WsEntry {
+  uintptr_t base;
+  size_t bytes;
+  int refs;
+};
+static std::mutex g_ws_mu;
+static std::vector<WsEntry> g_workspaces;
+void register_workspace(const void *base, size_t bytes) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  for (auto &w : g_workspaces)
+    if (w.base == (uintptr_t)base) {
+      w.refs++;
+      return;
+    }
+  g_workspaces.push_back({(uintptr_t)base, bytes, 1});
+}
+void unregister_workspace(const void *base) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  for (size_t k = 0; k < g_workspaces.size(); ++k)
+    if (g_workspaces[k].base == (uintptr_t)base) {
+      if (--g_workspaces[k].refs == 0) g_workspaces.erase(g_workspaces.begin() + k);
+      return;
+    }
+}
+Arena *&active_arena() {
+  static thread_local Arena *a = nullptr;
+  return a;
+}
+bool measuring() { return active_arena() && active_arena()->measure; }
+void *Arena::take(size_t bytes) {
+  const size_t b = (bytes + 255) & ~(size_t)255;
+  if (!measure && used + b > cap)
+    fail(SEIRD_ERR_WORKSPACE, "workspace exhausted: " + std::to_string(used + b) + " bytes needed, " +
+                                  std::to_string(cap) + " given");
+  void *p = base + used;
+  used += b;
+  return p;
+}
+void *dev_alloc_bytes(size_t bytes) {
+  if (Arena *a = active_arena()) return a->take(bytes);
+  void *p = nullptr;
+  HIPCHECK(hipMalloc(&p, bytes));
+  return p;
+}
 void dev_free(void *p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    for (const auto &w : g_workspaces)
+      if ((uintptr_t)p >= w.base && (uintptr_t)p < w.base + w.bytes) return;
+  }
+  (void)hipFree(p);
 }
 }  // namespace seird
 
@@ -77,6 +129,46 @@ struct seird_problem_s {
   double *d_svec = nullptr;
   int32_t *d_inst = nullptr;
   ParamsDev *d_Pinst = nullptr;
+  // caller workspace (seird_create_in_workspace), else null: device
+  // memory then comes from it only, with the Krylov basis reserved for
+  // ws_restart, a stored transmission field and a pool for adjoint records
+  void *ws_base = nullptr;
+  size_t ws_bytes = 0;
+  int ws_restart = 0;
+  Arena tape_pool;
+  double *gfield_store = nullptr;
+  // scalar CSR pattern of the Jacobian (seird_csr), built on first request
+  int64_t *csr_rowptr = nullptr;
+  int32_t *csr_col = nullptr;
+  int64_t csr_nnz = 0;
+  bool csr_reserved = false;  // workspace problems: room kept at creation
+  void build_csr() {
+    const int64_t n = mh.n;
+    std::vector<int64_t> rp(5 * n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t deg = mh.rowptr[i + 1] - mh.rowptr[i];
+      for (int c = 0; c < 5; ++c) rp[5 * i + c + 1] = rp[5 * i + c] + 5 * (deg + 1);
+    }
+    std::vector<int32_t> col(rp[5 * n]);
+    for (int64_t i = 0; i < n; ++i) {
+      std::vector<int32_t> nodes(mh.col.begin() + mh.rowptr[i], mh.col.begin() + mh.rowptr[i + 1]);
+      nodes.insert(std::lower_bound(nodes.begin(), nodes.end(), (int32_t)i), (int32_t)i);
+      for (int c = 0; c < 5; ++c) {
+        int64_t q = rp[5 * i + c];
+        for (int32_t j : nodes)
+          for (int cp = 0; cp < 5; ++cp) col[q++] = 5 * j + cp;
+      }
+    }
+    csr_nnz = rp[5 * n];
+    if (csr_rowptr) {  // reserved in the workspace: fill in place
+      HIPCHECK(hipMemcpy(csr_rowptr, rp.data(), sizeof(int64_t) * rp.size(), hipMemcpyHostToDevice));
+      HIPCHECK(hipMemcpy(csr_col, col.data(), sizeof(int32_t) * col.size(), hipMemcpyHostToDevice));
+    } else {
+      csr_rowptr = dev_upload(rp);
+      csr_col = dev_upload(col);
+    }
+  }
+  bool csr_ready = false;
   // adjoint record (checkpoints, last segment, regions)
   struct Tape {
     int n_steps = 0, every = 0, n_regions = 0;
@@ -103,6 +195,12 @@ struct seird_problem_s {
       valid = false;
     }
   } tape;
+  // the arena of adjoint-record allocations (null: hipMalloc)
+  Arena *tape_arena() { return ws_base ? &tape_pool : nullptr; }
+  void release_tape() {
+    tape.release();
+    tape_pool.used = 0;
+  }
 
   ~seird_problem_s() {
     dev_free(md.rowptr); dev_free(md.col); dev_free(md.tslot); dev_free(md.mass);
@@ -113,11 +211,13 @@ struct seird_problem_s {
     dev_free(V); dev_free(Zb); dev_free(w1);
     dev_free(seg.d_seg_start); dev_free(seg.d_blk_start); dev_free(seg.d_block_seg);
     dev_free(d_mask); dev_free(d_mask2); dev_free(d_svec); dev_free(d_inst); dev_free(d_Pinst);
+    dev_free(csr_rowptr); dev_free(csr_col);
     tape.release();
     if (stage) {
       (void)hipStreamSynchronize(stage_st);
       (void)hipHostFree(stage);
     }
+    if (ws_base) unregister_workspace(ws_base);
   }
 
   // segments from instance node offsets (node_start[S+1], node_start[S] = n)
@@ -220,6 +320,9 @@ struct seird_problem_s {
   }
   void ensure_krylov(int m) {
     if (kcap >= m) return;
+    if (ws_base)
+      fail(SEIRD_ERR_WORKSPACE, "GMRES restart " + std::to_string(m) + " above the " + std::to_string(ws_restart) +
+                                    " reserved in the workspace");
     dev_free(V); dev_free(Zb);
     V = dev_alloc<double>((size_t)(m + 1) * N);
     Zb = dev_alloc<double>((size_t)m * N);
@@ -240,6 +343,7 @@ constexpr double COARSE_INVERSE_BUDGET = 16.0e9;
 struct seird_precond_s {
   seird_problem prob = nullptr;
   PrecondHost ph;
+  void *ws_base = nullptr;   // caller workspace holding its device arrays, if any
   int64_t nvec = 0;          // length of the vectors it applies to (bs * n_nodes)
   void *Fs = nullptr;        // subdomain factors as factorised (float64, or float32)
   bool sub_float = false;
@@ -388,6 +492,7 @@ struct seird_precond_s {
     dev_free(coarse_dev); dev_free(gp); dev_free(gq); dev_free(gref); dev_free(cperm); dev_free(gptr); dev_free(gw);
     dev_free(z_ptr); dev_free(zt_ptr); dev_free(z_col); dev_free(zt_col); dev_free(z_val); dev_free(zt_val);
     dev_free(rc); dev_free(xc); dev_free(cscratch); dev_free(ybuf); dev_free(t1); dev_free(Xc); dev_free(Wc);
+    if (ws_base) unregister_workspace(ws_base);
   }
 
   // factors read by the subdomain solves, in the storage precision ph.prec
@@ -960,19 +1065,23 @@ extern "C" {
 const char *seird_last_error(void) { return g_last_error.c_str(); }
 const char *seird_version(void) { return "libseird 0.1 gfx950"; }
 
-seird_status seird_problem_create(int64_t n_nodes, const double *xy, int64_t n_tri, const int32_t *tri,
-                                  const seird_params *params, seird_problem *out) {
-  API_BEGIN
-  if (!out || !params) fail(SEIRD_ERR_ARG, "null argument");
-  *out = nullptr;
+struct seird_mesh_s {
+  MeshHost mh;
+};
+
+// A problem on a built mesh (the host data are copied).  Device memory
+// comes from the active arena, if any (see Arena).
+static seird_problem problem_create_impl(const MeshHost &mh, const seird_params &params) {
   auto P = new seird_problem_s();
   try {
-    HIPCHECK(hipGetDevice(&P->device));
-    int lds = 0;
-    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && lds > 0)
-      P->lds_limit = (size_t)lds;
-    build_mesh(n_nodes, xy, n_tri, tri, P->mh);
-    P->P = to_dev(*params);
+    if (!measuring()) {
+      HIPCHECK(hipGetDevice(&P->device));
+      int lds = 0;
+      if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && lds > 0)
+        P->lds_limit = (size_t)lds;
+    }
+    P->mh = mh;
+    P->P = to_dev(params);
     const MeshHost &m = P->mh;
     P->md.n = m.n;
     P->md.nslots = (int64_t)m.col.size();
@@ -995,13 +1104,165 @@ seird_status seird_problem_create(int64_t n_nodes, const double *xy, int64_t n_t
     P->delta = dev_alloc<double>(P->N);
     P->w1 = dev_alloc<double>(P->N);
     P->vals = dev_alloc<double>(P->nvals());
-    P->reserve_stage((size_t)1 << 20);
-    (void)static_scratch();  // this device's scratch address, looked up once
+    if (!measuring()) {
+      P->reserve_stage((size_t)1 << 20);
+      (void)static_scratch();  // this device's scratch address, looked up once
+    }
   } catch (...) {
     delete P;
     throw;
   }
-  *out = P;
+  return P;
+}
+
+seird_status seird_problem_create(int64_t n_nodes, const double *xy, int64_t n_tri, const int32_t *tri,
+                                  const seird_params *params, seird_problem *out) {
+  API_BEGIN
+  if (!out || !params) fail(SEIRD_ERR_ARG, "null argument");
+  *out = nullptr;
+  MeshHost mh;
+  build_mesh(n_nodes, xy, n_tri, tri, mh);
+  *out = problem_create_impl(mh, *params);
+  API_END
+}
+
+seird_status seird_mesh_create(int64_t n_nodes, const double *xy, int64_t n_tri, const int32_t *tri,
+                               seird_mesh *out) {
+  API_BEGIN
+  if (!out) fail(SEIRD_ERR_ARG, "null argument");
+  *out = nullptr;
+  auto m = new seird_mesh_s();
+  try {
+    build_mesh(n_nodes, xy, n_tri, tri, m->mh);
+  } catch (...) {
+    delete m;
+    throw;
+  }
+  *out = m;
+  API_END
+}
+
+void seird_mesh_destroy(seird_mesh m) { delete m; }
+
+seird_status seird_mesh_info(seird_mesh m, int64_t *n_nodes, int64_t *n_slots) {
+  API_BEGIN
+  if (!m) fail(SEIRD_ERR_ARG, "null mesh");
+  if (n_nodes) *n_nodes = m->mh.n;
+  if (n_slots) *n_slots = (int64_t)m->mh.col.size();
+  API_END
+}
+
+seird_status seird_problem_create_from_mesh(seird_mesh m, const seird_params *params, seird_problem *out) {
+  API_BEGIN
+  if (!m || !params || !out) fail(SEIRD_ERR_ARG, "null argument");
+  *out = nullptr;
+  *out = problem_create_impl(m->mh, *params);
+  API_END
+}
+
+static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
+                                         int bs);
+
+// bytes of the adjoint-record pool of a workspace
+static size_t tape_pool_bytes(int64_t n, const seird_workspace_opts &wo) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  if (wo.tape_states <= 0) return 0;
+  return (size_t)wo.tape_states * up(sizeof(double) * 5 * (size_t)n) + 2 * up(sizeof(int32_t) * (size_t)n) +
+         up(sizeof(int64_t) * ((size_t)std::max(wo.n_regions_max, 0) + 1)) +
+         up(sizeof(double) * (5 * (size_t)((n + 255) / 256) + 8)) + 4096;
+}
+
+// The problem (and, with opts, its preconditioner) with every device array
+// taken from `arena`; in measure mode nothing is allocated.
+static void create_in_arena(const MeshHost &mh, const seird_params &params, const seird_schwarz_opts *opts,
+                            const int32_t *part, const seird_workspace_opts &wo, Arena &arena, seird_problem *prob,
+                            seird_precond *pc) {
+  if (wo.restart_max < 1 || wo.restart_max > KRYLOV_MAX - 1) fail(SEIRD_ERR_ARG, "restart_max must be in [1, 31]");
+  if (wo.tape_states < 0 || wo.n_regions_max < 0) fail(SEIRD_ERR_ARG, "negative workspace reservation");
+  ArenaScope scope(&arena);
+  seird_problem P = problem_create_impl(mh, params);
+  try {
+    P->ensure_krylov(wo.restart_max);
+    P->gfield_store = dev_alloc<double>(mh.n);
+    if (wo.csr_pattern) {
+      const int64_t nnz = 25 * ((int64_t)mh.col.size() + mh.n);
+      P->csr_rowptr = dev_alloc<int64_t>(5 * mh.n + 1);
+      P->csr_col = dev_alloc<int32_t>(nnz);
+      P->csr_reserved = true;
+    }
+    const size_t tb = tape_pool_bytes(mh.n, wo);
+    if (tb > 0) {
+      P->tape_pool.base = static_cast<uint8_t *>(dev_alloc_bytes(tb));
+      P->tape_pool.cap = tb;
+    }
+    if (opts) *pc = precond_create_impl(P, opts, part, NC);
+  } catch (...) {
+    delete P;
+    throw;
+  }
+  *prob = P;
+}
+
+seird_status seird_workspace_bytes(seird_mesh m, const seird_schwarz_opts *opts, const int32_t *part,
+                                   const seird_workspace_opts *wo, int64_t *bytes) {
+  API_BEGIN
+  if (!m || !wo || !bytes) fail(SEIRD_ERR_ARG, "null argument");
+  if (opts && !part) fail(SEIRD_ERR_ARG, "a preconditioner needs the partition");
+  // run the creation with a measuring arena: the same allocations in the
+  // same order, sizes only (the fake addresses are never dereferenced)
+  Arena a;
+  a.measure = true;
+  a.base = reinterpret_cast<uint8_t *>((uintptr_t)1 << 12);
+  seird_params params{};
+  params.A = 0.0;
+  seird_problem P = nullptr;
+  seird_precond pc = nullptr;
+  try {
+    create_in_arena(m->mh, params, opts, part, *wo, a, &P, &pc);
+  } catch (...) {
+    throw;
+  }
+  // the objects' destructors must not free the fake addresses
+  register_workspace(a.base, a.used + 1);
+  if (pc) pc->prob = nullptr;
+  delete pc;
+  delete P;
+  unregister_workspace(a.base);
+  *bytes = (int64_t)a.used;
+  API_END
+}
+
+seird_status seird_create_in_workspace(seird_mesh m, const seird_params *params, const seird_schwarz_opts *opts,
+                                       const int32_t *part, const seird_workspace_opts *wo, void *ws,
+                                       int64_t ws_bytes, seird_problem *prob, seird_precond *pc) {
+  API_BEGIN
+  if (!m || !params || !wo || !ws || !prob || (opts && (!part || !pc))) fail(SEIRD_ERR_ARG, "null argument");
+  if (((uintptr_t)ws & 255) != 0) fail(SEIRD_ERR_ARG, "workspace must be 256-byte aligned");
+  *prob = nullptr;
+  if (pc) *pc = nullptr;
+  Arena a;
+  a.base = static_cast<uint8_t *>(ws);
+  a.cap = (size_t)std::max<int64_t>(ws_bytes, 0);
+  register_workspace(ws, a.cap);  // the creation's own reference, dropped below
+  seird_problem P = nullptr;
+  seird_precond C = nullptr;
+  try {
+    create_in_arena(m->mh, *params, opts, part, *wo, a, &P, &C);
+  } catch (...) {
+    unregister_workspace(ws);
+    throw;
+  }
+  P->ws_base = ws;
+  P->ws_bytes = a.cap;
+  P->ws_restart = wo->restart_max;
+  register_workspace(ws, a.cap);  // held by the problem
+  if (C) {
+    C->ws_base = ws;
+    register_workspace(ws, a.cap);  // held by the preconditioner
+  }
+  unregister_workspace(ws);
+  *prob = P;
+  if (pc) *pc = C;
   API_END
 }
 
@@ -1019,10 +1280,10 @@ seird_status seird_set_beta_field(seird_problem p, const double *g_dev, void *st
   if (!p) fail(SEIRD_ERR_ARG, "null problem");
   hipStream_t st = (hipStream_t)stream;
   if (!g_dev) {
-    dev_free(p->gfield);
+    if (p->gfield != p->gfield_store) dev_free(p->gfield);
     p->gfield = nullptr;
   } else {
-    if (!p->gfield) p->gfield = dev_alloc<double>(p->mh.n);
+    if (!p->gfield) p->gfield = p->gfield_store ? p->gfield_store : dev_alloc<double>(p->mh.n);
     HIPCHECK(hipMemcpyAsync(p->gfield, g_dev, sizeof(double) * p->mh.n, hipMemcpyDeviceToDevice, st));
   }
   API_END
@@ -1086,6 +1347,32 @@ seird_status seird_spmv(seird_problem p, const double *vals, const double *x, do
 
 static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
                                          int bs);
+
+seird_status seird_csr(seird_problem p, const int64_t **rowptr, const int32_t **col, int64_t *nnz,
+                       int64_t *nrows) {
+  API_BEGIN
+  if (!p) fail(SEIRD_ERR_ARG, "null problem");
+  if (!p->csr_ready) {
+    if (p->ws_base && !p->csr_reserved)
+      fail(SEIRD_ERR_WORKSPACE, "the workspace holds no CSR pattern (seird_workspace_opts.csr_pattern)");
+    p->build_csr();
+    p->csr_ready = true;
+  }
+  if (rowptr) *rowptr = p->csr_rowptr;
+  if (col) *col = p->csr_col;
+  if (nnz) *nnz = p->csr_nnz;
+  if (nrows) *nrows = p->N;
+  API_END
+}
+
+seird_status seird_csr_values(seird_problem p, const double *vals, double *csr_vals, void *stream) {
+  API_BEGIN
+  if (!p || !vals || !csr_vals) fail(SEIRD_ERR_ARG, "null argument");
+  if (!p->csr_ready) fail(SEIRD_ERR_ARG, "call seird_csr first (it builds the pattern)");
+  launch_csr_values(p->md, p->diag(vals), p->off(vals), p->csr_rowptr, csr_vals, (hipStream_t)stream);
+  HIPCHECK(hipGetLastError());
+  API_END
+}
 
 seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
                                   seird_precond *out) {
@@ -1176,7 +1463,7 @@ static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_op
       pc->rc = dev_alloc<double>(cpad);
       pc->xc = dev_alloc<double>(cpad);
       pc->cscratch = dev_alloc<double>(cpad);
-      HIPCHECK(hipMemset(pc->rc, 0, sizeof(double) * cpad));
+      if (!measuring()) HIPCHECK(hipMemset(pc->rc, 0, sizeof(double) * cpad));
       pc->t1 = dev_alloc<double>(p->N);
       if (T == 32 && coarse_inverse_bytes(ph.coarse.nt) <= COARSE_INVERSE_BUDGET) {
         const int64_t nt = ph.coarse.nt;
@@ -1187,9 +1474,15 @@ static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_op
         pc->coarse_block = (int)std::min<int64_t>(nt, std::max({COARSE_BLOCK, ph.coarse.bl, ph.coarse.bu}));
         pc->coarse_block_next = pc->coarse_block;
       }
-      HIPCHECK(hipStreamCreateWithFlags(&pc->st_coarse, hipStreamNonBlocking));
-      HIPCHECK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
-      HIPCHECK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
+      if (!measuring()) {
+        HIPCHECK(hipStreamCreateWithFlags(&pc->st_coarse, hipStreamNonBlocking));
+        HIPCHECK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
+        // first work on the stream now, so that the runtime's own resources
+        // for it are set up at creation and not during a later setup
+        HIPCHECK(hipMemsetAsync(pc->status, 0, sizeof(int), pc->st_coarse));
+        HIPCHECK(hipStreamSynchronize(pc->st_coarse));
+      }
     }
   } catch (...) {
     delete pc;
@@ -1576,7 +1869,8 @@ seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, 
   if (n_steps <= 0 || ckpt_every <= 0 || n_regions < 0) fail(SEIRD_ERR_ARG, "bad record sizes");
   hipStream_t st = (hipStream_t)stream;
   auto &T = p->tape;
-  T.release();
+  p->release_tape();
+  ArenaScope tape_scope(p->tape_arena());  // a workspace problem records into its reserved pool
   const int64_t n = p->mh.n, N = p->N;
   // regions: per-node id and CSR of the nodes of each region
   std::vector<int64_t> rp(n_regions + 1, 0);
@@ -1632,6 +1926,7 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
   seird_adjoint_stats as{};
   const int64_t n = p->mh.n, N = p->N;
   if (!T.lam) {
+    ArenaScope tape_scope(p->tape_arena());
     T.lam = dev_alloc<double>(N);
     T.lam_next = dev_alloc<double>(N);
     T.rhs = dev_alloc<double>(N);

@@ -22,17 +22,39 @@ struct Error {
 void hip_check(hipError_t e, const char *what);
 #define HIPCHECK(x) ::seird::hip_check((x), #x)
 
+// Where device memory comes from.  Without an active arena: hipMalloc.
+// With one (set for the duration of a creation inside a caller's
+// workspace): bump allocation of 256-byte aligned pieces of the workspace,
+// SEIRD_ERR_WORKSPACE when it runs out.  A measuring arena allocates and
+// copies nothing and only adds up the sizes (seird_workspace_bytes); code
+// that touches device memory during a creation checks measuring() first.
+struct Arena {
+  uint8_t *base = nullptr;
+  size_t cap = 0, used = 0;
+  bool measure = false;
+  void *take(size_t bytes);
+};
+Arena *&active_arena();  // thread-local; null = hipMalloc
+bool measuring();
+// makes `a` the active arena until the guard ends
+struct ArenaScope {
+  Arena *prev;
+  explicit ArenaScope(Arena *a) : prev(active_arena()) { active_arena() = a; }
+  ~ArenaScope() { active_arena() = prev; }
+};
+// device ranges owned by callers (their workspaces): dev_free skips them
+void register_workspace(const void *base, size_t bytes);
+void unregister_workspace(const void *base);
+
+void *dev_alloc_bytes(size_t bytes);
 template <class T>
 T *dev_alloc(size_t n) {
-  T *p = nullptr;
-  if (n == 0) n = 1;
-  HIPCHECK(hipMalloc(&p, n * sizeof(T)));
-  return p;
+  return static_cast<T *>(dev_alloc_bytes((n == 0 ? 1 : n) * sizeof(T)));
 }
 template <class T>
 T *dev_upload(const std::vector<T> &v) {
   T *p = dev_alloc<T>(v.size());
-  if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (!v.empty() && !measuring()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return p;
 }
 void dev_free(void *p);

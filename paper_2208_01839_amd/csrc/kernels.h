@@ -101,6 +101,9 @@ void launch_fill(double *y, double v, int64_t N, hipStream_t st);
 void launch_axpby(double *y, const double *x, double a, const double *aptr, int ainv, double b, int64_t N, int nb,
                   hipStream_t st);
 void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st);
+// scalar CSR values of the node-block Jacobian (pattern of seird_csr)
+void launch_csr_values(const MeshDev &m, const double *diag, const double *off, const int64_t *csr_rowptr,
+                       double *out, hipStream_t st);
 // decoupled Picard-Gauss-Seidel sweep: lagged scalar stiffness, one
 // compartment's scalar system (correction form), scalar SpMV, update
 void launch_pgs_stiffness(const MeshDev &m, const double *uk, double *Kd, double *Ko, hipStream_t st);

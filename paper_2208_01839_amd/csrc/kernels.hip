@@ -408,6 +408,37 @@ __global__ __launch_bounds__(256) void k_check_state(const double *__restrict__ 
 }
 
 // ----------------------------------------------------------------------
+// Scalar CSR values of the node-block Jacobian: row 5 i + c lists, for the
+// nodes j of {i} and its neighbours in increasing order, the five columns
+// 5 j .. 5 j + 4 (the block (i, j) row c).  One thread per scalar row.
+// ----------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_csr_values(MeshDev m, const double *__restrict__ diag,
+                                                    const double *__restrict__ off,
+                                                    const int64_t *__restrict__ csr_rowptr,
+                                                    double *__restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 5 * m.n) return;
+  const int64_t i = r / 5;
+  const int c = (int)(r % 5);
+  double *o = out + csr_rowptr[r];
+  bool diag_done = false;
+  auto put_diag = [&]() {
+#pragma unroll
+    for (int cp = 0; cp < 5; ++cp) o[cp] = diag[25 * i + 5 * c + cp];
+    o += 5;
+    diag_done = true;
+  };
+  for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
+    if (!diag_done && m.col[s] > i) put_diag();
+    const double a = off[10 * s + c], b = off[10 * s + 5 + c];
+#pragma unroll
+    for (int cp = 0; cp < 5; ++cp) o[cp] = b + (cp == c ? a : 0.0);
+    o += 5;
+  }
+  if (!diag_done) put_diag();
+}
+
+// ----------------------------------------------------------------------
 // Decoupled Picard-Gauss-Seidel sweep (Appendix A, Eq. weak_vec_implicit):
 // the compartments are solved one after the other as scalar systems whose
 // diffusion coefficient N and Allee factor a = 1 - A/N are lagged at the
@@ -2557,6 +2588,10 @@ void launch_axpby(double *y, const double *x, double a, const double *aptr, int 
 }
 void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2_partials, dim3(nb), dim3(256), 0, st, x, scale, N, partials);
+}
+void launch_csr_values(const MeshDev &m, const double *diag, const double *off, const int64_t *csr_rowptr,
+                       double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_csr_values, dim3(nblocks(5 * m.n)), dim3(256), 0, st, m, diag, off, csr_rowptr, out);
 }
 void launch_pgs_stiffness(const MeshDev &m, const double *uk, double *Kd, double *Ko, hipStream_t st) {
   hipLaunchKernelGGL(k_pgs_stiffness, dim3(nblocks(m.n)), dim3(256), 0, st, m, uk, Kd, Ko);

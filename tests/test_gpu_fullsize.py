@@ -172,3 +172,23 @@ def test_fullsize_differentiation_gradient_matches_finite_differences():
         d /= np.abs(d).max()
         fd = (J(g0 + h * d) - J(g0 - h * d)) / (2 * h)
         assert fd == pytest.approx(gg @ d, rel=1e-5), (fd, gg @ d, st)
+
+
+def test_fullsize_thirty_steps_each_solve_the_oracle_residual(big):
+    """The workload's 30 daily steps (FP64 factors, the benchmark's
+    launch configuration): after every step the oracle residual of the GPU
+    state, with the previous GPU state as u^n, is below the tolerance;
+    population is conserved throughout."""
+    cfg, prob, geo = big
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, coarse=(cfg.coarse_parents, cfg.coarse_n))
+    u = torch.tensor(cfg.u0, device="cuda")
+    prev = cfg.u0.copy()
+    P0 = fem.total_population(cfg.u0, geo)
+    for k in range(cfg.steps):
+        st = sk.step(prob, pc, u, cfg.dt, tol=cfg.newton_tol, pc_reuse=100)
+        ug = u.cpu().numpy()
+        Fo = fem.residual(ug, prev, cfg.dt, geo, cfg.params)
+        scale = np.linalg.norm(geo.mass[:, None] * prev)
+        assert np.linalg.norm(Fo) <= 1.01 * cfg.newton_tol * scale, (k, st)
+        assert abs(fem.total_population(ug, geo) - P0) <= 1e-9 * P0, k
+        prev = ug
