@@ -52,6 +52,46 @@ class Geometry:
         np.add.at(m, self.tri.ravel(), np.repeat(self.area / 3.0, 3))
         self.mass = m
 
+    def consistent_mass(self) -> sp.csr_matrix:
+        """Consistent P1 mass matrix M_ij = int phi_i phi_j, assembled from
+        the element matrices |T|/12 (1 + delta_kl)."""
+        tri = self.tri
+        Me = (np.ones((3, 3)) + np.eye(3))[None, :, :] * (self.area / 12.0)[:, None, None]
+        r = np.repeat(tri, 3, axis=1).ravel()
+        c = np.tile(tri, (1, 3)).ravel()
+        return sp.coo_matrix((Me.reshape(-1), (r, c)), shape=(self.n, self.n)).tocsr()
+
+    def boundary_edges(self):
+        """Edges that belong to exactly one triangle: (edges [nb, 2], outward
+        normals scaled by the edge lengths [nb, 2]).  The normal points away
+        from the triangle's third vertex."""
+        tri = self.tri
+        e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+        opp = np.concatenate([tri[:, 2], tri[:, 0], tri[:, 1]])
+        key = np.sort(e, axis=1)
+        _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+        keep = cnt[inv.ravel()] == 1
+        b, o = e[keep], opp[keep]
+        d = self.xy[b[:, 1]] - self.xy[b[:, 0]]
+        nl = np.stack([d[:, 1], -d[:, 0]], 1)        # |nl| = edge length
+        away = ((self.xy[b[:, 0]] - self.xy[o]) * nl).sum(1) < 0
+        nl[away] *= -1.0
+        return b, nl
+
+    def boundary_load(self, q: np.ndarray) -> np.ndarray:
+        """Boundary term of Eq. weakform, int_{dOmega} (q . n) phi_i ds, for a
+        nodal flux vector field q [n, 5, 2] (q = nu(u) grad u for the
+        compartments), P1 along each boundary edge and integrated exactly:
+        (2 q_i + q_j) . n L / 6 for node i of edge (i, j)."""
+        b, nl = self.boundary_edges()
+        i, j = b[:, 0], b[:, 1]
+        qi = np.einsum("ecd,ed->ec", q[i], nl)
+        qj = np.einsum("ecd,ed->ec", q[j], nl)
+        out = np.zeros((self.n, q.shape[1]))
+        np.add.at(out, i, (2.0 * qi + qj) / 6.0)
+        np.add.at(out, j, (2.0 * qj + qi) / 6.0)
+        return out
+
 
 def params_vec(p) -> dict:
     return dict(sigma=p.sigma, gE=p.gamma_E, gR=p.gamma_R, gD=p.gamma_D,
@@ -121,22 +161,34 @@ def diffusion(u: np.ndarray, geo: Geometry, nu) -> np.ndarray:
     return out
 
 
-def residual(u, u_prev, dt, geo: Geometry, p, g=None, src=None):
+def residual(u, u_prev, dt, geo: Geometry, p, g=None, src=None, mass="lumped", neumann=None):
     """Backward-Euler residual of the weak form (Eqs. timediscrete, weakform):
 
     F_{c,i} = m_i (u_{c,i} - u^n_{c,i}) + dt * diffusion_{c,i}(u)
               - dt * m_i * R_c(u_i) - dt * m_i * src_{c,i}
+              - dt * int_{dOmega} gN_c phi_i ds
 
     ``src`` is an optional nodal forcing (used only by manufactured
-    solutions)."""
+    solutions).  mass = "consistent" replaces the lumped mass of the time
+    derivative term by the consistent one, sum_j M_ij (u_j - u^n_j) (the
+    reaction keeps nodal quadrature).  ``neumann`` [n, 5, 2]: nodal values
+    of the flux vector nu(u) grad u whose normal component is Eq.
+    weakform's boundary term (only boundary nodes matter; None:
+    homogeneous Neumann)."""
     m = geo.mass[:, None]
-    F = m * (u - u_prev) + dt * diffusion(u, geo, p.nu) - dt * m * reaction(u, p, g)
+    if mass == "consistent":
+        Mt = geo.consistent_mass() @ (u - u_prev)
+    else:
+        Mt = m * (u - u_prev)
+    F = Mt + dt * diffusion(u, geo, p.nu) - dt * m * reaction(u, p, g)
     if src is not None:
         F -= dt * m * src
+    if neumann is not None:
+        F -= dt * geo.boundary_load(neumann)
     return F
 
 
-def jacobian(u, dt, geo: Geometry, p, g=None, mass_coef: float = 1.0):
+def jacobian(u, dt, geo: Geometry, p, g=None, mass_coef: float = 1.0, mass="lumped"):
     """Exact Jacobian dF/du of ``residual`` as a scipy CSR matrix of size
     5n x 5n (unknown 5*node + c).
 
@@ -174,17 +226,38 @@ def jacobian(u, dt, geo: Geometry, p, g=None, mass_coef: float = 1.0):
     for c in range(NC):
         for cp in range(NC):
             v = -dt * m * JR[:, c, cp]
-            if c == cp:
+            if c == cp and mass != "consistent":
                 v = v + mass_coef * m
             rows.append(5 * node + c)
             cols.append(5 * node + cp)
             vals.append(v)
+    if mass == "consistent":
+        M = geo.consistent_mass().tocoo()
+        for c in range(NC):
+            rows.append(5 * M.row + c)
+            cols.append(5 * M.col + c)
+            vals.append(mass_coef * M.data)
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
     vals = np.concatenate(vals)
     J = sp.coo_matrix((vals, (rows, cols)), shape=(NC * n, NC * n)).tocsr()
     J.sum_duplicates()
     return J
+
+
+def beta_time_factor(t, a, b, k, tc):
+    """Time factor of the transmission rate (Eq. beta_ie): a - b / (1 +
+    exp(k (tc - t))); the paper's is a = 0.101, b = 0.05, k = 1, tc = 130
+    days (the post-holiday lockdown)."""
+    return a - b / (1.0 + np.exp(k * (tc - t)))
+
+
+def beta_regional(x, beta_c, beta_e, beta_w, x_e, x_w, k_e=5.0, k_w=10.0):
+    """Regional transmission profile along the first coordinate (Eq.
+    beta_x): central value, with logistic steps to the eastern value past
+    x_e and to the western value before x_w."""
+    return (beta_c + (beta_e - beta_c) / (1.0 + np.exp(-k_e * (x - x_e)))
+            + (beta_w - beta_c) / (1.0 + np.exp(k_w * (x - x_w))))
 
 
 def node_graph(geo: Geometry) -> sp.csr_matrix:

@@ -37,16 +37,18 @@ def direct_solve(J, b):
 
 
 def newton_step(u_prev, dt, geo, p, g=None, src=None, tol=1e-10, max_it=20,
-                linsolve=None):
+                linsolve=None, mass="lumped", neumann=None):
     """One implicit step by Newton's method.  Returns (u_next, info) where
-    info holds the Newton count, the scaled residual history and epsilon."""
+    info holds the Newton count, the scaled residual history and epsilon.
+    ``mass`` and ``neumann`` select the discretisation variant (see
+    fem.residual); the stopping scale stays ||M_L u^n||."""
     linsolve = direct_solve if linsolve is None else linsolve
     u = np.array(u_prev, dtype=np.float64, copy=True)
     scale = np.linalg.norm(geo.mass[:, None] * u_prev)
     unorm = np.linalg.norm(u_prev)
     hist, eps_hist, lin_info = [], [], []
     for k in range(max_it + 1):
-        F = fem.residual(u, u_prev, dt, geo, p, g, src)
+        F = fem.residual(u, u_prev, dt, geo, p, g, src, mass=mass, neumann=neumann)
         fn = np.linalg.norm(F)
         hist.append(fn / scale)
         if not np.isfinite(fn):
@@ -56,7 +58,7 @@ def newton_step(u_prev, dt, geo, p, g=None, src=None, tol=1e-10, max_it=20,
                            lin=lin_info)
         if k == max_it:
             break
-        J = fem.jacobian(u, dt, geo, p, g)
+        J = fem.jacobian(u, dt, geo, p, g, mass=mass)
         out = linsolve(J, -F.ravel())
         if isinstance(out, tuple):
             delta, li = out

@@ -265,3 +265,109 @@ def test_planted_sign_error_is_caught_by_conservation(monkeypatch):
                                linsolve=lambda J, b: np.linalg.lstsq(J.toarray(), b, rcond=None)[0])
     P0 = fem.total_population(u0, geo)
     assert abs(fem.total_population(u1, geo) - P0) > 1e-6 * P0
+
+
+# ---------------------------------------------------------------------------
+# Discretisation and model variants: consistent mass, Neumann flux data,
+# the transmission rate's time and space profiles (Section 4.2).
+# ---------------------------------------------------------------------------
+
+def test_consistent_mass_closed_form_on_the_square_mesh():
+    """Right-triangle mesh of spacing h: an interior row of the consistent
+    mass matrix is h^2/2 on the diagonal and h^2/12 for each of its six
+    neighbours; every row sums to the lumped mass; M is symmetric."""
+    nx = 8
+    xy, tri, geo = _geo(nx)
+    h = 1.0 / nx
+    M = geo.consistent_mass().tocsr()
+    assert abs(M - M.T).max() == 0.0
+    assert np.allclose(np.asarray(M.sum(1)).ravel(), geo.mass, rtol=1e-14)
+    k = 4 * (nx + 1) + 4   # an interior node
+    row = M.getrow(k).toarray().ravel()
+    assert row[k] == pytest.approx(h * h / 2, rel=1e-13)
+    nb = np.nonzero(row)[0]
+    assert len(nb) == 7
+    for j in nb[nb != k]:
+        assert row[j] == pytest.approx(h * h / 12, rel=1e-13)
+
+
+def test_boundary_flux_integral_closed_forms():
+    """The boundary term of nodal flux fields integrates exactly for linear
+    fields (divergence theorem on the unit square): a constant flux gives
+    zero net outflow, q = (x, y) gives 2 (= div q times the area), and
+    q = (x, 0) gives 1."""
+    xy, tri, geo = _geo(6)
+    q = np.zeros((geo.n, 5, 2))
+    q[:, 0, :] = [0.3, -1.2]
+    q[:, 1, 0], q[:, 1, 1] = xy[:, 0], xy[:, 1]
+    q[:, 2, 0] = xy[:, 0]
+    b = geo.boundary_load(q).sum(0)
+    assert abs(b[0]) <= 1e-14 and b[1] == pytest.approx(2.0, rel=1e-14) and b[2] == pytest.approx(1.0, rel=1e-14)
+    _, nl = geo.boundary_edges()
+    assert np.linalg.norm(nl, axis=1).sum() == pytest.approx(4.0, rel=1e-14)
+
+
+def _mms_params():
+    return si.Params(sigma=1 / 7, gamma_E=1 / 6, gamma_R=1 / 24, gamma_D=1 / 160,
+                     A=100.0, beta_I=3.78e-4, beta_E=3.78e-4,
+                     nu=(3.94e-4, 3.94e-4, 1e-6, 3.94e-4, 0.0))
+
+
+@pytest.mark.parametrize("mass", ["lumped", "consistent"])
+def test_mms_with_neumann_flux_second_order(mass):
+    """The paper's 2D manufactured profile with its (time-dependent)
+    Neumann data: observed L2 order in h within the paper's printed range
+    (+-0.1), with lumped and with consistent mass."""
+    gold = _golden_orders()["spatial"]
+    p = _mms_params()
+    errs = [mms.neumann_spatial_error(nx, p, mass=mass) for nx in (8, 16, 32)]
+    orders = [mms.observed_order(errs[k], errs[k + 1], 2) for k in range(2)]
+    for o in orders:
+        assert min(gold) - 0.1 <= o <= max(gold) + 0.1, (orders, errs)
+
+
+def test_planted_missing_flux_is_caught_by_the_mms_order():
+    """Dropping the boundary flux (the homogeneous-Neumann mistake) leaves
+    an error that does not decrease at second order."""
+    p = _mms_params()
+    errs = [mms.neumann_spatial_error(nx, p, with_flux=False) for nx in (8, 16, 32)]
+    orders = [mms.observed_order(errs[k], errs[k + 1], 2) for k in range(2)]
+    assert max(orders) < 1.5, (orders, errs)
+
+
+def test_consistent_mass_jacobian_and_conservation():
+    """Consistent mass: the Jacobian agrees with central differences, and
+    the total population sum_i m_i N_i is still conserved (the columns of M
+    sum to the lumped masses) with alpha = mu = 0 and no flux."""
+    xy, tri, geo = _geo(4)
+    p = si.Params(**{**si.params_square().__dict__, "nu": (0.02, 0.01, 0.005, 0.02, 0.003)})
+    u = _rand_state(geo.n, 5)
+    J = fem.jacobian(u, 0.3, geo, p, mass="consistent").toarray()
+    n5 = 5 * geo.n
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        d = rng.standard_normal(n5).reshape(-1, 5)
+        h = 1e-6
+        fd = (fem.residual(u + h * d, u, 0.3, geo, p, mass="consistent")
+              - fem.residual(u - h * d, u, 0.3, geo, p, mass="consistent")).ravel() / (2 * h)
+        assert np.abs(J @ d.ravel() - fd).max() <= 1e-8 * np.abs(fd).max()
+    u0 = si.gaussian_bump_state(xy, 2, peak=0.05, width=0.2)
+    P0 = fem.total_population(u0, geo)
+    u1, _ = newton.newton_step(u0, 0.3, geo, p, tol=1e-13, mass="consistent")
+    assert abs(fem.total_population(u1, geo) - P0) <= 1e-12 * P0
+    assert np.abs(u1 - newton.newton_step(u0, 0.3, geo, p, tol=1e-13)[0]).max() > 1e-8
+
+
+def test_transmission_profiles_match_the_printed_formulas():
+    """Eq. beta_ie: 0.101 before the lockdown, 0.076 at day 130 (half the
+    drop), 0.051 long after; Eq. beta_x: the central value mid-domain and
+    the regional values far east and far west."""
+    f = lambda t: fem.beta_time_factor(t, 0.101, 0.05, 1.0, 130.0)  # noqa: E731
+    assert f(0.0) == pytest.approx(0.101, abs=1e-12)
+    assert f(130.0) == pytest.approx(0.076, rel=1e-14)
+    assert f(400.0) == pytest.approx(0.051, abs=1e-12)
+    b = lambda x: fem.beta_regional(x, 1.0, 2.0, 0.5, 3.0, -3.0)  # noqa: E731
+    assert b(0.0) == pytest.approx(1.0, abs=1e-6)
+    assert b(50.0) == pytest.approx(2.0, abs=1e-12)
+    assert b(-50.0) == pytest.approx(0.5, abs=1e-12)
+    assert b(3.0) == pytest.approx(1.5, abs=1e-6)
