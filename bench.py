@@ -237,9 +237,14 @@ def batch_bench(sk, torch, args):
                 f"{max(sum(p['gmres_its']) for p in per)} mean "
                 f"{np.mean([sum(p['gmres_its']) for p in per]):.1f}, setups {per[0]['pc_setups']}")
 
+    tune = None
     for w in range(args.warmup):
         per = b.step(u, bc.dt, **kw)
         log(f"[bench] batch warmup step {w}: {summary(per)}")
+        if w == 0:
+            # the solve width chosen on the ensemble itself (its first factors)
+            tune = b.autotune(reps=3)
+            log(f"[bench] batch autotune: {tune}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     allper = []
@@ -278,7 +283,9 @@ def batch_bench(sk, torch, args):
             "gmres_its_per_instance_max": [max(sum(p["gmres_its"]) for p in per) for per in allper],
             "gmres_its_per_instance_mean": [float(np.mean([sum(p["gmres_its"]) for p in per]))
                                             for per in allper],
-            "roofline": roof, "precond": info, "solve_threads": threads if t_ == 32 else 256,
+            "roofline": roof, "precond": info,
+            "solve_threads": tune["solve_threads"] if tune else (threads if t_ == 32 else 256),
+            "autotune": tune,
             "generate_s": t_gen, "create_s": t_create}
 
 
@@ -384,6 +391,22 @@ def oracle_precision_leg(sk, torch, args):
 
 
 PEAK_MFMA_TFLOPS = {0: 78.6, 1: 157.3, 2: 157.3}  # FP64, FP32 (BF16 factors are factored in FP32)
+
+
+def solve_roofline(stats, prec):
+    """The subdomain-solve kernel of a leg: algorithmic bytes per launch
+    (factors in the storage precision plus local vectors) over its HIP-event
+    time per launch."""
+    ras_ms = sum(s["t_ras_kernel_ms"] for s in stats)
+    ras_n = sum(s["n_ras_launches"] for s in stats)
+    if ras_n <= 0:
+        return None
+    nbytes = stats[0]["ras_bytes_per_launch"]
+    achieved = nbytes / (ras_ms / ras_n / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": "k_band_solve (subdomain solves of one RAS apply, "
+                                      + {0: "FP64", 1: "FP32", 2: "BF16"}[prec] + " factors)",
+            "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "avg_launch_ms": ras_ms / ras_n, "launches": ras_n, "bytes_per_launch": nbytes, "traffic": None}
 
 
 def factor_roofline(perf, prec):
@@ -553,6 +576,8 @@ def main():
                 "per_field_vs_fp64": {"step": r2["steps_done"],
                                       "errors": per_field_errors(r2["u"].cpu().numpy(), res["u"].cpu().numpy())},
                 "setup_lu_ms": (r2["perf"]["t_lu_ms"] / r2["perf"]["setups"]) if r2["perf"]["setups"] else None,
+                "roofline": solve_roofline(r2["stats"], p),
+                "factor_roofline": factor_roofline(r2["perf"], p),
                 "tile": r2["tile"], "solve_threads": r2["solve_threads"],
                 "phase_ms_per_step": {k: sum(st[k] for st in r2["stats"]) / max(1, len(r2["stats"])) for k in
                                       ("t_residual_ms", "t_jacobian_ms", "t_setup_ms", "t_gmres_ms")},

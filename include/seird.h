@@ -9,9 +9,10 @@
  *   d_t u - div(nu(u) grad u) = B(u) u,   u = (s, e, i, r, d),
  *   nu(u) = N diag(nu_S, nu_E, nu_I, nu_R, nu_D)      (Eq. vec_component1)
  *   B(u) the reaction matrix of Eq. vec_component2,
- * discretised by backward Euler (Eq. timediscrete) and the weak form with
- * homogeneous Neumann data (Eq. weakform) on P1 triangles, lumped nodal mass
- * for the mass and reaction terms, exact P1 diffusion with the
+ * discretised by backward Euler (Eq. timediscrete) and the weak form
+ * (Eq. weakform) on P1 triangles, homogeneous Neumann data and lumped nodal
+ * mass by default (see seird_set_mass and seird_set_boundary_flux for the
+ * variants), nodal quadrature of the reaction, exact P1 diffusion with the
  * element-mean density.  The discrete residual of one step is
  *
  *   F_{c,i}(u) = m_i (u_{c,i} - u^n_{c,i})
@@ -233,6 +234,10 @@ seird_status seird_create_in_workspace(seird_mesh m, const seird_params *params,
                                        seird_precond *pc);
 
 const char *seird_last_error(void);
+/* Device allocations (hipMalloc calls) the library has made in this
+ * process, and their bytes: lets a caller check that calls on workspace
+ * handles allocate nothing. */
+seird_status seird_device_allocations(int64_t *count, int64_t *bytes);
 /* Version string of the library (build identifier). */
 const char *seird_version(void);
 
@@ -247,6 +252,47 @@ seird_status seird_problem_create(int64_t n_nodes, const double *xy,
                                   seird_problem *out);
 void seird_problem_destroy(seird_problem p);
 seird_status seird_set_params(seird_problem p, const seird_params *params);
+/* ------------------------------------------------------------------
+ * Model and discretisation variants (Section 4.2, Appendix B.3).
+ * ------------------------------------------------------------------
+ * Time profile of the transmission rate (Eq. beta_ie): with a schedule,
+ * beta_I and beta_E are multiplied by a - b / (1 + exp(k (tc - t))) at the
+ * time t the coefficients refer to: the end of a step (t_n + dt) in
+ * seird_step, seird_pgs_step and the forward/adjoint sweeps, the problem's
+ * time in seird_residual and seird_jacobian.  NULL removes it.  The paper's
+ * profile is a = 0.101, b = 0.05, k = 1 per day, tc = 130 days.  Not for a
+ * batch's problem (SEIRD_ERR_ARG). */
+typedef struct {
+  double a, b, k, tc;
+} seird_beta_schedule;
+seird_status seird_set_beta_schedule(seird_problem p, const seird_beta_schedule *s);
+/* Model time of the current state: set by the caller, advanced by dt by
+ * every successful step (and by n_steps dt by a forward record). */
+seird_status seird_set_time(seird_problem p, double t);
+seird_status seird_get_time(seird_problem p, double *t);
+/* Regional transmission profile along the first coordinate (Eq. beta_x):
+ * sets the transmission field to
+ *   g(x) = beta_c + (beta_e - beta_c) / (1 + exp(-k_e (x - x_e)))
+ *               + (beta_w - beta_c) / (1 + exp(k_w (x - x_w)))
+ * at every node (the paper's k_e = 5, k_w = 10).  Synchronising. */
+seird_status seird_set_beta_regional(seird_problem p, double beta_c, double beta_e,
+                                     double beta_w, double x_e, double x_w,
+                                     double k_e, double k_w, void *stream);
+/* Mass of the time-derivative term: 0 lumped (default), 1 consistent
+ * (M_ij = int phi_i phi_j, so the term is sum_j M_ij (u - u^n)_j; the
+ * reaction keeps nodal quadrature and the Newton stopping scale stays
+ * ||M_L u^n||).  The Jacobian, preconditioners, Picard-Gauss-Seidel sweeps
+ * and the adjoint follow. */
+seird_status seird_set_mass(seird_problem p, int32_t consistent);
+/* Non-homogeneous Neumann data: the flux vector field q = nu(u) grad u of
+ * every compartment at every node, device float64 [n_nodes][5][2]
+ * (copied; only boundary nodes matter).  The residual then subtracts
+ * dt int_{boundary} (q . n) phi_i ds, with q P1 along each boundary edge
+ * and n the edge's outward normal (Eq. weakform's boundary term, taken as
+ * data that does not depend on the state).  NULL restores homogeneous
+ * Neumann.  Async. */
+seird_status seird_set_boundary_flux(seird_problem p, const double *q_dev, void *stream);
+
 /* Per-node transmission multiplier g [n_nodes] (device float64, copied);
  * NULL restores g = 1. */
 seird_status seird_set_beta_field(seird_problem p, const double *g_dev,
@@ -398,7 +444,17 @@ typedef struct {
   int32_t best_tile, best_solve_threads;
   int32_t n_candidates;
   seird_tune_candidate cand[SEIRD_TUNE_MAX];
+  int32_t from_cache;  /* 1: the choice came from the autotuner cache (no candidate timed) */
 } seird_tune_report;
+/* The autotuner cache: every choice of seird_autotune_schwarz and
+ * seird_batch_autotune is kept per (device architecture, kernel, shape
+ * bucket: nodes per subdomain in powers of two, overlap, one or two levels,
+ * factor precision) for the process and, when the environment variable
+ * SEIRD_TUNE_CACHE names a file, in that file; a later call with the same
+ * key returns the kept choice without timing (from_cache = 1).  This call
+ * empties the process's cache (the file is left alone and not read
+ * again). */
+seird_status seird_tune_cache_clear(void);
 seird_status seird_autotune_schwarz(seird_problem p,
                                     const seird_schwarz_opts *opts,
                                     const int32_t *part, const double *vals,
@@ -542,6 +598,13 @@ void seird_batch_destroy(seird_batch b);
 /* node_offsets [n_inst + 1] (host): instance k owns nodes
  * [node_offsets[k], node_offsets[k+1]) of the batch state. */
 seird_status seird_batch_info(seird_batch b, int64_t *node_offsets);
+/* Autotune the subdomain-solve width of the batch's preconditioner on the
+ * ensemble itself (its current factors: call after a step): times `reps`
+ * subdomain-solve launches over every instance for each width (256, 512,
+ * 1024 with tile 32), keeps the fastest (also in the autotuner cache).
+ * Synchronising. */
+seird_status seird_batch_autotune(seird_batch b, int32_t reps, seird_tune_report *report,
+                                  void *stream);
 /* The batch's preconditioner (one-level RAS over the subdomains of every
  * instance), borrowed: owned by the batch and valid until
  * seird_batch_destroy.  For seird_precond_timing / seird_precond_info. */

@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Mesh", "Problem", "Precond", "PicardGS", "Batch", "workspace_bytes", "create_in_workspace", "SeirdError", "autotune", "gmres", "gmres_noalloc", "step",
+__all__ = ["Mesh", "Problem", "Precond", "PicardGS", "Batch", "workspace_bytes", "create_in_workspace", "SeirdError", "autotune", "tune_cache_clear", "gmres", "gmres_noalloc", "step",
            "forward_record", "adjoint", "SEIRDRun", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -124,7 +124,8 @@ TUNE_MAX = 8
 
 class _TuneReport(ctypes.Structure):
     _fields_ = [("best_tile", ctypes.c_int32), ("best_solve_threads", ctypes.c_int32),
-                ("n_candidates", ctypes.c_int32), ("cand", _TuneCand * TUNE_MAX)]
+                ("n_candidates", ctypes.c_int32), ("cand", _TuneCand * TUNE_MAX),
+                ("from_cache", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -133,6 +134,7 @@ _I32P = ctypes.POINTER(ctypes.c_int32)
 _SIGS = {
     "seird_last_error": ([], ctypes.c_char_p),
     "seird_version": ([], ctypes.c_char_p),
+    "seird_device_allocations": ([_I64P, _I64P], ctypes.c_int),
     "seird_problem_create": ([ctypes.c_int64, _P, ctypes.c_int64, _P,
                               ctypes.POINTER(_Params), ctypes.POINTER(_P)], ctypes.c_int),
     "seird_problem_destroy": ([_P], None),
@@ -149,6 +151,12 @@ _SIGS = {
     "seird_csr_values": ([_P, _P, _P, _P], ctypes.c_int),
     "seird_set_params": ([_P, ctypes.POINTER(_Params)], ctypes.c_int),
     "seird_set_beta_field": ([_P, _P, _P], ctypes.c_int),
+    "seird_set_beta_schedule": ([_P, _P], ctypes.c_int),
+    "seird_set_time": ([_P, ctypes.c_double], ctypes.c_int),
+    "seird_get_time": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "seird_set_beta_regional": ([_P] + [ctypes.c_double] * 7 + [_P], ctypes.c_int),
+    "seird_set_mass": ([_P, ctypes.c_int32], ctypes.c_int),
+    "seird_set_boundary_flux": ([_P, _P, _P], ctypes.c_int),
     "seird_problem_info": ([_P, _I64P, _I64P], ctypes.c_int),
     "seird_pattern": ([_P, _P, _P], ctypes.c_int),
     "seird_lumped_mass": ([_P, _P, _P], ctypes.c_int),
@@ -168,6 +176,8 @@ _SIGS = {
     "seird_precond_set_coarse_block": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_autotune_schwarz": ([_P, ctypes.POINTER(_Schwarz), _P, _P, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.POINTER(_TuneReport), _P], ctypes.c_int),
+    "seird_tune_cache_clear": ([], ctypes.c_int),
+    "seird_batch_autotune": ([_P, ctypes.c_int32, ctypes.POINTER(_TuneReport), _P], ctypes.c_int),
     "seird_analyze_schwarz": ([ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.POINTER(_Schwarz), _P,
                                ctypes.POINTER(_SInfo), _P, _P], ctypes.c_int),
     "seird_precond_apply": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
@@ -276,6 +286,13 @@ class Mesh:
             self.h = None
 
 
+def device_allocations():
+    """(count, bytes) of the device allocations the library has made."""
+    c, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().seird_device_allocations(ctypes.byref(c), ctypes.byref(b)))
+    return c.value, b.value
+
+
 def _ws_opts(restart_max=30, tape_states=0, n_regions_max=0, csr_pattern=False):
     return _WsOpts(int(restart_max), int(tape_states), int(n_regions_max), int(bool(csr_pattern)))
 
@@ -379,6 +396,37 @@ class Problem:
 
     def set_beta_field(self, g):
         _check(lib().seird_set_beta_field(self.h, _dptr(g, self.n, "g"), _stream()))
+
+    def set_beta_schedule(self, a=None, b=0.0, k=1.0, tc=0.0):
+        """Time profile of the transmission rate (Eq. beta_ie): beta times
+        a - b / (1 + exp(k (tc - t))); a=None removes it."""
+        if a is None:
+            _check(lib().seird_set_beta_schedule(self.h, None))
+            return
+        arr = (ctypes.c_double * 4)(float(a), float(b), float(k), float(tc))
+        _check(lib().seird_set_beta_schedule(self.h, ctypes.cast(arr, ctypes.c_void_p)))
+
+    def set_time(self, t):
+        _check(lib().seird_set_time(self.h, float(t)))
+
+    def get_time(self):
+        t = ctypes.c_double()
+        _check(lib().seird_get_time(self.h, ctypes.byref(t)))
+        return t.value
+
+    def set_beta_regional(self, beta_c, beta_e, beta_w, x_e, x_w, k_e=5.0, k_w=10.0):
+        """Regional transmission field along x (Eq. beta_x)."""
+        _check(lib().seird_set_beta_regional(self.h, float(beta_c), float(beta_e), float(beta_w), float(x_e),
+                                             float(x_w), float(k_e), float(k_w), _stream()))
+
+    def set_mass(self, consistent):
+        """Mass of the time-derivative term: lumped (False) or consistent."""
+        _check(lib().seird_set_mass(self.h, int(bool(consistent))))
+
+    def set_boundary_flux(self, q):
+        """Neumann data: flux vectors [n, 5, 2] (float64 CUDA); None: zero."""
+        _check(lib().seird_set_boundary_flux(self.h, _dptr(q, 10 * self.n, "q") if q is not None else None,
+                                             _stream()))
 
     def pattern(self):
         rp = np.zeros(self.n + 1, dtype=np.int64)
@@ -586,9 +634,19 @@ def autotune(problem: Problem, part, n_sub, overlap, vals, factor_prec=0, coarse
                                         _dptr(vals, problem.nvals, "vals"), int(applies_per_setup),
                                         int(reps), ctypes.byref(rep), _stream()))
     del keep
+    return _tune_dict(rep)
+
+
+def _tune_dict(rep):
     cands = [dict(tile=c.tile, solve_threads=c.solve_threads, status=c.status, setup_ms=c.setup_ms,
                   apply_ms=c.apply_ms, score_ms=c.score_ms) for c in rep.cand[:rep.n_candidates]]
-    return dict(tile=rep.best_tile, solve_threads=rep.best_solve_threads, candidates=cands)
+    return dict(tile=rep.best_tile, solve_threads=rep.best_solve_threads, candidates=cands,
+                from_cache=bool(rep.from_cache))
+
+
+def tune_cache_clear():
+    """Empty the autotuner's in-process cache."""
+    _check(lib().seird_tune_cache_clear())
 
 
 def gmres(problem: Problem, pc, vals, b, transpose=False, x=None, **kw):
@@ -876,6 +934,13 @@ class Batch:
         if getattr(self, "h", None) and _lib is not None:
             _lib.seird_batch_destroy(self.h)
             self.h = None
+
+    def autotune(self, reps=3):
+        """Choose the subdomain-solve width on the ensemble itself (after a
+        step, so that the factors exist); see seird_batch_autotune."""
+        rep = _TuneReport()
+        _check(lib().seird_batch_autotune(self.h, int(reps), ctypes.byref(rep), _stream()))
+        return _tune_dict(rep)
 
     def step(self, u, dt, tol=1e-10, max_it=20, pc_reuse=0, **kw):
         """One implicit step of every instance, in place on u [n_total, 5].

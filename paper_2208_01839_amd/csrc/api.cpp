@@ -1,9 +1,12 @@
 // C ABI of libseird and the host orchestration: Newton time step, restarted
 // right-preconditioned GMRES, one-level and two-grid Schwarz apply.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
+#include <cstdio>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -59,10 +62,13 @@ void *Arena::take(size_t bytes) {
   used += b;
   return p;
 }
+static std::atomic<int64_t> g_dev_allocs{0}, g_dev_alloc_bytes{0};
 void *dev_alloc_bytes(size_t bytes) {
   if (Arena *a = active_arena()) return a->take(bytes);
   void *p = nullptr;
   HIPCHECK(hipMalloc(&p, bytes));
+  g_dev_allocs++;
+  g_dev_alloc_bytes += (int64_t)bytes;
   return p;
 }
 void dev_free(void *p) {
@@ -110,6 +116,26 @@ struct seird_problem_s {
   double *gfield = nullptr;
   int64_t N = 0;      // unknowns
   int nb = 1;         // reduction grid
+  // transmission schedule (Eq. beta_ie): beta_I and beta_E are multiplied
+  // by a - b / (1 + exp(k (tc - t))) at the time the coefficients refer to
+  bool sched = false;
+  double sa = 0.0, sb = 0.0, sk = 0.0, stc = 0.0;
+  double time = 0.0;  // model time of the current state
+  ParamsDev params_at(double t) const {
+    ParamsDev q = P;
+    if (sched) {
+      const double f = sa - sb / (1.0 + std::exp(sk * (stc - t)));
+      q.bI *= f;
+      q.bE *= f;
+    }
+    return q;
+  }
+  // discretisation variants: consistent-mass values and the stored
+  // boundary flux field (always allocated; md points at them when enabled)
+  double *d_cmass_d = nullptr, *d_cmass_o = nullptr, *d_qflux = nullptr;
+  int64_t *d_bnd_ptr = nullptr;
+  int32_t *d_bnd_j = nullptr;
+  double *d_bnd_nl = nullptr;
   double *partials = nullptr;
   double *hdev = nullptr;   // small device vector (Arnoldi coefficients, norms)
   double *ydev = nullptr;
@@ -121,6 +147,7 @@ struct seird_problem_s {
   int kcap = 0;
   double *w1 = nullptr;  // scratch vector
   size_t lds_limit = 65536;
+  int n_cu = 0;  // compute units of the device
   // segments of the unknown vector (one per instance of a batch; one for a
   // single problem), per-segment masks and scalars
   static constexpr int HLD = KRYLOV_MAX + 8;
@@ -172,7 +199,7 @@ struct seird_problem_s {
   // adjoint record (checkpoints, last segment, regions)
   struct Tape {
     int n_steps = 0, every = 0, n_regions = 0;
-    double dt = 0.0;
+    double dt = 0.0, t0 = 0.0;  // step size, model time of the first state
     seird_newton_opts nopts{};
     seird_krylov_opts kopts{};
     std::vector<double *> ckpt, seg;
@@ -212,6 +239,8 @@ struct seird_problem_s {
     dev_free(seg.d_seg_start); dev_free(seg.d_blk_start); dev_free(seg.d_block_seg);
     dev_free(d_mask); dev_free(d_mask2); dev_free(d_svec); dev_free(d_inst); dev_free(d_Pinst);
     dev_free(csr_rowptr); dev_free(csr_col);
+    dev_free(d_cmass_d); dev_free(d_cmass_o); dev_free(d_qflux); dev_free(d_bnd_ptr); dev_free(d_bnd_j);
+    dev_free(d_bnd_nl);
     tape.release();
     if (stage) {
       (void)hipStreamSynchronize(stage_st);
@@ -361,6 +390,9 @@ struct seird_precond_s {
   int32_t *g2l_idx = nullptr;
   double *yloc = nullptr;
   int32_t *sub_seg = nullptr;  // instance of every subdomain (batches)
+  std::vector<int32_t> sub_seg_host;
+  int32_t *order_act = nullptr;  // batches: the active instances' subdomains, in LPT order
+  std::vector<int32_t> order_act_host;
   int solve_threads = 256;     // workgroup size of the subdomain solves
   int max_nt = 0, max_bu = 0;
   // coarse
@@ -449,8 +481,10 @@ struct seird_precond_s {
   }
   // the same per instance of a batch (subdomains of that instance only)
   std::vector<double> seg_bytes;
-  void set_instances(const std::vector<int32_t> &sub_seg_host, int n_inst) {
+  void set_instances(const std::vector<int32_t> &sub_seg_in, int n_inst) {
+    sub_seg_host = sub_seg_in;
     sub_seg = dev_upload(sub_seg_host);
+    order_act = dev_alloc<int32_t>(ph.n_sub);
     const double fsz = ph.prec == 0 ? 8.0 : (ph.prec == 1 ? 4.0 : 2.0);
     const int T = ph.tile;
     seg_bytes.assign(n_inst, 0.0);
@@ -489,6 +523,7 @@ struct seird_precond_s {
     dev_free(Fs); dev_free(Fb); dev_free(Fc); dev_free(subs_dev); dev_free(order_dev); dev_free(ent_dev); dev_free(l2g);
     dev_free(env_row); dev_free(env_lo); dev_free(ent_ptr); dev_free(trow_ptr); dev_free(trow_sub);
     dev_free(owned); dev_free(status); dev_free(g2l_ptr); dev_free(g2l_idx); dev_free(yloc); dev_free(sub_seg);
+    dev_free(order_act);
     dev_free(coarse_dev); dev_free(gp); dev_free(gq); dev_free(gref); dev_free(cperm); dev_free(gptr); dev_free(gw);
     dev_free(z_ptr); dev_free(zt_ptr); dev_free(z_col); dev_free(zt_col); dev_free(z_val); dev_free(zt_val);
     dev_free(rc); dev_free(xc); dev_free(cscratch); dev_free(ybuf); dev_free(t1); dev_free(Xc); dev_free(Wc);
@@ -517,6 +552,20 @@ struct seird_precond_s {
     sl.subs = subs_dev;
     sl.order = order_dev;
     sl.nblocks = ph.n_sub;
+    if (sl.seg_active && seg_active_host && order_act) {
+      // a batch with finished instances: launch only the active
+      // instances' subdomains (compacted, still largest first), so that
+      // the launch's time follows its bytes
+      order_act_host.clear();
+      for (int32_t idx : ph.order)
+        if ((*seg_active_host)[sub_seg_host[idx]]) order_act_host.push_back(idx);
+      if ((int)order_act_host.size() < ph.n_sub) {
+        if (order_act_host.empty()) return;
+        prob->upload(order_act, order_act_host.data(), sizeof(int32_t) * order_act_host.size(), st);
+        sl.order = order_act;
+        sl.nblocks = (int)order_act_host.size();
+      }
+    }
     sl.l2g = l2g;
     sl.owned = owned;
     sl.erow = env_row;
@@ -739,7 +788,9 @@ static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, do
         launch_seg_maxpy_norm(seg_act, w, V, N, hdev, HLD, j + 1, partials, s);
         launch_seg_reduce(seg, partials, 1, hdev, HLD, j + 2, s);
       };
-      if (pc && o.graphs && !pc->timing)
+      // (graphs only for a single instance: a batch's launches depend on
+      // which instances are still running)
+      if (pc && o.graphs && !pc->timing && S == 1)
         pc->run_graph({P, V, Zb, vals, j, transpose, S > 1, pc->coarse_solver, pc->coarse_block, pc->solve_threads},
                       step_launches, st);
       else
@@ -873,7 +924,8 @@ static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t
 // applies to all segments together.
 static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, const double *src,
                       const seird_newton_opts *nopts, const seird_krylov_opts *kopts,
-                      std::vector<seird_step_stats> &stats, hipStream_t st) {
+                      std::vector<seird_step_stats> &stats, hipStream_t st, double t_next) {
+  const ParamsDev Pt = p ? p->params_at(t_next) : ParamsDev{};  // coefficients at the end of the step
   if (!p || !u || !nopts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
   if (nopts->max_it < 0 || nopts->max_it > SEIRD_MAX_NEWTON) fail(SEIRD_ERR_ARG, "Newton max_it out of range");
   if (nopts->pc_reuse < 0) fail(SEIRD_ERR_ARG, "pc_reuse must be >= 0");
@@ -913,7 +965,7 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
   int setups = 0;
   for (int k = 0;; ++k) {
     auto t0 = clk::now();
-    launch_residual(p->md, p->P, p->gfield, u, p->u_prev, dt, src, p->F, st);
+    launch_residual(p->md, Pt, p->gfield, u, p->u_prev, dt, src, p->F, st);
     const std::vector<double> fn = p->seg_norms(p->F, st);
     t_res += ms(t0, clk::now());
     bool any_act = false;
@@ -939,7 +991,7 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
       fail(SEIRD_ERR_NOT_CONVERGED, msg);
     }
     t0 = clk::now();
-    launch_jacobian(p->md, p->P, p->gfield, u, dt, diag, off, st);
+    launch_jacobian(p->md, Pt, p->gfield, u, dt, diag, off, st);
     HIPCHECK(hipStreamSynchronize(st));
     t_jac += ms(t0, clk::now());
     t0 = clk::now();
@@ -1063,6 +1115,13 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
 extern "C" {
 
 const char *seird_last_error(void) { return g_last_error.c_str(); }
+
+seird_status seird_device_allocations(int64_t *count, int64_t *bytes) {
+  API_BEGIN
+  if (count) *count = g_dev_allocs.load();
+  if (bytes) *bytes = g_dev_alloc_bytes.load();
+  API_END
+}
 const char *seird_version(void) { return "libseird 0.1 gfx950"; }
 
 struct seird_mesh_s {
@@ -1079,6 +1138,9 @@ static seird_problem problem_create_impl(const MeshHost &mh, const seird_params 
       int lds = 0;
       if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && lds > 0)
         P->lds_limit = (size_t)lds;
+      int cus = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && cus > 0)
+        P->n_cu = cus;
     }
     P->mh = mh;
     P->P = to_dev(params);
@@ -1095,6 +1157,15 @@ static seird_problem problem_create_impl(const MeshHost &mh, const seird_params 
     P->md.inc_sj = dev_upload(m.inc_sj);
     P->md.inc_sl = dev_upload(m.inc_sl);
     P->md.inc_K = dev_upload(m.inc_K);
+    P->d_cmass_d = dev_upload(m.cmass_d);
+    P->d_cmass_o = dev_upload(m.cmass_o);
+    P->d_bnd_ptr = dev_upload(m.bnd_ptr);
+    P->d_bnd_j = dev_upload(m.bnd_j);
+    P->d_bnd_nl = dev_upload(m.bnd_nl);
+    P->d_qflux = dev_alloc<double>((size_t)10 * m.n);
+    P->md.bnd_ptr = P->d_bnd_ptr;
+    P->md.bnd_j = P->d_bnd_j;
+    P->md.bnd_nl = P->d_bnd_nl;
     P->N = 5 * m.n;
     P->nb = reduction_blocks(P->N);
     P->setup_segments({0, m.n});
@@ -1289,6 +1360,72 @@ seird_status seird_set_beta_field(seird_problem p, const double *g_dev, void *st
   API_END
 }
 
+seird_status seird_set_beta_schedule(seird_problem p, const seird_beta_schedule *sch) {
+  API_BEGIN
+  if (!p) fail(SEIRD_ERR_ARG, "null problem");
+  if (p->md.inst) fail(SEIRD_ERR_ARG, "a batch's instances keep their own rates");
+  p->sched = sch != nullptr;
+  if (sch) {
+    p->sa = sch->a;
+    p->sb = sch->b;
+    p->sk = sch->k;
+    p->stc = sch->tc;
+  }
+  API_END
+}
+
+seird_status seird_set_time(seird_problem p, double t) {
+  API_BEGIN
+  if (!p) fail(SEIRD_ERR_ARG, "null problem");
+  p->time = t;
+  API_END
+}
+
+seird_status seird_get_time(seird_problem p, double *t) {
+  API_BEGIN
+  if (!p || !t) fail(SEIRD_ERR_ARG, "null argument");
+  *t = p->time;
+  API_END
+}
+
+seird_status seird_set_mass(seird_problem p, int32_t consistent) {
+  API_BEGIN
+  if (!p) fail(SEIRD_ERR_ARG, "null problem");
+  if (consistent != 0 && consistent != 1) fail(SEIRD_ERR_ARG, "mass must be 0 (lumped) or 1 (consistent)");
+  p->md.cmass_d = consistent ? p->d_cmass_d : nullptr;
+  p->md.cmass_o = consistent ? p->d_cmass_o : nullptr;
+  API_END
+}
+
+seird_status seird_set_boundary_flux(seird_problem p, const double *q_dev, void *stream) {
+  API_BEGIN
+  if (!p) fail(SEIRD_ERR_ARG, "null problem");
+  if (!q_dev) {
+    p->md.qflux = nullptr;
+  } else {
+    HIPCHECK(hipMemcpyAsync(p->d_qflux, q_dev, sizeof(double) * 10 * p->mh.n, hipMemcpyDeviceToDevice,
+                            (hipStream_t)stream));
+    p->md.qflux = p->d_qflux;
+  }
+  API_END
+}
+
+seird_status seird_set_beta_regional(seird_problem p, double beta_c, double beta_e, double beta_w, double x_e,
+                                     double x_w, double k_e, double k_w, void *stream) {
+  API_BEGIN
+  if (!p) fail(SEIRD_ERR_ARG, "null problem");
+  std::vector<double> g(p->mh.n);
+  for (int64_t i = 0; i < p->mh.n; ++i) {
+    const double x = p->mh.xy[2 * i];
+    g[i] = beta_c + (beta_e - beta_c) / (1.0 + std::exp(-k_e * (x - x_e))) +
+           (beta_w - beta_c) / (1.0 + std::exp(k_w * (x - x_w)));
+  }
+  if (!p->gfield) p->gfield = p->gfield_store ? p->gfield_store : dev_alloc<double>(p->mh.n);
+  HIPCHECK(hipMemcpyAsync(p->gfield, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice, (hipStream_t)stream));
+  HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+  API_END
+}
+
 seird_status seird_problem_info(seird_problem p, int64_t *n_nodes, int64_t *n_slots) {
   API_BEGIN
   if (!p) fail(SEIRD_ERR_ARG, "null problem");
@@ -1316,7 +1453,7 @@ seird_status seird_residual(seird_problem p, const double *u, const double *u_pr
                             double *F, void *stream) {
   API_BEGIN
   if (!p || !u || !u_prev || !F) fail(SEIRD_ERR_ARG, "null argument");
-  launch_residual(p->md, p->P, p->gfield, u, u_prev, dt, src, F, (hipStream_t)stream);
+  launch_residual(p->md, p->params_at(p->time), p->gfield, u, u_prev, dt, src, F, (hipStream_t)stream);
   HIPCHECK(hipGetLastError());
   API_END
 }
@@ -1331,7 +1468,7 @@ seird_status seird_jacobian_size(seird_problem p, int64_t *n_vals) {
 seird_status seird_jacobian(seird_problem p, const double *u, double dt, double *vals, void *stream) {
   API_BEGIN
   if (!p || !u || !vals) fail(SEIRD_ERR_ARG, "null argument");
-  launch_jacobian(p->md, p->P, p->gfield, u, dt, vals, vals + 25 * p->mh.n, (hipStream_t)stream);
+  launch_jacobian(p->md, p->params_at(p->time), p->gfield, u, dt, vals, vals + 25 * p->mh.n, (hipStream_t)stream);
   HIPCHECK(hipGetLastError());
   API_END
 }
@@ -1430,7 +1567,7 @@ static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_op
     pc->owned = dev_upload(ph.owned);
     pc->env_row = dev_upload(ph.env_row);
     pc->env_lo = dev_upload(ph.env_lo);
-    pc->status = dev_alloc<int>(1);
+    pc->status = dev_alloc<int>(2);  // status flag, factorisation queue counter
     // transposed-apply gather lists: global unknown -> local copies
     {
       const int64_t N = pc->nvec;
@@ -1478,10 +1615,11 @@ static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_op
         HIPCHECK(hipStreamCreateWithFlags(&pc->st_coarse, hipStreamNonBlocking));
         HIPCHECK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
         HIPCHECK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
-        // first work on the stream now, so that the runtime's own resources
-        // for it are set up at creation and not during a later setup
-        HIPCHECK(hipMemsetAsync(pc->status, 0, sizeof(int), pc->st_coarse));
-        HIPCHECK(hipStreamSynchronize(pc->st_coarse));
+        // first kernel and event on the stream now, so that the runtime's
+        // own resources for them are set up at creation, not in a setup
+        launch_fill_int(pc->status, 0, 2, pc->st_coarse);
+        HIPCHECK(hipEventRecord(pc->ev_join, pc->st_coarse));
+        HIPCHECK(hipEventSynchronize(pc->ev_join));
       }
     }
   } catch (...) {
@@ -1587,6 +1725,7 @@ seird_status seird_precond_perf(seird_precond pc, seird_precond_perf_report *r, 
 }
 
 static void precond_setup_raw(seird_precond pc, const double *diag, const double *off, hipStream_t st);
+static int P_ncu(seird_precond pc) { return pc->prob->n_cu; }
 
 static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t st) {
   seird_problem P = pc->prob;
@@ -1620,6 +1759,8 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
   fl.max_node_blocks = ph.max_node_blocks;
   fl.max_bu = pc->max_bu;
   fl.status = pc->status;
+  fl.queue = pc->status + 1;  // the int after the status flag
+  fl.n_cu = P_ncu(pc);
   if (ph.two_level) {
     fl.coarse = true;
     fl.cs = ph.coarse;
@@ -1687,6 +1828,73 @@ seird_status seird_precond_setup(seird_precond pc, const double *vals, void *str
   API_END
 }
 
+// ------------------------------------------------------------------------
+// Autotuner cache: the chosen (tile, solve width) per (device architecture,
+// kernel, shape bucket, factor precision), kept for the process and, when
+// SEIRD_TUNE_CACHE names a file, in that file (one "key tile threads" line
+// per entry, read on first use, appended on every new choice).
+// ------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<int, int>> g_tune_cache;
+static bool g_tune_loaded = false;
+
+static std::string tune_cache_file() {
+  const char *e = std::getenv("SEIRD_TUNE_CACHE");
+  return e ? std::string(e) : std::string();
+}
+static void tune_cache_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const std::string f = tune_cache_file();
+  if (f.empty()) return;
+  if (FILE *fp = std::fopen(f.c_str(), "r")) {
+    char key[512];
+    int tile = 0, th = 0;
+    while (std::fscanf(fp, "%511s %d %d", key, &tile, &th) == 3) g_tune_cache[key] = {tile, th};
+    std::fclose(fp);
+  }
+}
+static bool tune_cache_get(const std::string &key, int &tile, int &th) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_cache_load_locked();
+  auto it = g_tune_cache.find(key);
+  if (it == g_tune_cache.end()) return false;
+  tile = it->second.first;
+  th = it->second.second;
+  return true;
+}
+static void tune_cache_put(const std::string &key, int tile, int th) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_cache_load_locked();
+  g_tune_cache[key] = {tile, th};
+  const std::string f = tune_cache_file();
+  if (f.empty()) return;
+  if (FILE *fp = std::fopen(f.c_str(), "a")) {
+    std::fprintf(fp, "%s %d %d\n", key.c_str(), tile, th);
+    std::fclose(fp);
+  }
+}
+// shape bucket: nodes per subdomain (log2), overlap, levels, precision
+static std::string tune_key(const char *kernel, int device, int64_t n_nodes, int n_sub, int overlap, bool two_level,
+                            int prec) {
+  std::string arch = "unknown";
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+  for (char &c : arch)
+    if (c == ' ' || c == ':') c = '_';
+  const int nb = (int)std::lround(std::log2(std::max<double>(1.0, (double)n_nodes / std::max(1, n_sub))));
+  return arch + "|" + kernel + "|nodes_per_sub_2^" + std::to_string(nb) + "|overlap" + std::to_string(overlap) +
+         (two_level ? "|two_level" : "|one_level") + "|prec" + std::to_string(prec);
+}
+
+seird_status seird_tune_cache_clear(void) {
+  API_BEGIN
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache.clear();
+  g_tune_loaded = true;  // a cleared cache does not reload its file
+  API_END
+}
+
 seird_status seird_autotune_schwarz(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
                                     const double *vals, int32_t applies_per_setup, int32_t reps,
                                     seird_tune_report *report, void *stream) {
@@ -1696,6 +1904,17 @@ seird_status seird_autotune_schwarz(seird_problem p, const seird_schwarz_opts *o
   hipStream_t st = (hipStream_t)stream;
   using clk = std::chrono::steady_clock;
   *report = seird_tune_report{};
+  const std::string key =
+      tune_key("schwarz", p->device, p->mh.n, opts->n_sub, opts->overlap, opts->n_ref > 0, opts->factor_prec);
+  {
+    int tile = 0, th = 0;
+    if (tune_cache_get(key, tile, th)) {
+      report->best_tile = tile;
+      report->best_solve_threads = th;
+      report->from_cache = 1;
+      return SEIRD_OK;
+    }
+  }
   std::vector<double> h(p->N);
   for (int64_t i = 0; i < p->N; ++i) h[i] = 1.0 + 0.5 * std::sin(0.37 * (double)i);
   struct Buffers {
@@ -1771,8 +1990,10 @@ seird_status seird_autotune_schwarz(seird_problem p, const seird_schwarz_opts *o
     }
   }
   if (report->best_tile == 0) fail(SEIRD_ERR_ARG, "autotune: no candidate could be built (" + first_msg + ")");
+  tune_cache_put(key, report->best_tile, report->best_solve_threads);
   API_END
 }
+
 
 seird_status seird_precond_apply(seird_precond pc, const double *r, double *z, int transpose, void *stream) {
   API_BEGIN
@@ -1847,7 +2068,9 @@ seird_status seird_step(seird_problem p, seird_precond pc, double *u, double dt,
   int code = SEIRD_OK;
   try {
     std::vector<seird_step_stats> all;
-    step_impl(p, pc, u, dt, src, nopts, kopts, all, (hipStream_t)stream);
+    if (!p) fail(SEIRD_ERR_ARG, "null problem");
+    step_impl(p, pc, u, dt, src, nopts, kopts, all, (hipStream_t)stream, p->time + dt);
+    p->time += dt;
     if (!all.empty()) s = all[0];
   } catch (const Error &e) {
     code = e.code;
@@ -1892,6 +2115,7 @@ seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, 
   T.every = ckpt_every;
   T.n_regions = n_regions;
   T.dt = dt;
+  T.t0 = p->time;
   T.nopts = *nopts;
   T.kopts = *kopts;
   const int n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
@@ -1902,7 +2126,8 @@ seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, 
   if (last0 == 0) HIPCHECK(hipMemcpyAsync(T.seg[0], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
   for (int k = 1; k <= n_steps; ++k) {
     std::vector<seird_step_stats> s;
-    step_impl(p, pc, u, dt, nullptr, nopts, kopts, s, st);
+    step_impl(p, pc, u, dt, nullptr, nopts, kopts, s, st, T.t0 + k * dt);
+    p->time = T.t0 + k * dt;
     launch_region_counts(T.reg_ptr, T.reg_nodes, p->md.mass, u, counts + (int64_t)(k - 1) * n_regions, n_regions, st);
     if (k % ckpt_every == 0 && k / ckpt_every < n_seg)
       HIPCHECK(hipMemcpyAsync(T.ckpt[k / ckpt_every], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
@@ -1946,23 +2171,24 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
       for (int k = n0 + 1; k <= n1; ++k) {
         HIPCHECK(hipMemcpyAsync(T.seg[k - n0], T.seg[k - n0 - 1], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
         std::vector<seird_step_stats> ss;
-        step_impl(p, pc, T.seg[k - n0], T.dt, nullptr, &T.nopts, &T.kopts, ss, st);
+        step_impl(p, pc, T.seg[k - n0], T.dt, nullptr, &T.nopts, &T.kopts, ss, st, T.t0 + k * T.dt);
         as.recomputed_steps++;
       }
       T.seg_holds = s;
     }
     for (int k = n1; k > n0; --k) {
       const double *uk = T.seg[k - n0];
-      launch_jacobian(p->md, p->P, p->gfield, uk, T.dt, diag, off, st);
+      const ParamsDev Pk = p->params_at(T.t0 + k * T.dt);
+      launch_jacobian(p->md, Pk, p->gfield, uk, T.dt, diag, off, st);
       if (pc) precond_setup_impl(pc, p->vals, st);
-      launch_adjoint_rhs(p->md.mass, T.region, grad_counts + (int64_t)(k - 1) * T.n_regions, T.lam_next, T.rhs, n, st);
+      launch_adjoint_rhs(p->md, T.region, grad_counts + (int64_t)(k - 1) * T.n_regions, T.lam_next, T.rhs, st);
       std::vector<seird_krylov_stats> ks;
       gmres_impl(p, pc, p->vals, T.rhs, T.lam, *kopts, ks, std::vector<uint8_t>(p->seg.S, 1), 1, st);
       for (const auto &e : ks) {
         as.gmres_its_total += e.its;
         if (e.reason < 0) fail(e.reason, "transposed GMRES failed in the adjoint sweep");
       }
-      const int nb = launch_adjoint_grad(p->md, p->P, uk, T.lam, T.dt, grad_g, T.partials, st);
+      const int nb = launch_adjoint_grad(p->md, Pk, uk, T.lam, T.dt, grad_g, T.partials, st);
       part.resize(5 * (size_t)nb);
       HIPCHECK(hipMemcpyAsync(part.data(), T.partials, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
@@ -2010,6 +2236,7 @@ static void pgs_step_impl(seird_pgs g, double *u, double dt, const seird_pgs_opt
   if (p->seg.S != 1) fail(SEIRD_ERR_ARG, "Picard-Gauss-Seidel steps take a single problem");
   if (po.max_sweeps < 1 || po.max_sweeps > SEIRD_MAX_PGS) fail(SEIRD_ERR_ARG, "max_sweeps out of range");
   const int64_t n = p->mh.n, N = p->N;
+  const ParamsDev Pt = p->params_at(p->time + dt);  // coefficients at the end of the step
   stats = seird_pgs_stats{};
   HIPCHECK(hipMemcpyAsync(p->u_prev, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
   {
@@ -2040,9 +2267,9 @@ static void pgs_step_impl(seird_pgs g, double *u, double dt, const seird_pgs_opt
     HIPCHECK(hipMemcpyAsync(g->uk, u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     launch_pgs_stiffness(p->md, g->uk, g->Kd, g->Ko, st);
     for (int c = 0; c < NC; ++c) {
-      launch_pgs_system(p->md, p->P, p->gfield, c, dt, u, g->uk, p->u_prev, g->Kd, g->Ko, g->sdiag, g->soff, g->r,
+      launch_pgs_system(p->md, Pt, p->gfield, c, dt, u, g->uk, p->u_prev, g->Kd, g->Ko, g->sdiag, g->soff, g->r,
                         st);
-      if (p->P.nu[c] == 0.0) {  // lumped mass only: a diagonal system
+      if (Pt.nu[c] == 0.0 && !p->md.cmass_d) {  // lumped mass, no diffusion: a diagonal system
         launch_pgs_update(u, c, g->r, g->sdiag, n, st);
         continue;
       }
@@ -2076,7 +2303,7 @@ static void pgs_step_impl(seird_pgs g, double *u, double dt, const seird_pgs_opt
                                         std::to_string(k) + " sweeps (last " + std::to_string(eps) + ")");
   }
   // the coupled residual of the result, scaled as the Newton stopping test
-  launch_residual(p->md, p->P, p->gfield, u, p->u_prev, dt, nullptr, p->F, st);
+  launch_residual(p->md, Pt, p->gfield, u, p->u_prev, dt, nullptr, p->F, st);
   const double fn = p->seg_norms(p->F, st)[0];
   const double scale = p->seg_norms(p->u_prev, st, p->md.mass)[0];
   stats.res_scaled = fn / scale;
@@ -2149,6 +2376,7 @@ seird_status seird_pgs_step(seird_pgs g, double *u, double dt, const seird_pgs_o
   try {
     if (!g || !u || !popts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
     pgs_step_impl(g, u, dt, *popts, *kopts, s, (hipStream_t)stream);
+    g->prob->time += dt;
   } catch (const Error &e) {
     code = e.code;
     g_last_error = e.msg;
@@ -2254,8 +2482,79 @@ seird_status seird_batch_step(seird_batch b, double *u, double dt, const seird_n
   API_BEGIN
   if (!b || !u) fail(SEIRD_ERR_ARG, "null argument");
   std::vector<seird_step_stats> all;
-  step_impl(b->prob, b->pc, u, dt, nullptr, nopts, kopts, all, (hipStream_t)stream);
+  step_impl(b->prob, b->pc, u, dt, nullptr, nopts, kopts, all, (hipStream_t)stream, b->prob->time + dt);
+  b->prob->time += dt;
   if (per_instance) std::copy(all.begin(), all.end(), per_instance);
+  API_END
+}
+
+seird_status seird_batch_autotune(seird_batch b, int32_t reps, seird_tune_report *report, void *stream) {
+  API_BEGIN
+  if (!b || !report) fail(SEIRD_ERR_ARG, "null argument");
+  if (reps < 1) fail(SEIRD_ERR_ARG, "reps must be >= 1");
+  seird_precond pc = b->pc;
+  if (!pc->ready) fail(SEIRD_ERR_ARG, "batch autotune needs a set-up preconditioner (after a step)");
+  hipStream_t st = (hipStream_t)stream;
+  *report = seird_tune_report{};
+  const int T = pc->ph.tile;
+  const std::string key = tune_key("batch_schwarz_solve", b->prob->device, b->prob->mh.n, pc->ph.n_sub,
+                                   pc->ph.overlap, false, pc->ph.prec) +
+                          "|tile" + std::to_string(T);
+  {
+    int tile = 0, th = 0;
+    if (tune_cache_get(key, tile, th)) {
+      pc->solve_threads = th;
+      pc->clear_graphs();
+      report->best_tile = tile;
+      report->best_solve_threads = th;
+      report->from_cache = 1;
+      return SEIRD_OK;
+    }
+  }
+  const int64_t N = b->prob->N;
+  std::vector<double> h(N);
+  for (int64_t i = 0; i < N; ++i) h[i] = 1.0 + 0.5 * std::sin(0.37 * (double)i);
+  double *r = dev_upload(h), *z = dev_alloc<double>(N);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double best = 0.0;
+  try {
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    const std::vector<int> widths = T == 32 ? std::vector<int>{256, 512, 1024} : std::vector<int>{256};
+    for (int th : widths) {
+      pc->solve_threads = th;
+      pc->ras(r, z, 0, 0, st);
+      HIPCHECK(hipEventRecord(e0, st));
+      for (int k = 0; k < reps; ++k) pc->ras(r, z, 0, 0, st);
+      HIPCHECK(hipEventRecord(e1, st));
+      HIPCHECK(hipEventSynchronize(e1));
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+      seird_tune_candidate &c = report->cand[report->n_candidates++];
+      c.tile = T;
+      c.solve_threads = th;
+      c.status = SEIRD_OK;
+      c.apply_ms = c.score_ms = (double)t / reps;
+      if (report->best_tile == 0 || c.score_ms < best) {
+        best = c.score_ms;
+        report->best_tile = T;
+        report->best_solve_threads = th;
+      }
+    }
+  } catch (...) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dev_free(r);
+    dev_free(z);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dev_free(r);
+  dev_free(z);
+  pc->solve_threads = report->best_solve_threads;
+  pc->clear_graphs();
+  tune_cache_put(key, report->best_tile, report->best_solve_threads);
   API_END
 }
 

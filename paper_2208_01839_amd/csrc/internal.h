@@ -82,6 +82,13 @@ struct MeshHost {
   std::vector<int64_t> inc_ptr; // [n+1]
   std::vector<int32_t> inc_j, inc_l, inc_sj, inc_sl;
   std::vector<double> inc_K;    // [ninc][3]: Kii, Kij, Kil
+  // consistent mass M_ij = int phi_i phi_j: diagonal [n], slot values [nslots]
+  std::vector<double> cmass_d, cmass_o;
+  // boundary edges (in exactly one triangle), per node: the other end and
+  // the outward normal scaled by the edge length
+  std::vector<int64_t> bnd_ptr;  // [n+1]
+  std::vector<int32_t> bnd_j;
+  std::vector<double> bnd_nl;    // [nb][2]
 };
 
 struct MeshDev {
@@ -93,6 +100,13 @@ struct MeshDev {
   int64_t *inc_ptr = nullptr;
   int32_t *inc_j = nullptr, *inc_l = nullptr, *inc_sj = nullptr, *inc_sl = nullptr;
   double *inc_K = nullptr;
+  // discretisation variants: consistent mass (null: lumped) and boundary
+  // flux data [n][5][2] (null: homogeneous Neumann)
+  const double *cmass_d = nullptr, *cmass_o = nullptr;
+  const int64_t *bnd_ptr = nullptr;
+  const int32_t *bnd_j = nullptr;
+  const double *bnd_nl = nullptr;
+  const double *qflux = nullptr;
   // batches: instance of every node and the parameters of every instance
   // (both null for a single problem)
   const int32_t *inst = nullptr;
@@ -176,6 +190,16 @@ struct PrecondHost {
   std::vector<int64_t> gal_ptr;        // [nblocks+1]
   std::vector<int32_t> gal_ref;        // fine block ref (as ExtractEntry.ref)
   std::vector<double> gal_w;
+  // the coarse system as a graph over coarse positions, for the Krylov
+  // coarse solver (two-grid RAS-V2): adjacency without self loops, node
+  // points, the fine subdomain that owns each coarse node's own fine node,
+  // and where Galerkin block k goes (-p-1: diagonal block of position p;
+  // >= 0: slot of the coarse graph)
+  std::vector<int64_t> cg_rowptr;
+  std::vector<int32_t> cg_col;
+  std::vector<double> cg_xy;
+  std::vector<int32_t> cg_owner;
+  std::vector<int32_t> gal_dst;
 };
 
 void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,

@@ -29,6 +29,7 @@ struct SegHost {
 struct FactorLaunch {
   int tile = 32;
   int bs = 5;               // unknowns per node of the extracted matrix (5: node-block Jacobian; 1: scalar)
+  bool dense_off = false;   // bs 5 with dense off-diagonal blocks, off [slots][25] (the coarse graph matrix)
   void *Fs = nullptr;       // subdomain tile-envelope storage (float64, or float32 if sub_float)
   bool sub_float = false;   // factorise the subdomains in float32
   int64_t sub_entries = 0;
@@ -46,6 +47,11 @@ struct FactorLaunch {
   int max_node_blocks = 0;            // most extraction entries of one local node
   int max_bu = 0;
   int *status = nullptr;
+  // persistent factorisation grid: queue counter (device int), compute
+  // units, and workgroup slots left for the concurrent coarse chain
+  int *queue = nullptr;
+  int n_cu = 0;
+  int lu_spare = 32;
   // coarse
   bool coarse = false;
   SubInfo cs{};
@@ -98,6 +104,7 @@ void launch_maxpy_norm(double *w, const double *V, int64_t ldv, const double *h,
 void launch_gemv_update(double *x, const double *Z, int64_t ldz, const double *y, int nv, int64_t N, int nb,
                         hipStream_t st);
 void launch_fill(double *y, double v, int64_t N, hipStream_t st);
+void launch_fill_int(int *y, int v, int N, hipStream_t st);
 void launch_axpby(double *y, const double *x, double a, const double *aptr, int ainv, double b, int64_t N, int nb,
                   hipStream_t st);
 void launch_norm2_partials(const double *x, const double *scale, int64_t N, double *partials, int nb, hipStream_t st);
@@ -118,6 +125,14 @@ void launch_check_state(const double *u, int64_t n, const int32_t *inst, int *fl
 // the coarse factorisation goes to st_coarse (may equal st), the subdomains to st
 void launch_setup_factors(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st,
                           hipStream_t st_coarse);
+// Galerkin coarse matrix as dense 5x5 node blocks of the coarse graph
+// (block k to the diagonal block -gdst[k]-1 or to slot gdst[k])
+void launch_galerkin_blocks(const int32_t *gdst, const int64_t *gptr, const int32_t *gref, const double *gw,
+                            int64_t nblk, const double *diag, const double *off, double *cdiag, double *coff,
+                            hipStream_t st);
+// y = A x (b null) or b - A x for dense 5x5 node blocks: diag [n][25], off [slots][25]
+void launch_block_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *diag, const double *off,
+                       const double *x, const double *b, double *y, hipStream_t st);
 void launch_convert(void *dst, int dst_prec, const void *src, int src_float, int64_t N, hipStream_t st);
 void launch_band_solve(const SolveLaunch &sl, hipStream_t st);
 void launch_gather_copies(const int64_t *gptr, const int32_t *gidx, const double *yloc, double *z, int add, int64_t N,
@@ -129,8 +144,8 @@ void launch_coarse_prolong(const int64_t *z_ptr, const int32_t *z_col, const dou
 
 void launch_region_counts(const int64_t *reg_ptr, const int32_t *reg_nodes, const double *mass, const double *u,
                           double *counts, int n_regions, hipStream_t st);
-void launch_adjoint_rhs(const double *mass, const int32_t *region, const double *gc, const double *lam_next,
-                        double *rhs, int64_t n, hipStream_t st);
+void launch_adjoint_rhs(const MeshDev &m, const int32_t *region, const double *gc, const double *lam_next,
+                        double *rhs, hipStream_t st);
 // returns the number of blocks (nu partial sums per component)
 int launch_adjoint_grad(const MeshDev &m, const ParamsDev &P, const double *u, const double *lam, double dt,
                         double *grad_g, double *partials, hipStream_t st);

@@ -114,9 +114,40 @@ __global__ __launch_bounds__(256) void k_residual(MeshDev m, ParamsDev P0, const
   double R[5];
   reaction_at(ui, P, g, R);
   const double mi = m.mass[i];
+  // time-derivative term: lumped m_i (u - u^n)_i, or consistent
+  // sum_j M_ij (u - u^n)_j over the node and its graph neighbours
+  double mt[5];
+  if (m.cmass_d) {
+    const double md = m.cmass_d[i];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) mt[c] = md * (ui[c] - up[5 * i + c]);
+    for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
+      const int64_t j = m.col[s];
+      const double mo = m.cmass_o[s];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) mt[c] += mo * (u[5 * j + c] - up[5 * j + c]);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) mt[c] = mi * (ui[c] - up[5 * i + c]);
+  }
+  // boundary flux of Eq. weakform: int (q . n) phi_i over the boundary
+  // edges at node i, q P1 along the edge: (2 q_i + q_j) . n L / 6
+  double bq[5] = {0, 0, 0, 0, 0};
+  if (m.qflux) {
+    for (int64_t b = m.bnd_ptr[i]; b < m.bnd_ptr[i + 1]; ++b) {
+      const int64_t j = m.bnd_j[b];
+      const double nx = m.bnd_nl[2 * b], ny = m.bnd_nl[2 * b + 1];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const double *qi = m.qflux + 10 * i + 2 * c, *qj = m.qflux + 10 * j + 2 * c;
+        bq[c] += (2.0 * (qi[0] * nx + qi[1] * ny) + (qj[0] * nx + qj[1] * ny)) * (1.0 / 6.0);
+      }
+    }
+  }
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    double f = mi * (ui[c] - up[5 * i + c]) + dt * P.nu[c] * acc[c] - dt * mi * R[c];
+    double f = mt[c] + dt * P.nu[c] * acc[c] - dt * mi * R[c] - dt * bq[c];
     if (src) f -= dt * mi * src[5 * i + c];
     F[5 * i + c] = f;
   }
@@ -179,6 +210,11 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
         o[5 + c] += G3[c];
       }
     }
+    if (m.cmass_o) {
+      const double mo = m.cmass_o[s];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) o[c] += mo;
+    }
 #pragma unroll
     for (int q = 0; q < 10; ++q) off[10 * s + q] = o[q];
   }
@@ -186,11 +222,12 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
   double JR[5][5];
   reaction_jac_at(ui, P, g, JR);
   const double mi = m.mass[i];
+  const double mdiag = m.cmass_d ? m.cmass_d[i] : mi;  // the time-derivative term's diagonal
   double *D = diag + 25 * i;
 #pragma unroll
   for (int c = 0; c < 5; ++c)
 #pragma unroll
-    for (int cp = 0; cp < 5; ++cp) D[5 * c + cp] = -dt * mi * JR[c][cp] + db[c] + (c == cp ? mi + da[c] : 0.0);
+    for (int cp = 0; cp < 5; ++cp) D[5 * c + cp] = -dt * mi * JR[c][cp] + db[c] + (c == cp ? mdiag + da[c] : 0.0);
 }
 
 // ----------------------------------------------------------------------
@@ -368,6 +405,11 @@ __global__ void k_axpby(double *__restrict__ y, const double *__restrict__ x, do
     y[idx] = aa * x[idx] + (b != 0.0 ? b * y[idx] : 0.0);
 }
 
+// y[0..N) = v for int arrays (queue counters)
+__global__ void k_fill_int(int *__restrict__ y, int v, int N) {
+  for (int idx = threadIdx.x; idx < N; idx += blockDim.x) y[idx] = v;
+}
+
 // y[0..N) = v (a fill kernel rather than a memset, so that it can sit in a
 // captured stream)
 __global__ void k_fill(double *__restrict__ y, double v, int64_t N) {
@@ -521,15 +563,30 @@ __global__ __launch_bounds__(256) void k_pgs_system(MeshDev m, ParamsDev P, cons
   }
   const double mi = m.mass[i];
   const double sc = dt * P.nu[c];
-  const double di = mi * (1.0 + dt * q) + sc * Kd[i];
+  // time-derivative term: lumped m_i, or the consistent mass row (the
+  // reaction keeps nodal quadrature); boundary flux on the right-hand side
+  const double md = m.cmass_d ? m.cmass_d[i] : mi;
+  const double di = md + dt * mi * q + sc * Kd[i];
   sdiag[i] = di;
-  double Au = di * v[c];
+  double Au = di * v[c], Mun = md * un[5 * i + c];
   for (int64_t t = m.rowptr[i]; t < m.rowptr[i + 1]; ++t) {
-    const double o = sc * Ko[t];
+    const int64_t j = m.col[t];
+    const double mo = m.cmass_o ? m.cmass_o[t] : 0.0;
+    const double o = mo + sc * Ko[t];
     soff[t] = o;
-    Au += o * u[5 * (int64_t)m.col[t] + c];
+    Au += o * u[5 * j + c];
+    Mun += mo * un[5 * j + c];
   }
-  r[i] = mi * (un[5 * i + c] + dt * f) - Au;
+  double bq = 0.0;
+  if (m.qflux) {
+    for (int64_t b = m.bnd_ptr[i]; b < m.bnd_ptr[i + 1]; ++b) {
+      const int64_t j = m.bnd_j[b];
+      const double nx = m.bnd_nl[2 * b], ny = m.bnd_nl[2 * b + 1];
+      const double *qi = m.qflux + 10 * i + 2 * c, *qj = m.qflux + 10 * j + 2 * c;
+      bq += (2.0 * (qi[0] * nx + qi[1] * ny) + (qj[0] * nx + qj[1] * ny)) * (1.0 / 6.0);
+    }
+  }
+  r[i] = Mun + dt * mi * f + dt * bq - Au;
 }
 
 // y = A x (b == nullptr) or y = b - A x for a scalar matrix on the node
@@ -771,8 +828,10 @@ __global__ void k_pad_identity(ET *__restrict__ F, const SubInfo *__restrict__ s
 // row are the extraction entries of its local node.  BS = 5 (the coupled
 // Jacobian): diagonal blocks from diag [n][25], off-diagonal block
 // (c, c') = b_c + a_c [c = c'] from off [slots][10].  BS = 1 (one
-// compartment's scalar matrix): diag [n] and off [slots].
-template <int T, class ET, int MAXE, int BS = 5>
+// compartment's scalar matrix): diag [n] and off [slots].  DENSE (BS = 5,
+// the Galerkin coarse matrix on the coarse graph): off-diagonal blocks
+// dense, off [slots][25] row-major.
+template <int T, class ET, int MAXE, int BS = 5, bool DENSE = false>
 __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const SubInfo *__restrict__ subs,
                                                        const int32_t *__restrict__ trow_ptr,
                                                        const int32_t *__restrict__ trow_sub,
@@ -820,6 +879,7 @@ __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const
       return ref < 0 ? diag[-(int64_t)ref - 1] : off[ref];
     } else {
       if (ref < 0) return diag[25 * (int64_t)(-ref - 1) + 5 * c + cp];
+      if constexpr (DENSE) return off[25 * (int64_t)ref + 5 * c + cp];
       const double *o = off + 10 * (int64_t)ref;
       return o[5 + c] + (cp == c ? o[c] : 0.0);
     }
@@ -898,18 +958,12 @@ __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const
 }
 
 // Galerkin coarse matrix: coarse block k (local positions p, q) =
-// sum_j w_j * fine block(ref_j), written into the coarse tile-band storage.
-// One wave per coarse block: lanes stride over its contributions, each lane
-// accumulates the 25 entries, then a fixed-order wave reduction.
-template <int T>
-__global__ __launch_bounds__(256) void k_galerkin(double *__restrict__ F, SubInfo cs, const int32_t *__restrict__ gp,
-                                                  const int32_t *__restrict__ gq, const int64_t *__restrict__ gptr,
-                                                  const int32_t *__restrict__ gref, const double *__restrict__ gw,
-                                                  int64_t nblk, const double *__restrict__ diag,
-                                                  const double *__restrict__ off, int *status) {
-  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (k >= nblk) return;  // uniform per wave
+// sum_j w_j * fine block(ref_j).  One wave per coarse block: lanes stride
+// over its contributions, each lane accumulates the 25 entries, then a
+// fixed-order wave reduction; lane e < 25 returns entry e (row-major).
+__device__ inline double galerkin_entry(int64_t k, int lane, const int64_t *__restrict__ gptr,
+                                        const int32_t *__restrict__ gref, const double *__restrict__ gw,
+                                        const double *__restrict__ diag, const double *__restrict__ off) {
   double acc[25];
 #pragma unroll
   for (int e = 0; e < 25; ++e) acc[e] = 0.0;
@@ -933,11 +987,25 @@ __global__ __launch_bounds__(256) void k_galerkin(double *__restrict__ F, SubInf
   }
 #pragma unroll
   for (int e = 0; e < 25; ++e) acc[e] = wave_sum(acc[e]);
-  if (lane < 25) {
-    double v = 0.0;
+  double v = 0.0;
 #pragma unroll
-    for (int e = 0; e < 25; ++e)
-      if (e == lane) v = acc[e];
+  for (int e = 0; e < 25; ++e)
+    if (e == lane) v = acc[e];
+  return v;
+}
+
+// written into the coarse tile-band storage (direct coarse solve)
+template <int T>
+__global__ __launch_bounds__(256) void k_galerkin(double *__restrict__ F, SubInfo cs, const int32_t *__restrict__ gp,
+                                                  const int32_t *__restrict__ gq, const int64_t *__restrict__ gptr,
+                                                  const int32_t *__restrict__ gref, const double *__restrict__ gw,
+                                                  int64_t nblk, const double *__restrict__ diag,
+                                                  const double *__restrict__ off, int *status) {
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (k >= nblk) return;  // uniform per wave
+  const double v = galerkin_entry(k, lane, gptr, gref, gw, diag, off);
+  if (lane < 25) {
     const int c = lane / 5, cp = lane % 5;
     const int64_t at = tile_entry_checked<T>(cs, 5 * gp[k] + c, 5 * gq[k] + cp);
     if (at < 0)
@@ -945,6 +1013,54 @@ __global__ __launch_bounds__(256) void k_galerkin(double *__restrict__ F, SubInf
     else
       F[at] = v;
   }
+}
+
+// written as node blocks of the coarse graph (Krylov coarse solve): block k
+// goes to the diagonal block of position -dst-1 or to slot dst
+__global__ __launch_bounds__(256) void k_galerkin_blocks(double *__restrict__ cdiag, double *__restrict__ coff,
+                                                         const int32_t *__restrict__ gdst,
+                                                         const int64_t *__restrict__ gptr,
+                                                         const int32_t *__restrict__ gref,
+                                                         const double *__restrict__ gw, int64_t nblk,
+                                                         const double *__restrict__ diag,
+                                                         const double *__restrict__ off) {
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (k >= nblk) return;  // uniform per wave
+  const double v = galerkin_entry(k, lane, gptr, gref, gw, diag, off);
+  if (lane < 25) {
+    const int32_t d = gdst[k];
+    double *dst = d < 0 ? cdiag + 25 * (int64_t)(-d - 1) : coff + 25 * (int64_t)d;
+    dst[lane] = v;
+  }
+}
+
+// y = A x (or b - A x) for a matrix of dense 5x5 node blocks on a graph:
+// diag [n][25], off [slots][25] (row-major blocks).  Five lanes per node,
+// lane c producing row c; each output sums the diagonal block, then the
+// slots in CSR order.
+__global__ __launch_bounds__(256) void k_block_spmv(int64_t n, const int64_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const double *__restrict__ diag,
+                                                    const double *__restrict__ off, const double *__restrict__ x,
+                                                    const double *__restrict__ b, double *__restrict__ y) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane % 5;
+  const int64_t i = ((int64_t)blockIdx.x * 4 + w) * SPMV_WAVE_NODES + lane / 5;
+  if (lane >= 5 * SPMV_WAVE_NODES || i >= n) return;
+  double xi[5];
+  load5(x + 5 * i, xi);
+  const double *D = diag + 25 * i + 5 * c;
+  double acc = 0.0;
+#pragma unroll
+  for (int cp = 0; cp < 5; ++cp) acc += D[cp] * xi[cp];
+  for (int64_t s = rowptr[i]; s < rowptr[i + 1]; ++s) {
+    double xj[5];
+    load5(x + 5 * (int64_t)col[s], xj);
+    const double *o = off + 25 * s + 5 * c;
+#pragma unroll
+    for (int cp = 0; cp < 5; ++cp) acc += o[cp] * xj[cp];
+  }
+  y[5 * i + c] = b ? b[5 * i + c] - acc : acc;
 }
 
 template <class FT>
@@ -1241,152 +1357,182 @@ __device__ void lu_inv_diag_regs(CT *__restrict__ dk, CT (*Li)[33], CT (*Ui)[33]
   }
 }
 
-// LU of one subdomain per workgroup (tile 32, NW waves), right-
-// looking by block rows.  Step K:
+// LU of the subdomains (tile 32, NW waves per workgroup), right-looking by
+// block rows.  Step K:
 //   (1) the diagonal tile is factored and both factors inverted (register
 //       sweep above);
-//   (2) U panel U_KJ = L_KK^{-1} A_KJ on MFMA.  Wave w owns the panel tiles
-//       jj = w + NW q (q < QW) and keeps them in registers for the whole
-//       step: the accumulator layout of a 16x16 MFMA result is the B-operand
-//       layout of a later product whose k index runs over the result rows
-//       (in the accumulator's own row order), so U never goes through LDS;
+//   (2) U panel U_KJ = L_KK^{-1} A_KJ on MFMA, in chunks of NW QW tiles
+//       (one chunk unless the row is wider).  Wave w owns the chunk's
+//       tiles jj = c0 + w + NW q (q < QW) and keeps them in registers: the
+//       accumulator layout of a 16x16 MFMA result is the B-operand layout
+//       of a later product whose k index runs over the result rows (in the
+//       accumulator's own row order), so U never goes through LDS;
 //   (3) for each block row I below: L_IK = A_IK U_KK^{-1} (four waves, one
-//       16x16 quadrant each, A_IK read straight into the A-operand layout),
-//       staged in one of two LDS buffers (one barrier per row), and the
-//       C strip C_IJ -= L_IK U_KJ of the wave's own tiles on MFMA.
-// LDS: U_KK^{-1} and the two row buffers, the second of which holds
-// L_KK^{-1} during (1)-(2).
+//       16x16 quadrant each, A_IK read straight into the A-operand layout;
+//       later chunks read the stored L_IK back), staged in one of two LDS
+//       buffers (one barrier per row), and the C strip C_IJ -= L_IK U_KJ of
+//       the wave's own tiles on MFMA.
+// LDS: L_KK^{-1}, U_KK^{-1} and the two row buffers.  With four waves the
+// float64 kernel stays within 256 registers, so two workgroups share a
+// compute unit and hide each other's latencies.  Launched with a queue
+// counter, a grid smaller than the subdomain count draws subdomains until
+// they are exhausted (every workgroup exits once the counter passes nsub).
 template <class CT, int NW, int QW>
-__global__ __launch_bounds__(64 * NW) void k_band_lu32(CT *__restrict__ F, const SubInfo *__restrict__ subs,
-                                                       const int32_t *__restrict__ erow,
-                                                       const int32_t *__restrict__ elo,
-                                                       const int32_t *__restrict__ order, int *status) {
-  constexpr int T = 32, NT = 64 * NW;
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4 ? 2 : 1))) void k_band_lu32(
+    CT *__restrict__ F, const SubInfo *__restrict__ subs, const int32_t *__restrict__ erow,
+    const int32_t *__restrict__ elo, const int32_t *__restrict__ order, int nsub, int *__restrict__ queue,
+    int *status) {
+  constexpr int T = 32, NT = 64 * NW, CH = NW * QW;
   typedef typename Mfma<CT>::v4 v4;
   __shared__ CT Ui[T][T + 1];     // U_KK^{-1}, dense upper
-  __shared__ CT Sx[2][T][T + 1];  // L_KK^{-1} (in Sx[1]) in (1)-(2); L_IK buffers in (3)
-  const SubInfo s = subs[order[blockIdx.x]];
-  const TileRows R = tile_rows(s, erow, elo);
+  __shared__ CT Li[T][T + 1];     // L_KK^{-1}, dense unit lower
+  __shared__ CT Sx[2][T][T + 1];  // L_IK buffers of the row loop
+  __shared__ int next;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int qi = (wave >> 1) & 1, qj = wave & 1;
+  // subdomains in the queue's (largest-first) order: one per workgroup, or,
+  // with a queue counter, as many as the workgroup draws until none is left
+  for (int it = blockIdx.x; it < nsub;) {
+  const SubInfo s = subs[order[it]];
+  const TileRows R = tile_rows(s, erow, elo);
   for (int K = 0; K < s.nt; ++K) {
     // the envelope is symmetric: row K's U tiles and the rows below with a
     // tile in column K both end at last(K)
     const int je = R.last(K), nu = je - K;
     const int ie = je;
     // (1) diagonal tile: LU and both inverses in one sweep
-    lu_inv_diag_regs<CT, NT>(F + R.at<T>(K, K), Sx[1], Ui, status);
-    // (2) the wave's U-panel tiles, kept as B operands: ub[q][bj][4 bi + v]
-    // holds U_KJ[16 bi + row(lk, v)][16 bj + lr]
-    CT ub[QW][2][8];
-#pragma unroll
-    for (int q = 0; q < QW; ++q) {
-      const int jj = wave + NW * q;
-      if (jj < nu) {
-        CT *g = F + R.at<T>(K, K + 1 + jj);
-        CT bl[8][2];
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) bl[m][bj] = g[(4 * m + lk) * T + 16 * bj + lr];
-        v4 acc[2][2];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4{0, 0, 0, 0};
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          const CT a0 = Sx[1][lr][4 * m + lk], a1 = Sx[1][16 + lr][4 * m + lk];
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) {
-            acc[0][bj] = Mfma<CT>::op(a0, bl[m][bj], acc[0][bj]);
-            acc[1][bj] = Mfma<CT>::op(a1, bl[m][bj], acc[1][bj]);
-          }
-        }
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              ub[q][bj][4 * bi + v] = acc[bi][bj][v];
-              g[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr] = acc[bi][bj][v];
-            }
-      }
-    }
-    // (3) block rows below
-    for (int I = K + 1; I <= ie; ++I) {
-      const int buf = (I - K - 1) & 1;
-      CT *aik = F + R.at<T>(I, K);
-      // A_IK quadrant rows in the A-operand layout (issued first: the
-      // quadrant product waits on these loads only)
-      CT ra[8];
-      if (wave < 4) {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) ra[m] = aik[(16 * qi + lr) * T + 4 * m + lk];
-      }
-      v4 acc[QW][2][2];
+    lu_inv_diag_regs<CT, NT>(F + R.at<T>(K, K), Li, Ui, status);
+    // the panel in chunks of CH tiles (one chunk unless the row is wider)
+    for (int c0 = 0; c0 < nu; c0 += CH) {
+      // (2) the wave's U-panel tiles of this chunk, kept as B operands:
+      // ub[q][bj][4 bi + v] holds U_KJ[16 bi + row(lk, v)][16 bj + lr]
+      CT ub[QW][2][8];
 #pragma unroll
       for (int q = 0; q < QW; ++q) {
-        const int jj = wave + NW * q;
+        const int jj = c0 + wave + NW * q;
         if (jj < nu) {
-          const CT *c = F + R.at<T>(I, K + 1 + jj);
+          CT *g = F + R.at<T>(K, K + 1 + jj);
+          CT bl[8][2];
+#pragma unroll
+          for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) bl[m][bj] = g[(4 * m + lk) * T + 16 * bj + lr];
+          v4 acc[2][2];
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4{0, 0, 0, 0};
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            const CT a0 = Li[lr][4 * m + lk], a1 = Li[16 + lr][4 * m + lk];
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+              acc[0][bj] = Mfma<CT>::op(a0, bl[m][bj], acc[0][bj]);
+              acc[1][bj] = Mfma<CT>::op(a1, bl[m][bj], acc[1][bj]);
+            }
+          }
 #pragma unroll
           for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-              for (int v = 0; v < 4; ++v) acc[q][bi][bj][v] = c[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr];
+              for (int v = 0; v < 4; ++v) {
+                ub[q][bj][4 * bi + v] = acc[bi][bj][v];
+                g[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr] = acc[bi][bj][v];
+              }
         }
       }
-      v4 l = {0, 0, 0, 0};
-      if (wave < 4) {
+      // (3) block rows below: L_IK (first chunk: computed and stored; later
+      // chunks: read back), then the wave's C tiles of the chunk
+      for (int I = K + 1; I <= ie; ++I) {
+        const int buf = (I - K - 1) & 1;
+        CT *aik = F + R.at<T>(I, K);
+        v4 acc[QW][2][2];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) l = Mfma<CT>::op(ra[m], Ui[4 * m + lk][16 * qj + lr], l);
+        for (int q = 0; q < QW; ++q) {
+          const int jj = c0 + wave + NW * q;
+          if (jj < nu) {
+            const CT *c = F + R.at<T>(I, K + 1 + jj);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Sx[buf][16 * qi + Mfma<CT>::row(lk, v)][16 * qj + lr] = l[v];
-      }
-      __syncthreads();  // L_IK staged; every wave has read A_IK
-      if (wave < 4) {
+            for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) aik[(16 * qi + Mfma<CT>::row(lk, v)) * T + 16 * qj + lr] = l[v];
-      }
-      // C_IJ -= L_IK U_KJ; the k index of step (bi, v) is 16 bi + row(lk, v)
+              for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int kc = 16 * bi + Mfma<CT>::row(lk, v);
-          const CT a0 = -Sx[buf][lr][kc], a1 = -Sx[buf][16 + lr][kc];
-#pragma unroll
-          for (int q = 0; q < QW; ++q) {
-            const int jj = wave + NW * q;
-            if (jj < nu) {
-              acc[q][0][0] = Mfma<CT>::op(a0, ub[q][0][4 * bi + v], acc[q][0][0]);
-              acc[q][0][1] = Mfma<CT>::op(a0, ub[q][1][4 * bi + v], acc[q][0][1]);
-              acc[q][1][0] = Mfma<CT>::op(a1, ub[q][0][4 * bi + v], acc[q][1][0]);
-              acc[q][1][1] = Mfma<CT>::op(a1, ub[q][1][4 * bi + v], acc[q][1][1]);
-            }
+                for (int v = 0; v < 4; ++v)
+                  acc[q][bi][bj][v] = c[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr];
           }
         }
+        if (c0 == 0) {
+          // A_IK quadrant rows in the A-operand layout
+          CT ra[8];
+          if (wave < 4) {
 #pragma unroll
-      for (int q = 0; q < QW; ++q) {
-        const int jj = wave + NW * q;
-        if (jj < nu) {
-          CT *c = F + R.at<T>(I, K + 1 + jj);
+            for (int m = 0; m < 8; ++m) ra[m] = aik[(16 * qi + lr) * T + 4 * m + lk];
+          }
+          v4 l = {0, 0, 0, 0};
+          if (wave < 4) {
 #pragma unroll
-          for (int bi = 0; bi < 2; ++bi)
+            for (int m = 0; m < 8; ++m) l = Mfma<CT>::op(ra[m], Ui[4 * m + lk][16 * qj + lr], l);
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
+            for (int v = 0; v < 4; ++v) Sx[buf][16 * qi + Mfma<CT>::row(lk, v)][16 * qj + lr] = l[v];
+          }
+          __syncthreads();  // L_IK staged; every wave has read A_IK
+          if (wave < 4) {
 #pragma unroll
-              for (int v = 0; v < 4; ++v) c[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr] = acc[q][bi][bj][v];
+            for (int v = 0; v < 4; ++v) aik[(16 * qi + Mfma<CT>::row(lk, v)) * T + 16 * qj + lr] = l[v];
+          }
+        } else {
+          for (int e = tid; e < T * T; e += NT) Sx[buf][e / T][e % T] = aik[e];
+          __syncthreads();  // L_IK staged
+        }
+        // C_IJ -= L_IK U_KJ; the k index of step (bi, v) is 16 bi + row(lk, v)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int kc = 16 * bi + Mfma<CT>::row(lk, v);
+            const CT a0 = -Sx[buf][lr][kc], a1 = -Sx[buf][16 + lr][kc];
+#pragma unroll
+            for (int q = 0; q < QW; ++q) {
+              const int jj = c0 + wave + NW * q;
+              if (jj < nu) {
+                acc[q][0][0] = Mfma<CT>::op(a0, ub[q][0][4 * bi + v], acc[q][0][0]);
+                acc[q][0][1] = Mfma<CT>::op(a0, ub[q][1][4 * bi + v], acc[q][0][1]);
+                acc[q][1][0] = Mfma<CT>::op(a1, ub[q][0][4 * bi + v], acc[q][1][0]);
+                acc[q][1][1] = Mfma<CT>::op(a1, ub[q][1][4 * bi + v], acc[q][1][1]);
+              }
+            }
+          }
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+          const int jj = c0 + wave + NW * q;
+          if (jj < nu) {
+            CT *c = F + R.at<T>(I, K + 1 + jj);
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+              for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) c[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr] = acc[q][bi][bj][v];
+          }
         }
       }
+      // L tiles stored by other waves are read back by the next chunk
+      __threadfence_block();
+      __syncthreads();
     }
     // the next step's diagonal tile and U panel were written by other waves
     // of this workgroup: make the stores visible before they are read
     __threadfence_block();
+    __syncthreads();
+  }
+    if (!queue) break;
+    // the counter starts at the grid size: the first subdomains went to
+    // the workgroups by their index
+    if (tid == 0) next = atomicAdd(queue, 1);
+    __syncthreads();
+    it = next;
     __syncthreads();
   }
 }
@@ -2453,14 +2599,32 @@ __global__ __launch_bounds__(256) void k_region_counts(const int64_t *__restrict
   if (threadIdx.x == 0) counts[r] = t;
 }
 
-__global__ __launch_bounds__(256) void k_adjoint_rhs(const double *__restrict__ mass, const int32_t *__restrict__ region,
+// rhs = M^T lam^{n+1} + dL/du^n (the observation weights the infected
+// compartment by the lumped mass); M^T = M for the lumped and the
+// consistent mass
+__global__ __launch_bounds__(256) void k_adjoint_rhs(MeshDev md, const int32_t *__restrict__ region,
                                                      const double *__restrict__ gc, const double *__restrict__ lam_next,
-                                                     double *__restrict__ rhs, int64_t n) {
+                                                     double *__restrict__ rhs) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const double m = mass[j];
+  if (j >= md.n) return;
+  const double m = md.mass[j];
+  double v[5];
+  if (md.cmass_d) {
+    const double d = md.cmass_d[j];
 #pragma unroll
-  for (int c = 0; c < 5; ++c) rhs[5 * j + c] = m * lam_next[5 * j + c];
+    for (int c = 0; c < 5; ++c) v[c] = d * lam_next[5 * j + c];
+    for (int64_t s = md.rowptr[j]; s < md.rowptr[j + 1]; ++s) {
+      const int64_t k = md.col[s];
+      const double o = md.cmass_o[s];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) v[c] += o * lam_next[5 * k + c];
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = m * lam_next[5 * j + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) rhs[5 * j + c] = v[c];
   const int32_t r = region[j];
   if (r >= 0) rhs[5 * j + 2] += gc[r] * m;
 }
@@ -2510,10 +2674,11 @@ void launch_region_counts(const int64_t *reg_ptr, const int32_t *reg_nodes, cons
   if (n_regions > 0)
     hipLaunchKernelGGL(k_region_counts, dim3(n_regions), dim3(256), 0, st, reg_ptr, reg_nodes, mass, u, counts);
 }
-void launch_adjoint_rhs(const double *mass, const int32_t *region, const double *gc, const double *lam_next,
-                        double *rhs, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_adjoint_rhs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, mass, region, gc, lam_next,
-                     rhs, n);
+void launch_adjoint_rhs(const MeshDev &m, const int32_t *region, const double *gc, const double *lam_next,
+                        double *rhs, hipStream_t st) {
+  const int64_t n = m.n;
+  hipLaunchKernelGGL(k_adjoint_rhs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m, region, gc, lam_next,
+                     rhs);
 }
 int launch_adjoint_grad(const MeshDev &m, const ParamsDev &P, const double *u, const double *lam, double dt,
                         double *grad_g, double *partials, hipStream_t st) {
@@ -2626,6 +2791,9 @@ static void extract_t(const FactorLaunch &fl, ET *F, const double *diag, const d
     else
       hipLaunchKernelGGL((k_extract_tiles<T, ET, 16, 1>), g, dim3(256), 0, st, F, fl.subs, fl.trow_ptr, fl.trow_sub,
                          fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
+  } else if (fl.dense_off) {
+    hipLaunchKernelGGL((k_extract_tiles<T, ET, 16, 5, true>), g, dim3(256), 0, st, F, fl.subs, fl.trow_ptr,
+                       fl.trow_sub, fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
   } else if (fl.max_node_blocks <= 10) {
     hipLaunchKernelGGL((k_extract_tiles<T, ET, 10>), g, dim3(256), 0, st, F, fl.subs, fl.trow_ptr, fl.trow_sub,
                        fl.erow, fl.elo, fl.ent, fl.ent_ptr, diag, off);
@@ -2666,15 +2834,29 @@ static void coarse_factor_t(const FactorLaunch &fl, const double *diag, const do
 // workgroups of 128 would fill the register file.
 template <class CT>
 static void band_lu32(const FactorLaunch &fl, CT *F, hipStream_t st) {
-  if (fl.max_bu <= 8)
-    hipLaunchKernelGGL((k_band_lu32<CT, 4, 2>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo, fl.order,
-                       fl.status);
-  else if (sizeof(CT) == 4 && fl.coarse && fl.max_bu <= 12)
-    hipLaunchKernelGGL((k_band_lu32<CT, 4, 3>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo, fl.order,
-                       fl.status);
-  else
-    hipLaunchKernelGGL((k_band_lu32<CT, 8, 2>), dim3(fl.nsub), dim3(512), 0, st, F, fl.subs, fl.erow, fl.elo, fl.order,
-                       fl.status);
+  if (sizeof(CT) == 4) {
+    // float32: four waves with three panel tiles each, two workgroups per
+    // compute unit with room left for the float64 coarse-chain kernels
+    hipLaunchKernelGGL((k_band_lu32<CT, 4, 3>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo,
+                       fl.order, fl.nsub, nullptr, fl.status);
+    return;
+  }
+  // float64: two workgroups of four waves per compute unit.  Beside a
+  // coarse chain (its kernels need 64 registers per lane), a persistent
+  // grid of 2 CUs - lu_spare workgroups draws the subdomains from a queue,
+  // so that some compute units keep room for the chain.
+  const int per_cu = 2;
+  int grid = fl.nsub;
+  int *queue = nullptr;
+  if (fl.coarse && fl.queue && fl.n_cu > 0) {
+    grid = std::min(fl.nsub, std::max(1, per_cu * fl.n_cu - fl.lu_spare));
+    if (grid < fl.nsub) {
+      queue = fl.queue;
+      hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, queue, grid, 1);
+    }
+  }
+  hipLaunchKernelGGL((k_band_lu32<CT, 4, 2>), dim3(grid), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo, fl.order,
+                     fl.nsub, queue, fl.status);
 }
 
 static void coarse_factor(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st) {
@@ -2718,6 +2900,22 @@ void launch_setup_factors(const FactorLaunch &fl, const double *diag, const doub
     mark(fl.ev_lu_end);
   }
   if (fl.coarse && !coarse_first) coarse_factor(fl, diag, off, st_coarse);
+}
+
+void launch_galerkin_blocks(const int32_t *gdst, const int64_t *gptr, const int32_t *gref, const double *gw,
+                            int64_t nblk, const double *diag, const double *off, double *cdiag, double *coff,
+                            hipStream_t st) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(k_galerkin_blocks, dim3(nblocks(nblk * 64)), dim3(256), 0, st, cdiag, coff, gdst, gptr, gref, gw,
+                     nblk, diag, off);
+}
+
+void launch_block_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *diag, const double *off,
+                       const double *x, const double *b, double *y, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t per_block = 4 * SPMV_WAVE_NODES;
+  hipLaunchKernelGGL(k_block_spmv, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(256), 0, st, n, rowptr, col,
+                     diag, off, x, b, y);
 }
 
 void launch_convert(void *dst, int dst_prec, const void *src, int src_float, int64_t N, hipStream_t st) {
@@ -2770,6 +2968,9 @@ void launch_band_solve(const SolveLaunch &sl, hipStream_t st) {
   }
 }
 
+void launch_fill_int(int *y, int v, int N, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, y, v, N);
+}
 void launch_fill(double *y, double v, int64_t N, hipStream_t st) {
   const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((N + 255) / 256, 4096));
   hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, st, y, v, N);

@@ -3,6 +3,7 @@
 // envelopes, extraction maps (Section 3, Eq. RAS); nested P1 coarse space and
 // Galerkin maps (Section 3.1).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 #include <queue>
@@ -21,6 +22,7 @@ void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,
   for (int64_t i = 0; i < 2 * n; ++i)
     if (!std::isfinite(xy[i])) fail(SEIRD_ERR_MESH, "nonfinite node coordinate");
   std::vector<double> K(nt * 6);  // Kaa, Kbb, Kcc, Kab, Kac, Kbc
+  std::vector<double> areas(nt);
   m.mass.assign(n, 0.0);
   std::vector<int32_t> deg(n, 0);
   for (int64_t t = 0; t < nt; ++t) {
@@ -37,6 +39,7 @@ void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,
     if (!(std::fabs(det) > 1e-14 * scale) || !std::isfinite(det))
       fail(SEIRD_ERR_MESH, "triangle " + std::to_string(t) + " has zero area");
     const double area = 0.5 * std::fabs(det);
+    areas[t] = area;
     // grad phi_k = (y_{k+1} - y_{k+2}, x_{k+2} - x_{k+1}) / det
     const double gx[3] = {(y1 - y2) / det, (y2 - y0) / det, (y0 - y1) / det};
     const double gy[3] = {(x2 - x1) / det, (x0 - x2) / det, (x1 - x0) / det};
@@ -82,6 +85,63 @@ void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,
   m.tslot.resize(m.col.size());
   for (int64_t i = 0; i < n; ++i)
     for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) m.tslot[s] = slot_of(m.col[s], (int32_t)i);
+  // consistent mass: the element matrix |T|/12 (1 + delta_kl), the
+  // off-diagonal part summed into the slots of the node graph
+  m.cmass_d.assign(n, 0.0);
+  m.cmass_o.assign(m.col.size(), 0.0);
+  // boundary edges: an edge (a, b) seen in one triangle only
+  std::vector<std::array<int64_t, 3>> edges;  // (min, max, triangle)
+  edges.reserve(3 * nt);
+  for (int64_t t = 0; t < nt; ++t) {
+    const int32_t v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+    for (int k = 0; k < 3; ++k) {
+      const int32_t a = v[k], b = v[(k + 1) % 3];
+      m.cmass_d[a] += areas[t] / 6.0;
+      m.cmass_o[slot_of(a, b)] += areas[t] / 12.0;
+      m.cmass_o[slot_of(b, a)] += areas[t] / 12.0;
+      edges.push_back({std::min(a, b), std::max(a, b), t});
+    }
+  }
+  std::sort(edges.begin(), edges.end());
+  std::vector<std::array<int64_t, 3>> bnd;  // boundary edges (a, b, third vertex)
+  for (size_t k = 0; k < edges.size();) {
+    size_t e = k + 1;
+    while (e < edges.size() && edges[e][0] == edges[k][0] && edges[e][1] == edges[k][1]) ++e;
+    if (e - k == 1) {
+      const int64_t t = edges[k][2];
+      int32_t third = tri[3 * t];
+      for (int q = 0; q < 3; ++q)
+        if (tri[3 * t + q] != edges[k][0] && tri[3 * t + q] != edges[k][1]) third = tri[3 * t + q];
+      bnd.push_back({edges[k][0], edges[k][1], third});
+    }
+    k = e;
+  }
+  m.bnd_ptr.assign(n + 1, 0);
+  for (const auto &b : bnd) {
+    m.bnd_ptr[b[0] + 1]++;
+    m.bnd_ptr[b[1] + 1]++;
+  }
+  for (int64_t i = 0; i < n; ++i) m.bnd_ptr[i + 1] += m.bnd_ptr[i];
+  m.bnd_j.assign(m.bnd_ptr[n], 0);
+  m.bnd_nl.assign(2 * m.bnd_ptr[n], 0.0);
+  {
+    std::vector<int64_t> f(m.bnd_ptr.begin(), m.bnd_ptr.end() - 1);
+    for (const auto &b : bnd) {
+      const double dx = xy[2 * b[1]] - xy[2 * b[0]], dy = xy[2 * b[1] + 1] - xy[2 * b[0] + 1];
+      double nx = dy, ny = -dx;  // |(nx, ny)| = edge length
+      const double ox = xy[2 * b[0]] - xy[2 * b[2]], oy = xy[2 * b[0] + 1] - xy[2 * b[2] + 1];
+      if (ox * nx + oy * ny < 0) {  // point away from the third vertex
+        nx = -nx;
+        ny = -ny;
+      }
+      for (int side = 0; side < 2; ++side) {
+        const int64_t i = b[side], r = f[i]++;
+        m.bnd_j[r] = (int32_t)b[1 - side];
+        m.bnd_nl[2 * r] = nx;
+        m.bnd_nl[2 * r + 1] = ny;
+      }
+    }
+  }
   // incidence records grouped by node
   m.inc_ptr.assign(n + 1, 0);
   for (int64_t i = 0; i < n; ++i) m.inc_ptr[i + 1] = m.inc_ptr[i] + deg[i] / 2;
@@ -541,6 +601,49 @@ void build_precond(const MeshHost &m, const seird_schwarz_opts &o, const int32_t
     }
     if (!rw.empty()) ph.gal_ptr.push_back((int64_t)ph.gal_ref.size());
     std::vector<Contrib>().swap(rows[I]);
+  }
+  // coarse graph over positions (sorted neighbour lists), node points and
+  // owners: the owner of coarse node I is the subdomain of the fine node
+  // with the largest weight in column I of Z (the node itself when nested)
+  {
+    std::vector<std::vector<int32_t>> nb(nc);
+    for (int64_t I = 0; I < nc; ++I)
+      for (int64_t k = cptr[I]; k < cptr[I + 1]; ++k)
+        if (cadj[k] != I) nb[ph.c_perm[I]].push_back(ph.c_perm[cadj[k]]);
+    ph.cg_rowptr.assign(nc + 1, 0);
+    ph.cg_xy.assign(2 * (size_t)nc, 0.0);
+    ph.cg_owner.assign(nc, 0);
+    for (int64_t p = 0; p < nc; ++p) {
+      std::sort(nb[p].begin(), nb[p].end());
+      ph.cg_col.insert(ph.cg_col.end(), nb[p].begin(), nb[p].end());
+      ph.cg_rowptr[p + 1] = (int64_t)ph.cg_col.size();
+    }
+    for (int64_t I = 0; I < nc; ++I) {
+      const int32_t p = ph.c_perm[I];
+      ph.cg_xy[2 * (size_t)p] = cpts[2 * I];
+      ph.cg_xy[2 * (size_t)p + 1] = cpts[2 * I + 1];
+      double wbest = -1.0;
+      int32_t abest = -1;
+      for (int64_t k = ph.zt_ptr[I]; k < ph.zt_ptr[I + 1]; ++k)
+        if (ph.zt_val[k] > wbest) {
+          wbest = ph.zt_val[k];
+          abest = ph.zt_col[k];
+        }
+      if (abest < 0) fail(SEIRD_ERR_ARG, "coarse node with an empty interpolation column");
+      ph.cg_owner[p] = part[abest];
+    }
+    ph.gal_dst.resize(ph.gal_p.size());
+    for (size_t k = 0; k < ph.gal_p.size(); ++k) {
+      const int32_t p = ph.gal_p[k], q = ph.gal_q[k];
+      if (p == q) {
+        ph.gal_dst[k] = -p - 1;
+        continue;
+      }
+      const auto b = ph.cg_col.begin() + ph.cg_rowptr[p], e = ph.cg_col.begin() + ph.cg_rowptr[p + 1];
+      const auto it = std::lower_bound(b, e, q);
+      if (it == e || *it != q) fail(SEIRD_ERR_ARG, "internal: Galerkin block outside the coarse graph");
+      ph.gal_dst[k] = (int32_t)(it - ph.cg_col.begin());
+    }
   }
 }
 

@@ -128,3 +128,39 @@ def test_coarse_block_sweep_agrees_with_band_sweeps(block):
         assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b), (block, k)
     with pytest.raises(sk.SeirdError):
         pc.set_coarse_block(1)  # below the coarse band width
+
+
+def test_autotuner_cache_returns_the_kept_choice(tmp_path, monkeypatch):
+    """A second autotune of the same shape comes from the cache (no
+    candidate timed) with the same choice; the cache file written through
+    SEIRD_TUNE_CACHE holds the key; clearing the cache times again."""
+    import seird_inputs as si
+    monkeypatch.setenv("SEIRD_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    sk.tune_cache_clear()
+    cfg = si.config_small(nx=32)
+    prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+    vals = prob.jacobian(torch.tensor(cfg.u0, device="cuda"), cfg.dt)
+    a = sk.autotune(prob, cfg.part, cfg.n_sub, cfg.overlap, vals, reps=2)
+    b = sk.autotune(prob, cfg.part, cfg.n_sub, cfg.overlap, vals, reps=2)
+    assert not a["from_cache"] and b["from_cache"]
+    assert (a["tile"], a["solve_threads"]) == (b["tile"], b["solve_threads"])
+    assert len(b["candidates"]) == 0
+    sk.tune_cache_clear()
+    c = sk.autotune(prob, cfg.part, cfg.n_sub, cfg.overlap, vals, reps=2)
+    assert not c["from_cache"] and len(c["candidates"]) > 0
+    sk.tune_cache_clear()
+
+
+def test_batch_autotune_on_the_ensemble():
+    import seird_inputs as si
+    sk.tune_cache_clear()
+    bc = si.config_batch(n_inst=3, n_min=2000, n_max=6000, nodes_per_sub=500)
+    b = sk.Batch([(c.xy, c.tri, c.params, c.part, c.n_sub) for c in bc.instances], overlap=bc.overlap)
+    u = torch.tensor(np.concatenate([c.u0 for c in bc.instances]), device="cuda")
+    b.step(u, bc.dt, tol=1e-10)
+    t = b.autotune(reps=2)
+    assert t["solve_threads"] in (256, 512, 1024) and len(t["candidates"]) == 3
+    assert b.autotune(reps=2)["from_cache"]
+    per = b.step(u, bc.dt, tol=1e-10)
+    assert all(p["res_hist"][-1] <= 1e-10 for p in per)
+    sk.tune_cache_clear()
