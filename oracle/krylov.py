@@ -15,6 +15,10 @@ TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
   pre-smooth with RAS, coarse correction Q = Z A_c^{-1} Z^T with the Galerkin
   coarse matrix A_c = Z^T A Z (Section 3.1), post-smooth with RAS.  Z is the
   P1 interpolation from a nested coarse grid, applied to each compartment.
+* ``TwoLevelKrylov`` -- the same recurrence with the coarse system solved by
+  GMRES preconditioned with RAS on the coarse graph ("Two-grid RAS - V2",
+  Section 3.2), the outer solver being the flexible GMRES above (it keeps
+  the preconditioned vectors).
 """
 from __future__ import annotations
 
@@ -223,3 +227,70 @@ def make_linsolve(geo, part, n_sub, overlap, coarse=None, restart=30,
         return x, info
 
     return solve
+
+
+def coarse_graph(Znodes: sp.csr_matrix, G: sp.csr_matrix) -> sp.csr_matrix:
+    """Node graph of the Galerkin coarse matrix, including the diagonal (as
+    ``fem.node_graph``): coarse nodes I and J are coupled when some fine a
+    with Z_aI != 0 and b in {a} U adj(a) with Z_bJ != 0 exist, i.e. the
+    pattern of Z^T (G + I) Z."""
+    n = G.shape[0]
+    Gi = (G + sp.identity(n, format="csr")).tocsr()
+    Gi.data[:] = 1.0
+    Zp = Znodes.copy().tocsr()
+    Zp.data[:] = 1.0
+    C = (Zp.T @ Gi @ Zp).tocsr()
+    C.data[:] = 1.0
+    return C
+
+
+def coarse_partition(Znodes: sp.csr_matrix, part: np.ndarray, n_sub: int,
+                     n_groups: int = 0) -> np.ndarray:
+    """Coarse subdomain of every coarse node: the subdomain of the fine node
+    with the largest interpolation weight in its column of Z (on a nested
+    grid, the coarse node's own fine node; the lowest such fine index on a
+    tie); with n_groups > 0 the fine subdomains s are merged into groups
+    s * n_groups // n_sub.  Group numbers are then renumbered over the
+    non-empty groups in increasing order."""
+    Zc = Znodes.tocsc()
+    owner = np.empty(Zc.shape[1], dtype=np.int64)
+    for I in range(Zc.shape[1]):
+        rows = Zc.indices[Zc.indptr[I]:Zc.indptr[I + 1]]
+        vals = Zc.data[Zc.indptr[I]:Zc.indptr[I + 1]]
+        order = np.lexsort((rows, -vals))  # largest weight, then lowest index
+        owner[I] = part[rows[order[0]]]
+    if n_groups > 0:
+        owner = owner * n_groups // n_sub
+    used = np.unique(owner)
+    return np.searchsorted(used, owner), len(used)
+
+
+class TwoLevelKrylov(TwoLevel):
+    """Two-grid RAS with the coarse system A_c x = Z^T r solved by GMRES
+    (x0 = 0, right preconditioning, restart, rtol/atol, max_it) with
+    one-level RAS on the coarse graph; the coarse subdomains are those of
+    ``coarse_partition`` grown by ``overlap`` coarse-graph layers.  ``infos``
+    collects the inner solves' reports."""
+
+    def __init__(self, A, ras: RAS, Znodes: sp.csr_matrix, G: sp.csr_matrix,
+                 part: np.ndarray, n_sub: int, n_groups: int = 0, overlap: int = 1,
+                 restart: int = 30, max_it: int = 100, rtol: float = 1e-5,
+                 atol: float = 1e-50):
+        self.A = A.tocsr()
+        self.ras = ras
+        self.Z = sp.kron(Znodes, sp.identity(NC), format="csr")
+        self.Ac = (self.Z.T @ self.A @ self.Z).tocsr()
+        cpart, nsc = coarse_partition(Znodes, part, n_sub, n_groups)
+        self.ras_c = RAS(self.Ac, coarse_graph(Znodes, G), cpart, nsc, overlap)
+        self.n_coarse_sub = nsc
+        self.kw = dict(restart=restart, max_it=max_it, rtol=rtol, atol=atol, dtol=np.inf)
+        self.infos = []
+
+    def coarse(self, r):
+        rc = self.Z.T @ r
+        xc, info = gmres(lambda v: self.Ac @ v, rc, self.ras_c.apply, **self.kw)
+        self.infos.append(info)
+        return self.Z @ xc
+
+    def coarse_T(self, r):
+        raise NotImplementedError("the Krylov coarse solve has no transposed form")

@@ -251,3 +251,104 @@ def test_scalar_ras_pins():
     ras = krylov.RAS(Ad, G, cfg.part, cfg.n_sub, 2, bs=1)
     assert np.linalg.norm(ras.apply(b) - xd) <= 1e-12 * np.linalg.norm(xd)
     assert np.linalg.norm(_asm_apply(ras, b) - xd) >= 1e-3 * np.linalg.norm(xd)
+
+
+# ---------------------------------------------------------------------------
+# Two-grid RAS-V2 (Section 3.2): coarse system solved by GMRES + coarse RAS
+# ---------------------------------------------------------------------------
+def _krylov_pieces(**kw):
+    cfg = si.config_nested_square(n_base=4, n_ref=2, n_sub=16)
+    geo = fem.Geometry(cfg.xy, cfg.tri)
+    J = fem.jacobian(cfg.u0, 10.0, geo, cfg.params)
+    G = fem.node_graph(geo)
+    ras = krylov.RAS(J, G, cfg.part, cfg.n_sub, cfg.overlap)
+    Zn = krylov.nested_interpolation(cfg.coarse_parents, cfg.coarse_n)
+    tl = krylov.TwoLevel(J, ras, Zn)
+    tk = krylov.TwoLevelKrylov(J, ras, Zn, G, cfg.part, cfg.n_sub, **kw)
+    return cfg, J, Zn, G, tl, tk
+
+
+def test_krylov_coarse_graph_is_the_coarse_triangulation():
+    """On a nested grid the Galerkin coarse matrix couples exactly the
+    coarse nodes joined by an edge of the coarse triangulation (a coarse hat
+    function's support is its coarse star)."""
+    nm = si.nested_square_mesh(4, 2)
+    xy_c, tri_c = nm.levels[0]
+    Zn = krylov.nested_interpolation(nm.parents[1:], len(xy_c))
+    G = fem.node_graph(fem.Geometry(*nm.levels[-1]))
+    C = krylov.coarse_graph(Zn, G)
+    edges = set()
+    for t in tri_c:
+        for a, b in ((0, 1), (1, 2), (2, 0)):
+            edges.add((min(t[a], t[b]), max(t[a], t[b])))
+    Cu = sp.triu(C, 1).tocoo()
+    assert set(zip(Cu.row.tolist(), Cu.col.tolist())) == edges
+
+
+def test_krylov_coarse_partition_follows_the_coarse_nodes_own_fine_nodes():
+    cfg, J, Zn, G, tl, tk = _krylov_pieces()
+    cpart, nsc = krylov.coarse_partition(Zn, cfg.part, cfg.n_sub)
+    Zc = Zn.tocsc()
+    owners = []
+    for I in range(Zn.shape[1]):
+        col = Zc[:, I].toarray().ravel()
+        own = np.nonzero(col == 1.0)[0]
+        assert len(own) == 1          # the coarse node itself, on a nested grid
+        owners.append(cfg.part[own[0]])
+    used = sorted(set(owners))
+    assert nsc == len(used)
+    assert np.array_equal(cpart, [used.index(o) for o in owners])
+    # merged groups: consecutive fine subdomain numbers
+    cpart2, nsc2 = krylov.coarse_partition(Zn, cfg.part, cfg.n_sub, n_groups=4)
+    assert nsc2 <= 4
+    g = [o * 4 // cfg.n_sub for o in owners]
+    assert np.array_equal(cpart2, np.searchsorted(sorted(set(g)), g))
+
+
+def test_krylov_coarse_with_an_exact_inner_solve_is_the_two_grid_operator():
+    """With the inner GMRES run to a tolerance near rounding, V2 applies the
+    same operator as the direct coarse solve (pinned above against the
+    three-step recurrence)."""
+    cfg, J, Zn, G, tl, tk = _krylov_pieces(rtol=1e-15, atol=0.0, max_it=1000)
+    r = np.random.default_rng(11).standard_normal(J.shape[0])
+    a, b = tk.apply(r), tl.apply(r)
+    assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b)
+    assert all(i["reason"] == "converged" for i in tk.infos)
+
+
+def test_krylov_coarse_one_inner_iteration_has_its_closed_form():
+    """One inner GMRES iteration from x0 = 0 returns alpha M_c r_c with
+    alpha = <r_c, w> / <w, w>, w = A_c M_c r_c (the minimiser of the
+    residual over span{M_c r_c}), M_c the coarse RAS."""
+    cfg, J, Zn, G, tl, tk = _krylov_pieces(rtol=0.0, atol=0.0, max_it=1)
+    r = np.random.default_rng(12).standard_normal(J.shape[0])
+    rc = tk.Z.T @ r
+    m = tk.ras_c.apply(rc)
+    w = tk.Ac @ m
+    alpha = np.dot(rc, w) / np.dot(w, w)
+    got = tk.coarse(r)
+    want = tk.Z @ (alpha * m)
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    assert tk.infos[-1]["its"] == 1
+
+
+def test_krylov_coarse_ras_is_restricted_on_the_coarse_graph():
+    """The coarse RAS restricts with Boolean D_i: on a coarse matrix whose
+    owner-to-owner couplings between subdomains are removed it is the exact
+    inverse (as the fine-level pin above), which an additive (ASM) sum of
+    the overlapping copies is not."""
+    cfg, J, Zn, G, tl, tk = _krylov_pieces()
+    cpart, nsc = krylov.coarse_partition(Zn, cfg.part, cfg.n_sub)
+    Cg = krylov.coarse_graph(Zn, G)
+    Ac = tk.Ac.tocoo()
+    node_r, node_c = Ac.row // krylov.NC, Ac.col // krylov.NC
+    keep = cpart[node_r] == cpart[node_c]
+    Ad = sp.coo_matrix((Ac.data[keep], (Ac.row[keep], Ac.col[keep])), shape=Ac.shape).tocsr()
+    ras_c = krylov.RAS(Ad, Cg, cpart, nsc, 1)
+    b = np.random.default_rng(13).standard_normal(Ad.shape[0])
+    x = spla.spsolve(Ad.tocsc(), b)
+    assert np.linalg.norm(ras_c.apply(b) - x) <= 1e-10 * np.linalg.norm(x)
+    asm = np.zeros_like(b)
+    for idx, own, lu in ras_c.subs:
+        asm[idx] += lu.solve(b[idx])
+    assert np.linalg.norm(asm - x) > 1e-3 * np.linalg.norm(x)
