@@ -452,6 +452,65 @@ def spmv_roofline(sk, torch, prob, u, dt, reps=50):
             "traffic": None}
 
 
+def precond_variants_bench(sk, torch, args, cfg, coarse, direct):
+    """The preconditioner variants of Section 3.2 on the realistic workload,
+    beside the direct two-grid RAS of the headline (``direct``: its steps/s
+    and GMRES counts): two-grid RAS-V2 (coarse system by inner GMRES(30),
+    rtol 1e-5, at most 100 iterations, preconditioned by RAS on the coarse
+    graph with the fine partition's coarse shares, overlap 1; flexible outer
+    GMRES) and one-level RAS (outer cap 200).  Each starts from the initial
+    state after one untimed step, as the headline does."""
+    out = {}
+    kw = dict(tol=cfg.newton_tol, max_it=cfg.newton_max_it, restart=cfg.gmres_restart,
+              rtol=cfg.gmres_rtol, atol=cfg.gmres_atol, dtol=cfg.gmres_dtol, pc_reuse=args.pc_reuse,
+              gmres_max_it=200)
+    tile, threads = args.tuned.get(0, (32, 256))
+    for name in ("two_grid_v2", "one_level"):
+        steps = args.variant_steps if name == "two_grid_v2" else 1
+        prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+        pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, tile=tile, solve_threads=threads,
+                        coarse=coarse if name == "two_grid_v2" else None)
+        if name == "two_grid_v2":
+            pc.set_coarse_krylov(n_sub=0, overlap=1, restart=30, max_it=100, rtol=1e-5)
+        u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
+        st = sk.step(prob, pc, u, cfg.dt, **kw)
+        log(f"[bench] {name} warmup: newton {st['newton_its']} gmres {st['gmres_its']}")
+        if name == "two_grid_v2":
+            pc.coarse_krylov_stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for k in range(steps):
+            st = sk.step(prob, pc, u, cfg.dt, **kw)
+            stats.append(st)
+            log(f"[bench] {name} step {k}: newton {st['newton_its']} gmres {st['gmres_its']} "
+                f"setup/gmres ms {st['t_setup_ms']:.0f}/{st['t_gmres_ms']:.0f}")
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        its = [g for s in stats for g in s["gmres_its"]]
+        rec = {"steps": steps, "steps_per_s": steps / sec, "ms_per_step": 1e3 * sec / steps,
+               "vs_direct_two_grid": (steps / sec) / direct["value"],
+               "newton_its": [s["newton_its"] for s in stats],
+               "gmres_its": [s["gmres_its"] for s in stats],
+               "mean_gmres_its_per_newton": sum(its) / max(1, len(its)),
+               "inexact_solves": sum(s.get("inexact_solves", 0) for s in stats),
+               "phase_ms_per_step": {k: sum(s[k] for s in stats) / len(stats)
+                                     for k in ("t_setup_ms", "t_gmres_ms")}}
+        if name == "two_grid_v2":
+            ks = pc.coarse_krylov_stats()
+            rec["inner"] = {"solves": ks["solves"], "mean_its": ks["its"] / max(1, ks["solves"]),
+                            "max_its": ks["its_max"], "capped_at_100": ks["unconverged"],
+                            "coarse_subdomains": ks["coarse_subdomains"]}
+        out[name] = rec
+        del pc, prob, u
+        torch.cuda.empty_cache()
+    out["two_grid_direct"] = {"steps_per_s": direct["value"],
+                              "mean_gmres_its_per_newton": direct["mean_its"]}
+    out["workload"] = (f"{cfg.name}: the headline workload and tolerances; Section 3.2 variants "
+                       f"(Table 2 of Section 4.1 compares the same four on a unit square)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -485,6 +544,8 @@ def main():
                          "added after the timed ones to reach it)")
     ap.add_argument("--pgs-steps", type=int, default=3,
                     help="timed steps of the Picard-Gauss-Seidel leg (0: skip)")
+    ap.add_argument("--variant-steps", type=int, default=2,
+                    help="timed steps of the two-grid RAS-V2 leg (one-level RAS runs one step; 0: skip both)")
     ap.add_argument("--pgs-tol", type=float, default=1e-10,
                     help="epsilon tolerance of the Picard-Gauss-Seidel sweeps")
     ap.add_argument("--cpu-workers", type=int, default=16,
@@ -585,6 +646,10 @@ def main():
         log("[bench] precision legs on the nested instance against the oracle's step-30 state")
         mixed["vs_oracle_nested"] = oracle_precision_leg(sk, torch, args)
         out["mixed"] = mixed
+    if args.variant_steps > 0 and coarse is not None:
+        its = [g for st in stats for g in st["gmres_its"]]
+        out["precond_variants"] = precond_variants_bench(
+            sk, torch, args, cfg, coarse, {"value": value, "mean_its": sum(its) / max(1, len(its))})
     if args.pgs_steps > 0:
         out["pgs"] = pgs_bench(sk, torch, args, cfg)
         out["pgs"]["vs_newton"] = out["pgs"]["value"] / value

@@ -396,7 +396,8 @@ typedef struct {
 } seird_precond_perf_report;
 seird_status seird_precond_perf(seird_precond pc, seird_precond_perf_report *r,
                                 int reset);
-/* Coarse solver of a two-level preconditioner.  1: the inverses of the
+/* Coarse solver of a two-level preconditioner.  2: the Krylov coarse solver
+ * of seird_precond_set_coarse_krylov (once that has been called).  1: the inverses of the
  * diagonal super-blocks of the coarse factors, X_II = L_II^{-1} and
  * W_II = U_II^{-1}, are formed at every setup (FP64 MFMA, on the coarse
  * stream) and A_c^{-1} r is a block forward/backward sweep: per block a
@@ -404,9 +405,50 @@ seird_status seird_precond_perf(seird_precond pc, seird_precond_perf_report *r,
  * neighbouring block (see seird_precond_set_coarse_block); the default with
  * tile 32 when the storage fits 16 GB (nt(nt+1) tiles of 8 KB for nt coarse
  * tile rows, whatever the block size).  0: the band forward/backward sweeps
- * over the factors (one workgroup).  Results agree to rounding.
- * SEIRD_ERR_ARG for 1 without inverses. */
+ * over the factors (one workgroup).  Results of 0 and 1 agree to rounding.
+ * SEIRD_ERR_ARG for 1 without inverses or 2 without a Krylov coarse solver. */
 seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver);
+/* Two-grid RAS-V2 (Section 3.2, compared with the direct coarse solve in
+ * Table 2 of Section 4.1): the coarse system A_c x_c = Z^T r is solved by an
+ * inner GMRES (x0 = 0, right preconditioning) with one-level RAS on the
+ * coarse graph, instead of the coarse factorisation.  A_c is the Galerkin
+ * matrix Z^T A Z held as dense 5x5 node blocks of the coarse graph.  Coarse
+ * subdomains: each coarse node belongs to the fine subdomain that owns the
+ * fine node carrying its largest interpolation weight (its own node on a
+ * nested grid), so the coarse problem is split like the fine one; n_sub > 0
+ * merges fine subdomains s into groups s * n_sub / n_fine first.  Empty
+ * groups are dropped; each group grows by `overlap` layers of the coarse
+ * graph.  Inner stopping: ||r|| < max(rtol ||b||, atol) or max_it
+ * iterations (restart inner restart); a capped inner solve returns its
+ * iterate and is counted.  The outer GMRES keeps its preconditioned
+ * vectors (x = x0 + Z y), which is the flexible form (FGMRES) that a
+ * preconditioner changing from one application to the next requires.
+ * Allocates the coarse graph problem, its RAS and Krylov basis (device
+ * memory) and selects coarse solver 2; the coarse data are formed by the
+ * next seird_precond_setup.  Two-level preconditioners only; no transposed
+ * form (SEIRD_ERR_ARG from a transposed apply).  Switching between the
+ * direct solvers (0, 1) and 2 takes effect at the next setup (an apply in
+ * between returns SEIRD_ERR_ARG). */
+typedef struct {
+  int32_t n_sub;    /* 0: one coarse subdomain per fine subdomain with coarse nodes */
+  int32_t overlap;  /* layers of coarse-graph neighbours (1: minimal overlap) */
+  int32_t restart;  /* inner GMRES restart, 1..31 */
+  int32_t max_it;   /* inner iteration cap (100 in Section 3.2) */
+  double rtol, atol;
+} seird_coarse_krylov_opts;
+seird_status seird_precond_set_coarse_krylov(seird_precond pc,
+                                             const seird_coarse_krylov_opts *o);
+typedef struct {
+  int64_t solves;       /* inner solves since the last reset */
+  int64_t its;          /* their iterations, summed */
+  int64_t its_max;
+  int64_t unconverged;  /* stopped by the cap (or the divergence test) */
+  int32_t coarse_subdomains;
+  int64_t coarse_local_unknowns;  /* summed over the coarse subdomains */
+} seird_coarse_krylov_stats;
+seird_status seird_precond_coarse_krylov_stats(seird_precond pc,
+                                               seird_coarse_krylov_stats *s,
+                                               int reset);
 /* Super-block size of the coarse inverses, in coarse tile rows (takes effect
  * at the next seird_precond_setup).  0: one block, the full inverses
  * X = L^{-1}, W = U^{-1} (the solve is two triangular mat-vecs).  Smaller

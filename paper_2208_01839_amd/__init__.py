@@ -90,6 +90,17 @@ class _PerfReport(ctypes.Structure):
                 ("setups", ctypes.c_int32), ("t_extract_ms", ctypes.c_double), ("t_lu_ms", ctypes.c_double)]
 
 
+class _CoarseKrylovOpts(ctypes.Structure):
+    _fields_ = [("n_sub", ctypes.c_int32), ("overlap", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("max_it", ctypes.c_int32), ("rtol", ctypes.c_double), ("atol", ctypes.c_double)]
+
+
+class _CoarseKrylovStats(ctypes.Structure):
+    _fields_ = [("solves", ctypes.c_int64), ("its", ctypes.c_int64), ("its_max", ctypes.c_int64),
+                ("unconverged", ctypes.c_int64), ("coarse_subdomains", ctypes.c_int32),
+                ("coarse_local_unknowns", ctypes.c_int64)]
+
+
 MAX_PGS = 64
 
 
@@ -174,6 +185,8 @@ _SIGS = {
     "seird_precond_set_solve_threads": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_precond_set_coarse_solver": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_precond_set_coarse_block": ([_P, ctypes.c_int32], ctypes.c_int),
+    "seird_precond_set_coarse_krylov": ([_P, ctypes.POINTER(_CoarseKrylovOpts)], ctypes.c_int),
+    "seird_precond_coarse_krylov_stats": ([_P, ctypes.POINTER(_CoarseKrylovStats), ctypes.c_int], ctypes.c_int),
     "seird_autotune_schwarz": ([_P, ctypes.POINTER(_Schwarz), _P, _P, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.POINTER(_TuneReport), _P], ctypes.c_int),
     "seird_tune_cache_clear": ([], ctypes.c_int),
@@ -602,8 +615,21 @@ class Precond:
 
     def set_coarse_solver(self, solver):
         """1: block sweep over inverted diagonal super-blocks of the coarse
-        factors; 0: band sweeps."""
+        factors; 0: band sweeps; 2: the Krylov coarse solver (after
+        set_coarse_krylov)."""
         _check(lib().seird_precond_set_coarse_solver(self.h, int(solver)))
+
+    def set_coarse_krylov(self, n_sub=0, overlap=1, restart=30, max_it=100, rtol=1e-5, atol=1e-50):
+        """Two-grid RAS-V2: the coarse system solved by inner GMRES with RAS
+        on the coarse graph (selects coarse solver 2; set up again before
+        applying)."""
+        o = _CoarseKrylovOpts(int(n_sub), int(overlap), int(restart), int(max_it), float(rtol), float(atol))
+        _check(lib().seird_precond_set_coarse_krylov(self.h, ctypes.byref(o)))
+
+    def coarse_krylov_stats(self, reset=False):
+        r = _CoarseKrylovStats()
+        _check(lib().seird_precond_coarse_krylov_stats(self.h, ctypes.byref(r), int(bool(reset))))
+        return {k: getattr(r, k) for k, _ in _CoarseKrylovStats._fields_}
 
     def set_coarse_block(self, tiles):
         """Super-block size of the coarse inverses in tile rows (0: full

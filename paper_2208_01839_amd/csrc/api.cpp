@@ -369,9 +369,27 @@ constexpr int COARSE_BLOCK = 128;
 static inline double coarse_inverse_bytes(int64_t nt) { return 2.0 * (double)(nt * (nt + 1) / 2) * 1024 * 8; }
 constexpr double COARSE_INVERSE_BUDGET = 16.0e9;
 
+// Two-grid RAS-V2 (Section 3.2): the coarse system solved by an inner
+// GMRES preconditioned with one-level RAS on the coarse graph
+struct KrylovCoarse {
+  seird_problem cp = nullptr;   // the coarse graph as a problem: vectors, Krylov basis, segment views
+  seird_precond cpc = nullptr;  // RAS on the coarse graph (dense off-diagonal blocks)
+  double *cvals = nullptr;      // Galerkin coarse matrix: diag [nc][25], then off [slots][25]
+  int32_t *gdst = nullptr;      // Galerkin block -> diagonal block or slot
+  seird_krylov_opts ko{};
+  int64_t solves = 0, its = 0, its_max = 0, unconverged = 0;
+};
+static void krylov_coarse_solve(seird_precond pc, const double *rc, double *xc, hipStream_t st);
+static void krylov_coarse_free(KrylovCoarse *kc);
+
 struct seird_precond_s {
   seird_problem prob = nullptr;
   PrecondHost ph;
+  bool dense_off = false;      // a coarse-graph RAS: dense off-diagonal node blocks (off [slots][25])
+  KrylovCoarse *kc = nullptr;  // coarse_solver 2
+  // coarse system prepared by the last setup: -1 none, 0 direct factors
+  // (coarse_solver 0 or 1), 2 the Krylov coarse solver's matrix and RAS
+  int coarse_prepared = -1;
   void *ws_base = nullptr;   // caller workspace holding its device arrays, if any
   int64_t nvec = 0;          // length of the vectors it applies to (bs * n_nodes)
   void *Fs = nullptr;        // subdomain factors as factorised (float64, or float32)
@@ -510,6 +528,7 @@ struct seird_precond_s {
 
   ~seird_precond_s() {
     clear_graphs();
+    krylov_coarse_free(kc);
     if (st_capture) (void)hipStreamDestroy(st_capture);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -602,7 +621,15 @@ struct seird_precond_s {
 
   // z += Z A_c^{-1} Z^T r  (or the transposed coarse operator)
   void coarse_add(const double *r, double *z, int transpose, hipStream_t st) {
+    if ((coarse_solver == 2) != (coarse_prepared == 2))
+      fail(SEIRD_ERR_ARG, "coarse solver changed between direct and Krylov since the last setup");
+    if (coarse_solver == 2 && transpose) fail(SEIRD_ERR_ARG, "the Krylov coarse solver has no transposed form");
     launch_coarse_restrict(zt_ptr, zt_col, zt_val, cperm, r, rc, ph.nc, st);
+    if (coarse_solver == 2) {
+      krylov_coarse_solve(this, rc, xc, st);
+      launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
+      return;
+    }
     if (coarse_solver == 1) {
       launch_coarse_inverse_apply(Xc, Wc, Fc, ph.coarse, coarse_block, rc, xc, cscratch, transpose, st);
       launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
@@ -790,7 +817,7 @@ static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, do
       };
       // (graphs only for a single instance: a batch's launches depend on
       // which instances are still running)
-      if (pc && o.graphs && !pc->timing && S == 1)
+      if (pc && o.graphs && !pc->timing && S == 1 && pc->coarse_solver != 2)
         pc->run_graph({P, V, Zb, vals, j, transpose, S > 1, pc->coarse_solver, pc->coarse_block, pc->solve_threads},
                       step_launches, st);
       else
@@ -1664,8 +1691,9 @@ seird_status seird_precond_timing(seird_precond pc, int enable) {
 seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver) {
   API_BEGIN
   if (!pc) fail(SEIRD_ERR_ARG, "null preconditioner");
-  if (solver != 0 && solver != 1) fail(SEIRD_ERR_ARG, "coarse solver must be 0 or 1");
+  if (solver < 0 || solver > 2) fail(SEIRD_ERR_ARG, "coarse solver must be 0, 1 or 2");
   if (solver == 1 && !pc->Xc) fail(SEIRD_ERR_ARG, "no coarse inverses for this preconditioner");
+  if (solver == 2 && !pc->kc) fail(SEIRD_ERR_ARG, "no Krylov coarse solver (seird_precond_set_coarse_krylov)");
   pc->coarse_solver = solver;
   pc->clear_graphs();
   API_END
@@ -1761,7 +1789,9 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
   fl.status = pc->status;
   fl.queue = pc->status + 1;  // the int after the status flag
   fl.n_cu = P_ncu(pc);
-  if (ph.two_level) {
+  fl.dense_off = pc->dense_off;
+  const bool krylov_coarse = ph.two_level && pc->coarse_solver == 2;
+  if (ph.two_level && !krylov_coarse) {
     fl.coarse = true;
     fl.cs = ph.coarse;
     fl.coarse_dev = pc->coarse_dev;
@@ -1779,7 +1809,7 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
     fl.ev_lu = pc->ev_set[1];
     fl.ev_lu_end = pc->ev_set[2];
   }
-  if (ph.two_level) {
+  if (ph.two_level && !krylov_coarse) {
     // fork: the coarse chain waits for everything already queued on st
     HIPCHECK(hipEventRecord(pc->ev_fork, st));
     HIPCHECK(hipStreamWaitEvent(pc->st_coarse, pc->ev_fork, 0));
@@ -1795,6 +1825,16 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
     launch_setup_factors(fl, diag, off, st, st);
   }
   HIPCHECK(hipGetLastError());
+  pc->coarse_prepared = -1;
+  if (krylov_coarse) {
+    // Galerkin coarse matrix as node blocks of the coarse graph, then the
+    // coarse RAS factors (no coarse factorisation)
+    KrylovCoarse &kc = *pc->kc;
+    const int64_t nc = ph.nc;
+    launch_galerkin_blocks(kc.gdst, pc->gptr, pc->gref, pc->gw, (int64_t)ph.gal_p.size(), diag, off, kc.cvals,
+                           kc.cvals + 25 * nc, st);
+    precond_setup_raw(kc.cpc, kc.cvals, kc.cvals + 25 * nc, st);
+  }
   if (pc->Fb) launch_convert(pc->Fb, ph.prec, pc->Fs, pc->sub_float ? 1 : 0, ph.factor_entries, st);
   int status = 0;
   HIPCHECK(hipMemcpyAsync(&status, pc->status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1808,6 +1848,7 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
     pc->set_count++;
   }
   pc->ready = true;
+  if (ph.two_level) pc->coarse_prepared = krylov_coarse ? 2 : 0;
   if (status & 2) fail(SEIRD_ERR_ARG, "internal: local matrix entry outside the stored tiles");
   if (status) fail(SEIRD_ERR_BREAKDOWN, "zero or nonfinite pivot in a local LU factorisation");
 }
@@ -1817,6 +1858,116 @@ seird_status seird_precond_setup_scalar(seird_precond pc, const double *diag, co
   if (!pc || !diag || !off) fail(SEIRD_ERR_ARG, "null argument");
   if (pc->ph.bs != 1) fail(SEIRD_ERR_ARG, "not a scalar (compartment-wise) preconditioner");
   precond_setup_raw(pc, diag, off, (hipStream_t)stream);
+  API_END
+}
+
+static void krylov_coarse_free(KrylovCoarse *kc) {
+  if (!kc) return;
+  delete kc->cpc;
+  delete kc->cp;
+  dev_free(kc->cvals);
+  dev_free(kc->gdst);
+  delete kc;
+}
+
+// inner GMRES on the coarse system, x0 = 0; an inner solve stopped by its
+// iteration cap (or by its divergence test) returns its iterate
+static void krylov_coarse_solve(seird_precond pc, const double *rc, double *xc, hipStream_t st) {
+  KrylovCoarse &kc = *pc->kc;
+  seird_problem C = kc.cp;
+  const int64_t nc = C->mh.n;
+  const double *cd = kc.cvals, *co = kc.cvals + 25 * nc;
+  GmresOps ops;
+  ops.N = 5 * nc;
+  ops.seg = &C->seg;
+  ops.seg_act = &C->seg_act;
+  ops.seg_re = &C->seg_re;
+  ops.spmv = [C, cd, co](const double *x, const double *b, double *y, hipStream_t s) {
+    launch_block_spmv(C->md.n, C->md.rowptr, C->md.col, cd, co, x, b, y, s);
+  };
+  seird_precond cpc = kc.cpc;
+  ops.prec = [cpc](const double *r, double *z, hipStream_t s, const uint8_t *, const std::vector<uint8_t> *) {
+    cpc->ras(r, z, 0, 0, s);
+  };
+  std::vector<seird_krylov_stats> stats;
+  gmres_core(C, ops, rc, xc, kc.ko, stats, std::vector<uint8_t>{1}, st, KrylovWork{});
+  kc.solves++;
+  kc.its += stats[0].its;
+  kc.its_max = std::max<int64_t>(kc.its_max, stats[0].its);
+  if (stats[0].reason < 0) kc.unconverged++;
+}
+
+seird_status seird_precond_set_coarse_krylov(seird_precond pc, const seird_coarse_krylov_opts *o) {
+  API_BEGIN
+  if (!pc || !o) fail(SEIRD_ERR_ARG, "null argument");
+  const PrecondHost &ph = pc->ph;
+  if (!ph.two_level) fail(SEIRD_ERR_ARG, "the Krylov coarse solver needs a two-level preconditioner");
+  if (o->restart < 1 || o->restart > KRYLOV_MAX - 1) fail(SEIRD_ERR_ARG, "inner restart must be in [1, 31]");
+  if (o->max_it < 1) fail(SEIRD_ERR_ARG, "inner max_it must be >= 1");
+  if (!(o->rtol >= 0.0) || !(o->atol >= 0.0)) fail(SEIRD_ERR_ARG, "inner tolerances must be >= 0");
+  if (o->n_sub < 0 || o->overlap < 0) fail(SEIRD_ERR_ARG, "bad coarse subdomain options");
+  const int64_t nc = ph.nc;
+  // coarse subdomains: the fine subdomains' shares of the coarse nodes
+  // (or n_sub groups of consecutive fine subdomain numbers), renumbered
+  // over the non-empty ones
+  const int nfine = ph.n_sub;
+  std::vector<int32_t> grp(nc);
+  for (int64_t p = 0; p < nc; ++p)
+    grp[p] = o->n_sub > 0 ? (int32_t)((int64_t)ph.cg_owner[p] * o->n_sub / nfine) : ph.cg_owner[p];
+  std::vector<int32_t> id(std::max(nfine, o->n_sub), -1);
+  for (int64_t p = 0; p < nc; ++p) id[grp[p]] = 0;
+  int nsc = 0;
+  for (auto &v : id)
+    if (v == 0) v = nsc++;
+  for (int64_t p = 0; p < nc; ++p) grp[p] = id[grp[p]];
+  MeshHost cm;
+  cm.n = nc;
+  cm.rowptr = ph.cg_rowptr;
+  cm.col = ph.cg_col;
+  cm.xy = ph.cg_xy;
+  seird_schwarz_opts co{};
+  co.n_sub = nsc;
+  co.overlap = o->overlap;
+  co.tile = ph.tile;
+  co.factor_prec = 0;
+  co.n_ref = 0;
+  auto kc = new KrylovCoarse();
+  try {
+    kc->cp = problem_create_impl(cm, seird_params{});
+    kc->cpc = precond_create_impl(kc->cp, &co, grp.data(), NC);
+    kc->cpc->dense_off = true;
+    kc->cvals = dev_alloc<double>((size_t)25 * (nc + (int64_t)ph.cg_col.size()));
+    kc->gdst = dev_upload(ph.gal_dst);
+    kc->cp->ensure_krylov(o->restart);
+    kc->ko.restart = o->restart;
+    kc->ko.max_it = o->max_it;
+    kc->ko.rtol = o->rtol;
+    kc->ko.atol = o->atol;
+    kc->ko.dtol = 1e300;
+    kc->ko.graphs = 0;
+  } catch (...) {
+    krylov_coarse_free(kc);
+    throw;
+  }
+  krylov_coarse_free(pc->kc);
+  pc->kc = kc;
+  pc->coarse_solver = 2;
+  pc->clear_graphs();
+  API_END
+}
+
+seird_status seird_precond_coarse_krylov_stats(seird_precond pc, seird_coarse_krylov_stats *s, int reset) {
+  API_BEGIN
+  if (!pc || !s) fail(SEIRD_ERR_ARG, "null argument");
+  if (!pc->kc) fail(SEIRD_ERR_ARG, "no Krylov coarse solver");
+  KrylovCoarse &kc = *pc->kc;
+  s->solves = kc.solves;
+  s->its = kc.its;
+  s->its_max = kc.its_max;
+  s->unconverged = kc.unconverged;
+  s->coarse_subdomains = kc.cpc->ph.n_sub;
+  s->coarse_local_unknowns = (int64_t)kc.cpc->ph.l2g.size();
+  if (reset) kc.solves = kc.its = kc.its_max = kc.unconverged = 0;
   API_END
 }
 
