@@ -302,6 +302,83 @@ def _rcb_leaf_order(xy, idx, leaf):
     return np.concatenate(res)
 
 
+# ---------------------------------------------------------------------------
+# 22-compartment model (Appendix C): compartments, synthetic rates, state
+# ---------------------------------------------------------------------------
+COMPARTMENTS22 = ["S", "V", "E", "Q", "A", "W", "F", "B", "C", "X", "Y", "Z", "G", "N", "H", "H1", "I",
+                  "H2", "R1", "R2", "P", "D"]
+DIFFUSING22 = ["S", "V", "E", "A", "F", "B", "C", "P", "R1", "R2"]
+
+
+@dataclasses.dataclass
+class Params22:
+    """Parameters of the 22-compartment model (names of its parameter
+    table; phi_C as in its equations).  The paper gives no values: these are
+    synthetic rates per day of a plausible size.  beta_* weigh the four
+    moving, non-isolating infectious compartments in the force of
+    infection; ``nu`` holds the diffusion coefficients of S V E A F B C P R1
+    R2 in that order."""
+    beta_A: float = 0.3
+    beta_F: float = 0.2
+    beta_B: float = 0.3
+    beta_C: float = 0.1
+    r_V: float = 0.7
+    delta_S: float = 0.1
+    delta_V: float = 0.15
+    gamma_A: float = 1 / 7
+    gamma_C: float = 1 / 60
+    gamma_DA: float = 0.05
+    gamma_DM: float = 0.2
+    gamma_E: float = 1 / 3
+    gamma_I: float = 1 / 10
+    gamma_L: float = 2e-4
+    gamma_M: float = 1 / 7
+    gamma_P: float = 1 / 2
+    gamma_R: float = 1 / 180
+    gamma_S1: float = 1 / 5
+    gamma_S2: float = 1 / 10
+    gamma_T: float = 1 / 200
+    gamma_V: float = 5e-3
+    sigma_A: float = 0.4
+    sigma_C: float = 0.2
+    sigma_H: float = 0.9
+    sigma_S: float = 0.05
+    pi_A: float = 1 / 3
+    pi_B: float = 1 / 10
+    pi_C: float = 1 / 7
+    pi_H: float = 1 / 8
+    phi_C: float = 0.1
+    phi_M: float = 0.05
+    phi_S: float = 0.2
+    phi_P: float = 0.1
+    kappa_H: float = 0.1
+    kappa_I: float = 0.3
+    kappa_N: float = 0.5
+    kappa_P: float = 0.01
+    nu: tuple = (1e-3, 1e-3, 1e-3, 5e-4, 5e-4, 2e-4, 1e-4, 2e-4, 1e-3, 1e-3)
+
+
+def state22(xy: np.ndarray, seed: int = 0, peak: float = 1e-2, width: float = 0.1,
+            jitter: float = 0.0) -> np.ndarray:
+    """[n, 22] initial densities: total 1 per unit area, a seeded bump of
+    exposed (60%) and presymptomatic (40%) people, 20% of the rest
+    vaccinated, the others susceptible; ``jitter`` > 0 adds seeded
+    nonnegative noise to every compartment (test states)."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.3, 0.7, 2)
+    r2 = ((xy - c[None, :]) ** 2).sum(1)
+    bump = peak * np.exp(-r2 / (2 * width ** 2))
+    ix = {nm: k for k, nm in enumerate(COMPARTMENTS22)}
+    u = np.zeros((len(xy), len(COMPARTMENTS22)))
+    u[:, ix["E"]] = 0.6 * bump
+    u[:, ix["A"]] = 0.4 * bump
+    u[:, ix["V"]] = 0.2 * (1.0 - bump)
+    if jitter > 0:
+        u += jitter * rng.uniform(0.0, 1.0, u.shape)
+    u[:, ix["S"]] = np.maximum(1.0 - (u.sum(1) - u[:, ix["S"]]), 0.0)
+    return u
+
+
 @dataclasses.dataclass
 class NestedMesh:
     """A mesh obtained by ``n_ref`` red refinements of a base mesh.
