@@ -511,6 +511,47 @@ def precond_variants_bench(sk, torch, args, cfg, coarse, direct):
     return out
 
 
+def model22_bench(sk, torch, args, cfg):
+    """The 22-compartment model of Appendix C on the realistic mesh (22
+    unknowns per node): compartment-wise Picard-Gauss-Seidel sweeps to
+    epsilon 1e-10, the ten diffusing compartments by GMRES(30) rtol 1e-5 with
+    one-level RAS of the same 1024 subdomains (scalar, overlap 2)."""
+    import seird_inputs as si
+    p = si.params22_realistic()
+    mesh = sk.Mesh(cfg.xy, cfg.tri)
+    t = time.perf_counter()
+    model = sk.Model22(mesh, p, cfg.part, cfg.n_sub, cfg.overlap, tile=32)
+    log(f"[bench] model22 created ({time.perf_counter() - t:.1f} s)")
+    u = torch.tensor(si.state22_from(cfg.u0), dtype=torch.float64, device="cuda")
+    kw = dict(tol=1e-10, max_sweeps=64, restart=cfg.gmres_restart, rtol=cfg.gmres_rtol)
+    st = model.step(u, cfg.dt, **kw)
+    log(f"[bench] model22 warmup: sweeps {st['sweeps']} setups {st['pc_setups']} res {st['res_scaled']:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.m22_steps):
+        st = model.step(u, cfg.dt, **kw)
+        stats.append(st)
+        log(f"[bench] model22 step {k}: sweeps {st['sweeps']} gmres {sum(st['gmres_its'])} setups {st['pc_setups']} "
+            f"res {st['res_scaled']:.2e} setup/gmres ms {st['t_setup_ms']:.0f}/{st['t_gmres_ms']:.0f}")
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    names = si.COMPARTMENTS22
+    return {"metric": "implicit steps/s, 22-compartment model", "value": args.m22_steps / sec, "unit": "steps/s",
+            "steps": args.m22_steps, "ms_per_step": 1e3 * sec / args.m22_steps,
+            "workload": (f"{cfg.name}: {cfg.n} nodes x 22 compartments ({22 * cfg.n} unknowns), dt {cfg.dt} day, "
+                         f"Appendix C model with synthetic rates, compartment-wise Picard-Gauss-Seidel to "
+                         f"epsilon 1e-10, inner GMRES({cfg.gmres_restart}) rtol {cfg.gmres_rtol} with one-level "
+                         f"RAS of {cfg.n_sub} scalar subdomains overlap {cfg.overlap}"),
+            "sweeps": [s["sweeps"] for s in stats],
+            "gmres_its_per_compartment": [{nm: s["gmres_its"][k] for k, nm in enumerate(names)
+                                           if s["gmres_its"][k]} for s in stats],
+            "pc_setups": [s["pc_setups"] for s in stats],
+            "res_scaled": [s["res_scaled"] for s in stats],
+            "phase_ms_per_step": {"t_setup_ms": sum(s["t_setup_ms"] for s in stats) / len(stats),
+                                  "t_gmres_ms": sum(s["t_gmres_ms"] for s in stats) / len(stats)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -546,6 +587,8 @@ def main():
                     help="timed steps of the Picard-Gauss-Seidel leg (0: skip)")
     ap.add_argument("--variant-steps", type=int, default=2,
                     help="timed steps of the two-grid RAS-V2 leg (one-level RAS runs one step; 0: skip both)")
+    ap.add_argument("--m22-steps", type=int, default=2,
+                    help="timed steps of the 22-compartment leg (0: skip)")
     ap.add_argument("--pgs-tol", type=float, default=1e-10,
                     help="epsilon tolerance of the Picard-Gauss-Seidel sweeps")
     ap.add_argument("--cpu-workers", type=int, default=16,
@@ -653,6 +696,8 @@ def main():
     if args.pgs_steps > 0:
         out["pgs"] = pgs_bench(sk, torch, args, cfg)
         out["pgs"]["vs_newton"] = out["pgs"]["value"] / value
+    if args.m22_steps > 0 and args.workload == "realistic":
+        out["model22"] = model22_bench(sk, torch, args, cfg)
     if args.batch_steps > 0:
         del res
         torch.cuda.empty_cache()

@@ -696,6 +696,68 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc,
                            double *grad_nu, const seird_krylov_opts *kopts,
                            seird_adjoint_stats *stats, void *stream);
 
+/* ------------------------------------------------------------------
+ * The 22-compartment model of Appendix C (Eqs. S ... D).  Compartments in
+ * the order of its compartment table, node-major state [n][22]:
+ *   S V E Q A W F B C X Y Z G N H H1 I H2 R1 R2 P D   (indices 0 .. 21);
+ * S V E A F B C P R1 R2 diffuse with constant coefficients nu[0..9] (in
+ * that order), the others are nodal.  Backward Euler with the lumped mass
+ * and homogeneous Neumann data of the five-compartment path:
+ *   F_c(u) = m (u_c - u_c^n) + dt nu_c K u_c - dt m R_c(u) = 0.
+ * The force of infection, which Appendix C uses but does not define, is
+ * lambda = beta_A A + beta_F F + beta_B B + beta_C C (mass action in the
+ * moving, non-isolating infectious densities, as in Eqs. seird1-5); phi_C
+ * of the equations is the parameter the table calls phi_A.
+ * ------------------------------------------------------------------ */
+#define SEIRD22_NC 22
+typedef struct {
+  double beta_A, beta_F, beta_B, beta_C;
+  double r_V, delta_S, delta_V;
+  double gamma_A, gamma_C, gamma_DA, gamma_DM, gamma_E, gamma_I, gamma_L,
+      gamma_M, gamma_P, gamma_R, gamma_S1, gamma_S2, gamma_T, gamma_V;
+  double sigma_A, sigma_C, sigma_H, sigma_S;
+  double pi_A, pi_B, pi_C, pi_H;
+  double phi_C, phi_M, phi_S, phi_P;
+  double kappa_H, kappa_I, kappa_N, kappa_P;
+  double nu[10]; /* S V E A F B C P R1 R2 */
+} seird22_params;
+typedef struct seird22_s *seird22;
+/* A 22-compartment problem on a mesh handle, stepped by the decoupled
+ * Picard-Gauss-Seidel iteration of Appendix A applied compartment by
+ * compartment: every reaction term is affine in its own density,
+ * R_c = s_c - d_c u_c, so a sweep solves, in table order and with the
+ * latest densities of the others, (m (1 + dt d_c) + dt nu_c K) u_c =
+ * m u_c^n + dt m s_c: a diagonal division for the twelve nodal
+ * compartments, and for the ten diffusing ones GMRES with a one-level RAS
+ * of scalar subdomains (opts: n_sub, overlap, tile; one-level, FP64) built
+ * from part.  The preconditioner of a compartment whose d_c does not depend
+ * on the state (all but S and V) is set up once per time-step size; those
+ * of S and V at the first sweep of every step.  Allocates device memory. */
+seird_status seird22_create(seird_mesh mesh, const seird22_params *p,
+                            const seird_schwarz_opts *opts,
+                            const int32_t *part, seird22 *out);
+void seird22_destroy(seird22 h);
+seird_status seird22_set_params(seird22 h, const seird22_params *p);
+/* F [n][22] = the residual above at u (device [n][22]) with u^n = u_prev. */
+seird_status seird22_residual(seird22 h, const double *u, const double *u_prev,
+                              double dt, double *F, void *stream);
+typedef struct {
+  int32_t sweeps;
+  int32_t gmres_its[SEIRD22_NC]; /* per compartment, summed over the sweeps */
+  double eps_hist[SEIRD_MAX_PGS];  /* ||u^{k+1} - u^k|| / ||u^n|| */
+  double res_scaled;               /* ||F(u)|| / ||m u^n|| of the result */
+  int32_t pc_setups, inexact_solves;
+  int32_t reason;
+  double t_setup_ms, t_gmres_ms, t_total_ms;
+} seird22_stats;
+/* One step in place on u (device [n][22]).  Sweeps until epsilon <= tol
+ * (SEIRD_ERR_NOT_CONVERGED after max_sweeps); kopts: the inner GMRES.
+ * SEIRD_ERR_NONFINITE for a nonfinite state.  Synchronising. */
+seird_status seird22_step(seird22 h, double *u, double dt,
+                          const seird_pgs_opts *popts,
+                          const seird_krylov_opts *kopts,
+                          seird22_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -102,6 +102,24 @@ class _CoarseKrylovStats(ctypes.Structure):
 
 
 MAX_PGS = 64
+NC22 = 22
+_P22_FIELDS = ["beta_A", "beta_F", "beta_B", "beta_C", "r_V", "delta_S", "delta_V",
+               "gamma_A", "gamma_C", "gamma_DA", "gamma_DM", "gamma_E", "gamma_I", "gamma_L",
+               "gamma_M", "gamma_P", "gamma_R", "gamma_S1", "gamma_S2", "gamma_T", "gamma_V",
+               "sigma_A", "sigma_C", "sigma_H", "sigma_S", "pi_A", "pi_B", "pi_C", "pi_H",
+               "phi_C", "phi_M", "phi_S", "phi_P", "kappa_H", "kappa_I", "kappa_N", "kappa_P"]
+
+
+class _Params22(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in _P22_FIELDS] + [("nu", ctypes.c_double * 10)]
+
+
+class _Stats22(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("gmres_its", ctypes.c_int32 * 22),
+                ("eps_hist", ctypes.c_double * 64), ("res_scaled", ctypes.c_double),
+                ("pc_setups", ctypes.c_int32), ("inexact_solves", ctypes.c_int32),
+                ("reason", ctypes.c_int32), ("t_setup_ms", ctypes.c_double),
+                ("t_gmres_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
 
 
 class _PgsOpts(ctypes.Structure):
@@ -185,6 +203,13 @@ _SIGS = {
     "seird_precond_set_solve_threads": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_precond_set_coarse_solver": ([_P, ctypes.c_int32], ctypes.c_int),
     "seird_precond_set_coarse_block": ([_P, ctypes.c_int32], ctypes.c_int),
+    "seird22_create": ([_P, ctypes.POINTER(_Params22), ctypes.POINTER(_Schwarz), _P, ctypes.POINTER(_P)],
+                       ctypes.c_int),
+    "seird22_destroy": ([_P], None),
+    "seird22_set_params": ([_P, ctypes.POINTER(_Params22)], ctypes.c_int),
+    "seird22_residual": ([_P, _P, _P, ctypes.c_double, _P, _P], ctypes.c_int),
+    "seird22_step": ([_P, _P, ctypes.c_double, ctypes.POINTER(_PgsOpts), ctypes.POINTER(_Krylov),
+                      ctypes.POINTER(_Stats22), _P], ctypes.c_int),
     "seird_precond_set_coarse_krylov": ([_P, ctypes.POINTER(_CoarseKrylovOpts)], ctypes.c_int),
     "seird_precond_coarse_krylov_stats": ([_P, ctypes.POINTER(_CoarseKrylovStats), ctypes.c_int], ctypes.c_int),
     "seird_autotune_schwarz": ([_P, ctypes.POINTER(_Schwarz), _P, _P, ctypes.c_int32, ctypes.c_int32,
@@ -911,6 +936,70 @@ class PicardGS:
         s = _PgsStats()
         code = lib().seird_pgs_step(self.h, _dptr(u, self.problem.N, "u"), float(dt), ctypes.byref(po),
                                     ctypes.byref(o), ctypes.byref(s), _stream())
+        k = s.sweeps
+        stats = dict(sweeps=k, gmres_its=list(s.gmres_its), eps_hist=list(s.eps_hist[:k]),
+                     res_scaled=s.res_scaled, pc_setups=s.pc_setups, inexact_solves=s.inexact_solves,
+                     reason=s.reason, t_setup_ms=s.t_setup_ms, t_gmres_ms=s.t_gmres_ms,
+                     t_total_ms=s.t_total_ms)
+        _check(code)
+        return stats
+
+
+def _params22(p) -> _Params22:
+    c = _Params22()
+    for f in _P22_FIELDS:
+        setattr(c, f, float(getattr(p, f)))
+    if len(p.nu) != 10:
+        raise ValueError("nu holds the 10 diffusion coefficients of S V E A F B C P R1 R2")
+    for k in range(10):
+        c.nu[k] = float(p.nu[k])
+    return c
+
+
+class Model22:
+    """The 22-compartment model of Appendix C on a mesh (state: float64 CUDA
+    [n, 22], compartments S V E Q A W F B C X Y Z G N H H1 I H2 R1 R2 P D),
+    stepped by compartment-wise Picard-Gauss-Seidel sweeps with one-level
+    scalar RAS + GMRES for the ten diffusing compartments.  ``p`` has the
+    fields of the parameter table (see seird22_params)."""
+
+    def __init__(self, mesh: Mesh, p, part, n_sub, overlap, tile=32):
+        self.mesh = mesh
+        self.n = mesh.n
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        if len(part) != mesh.n:
+            raise ValueError("partition length must equal the node count")
+        o, keep = _schwarz_opts(n_sub, overlap, tile, 0, None)
+        c = _params22(p)
+        h = ctypes.c_void_p()
+        _check(lib().seird22_create(mesh.h, ctypes.byref(c), ctypes.byref(o), part.ctypes.data, ctypes.byref(h)))
+        del keep
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.seird22_destroy(self.h)
+            self.h = None
+
+    def set_params(self, p):
+        c = _params22(p)
+        _check(lib().seird22_set_params(self.h, ctypes.byref(c)))
+
+    def residual(self, u, u_prev, dt, out=None):
+        out = _torch().empty_like(u) if out is None else out
+        N = NC22 * self.n
+        _check(lib().seird22_residual(self.h, _dptr(u, N, "u"), _dptr(u_prev, N, "u_prev"), float(dt),
+                                      _dptr(out, N, "F"), _stream()))
+        return out
+
+    def step(self, u, dt, tol=1e-10, max_sweeps=64, strict_linear=False, gmres_max_it=200, **kw):
+        """One implicit step in place on u; sweeps until epsilon <= tol.
+        Returns the statistics."""
+        po = _PgsOpts(float(tol), int(max_sweeps), int(bool(strict_linear)))
+        o = _krylov(max_it=gmres_max_it, **kw)
+        s = _Stats22()
+        code = lib().seird22_step(self.h, _dptr(u, NC22 * self.n, "u"), float(dt), ctypes.byref(po),
+                                  ctypes.byref(o), ctypes.byref(s), _stream())
         k = s.sweeps
         stats = dict(sweeps=k, gmres_its=list(s.gmres_its), eps_hist=list(s.eps_hist[:k]),
                      res_scaled=s.res_scaled, pc_setups=s.pc_setups, inexact_solves=s.inexact_solves,

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libseird.so")
 
-SOURCES = ["kernels.hip", "setup.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "kernels22.hip", "setup.cpp", "api.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # never emit packed FP32 arithmetic

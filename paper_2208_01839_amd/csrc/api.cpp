@@ -232,6 +232,7 @@ struct seird_problem_s {
   ~seird_problem_s() {
     dev_free(md.rowptr); dev_free(md.col); dev_free(md.tslot); dev_free(md.mass);
     dev_free(md.inc_ptr); dev_free(md.inc_j); dev_free(md.inc_l); dev_free(md.inc_sj); dev_free(md.inc_sl);
+    dev_free(md.slot_row); dev_free(md.slot_ek);
     dev_free(md.inc_K);
     dev_free(gfield); dev_free(partials); dev_free(hdev); dev_free(ydev); dev_free(flags);
     dev_free(u_prev); dev_free(F); dev_free(rhs); dev_free(delta); dev_free(vals);
@@ -297,7 +298,7 @@ struct seird_problem_s {
     HIPCHECK(hipMemcpyAsync(h.data(), hv, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     std::vector<double> out(sg.S);
-    for (int s = 0; s < seg.S; ++s) out[s] = std::sqrt(h[(size_t)s * HLD]);
+    for (int s = 0; s < sg.S; ++s) out[s] = std::sqrt(h[(size_t)s * HLD]);
     return out;
   }
   // Small host->device uploads (masks, scalars, GMRES coefficients) go
@@ -703,6 +704,13 @@ struct GmresOps {
   const double *vals = nullptr;
   int transpose = 0;
 };
+
+// a double for messages, in %g form
+static std::string fmt_g(double v) {
+  char b[32];
+  std::snprintf(b, sizeof b, "%.3g", v);
+  return b;
+}
 
 static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, double *x, const seird_krylov_opts &o,
                        std::vector<seird_krylov_stats> &stats, const std::vector<uint8_t> &active_in, hipStream_t st,
@@ -1182,6 +1190,8 @@ static seird_problem problem_create_impl(const MeshHost &mh, const seird_params 
     P->md.inc_j = dev_upload(m.inc_j);
     P->md.inc_l = dev_upload(m.inc_l);
     P->md.inc_sj = dev_upload(m.inc_sj);
+    P->md.slot_row = dev_upload(m.slot_row);
+    P->md.slot_ek = dev_upload(m.slot_ek);
     P->md.inc_sl = dev_upload(m.inc_sl);
     P->md.inc_K = dev_upload(m.inc_K);
     P->d_cmass_d = dev_upload(m.cmass_d);
@@ -1259,7 +1269,7 @@ seird_status seird_problem_create_from_mesh(seird_mesh m, const seird_params *pa
 }
 
 static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
-                                         int bs);
+                                         int bs, const PrecondHost *proto = nullptr);
 
 // bytes of the adjoint-record pool of a workspace
 static size_t tape_pool_bytes(int64_t n, const seird_workspace_opts &wo) {
@@ -1510,7 +1520,7 @@ seird_status seird_spmv(seird_problem p, const double *vals, const double *x, do
 }
 
 static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
-                                         int bs);
+                                         int bs, const PrecondHost *proto);
 
 seird_status seird_csr(seird_problem p, const int64_t **rowptr, const int32_t **col, int64_t *nnz,
                        int64_t *nrows) {
@@ -1550,12 +1560,15 @@ seird_status seird_precond_create(seird_problem p, const seird_schwarz_opts *opt
 // Schwarz preconditioner of the coupled node-block Jacobian (bs = 5) or of
 // one compartment's scalar matrix on the node graph (bs = 1, one-level).
 static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_opts *opts, const int32_t *part,
-                                         int bs) {
+                                         int bs, const PrecondHost *proto) {
   auto pc = new seird_precond_s();
   try {
     pc->prob = p;
     pc->nvec = (int64_t)bs * p->mh.n;
-    build_precond(p->mh, *opts, part, pc->ph, bs);
+    if (proto)  // the host structures of an identical preconditioner
+      pc->ph = *proto;
+    else
+      build_precond(p->mh, *opts, part, pc->ph, bs);
     PrecondHost &ph = pc->ph;
     const int T = ph.tile;
     for (const SubInfo &s : ph.subs) {
@@ -2450,8 +2463,8 @@ static void pgs_step_impl(seird_pgs g, double *u, double dt, const seird_pgs_opt
     if (!std::isfinite(eps)) fail(SEIRD_ERR_NONFINITE, "nonfinite Picard-Gauss-Seidel update");
     if (eps <= po.tol) break;
     if (k >= po.max_sweeps)
-      fail(SEIRD_ERR_NOT_CONVERGED, "Picard-Gauss-Seidel did not reach epsilon " + std::to_string(po.tol) + " in " +
-                                        std::to_string(k) + " sweeps (last " + std::to_string(eps) + ")");
+      fail(SEIRD_ERR_NOT_CONVERGED, "Picard-Gauss-Seidel did not reach epsilon " + fmt_g(po.tol) + " in " +
+                                        std::to_string(k) + " sweeps (last " + fmt_g(eps) + ")");
   }
   // the coupled residual of the result, scaled as the Newton stopping test
   launch_residual(p->md, Pt, p->gfield, u, p->u_prev, dt, nullptr, p->F, st);
@@ -2710,3 +2723,231 @@ seird_status seird_batch_autotune(seird_batch b, int32_t reps, seird_tune_report
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------
+// The 22-compartment model of Appendix C: decoupled Picard-Gauss-Seidel
+// steps, one scalar system per compartment and sweep (Appendix A's
+// iteration applied to Eqs. S ... D).
+// ------------------------------------------------------------------------
+namespace {
+constexpr int NC22 = SEIRD22_NC;
+// compartments whose loss rate d_c depends on the state (through lambda)
+inline bool state_dependent_loss(int c) { return c == 0 || c == 1; }
+inline double nu22(const seird22_params &p, int c) {
+  static const int slot[NC22] = {0, 1, 2, -1, 3, -1, 4, 5, 6, -1, -1, -1, -1, -1, -1, -1, -1, -1, 8, 9, 7, -1};
+  return slot[c] < 0 ? 0.0 : p.nu[slot[c]];
+}
+}  // namespace
+
+struct seird22_s {
+  seird_problem prob = nullptr;  // the mesh on the device, scalar Krylov basis and buffers
+  seird22_params p{};
+  seird_precond pc[NC22] = {};   // one-level scalar RAS of each diffusing compartment
+  double pc_dt[NC22] = {};       // time step the preconditioner was set up for (0: never)
+  SegHost seg, seg_act, seg_re;  // one segment of n entries (scalar systems)
+  SegHost seg22;                 // one segment of 22 n entries (states)
+  double *up = nullptr, *uk = nullptr, *w = nullptr, *Kd = nullptr, *Ko = nullptr, *sdiag = nullptr,
+         *soff = nullptr, *r = nullptr, *delta = nullptr, *part22 = nullptr;
+  int *flags = nullptr;
+  ~seird22_s() {
+    for (auto &q : pc) delete q;
+    for (SegHost *g : {&seg, &seg22}) {
+      dev_free(g->d_seg_start); dev_free(g->d_blk_start); dev_free(g->d_block_seg);
+    }
+    dev_free(up); dev_free(uk); dev_free(w); dev_free(Kd); dev_free(Ko); dev_free(sdiag); dev_free(soff);
+    dev_free(r); dev_free(delta); dev_free(part22); dev_free(flags);
+    delete prob;
+  }
+};
+
+static SegHost one_segment(int64_t len) {
+  SegHost sg;
+  sg.S = 1;
+  sg.seg_start = {0, len};
+  sg.blk_start = {0, std::max<int64_t>(1, (len + SEG_CH - 1) / SEG_CH)};
+  sg.B = (int)sg.blk_start[1];
+  sg.block_seg.assign(sg.B, 0);
+  sg.d_seg_start = dev_upload(sg.seg_start);
+  sg.d_blk_start = dev_upload(sg.blk_start);
+  sg.d_block_seg = dev_upload(sg.block_seg);
+  return sg;
+}
+
+static void check22_params(const seird22_params &p) {
+  const double *v = &p.beta_A;
+  const size_t nv = sizeof(seird22_params) / sizeof(double);
+  for (size_t k = 0; k < nv; ++k)
+    if (!std::isfinite(v[k]) || v[k] < 0.0) fail(SEIRD_ERR_ARG, "22-compartment parameters must be finite and >= 0");
+}
+
+seird_status seird22_create(seird_mesh mesh, const seird22_params *p, const seird_schwarz_opts *opts,
+                            const int32_t *part, seird22 *out) {
+  API_BEGIN
+  if (!mesh || !p || !opts || !part || !out) fail(SEIRD_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (opts->n_ref != 0) fail(SEIRD_ERR_ARG, "the compartment-wise preconditioner is one-level (n_ref = 0)");
+  if (opts->factor_prec != 0) fail(SEIRD_ERR_ARG, "the compartment-wise preconditioner is FP64 (factor_prec = 0)");
+  check22_params(*p);
+  auto h = new seird22_s();
+  try {
+    h->p = *p;
+    h->prob = problem_create_impl(mesh->mh, seird_params{});
+    seird_problem P = h->prob;
+    const int64_t n = P->mh.n, ns = (int64_t)P->mh.col.size();
+    // every diffusing compartment gets its own preconditioner (also with
+    // nu_c = 0, so that seird22_set_params may turn its diffusion on)
+    int first = -1;
+    for (int c = 0; c < NC22; ++c) {
+      static const bool diffusing[NC22] = {1, 1, 1, 0, 1, 0, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 0};
+      if (!diffusing[c]) continue;
+      // the compartments share the subdomains: the host structures are built once
+      h->pc[c] = precond_create_impl(P, opts, part, 1, first >= 0 ? &h->pc[first]->ph : nullptr);
+      if (first < 0) first = c;
+    }
+    h->seg = one_segment(n);
+    h->seg_act = h->seg;
+    h->seg_act.d_active = P->d_mask;
+    h->seg_re = h->seg;
+    h->seg_re.d_active = P->d_mask2;
+    h->seg22 = one_segment(NC22 * n);
+    h->up = dev_alloc<double>(NC22 * n);
+    h->uk = dev_alloc<double>(NC22 * n);
+    h->w = dev_alloc<double>(NC22 * n);
+    h->Kd = dev_alloc<double>(n);
+    h->Ko = dev_alloc<double>(ns);
+    h->sdiag = dev_alloc<double>(n);
+    h->soff = dev_alloc<double>(ns);
+    h->r = dev_alloc<double>(n);
+    h->delta = dev_alloc<double>(n);
+    h->part22 = dev_alloc<double>(h->seg22.B);
+    h->flags = dev_alloc<int>(1);
+    launch22_stiffness(P->md, h->Kd, h->Ko, nullptr);
+    HIPCHECK(hipStreamSynchronize(nullptr));
+  } catch (...) {
+    delete h;
+    throw;
+  }
+  *out = h;
+  API_END
+}
+
+void seird22_destroy(seird22 h) { delete h; }
+
+seird_status seird22_set_params(seird22 h, const seird22_params *p) {
+  API_BEGIN
+  if (!h || !p) fail(SEIRD_ERR_ARG, "null argument");
+  check22_params(*p);
+  h->p = *p;
+  for (double &t : h->pc_dt) t = 0.0;  // the scalar matrices change: set up again
+  API_END
+}
+
+seird_status seird22_residual(seird22 h, const double *u, const double *u_prev, double dt, double *F, void *stream) {
+  API_BEGIN
+  if (!h || !u || !u_prev || !F) fail(SEIRD_ERR_ARG, "null argument");
+  launch22_residual(h->prob->md, h->p, u, u_prev, dt, F, (hipStream_t)stream);
+  HIPCHECK(hipGetLastError());
+  API_END
+}
+
+static void step22_impl(seird22 h, double *u, double dt, const seird_pgs_opts &po, const seird_krylov_opts &ko,
+                        seird22_stats &stats, hipStream_t st) {
+  using clk = std::chrono::steady_clock;
+  const auto t_start = clk::now();
+  seird_problem P = h->prob;
+  if (!(dt > 0.0)) fail(SEIRD_ERR_ARG, "dt must be > 0");
+  if (po.max_sweeps < 1 || po.max_sweeps > SEIRD_MAX_PGS) fail(SEIRD_ERR_ARG, "max_sweeps out of range");
+  const int64_t n = P->mh.n, N22 = NC22 * n;
+  stats = seird22_stats{};
+  HIPCHECK(hipMemcpyAsync(h->up, u, sizeof(double) * N22, hipMemcpyDeviceToDevice, st));
+  {
+    HIPCHECK(hipMemsetAsync(h->flags, 0, sizeof(int), st));
+    launch22_check(u, N22, h->flags, st);
+    int f = 0;
+    HIPCHECK(hipMemcpyAsync(&f, h->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    if (f) fail(SEIRD_ERR_NONFINITE, "nonfinite state");
+  }
+  auto norm22 = [&](const double *x) { return P->seg_norms(x, st, nullptr, h->part22, nullptr, &h->seg22)[0]; };
+  const double unorm = norm22(h->up);
+  GmresOps ops;
+  ops.N = n;
+  ops.seg = &h->seg;
+  ops.seg_act = &h->seg_act;
+  ops.seg_re = &h->seg_re;
+  ops.spmv = [h](const double *x, const double *b, double *y, hipStream_t s) {
+    launch_scalar_spmv(h->prob->md, h->sdiag, h->soff, x, b, y, s);
+  };
+  int cur = -1;  // compartment whose preconditioner the GMRES applies
+  ops.prec = [h, &cur](const double *r, double *z, hipStream_t s, const uint8_t *, const std::vector<uint8_t> *) {
+    h->pc[cur]->apply(nullptr, r, z, 0, s);
+  };
+  seird_krylov_opts o = ko;
+  o.graphs = 0;
+  std::vector<seird_krylov_stats> ks;
+  for (int k = 1;; ++k) {
+    HIPCHECK(hipMemcpyAsync(h->uk, u, sizeof(double) * N22, hipMemcpyDeviceToDevice, st));
+    for (int c = 0; c < NC22; ++c) {
+      launch22_system(P->md, h->p, c, dt, u, h->up, h->Kd, h->Ko, h->sdiag, h->r, st);
+      const double coef = dt * nu22(h->p, c);
+      if (coef == 0.0) continue;  // solved in place
+      launch22_offdiag((int64_t)P->mh.col.size(), coef, h->Ko, h->soff, st);
+      cur = c;
+      const bool fresh = h->pc_dt[c] != dt || (state_dependent_loss(c) && k == 1);
+      if (fresh) {
+        auto t0 = clk::now();
+        precond_setup_raw(h->pc[c], h->sdiag, h->soff, st);
+        h->pc_dt[c] = dt;
+        stats.pc_setups++;
+        stats.t_setup_ms += std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+      }
+      auto t0 = clk::now();
+      gmres_core(P, ops, h->r, h->delta, o, ks, std::vector<uint8_t>(1, 1), st, KrylovWork{});
+      stats.t_gmres_ms += std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+      stats.gmres_its[c] += ks[0].its;
+      if (ks[0].reason == SEIRD_ERR_DIVERGED)
+        fail(SEIRD_ERR_DIVERGED, "GMRES diverged in compartment " + std::to_string(c));
+      if (ks[0].reason == SEIRD_ERR_NOT_CONVERGED) {
+        stats.inexact_solves++;
+        if (po.strict_linear)
+          fail(SEIRD_ERR_NOT_CONVERGED, "GMRES reached max_it in compartment " + std::to_string(c));
+      }
+      launch22_update(u, c, h->delta, n, st);
+    }
+    // epsilon: ||u^{k+1} - u^k|| / ||u^n||
+    HIPCHECK(hipMemcpyAsync(h->w, h->uk, sizeof(double) * N22, hipMemcpyDeviceToDevice, st));
+    launch_axpby(h->w, u, 1.0, nullptr, 0, -1.0, N22, reduction_blocks(N22), st);
+    const double eps = norm22(h->w) / unorm;
+    stats.eps_hist[k - 1] = eps;
+    stats.sweeps = k;
+    if (!std::isfinite(eps)) fail(SEIRD_ERR_NONFINITE, "nonfinite Picard-Gauss-Seidel update");
+    if (eps <= po.tol) break;
+    if (k >= po.max_sweeps)
+      fail(SEIRD_ERR_NOT_CONVERGED, "Picard-Gauss-Seidel did not reach epsilon " + fmt_g(po.tol) + " in " +
+                                        std::to_string(k) + " sweeps (last " + fmt_g(eps) + ")");
+  }
+  launch22_residual(P->md, h->p, u, h->up, dt, h->w, st);
+  const double fn = norm22(h->w);
+  launch22_mass_scale(P->md.mass, h->up, h->w, n, st);
+  stats.res_scaled = fn / norm22(h->w);
+  stats.t_total_ms = std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
+}
+
+seird_status seird22_step(seird22 h, double *u, double dt, const seird_pgs_opts *popts,
+                          const seird_krylov_opts *kopts, seird22_stats *stats, void *stream) {
+  seird22_stats s{};
+  int code = SEIRD_OK;
+  try {
+    if (!h || !u || !popts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
+    step22_impl(h, u, dt, *popts, *kopts, s, (hipStream_t)stream);
+  } catch (const Error &e) {
+    code = e.code;
+    g_last_error = e.msg;
+  } catch (const std::exception &e) {
+    code = SEIRD_ERR_ARG;
+    g_last_error = std::string("internal: ") + e.what();
+  }
+  s.reason = code;
+  if (stats) *stats = s;
+  return code;
+}

@@ -82,6 +82,12 @@ struct MeshHost {
   std::vector<int64_t> inc_ptr; // [n+1]
   std::vector<int32_t> inc_j, inc_l, inc_sj, inc_sl;
   std::vector<double> inc_K;    // [ninc][3]: Kii, Kij, Kil
+  // per off-diagonal slot (i, j): its row i, and the (at most two)
+  // incidence records of row i whose element holds edge (i, j), in record
+  // order, as 2 k + w (w = 0: j is the record's first other vertex, 1:
+  // its second), -1 when absent
+  std::vector<int32_t> slot_row;
+  std::vector<int32_t> slot_ek;  // [nslots][2]
   // consistent mass M_ij = int phi_i phi_j: diagonal [n], slot values [nslots]
   std::vector<double> cmass_d, cmass_o;
   // boundary edges (in exactly one triangle), per node: the other end and
@@ -100,6 +106,7 @@ struct MeshDev {
   int64_t *inc_ptr = nullptr;
   int32_t *inc_j = nullptr, *inc_l = nullptr, *inc_sj = nullptr, *inc_sl = nullptr;
   double *inc_K = nullptr;
+  int32_t *slot_row = nullptr, *slot_ek = nullptr;
   // discretisation variants: consistent mass (null: lumped) and boundary
   // flux data [n][5][2] (null: homogeneous Neumann)
   const double *cmass_d = nullptr, *cmass_o = nullptr;

@@ -133,6 +133,16 @@ void launch_galerkin_blocks(const int32_t *gdst, const int64_t *gptr, const int3
 // y = A x (b null) or b - A x for dense 5x5 node blocks: diag [n][25], off [slots][25]
 void launch_block_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *diag, const double *off,
                        const double *x, const double *b, double *y, hipStream_t st);
+// 22-compartment model (Appendix C), state [n][22]
+void launch22_residual(const MeshDev &m, const seird22_params &p, const double *u, const double *up, double dt,
+                       double *F, hipStream_t st);
+void launch22_stiffness(const MeshDev &m, double *Kd, double *Ko, hipStream_t st);
+void launch22_system(const MeshDev &m, const seird22_params &p, int c, double dt, double *u, const double *up,
+                     const double *Kd, const double *Ko, double *sdiag, double *r, hipStream_t st);
+void launch22_offdiag(int64_t ns, double coef, const double *Ko, double *soff, hipStream_t st);
+void launch22_update(double *u, int c, const double *delta, int64_t n, hipStream_t st);
+void launch22_mass_scale(const double *mass, const double *x, double *y, int64_t n, hipStream_t st);
+void launch22_check(const double *u, int64_t N, int *flags, hipStream_t st);
 void launch_convert(void *dst, int dst_prec, const void *src, int src_float, int64_t N, hipStream_t st);
 void launch_band_solve(const SolveLaunch &sl, hipStream_t st);
 void launch_gather_copies(const int64_t *gptr, const int32_t *gidx, const double *yloc, double *z, int add, int64_t N,

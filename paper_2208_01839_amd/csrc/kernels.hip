@@ -154,14 +154,31 @@ __global__ __launch_bounds__(256) void k_residual(MeshDev m, ParamsDev P0, const
 }
 
 // ----------------------------------------------------------------------
-// Jacobian: one thread per node row.
+// Jacobian.
 //   diag[i][c][c'] = m_i (delta - dt dR_c/du_c') + dt nu_c (sum_T Nbar K_ii) delta
 //                    + dt nu_c (1/3) sum_T sum_k K_ik u_c,k
 //   off[s] = (a[5], b[5]): a_c = dt nu_c sum_T Nbar K_ij ; b_c = dt nu_c (1/3) sum_T sum_k K_ik u_c,k
+// Two kernels: one thread per node row for the diagonal blocks, one thread
+// per off-diagonal slot for the slots (each slot reads only the one or two
+// elements holding its edge and writes its 10 values next to its
+// neighbours' in memory).
 // ----------------------------------------------------------------------
+// element k's coupling of node i (state ui, total Ni) with its other two
+// vertices j, l: Nbar and G3_c = dt nu_c (Kii u_c,i + Kij u_c,j + Kil u_c,l) / 3
+__device__ inline void jac_element(const MeshDev &m, const double *__restrict__ u, const double (&ui)[5], double Ni,
+                                   const double (&coef)[5], int64_t k, double &Nbar, double (&G3)[5]) {
+  const int32_t j = m.inc_j[k], l = m.inc_l[k];
+  const double Kii = m.inc_K[3 * k], Kij = m.inc_K[3 * k + 1], Kil = m.inc_K[3 * k + 2];
+  double uj[5], ul[5];
+  load5(u + 5 * (int64_t)j, uj);
+  load5(u + 5 * (int64_t)l, ul);
+  Nbar = (Ni + (uj[0] + uj[1] + uj[2] + uj[3] + uj[4]) + (ul[0] + ul[1] + ul[2] + ul[3] + ul[4])) * (1.0 / 3.0);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) G3[c] = coef[c] * (Kii * ui[c] + Kij * uj[c] + Kil * ul[c]) * (1.0 / 3.0);
+}
+
 __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const double *__restrict__ gfield,
-                                                  const double *__restrict__ u, double dt, double *__restrict__ diag,
-                                                  double *__restrict__ off) {
+                                                  const double *__restrict__ u, double dt, double *__restrict__ diag) {
   const int64_t i = xcd_thread();
   if (i >= m.n) return;
   const ParamsDev P = m.inst ? m.Pinst[m.inst[i]] : P0;
@@ -172,51 +189,15 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
   double coef[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) coef[c] = dt * P.nu[c];
-  const int64_t k0 = m.inc_ptr[i], k1 = m.inc_ptr[i + 1];
-  // element k's coupling of node i with its other two vertices j, l
-  auto element = [&](int64_t k, double &Nbar, double (&G3)[5]) {
-    const int32_t j = m.inc_j[k], l = m.inc_l[k];
-    const double Kii = m.inc_K[3 * k], Kij = m.inc_K[3 * k + 1], Kil = m.inc_K[3 * k + 2];
-    double uj[5], ul[5];
-    load5(u + 5 * (int64_t)j, uj);
-    load5(u + 5 * (int64_t)l, ul);
-    Nbar = (Ni + (uj[0] + uj[1] + uj[2] + uj[3] + uj[4]) + (ul[0] + ul[1] + ul[2] + ul[3] + ul[4])) * (1.0 / 3.0);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) G3[c] = coef[c] * (Kii * ui[c] + Kij * uj[c] + Kil * ul[c]) * (1.0 / 3.0);
-  };
-  for (int64_t k = k0; k < k1; ++k) {
+  for (int64_t k = m.inc_ptr[i]; k < m.inc_ptr[i + 1]; ++k) {
     double Nbar, G3[5];
-    element(k, Nbar, G3);
+    jac_element(m, u, ui, Ni, coef, k, Nbar, G3);
     const double Kii = m.inc_K[3 * k];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       da[c] += coef[c] * Nbar * Kii;
       db[c] += G3[c];
     }
-  }
-  // each off-diagonal slot of row i: its 10 values summed over the
-  // elements that share the edge (in element order) and stored once
-  for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
-    double o[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k = k0; k < k1; ++k) {
-      const bool atj = m.inc_sj[k] == s, atl = m.inc_sl[k] == s;
-      if (!atj && !atl) continue;
-      double Nbar, G3[5];
-      element(k, Nbar, G3);
-      const double Kx = atj ? m.inc_K[3 * k + 1] : m.inc_K[3 * k + 2];
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        o[c] += coef[c] * Nbar * Kx;
-        o[5 + c] += G3[c];
-      }
-    }
-    if (m.cmass_o) {
-      const double mo = m.cmass_o[s];
-#pragma unroll
-      for (int c = 0; c < 5; ++c) o[c] += mo;
-    }
-#pragma unroll
-    for (int q = 0; q < 10; ++q) off[10 * s + q] = o[q];
   }
   const double g = gfield ? gfield[i] : 1.0;
   double JR[5][5];
@@ -230,6 +211,45 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
     for (int cp = 0; cp < 5; ++cp) D[5 * c + cp] = -dt * mi * JR[c][cp] + db[c] + (c == cp ? mdiag + da[c] : 0.0);
 }
 
+// off-diagonal slot s of row i: its 10 values summed over the elements
+// that share the edge, in incidence-record order
+__global__ __launch_bounds__(256) void k_jacobian_off(MeshDev m, ParamsDev P0, const double *__restrict__ u, double dt,
+                                                      double *__restrict__ off) {
+  const int64_t s = xcd_thread();
+  if (s >= m.nslots) return;
+  const int64_t i = m.slot_row[s];
+  const int32_t e0 = m.slot_ek[2 * s], e1 = m.slot_ek[2 * s + 1];
+  const ParamsDev P = m.inst ? m.Pinst[m.inst[i]] : P0;
+  double ui[5];
+  load5(u + 5 * i, ui);
+  const double Ni = ui[0] + ui[1] + ui[2] + ui[3] + ui[4];
+  double coef[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) coef[c] = dt * P.nu[c];
+  double o[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int32_t ek = t == 0 ? e0 : e1;
+    if (ek < 0) continue;
+    const int64_t k = ek >> 1;
+    double Nbar, G3[5];
+    jac_element(m, u, ui, Ni, coef, k, Nbar, G3);
+    const double Kx = m.inc_K[3 * k + 1 + (ek & 1)];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      o[c] += coef[c] * Nbar * Kx;
+      o[5 + c] += G3[c];
+    }
+  }
+  if (m.cmass_o) {
+    const double mo = m.cmass_o[s];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) o[c] += mo;
+  }
+#pragma unroll
+  for (int q = 0; q < 10; ++q) off[10 * s + q] = o[q];
+}
+
 // ----------------------------------------------------------------------
 // SpMV with the node-block Jacobian: y = J x, or y = b - J x when b != 0.
 // Five lanes per node, lane c producing row c of the node's block row (of
@@ -240,7 +260,17 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
 constexpr int SPMV_WAVE_NODES = 12;  // nodes per wave (lanes 60..63 idle)
 
 // A wave holds 12 whole nodes, so the five lanes of a node exchange their
-// neighbour components with shuffles (each lane loads one).
+// neighbour components with shuffles (each lane loads one).  The first
+// SPMV_PF slots of a row are loaded before any of them is used (column
+// indices, then neighbour values and matrix entries), so a wave has all of
+// its row's loads in flight at once instead of one slot's chain at a time;
+// the loads past the row's last slot re-read that slot (every node of a
+// valid mesh has neighbours) and their terms are dropped, which keeps the
+// loads unconditional.  Rows with more slots finish in a loop.
+#ifndef SEIRD_SPMV_PF
+#define SEIRD_SPMV_PF 6
+#endif
+constexpr int SPMV_PF = SEIRD_SPMV_PF;
 __global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restrict__ diag,
                                               const double *__restrict__ off, const double *__restrict__ x,
                                               const double *__restrict__ b, double *__restrict__ y) {
@@ -248,13 +278,36 @@ __global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restric
   const int c = lane % 5, g0 = lane - c;  // first lane of this node's group
   const int64_t i = (xcd_block(blockIdx.x, gridDim.x) * 4 + w) * SPMV_WAVE_NODES + lane / 5;
   if (lane >= 5 * SPMV_WAVE_NODES || i >= m.n) return;
+  const int64_t s0 = m.rowptr[i], s1 = m.rowptr[i + 1];
+  const int64_t slast = s1 > s0 ? s1 - 1 : s0;
+  int32_t cj[SPMV_PF];
+#pragma unroll
+  for (int k = 0; k < SPMV_PF; ++k) cj[k] = m.col[min(s0 + k, slast)];
   double xi[5];
   load5(x + 5 * i, xi);
   const double *D = diag + 25 * i + 5 * c;
+  double dv[5];
+#pragma unroll
+  for (int cp = 0; cp < 5; ++cp) dv[cp] = D[cp];
+  double xa[SPMV_PF], oa[SPMV_PF], ob[SPMV_PF];
+#pragma unroll
+  for (int k = 0; k < SPMV_PF; ++k) {
+    const double *o = off + 10 * min(s0 + k, slast);
+    xa[k] = x[5 * (int64_t)cj[k] + c];
+    oa[k] = o[c];
+    ob[k] = o[5 + c];
+  }
   double acc = 0.0;
 #pragma unroll
-  for (int cp = 0; cp < 5; ++cp) acc += D[cp] * xi[cp];
-  for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
+  for (int cp = 0; cp < 5; ++cp) acc += dv[cp] * xi[cp];
+#pragma unroll
+  for (int k = 0; k < SPMV_PF; ++k) {
+    const double xjc = xa[k];
+    const double S = __shfl(xjc, g0, 64) + __shfl(xjc, g0 + 1, 64) + __shfl(xjc, g0 + 2, 64) +
+                     __shfl(xjc, g0 + 3, 64) + __shfl(xjc, g0 + 4, 64);
+    if (s0 + k < s1) acc += oa[k] * xjc + ob[k] * S;
+  }
+  for (int64_t s = s0 + SPMV_PF; s < s1; ++s) {
     const double xjc = x[5 * (int64_t)m.col[s] + c];
     const double S = __shfl(xjc, g0, 64) + __shfl(xjc, g0 + 1, 64) + __shfl(xjc, g0 + 2, 64) +
                      __shfl(xjc, g0 + 3, 64) + __shfl(xjc, g0 + 4, 64);
@@ -275,13 +328,41 @@ __global__ __launch_bounds__(256) void k_spmv_t(MeshDev m, const double *__restr
   const int cp = lane % 5, g0 = lane - cp;  // first lane of this node's group
   const int64_t j = (xcd_block(blockIdx.x, gridDim.x) * 4 + w) * SPMV_WAVE_NODES + lane / 5;
   if (lane >= 5 * SPMV_WAVE_NODES || j >= m.n) return;
+  const int64_t s0 = m.rowptr[j], s1 = m.rowptr[j + 1];
+  int32_t ci[SPMV_PF], ts[SPMV_PF];
+#pragma unroll
+  for (int k = 0; k < SPMV_PF; ++k) {
+    const bool v = s0 + k < s1;
+    ci[k] = v ? m.col[s0 + k] : (int32_t)j;
+    ts[k] = v ? m.tslot[s0 + k] : 0;
+  }
   double xj[5];
   load5(x + 5 * j, xj);
   const double *D = diag + 25 * j + cp;
+  double dv[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) dv[c] = D[5 * c];
+  double xa[SPMV_PF], oa[SPMV_PF], ob[SPMV_PF];
+#pragma unroll
+  for (int k = 0; k < SPMV_PF; ++k) {
+    const bool v = s0 + k < s1;
+    const double *o = off + 10 * (int64_t)ts[k];
+    xa[k] = x[5 * (int64_t)ci[k] + cp];
+    oa[k] = v ? o[cp] : 0.0;
+    ob[k] = v ? o[5 + cp] : 0.0;
+  }
   double acc = 0.0;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) acc += D[5 * c] * xj[c];
-  for (int64_t s = m.rowptr[j]; s < m.rowptr[j + 1]; ++s) {
+  for (int c = 0; c < 5; ++c) acc += dv[c] * xj[c];
+#pragma unroll
+  for (int k = 0; k < SPMV_PF; ++k) {
+    const double xic = xa[k];
+    const double pr = ob[k] * xic;
+    const double bsum = __shfl(pr, g0, 64) + __shfl(pr, g0 + 1, 64) + __shfl(pr, g0 + 2, 64) +
+                        __shfl(pr, g0 + 3, 64) + __shfl(pr, g0 + 4, 64);
+    if (s0 + k < s1) acc += oa[k] * xic + bsum;
+  }
+  for (int64_t s = s0 + SPMV_PF; s < s1; ++s) {
     const double xic = x[5 * (int64_t)m.col[s] + cp];
     const double *o = off + 10 * (int64_t)m.tslot[s];  // block (i, j) lives at slot tslot of row i
     const double pr = o[5 + cp] * xic;
@@ -960,11 +1041,11 @@ __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const
 // Galerkin coarse matrix: coarse block k (local positions p, q) =
 // sum_j w_j * fine block(ref_j).  One wave per coarse block: lanes stride
 // over its contributions, each lane accumulates the 25 entries, then a
-// fixed-order wave reduction; lane e < 25 returns entry e (row-major).
-__device__ inline double galerkin_entry(int64_t k, int lane, const int64_t *__restrict__ gptr,
-                                        const int32_t *__restrict__ gref, const double *__restrict__ gw,
-                                        const double *__restrict__ diag, const double *__restrict__ off) {
-  double acc[25];
+// fixed-order wave reduction leaves the block's entries in every lane.
+__device__ inline void galerkin_sum(int64_t k, int lane, const int64_t *__restrict__ gptr,
+                                    const int32_t *__restrict__ gref, const double *__restrict__ gw,
+                                    const double *__restrict__ diag, const double *__restrict__ off,
+                                    double (&acc)[25]) {
 #pragma unroll
   for (int e = 0; e < 25; ++e) acc[e] = 0.0;
   for (int64_t j = gptr[k] + lane; j < gptr[k + 1]; j += 64) {
@@ -987,6 +1068,10 @@ __device__ inline double galerkin_entry(int64_t k, int lane, const int64_t *__re
   }
 #pragma unroll
   for (int e = 0; e < 25; ++e) acc[e] = wave_sum(acc[e]);
+}
+
+// entry `lane` (< 25) of the reduced block
+__device__ inline double galerkin_pick(const double (&acc)[25], int lane) {
   double v = 0.0;
 #pragma unroll
   for (int e = 0; e < 25; ++e)
@@ -1004,8 +1089,10 @@ __global__ __launch_bounds__(256) void k_galerkin(double *__restrict__ F, SubInf
   const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (k >= nblk) return;  // uniform per wave
-  const double v = galerkin_entry(k, lane, gptr, gref, gw, diag, off);
+  double acc[25];
+  galerkin_sum(k, lane, gptr, gref, gw, diag, off, acc);
   if (lane < 25) {
+    const double v = galerkin_pick(acc, lane);
     const int c = lane / 5, cp = lane % 5;
     const int64_t at = tile_entry_checked<T>(cs, 5 * gp[k] + c, 5 * gq[k] + cp);
     if (at < 0)
@@ -1027,8 +1114,10 @@ __global__ __launch_bounds__(256) void k_galerkin_blocks(double *__restrict__ cd
   const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (k >= nblk) return;  // uniform per wave
-  const double v = galerkin_entry(k, lane, gptr, gref, gw, diag, off);
+  double acc[25];
+  galerkin_sum(k, lane, gptr, gref, gw, diag, off, acc);
   if (lane < 25) {
+    const double v = galerkin_pick(acc, lane);
     const int32_t d = gdst[k];
     double *dst = d < 0 ? cdiag + 25 * (int64_t)(-d - 1) : coff + 25 * (int64_t)d;
     dst[lane] = v;
@@ -2723,7 +2812,9 @@ void launch_residual(const MeshDev &m, const ParamsDev &P, const double *g, cons
 }
 void launch_jacobian(const MeshDev &m, const ParamsDev &P, const double *g, const double *u, double dt, double *diag,
                      double *off, hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobian, dim3(nblocks(m.n)), dim3(256), 0, st, m, P, g, u, dt, diag, off);
+  hipLaunchKernelGGL(k_jacobian, dim3(nblocks(m.n)), dim3(256), 0, st, m, P, g, u, dt, diag);
+  if (m.nslots > 0)
+    hipLaunchKernelGGL(k_jacobian_off, dim3(nblocks(m.nslots)), dim3(256), 0, st, m, P, u, dt, off);
 }
 void launch_spmv(const MeshDev &m, const double *diag, const double *off, const double *x, const double *b, double *y,
                  int transpose, hipStream_t st) {

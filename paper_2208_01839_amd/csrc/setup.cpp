@@ -167,6 +167,26 @@ void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,
       m.inc_K[3 * r + 2] = Kf[k][k2];
     }
   }
+  // slot -> row and the incidence records that reach it (an edge lies in
+  // one or two triangles of a conforming mesh)
+  const int64_t ns = (int64_t)m.col.size();
+  if (2 * ninc >= (int64_t)INT32_MAX) fail(SEIRD_ERR_MESH, "mesh too large for 32-bit incidence indices");
+  m.slot_row.assign(ns, 0);
+  m.slot_ek.assign(2 * ns, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) m.slot_row[s] = (int32_t)i;
+    for (int64_t k = m.inc_ptr[i]; k < m.inc_ptr[i + 1]; ++k)
+      for (int w = 0; w < 2; ++w) {
+        const int32_t s = w == 0 ? m.inc_sj[k] : m.inc_sl[k];
+        int32_t *e = &m.slot_ek[2 * (int64_t)s];
+        if (e[0] < 0)
+          e[0] = (int32_t)(2 * k + w);
+        else if (e[1] < 0)
+          e[1] = (int32_t)(2 * k + w);
+        else
+          fail(SEIRD_ERR_MESH, "an edge is shared by more than two triangles");
+      }
+  }
 }
 
 // Reverse Cuthill-McKee ordering of an induced subgraph given as a local

@@ -616,6 +616,33 @@ def bump_field(xy: np.ndarray, seed: int, n_bumps: int = 8,
     return 1.0 + amp * np.tanh(xi)
 
 
+def params22_realistic() -> "Params22":
+    """Rates of ``Params22`` for the realistic polygon, whose densities reach
+    ~130 per unit: transmission weights divided by 100 (so that beta times
+    the largest densities stays below about 0.4 per day, as on the unit
+    square with density 1) and constant diffusion coefficients in km^2/day
+    (the five-compartment case's 0.05 per density unit times a typical
+    density of 10)."""
+    return Params22(beta_A=3e-3, beta_F=2e-3, beta_B=3e-3, beta_C=1e-3,
+                    nu=(0.5, 0.5, 0.5, 0.25, 0.25, 0.1, 0.02, 0.1, 0.5, 0.5))
+
+
+def state22_from(u5: np.ndarray) -> np.ndarray:
+    """[n, 22] state from a five-compartment state [n, 5] (S E I R D): the
+    total density is kept, the exposed stay exposed, the infected become
+    presymptomatic, the recovered R1, the deceased D, and 20% of the
+    susceptible are vaccinated."""
+    ix = {nm: k for k, nm in enumerate(COMPARTMENTS22)}
+    u = np.zeros((len(u5), len(COMPARTMENTS22)))
+    u[:, ix["S"]] = 0.8 * u5[:, 0]
+    u[:, ix["V"]] = 0.2 * u5[:, 0]
+    u[:, ix["E"]] = u5[:, 1]
+    u[:, ix["A"]] = u5[:, 2]
+    u[:, ix["R1"]] = u5[:, 3]
+    u[:, ix["D"]] = u5[:, 4]
+    return u
+
+
 @dataclasses.dataclass
 class BatchConfig:
     """An ensemble of independent instances stepped together."""
