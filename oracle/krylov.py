@@ -18,7 +18,8 @@ TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
 * ``TwoLevelKrylov`` -- the same recurrence with the coarse system solved by
   GMRES preconditioned with RAS on the coarse graph ("Two-grid RAS - V2",
   Section 3.2), the outer solver being the flexible GMRES above (it keeps
-  the preconditioned vectors).
+  the preconditioned vectors); with ``inner="amg"`` the inner preconditioner
+  is the aggregation AMG V-cycle of ``oracle/amg.py`` ("Two-grid RAS - V3").
 """
 from __future__ import annotations
 
@@ -268,21 +269,28 @@ def coarse_partition(Znodes: sp.csr_matrix, part: np.ndarray, n_sub: int,
 class TwoLevelKrylov(TwoLevel):
     """Two-grid RAS with the coarse system A_c x = Z^T r solved by GMRES
     (x0 = 0, right preconditioning, restart, rtol/atol, max_it) with
-    one-level RAS on the coarse graph; the coarse subdomains are those of
-    ``coarse_partition`` grown by ``overlap`` coarse-graph layers.  ``infos``
-    collects the inner solves' reports."""
+    one-level RAS on the coarse graph (inner="ras"; the coarse subdomains are
+    those of ``coarse_partition`` grown by ``overlap`` coarse-graph layers)
+    or the aggregation AMG V-cycle (inner="amg"; ``amg`` holds its
+    options).  ``infos`` collects the inner solves' reports."""
 
     def __init__(self, A, ras: RAS, Znodes: sp.csr_matrix, G: sp.csr_matrix,
                  part: np.ndarray, n_sub: int, n_groups: int = 0, overlap: int = 1,
                  restart: int = 30, max_it: int = 100, rtol: float = 1e-5,
-                 atol: float = 1e-50):
+                 atol: float = 1e-50, inner: str = "ras", amg=None):
         self.A = A.tocsr()
         self.ras = ras
         self.Z = sp.kron(Znodes, sp.identity(NC), format="csr")
         self.Ac = (self.Z.T @ self.A @ self.Z).tocsr()
-        cpart, nsc = coarse_partition(Znodes, part, n_sub, n_groups)
-        self.ras_c = RAS(self.Ac, coarse_graph(Znodes, G), cpart, nsc, overlap)
-        self.n_coarse_sub = nsc
+        if inner == "amg":
+            from .amg import AggregationAMG
+            self.amg = AggregationAMG(self.Ac, coarse_graph(Znodes, G), **(amg or {}))
+            self.ras_c = self.amg
+            self.n_coarse_sub = 0
+        else:
+            cpart, nsc = coarse_partition(Znodes, part, n_sub, n_groups)
+            self.ras_c = RAS(self.Ac, coarse_graph(Znodes, G), cpart, nsc, overlap)
+            self.n_coarse_sub = nsc
         self.kw = dict(restart=restart, max_it=max_it, rtol=rtol, atol=atol, dtol=np.inf)
         self.infos = []
 
