@@ -458,24 +458,28 @@ def precond_variants_bench(sk, torch, args, cfg, coarse, direct):
     and GMRES counts): two-grid RAS-V2 (coarse system by inner GMRES(30),
     rtol 1e-5, at most 100 iterations, preconditioned by RAS on the coarse
     graph with the fine partition's coarse shares, overlap 1; flexible outer
-    GMRES) and one-level RAS (outer cap 200).  Each starts from the initial
+    GMRES), two-grid RAS-V3 (the same inner GMRES preconditioned by an
+    aggregation-AMG V-cycle, one Jacobi sweep each side, last level at most
+    40 nodes) and one-level RAS (outer cap 200).  Each starts from the initial
     state after one untimed step, as the headline does."""
     out = {}
     kw = dict(tol=cfg.newton_tol, max_it=cfg.newton_max_it, restart=cfg.gmres_restart,
               rtol=cfg.gmres_rtol, atol=cfg.gmres_atol, dtol=cfg.gmres_dtol, pc_reuse=args.pc_reuse,
               gmres_max_it=200)
     tile, threads = args.tuned.get(0, (32, 256))
-    for name in ("two_grid_v2", "one_level"):
-        steps = args.variant_steps if name == "two_grid_v2" else 1
+    for name in ("two_grid_v2", "two_grid_v3", "one_level"):
+        steps = args.variant_steps if name != "one_level" else 1
         prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
         pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, tile=tile, solve_threads=threads,
-                        coarse=coarse if name == "two_grid_v2" else None)
+                        coarse=coarse if name != "one_level" else None)
         if name == "two_grid_v2":
             pc.set_coarse_krylov(n_sub=0, overlap=1, restart=30, max_it=100, rtol=1e-5)
+        if name == "two_grid_v3":
+            pc.set_coarse_amg(max_coarse=40, nu=1, omega=2.0 / 3.0, restart=30, max_it=100, rtol=1e-5)
         u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
         st = sk.step(prob, pc, u, cfg.dt, **kw)
         log(f"[bench] {name} warmup: newton {st['newton_its']} gmres {st['gmres_its']}")
-        if name == "two_grid_v2":
+        if name != "one_level":
             pc.coarse_krylov_stats(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -496,11 +500,15 @@ def precond_variants_bench(sk, torch, args, cfg, coarse, direct):
                "inexact_solves": sum(s.get("inexact_solves", 0) for s in stats),
                "phase_ms_per_step": {k: sum(s[k] for s in stats) / len(stats)
                                      for k in ("t_setup_ms", "t_gmres_ms")}}
-        if name == "two_grid_v2":
+        if name != "one_level":
             ks = pc.coarse_krylov_stats()
             rec["inner"] = {"solves": ks["solves"], "mean_its": ks["its"] / max(1, ks["solves"]),
-                            "max_its": ks["its_max"], "capped_at_100": ks["unconverged"],
-                            "coarse_subdomains": ks["coarse_subdomains"]}
+                            "max_its": ks["its_max"], "capped_at_100": ks["unconverged"]}
+            if name == "two_grid_v2":
+                rec["inner"]["coarse_subdomains"] = ks["coarse_subdomains"]
+            else:
+                rec["inner"]["amg_levels"] = ks["amg_levels"]
+                rec["inner"]["amg_last_nodes"] = ks["amg_last_nodes"]
         out[name] = rec
         del pc, prob, u
         torch.cuda.empty_cache()

@@ -396,8 +396,9 @@ typedef struct {
 } seird_precond_perf_report;
 seird_status seird_precond_perf(seird_precond pc, seird_precond_perf_report *r,
                                 int reset);
-/* Coarse solver of a two-level preconditioner.  2: the Krylov coarse solver
- * of seird_precond_set_coarse_krylov (once that has been called).  1: the inverses of the
+/* Coarse solver of a two-level preconditioner.  3: the Krylov-AMG coarse
+ * solver of seird_precond_set_coarse_amg, 2: the Krylov-RAS coarse solver
+ * of seird_precond_set_coarse_krylov (once set).  1: the inverses of the
  * diagonal super-blocks of the coarse factors, X_II = L_II^{-1} and
  * W_II = U_II^{-1}, are formed at every setup (FP64 MFMA, on the coarse
  * stream) and A_c^{-1} r is a block forward/backward sweep: per block a
@@ -406,7 +407,8 @@ seird_status seird_precond_perf(seird_precond pc, seird_precond_perf_report *r,
  * tile 32 when the storage fits 16 GB (nt(nt+1) tiles of 8 KB for nt coarse
  * tile rows, whatever the block size).  0: the band forward/backward sweeps
  * over the factors (one workgroup).  Results of 0 and 1 agree to rounding.
- * SEIRD_ERR_ARG for 1 without inverses or 2 without a Krylov coarse solver. */
+ * SEIRD_ERR_ARG for 1 without inverses, 2 or 3 without their Krylov
+ * coarse solver. */
 seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver);
 /* Two-grid RAS-V2 (Section 3.2, compared with the direct coarse solve in
  * Table 2 of Section 4.1): the coarse system A_c x_c = Z^T r is solved by an
@@ -445,7 +447,32 @@ typedef struct {
   int64_t unconverged;  /* stopped by the cap (or the divergence test) */
   int32_t coarse_subdomains;
   int64_t coarse_local_unknowns;  /* summed over the coarse subdomains */
+  int32_t amg_levels;             /* V3: levels of the AMG hierarchy */
+  int64_t amg_last_nodes;         /* V3: nodes of its last level */
 } seird_coarse_krylov_stats;
+/* Two-grid RAS-V3 (Section 3.2): as V2, but the inner GMRES is
+ * preconditioned by one V-cycle of algebraic multigrid on the coarse
+ * system: plain aggregation of the coarse graph (greedy in the coarse
+ * grid's node order: a node with no aggregated neighbour starts an
+ * aggregate with its neighbours, the remaining nodes join the aggregate of
+ * their lowest-numbered neighbour aggregated first, nodes still left start
+ * aggregates with their free neighbours), piecewise-constant prolongation
+ * per component, Galerkin block sums, until a level has at most max_coarse
+ * nodes (or stops shrinking); nu damped (omega) node-block Jacobi sweeps
+ * before and after each coarse correction, starting from zero; an explicit
+ * dense inverse of the last level (Gaussian elimination with partial
+ * pivoting at every setup; SEIRD_ERR_BREAKDOWN if singular).  The package
+ * the paper uses (BoomerAMG) coarsens by classical splitting instead.
+ * Selects coarse solver 3; allocates the hierarchy (device memory). */
+typedef struct {
+  int32_t max_coarse;  /* nodes of the last level, 1 .. 800 */
+  int32_t nu;          /* smoothing sweeps before and after, 1 .. 8 */
+  double omega;        /* Jacobi damping, (0, 2) */
+  int32_t restart, max_it;
+  double rtol, atol;
+} seird_coarse_amg_opts;
+seird_status seird_precond_set_coarse_amg(seird_precond pc,
+                                          const seird_coarse_amg_opts *o);
 seird_status seird_precond_coarse_krylov_stats(seird_precond pc,
                                                seird_coarse_krylov_stats *s,
                                                int reset);

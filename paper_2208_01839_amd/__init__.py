@@ -98,7 +98,14 @@ class _CoarseKrylovOpts(ctypes.Structure):
 class _CoarseKrylovStats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_int64), ("its", ctypes.c_int64), ("its_max", ctypes.c_int64),
                 ("unconverged", ctypes.c_int64), ("coarse_subdomains", ctypes.c_int32),
-                ("coarse_local_unknowns", ctypes.c_int64)]
+                ("coarse_local_unknowns", ctypes.c_int64), ("amg_levels", ctypes.c_int32),
+                ("amg_last_nodes", ctypes.c_int64)]
+
+
+class _CoarseAmgOpts(ctypes.Structure):
+    _fields_ = [("max_coarse", ctypes.c_int32), ("nu", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("restart", ctypes.c_int32), ("max_it", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("atol", ctypes.c_double)]
 
 
 MAX_PGS = 64
@@ -212,6 +219,7 @@ _SIGS = {
                       ctypes.POINTER(_Stats22), _P], ctypes.c_int),
     "seird_precond_set_coarse_krylov": ([_P, ctypes.POINTER(_CoarseKrylovOpts)], ctypes.c_int),
     "seird_precond_coarse_krylov_stats": ([_P, ctypes.POINTER(_CoarseKrylovStats), ctypes.c_int], ctypes.c_int),
+    "seird_precond_set_coarse_amg": ([_P, ctypes.POINTER(_CoarseAmgOpts)], ctypes.c_int),
     "seird_autotune_schwarz": ([_P, ctypes.POINTER(_Schwarz), _P, _P, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.POINTER(_TuneReport), _P], ctypes.c_int),
     "seird_tune_cache_clear": ([], ctypes.c_int),
@@ -650,6 +658,15 @@ class Precond:
         applying)."""
         o = _CoarseKrylovOpts(int(n_sub), int(overlap), int(restart), int(max_it), float(rtol), float(atol))
         _check(lib().seird_precond_set_coarse_krylov(self.h, ctypes.byref(o)))
+
+    def set_coarse_amg(self, max_coarse=40, nu=1, omega=2.0 / 3.0, restart=30, max_it=100, rtol=1e-5,
+                       atol=1e-50):
+        """Two-grid RAS-V3: the coarse system solved by inner GMRES with an
+        aggregation-AMG V-cycle (selects coarse solver 3; set up again
+        before applying)."""
+        o = _CoarseAmgOpts(int(max_coarse), int(nu), float(omega), int(restart), int(max_it), float(rtol),
+                           float(atol))
+        _check(lib().seird_precond_set_coarse_amg(self.h, ctypes.byref(o)))
 
     def coarse_krylov_stats(self, reset=False):
         r = _CoarseKrylovStats()

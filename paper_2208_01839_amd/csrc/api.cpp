@@ -370,11 +370,59 @@ constexpr int COARSE_BLOCK = 128;
 static inline double coarse_inverse_bytes(int64_t nt) { return 2.0 * (double)(nt * (nt + 1) / 2) * 1024 * 8; }
 constexpr double COARSE_INVERSE_BUDGET = 16.0e9;
 
-// Two-grid RAS-V2 (Section 3.2): the coarse system solved by an inner
-// GMRES preconditioned with one-level RAS on the coarse graph
+// Aggregation AMG V-cycle over dense 5x5 node blocks (the inner
+// preconditioner of two-grid RAS-V3).  Level 0 is the coarse system in
+// coarse positions; each level's nodes are grouped into aggregates that
+// form the next level (piecewise-constant prolongation per component,
+// Galerkin products as block sums); the last level is solved with an
+// explicit dense inverse.
+struct AmgLevel {
+  int64_t n = 0, nslots = 0;
+  int64_t *rowptr = nullptr;  // node graph without self loops (level 0: the coarse problem's)
+  int32_t *col = nullptr;
+  double *diag = nullptr, *off = nullptr;  // dense blocks: diag [n][25], off [nslots][25]
+  double *dinv = nullptr;                  // inverted diagonal blocks
+  double *x = nullptr, *b = nullptr, *r = nullptr;  // work vectors [5 n]
+  // to the next level (all but the last)
+  int64_t nagg = 0;
+  int32_t *agg = nullptr;       // aggregate of each node
+  int64_t *agg_ptr = nullptr;   // member nodes of each aggregate [nagg + 1]
+  int32_t *agg_nodes = nullptr;
+  int32_t *gdst = nullptr;      // next level's blocks: diagonal (-a-1) or slot
+  int64_t *gptr = nullptr;      // sources of each next-level block [gnblk + 1]
+  int32_t *gref = nullptr;      // source block: diagonal (-i-1) or slot of this level
+  int64_t gnblk = 0;
+  bool owns_graph = true;
+};
+struct AmgHier {
+  std::vector<AmgLevel> lv;
+  int nu = 1;
+  double omega = 2.0 / 3.0;
+  double *Ainv = nullptr;  // dense inverse of the last level (5 n_last)^2, row-major
+  int m_last = 0;
+  ~AmgHier() {
+    for (AmgLevel &L : lv) {
+      if (L.owns_graph) {
+        dev_free(L.rowptr);
+        dev_free(L.col);
+        dev_free(L.diag);
+        dev_free(L.off);
+      }
+      dev_free(L.dinv); dev_free(L.x); dev_free(L.b); dev_free(L.r);
+      dev_free(L.agg); dev_free(L.agg_ptr); dev_free(L.agg_nodes);
+      dev_free(L.gdst); dev_free(L.gptr); dev_free(L.gref);
+    }
+    dev_free(Ainv);
+  }
+};
+
+// Two-grid RAS-V2 and V3 (Section 3.2): the coarse system solved by an
+// inner GMRES preconditioned with one-level RAS on the coarse graph (V2)
+// or with the aggregation AMG V-cycle (V3)
 struct KrylovCoarse {
   seird_problem cp = nullptr;   // the coarse graph as a problem: vectors, Krylov basis, segment views
-  seird_precond cpc = nullptr;  // RAS on the coarse graph (dense off-diagonal blocks)
+  seird_precond cpc = nullptr;  // V2: RAS on the coarse graph (dense off-diagonal blocks)
+  AmgHier *amg = nullptr;       // V3: the AMG hierarchy
   double *cvals = nullptr;      // Galerkin coarse matrix: diag [nc][25], then off [slots][25]
   int32_t *gdst = nullptr;      // Galerkin block -> diagonal block or slot
   seird_krylov_opts ko{};
@@ -382,6 +430,7 @@ struct KrylovCoarse {
 };
 static void krylov_coarse_solve(seird_precond pc, const double *rc, double *xc, hipStream_t st);
 static void krylov_coarse_free(KrylovCoarse *kc);
+static void amg_setup(AmgHier &H, double *cdiag, double *coff, int *status, hipStream_t st);
 
 struct seird_precond_s {
   seird_problem prob = nullptr;
@@ -622,11 +671,12 @@ struct seird_precond_s {
 
   // z += Z A_c^{-1} Z^T r  (or the transposed coarse operator)
   void coarse_add(const double *r, double *z, int transpose, hipStream_t st) {
-    if ((coarse_solver == 2) != (coarse_prepared == 2))
-      fail(SEIRD_ERR_ARG, "coarse solver changed between direct and Krylov since the last setup");
-    if (coarse_solver == 2 && transpose) fail(SEIRD_ERR_ARG, "the Krylov coarse solver has no transposed form");
+    const bool krylov = coarse_solver >= 2;
+    if ((krylov ? coarse_solver : 0) != coarse_prepared)
+      fail(SEIRD_ERR_ARG, "coarse solver changed (direct, Krylov-RAS, Krylov-AMG) since the last setup");
+    if (krylov && transpose) fail(SEIRD_ERR_ARG, "the Krylov coarse solvers have no transposed form");
     launch_coarse_restrict(zt_ptr, zt_col, zt_val, cperm, r, rc, ph.nc, st);
-    if (coarse_solver == 2) {
+    if (krylov) {
       krylov_coarse_solve(this, rc, xc, st);
       launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
       return;
@@ -825,7 +875,7 @@ static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, do
       };
       // (graphs only for a single instance: a batch's launches depend on
       // which instances are still running)
-      if (pc && o.graphs && !pc->timing && S == 1 && pc->coarse_solver != 2)
+      if (pc && o.graphs && !pc->timing && S == 1 && pc->coarse_solver < 2)
         pc->run_graph({P, V, Zb, vals, j, transpose, S > 1, pc->coarse_solver, pc->coarse_block, pc->solve_threads},
                       step_launches, st);
       else
@@ -1704,9 +1754,12 @@ seird_status seird_precond_timing(seird_precond pc, int enable) {
 seird_status seird_precond_set_coarse_solver(seird_precond pc, int32_t solver) {
   API_BEGIN
   if (!pc) fail(SEIRD_ERR_ARG, "null preconditioner");
-  if (solver < 0 || solver > 2) fail(SEIRD_ERR_ARG, "coarse solver must be 0, 1 or 2");
+  if (solver < 0 || solver > 3) fail(SEIRD_ERR_ARG, "coarse solver must be 0, 1, 2 or 3");
   if (solver == 1 && !pc->Xc) fail(SEIRD_ERR_ARG, "no coarse inverses for this preconditioner");
-  if (solver == 2 && !pc->kc) fail(SEIRD_ERR_ARG, "no Krylov coarse solver (seird_precond_set_coarse_krylov)");
+  if (solver == 2 && !(pc->kc && pc->kc->cpc))
+    fail(SEIRD_ERR_ARG, "no Krylov-RAS coarse solver (seird_precond_set_coarse_krylov)");
+  if (solver == 3 && !(pc->kc && pc->kc->amg))
+    fail(SEIRD_ERR_ARG, "no Krylov-AMG coarse solver (seird_precond_set_coarse_amg)");
   pc->coarse_solver = solver;
   pc->clear_graphs();
   API_END
@@ -1803,7 +1856,7 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
   fl.queue = pc->status + 1;  // the int after the status flag
   fl.n_cu = P_ncu(pc);
   fl.dense_off = pc->dense_off;
-  const bool krylov_coarse = ph.two_level && pc->coarse_solver == 2;
+  const bool krylov_coarse = ph.two_level && pc->coarse_solver >= 2;
   if (ph.two_level && !krylov_coarse) {
     fl.coarse = true;
     fl.cs = ph.coarse;
@@ -1846,7 +1899,10 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
     const int64_t nc = ph.nc;
     launch_galerkin_blocks(kc.gdst, pc->gptr, pc->gref, pc->gw, (int64_t)ph.gal_p.size(), diag, off, kc.cvals,
                            kc.cvals + 25 * nc, st);
-    precond_setup_raw(kc.cpc, kc.cvals, kc.cvals + 25 * nc, st);
+    if (kc.amg)
+      amg_setup(*kc.amg, kc.cvals, kc.cvals + 25 * nc, pc->status, st);
+    else
+      precond_setup_raw(kc.cpc, kc.cvals, kc.cvals + 25 * nc, st);
   }
   if (pc->Fb) launch_convert(pc->Fb, ph.prec, pc->Fs, pc->sub_float ? 1 : 0, ph.factor_entries, st);
   int status = 0;
@@ -1861,7 +1917,7 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
     pc->set_count++;
   }
   pc->ready = true;
-  if (ph.two_level) pc->coarse_prepared = krylov_coarse ? 2 : 0;
+  if (ph.two_level) pc->coarse_prepared = krylov_coarse ? pc->coarse_solver : 0;
   if (status & 2) fail(SEIRD_ERR_ARG, "internal: local matrix entry outside the stored tiles");
   if (status) fail(SEIRD_ERR_BREAKDOWN, "zero or nonfinite pivot in a local LU factorisation");
 }
@@ -1874,8 +1930,270 @@ seird_status seird_precond_setup_scalar(seird_precond pc, const double *diag, co
   API_END
 }
 
+// greedy aggregation of a node graph (sorted neighbour lists, no self
+// loops) in node order: (1) a node with no taken neighbour starts an
+// aggregate with all its neighbours; (2) a free node joins the aggregate
+// of its lowest-numbered neighbour taken in (1); (3) a node still free
+// starts an aggregate with its free neighbours
+static std::vector<int32_t> amg_aggregate(const std::vector<int64_t> &rp, const std::vector<int32_t> &cl,
+                                          int64_t &na_out) {
+  const int64_t n = (int64_t)rp.size() - 1;
+  std::vector<int32_t> agg(n, -1);
+  int32_t na = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    bool free_nbrs = true;
+    for (int64_t k = rp[i]; k < rp[i + 1] && free_nbrs; ++k) free_nbrs = agg[cl[k]] < 0;
+    if (!free_nbrs) continue;
+    agg[i] = na;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) agg[cl[k]] = na;
+    ++na;
+  }
+  const std::vector<int32_t> first = agg;
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (first[cl[k]] >= 0) {
+        agg[i] = first[cl[k]];
+        break;
+      }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    agg[i] = na;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (agg[cl[k]] < 0) agg[cl[k]] = na;
+    ++na;
+  }
+  na_out = na;
+  return agg;
+}
+
+// The hierarchy's structure from the coarse graph (positions; perm maps
+// original coarse numbers to positions).  The aggregation of level 0 runs
+// in the original numbering (node order of the method), the later levels
+// in aggregate order.
+static AmgHier *amg_build(seird_problem C, const PrecondHost &ph, int max_coarse, int nu, double omega) {
+  auto H = new AmgHier();
+  try {
+    H->nu = nu;
+    H->omega = omega;
+    const int64_t nc = ph.nc;
+    std::vector<int32_t> pos_of = ph.c_perm, orig_of(nc);
+    for (int64_t I = 0; I < nc; ++I) orig_of[pos_of[I]] = (int32_t)I;
+    // level graph in the level's own node numbering (level 0: original)
+    std::vector<int64_t> rp(nc + 1, 0);
+    std::vector<int32_t> cl;
+    for (int64_t I = 0; I < nc; ++I) {
+      const int32_t p = pos_of[I];
+      std::vector<int32_t> nb;
+      for (int64_t k = ph.cg_rowptr[p]; k < ph.cg_rowptr[p + 1]; ++k) nb.push_back(orig_of[ph.cg_col[k]]);
+      std::sort(nb.begin(), nb.end());
+      cl.insert(cl.end(), nb.begin(), nb.end());
+      rp[I + 1] = (int64_t)cl.size();
+    }
+    // device index of a level node: level 0 keeps positions, later levels the numbering itself
+    std::vector<int32_t> dev_of(orig_of.size());
+    for (int64_t I = 0; I < nc; ++I) dev_of[I] = pos_of[I];
+    // level 0 device graph: the coarse problem's (positions)
+    {
+      AmgLevel L;
+      L.n = nc;
+      L.nslots = (int64_t)ph.cg_col.size();
+      L.rowptr = C->md.rowptr;
+      L.col = C->md.col;
+      L.owns_graph = false;  // diag/off point into the Galerkin output, graph into the coarse problem
+      H->lv.push_back(L);
+    }
+    // device slot of (device row, device column) for a level's device graph
+    std::vector<int64_t> drp = ph.cg_rowptr;
+    std::vector<int32_t> dcl = ph.cg_col;
+    for (;;) {
+      AmgLevel &L = H->lv.back();
+      const int64_t n = L.n;
+      if (n <= max_coarse) break;
+      int64_t na = 0;
+      const std::vector<int32_t> agg = amg_aggregate(rp, cl, na);
+      if (na >= n) break;
+      // next level graph (aggregates adjacent through any member edge), sorted
+      std::vector<std::vector<int32_t>> nb(na);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+          if (agg[i] != agg[cl[k]]) nb[agg[i]].push_back(agg[cl[k]]);
+      std::vector<int64_t> rp2(na + 1, 0);
+      std::vector<int32_t> cl2;
+      for (int64_t a = 0; a < na; ++a) {
+        std::sort(nb[a].begin(), nb[a].end());
+        nb[a].erase(std::unique(nb[a].begin(), nb[a].end()), nb[a].end());
+        cl2.insert(cl2.end(), nb[a].begin(), nb[a].end());
+        rp2[a + 1] = (int64_t)cl2.size();
+      }
+      // aggregate of each device node, members (ascending level numbering) per aggregate
+      std::vector<int32_t> agg_dev(n);
+      for (int64_t i = 0; i < n; ++i) agg_dev[dev_of[i]] = agg[i];
+      std::vector<int64_t> aptr(na + 1, 0);
+      for (int64_t i = 0; i < n; ++i) aptr[agg[i] + 1]++;
+      for (int64_t a = 0; a < na; ++a) aptr[a + 1] += aptr[a];
+      std::vector<int32_t> anodes(n);
+      {
+        std::vector<int64_t> f(aptr.begin(), aptr.end() - 1);
+        for (int64_t i = 0; i < n; ++i) anodes[f[agg[i]]++] = dev_of[i];
+      }
+      // Galerkin map: every block of this level (device numbering) to its next-level block
+      struct Src { int32_t dst; int32_t ref; };
+      std::vector<Src> src;
+      auto next_slot = [&](int32_t a, int32_t b) -> int32_t {
+        const auto bg = cl2.begin() + rp2[a], en = cl2.begin() + rp2[a + 1];
+        const auto it = std::lower_bound(bg, en, b);
+        if (it == en || *it != b) fail(SEIRD_ERR_ARG, "internal: aggregate graph misses an edge");
+        return (int32_t)(it - cl2.begin());
+      };
+      for (int64_t di = 0; di < n; ++di) {
+        const int32_t a = agg_dev[di];
+        src.push_back({-a - 1, (int32_t)(-di - 1)});
+        for (int64_t k = drp[di]; k < drp[di + 1]; ++k) {
+          const int32_t b = agg_dev[dcl[k]];
+          src.push_back({a == b ? -a - 1 : next_slot(a, b), (int32_t)k});
+        }
+      }
+      std::stable_sort(src.begin(), src.end(), [](const Src &x, const Src &y) { return x.dst < y.dst; });
+      std::vector<int32_t> gdst, gref;
+      std::vector<int64_t> gptr{0};
+      for (size_t k = 0; k < src.size(); ++k) {
+        if (k > 0 && src[k].dst != src[k - 1].dst) gptr.push_back((int64_t)gref.size());
+        if (k == 0 || src[k].dst != src[k - 1].dst) gdst.push_back(src[k].dst);
+        gref.push_back(src[k].ref);
+      }
+      gptr.push_back((int64_t)gref.size());
+      L.nagg = na;
+      L.agg = dev_upload(agg_dev);
+      L.agg_ptr = dev_upload(aptr);
+      L.agg_nodes = dev_upload(anodes);
+      L.gdst = dev_upload(gdst);
+      L.gptr = dev_upload(gptr);
+      L.gref = dev_upload(gref);
+      L.gnblk = (int64_t)gdst.size();
+      AmgLevel N;
+      N.n = na;
+      N.nslots = (int64_t)cl2.size();
+      N.rowptr = dev_upload(rp2);
+      N.col = dev_upload(cl2);
+      N.diag = dev_alloc<double>(25 * (size_t)na);
+      N.off = dev_alloc<double>(25 * std::max<size_t>(cl2.size(), 1));
+      H->lv.push_back(N);
+      rp = rp2;
+      cl = cl2;
+      drp = rp2;
+      dcl = cl2;
+      dev_of.assign(na, 0);
+      for (int64_t a = 0; a < na; ++a) dev_of[a] = (int32_t)a;
+    }
+    for (AmgLevel &L : H->lv) {
+      L.dinv = dev_alloc<double>(25 * (size_t)L.n);
+      L.x = dev_alloc<double>(5 * (size_t)L.n);
+      L.b = dev_alloc<double>(5 * (size_t)L.n);
+      L.r = dev_alloc<double>(5 * (size_t)L.n);
+    }
+    H->m_last = (int)(5 * H->lv.back().n);
+    if (H->m_last > 4096) fail(SEIRD_ERR_ARG, "AMG last level too large for its dense inverse");
+    H->Ainv = dev_alloc<double>((size_t)H->m_last * H->m_last);
+  } catch (...) {
+    delete H;
+    throw;
+  }
+  return H;
+}
+
+// numeric setup: level 0's blocks are the Galerkin coarse matrix; the
+// later levels are block sums; every level's diagonal blocks inverted; the
+// last level's dense inverse by Gauss-Jordan with partial pivoting on the
+// host
+static void amg_setup(AmgHier &H, double *cdiag, double *coff, int *status, hipStream_t st) {
+  H.lv[0].diag = cdiag;
+  H.lv[0].off = coff;
+  for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+    const AmgLevel &L = H.lv[l];
+    AmgLevel &N = H.lv[l + 1];
+    launch_galerkin_dense(L.gdst, L.gptr, L.gref, L.gnblk, L.diag, L.off, N.diag, N.off, st);
+  }
+  for (AmgLevel &L : H.lv) launch_block_inv5(L.n, L.diag, L.dinv, status, st);
+  const AmgLevel &E = H.lv.back();
+  std::vector<double> dg(25 * (size_t)E.n), of(25 * (size_t)E.nslots);
+  std::vector<int64_t> rp(E.n + 1);
+  std::vector<int32_t> cl(E.nslots);
+  HIPCHECK(hipMemcpyAsync(dg.data(), E.diag, sizeof(double) * dg.size(), hipMemcpyDeviceToHost, st));
+  if (E.nslots) HIPCHECK(hipMemcpyAsync(of.data(), E.off, sizeof(double) * of.size(), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipMemcpyAsync(rp.data(), E.rowptr, sizeof(int64_t) * rp.size(), hipMemcpyDeviceToHost, st));
+  if (E.nslots) HIPCHECK(hipMemcpyAsync(cl.data(), E.col, sizeof(int32_t) * cl.size(), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  const int m = H.m_last;
+  std::vector<double> A((size_t)m * m, 0.0), X((size_t)m * m, 0.0);
+  for (int64_t i = 0; i < E.n; ++i) {
+    for (int r = 0; r < 5; ++r)
+      for (int c = 0; c < 5; ++c) A[(5 * i + r) * m + 5 * i + c] = dg[25 * i + 5 * r + c];
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+      for (int r = 0; r < 5; ++r)
+        for (int c = 0; c < 5; ++c) A[(5 * i + r) * m + 5 * (int64_t)cl[k] + c] = of[25 * k + 5 * r + c];
+  }
+  for (int i = 0; i < m; ++i) X[(size_t)i * m + i] = 1.0;
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int r = k + 1; r < m; ++r)
+      if (std::fabs(A[(size_t)r * m + k]) > std::fabs(A[(size_t)p * m + k])) p = r;
+    const double piv = A[(size_t)p * m + k];
+    if (!(std::fabs(piv) > 0.0) || !std::isfinite(piv))
+      fail(SEIRD_ERR_BREAKDOWN, "singular last AMG level");
+    if (p != k)
+      for (int c = 0; c < m; ++c) {
+        std::swap(A[(size_t)k * m + c], A[(size_t)p * m + c]);
+        std::swap(X[(size_t)k * m + c], X[(size_t)p * m + c]);
+      }
+    const double rp_ = 1.0 / A[(size_t)k * m + k];
+    for (int c = 0; c < m; ++c) {
+      A[(size_t)k * m + c] *= rp_;
+      X[(size_t)k * m + c] *= rp_;
+    }
+    for (int r = 0; r < m; ++r) {
+      if (r == k) continue;
+      const double f = A[(size_t)r * m + k];
+      if (f == 0.0) continue;
+      for (int c = 0; c < m; ++c) {
+        A[(size_t)r * m + c] -= f * A[(size_t)k * m + c];
+        X[(size_t)r * m + c] -= f * X[(size_t)k * m + c];
+      }
+    }
+  }
+  HIPCHECK(hipMemcpyAsync(H.Ainv, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
+// z = V(r) at level l (z, r of length 5 n_l): nu damped block-Jacobi sweeps
+// from zero, coarse correction, nu sweeps; the last level's dense inverse
+static void amg_vcycle(AmgHier &H, size_t l, const double *r, double *z, hipStream_t st) {
+  AmgLevel &L = H.lv[l];
+  if (l + 1 == H.lv.size()) {
+    launch_dense_gemv(H.m_last, H.Ainv, r, z, st);
+    return;
+  }
+  launch_fill(z, 0.0, 5 * L.n, st);
+  for (int s = 0; s < H.nu; ++s) {
+    launch_block_spmv(L.n, L.rowptr, L.col, L.diag, L.off, z, r, L.r, st);
+    launch_block_jacobi(L.n, L.dinv, L.r, H.omega, z, st);
+  }
+  launch_block_spmv(L.n, L.rowptr, L.col, L.diag, L.off, z, r, L.r, st);
+  AmgLevel &N = H.lv[l + 1];
+  launch_agg_restrict(L.nagg, L.agg_ptr, L.agg_nodes, L.r, N.b, st);
+  amg_vcycle(H, l + 1, N.b, N.x, st);
+  launch_agg_prolong(L.n, L.agg, N.x, z, st);
+  for (int s = 0; s < H.nu; ++s) {
+    launch_block_spmv(L.n, L.rowptr, L.col, L.diag, L.off, z, r, L.r, st);
+    launch_block_jacobi(L.n, L.dinv, L.r, H.omega, z, st);
+  }
+}
+
 static void krylov_coarse_free(KrylovCoarse *kc) {
   if (!kc) return;
+  delete kc->amg;
   delete kc->cpc;
   delete kc->cp;
   dev_free(kc->cvals);
@@ -1899,9 +2217,15 @@ static void krylov_coarse_solve(seird_precond pc, const double *rc, double *xc, 
     launch_block_spmv(C->md.n, C->md.rowptr, C->md.col, cd, co, x, b, y, s);
   };
   seird_precond cpc = kc.cpc;
-  ops.prec = [cpc](const double *r, double *z, hipStream_t s, const uint8_t *, const std::vector<uint8_t> *) {
-    cpc->ras(r, z, 0, 0, s);
-  };
+  AmgHier *amg = kc.amg;
+  if (amg)
+    ops.prec = [amg](const double *r, double *z, hipStream_t s, const uint8_t *, const std::vector<uint8_t> *) {
+      amg_vcycle(*amg, 0, r, z, s);
+    };
+  else
+    ops.prec = [cpc](const double *r, double *z, hipStream_t s, const uint8_t *, const std::vector<uint8_t> *) {
+      cpc->ras(r, z, 0, 0, s);
+    };
   std::vector<seird_krylov_stats> stats;
   gmres_core(C, ops, rc, xc, kc.ko, stats, std::vector<uint8_t>{1}, st, KrylovWork{});
   kc.solves++;
@@ -1969,6 +2293,47 @@ seird_status seird_precond_set_coarse_krylov(seird_precond pc, const seird_coars
   API_END
 }
 
+seird_status seird_precond_set_coarse_amg(seird_precond pc, const seird_coarse_amg_opts *o) {
+  API_BEGIN
+  if (!pc || !o) fail(SEIRD_ERR_ARG, "null argument");
+  const PrecondHost &ph = pc->ph;
+  if (!ph.two_level) fail(SEIRD_ERR_ARG, "the Krylov coarse solver needs a two-level preconditioner");
+  if (o->restart < 1 || o->restart > KRYLOV_MAX - 1) fail(SEIRD_ERR_ARG, "inner restart must be in [1, 31]");
+  if (o->max_it < 1) fail(SEIRD_ERR_ARG, "inner max_it must be >= 1");
+  if (!(o->rtol >= 0.0) || !(o->atol >= 0.0)) fail(SEIRD_ERR_ARG, "inner tolerances must be >= 0");
+  if (o->max_coarse < 1 || o->max_coarse > 800) fail(SEIRD_ERR_ARG, "max_coarse must be in [1, 800]");
+  if (o->nu < 1 || o->nu > 8) fail(SEIRD_ERR_ARG, "smoothing sweeps must be in [1, 8]");
+  if (!(o->omega > 0.0 && o->omega < 2.0)) fail(SEIRD_ERR_ARG, "omega must be in (0, 2)");
+  const int64_t nc = ph.nc;
+  MeshHost cm;
+  cm.n = nc;
+  cm.rowptr = ph.cg_rowptr;
+  cm.col = ph.cg_col;
+  cm.xy = ph.cg_xy;
+  auto kc = new KrylovCoarse();
+  try {
+    kc->cp = problem_create_impl(cm, seird_params{});
+    kc->amg = amg_build(kc->cp, ph, o->max_coarse, o->nu, o->omega);
+    kc->cvals = dev_alloc<double>((size_t)25 * (nc + (int64_t)ph.cg_col.size()));
+    kc->gdst = dev_upload(ph.gal_dst);
+    kc->cp->ensure_krylov(o->restart);
+    kc->ko.restart = o->restart;
+    kc->ko.max_it = o->max_it;
+    kc->ko.rtol = o->rtol;
+    kc->ko.atol = o->atol;
+    kc->ko.dtol = 1e300;
+    kc->ko.graphs = 0;
+  } catch (...) {
+    krylov_coarse_free(kc);
+    throw;
+  }
+  krylov_coarse_free(pc->kc);
+  pc->kc = kc;
+  pc->coarse_solver = 3;
+  pc->clear_graphs();
+  API_END
+}
+
 seird_status seird_precond_coarse_krylov_stats(seird_precond pc, seird_coarse_krylov_stats *s, int reset) {
   API_BEGIN
   if (!pc || !s) fail(SEIRD_ERR_ARG, "null argument");
@@ -1978,8 +2343,10 @@ seird_status seird_precond_coarse_krylov_stats(seird_precond pc, seird_coarse_kr
   s->its = kc.its;
   s->its_max = kc.its_max;
   s->unconverged = kc.unconverged;
-  s->coarse_subdomains = kc.cpc->ph.n_sub;
-  s->coarse_local_unknowns = (int64_t)kc.cpc->ph.l2g.size();
+  s->coarse_subdomains = kc.cpc ? kc.cpc->ph.n_sub : 0;
+  s->coarse_local_unknowns = kc.cpc ? (int64_t)kc.cpc->ph.l2g.size() : 0;
+  s->amg_levels = kc.amg ? (int32_t)kc.amg->lv.size() : 0;
+  s->amg_last_nodes = kc.amg ? kc.amg->lv.back().n : 0;
   if (reset) kc.solves = kc.its = kc.its_max = kc.unconverged = 0;
   API_END
 }

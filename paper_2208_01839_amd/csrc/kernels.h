@@ -143,6 +143,18 @@ void launch22_offdiag(int64_t ns, double coef, const double *Ko, double *soff, h
 void launch22_update(double *u, int c, const double *delta, int64_t n, hipStream_t st);
 void launch22_mass_scale(const double *mass, const double *x, double *y, int64_t n, hipStream_t st);
 void launch22_check(const double *u, int64_t N, int *flags, hipStream_t st);
+// aggregation AMG over dense 5x5 node blocks: Galerkin sums of dense blocks
+// (weights 1), diagonal-block inverses (*status |= 1 if singular), damped
+// block Jacobi x += omega D^{-1} r, restriction / prolongation over the
+// aggregates, dense matrix-vector product of the last level
+void launch_galerkin_dense(const int32_t *gdst, const int64_t *gptr, const int32_t *gref, int64_t nblk,
+                           const double *diag, const double *off, double *cdiag, double *coff, hipStream_t st);
+void launch_block_inv5(int64_t n, const double *diag, double *dinv, int *status, hipStream_t st);
+void launch_block_jacobi(int64_t n, const double *dinv, const double *r, double omega, double *x, hipStream_t st);
+void launch_agg_restrict(int64_t nagg, const int64_t *agg_ptr, const int32_t *agg_nodes, const double *r, double *bc,
+                         hipStream_t st);
+void launch_agg_prolong(int64_t n, const int32_t *agg, const double *xc, double *x, hipStream_t st);
+void launch_dense_gemv(int m, const double *M, const double *b, double *y, hipStream_t st);
 void launch_convert(void *dst, int dst_prec, const void *src, int src_float, int64_t N, hipStream_t st);
 void launch_band_solve(const SolveLaunch &sl, hipStream_t st);
 void launch_gather_copies(const int64_t *gptr, const int32_t *gidx, const double *yloc, double *z, int add, int64_t N,

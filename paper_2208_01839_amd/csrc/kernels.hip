@@ -283,8 +283,11 @@ __global__ __launch_bounds__(256) void k_spmv(MeshDev m, const double *__restric
   int32_t cj[SPMV_PF];
 #pragma unroll
   for (int k = 0; k < SPMV_PF; ++k) cj[k] = m.col[min(s0 + k, slast)];
+  // the node's own state: one load per lane, shared by shuffles
+  const double xic = x[5 * i + c];
   double xi[5];
-  load5(x + 5 * i, xi);
+#pragma unroll
+  for (int cp = 0; cp < 5; ++cp) xi[cp] = __shfl(xic, g0 + cp, 64);
   const double *D = diag + 25 * i + 5 * c;
   double dv[5];
 #pragma unroll
@@ -1042,6 +1045,9 @@ __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const
 // sum_j w_j * fine block(ref_j).  One wave per coarse block: lanes stride
 // over its contributions, each lane accumulates the 25 entries, then a
 // fixed-order wave reduction leaves the block's entries in every lane.
+// DENSE: the fine blocks are dense 5x5 (off [slots][25]) instead of the
+// Jacobian's diag(a) + b 1^T form; gw null: every weight is 1.
+template <bool DENSE = false>
 __device__ inline void galerkin_sum(int64_t k, int lane, const int64_t *__restrict__ gptr,
                                     const int32_t *__restrict__ gref, const double *__restrict__ gw,
                                     const double *__restrict__ diag, const double *__restrict__ off,
@@ -1050,9 +1056,9 @@ __device__ inline void galerkin_sum(int64_t k, int lane, const int64_t *__restri
   for (int e = 0; e < 25; ++e) acc[e] = 0.0;
   for (int64_t j = gptr[k] + lane; j < gptr[k + 1]; j += 64) {
     const int32_t ref = gref[j];
-    const double w = gw[j];
-    if (ref < 0) {
-      const double *D = diag + 25 * (int64_t)(-ref - 1);
+    const double w = gw ? gw[j] : 1.0;
+    if (ref < 0 || DENSE) {
+      const double *D = ref < 0 ? diag + 25 * (int64_t)(-ref - 1) : off + 25 * (int64_t)ref;
 #pragma unroll
       for (int e = 0; e < 25; ++e) acc[e] += w * D[e];
     } else {
@@ -1104,6 +1110,7 @@ __global__ __launch_bounds__(256) void k_galerkin(double *__restrict__ F, SubInf
 
 // written as node blocks of the coarse graph (Krylov coarse solve): block k
 // goes to the diagonal block of position -dst-1 or to slot dst
+template <bool DENSE>
 __global__ __launch_bounds__(256) void k_galerkin_blocks(double *__restrict__ cdiag, double *__restrict__ coff,
                                                          const int32_t *__restrict__ gdst,
                                                          const int64_t *__restrict__ gptr,
@@ -1115,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_galerkin_blocks(double *__restrict__ cd
   const int lane = threadIdx.x & 63;
   if (k >= nblk) return;  // uniform per wave
   double acc[25];
-  galerkin_sum(k, lane, gptr, gref, gw, diag, off, acc);
+  galerkin_sum<DENSE>(k, lane, gptr, gref, gw, diag, off, acc);
   if (lane < 25) {
     const double v = galerkin_pick(acc, lane);
     const int32_t d = gdst[k];
@@ -1150,6 +1157,121 @@ __global__ __launch_bounds__(256) void k_block_spmv(int64_t n, const int64_t *__
     for (int cp = 0; cp < 5; ++cp) acc += o[cp] * xj[cp];
   }
   y[5 * i + c] = b ? b[5 * i + c] - acc : acc;
+}
+
+// ----------------------------------------------------------------------
+// Aggregation AMG over dense 5x5 node blocks (V-cycle of the coarse solver)
+// ----------------------------------------------------------------------
+// dinv = inverse of every diagonal block (Gauss-Jordan with partial
+// pivoting, one thread per node); *status |= 1 on a singular block
+__global__ __launch_bounds__(256) void k_block_inv5(int64_t n, const double *__restrict__ diag,
+                                                    double *__restrict__ dinv, int *status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a[5][5], x[5][5];
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      a[r][c] = diag[25 * i + 5 * r + c];
+      x[r][c] = r == c ? 1.0 : 0.0;
+    }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    int p = k;
+    double best = fabs(a[k][k]);
+#pragma unroll
+    for (int r = k + 1; r < 5; ++r)
+      if (fabs(a[r][k]) > best) {
+        best = fabs(a[r][k]);
+        p = r;
+      }
+    if (!(best > 0.0) || !isfinite(best)) {
+      atomicOr(status, 1);
+      return;
+    }
+    // swap rows k and p (selects, so the arrays stay in registers)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      double t0 = a[k][c], t1 = x[k][c];
+#pragma unroll
+      for (int r = k + 1; r < 5; ++r)
+        if (r == p) {
+          a[k][c] = a[r][c];
+          a[r][c] = t0;
+          x[k][c] = x[r][c];
+          x[r][c] = t1;
+        }
+    }
+    const double rp = 1.0 / a[k][k];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      a[k][c] *= rp;
+      x[k][c] *= rp;
+    }
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+      if (r != k) {
+        const double f = a[r][k];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          a[r][c] -= f * a[k][c];
+          x[r][c] -= f * x[k][c];
+        }
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) dinv[25 * i + 5 * r + c] = x[r][c];
+}
+
+// x += omega D^{-1} r over the node blocks (lane c of a node: row c)
+__global__ __launch_bounds__(256) void k_block_jacobi(int64_t n, const double *__restrict__ dinv,
+                                                      const double *__restrict__ r, double omega,
+                                                      double *__restrict__ x) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 5 * n) return;
+  const int64_t i = idx / 5;
+  const int c = (int)(idx % 5);
+  const double *D = dinv + 25 * i + 5 * c;
+  double a = 0.0;
+#pragma unroll
+  for (int cp = 0; cp < 5; ++cp) a += D[cp] * r[5 * i + cp];
+  x[idx] += omega * a;
+}
+
+// bc[a] = sum over the aggregate's member nodes (in list order) of r
+__global__ __launch_bounds__(256) void k_agg_restrict(int64_t nagg, const int64_t *__restrict__ agg_ptr,
+                                                      const int32_t *__restrict__ agg_nodes,
+                                                      const double *__restrict__ r, double *__restrict__ bc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 5 * nagg) return;
+  const int64_t a = idx / 5;
+  const int c = (int)(idx % 5);
+  double s = 0.0;
+  for (int64_t k = agg_ptr[a]; k < agg_ptr[a + 1]; ++k) s += r[5 * (int64_t)agg_nodes[k] + c];
+  bc[idx] = s;
+}
+
+// x[i] += xc[agg(i)] per component
+__global__ __launch_bounds__(256) void k_agg_prolong(int64_t n, const int32_t *__restrict__ agg,
+                                                     const double *__restrict__ xc, double *__restrict__ x) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 5 * n) return;
+  const int64_t i = idx / 5;
+  x[idx] += xc[5 * (int64_t)agg[i] + idx % 5];
+}
+
+// y = M b for a dense m x m matrix (row-major), one thread per row
+__global__ __launch_bounds__(256) void k_dense_gemv(int m, const double *__restrict__ M, const double *__restrict__ b,
+                                                    double *__restrict__ y) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  const double *row = M + (int64_t)r * m;
+  double s = 0.0;
+  for (int c = 0; c < m; ++c) s += row[c] * b[c];
+  y[r] = s;
 }
 
 template <class FT>
@@ -2997,10 +3119,33 @@ void launch_galerkin_blocks(const int32_t *gdst, const int64_t *gptr, const int3
                             int64_t nblk, const double *diag, const double *off, double *cdiag, double *coff,
                             hipStream_t st) {
   if (nblk <= 0) return;
-  hipLaunchKernelGGL(k_galerkin_blocks, dim3(nblocks(nblk * 64)), dim3(256), 0, st, cdiag, coff, gdst, gptr, gref, gw,
+  hipLaunchKernelGGL(k_galerkin_blocks<false>, dim3(nblocks(nblk * 64)), dim3(256), 0, st, cdiag, coff, gdst, gptr, gref, gw,
                      nblk, diag, off);
 }
 
+void launch_galerkin_dense(const int32_t *gdst, const int64_t *gptr, const int32_t *gref, int64_t nblk,
+                           const double *diag, const double *off, double *cdiag, double *coff, hipStream_t st) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(k_galerkin_blocks<true>, dim3(nblocks(nblk * 64)), dim3(256), 0, st, cdiag, coff, gdst, gptr,
+                     gref, (const double *)nullptr, nblk, diag, off);
+}
+void launch_block_inv5(int64_t n, const double *diag, double *dinv, int *status, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_block_inv5, dim3(nblocks(n)), dim3(256), 0, st, n, diag, dinv, status);
+}
+void launch_block_jacobi(int64_t n, const double *dinv, const double *r, double omega, double *x, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_block_jacobi, dim3(nblocks(5 * n)), dim3(256), 0, st, n, dinv, r, omega, x);
+}
+void launch_agg_restrict(int64_t nagg, const int64_t *agg_ptr, const int32_t *agg_nodes, const double *r, double *bc,
+                         hipStream_t st) {
+  if (nagg > 0)
+    hipLaunchKernelGGL(k_agg_restrict, dim3(nblocks(5 * nagg)), dim3(256), 0, st, nagg, agg_ptr, agg_nodes, r, bc);
+}
+void launch_agg_prolong(int64_t n, const int32_t *agg, const double *xc, double *x, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_agg_prolong, dim3(nblocks(5 * n)), dim3(256), 0, st, n, agg, xc, x);
+}
+void launch_dense_gemv(int m, const double *M, const double *b, double *y, hipStream_t st) {
+  if (m > 0) hipLaunchKernelGGL(k_dense_gemv, dim3(nblocks(m)), dim3(256), 0, st, m, M, b, y);
+}
 void launch_block_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *diag, const double *off,
                        const double *x, const double *b, double *y, hipStream_t st) {
   if (n <= 0) return;

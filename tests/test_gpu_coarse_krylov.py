@@ -1,6 +1,7 @@
-"""Two-grid RAS-V2 on the GPU (coarse system solved by an inner GMRES with RAS
-on the coarse graph, Section 3.2) against the oracle's ``TwoLevelKrylov``
-and its direct two-grid operator, through the C ABI."""
+"""Two-grid RAS-V2 and V3 on the GPU (coarse system solved by an inner GMRES
+with RAS on the coarse graph, or with an aggregation-AMG V-cycle, Section
+3.2) against the oracle's ``TwoLevelKrylov`` and its direct two-grid
+operator, through the C ABI."""
 import numpy as np
 import pytest
 
@@ -159,3 +160,82 @@ def test_krylov_coarse_misuse_is_reported(nested):
     assert e.value.code == -1
     with pytest.raises(sk.SeirdError):
         pc.set_coarse_krylov(restart=0)
+
+
+# --------------------------------------------------------------------------
+# V3: inner GMRES preconditioned by the aggregation AMG V-cycle
+# --------------------------------------------------------------------------
+AMG = dict(max_coarse=4, nu=1, omega=2.0 / 3.0)  # levels of 81, 9 and 1 nodes
+
+
+def _precond_amg(cfg, prob, vals, **kw):
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, coarse=(cfg.coarse_parents, cfg.coarse_n))
+    pc.set_coarse_amg(**{**AMG, **kw})
+    pc.setup(vals)
+    return pc
+
+
+def test_v3_exact_inner_solve_gives_the_direct_two_grid_operator(nested):
+    cfg, prob, geo = nested
+    try:
+        vals, Jo, G, ras, Zn = _system(cfg, prob, geo, 31)
+        pc = _precond_amg(cfg, prob, vals, rtol=1e-14, atol=0.0, max_it=400)
+        r = np.random.default_rng(6).standard_normal(5 * cfg.n)
+        assert relerr(H(pc.apply(T(r))), krylov.TwoLevel(Jo, ras, Zn).apply(r)) < 1e-9
+        st = pc.coarse_krylov_stats()
+        tk = krylov.TwoLevelKrylov(Jo, ras, Zn, G, cfg.part, cfg.n_sub, inner="amg", amg=AMG)
+        assert st["amg_levels"] == tk.amg.levels >= 3
+        assert st["amg_last_nodes"] == tk.amg.A[-1].shape[0] // 5
+        assert st["unconverged"] == 0
+    finally:
+        prob.set_params(cfg.params)
+
+
+@pytest.mark.parametrize("its,nu", [(1, 1), (4, 1), (3, 2)])
+def test_v3_capped_inner_solve_matches_oracle(nested, its, nu):
+    """The same aggregates, smoothing and last-level solve as the oracle's
+    AMG: the capped inner solves give the same operator."""
+    cfg, prob, geo = nested
+    try:
+        vals, Jo, G, ras, Zn = _system(cfg, prob, geo, 32)
+        pc = _precond_amg(cfg, prob, vals, nu=nu, rtol=0.0, atol=0.0, max_it=its)
+        tk = krylov.TwoLevelKrylov(Jo, ras, Zn, G, cfg.part, cfg.n_sub, inner="amg", amg={**AMG, "nu": nu},
+                                   rtol=0.0, atol=0.0, max_it=its)
+        r = np.random.default_rng(7).standard_normal(5 * cfg.n)
+        assert relerr(H(pc.apply(T(r))), tk.apply(r)) < 1e-10
+    finally:
+        prob.set_params(cfg.params)
+
+
+def test_v3_outer_gmres_matches_oracle(nested):
+    cfg, prob, geo = nested
+    try:
+        vals, Jo, G, ras, Zn = _system(cfg, prob, geo, 33)
+        pc = _precond_amg(cfg, prob, vals)
+        tk = krylov.TwoLevelKrylov(Jo, ras, Zn, G, cfg.part, cfg.n_sub, inner="amg", amg=AMG)
+        b = np.random.default_rng(8).standard_normal(5 * cfg.n)
+        x, st = sk.gmres(prob, pc, vals, T(b), rtol=1e-8)
+        xo, io = krylov.gmres(lambda v: Jo @ v, b, tk.apply, rtol=1e-8)
+        assert st["reason"] == 1 and io["reason"] == "converged"
+        assert abs(st["its"] - io["its"]) <= 1, (st, io)
+        assert np.linalg.norm(Jo @ H(x) - b) <= 1.01e-8 * np.linalg.norm(b)
+    finally:
+        prob.set_params(cfg.params)
+
+
+def test_v3_newton_steps_reach_the_oracle_root(nested):
+    cfg, prob, geo = nested
+    pc = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap, coarse=(cfg.coarse_parents, cfg.coarse_n))
+    pc.set_coarse_amg()
+    u = T(cfg.u0.copy())
+    uo = cfg.u0.copy()
+    for _ in range(3):
+        sk.step(prob, pc, u, cfg.dt, tol=1e-13, rtol=1e-9)
+        uo, _ = newton.newton_step(uo, cfg.dt, geo, cfg.params, tol=1e-14)
+    ug = H(u)
+    for c in range(5):
+        assert np.abs(ug[:, c] - uo[:, c]).max() <= 1e-8 * max(np.abs(uo[:, c]).max(), 1e-30), c
+    with pytest.raises(sk.SeirdError):
+        pc.set_coarse_solver(2)  # no Krylov-RAS coarse solver on this preconditioner
+    with pytest.raises(sk.SeirdError):
+        pc.set_coarse_amg(omega=2.5)
