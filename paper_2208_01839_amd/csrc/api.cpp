@@ -232,7 +232,7 @@ struct seird_problem_s {
   ~seird_problem_s() {
     dev_free(md.rowptr); dev_free(md.col); dev_free(md.tslot); dev_free(md.mass);
     dev_free(md.inc_ptr); dev_free(md.inc_j); dev_free(md.inc_l); dev_free(md.inc_sj); dev_free(md.inc_sl);
-    dev_free(md.slot_row); dev_free(md.slot_ek);
+    dev_free(md.slot_row); dev_free(md.slot_ek); dev_free(md.kd); dev_free(md.ko); dev_free(md.kw);
     dev_free(md.inc_K);
     dev_free(gfield); dev_free(partials); dev_free(hdev); dev_free(ydev); dev_free(flags);
     dev_free(u_prev); dev_free(F); dev_free(rhs); dev_free(delta); dev_free(vals);
@@ -1242,6 +1242,9 @@ static seird_problem problem_create_impl(const MeshHost &mh, const seird_params 
     P->md.inc_sj = dev_upload(m.inc_sj);
     P->md.slot_row = dev_upload(m.slot_row);
     P->md.slot_ek = dev_upload(m.slot_ek);
+    P->md.kd = dev_upload(m.kd);
+    P->md.ko = dev_upload(m.ko);
+    P->md.kw = dev_upload(m.kw);
     P->md.inc_sl = dev_upload(m.inc_sl);
     P->md.inc_K = dev_upload(m.inc_K);
     P->d_cmass_d = dev_upload(m.cmass_d);

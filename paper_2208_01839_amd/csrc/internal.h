@@ -88,6 +88,9 @@ struct MeshHost {
   // its second), -1 when absent
   std::vector<int32_t> slot_row;
   std::vector<int32_t> slot_ek;  // [nslots][2]
+  // assembled P1 stiffness: K_ii [n], K_ij [nslots], and per slot (i, j)
+  // the sum of K^T_ii over the elements holding edge (i, j)
+  std::vector<double> kd, ko, kw;
   // consistent mass M_ij = int phi_i phi_j: diagonal [n], slot values [nslots]
   std::vector<double> cmass_d, cmass_o;
   // boundary edges (in exactly one triangle), per node: the other end and
@@ -107,6 +110,7 @@ struct MeshDev {
   int32_t *inc_j = nullptr, *inc_l = nullptr, *inc_sj = nullptr, *inc_sl = nullptr;
   double *inc_K = nullptr;
   int32_t *slot_row = nullptr, *slot_ek = nullptr;
+  double *kd = nullptr, *ko = nullptr, *kw = nullptr;
   // discretisation variants: consistent mass (null: lumped) and boundary
   // flux data [n][5][2] (null: homogeneous Neumann)
   const double *cmass_d = nullptr, *cmass_o = nullptr;

@@ -177,6 +177,11 @@ __device__ inline void jac_element(const MeshDev &m, const double *__restrict__ 
   for (int c = 0; c < 5; ++c) G3[c] = coef[c] * (Kii * ui[c] + Kij * uj[c] + Kil * ul[c]) * (1.0 / 3.0);
 }
 
+// diagonal blocks from the assembled stiffness, one thread per node row:
+//   sum_T (K^T u_c)_i      = K_ii u_c,i + sum_s K_is u_c,col(s)
+//   sum_T Nbar_T K^T_ii    = (N_i K_ii + sum_s W_s N_col(s)) / 3
+// (W_s: K^T_ii summed over the elements holding the slot's edge), so the
+// row reads each neighbour's state once instead of once per element
 __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const double *__restrict__ gfield,
                                                   const double *__restrict__ u, double dt, double *__restrict__ diag) {
   const int64_t i = xcd_thread();
@@ -185,19 +190,17 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
   double ui[5];
   load5(u + 5 * i, ui);
   const double Ni = ui[0] + ui[1] + ui[2] + ui[3] + ui[4];
-  double da[5] = {0, 0, 0, 0, 0}, db[5] = {0, 0, 0, 0, 0};
-  double coef[5];
+  const double kii = m.kd[i];
+  double ku[5], nk = Ni * kii;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) coef[c] = dt * P.nu[c];
-  for (int64_t k = m.inc_ptr[i]; k < m.inc_ptr[i + 1]; ++k) {
-    double Nbar, G3[5];
-    jac_element(m, u, ui, Ni, coef, k, Nbar, G3);
-    const double Kii = m.inc_K[3 * k];
+  for (int c = 0; c < 5; ++c) ku[c] = kii * ui[c];
+  for (int64_t s = m.rowptr[i]; s < m.rowptr[i + 1]; ++s) {
+    double uj[5];
+    load5(u + 5 * (int64_t)m.col[s], uj);
+    const double ko = m.ko[s];
+    nk += m.kw[s] * (uj[0] + uj[1] + uj[2] + uj[3] + uj[4]);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      da[c] += coef[c] * Nbar * Kii;
-      db[c] += G3[c];
-    }
+    for (int c = 0; c < 5; ++c) ku[c] += ko * uj[c];
   }
   const double g = gfield ? gfield[i] : 1.0;
   double JR[5][5];
@@ -206,9 +209,12 @@ __global__ __launch_bounds__(256) void k_jacobian(MeshDev m, ParamsDev P0, const
   const double mdiag = m.cmass_d ? m.cmass_d[i] : mi;  // the time-derivative term's diagonal
   double *D = diag + 25 * i;
 #pragma unroll
-  for (int c = 0; c < 5; ++c)
+  for (int c = 0; c < 5; ++c) {
+    const double coef = dt * P.nu[c];
+    const double da = coef * nk * (1.0 / 3.0), db = coef * ku[c] * (1.0 / 3.0);
 #pragma unroll
-    for (int cp = 0; cp < 5; ++cp) D[5 * c + cp] = -dt * mi * JR[c][cp] + db[c] + (c == cp ? mdiag + da[c] : 0.0);
+    for (int cp = 0; cp < 5; ++cp) D[5 * c + cp] = -dt * mi * JR[c][cp] + db + (c == cp ? mdiag + da : 0.0);
+  }
 }
 
 // off-diagonal slot s of row i: its 10 values summed over the elements

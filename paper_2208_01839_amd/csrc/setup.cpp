@@ -187,6 +187,17 @@ void build_mesh(int64_t n, const double *xy, int64_t nt, const int32_t *tri,
           fail(SEIRD_ERR_MESH, "an edge is shared by more than two triangles");
       }
   }
+  m.kd.assign(n, 0.0);
+  m.ko.assign(ns, 0.0);
+  m.kw.assign(ns, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = m.inc_ptr[i]; k < m.inc_ptr[i + 1]; ++k) {
+      m.kd[i] += m.inc_K[3 * k];
+      m.ko[m.inc_sj[k]] += m.inc_K[3 * k + 1];
+      m.ko[m.inc_sl[k]] += m.inc_K[3 * k + 2];
+      m.kw[m.inc_sj[k]] += m.inc_K[3 * k];
+      m.kw[m.inc_sl[k]] += m.inc_K[3 * k];
+    }
 }
 
 // Reverse Cuthill-McKee ordering of an induced subgraph given as a local
