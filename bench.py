@@ -571,7 +571,7 @@ def main():
                     help="skip the FP32/BF16-factor legs")
     ap.add_argument("--tile", default="auto", choices=["auto", "16", "32"],
                     help="tile size of the subdomain band storage (auto: chosen by the autotuner)")
-    ap.add_argument("--solve-threads", type=int, default=256, choices=[256, 512, 1024],
+    ap.add_argument("--solve-threads", type=int, default=256, choices=[256, 128, 512, 1024],
                     help="subdomain-solve workgroup size when --tile is given")
     ap.add_argument("--n-base", type=int, default=3900)
     ap.add_argument("--n-ref", type=int, default=4)

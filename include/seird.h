@@ -485,9 +485,9 @@ seird_status seird_precond_coarse_krylov_stats(seird_precond pc,
  * size is below the coarse band width in tiles (the blocks must couple only
  * with their neighbours). */
 seird_status seird_precond_set_coarse_block(seird_precond pc, int32_t tiles);
-/* Workgroup size of the subdomain solves: 256 (any tile), 512 or 1024
- * (tile 32 only).  A launch choice: each row's sums are split over 8, 16
- * or 32 lanes (float64 accumulation), so results agree to rounding.
+/* Workgroup size of the subdomain solves: 256 (any tile), 128, 512 or
+ * 1024 (tile 32 only).  A launch choice: each row's sums are split over 4,
+ * 8, 16 or 32 lanes (float64 accumulation), so results agree to rounding.
  * Default 256; SEIRD_ERR_ARG for other values. */
 seird_status seird_precond_set_solve_threads(seird_precond pc, int32_t threads);
 
@@ -669,8 +669,8 @@ void seird_batch_destroy(seird_batch b);
 seird_status seird_batch_info(seird_batch b, int64_t *node_offsets);
 /* Autotune the subdomain-solve width of the batch's preconditioner on the
  * ensemble itself (its current factors: call after a step): times `reps`
- * subdomain-solve launches over every instance for each width (256, 512,
- * 1024 with tile 32), keeps the fastest (also in the autotuner cache).
+ * subdomain-solve launches over every instance for each width (256, 128,
+ * 512, 1024 with tile 32), keeps the fastest (also in the autotuner cache).
  * Synchronising. */
 seird_status seird_batch_autotune(seird_batch b, int32_t reps, seird_tune_report *report,
                                   void *stream);

@@ -643,7 +643,7 @@ class Precond:
         return {k: getattr(r, k) for k, _ in _PerfReport._fields_}
 
     def set_solve_threads(self, threads):
-        """Workgroup size of the subdomain solves (256; 512 or 1024 with tile 32)."""
+        """Workgroup size of the subdomain solves (256; 128, 512 or 1024 with tile 32)."""
         _check(lib().seird_precond_set_solve_threads(self.h, int(threads)))
 
     def set_coarse_solver(self, solver):

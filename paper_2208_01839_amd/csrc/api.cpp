@@ -1785,8 +1785,8 @@ seird_status seird_precond_set_coarse_block(seird_precond pc, int32_t tiles) {
 seird_status seird_precond_set_solve_threads(seird_precond pc, int32_t threads) {
   API_BEGIN
   if (!pc) fail(SEIRD_ERR_ARG, "null preconditioner");
-  const bool ok = threads == 256 || (pc->ph.tile == 32 && (threads == 512 || threads == 1024));
-  if (!ok) fail(SEIRD_ERR_ARG, "solve workgroup size must be 256, or 512/1024 with tile 32");
+  const bool ok = threads == 256 || (pc->ph.tile == 32 && (threads == 128 || threads == 512 || threads == 1024));
+  if (!ok) fail(SEIRD_ERR_ARG, "solve workgroup size must be 256, or 128/512/1024 with tile 32");
   pc->solve_threads = threads;
   pc->clear_graphs();
   API_END
@@ -2484,7 +2484,7 @@ seird_status seird_autotune_schwarz(seird_problem p, const seird_schwarz_opts *o
     }
   };
   for (int tile : {32, 16}) {
-    const std::vector<int> widths = tile == 32 ? std::vector<int>{256, 512, 1024} : std::vector<int>{256};
+    const std::vector<int> widths = tile == 32 ? std::vector<int>{256, 128, 512, 1024} : std::vector<int>{256};
     seird_schwarz_opts o = *opts;
     o.tile = tile;
     seird_precond pc = nullptr;
@@ -3054,7 +3054,7 @@ seird_status seird_batch_autotune(seird_batch b, int32_t reps, seird_tune_report
   try {
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
-    const std::vector<int> widths = T == 32 ? std::vector<int>{256, 512, 1024} : std::vector<int>{256};
+    const std::vector<int> widths = T == 32 ? std::vector<int>{256, 128, 512, 1024} : std::vector<int>{256};
     for (int th : widths) {
       pc->solve_threads = th;
       pc->ras(r, z, 0, 0, st);

@@ -863,6 +863,21 @@ struct TileRows {
   }
   __device__ inline int first(int K) const { return row ? lo[K] : max(0, K - bl); }
   __device__ inline int last(int K) const { return row ? lo[K] + (row[K + 1] - row[K]) - 1 : min(nt - 1, K + bu); }
+  // block row K at once: tile (K, J) starts at entry off0 + J T^2, for J
+  // in first .. last (one read of the row tables instead of one per tile)
+  template <int T>
+  __device__ inline void row_info(int K, int64_t &off0, int &first_, int &last_) const {
+    if (row) {
+      const int r0 = row[K], r1 = row[K + 1], l0 = lo[K];
+      off0 = base + ((int64_t)r0 - l0) * (T * T);
+      first_ = l0;
+      last_ = l0 + (r1 - r0) - 1;
+    } else {
+      off0 = base + ((int64_t)K * (bl + bu + 1) - K + bl) * (T * T);
+      first_ = max(0, K - bl);
+      last_ = min(nt - 1, K + bu);
+    }
+  }
 };
 __device__ inline TileRows tile_rows(const SubInfo &s, const int32_t *erow, const int32_t *elo) {
   TileRows r;
@@ -1966,11 +1981,19 @@ __device__ inline double group_sum(double v) {
 //       1 = transposed: masked gather, result written to the per-subdomain
 //           buffer yloc (summed over copies afterwards)
 constexpr int RING = 32;  // block rows of the local vector kept in LDS (> bl, bu)
+static_assert((RING & (RING - 1)) == 0, "ring indices are taken modulo RING with a mask");
 // off-diagonal tiles per block row held in registers at once
 // (the summation order does not depend on it)
 template <int T, class FT, int NTHR>
 constexpr int solve_bmax() {
-  if (T == 32 && NTHR == 256) return sizeof(FT) == 8 ? 6 : 8;
+  // 256 threads: the register sets of the rows in flight (below) stay
+  // within 128 registers, so that four subdomains share a compute unit
+  // (float64 loads each row's tiles in the row: ahead-loading measured no
+  // faster there)
+  if (T == 32 && NTHR == 256) return sizeof(FT) == 8 ? 6 : (sizeof(FT) == 4 ? 6 : 8);
+  // 128 threads (two waves per subdomain, 8 elements of a tile row per
+  // lane): 256 registers per lane
+  if (T == 32 && NTHR == 128) return sizeof(FT) == 8 ? 4 : (sizeof(FT) == 4 ? 6 : 8);
   // float64 at 512 threads: 8 tiles (a typical band), so that two block
   // rows' first chunks fit the cross-row prefetch budget
   if (T == 32 && NTHR == 512 && sizeof(FT) == 8) return 8;
@@ -1978,6 +2001,16 @@ constexpr int solve_bmax() {
   constexpr int regs = per * (sizeof(FT) >= 4 ? (int)sizeof(FT) / 4 : 1);
   constexpr int b = 48 / regs;
   return b > 16 ? 16 : (b < 1 ? 1 : b);
+}
+// block rows ahead of the one computing whose first tile chunk is already
+// being loaded (0: every row loads its own tiles)
+template <int T, class FT, int NTHR>
+constexpr int solve_depth() {
+  if (T == 32 && NTHR == 256) return sizeof(FT) == 8 ? 0 : 2;
+  if (T == 32 && NTHR == 128) return sizeof(FT) == 8 ? 1 : (sizeof(FT) == 4 ? 2 : 3);
+  constexpr int per = T * T / NTHR;
+  constexpr int regs = per * (((int)sizeof(FT) + 3) / 4);
+  return (solve_bmax<T, FT, NTHR>() + 1) * regs <= 40 ? 1 : 0;
 }
 
 // PER consecutive elements of one tile row (aligned to PER elements), read
@@ -1999,7 +2032,7 @@ __device__ inline void load_chunk(const FT *__restrict__ p, FT (&out)[PER]) {
 //   mode non-transposed: z[g] = x (owned entries; or z[g] += x when add)
 //   mode transposed: input masked by D_i, output to yloc (summed later)
 template <int T, class FT, int NTHR, bool TRANS>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(NTHR == 256 ? 4 : 1, 8)))
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(NTHR == 256 ? 4 : (NTHR == 128 ? 2 : 1), 8)))
 void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, const int32_t *__restrict__ erow,
                   const int32_t *__restrict__ elo, const int32_t *__restrict__ order,
                   const int32_t *__restrict__ l2g, const uint8_t *__restrict__ owned, const double *__restrict__ r,
@@ -2046,113 +2079,151 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
   // gather the right-hand side R_i r (D_i R_i r when transposed) into ybuf
   for (int l = tid; l < s.n_loc; l += NTHR) ybuf[yo + l] = rhs(l);
   __syncthreads();
-  constexpr bool XPF = (SOLVE_BMAX + 1) * PER * (((int)sizeof(FT) + 3) / 4) <= 40;
-  if constexpr (!TRANS && XPF) {
+  constexpr int DEPTH = solve_depth<T, FT, NTHR>();
+  if constexpr (!TRANS && DEPTH > 0) {
     const int i = tid / G, g = tid % G;
-    // A block row's first chunk of off-diagonal tiles and its diagonal tile,
-    // in registers.  When two such sets fit the register budget, the next
-    // row's set is loaded while the current row computes (its loads do not
-    // depend on the solution); further chunks of a wide band are loaded in
-    // the row itself.  The summation order is the same either way.
+    // A block row's first chunk of off-diagonal tiles, its diagonal-tile
+    // chunk and its right-hand side entry, in registers.  DEPTH + 1 such
+    // sets rotate: while row K computes, the loads of rows K + 1 .. K +
+    // DEPTH are in flight.  Every row issues the same loads whatever its
+    // width (slots past the row's last tile re-read its diagonal tile, rows
+    // past the end re-read the last row), so that the wait before a row's
+    // arithmetic counts exactly the loads issued after that row's set;
+    // conditional loads would make it wait for all of them.  Further chunks
+    // of a wide band are loaded in the row itself.  The summation order is
+    // the same as without the rotation.
     struct RowRegs {
       FT buf[SOLVE_BMAX][PER];
       FT dv[PER];
+      double bv;
+      const FT *t0;  // tile (K, 0) of the row's storage (tile (K, J) at t0 + J T^2)
+      int c0, c1;    // off-diagonal tile columns in use
     };
-    auto load_row = [&](int K, int c0, int c1, bool lower, RowRegs &Rr) {  // off-diagonal tile columns c0 .. c1
-      load_diag(K, lower, i, g, Rr.dv);
+    // row K's off-diagonal tile columns (left of the diagonal when lower,
+    // right of it otherwise), its first chunk of them, its diagonal-tile
+    // chunk (a lane with no entry in the triangle in use reads a chunk of
+    // its row that another lane uses, and masks it) and ybuf entry K T + i
+    auto load_row = [&](int K, bool lower, RowRegs &Rr) {
+      int64_t off0;
+      int first, last;
+      R.row_info<T>(K, off0, first, last);
+      Rr.t0 = F + off0;
+      Rr.c0 = lower ? first : K + 1;
+      Rr.c1 = lower ? K - 1 : last;
+      const FT *dk = Rr.t0 + (int64_t)K * (T * T);
+      const bool used = lower ? (g * PER < i) : (g * PER + PER - 1 >= i);
+      load_chunk<FT, PER>(dk + i * T + (used ? g * PER : (lower ? 0 : T - PER)), Rr.dv);
 #pragma unroll
-      for (int t = 0; t < SOLVE_BMAX; ++t)
-        if (c0 + t <= c1) load_chunk<FT, PER>(tile(K, c0 + t) + i * T + g * PER, Rr.buf[t]);
+      for (int t = 0; t < SOLVE_BMAX; ++t) {
+        const FT *tp = (Rr.c0 + t <= Rr.c1) ? Rr.t0 + (int64_t)(Rr.c0 + t) * (T * T) : dk;
+        load_chunk<FT, PER>(tp + i * T + g * PER, Rr.buf[t]);
+      }
+      Rr.bv = ybuf[yo + min(K * T + i, s.n_loc - 1)];
     };
-    // sum over the off-diagonal tile columns c0 .. c1 of row K (first chunk
-    // from R) against the ring
-    auto off_sum = [&](int K, int c0, int c1, const RowRegs &Rr) {
+    auto off_sum = [&](const RowRegs &Rr) {
+      const int c0 = Rr.c0, c1 = Rr.c1;
       double a = 0.0;
 #pragma unroll
       for (int t = 0; t < SOLVE_BMAX; ++t)
         if (c0 + t <= c1) {
-          const double *xr = ring[(c0 + t) % RING];
+          const double *xr = ring[(c0 + t) & (RING - 1)];
 #pragma unroll
           for (int m = 0; m < PER; ++m) a += from_ft<FT>(Rr.buf[t][m]) * xr[g * PER + m];
         }
+      // (a further chunk's loads all go out before its first use; slots
+      // past c1 re-read the chunk's first tile)
       for (int C0 = c0 + SOLVE_BMAX; C0 <= c1; C0 += SOLVE_BMAX) {
         FT buf[SOLVE_BMAX][PER];
+        const FT *tc = Rr.t0 + (int64_t)C0 * (T * T);
 #pragma unroll
-        for (int t = 0; t < SOLVE_BMAX; ++t)
-          if (C0 + t <= c1) load_chunk<FT, PER>(tile(K, C0 + t) + i * T + g * PER, buf[t]);
+        for (int t = 0; t < SOLVE_BMAX; ++t) {
+          const FT *tp = (C0 + t <= c1) ? tc + t * (T * T) : tc;
+          load_chunk<FT, PER>(tp + i * T + g * PER, buf[t]);
+        }
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (C0 + t <= c1) {
-            const double *xr = ring[(C0 + t) % RING];
+            const double *xr = ring[(C0 + t) & (RING - 1)];
 #pragma unroll
             for (int m = 0; m < PER; ++m) a += from_ft<FT>(buf[t][m]) * xr[g * PER + m];
           }
       }
       return a;
     };
-    RowRegs cur, nxt;
-    // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P), P = first(K) .. K - 1
-    if (s.nt > 0) load_row(0, 0, -1, true, cur);
-    for (int K = 0; K < s.nt; ++K) {
-      if (K + 1 < s.nt) load_row(K + 1, R.first(K + 1), K, true, nxt);
-      const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
-      double a = off_sum(K, R.first(K), K - 1, cur);
+    // one block row: v_K = D_KK (b_K - sum of the off-diagonal tiles times
+    // the ring), D_KK the strict-lower (forward, unit diagonal) or upper
+    // (backward) part of the stored inverse; v_K goes to the ring and ybuf
+    auto row = [&](int K, bool lower, const RowRegs &Rr) {
+      double a = off_sum(Rr);
       a = group_sum<G>(a);
-      if (g == 0) acc_s[i] = bv - a;
+      const bool in = K * T + i < s.n_loc;
+      if (g == 0) acc_s[i] = (in ? Rr.bv : 0.0) - a;
       lds_barrier();
       double y = 0.0;
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
         const int j = g * PER + m;
-        if (j < i) y += from_ft<FT>(cur.dv[m]) * acc_s[j];
+        if (lower ? (j < i) : (j >= i)) y += from_ft<FT>(Rr.dv[m]) * acc_s[j];
       }
       y = group_sum<G>(y);
       if (g == 0) {
-        const double v = acc_s[i] + y;
+        const double v = lower ? acc_s[i] + y : y;
         ring[K % RING][i] = v;
-        if (K * T + i < s.n_loc) ybuf[yo + K * T + i] = v;
+        if (in) ybuf[yo + K * T + i] = v;
       }
       lds_barrier();
-      cur = nxt;
-    }
-    // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J), J = K + 1 .. last(K)
-    if (s.nt > 0) load_row(s.nt - 1, s.nt, s.nt - 1, false, cur);
-    for (int K = s.nt - 1; K >= 0; --K) {
-      if (K > 0) load_row(K - 1, K, R.last(K - 1), false, nxt);
-      const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
-      double a = off_sum(K, K + 1, R.last(K), cur);
-      a = group_sum<G>(a);
-      if (g == 0) acc_s[i] = bv - a;
-      lds_barrier();
-      double y = 0.0;
+    };
+    if (s.nt > 0) {
+      RowRegs S[DEPTH + 1];
+      const int nt = s.nt;
+      // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P), P = first(K) .. K - 1
 #pragma unroll
-      for (int m = 0; m < PER; ++m) {
-        const int j = g * PER + m;
-        if (j >= i) y += from_ft<FT>(cur.dv[m]) * acc_s[j];
+      for (int j = 0; j < DEPTH; ++j) {
+        load_row(min(j, nt - 1), true, S[j]);
       }
-      y = group_sum<G>(y);
-      if (g == 0) {
-        ring[K % RING][i] = y;
-        const int l = K * T + i;
-        if (l < s.n_loc) {
-          if (local) {
-            if (owned[s.l2g_off + l]) {
-              const int32_t gi = l2g[s.l2g_off + l];
-              z[gi] = add ? z[gi] + y : y;
-            }
-          } else {
-            z[l] = add ? z[l] + y : y;
-          }
+      for (int K0 = 0; K0 < nt; K0 += DEPTH + 1) {
+#pragma unroll
+        for (int j = 0; j <= DEPTH; ++j) {
+          load_row(min(K0 + j + DEPTH, nt - 1), true, S[(j + DEPTH) % (DEPTH + 1)]);
+          if (K0 + j < nt) row(K0 + j, true, S[j]);
         }
       }
-      lds_barrier();
-      cur = nxt;
+      // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J), J = K + 1 .. last(K);
+      // x overwrites y in ybuf (y_K is read before x_K is written)
+#pragma unroll
+      for (int j = 0; j < DEPTH; ++j) {
+        load_row(max(nt - 1 - j, 0), false, S[j]);
+      }
+      for (int K0 = nt - 1; K0 >= 0; K0 -= DEPTH + 1) {
+#pragma unroll
+        for (int j = 0; j <= DEPTH; ++j) {
+          load_row(max(K0 - j - DEPTH, 0), false, S[(j + DEPTH) % (DEPTH + 1)]);
+          if (K0 - j >= 0) row(K0 - j, false, S[j]);
+        }
+      }
+    }
+    // the owned entries of x to z, after the sweeps (no load of z inside
+    // them); ybuf entries were written by other threads of the workgroup
+    __syncthreads();
+    for (int l = tid; l < s.n_loc; l += NTHR) {
+      const double x = ybuf[yo + l];
+      if (local) {
+        if (owned[s.l2g_off + l]) {
+          const int32_t gi = l2g[s.l2g_off + l];
+          z[gi] = add ? z[gi] + x : x;
+        }
+      } else {
+        z[l] = add ? z[l] + x : x;
+      }
     }
   } else if constexpr (!TRANS) {
     const int i = tid / G, g = tid % G;
     // forward: y_K = Linv_KK (b_K - sum_{P<K} L_KP y_P)
     for (int K = 0; K < s.nt; ++K) {
-      const int p0 = R.first(K);
+      int64_t off0;
+      int p0, je;
+      R.row_info<T>(K, off0, p0, je);
+      const FT *t0 = F + off0;
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
       // the diagonal tile's loads go out with the first off-diagonal chunk
       FT dv[PER];
@@ -2163,7 +2234,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (P0 + t < K) {
-            const FT *A = tile(K, P0 + t);
+            const FT *A = t0 + (int64_t)(P0 + t) * (T * T);
             load_chunk<FT, PER>(A + i * T + g * PER, buf[t]);
           }
 #pragma unroll
@@ -2193,7 +2264,10 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     }
     // backward: x_K = Uinv_KK (y_K - sum_{J>K} U_KJ x_J)
     for (int K = s.nt - 1; K >= 0; --K) {
-      const int je = R.last(K);
+      int64_t off0;
+      int p0, je;
+      R.row_info<T>(K, off0, p0, je);
+      const FT *t0 = F + off0;
       const double bv = (g == 0 && K * T + i < s.n_loc) ? ybuf[yo + K * T + i] : 0.0;
       FT dv[PER];
       load_diag(K, false, i, g, dv);
@@ -2203,7 +2277,7 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
 #pragma unroll
         for (int t = 0; t < SOLVE_BMAX; ++t)
           if (J0 + t <= je) {
-            const FT *A = tile(K, J0 + t);
+            const FT *A = t0 + (int64_t)(J0 + t) * (T * T);
             load_chunk<FT, PER>(A + i * T + g * PER, buf[t]);
           }
 #pragma unroll
@@ -3187,6 +3261,7 @@ static void solve_tt(const SolveLaunch &sl, hipStream_t st) {
   if constexpr (T == 32) {
     if (thr == 1024) return solve_launch<T, FT, TR, 1024>(sl, st);
     if (thr == 512) return solve_launch<T, FT, TR, 512>(sl, st);
+    if (thr == 128) return solve_launch<T, FT, TR, 128>(sl, st);
   }
   solve_launch<T, FT, TR, 256>(sl, st);
 }

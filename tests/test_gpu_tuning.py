@@ -27,10 +27,10 @@ def test_solve_widths_agree_to_rounding(prec, two_level):
     pc.setup(vals)
     r = torch.tensor(np.random.default_rng(2).standard_normal(prob.N), device="cuda")
     out = {}
-    for th in (256, 512, 1024):
+    for th in (256, 128, 512, 1024):
         pc.set_solve_threads(th)
         out[th] = (pc.apply(r).cpu().numpy(), pc.apply(r, transpose=True).cpu().numpy())
-    for th in (512, 1024):
+    for th in (128, 512, 1024):
         for k in (0, 1):  # apply and transposed apply
             a, b = out[th][k], out[256][k]
             assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b), (th, k)
@@ -57,7 +57,8 @@ def test_autotune_picks_a_valid_fastest_candidate():
     vals = prob.jacobian(torch.tensor(u0, device="cuda"), 1.0)
     rep = sk.autotune(prob, cfg.part, cfg.n_sub, 1, vals, coarse=coarse, applies_per_setup=10, reps=3)
     ok = [c for c in rep["candidates"] if c["status"] == 0]
-    assert {(c["tile"], c["solve_threads"]) for c in rep["candidates"]} == {(32, 256), (32, 512), (32, 1024), (16, 256)}
+    assert {(c["tile"], c["solve_threads"]) for c in rep["candidates"]} == {(32, 256), (32, 128), (32, 512), (32, 1024),
+                                                                           (16, 256)}
     assert ok and all(c["apply_ms"] > 0 and c["setup_ms"] > 0 for c in ok)
     best = min(ok, key=lambda c: c["score_ms"])
     assert (rep["tile"], rep["solve_threads"]) == (best["tile"], best["solve_threads"])
@@ -159,7 +160,7 @@ def test_batch_autotune_on_the_ensemble():
     u = torch.tensor(np.concatenate([c.u0 for c in bc.instances]), device="cuda")
     b.step(u, bc.dt, tol=1e-10)
     t = b.autotune(reps=2)
-    assert t["solve_threads"] in (256, 512, 1024) and len(t["candidates"]) == 3
+    assert t["solve_threads"] in (256, 128, 512, 1024) and len(t["candidates"]) == 4
     assert b.autotune(reps=2)["from_cache"]
     per = b.step(u, bc.dt, tol=1e-10)
     assert all(p["res_hist"][-1] <= 1e-10 for p in per)
