@@ -472,6 +472,7 @@ struct seird_precond_s {
   int32_t *z_col = nullptr, *zt_col = nullptr;
   double *z_val = nullptr, *zt_val = nullptr;
   double *rc = nullptr, *xc = nullptr, *cscratch = nullptr, *ybuf = nullptr;
+  double *cpart = nullptr;  // partial sums of the coarse triangular mat-vecs
   // explicit inverses of the coarse triangular factors (tile 32, when they
   // fit the budget); coarse_solver 1 uses them, 0 the band sweeps
   double *Xc = nullptr, *Wc = nullptr;
@@ -596,6 +597,7 @@ struct seird_precond_s {
     dev_free(coarse_dev); dev_free(gp); dev_free(gq); dev_free(gref); dev_free(cperm); dev_free(gptr); dev_free(gw);
     dev_free(z_ptr); dev_free(zt_ptr); dev_free(z_col); dev_free(zt_col); dev_free(z_val); dev_free(zt_val);
     dev_free(rc); dev_free(xc); dev_free(cscratch); dev_free(ybuf); dev_free(t1); dev_free(Xc); dev_free(Wc);
+    dev_free(cpart);
     if (ws_base) unregister_workspace(ws_base);
   }
 
@@ -682,7 +684,7 @@ struct seird_precond_s {
       return;
     }
     if (coarse_solver == 1) {
-      launch_coarse_inverse_apply(Xc, Wc, Fc, ph.coarse, coarse_block, rc, xc, cscratch, transpose, st);
+      launch_coarse_inverse_apply(Xc, Wc, Fc, ph.coarse, coarse_block, rc, xc, cscratch, cpart, transpose, st);
       launch_coarse_prolong(z_ptr, z_col, z_val, cperm, xc, z, prob->mh.n, st);
       return;
     }
@@ -1700,6 +1702,8 @@ static seird_precond precond_create_impl(seird_problem p, const seird_schwarz_op
         // sized for the full inverses, so that any super-block size fits
         pc->Xc = dev_alloc<double>((size_t)(nt * (nt + 1) / 2) * 1024);
         pc->Wc = dev_alloc<double>((size_t)(nt * (nt + 1) / 2) * 1024);
+        // the partial sums of a mat-vec over the largest block (any block size)
+        pc->cpart = dev_alloc<double>((size_t)coarse_tri_chunks((int)nt) * T);
         pc->coarse_solver = 1;
         pc->coarse_block = (int)std::min<int64_t>(nt, std::max({COARSE_BLOCK, ph.coarse.bl, ph.coarse.bu}));
         pc->coarse_block_next = pc->coarse_block;

@@ -182,7 +182,10 @@ void launch_coarse_inverse(const double *F, const SubInfo &cs, int S, double *X,
 // coarse solve z = A_c^{-1} r (or A_c^{-T} r) by the block sweep over those
 // super-blocks; r (overwritten), z, tmp: nt * 32 doubles
 void launch_coarse_inverse_apply(const double *X, const double *W, const double *F, const SubInfo &cs, int S,
-                                 double *r, double *z, double *tmp, int transpose, hipStream_t st);
+                                 double *r, double *z, double *tmp, double *part, int transpose, hipStream_t st);
+// partial-sum slots (of 32 doubles) that one triangular mat-vec over a block
+// of nt tile rows uses
+int64_t coarse_tri_chunks(int nt);
 
 void launch_seg_mdot(const SegHost &g, const double *V, int64_t ldv, int nv, const double *w, int with_self,
                      double *partials, hipStream_t st);

@@ -2705,78 +2705,115 @@ __global__ __launch_bounds__(256) void k_coarse_tri_inverse(const double *__rest
 }
 
 // y = M x for a packed triangular tile matrix M (X: lower, W: upper), or
-// y = M^T x (TRANS).  One workgroup per output tile row, longest rows
-// first.  Non-transposed: thread = (row i, 4-column chunk g) of every tile
-// of the row; transposed: thread = (column j, 4-row group g) of every tile
-// of the column.  FP64 throughout.
+// y = M^T x (TRANS), in two launches.  The tile rows of M (the tile columns
+// when transposed) are cut into chunks of TRI_CW tiles, one workgroup per
+// chunk, so that the longest rows no longer set the time of the launch;
+// each chunk writes its partial sums, and a second launch adds a row's
+// partials in chunk order (fixed order, so results are reproducible).
+// Row K (0-based in the block of nt rows) holds len(K) tiles: K + 1 when
+// the stored rows grow (lower non-transposed, upper transposed), else
+// nt - K.  Chunks are numbered row by row: row K's first chunk is
+// before(K) = C(K) (growing) or C(nt) - C(nt - K), with C(n) the sum of
+// ceil(m / TRI_CW) over m = 1 .. n; C(nt) chunks in all.
+constexpr int TRI_CW = 8;
+__host__ __device__ inline int64_t tri_csum(int n) {
+  const int64_t q = n / TRI_CW, r = n % TRI_CW;
+  return n + TRI_CW * q * (q - 1) / 2 + r * q;
+}
+__host__ __device__ inline int64_t tri_before(int K, int nt, bool grows) {
+  return grows ? tri_csum(K) : tri_csum(nt) - tri_csum(nt - K);
+}
+int64_t coarse_tri_chunks(int nt) { return tri_csum(nt); }
+
 template <bool UPPER, bool TRANS>
 __global__ __launch_bounds__(256) void k_coarse_tri_gemv(const double *__restrict__ M, int nt,
-                                                         const double *__restrict__ x, double *__restrict__ y) {
+                                                         const double *__restrict__ x, double *__restrict__ part) {
   constexpr int T = 32;
   __shared__ double red[8][T];
   const int tid = threadIdx.x;
-  // the stored tiles of output row K: lower non-transposed and upper
-  // transposed rows hold K + 1 tiles (longest at K = nt - 1)
   const bool grows = (!UPPER) != TRANS;
-  const int K = grows ? nt - 1 - (int)blockIdx.x : (int)blockIdx.x;
-  const int c_lo = grows ? 0 : K, c_hi = grows ? K : nt - 1;
-  auto tile = [&](int c) -> const double * {
-    // tile (row, col) of M: M_Kc, or M_cK when transposed
-    const int r0 = TRANS ? c : K, c0 = TRANS ? K : c;
+  // the chunk's row: the last K with before(K) <= chunk (uniform search)
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = nt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tri_before(mid, nt, grows) <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int K = lo;
+  const int c = (int)(b - tri_before(K, nt, grows));
+  const int r_lo = grows ? 0 : K, r_hi = grows ? K : nt - 1;
+  const int c_lo = r_lo + c * TRI_CW, c_hi = min(r_hi, c_lo + TRI_CW - 1);
+  auto tile = [&](int cc) -> const double * {
+    // tile (row, col) of M: M_K,cc, or M_cc,K when transposed
+    const int r0 = TRANS ? cc : K, c0 = TRANS ? K : cc;
     return M + (UPPER ? upper_packed(r0, c0, nt) : lower_packed(r0, c0)) * (T * T);
   };
   double acc = 0.0;
   if constexpr (!TRANS) {
     const int i = tid >> 3, g = tid & 7;
-    int c = c_lo;
-    for (; c + 3 <= c_hi; c += 4) {
-      double4 a[4], b[4];
+    int cc = c_lo;
+    for (; cc + 3 <= c_hi; cc += 4) {
+      double4 a4[4], b4[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        a[u] = *reinterpret_cast<const double4 *>(tile(c + u) + i * T + 4 * g);
-        b[u] = *reinterpret_cast<const double4 *>(x + (int64_t)(c + u) * T + 4 * g);
+        a4[u] = *reinterpret_cast<const double4 *>(tile(cc + u) + i * T + 4 * g);
+        b4[u] = *reinterpret_cast<const double4 *>(x + (int64_t)(cc + u) * T + 4 * g);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc += a[u].x * b[u].x + a[u].y * b[u].y + a[u].z * b[u].z + a[u].w * b[u].w;
+      for (int u = 0; u < 4; ++u)
+        acc += a4[u].x * b4[u].x + a4[u].y * b4[u].y + a4[u].z * b4[u].z + a4[u].w * b4[u].w;
     }
-    for (; c <= c_hi; ++c) {
-      const double4 a = *reinterpret_cast<const double4 *>(tile(c) + i * T + 4 * g);
-      const double4 b = *reinterpret_cast<const double4 *>(x + (int64_t)c * T + 4 * g);
-      acc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+    for (; cc <= c_hi; ++cc) {
+      const double4 a4 = *reinterpret_cast<const double4 *>(tile(cc) + i * T + 4 * g);
+      const double4 b4 = *reinterpret_cast<const double4 *>(x + (int64_t)cc * T + 4 * g);
+      acc += a4.x * b4.x + a4.y * b4.y + a4.z * b4.z + a4.w * b4.w;
     }
-    // sum the 8 chunks of row i (consecutive lanes)
+    // sum the 8 column groups of row i (consecutive lanes)
 #pragma unroll
     for (int o = 1; o < 8; o <<= 1) acc += __shfl_xor(acc, o, 8);
-    if (g == 0) y[(int64_t)K * T + i] = acc;
+    if (g == 0) part[b * T + i] = acc;
   } else {
     const int j = tid & 31, g = tid >> 5;  // rows 4g .. 4g+3 of each tile
-    int c = c_lo;
-    for (; c + 1 <= c_hi; c += 2) {
-      double a[2][4], b[2][4];
+    int cc = c_lo;
+    for (; cc + 1 <= c_hi; cc += 2) {
+      double a2[2][4], b2[2][4];
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          a[u][m] = tile(c + u)[(4 * g + m) * T + j];
-          b[u][m] = x[(int64_t)(c + u) * T + 4 * g + m];
+          a2[u][m] = tile(cc + u)[(4 * g + m) * T + j];
+          b2[u][m] = x[(int64_t)(cc + u) * T + 4 * g + m];
         }
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) acc += a[u][m] * b[u][m];
+        for (int m = 0; m < 4; ++m) acc += a2[u][m] * b2[u][m];
     }
-    for (; c <= c_hi; ++c)
+    for (; cc <= c_hi; ++cc)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) acc += tile(c)[(4 * g + m) * T + j] * x[(int64_t)c * T + 4 * g + m];
+      for (int m = 0; m < 4; ++m) acc += tile(cc)[(4 * g + m) * T + j] * x[(int64_t)cc * T + 4 * g + m];
     red[g][j] = acc;
     __syncthreads();
     if (tid < T) {
       double t = 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) t += red[q][tid];
-      y[(int64_t)K * T + tid] = t;
+      part[b * T + tid] = t;
     }
   }
+}
+
+// y_K = sum of row K's chunk partials, in chunk order (one workgroup of T
+// threads per row)
+__global__ __launch_bounds__(32) void k_coarse_tri_reduce(const double *__restrict__ part, int nt, int grows,
+                                                          double *__restrict__ y) {
+  constexpr int T = 32;
+  const int K = blockIdx.x, i = threadIdx.x;
+  const int64_t b0 = tri_before(K, nt, grows), b1 = tri_before(K + 1, nt, grows);
+  double t = 0.0;
+  for (int64_t b = b0; b < b1; ++b) t += part[b * T + i];
+  y[(int64_t)K * T + i] = t;
 }
 
 // Coupling step of the coarse block sweep: v_K -= (tiles of row K of the
@@ -2834,35 +2871,36 @@ void launch_coarse_inverse(const double *F, const SubInfo &cs, int S, double *X,
 }
 
 void launch_coarse_inverse_apply(const double *X, const double *W, const double *F, const SubInfo &cs, int S,
-                                 double *r, double *z, double *tmp, int transpose, hipStream_t st) {
+                                 double *r, double *z, double *tmp, double *part, int transpose, hipStream_t st) {
   constexpr int T = 32;
   const int nt = cs.nt, NS = (nt + S - 1) / S;
-  auto gemv = [&](auto kern, const double *M, int sb, const double *x, double *y) {
+  auto gemv = [&](auto kern, bool grows, const double *M, int sb, const double *x, double *y) {
     const int s0 = sb * S, nb = std::min(S, nt - s0);
     const int64_t off = (int64_t)sb * S * (S + 1) / 2 * (T * T);
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, M + off, nb, x + (int64_t)s0 * T, y + (int64_t)s0 * T);
+    hipLaunchKernelGGL(kern, dim3((unsigned)tri_csum(nb)), dim3(256), 0, st, M + off, nb, x + (int64_t)s0 * T, part);
+    hipLaunchKernelGGL(k_coarse_tri_reduce, dim3(nb), dim3(T), 0, st, part, nb, (int)grows, y + (int64_t)s0 * T);
   };
   if (!transpose) {  // L y = r (y in tmp) forward, then U z = y backward
     for (int sb = 0; sb < NS; ++sb) {
       if (sb > 0)
         hipLaunchKernelGGL((k_coarse_couple<false, false>), dim3(cs.bl), dim3(256), 0, st, F, cs, S, sb, r, tmp);
-      gemv(k_coarse_tri_gemv<false, false>, X, sb, r, tmp);
+      gemv(k_coarse_tri_gemv<false, false>, true, X, sb, r, tmp);
     }
     for (int sb = NS - 1; sb >= 0; --sb) {
       if (sb < NS - 1)
         hipLaunchKernelGGL((k_coarse_couple<true, false>), dim3(cs.bu), dim3(256), 0, st, F, cs, S, sb, tmp, z);
-      gemv(k_coarse_tri_gemv<true, false>, W, sb, tmp, z);
+      gemv(k_coarse_tri_gemv<true, false>, false, W, sb, tmp, z);
     }
   } else {  // U^T y = r forward, then L^T z = y backward
     for (int sb = 0; sb < NS; ++sb) {
       if (sb > 0)
         hipLaunchKernelGGL((k_coarse_couple<true, true>), dim3(cs.bu), dim3(256), 0, st, F, cs, S, sb, r, tmp);
-      gemv(k_coarse_tri_gemv<true, true>, W, sb, r, tmp);
+      gemv(k_coarse_tri_gemv<true, true>, true, W, sb, r, tmp);
     }
     for (int sb = NS - 1; sb >= 0; --sb) {
       if (sb < NS - 1)
         hipLaunchKernelGGL((k_coarse_couple<false, true>), dim3(cs.bl), dim3(256), 0, st, F, cs, S, sb, tmp, z);
-      gemv(k_coarse_tri_gemv<false, true>, X, sb, tmp, z);
+      gemv(k_coarse_tri_gemv<false, true>, false, X, sb, tmp, z);
     }
   }
 }
