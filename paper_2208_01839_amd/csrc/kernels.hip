@@ -1997,10 +1997,12 @@ constexpr int solve_bmax() {
   // float64 at 512 threads: 8 tiles (a typical band), so that two block
   // rows' first chunks fit the cross-row prefetch budget
   if (T == 32 && NTHR == 512 && sizeof(FT) == 8) return 8;
+  // otherwise as many as 48 registers hold, at most 8 (rows past their
+  // last tile re-read the diagonal tile in the slots beyond it)
   constexpr int per = T * T / NTHR;  // tile elements per lane
   constexpr int regs = per * (sizeof(FT) >= 4 ? (int)sizeof(FT) / 4 : 1);
   constexpr int b = 48 / regs;
-  return b > 16 ? 16 : (b < 1 ? 1 : b);
+  return b > 8 ? 8 : (b < 1 ? 1 : b);
 }
 // block rows ahead of the one computing whose first tile chunk is already
 // being loaded (0: every row loads its own tiles)
