@@ -84,7 +84,8 @@ typedef struct {
  *    preconditioner apply: 0 = float64, 1 = float32, 2 = bfloat16.  With
  *    tile 32 and factor_prec 1 or 2 the subdomain factorisation runs in
  *    float32 on the float32 MFMA (float32 accumulation); factor_prec 2 then
- *    rounds the float32 factors to bfloat16 for the apply.  With tile 16
+ *    rounds the float32 factors to bfloat16 for the apply (each tile as it
+ *    becomes final).  With tile 16
  *    the factorisation runs in float64 and the factors are rounded to the
  *    storage precision.  The coarse factorisation is always float64, and
  *    the vectors and accumulations of the apply stay float64.

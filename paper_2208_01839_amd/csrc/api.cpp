@@ -1844,6 +1844,8 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
   fl.bs = ph.bs;
   fl.Fs = pc->Fs;
   fl.sub_float = pc->sub_float;
+  // bfloat16 factors: the float32 factorisation writes their copy itself
+  fl.Fh = (ph.prec == 2 && pc->sub_float) ? pc->Fb : nullptr;
   fl.sub_entries = ph.factor_entries;
   fl.Fc = pc->Fc;
   fl.coarse_entries = ph.coarse_entries;
@@ -1911,7 +1913,7 @@ static void precond_setup_raw(seird_precond pc, const double *diag, const double
     else
       precond_setup_raw(kc.cpc, kc.cvals, kc.cvals + 25 * nc, st);
   }
-  if (pc->Fb) launch_convert(pc->Fb, ph.prec, pc->Fs, pc->sub_float ? 1 : 0, ph.factor_entries, st);
+  if (pc->Fb && !fl.Fh) launch_convert(pc->Fb, ph.prec, pc->Fs, pc->sub_float ? 1 : 0, ph.factor_entries, st);
   int status = 0;
   HIPCHECK(hipMemcpyAsync(&status, pc->status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));

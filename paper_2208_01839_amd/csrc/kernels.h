@@ -32,6 +32,7 @@ struct FactorLaunch {
   bool dense_off = false;   // bs 5 with dense off-diagonal blocks, off [slots][25] (the coarse graph matrix)
   void *Fs = nullptr;       // subdomain tile-envelope storage (float64, or float32 if sub_float)
   bool sub_float = false;   // factorise the subdomains in float32
+  void *Fh = nullptr;       // with sub_float and tile 32: also write each final factor entry here in bfloat16
   int64_t sub_entries = 0;
   double *Fc = nullptr;     // coarse tile-band storage (float64)
   int64_t coarse_entries = 0;

@@ -1519,8 +1519,10 @@ struct Mfma<float> {
 // global memory (read, then replaced by the strict lower of L^{-1} and the
 // upper of U^{-1}); Li, Ui: LDS tiles that receive L^{-1} (dense unit lower)
 // and U^{-1} (dense upper).  Raises *status on a zero or nonfinite pivot.
+// dh, when given: the tile's bfloat16 copy, written with dk.
 template <class CT, int NT>
-__device__ void lu_inv_diag_regs(CT *__restrict__ dk, CT (*Li)[33], CT (*Ui)[33], int *status) {
+__device__ void lu_inv_diag_regs(CT *__restrict__ dk, CT (*Li)[33], CT (*Ui)[33], int *status,
+                                 __hip_bfloat16 *__restrict__ dh = nullptr) {
   constexpr int T = 32, RS = NT / T, R = T / RS;
   static_assert(NT % T == 0 && R >= 1 && R <= 4, "workgroup size");
   __shared__ CT pub[2][4][T];  // [parity][row A, row X, row Z, column A]
@@ -1585,7 +1587,9 @@ __device__ void lu_inv_diag_regs(CT *__restrict__ dk, CT (*Li)[33], CT (*Ui)[33]
   __syncthreads();
   for (int e = tid; e < T * T; e += NT) {
     const int i = e / T, j = e % T;
-    dk[e] = (i > j) ? Li[i][j] : Ui[i][j];
+    const CT v = (i > j) ? Li[i][j] : Ui[i][j];
+    dk[e] = v;
+    if (dh) dh[e] = to_ft<__hip_bfloat16>((double)v);
   }
 }
 
@@ -1609,11 +1613,11 @@ __device__ void lu_inv_diag_regs(CT *__restrict__ dk, CT (*Li)[33], CT (*Ui)[33]
 // compute unit and hide each other's latencies.  Launched with a queue
 // counter, a grid smaller than the subdomain count draws subdomains until
 // they are exhausted (every workgroup exits once the counter passes nsub).
-template <class CT, int NW, int QW>
+template <class CT, int NW, int QW, bool HCOPY>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4 ? 2 : 1))) void k_band_lu32(
     CT *__restrict__ F, const SubInfo *__restrict__ subs, const int32_t *__restrict__ erow,
     const int32_t *__restrict__ elo, const int32_t *__restrict__ order, int nsub, int *__restrict__ queue,
-    int *status) {
+    int *status, __hip_bfloat16 *__restrict__ Fh) {
   constexpr int T = 32, NT = 64 * NW, CH = NW * QW;
   typedef typename Mfma<CT>::v4 v4;
   __shared__ CT Ui[T][T + 1];     // U_KK^{-1}, dense upper
@@ -1634,7 +1638,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4
     const int je = R.last(K), nu = je - K;
     const int ie = je;
     // (1) diagonal tile: LU and both inverses in one sweep
-    lu_inv_diag_regs<CT, NT>(F + R.at<T>(K, K), Li, Ui, status);
+    lu_inv_diag_regs<CT, NT>(F + R.at<T>(K, K), Li, Ui, status, HCOPY ? Fh + R.at<T>(K, K) : nullptr);
     // the panel in chunks of CH tiles (one chunk unless the row is wider)
     for (int c0 = 0; c0 < nu; c0 += CH) {
       // (2) the wave's U-panel tiles of this chunk, kept as B operands:
@@ -1673,6 +1677,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4
                 ub[q][bj][4 * bi + v] = acc[bi][bj][v];
                 g[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr] = acc[bi][bj][v];
               }
+          // U_KJ is final: its bfloat16 copy
+          if constexpr (HCOPY) {
+            __hip_bfloat16 *gh = Fh + R.at<T>(K, K + 1 + jj);
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+              for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                  gh[(16 * bi + Mfma<CT>::row(lk, v)) * T + 16 * bj + lr] = to_ft<__hip_bfloat16>((double)acc[bi][bj][v]);
+          }
         }
       }
       // (3) block rows below: L_IK (first chunk: computed and stored; later
@@ -1713,6 +1728,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4
           if (wave < 4) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) aik[(16 * qi + Mfma<CT>::row(lk, v)) * T + 16 * qj + lr] = l[v];
+            // L_IK is final: its bfloat16 copy
+            if constexpr (HCOPY) {
+              __hip_bfloat16 *ah = Fh + R.at<T>(I, K);
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                ah[(16 * qi + Mfma<CT>::row(lk, v)) * T + 16 * qj + lr] = to_ft<__hip_bfloat16>((double)l[v]);
+            }
           }
         } else {
           for (int e = tid; e < T * T; e += NT) Sx[buf][e / T][e % T] = aik[e];
@@ -3170,8 +3192,12 @@ static void band_lu32(const FactorLaunch &fl, CT *F, hipStream_t st) {
   if (sizeof(CT) == 4) {
     // float32: four waves with three panel tiles each, two workgroups per
     // compute unit with room left for the float64 coarse-chain kernels
-    hipLaunchKernelGGL((k_band_lu32<CT, 4, 3>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo,
-                       fl.order, fl.nsub, nullptr, fl.status);
+    if (fl.Fh)
+      hipLaunchKernelGGL((k_band_lu32<CT, 4, 3, true>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow,
+                         fl.elo, fl.order, fl.nsub, nullptr, fl.status, (__hip_bfloat16 *)fl.Fh);
+    else
+      hipLaunchKernelGGL((k_band_lu32<CT, 4, 3, false>), dim3(fl.nsub), dim3(256), 0, st, F, fl.subs, fl.erow,
+                         fl.elo, fl.order, fl.nsub, nullptr, fl.status, (__hip_bfloat16 *)nullptr);
     return;
   }
   // float64: two workgroups of four waves per compute unit.  Beside a
@@ -3188,8 +3214,8 @@ static void band_lu32(const FactorLaunch &fl, CT *F, hipStream_t st) {
       hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, queue, grid, 1);
     }
   }
-  hipLaunchKernelGGL((k_band_lu32<CT, 4, 2>), dim3(grid), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo, fl.order,
-                     fl.nsub, queue, fl.status);
+  hipLaunchKernelGGL((k_band_lu32<CT, 4, 2, false>), dim3(grid), dim3(256), 0, st, F, fl.subs, fl.erow, fl.elo,
+                     fl.order, fl.nsub, queue, fl.status, (__hip_bfloat16 *)nullptr);
 }
 
 static void coarse_factor(const FactorLaunch &fl, const double *diag, const double *off, hipStream_t st) {
