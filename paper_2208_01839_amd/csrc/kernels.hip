@@ -2101,7 +2101,22 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     return v;
   };
   // gather the right-hand side R_i r (D_i R_i r when transposed) into ybuf
-  for (int l = tid; l < s.n_loc; l += NTHR) ybuf[yo + l] = rhs(l);
+  // (in batches of GB entries per thread, so that their index and value
+  // loads are in flight together)
+  constexpr int GB = 8;
+  for (int l0 = 0; l0 < s.n_loc; l0 += GB * NTHR) {
+    double v[GB];
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      const int l = l0 + q * NTHR + tid;
+      v[q] = l < s.n_loc ? rhs(l) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      const int l = l0 + q * NTHR + tid;
+      if (l < s.n_loc) ybuf[yo + l] = v[q];
+    }
+  }
   __syncthreads();
   constexpr int DEPTH = solve_depth<T, FT, NTHR>();
   if constexpr (!TRANS && DEPTH > 0) {
@@ -2229,16 +2244,19 @@ void k_band_solve(const FT *__restrict__ F, const SubInfo *__restrict__ subs, co
     // the owned entries of x to z, after the sweeps (no load of z inside
     // them); ybuf entries were written by other threads of the workgroup
     __syncthreads();
-    for (int l = tid; l < s.n_loc; l += NTHR) {
-      const double x = ybuf[yo + l];
-      if (local) {
-        if (owned[s.l2g_off + l]) {
-          const int32_t gi = l2g[s.l2g_off + l];
-          z[gi] = add ? z[gi] + x : x;
-        }
-      } else {
-        z[l] = add ? z[l] + x : x;
+    for (int l0 = 0; l0 < s.n_loc; l0 += GB * NTHR) {
+      double x[GB];
+      int32_t gi[GB];
+#pragma unroll
+      for (int q = 0; q < GB; ++q) {
+        const int l = l0 + q * NTHR + tid;
+        const bool in = l < s.n_loc;
+        x[q] = in ? ybuf[yo + l] : 0.0;
+        gi[q] = !in ? -1 : (local ? (owned[s.l2g_off + l] ? l2g[s.l2g_off + l] : -1) : l);
       }
+#pragma unroll
+      for (int q = 0; q < GB; ++q)
+        if (gi[q] >= 0) z[gi[q]] = add ? z[gi[q]] + x[q] : x[q];
     }
   } else if constexpr (!TRANS) {
     const int i = tid / G, g = tid % G;
