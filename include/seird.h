@@ -613,6 +613,13 @@ typedef struct {
   double tol;          /* epsilon tolerance of Eq. picardtol */
   int32_t max_sweeps;  /* 1 .. SEIRD_MAX_PGS */
   int32_t strict_linear; /* 1: a GMRES solve stopping at max_it fails the step */
+  /* 1: each diffusing compartment's preconditioner is set up at the first
+   * sweep of the step and kept for its later sweeps (one setup per
+   * compartment and step; each compartment then holds its own factors);
+   * 0: a setup before every solve.  The fixed point does not depend on it,
+   * only the GMRES counts do.  seird22_step ignores it (its preconditioners
+   * are kept by design). */
+  int32_t pc_lag;
 } seird_pgs_opts;
 typedef struct {
   int32_t sweeps;

@@ -130,7 +130,8 @@ class _Stats22(ctypes.Structure):
 
 
 class _PgsOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("strict_linear", ctypes.c_int32)]
+    _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("strict_linear", ctypes.c_int32),
+                ("pc_lag", ctypes.c_int32)]
 
 
 class _PgsStats(ctypes.Structure):
@@ -945,10 +946,12 @@ class PicardGS:
             _lib.seird_pgs_destroy(self.h)
             self.h = None
 
-    def step(self, u, dt, tol=1e-10, max_sweeps=50, strict_linear=False, gmres_max_it=200, **kw):
+    def step(self, u, dt, tol=1e-10, max_sweeps=50, strict_linear=False, gmres_max_it=200, pc_lag=False, **kw):
         """One implicit step in place on u (float64 CUDA [n, 5]); sweeps
-        until epsilon (Eq. picardtol) <= tol.  Returns the statistics."""
-        po = _PgsOpts(float(tol), int(max_sweeps), int(bool(strict_linear)))
+        until epsilon (Eq. picardtol) <= tol.  pc_lag: set each diffusing
+        compartment's preconditioner up at the first sweep only.  Returns
+        the statistics."""
+        po = _PgsOpts(float(tol), int(max_sweeps), int(bool(strict_linear)), int(bool(pc_lag)))
         o = _krylov(max_it=gmres_max_it, **kw)
         s = _PgsStats()
         code = lib().seird_pgs_step(self.h, _dptr(u, self.problem.N, "u"), float(dt), ctypes.byref(po),

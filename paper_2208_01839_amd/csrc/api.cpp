@@ -2758,10 +2758,16 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
 struct seird_pgs_s {
   seird_problem prob = nullptr;
   seird_precond pc = nullptr;  // bs = 1
+  // kept per compartment (pc_lag), sharing pc's host structures; made on
+  // first use from the creation's options and partition
+  seird_precond lag[NC] = {};
+  seird_schwarz_opts opts{};
+  std::vector<int32_t> part;
   SegHost seg, seg_act, seg_re;  // one segment of n entries
   double *uk = nullptr, *Kd = nullptr, *Ko = nullptr, *sdiag = nullptr, *soff = nullptr, *r = nullptr,
          *delta = nullptr;
   ~seird_pgs_s() {
+    for (seird_precond q : lag) delete q;
     delete pc;
     dev_free(seg.d_seg_start); dev_free(seg.d_blk_start); dev_free(seg.d_block_seg);
     dev_free(uk); dev_free(Kd); dev_free(Ko); dev_free(sdiag); dev_free(soff); dev_free(r); dev_free(delta);
@@ -2797,8 +2803,9 @@ static void pgs_step_impl(seird_pgs g, double *u, double dt, const seird_pgs_opt
   ops.spmv = [g](const double *x, const double *b, double *y, hipStream_t s) {
     launch_scalar_spmv(g->prob->md, g->sdiag, g->soff, x, b, y, s);
   };
-  ops.prec = [g](const double *r, double *z, hipStream_t s, const uint8_t *, const std::vector<uint8_t> *) {
-    g->pc->apply(nullptr, r, z, 0, s);
+  seird_precond cur = g->pc;  // the preconditioner of the compartment being solved
+  ops.prec = [&cur](const double *r, double *z, hipStream_t s, const uint8_t *, const std::vector<uint8_t> *) {
+    cur->apply(nullptr, r, z, 0, s);
   };
   seird_krylov_opts o = ko;
   o.graphs = 0;
@@ -2814,8 +2821,17 @@ static void pgs_step_impl(seird_pgs g, double *u, double dt, const seird_pgs_opt
         continue;
       }
       auto t0 = clk::now();
-      precond_setup_raw(g->pc, g->sdiag, g->soff, st);
-      stats.pc_setups++;
+      cur = g->pc;
+      bool setup = true;
+      if (po.pc_lag) {
+        if (!g->lag[c]) g->lag[c] = precond_create_impl(p, &g->opts, g->part.data(), 1, &g->pc->ph);
+        cur = g->lag[c];
+        setup = k == 1;
+      }
+      if (setup) {
+        precond_setup_raw(cur, g->sdiag, g->soff, st);
+        stats.pc_setups++;
+      }
       stats.t_setup_ms += std::chrono::duration<double, std::milli>(clk::now() - t0).count();
       t0 = clk::now();
       gmres_core(p, ops, g->r, g->delta, o, ks, std::vector<uint8_t>(1, 1), st, KrylovWork{});
@@ -2870,6 +2886,8 @@ seird_status seird_pgs_create(seird_problem p, const seird_schwarz_opts *opts, c
   try {
     g->prob = p;
     g->pc = precond_create_impl(p, opts, part, 1);
+    g->opts = *opts;
+    g->part.assign(part, part + p->mh.n);
     const int64_t n = p->mh.n, ns = (int64_t)p->mh.col.size();
     SegHost sg;
     sg.S = 1;

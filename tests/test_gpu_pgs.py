@@ -111,3 +111,26 @@ def test_pgs_reports_non_convergence():
     with pytest.raises(sk.SeirdError) as e:
         pgs.step(u, 0.3, tol=1e-14, max_sweeps=2)
     assert e.value.code == -7
+
+
+def test_lagged_preconditioners_reach_the_same_fixed_point():
+    """With each compartment's preconditioner set up at the first sweep only
+    (pc_lag) the step reaches the same fixed point with one setup per
+    diffusing compartment, on two steps in a row (the second sets up anew)."""
+    cfg, p, u0 = _case()
+    geo = fem.Geometry(cfg.xy, cfg.tri)
+    prob = sk.Problem(cfg.xy, cfg.tri, p)
+    pgs = sk.PicardGS(prob, cfg.part, cfg.n_sub, 1)
+    ua = torch.tensor(u0, device="cuda")
+    ub = ua.clone()
+    uo = u0.copy()
+    for _ in range(2):
+        sa = pgs.step(ua, 0.3, tol=1e-13, rtol=1e-12)
+        sb = pgs.step(ub, 0.3, tol=1e-13, rtol=1e-12, pc_lag=True)
+        uo, _ = newton.picard_gs_step(uo, 0.3, geo, p, None, tol=1e-13)
+        assert sb["pc_setups"] == 4 and sa["pc_setups"] == 4 * sa["sweeps"]
+        assert abs(sb["sweeps"] - sa["sweeps"]) <= 1
+        assert sb["res_scaled"] <= 1e-10
+    torch.cuda.synchronize()
+    assert max(field_errors(ub.cpu().numpy(), uo)) <= 1e-8
+    assert max(field_errors(ub.cpu().numpy(), ua.cpu().numpy())) <= 1e-9
