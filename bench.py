@@ -66,7 +66,7 @@ def build_workload(args):
     return cfg, coarse
 
 
-def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0, threads=256, until=0):
+def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0, threads=256, until=0, pc_keep=0):
     prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
     tune = None
     if tile == "auto":
@@ -86,7 +86,8 @@ def run_steps(sk, torch, cfg, coarse, prec, steps, warmup, tile, pc_reuse=0, thr
     info = pc.info()
     u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
     kw = dict(tol=cfg.newton_tol, max_it=cfg.newton_max_it, restart=cfg.gmres_restart,
-              rtol=cfg.gmres_rtol, atol=cfg.gmres_atol, dtol=cfg.gmres_dtol, pc_reuse=pc_reuse)
+              rtol=cfg.gmres_rtol, atol=cfg.gmres_atol, dtol=cfg.gmres_dtol, pc_reuse=pc_reuse,
+              pc_keep_steps=pc_keep)
     for w in range(warmup):
         st = sk.step(prob, pc, u, cfg.dt, **kw)
         log(f"[bench] prec={prec} warmup step {w}: newton={st['newton_its']} gmres={st['gmres_its']}")
@@ -620,6 +621,9 @@ def main():
                     help="timed steps of the two-grid RAS-V2 leg (one-level RAS runs one step; 0: skip both)")
     ap.add_argument("--m22-steps", type=int, default=2,
                     help="timed steps of the 22-compartment leg (0: skip)")
+    ap.add_argument("--keep-steps", type=int, default=2,
+                    help="FP64 leg repeated with each step's preconditioner setup kept for this many "
+                         "later steps (0: skip)")
     ap.add_argument("--pgs-tol", type=float, default=1e-10,
                     help="epsilon tolerance of the Picard-Gauss-Seidel sweeps")
     ap.add_argument("--cpu-workers", type=int, default=16,
@@ -720,6 +724,26 @@ def main():
         log("[bench] precision legs on the nested instance against the oracle's step-30 state")
         mixed["vs_oracle_nested"] = oracle_precision_leg(sk, torch, args)
         out["mixed"] = mixed
+    if args.keep_steps > 0:
+        # the headline leg again, a setup serving up to 1 + keep_steps steps
+        tk, thk = args.tuned.get(0, (32, 256))
+        rk = run_steps(sk, torch, cfg, coarse, 0, args.steps, args.warmup, tk, args.pc_reuse, thk,
+                       until=res["steps_done"], pc_keep=args.keep_steps)
+        out["kept_setups"] = {
+            "steps_per_s": args.steps / rk["seconds"], "vs_headline": (args.steps / rk["seconds"]) / value,
+            "keep_steps": args.keep_steps,
+            "setups_per_step": [st["pc_setups"] for st in rk["stats"]],
+            "newton_its": [st["newton_its"] for st in rk["stats"]],
+            "gmres_its": [st["gmres_its"] for st in rk["stats"]],
+            "max_rel_diff_vs_headline": {"step": rk["steps_done"],
+                                         "value": float(((rk["u"] - res["u"]).abs().max()
+                                                         / res["u"].abs().max()).item())},
+            "phase_ms_per_step": {k: sum(st[k] for st in rk["stats"]) / max(1, len(rk["stats"])) for k in
+                                  ("t_residual_ms", "t_jacobian_ms", "t_setup_ms", "t_gmres_ms")},
+            "workload": "the headline workload and tolerances; each preconditioner setup made by a step "
+                        f"also serves the next {args.keep_steps} steps (rebuilt earlier if its GMRES count "
+                        "exceeds twice its fresh count plus 5)"}
+        del rk
     if args.variant_steps > 0 and coarse is not None:
         its = [g for st in stats for g in st["gmres_its"]]
         out["precond_variants"] = precond_variants_bench(

@@ -138,12 +138,19 @@ typedef struct {
  * it, only the GMRES iteration counts do).  strict_linear: when GMRES stops
  * at its max_it without reaching its tolerance inside a Newton iteration,
  * 1 fails the step with SEIRD_ERR_NOT_CONVERGED; 0 takes the inexact
- * update (inexact Newton) and counts it in seird_step_stats.inexact_solves. */
+ * update (inexact Newton) and counts it in seird_step_stats.inexact_solves.
+ * pc_keep_steps: a setup made by a step may also serve the first
+ * iterations of this many later steps of the same problem and dt (0 = a
+ * fresh setup at every step's first iteration); a kept setup whose GMRES
+ * fails or needs more than twice its fresh count plus 5 is rebuilt, as a
+ * reused one within a step.  A setup made outside the step calls is never
+ * kept, and the steps of seird_forward_record ignore it. */
 typedef struct {
   double tol;
   int32_t max_it;
   int32_t pc_reuse;
   int32_t strict_linear;
+  int32_t pc_keep_steps;
 } seird_newton_opts;
 
 #define SEIRD_MAX_NEWTON 32

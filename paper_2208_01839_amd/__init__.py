@@ -58,7 +58,7 @@ class _KStats(ctypes.Structure):
 
 class _Newton(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int32), ("pc_reuse", ctypes.c_int32),
-                ("strict_linear", ctypes.c_int32)]
+                ("strict_linear", ctypes.c_int32), ("pc_keep_steps", ctypes.c_int32)]
 
 
 MAX_NEWTON = 32
@@ -753,12 +753,13 @@ def gmres_noalloc(problem: Problem, pc, vals, b, x, transpose=False, **kw):
 
 
 def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, pc_reuse=0, strict_linear=False,
-         gmres_max_it=200, **kw):
+         gmres_max_it=200, pc_keep_steps=0, **kw):
     """One implicit step in place on u (float64 CUDA [n,5]).  Returns stats.
     max_it: Newton iterations; gmres_max_it: iterations of each GMRES solve.
     strict_linear: fail (NOT_CONVERGED) when a GMRES solve inside Newton
-    stops at its max_it, instead of taking the inexact update."""
-    n = _Newton(float(tol), int(max_it), int(pc_reuse), int(bool(strict_linear)))
+    stops at its max_it, instead of taking the inexact update.
+    pc_keep_steps: a step's setup may serve this many later steps."""
+    n = _Newton(float(tol), int(max_it), int(pc_reuse), int(bool(strict_linear)), int(pc_keep_steps))
     o = _krylov(max_it=gmres_max_it, **kw)
     s = _SStats()
     code = lib().seird_step(problem.h, pc.h if pc is not None else None,

@@ -463,6 +463,11 @@ struct seird_precond_s {
   std::vector<int32_t> order_act_host;
   int solve_threads = 256;     // workgroup size of the subdomain solves
   int max_nt = 0, max_bu = 0;
+  // a setup made by a Newton step, kept for later steps (pc_keep_steps):
+  // steps that reused it so far (-1: the last setup was not made by a step),
+  // the step size it was made for, and GMRES iterations of its first solve
+  int kept_steps = -1, kept_its = 0;
+  double kept_dt = 0.0;
   // coarse
   SubInfo *coarse_dev = nullptr;
   int32_t *gp = nullptr, *gq = nullptr, *gref = nullptr, *cperm = nullptr;
@@ -1016,6 +1021,7 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
   if (!p || !u || !nopts || !kopts) fail(SEIRD_ERR_ARG, "null argument");
   if (nopts->max_it < 0 || nopts->max_it > SEIRD_MAX_NEWTON) fail(SEIRD_ERR_ARG, "Newton max_it out of range");
   if (nopts->pc_reuse < 0) fail(SEIRD_ERR_ARG, "pc_reuse must be >= 0");
+  if (nopts->pc_keep_steps < 0) fail(SEIRD_ERR_ARG, "pc_keep_steps must be >= 0");
   using clk = std::chrono::steady_clock;
   auto ms = [](clk::time_point a0, clk::time_point b0) {
     return std::chrono::duration<double, std::milli>(b0 - a0).count();
@@ -1083,7 +1089,13 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
     t_jac += ms(t0, clk::now());
     t0 = clk::now();
     bool fresh = false;
-    if (pc && (k == 0 || stale || (k - last_setup) > nopts->pc_reuse)) {
+    // the first iteration may take a setup kept from an earlier step
+    const bool keep = k == 0 && pc && nopts->pc_keep_steps > 0 && pc->prob == p && pc->kept_steps >= 0 &&
+                      pc->kept_steps < nopts->pc_keep_steps && pc->kept_dt == dt;
+    if (keep) {
+      ++pc->kept_steps;
+      its_fresh = pc->kept_its;
+    } else if (pc && (k == 0 || stale || (k - last_setup) > nopts->pc_reuse)) {
       precond_setup_impl(pc, p->vals, st);
       ++setups;
       last_setup = k;
@@ -1117,8 +1129,15 @@ static void step_impl(seird_problem p, seird_precond pc, double *u, double dt, c
     int its_max = 0;
     for (int s = 0; s < S; ++s)
       if (act[s]) its_max = std::max(its_max, ks[s].its + its_first[s]);
-    if (fresh) its_fresh = its_max;
-    else if (its_max > 2 * its_fresh + 5) stale = true;  // reuse no longer pays
+    if (fresh) {
+      its_fresh = its_max;
+      // this step's own setup: a later step may keep it
+      pc->kept_steps = 0;
+      pc->kept_dt = dt;
+      pc->kept_its = its_max;
+    } else if (its_max > 2 * its_fresh + 5) {
+      stale = true;  // reuse no longer pays
+    }
     t_gm += ms(t0, clk::now());
     if (pc && pc->timing) {
       HIPCHECK(hipStreamSynchronize(st));
@@ -1831,6 +1850,7 @@ static int P_ncu(seird_precond pc) { return pc->prob->n_cu; }
 static void precond_setup_impl(seird_precond pc, const double *vals, hipStream_t st) {
   seird_problem P = pc->prob;
   pc->vals_setup = vals;
+  pc->kept_steps = -1;
   precond_setup_raw(pc, P->diag(vals), P->off(vals), st);
 }
 
@@ -2656,7 +2676,10 @@ seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, 
   T.n_regions = n_regions;
   T.dt = dt;
   T.t0 = p->time;
+  // the recorded steps take a fresh setup each (no kept setups), so that the
+  // reverse sweep's recomputation of a segment repeats them exactly
   T.nopts = *nopts;
+  T.nopts.pc_keep_steps = 0;
   T.kopts = *kopts;
   const int n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
   const int last0 = (n_seg - 1) * ckpt_every;  // first step index of the last segment
@@ -2666,7 +2689,7 @@ seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, 
   if (last0 == 0) HIPCHECK(hipMemcpyAsync(T.seg[0], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
   for (int k = 1; k <= n_steps; ++k) {
     std::vector<seird_step_stats> s;
-    step_impl(p, pc, u, dt, nullptr, nopts, kopts, s, st, T.t0 + k * dt);
+    step_impl(p, pc, u, dt, nullptr, &T.nopts, kopts, s, st, T.t0 + k * dt);
     p->time = T.t0 + k * dt;
     launch_region_counts(T.reg_ptr, T.reg_nodes, p->md.mass, u, counts + (int64_t)(k - 1) * n_regions, n_regions, st);
     if (k % ckpt_every == 0 && k / ckpt_every < n_seg)

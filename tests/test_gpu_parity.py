@@ -381,3 +381,25 @@ def test_error_paths_return_status_codes(small):
     with pytest.raises(sk.SeirdError) as e:
         sk.Precond(prob, np.full(cfg.n, 99, np.int32), 4, 1)
     assert e.value.code == -1
+
+
+def test_kept_setups_across_steps_reach_the_same_states():
+    """A setup kept for two later steps (pc_keep_steps) gives the states of
+    one setup per step within the Newton tolerance, with fewer setups; a
+    change of dt takes a fresh setup."""
+    cfg = si.config_small()
+    prob = sk.Problem(cfg.xy, cfg.tri, cfg.params)
+    pa = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap)
+    pb = sk.Precond(prob, cfg.part, cfg.n_sub, cfg.overlap)
+    ua = T(cfg.u0)
+    ub = T(cfg.u0)
+    kw = dict(tol=1e-12, rtol=1e-10, pc_reuse=100)
+    setups = []
+    for _ in range(cfg.steps):
+        sk.step(prob, pa, ua, cfg.dt, **kw)
+        setups.append(sk.step(prob, pb, ub, cfg.dt, pc_keep_steps=2, **kw)["pc_setups"])
+    # one setup serves three steps unless its GMRES count grows past its budget
+    assert setups[0] == 1 and setups[1] == 0 and sum(setups) <= (cfg.steps + 2) // 3 + 2, setups
+    assert relerr(H(ub), H(ua)) < 1e-9
+    st = sk.step(prob, pb, ub, 0.5 * cfg.dt, pc_keep_steps=2, **kw)
+    assert st["pc_setups"] == 1
