@@ -138,19 +138,35 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
     u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
     log(f"[bench] adjoint: {cfg.name}, {steps} steps; truth run")
     truth = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=every, **kw)
-    log("[bench] adjoint: timed forward record")
     prob.set_beta_field(torch.ones(cfg.n, dtype=torch.float64, device="cuda"))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
-    counts = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=every, **kw)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log(f"[bench] adjoint: forward {t1 - t0:.2f} s; reverse sweep")
-    grad_g, grad_nu, st = sk.adjoint(prob, pc, 2 * (counts - truth), rtol=1e-8)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    log(f"[bench] adjoint: forward {t1 - t0:.2f} s, reverse {t2 - t1:.2f} s, {st}")
+
+    def gradient(keep):
+        log(f"[bench] adjoint: timed forward record (pc_keep_steps={keep})")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
+        counts = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=every,
+                                   pc_keep_steps=keep, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        log(f"[bench] adjoint: forward {t1 - t0:.2f} s; reverse sweep")
+        grad_g, grad_nu, st = sk.adjoint(prob, pc, 2 * (counts - truth), rtol=1e-8)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        log(f"[bench] adjoint: forward {t1 - t0:.2f} s, reverse {t2 - t1:.2f} s, {st}")
+        return counts, grad_g, grad_nu, st, t0, t1, t2
+
+    counts, grad_g, grad_nu, st, t0, t1, t2 = gradient(0)
+    kept = None
+    if args.keep_steps > 0:
+        # the same gradient with setups kept across the steps of each
+        # checkpoint segment, forward and in the transposed solves
+        _, kg, knu, kst, k0, k1, k2 = gradient(args.keep_steps)
+        kept = {"keep_steps": args.keep_steps, "value": 1.0 / (k2 - k0), "unit": "grads/s",
+                "forward_s": k1 - k0, "reverse_s": k2 - k1,
+                "transposed_gmres_its": kst["gmres_its_total"], "reverse_setups": kst["setups"],
+                "grad_g_rel_diff": float((kg - grad_g).norm().item() / grad_g.norm().item()),
+                "grad_nu_rel_diff": float(np.abs(knu - grad_nu).max() / np.abs(grad_nu).max())}
     return {"metric": "adjoint gradients/s", "value": 1.0 / (t2 - t0), "unit": "grads/s",
             "workload": (f"{cfg.name}: {cfg.n} nodes ({5 * cfg.n} unknowns), {steps} daily steps, "
                          f"checkpoint every {every}, 40 Voronoi regions, gradient w.r.t. the per-node "
@@ -160,6 +176,7 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
                             if args.adjoint == "full" else "")),
             "forward_s": t1 - t0, "reverse_s": t2 - t1,
             "transposed_gmres_its": st["gmres_its_total"], "recomputed_steps": st["recomputed_steps"],
+            "reverse_setups": st["setups"], "kept_setups": kept,
             "misfit": float(((counts - truth) ** 2).sum().item()),
             "grad_nu": [float(x) for x in grad_nu],
             "grad_g_norm": float(grad_g.norm().item())}
@@ -622,8 +639,8 @@ def main():
     ap.add_argument("--m22-steps", type=int, default=2,
                     help="timed steps of the 22-compartment leg (0: skip)")
     ap.add_argument("--keep-steps", type=int, default=2,
-                    help="FP64 leg repeated with each step's preconditioner setup kept for this many "
-                         "later steps (0: skip)")
+                    help="FP64 leg, and the adjoint gradient, repeated with each step's preconditioner "
+                         "setup kept for this many later steps (0: skip)")
     ap.add_argument("--pgs-tol", type=float, default=1e-10,
                     help="epsilon tolerance of the Picard-Gauss-Seidel sweeps")
     ap.add_argument("--cpu-workers", type=int, default=16,

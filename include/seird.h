@@ -144,7 +144,10 @@ typedef struct {
  * fresh setup at every step's first iteration); a kept setup whose GMRES
  * fails or needs more than twice its fresh count plus 5 is rebuilt, as a
  * reused one within a step.  A setup made outside the step calls is never
- * kept, and the steps of seird_forward_record ignore it. */
+ * kept.  In seird_forward_record the kept setups restart at every
+ * checkpoint (so that seird_adjoint's recomputation of a segment repeats
+ * its steps exactly), and seird_adjoint's transposed solves keep their
+ * setups for as many further reverse steps of a segment. */
 typedef struct {
   double tol;
   int32_t max_it;
@@ -715,6 +718,7 @@ typedef struct {
   int32_t gmres_its_total;  /* transposed solves */
   int32_t recomputed_steps;
   double t_forward_ms, t_reverse_ms;
+  int32_t setups;           /* preconditioner setups of the transposed solves */
 } seird_adjoint_stats;
 
 /* Run n_steps implicit steps from u (in: u^0, out: u^{n_steps}), record

@@ -148,7 +148,8 @@ class _WsOpts(ctypes.Structure):
 
 class _AStats(ctypes.Structure):
     _fields_ = [("gmres_its_total", ctypes.c_int32), ("recomputed_steps", ctypes.c_int32),
-                ("t_forward_ms", ctypes.c_double), ("t_reverse_ms", ctypes.c_double)]
+                ("t_forward_ms", ctypes.c_double), ("t_reverse_ms", ctypes.c_double),
+                ("setups", ctypes.c_int32)]
 
 
 class _TuneCand(ctypes.Structure):
@@ -778,15 +779,18 @@ def step(problem: Problem, pc, u, dt, src=None, tol=1e-10, max_it=20, pc_reuse=0
 
 
 def forward_record(problem: Problem, pc, u, n_steps, dt, region, n_regions, ckpt_every=10,
-                   tol=1e-10, max_it=20, pc_reuse=0, **kw):
+                   tol=1e-10, max_it=20, pc_reuse=0, pc_keep_steps=0, **kw):
     """Run n_steps implicit steps in place on u, recording checkpoints for
-    ``adjoint``; returns the counts [n_steps, n_regions] (CUDA float64)."""
+    ``adjoint``; returns the counts [n_steps, n_regions] (CUDA float64).
+    pc_keep_steps > 0 keeps a step's preconditioner setup for that many
+    further steps within each checkpoint segment, and ``adjoint`` then keeps
+    its transposed-solve setups the same way."""
     torch = _torch()
     region = np.ascontiguousarray(region, dtype=np.int32)
     if len(region) != problem.n:
         raise ValueError("region must have one entry per node")
     counts = torch.empty((int(n_steps), int(n_regions)), dtype=torch.float64, device=u.device)
-    nopt = _Newton(float(tol), int(max_it), int(pc_reuse), 0)
+    nopt = _Newton(float(tol), int(max_it), int(pc_reuse), 0, int(pc_keep_steps))
     kopt = _krylov(**kw)
     # a new record replaces the problem's previous one (the library keeps one)
     problem.record_generation = getattr(problem, "record_generation", 0) + 1
@@ -813,7 +817,7 @@ def adjoint(problem: Problem, pc, grad_counts, **kw):
                                ctypes.byref(kopt), ctypes.byref(st), _stream()))
     return grad_g, grad_nu, dict(gmres_its_total=st.gmres_its_total,
                                  recomputed_steps=st.recomputed_steps,
-                                 t_reverse_ms=st.t_reverse_ms)
+                                 setups=st.setups, t_reverse_ms=st.t_reverse_ms)
 
 
 def _make_run_function():

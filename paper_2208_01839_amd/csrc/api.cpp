@@ -2676,10 +2676,12 @@ seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, 
   T.n_regions = n_regions;
   T.dt = dt;
   T.t0 = p->time;
-  // the recorded steps take a fresh setup each (no kept setups), so that the
-  // reverse sweep's recomputation of a segment repeats them exactly
+  // kept setups (pc_keep_steps) restart at every checkpoint: the first step
+  // of a segment takes a fresh setup, here and when the reverse sweep
+  // recomputes the segment, so that the recomputation repeats the recorded
+  // steps exactly; the reverse sweep keeps its own transposed-solve setups
+  // the same way
   T.nopts = *nopts;
-  T.nopts.pc_keep_steps = 0;
   T.kopts = *kopts;
   const int n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
   const int last0 = (n_seg - 1) * ckpt_every;  // first step index of the last segment
@@ -2689,6 +2691,7 @@ seird_status seird_forward_record(seird_problem p, seird_precond pc, double *u, 
   if (last0 == 0) HIPCHECK(hipMemcpyAsync(T.seg[0], u, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
   for (int k = 1; k <= n_steps; ++k) {
     std::vector<seird_step_stats> s;
+    if (pc && (k - 1) % ckpt_every == 0) pc->kept_steps = -1;  // a segment starts: fresh setup
     step_impl(p, pc, u, dt, nullptr, &T.nopts, kopts, s, st, T.t0 + k * dt);
     p->time = T.t0 + k * dt;
     launch_region_counts(T.reg_ptr, T.reg_nodes, p->md.mass, u, counts + (int64_t)(k - 1) * n_regions, n_regions, st);
@@ -2734,22 +2737,52 @@ seird_status seird_adjoint(seird_problem p, seird_precond pc, const double *grad
       for (int k = n0 + 1; k <= n1; ++k) {
         HIPCHECK(hipMemcpyAsync(T.seg[k - n0], T.seg[k - n0 - 1], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
         std::vector<seird_step_stats> ss;
+        if (pc && k == n0 + 1) pc->kept_steps = -1;  // as in the recorded run
         step_impl(p, pc, T.seg[k - n0], T.dt, nullptr, &T.nopts, &T.kopts, ss, st, T.t0 + k * T.dt);
         as.recomputed_steps++;
       }
       T.seg_holds = s;
     }
+    // the transposed solves' setups: one per reverse step, or with
+    // pc_keep_steps one serving that many further reverse steps of the
+    // segment; a kept setup whose solve fails is rebuilt and the solve
+    // repeated, and one that needs more than twice the iterations of its
+    // fresh solve plus 5 is rebuilt at the next reverse step
+    const int keep = pc ? T.nopts.pc_keep_steps : 0;
+    int since = keep, fresh_its = 0;
     for (int k = n1; k > n0; --k) {
       const double *uk = T.seg[k - n0];
       const ParamsDev Pk = p->params_at(T.t0 + k * T.dt);
       launch_jacobian(p->md, Pk, p->gfield, uk, T.dt, diag, off, st);
-      if (pc) precond_setup_impl(pc, p->vals, st);
+      bool fresh = since >= keep;
+      if (pc && fresh) {
+        precond_setup_impl(pc, p->vals, st);
+        as.setups++;
+        since = 0;
+      } else {
+        ++since;
+      }
       launch_adjoint_rhs(p->md, T.region, grad_counts + (int64_t)(k - 1) * T.n_regions, T.lam_next, T.rhs, st);
-      std::vector<seird_krylov_stats> ks;
-      gmres_impl(p, pc, p->vals, T.rhs, T.lam, *kopts, ks, std::vector<uint8_t>(p->seg.S, 1), 1, st);
-      for (const auto &e : ks) {
-        as.gmres_its_total += e.its;
-        if (e.reason < 0) fail(e.reason, "transposed GMRES failed in the adjoint sweep");
+      for (;;) {
+        std::vector<seird_krylov_stats> ks;
+        gmres_impl(p, pc, p->vals, T.rhs, T.lam, *kopts, ks, std::vector<uint8_t>(p->seg.S, 1), 1, st);
+        int its = 0, reason = 0;
+        for (const auto &e : ks) {
+          its += e.its;
+          if (e.reason < 0) reason = e.reason;
+        }
+        as.gmres_its_total += its;
+        if (reason < 0 && !fresh) {  // kept setup failed: rebuild and solve again
+          precond_setup_impl(pc, p->vals, st);
+          as.setups++;
+          since = 0;
+          fresh = true;
+          continue;
+        }
+        if (reason < 0) fail(reason, "transposed GMRES failed in the adjoint sweep");
+        if (fresh) fresh_its = its;
+        else if (its > 2 * fresh_its + 5) since = keep;  // rebuild at the next reverse step
+        break;
       }
       const int nb = launch_adjoint_grad(p->md, Pk, uk, T.lam, T.dt, grad_g, T.partials, st);
       part.resize(5 * (size_t)nb);

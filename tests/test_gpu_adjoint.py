@@ -117,3 +117,33 @@ def test_autograd_function_backward():
                                       2 * (co - target.cpu().numpy()))
     assert np.linalg.norm(gt.grad.cpu().numpy() - ogg) <= 1e-7 * np.linalg.norm(ogg)
     assert np.abs(nut.grad.cpu().numpy() - ognu).max() <= 1e-7 * np.abs(ognu).max()
+
+
+def test_kept_setups_match_the_oracle_adjoint():
+    """pc_keep_steps: a setup kept across the steps of a checkpoint segment,
+    forward and in the transposed solves, reaches the oracle's gradient; the
+    reverse sweep makes fewer setups than it has steps."""
+    xy, tri, p, u0, g, region, part, n_sub, coarse = _case(True)
+    steps, dt = 7, 0.5
+    prob = sk.Problem(xy, tri, p)
+    pc = sk.Precond(prob, part, n_sub, 1, coarse=coarse)
+    prob.set_params(p)
+    prob.set_beta_field(torch.tensor(g, device="cuda"))
+    u = torch.tensor(u0, device="cuda")
+    c = sk.forward_record(prob, pc, u, steps, dt, region, 4, ckpt_every=3, pc_keep_steps=2,
+                          **TIGHT).cpu().numpy()
+    geo = fem.Geometry(xy, tri)
+    states, co = oadj.forward(u0, steps, dt, geo, p, g, region, 4, tol=1e-14)
+    assert np.abs(c - co).max() <= 1e-9 * np.abs(co).max()
+    gc = 2 * (co - (co * 0.9 + 1e-4))
+    gg, gnu, st = sk.adjoint(prob, pc, torch.tensor(gc, device="cuda"), **ADJ)
+    ogg, ognu = oadj.adjoint_gradient(states, dt, geo, p, g, region, 4, gc)
+    assert np.linalg.norm(gg.cpu().numpy() - ogg) <= 1e-7 * np.linalg.norm(ogg)
+    assert np.abs(gnu - ognu).max() <= 1e-7 * np.abs(ognu).max()
+    assert st["recomputed_steps"] == 6
+    assert 3 <= st["setups"] < steps  # one per segment at least; segments of 3, 3, 1
+    # without keeping, one setup per reverse step
+    u = torch.tensor(u0, device="cuda")
+    sk.forward_record(prob, pc, u, steps, dt, region, 4, ckpt_every=3, **TIGHT)
+    _, _, st0 = sk.adjoint(prob, pc, torch.tensor(gc, device="cuda"), **ADJ)
+    assert st0["setups"] == steps
