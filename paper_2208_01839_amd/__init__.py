@@ -830,7 +830,8 @@ def _make_run_function():
         transmission field g [n] and the diffusion coefficients nu [5]
         through the library's discrete adjoint (reverse sweep with
         checkpoints).  ``options`` is a dict with base_params (rates),
-        ckpt_every, tol and the forward/adjoint Krylov settings."""
+        ckpt_every, tol, pc_reuse, pc_keep_steps and the forward/adjoint
+        Krylov settings."""
 
         @staticmethod
         def _record(problem, pc, g, nu, u0, n_steps, dt, region, n_regions, options):
@@ -842,7 +843,9 @@ def _make_run_function():
             u = u0.clone()
             return forward_record(problem, pc, u, n_steps, dt, region, n_regions,
                                   ckpt_every=options.get("ckpt_every", 10),
-                                  tol=options.get("tol", 1e-10), **options.get("krylov", {}))
+                                  tol=options.get("tol", 1e-10), pc_reuse=options.get("pc_reuse", 0),
+                                  pc_keep_steps=options.get("pc_keep_steps", 0),
+                                  **options.get("krylov", {}))
 
         @staticmethod
         def forward(ctx, g, nu, problem, pc, u0, n_steps, dt, region, n_regions, options):
