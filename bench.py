@@ -651,8 +651,8 @@ def main():
     if args.tile != "auto":
         args.tile = int(args.tile)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path "
-              "is not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     import torch
