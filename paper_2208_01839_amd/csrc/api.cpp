@@ -247,6 +247,7 @@ struct seird_problem_s {
       (void)hipStreamSynchronize(stage_st);
       (void)hipHostFree(stage);
     }
+    if (dl) (void)hipHostFree(dl);
     if (ws_base) unregister_workspace(ws_base);
   }
 
@@ -295,8 +296,7 @@ struct seird_problem_s {
     launch_seg_norm2(sg, x, scale, part, st);
     launch_seg_reduce(sg, part, 1, hv, HLD, 0, st);
     std::vector<double> h((size_t)sg.S * HLD);
-    HIPCHECK(hipMemcpyAsync(h.data(), hv, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
+    download(h.data(), hv, sizeof(double) * h.size(), st);
     std::vector<double> out(sg.S);
     for (int s = 0; s < sg.S; ++s) out[s] = std::sqrt(h[(size_t)s * HLD]);
     return out;
@@ -326,9 +326,29 @@ struct seird_problem_s {
     stage_off += need;
     stage_st = st;
   }
-  // the staging arena, allocated up front so that later uploads of up to
-  // its size never allocate
+  // Small device->host reads (Arnoldi coefficients, norms) land in a pinned
+  // buffer and are copied out once the stream has synchronised (a pageable
+  // destination makes each read a staged transfer).
+  uint8_t *dl = nullptr;
+  size_t dl_cap = 0;
+  void download(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    if (bytes > dl_cap) {  // no copy into dl is in flight: each read synchronises
+      if (dl) HIPCHECK(hipHostFree(dl));
+      dl = nullptr;
+      dl_cap = std::max<size_t>(bytes, (size_t)1 << 16);
+      HIPCHECK(hipHostMalloc((void **)&dl, dl_cap, hipHostMallocDefault));
+    }
+    HIPCHECK(hipMemcpyAsync(dl, src, bytes, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    std::memcpy(dst, dl, bytes);
+  }
+  // the staging arena and the download buffer, allocated up front so that
+  // later transfers of up to their sizes never allocate
   void reserve_stage(size_t bytes) {
+    if (!dl) {
+      dl_cap = (size_t)1 << 16;
+      HIPCHECK(hipHostMalloc((void **)&dl, dl_cap, hipHostMallocDefault));
+    }
     if (stage) return;
     stage_cap = bytes;
     HIPCHECK(hipHostMalloc((void **)&stage, stage_cap, hipHostMallocDefault));
@@ -867,7 +887,9 @@ static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, do
     int j = 0;
     for (; j < m && any(cyc); ++j) {
       double *vj = V + (int64_t)j * N, *zj = Zb + (int64_t)j * N, *w = V + (int64_t)(j + 1) * N;
-      P->upload_mask(P->d_mask, cyc, st);
+      // (a single segment's mask is set before the cycle and cannot change
+      // within it: the cycle ends when its one segment finishes)
+      if (S > 1) P->upload_mask(P->d_mask, cyc, st);
       // z_j = M^{-1} v_j, w = A z_j, then h = V^T w, w -= V h, |w|^2
       auto step_launches = [&](hipStream_t s) {
         if (ops.prec)
@@ -887,8 +909,7 @@ static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, do
                       step_launches, st);
       else
         step_launches(st);
-      HIPCHECK(hipMemcpyAsync(hbuf.data(), hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipStreamSynchronize(st));
+      P->download(hbuf.data(), hdev, sizeof(double) * hbuf.size(), st);
       std::vector<uint8_t> re(S, 0);
       std::vector<double> wn(S, 0.0);
       bool any_re = false;
@@ -909,8 +930,7 @@ static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, do
         launch_seg_reduce(seg, partials, j + 1, hdev, HLD, 0, st);
         launch_seg_maxpy_norm(seg_re, w, V, N, hdev, HLD, j + 1, partials, st);
         launch_seg_reduce(seg, partials, 1, hdev, HLD, j + 1, st);
-        HIPCHECK(hipMemcpyAsync(hbuf.data(), hdev, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipStreamSynchronize(st));
+        P->download(hbuf.data(), hdev, sizeof(double) * hbuf.size(), st);
         for (int s = 0; s < S; ++s) {
           if (!re[s]) continue;
           for (int i = 0; i <= j; ++i) Hs(s, i, j) += hbuf[(size_t)s * HLD + i];
@@ -918,8 +938,12 @@ static void gmres_core(seird_problem P, const GmresOps &ops, const double *b, do
         }
       }
       for (int s = 0; s < S; ++s) sc[s] = (cyc[s] && wn[s] > 0.0) ? 1.0 / wn[s] : 0.0;
-      P->upload_scalars(sc, st);
-      launch_seg_axpby(seg_act, w, w, P->d_svec, 0.0, st);
+      if (S == 1) {  // the scale as a kernel argument: no upload
+        launch_axpby(w, w, sc[0], nullptr, 0, 0.0, N, reduction_blocks(N), st);
+      } else {
+        P->upload_scalars(sc, st);
+        launch_seg_axpby(seg_act, w, w, P->d_svec, 0.0, st);
+      }
       std::vector<uint8_t> fin(S, 0);
       std::vector<int> kfin(S, 0);
       bool any_fin = false;
