@@ -140,12 +140,12 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
     truth = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=every, **kw)
     prob.set_beta_field(torch.ones(cfg.n, dtype=torch.float64, device="cuda"))
 
-    def gradient(keep):
-        log(f"[bench] adjoint: timed forward record (pc_keep_steps={keep})")
+    def gradient(keep, ckpt=every):
+        log(f"[bench] adjoint: timed forward record (pc_keep_steps={keep}, checkpoint every {ckpt})")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         u = torch.tensor(cfg.u0, dtype=torch.float64, device="cuda")
-        counts = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=every,
+        counts = sk.forward_record(prob, pc, u, steps, cfg.dt, region, 40, ckpt_every=ckpt,
                                    pc_keep_steps=keep, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -167,6 +167,19 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
                 "transposed_gmres_its": kst["gmres_its_total"], "reverse_setups": kst["setups"],
                 "grad_g_rel_diff": float((kg - grad_g).norm().item() / grad_g.norm().item()),
                 "grad_nu_rel_diff": float(np.abs(knu - grad_nu).max() / np.abs(grad_nu).max())}
+    resident = None
+    if args.adjoint_resident:
+        # every state of the run kept in device memory (one checkpoint
+        # segment: 61 states of 5n float64), so the reverse sweep recomputes
+        # nothing; setups kept as above
+        keep = max(args.keep_steps, 0)
+        _, rg, rnu, rst, r0, r1, r2 = gradient(keep, ckpt=steps)
+        resident = {"keep_steps": keep, "value": 1.0 / (r2 - r0), "unit": "grads/s",
+                    "forward_s": r1 - r0, "reverse_s": r2 - r1, "recomputed_steps": rst["recomputed_steps"],
+                    "state_gb": (steps + 1) * 5 * cfg.n * 8 / 1e9,
+                    "transposed_gmres_its": rst["gmres_its_total"], "reverse_setups": rst["setups"],
+                    "grad_g_rel_diff": float((rg - grad_g).norm().item() / grad_g.norm().item()),
+                    "grad_nu_rel_diff": float(np.abs(rnu - grad_nu).max() / np.abs(grad_nu).max())}
     return {"metric": "adjoint gradients/s", "value": 1.0 / (t2 - t0), "unit": "grads/s",
             "workload": (f"{cfg.name}: {cfg.n} nodes ({5 * cfg.n} unknowns), {steps} daily steps, "
                          f"checkpoint every {every}, 40 Voronoi regions, gradient w.r.t. the per-node "
@@ -176,7 +189,7 @@ def adjoint_bench(sk, torch, args, cfg, coarse):
                             if args.adjoint == "full" else "")),
             "forward_s": t1 - t0, "reverse_s": t2 - t1,
             "transposed_gmres_its": st["gmres_its_total"], "recomputed_steps": st["recomputed_steps"],
-            "reverse_setups": st["setups"], "kept_setups": kept,
+            "reverse_setups": st["setups"], "kept_setups": kept, "resident_states": resident,
             "misfit": float(((counts - truth) ** 2).sum().item()),
             "grad_nu": [float(x) for x in grad_nu],
             "grad_g_norm": float(grad_g.norm().item())}
@@ -629,6 +642,9 @@ def main():
                          "(full), --adjoint-steps steps of the realistic mesh (short), or none")
     ap.add_argument("--adjoint-steps", type=int, default=10,
                     help="implicit steps of the short adjoint leg")
+    ap.add_argument("--no-adjoint-resident", dest="adjoint_resident", action="store_false",
+                    help="skip the adjoint variant that keeps every state of the run in device memory "
+                         "(no checkpoint recomputation)")
     ap.add_argument("--p-steps", type=int, default=30,
                     help="step at which the precision legs compare their fields (untimed steps are "
                          "added after the timed ones to reach it)")

@@ -147,3 +147,24 @@ def test_kept_setups_match_the_oracle_adjoint():
     sk.forward_record(prob, pc, u, steps, dt, region, 4, ckpt_every=3, **TIGHT)
     _, _, st0 = sk.adjoint(prob, pc, torch.tensor(gc, device="cuda"), **ADJ)
     assert st0["setups"] == steps
+
+
+def test_one_segment_record_keeps_every_state_and_gives_the_same_gradient():
+    """ckpt_every >= n_steps: every state of the run stays in device memory,
+    the reverse sweep recomputes nothing, and the gradient is the one of a
+    checkpointed record of the same run."""
+    xy, tri, p, u0, g, region, part, n_sub, coarse = _case(True)
+    steps, dt = 7, 0.5
+    prob = sk.Problem(xy, tri, p)
+    pc = sk.Precond(prob, part, n_sub, 1, coarse=coarse)
+    out = {}
+    for ckpt in (3, steps):
+        c = _gpu_forward(prob, pc, p, u0, g, region, steps, dt, ckpt=ckpt)
+        gc = 2 * (c - (c * 0.9 + 1e-4))
+        gg, gnu, st = sk.adjoint(prob, pc, torch.tensor(gc, device="cuda"), **ADJ)
+        out[ckpt] = (c, gg.cpu().numpy(), gnu, st)
+    assert out[steps][3]["recomputed_steps"] == 0
+    assert out[3][3]["recomputed_steps"] == 6
+    assert np.array_equal(out[3][0], out[steps][0])  # the same forward run
+    assert np.linalg.norm(out[3][1] - out[steps][1]) <= 1e-12 * np.linalg.norm(out[3][1])
+    assert np.abs(out[3][2] - out[steps][2]).max() <= 1e-12 * np.abs(out[3][2]).max()
