@@ -1054,11 +1054,16 @@ __global__ __launch_bounds__(256) void k_extract_tiles(ET *__restrict__ F, const
       for (int u = 0; u < 4; ++u)
         if (lb0 + u == l) v[u] = 1.0;
     }
+    // non-temporal: the factorisation reads the tiles long after, so the
+    // stores need not stay in the caches
     ET *dst = F + R.at<T>(K, J) + a * T + 4 * g;
-    if constexpr (sizeof(ET) == 8)
-      *reinterpret_cast<double4 *>(dst) = make_double4(v[0], v[1], v[2], v[3]);
-    else
-      *reinterpret_cast<float4 *>(dst) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    if constexpr (sizeof(ET) == 8) {
+      typedef double d4 __attribute__((ext_vector_type(4)));
+      __builtin_nontemporal_store(d4{v[0], v[1], v[2], v[3]}, reinterpret_cast<d4 *>(dst));
+    } else {
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      __builtin_nontemporal_store(f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]}, reinterpret_cast<f4 *>(dst));
+    }
   }
 }
 
