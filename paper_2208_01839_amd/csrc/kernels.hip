@@ -2046,10 +2046,20 @@ constexpr int solve_depth() {
 // as one or two vector loads
 template <class FT, int PER>
 __device__ inline void load_chunk(const FT *__restrict__ p, FT (&out)[PER]) {
-  struct alignas(PER * sizeof(FT)) Chunk { FT v[PER]; };
-  const Chunk c = *reinterpret_cast<const Chunk *>(p);
+  if constexpr (sizeof(FT) == 4 && PER == 4) {
+    // float32 chunks of 16 B as non-temporal loads (the realistic FP32
+    // solve 1.3% faster, the ensemble's 4.8%; the same hint on the float64
+    // chunks made those solves 10% slower)
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 c = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p));
 #pragma unroll
-  for (int m = 0; m < PER; ++m) out[m] = c.v[m];
+    for (int m = 0; m < PER; ++m) out[m] = c[m];
+  } else {
+    struct alignas(PER * sizeof(FT)) Chunk { FT v[PER]; };
+    const Chunk c = *reinterpret_cast<const Chunk *>(p);
+#pragma unroll
+    for (int m = 0; m < PER; ++m) out[m] = c.v[m];
+  }
 }
 
 // Forward and backward sweeps of one subdomain (or of the coarse system).
