@@ -724,8 +724,10 @@ typedef struct {
 /* Run n_steps implicit steps from u (in: u^0, out: u^{n_steps}), record
  * checkpoints every ckpt_every steps (device memory owned by the problem;
  * replaces any previous record) and write the counts [n_steps][n_regions]
- * (device float64) .  region: host int32 [n_nodes], -1 = unobserved.
- * Synchronising. */
+ * (device float64).  The states of the last checkpoint segment are kept
+ * as well: with ckpt_every >= n_steps every state stays in device memory
+ * (ckpt_every + 1 state vectors) and seird_adjoint recomputes no step.
+ * region: host int32 [n_nodes], -1 = unobserved.  Synchronising. */
 seird_status seird_forward_record(seird_problem p, seird_precond pc,
                                   double *u, int32_t n_steps, double dt,
                                   int32_t ckpt_every, const int32_t *region,
