@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE and WRITE_SIZE, copy-calibrated) of the current kernel, by
 # (factor precision, tile, solve threads); the table and commands are in
 # profiles/traffic_realistic_fp64.md.  Legs without a measurement report null.
-MEASURED_SOLVE_TRAFFIC = {(0, 32, 256): (20.927 + 0.177) * 1e9, (0, 32, 512): (21.647 + 0.218) * 1e9}
+MEASURED_SOLVE_TRAFFIC = {(0, 32, 256): (20.927 + 0.177) * 1e9, (0, 32, 512): (21.950 + 0.190) * 1e9}
 
 
 def log(*a):
